@@ -1,0 +1,208 @@
+/*
+ * fgbd.h -- C ABI of the MI355X (gfx950) implementation of fast graph-based
+ * denoising (FGBD) of point-cloud colour: Watanabe, Nonaka, Pavez, Kobayashi,
+ * Ortega, "Fast graph-based denoising for point cloud color information",
+ * arXiv:2401.09721.
+ *
+ * The per-frame path of the paper (Sec. 2.1, Fig. 1(b)) is exposed as four
+ * calls that can be used one by one or fused:
+ *   fgbd_build_slg       scan-line graph, Sec. 2.2, eqs. 1-4
+ *   fgbd_estimate_noise  NE-GBP noise level, Sec. 2.3
+ *   fgbd_filter          FSLR filter selection and the low-pass filter, Sec. 2.4,
+ *                        eqs. 5-6
+ *   fgbd_denoise         all four steps in one call
+ *
+ * Conventions shared by every call
+ *   - Every pointer named in a call is a DEVICE pointer on the context's GPU
+ *     unless its comment says "host".  Arrays are dense, row-major, with no
+ *     padding: coordinates int32 [n][3] (x, y, z), colours float32 [n][3]
+ *     (R, G, B) on the 0..255 scale.  The caller owns every input and output
+ *     buffer; the context owns only its workspace.
+ *   - Every call validates its arguments on the host and returns a status
+ *     before enqueuing anything.  On success all work is enqueued
+ *     asynchronously on `stream` (a hipStream_t; NULL is the default stream)
+ *     and the call returns without waiting, so a sequence of calls can be
+ *     captured in a HIP graph.  Values that steer control flow (sigma_est, q)
+ *     stay in device memory, in an fgbd_result the caller provides.
+ *   - A call allocates device memory only when no workspace has been set with
+ *     fgbd_set_workspace and the context's own workspace is too small.
+ *   - Errors never throw across the ABI; the message of the last failing call
+ *     on this thread is available from fgbd_last_error().
+ *   - Results are deterministic: the same inputs and parameters give bitwise
+ *     identical outputs on the same device (no floating-point atomics).
+ *   - Calls on one context must not overlap in time (they share the
+ *     workspace); use one context per concurrent stream.
+ */
+#ifndef FGBD_H_
+#define FGBD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGBD_ABI_VERSION 1
+
+typedef enum {
+  FGBD_OK = 0,
+  FGBD_E_INVALID = -1,     /* bad argument (null pointer, size or parameter out of range) */
+  FGBD_E_NOMEM = -2,       /* device allocation of the workspace failed                   */
+  FGBD_E_HIP = -3,         /* a HIP runtime call failed (message names it)                 */
+  FGBD_E_WORKSPACE = -4,   /* the workspace set with fgbd_set_workspace is too small      */
+  FGBD_E_UNSUPPORTED = -5  /* valid but not supported by this build (e.g. bits > 10)      */
+} fgbd_status;
+
+/* Device-detected conditions, OR-ed into fgbd_result.status. */
+#define FGBD_ST_COORD_RANGE 1 /* a coordinate was outside 0 .. 2^bits - 1 (graph undefined)  */
+#define FGBD_ST_NO_PATCH 2    /* no point had P neighbours: sigma_est set to 0 (Sec. 2.3)    */
+
+/* Parameters of one run.  fgbd_default_params gives the values used for 1M-point
+ * frames (b = 10, L = 8, w = 4, K = 8). */
+typedef struct {
+  int32_t bits;       /* b: coordinates lie in 0 .. 2^b - 1 (Sec. 2.2); 1..10 (codes fit 32 bits) */
+  int32_t num_dirs;   /* L: scan directions 1..16; the first three are eqs. 1-3, the rest diagonal
+                         lines (Sec. 2.2 mentions them as an alternative)                          */
+  int32_t window;     /* w >= 1: candidates are the w predecessors and w successors in each scan
+                         order (the paper connects consecutive points: w = 1); w <= 64              */
+  int32_t k;          /* K: neighbours kept per point, the first K candidates by (squared distance,
+                         index); 1..32.  Paper mode L = 3, w = 1, K = 6 keeps all candidates.      */
+  int32_t patch;      /* P: NE-GBP patch = the point plus its P nearest neighbours (D = P + 1
+                         entries, Sec. 2.3); 0 means K; 1..K                                       */
+  int32_t q_max;      /* largest number of filter sweeps tried by the selection (eq. 6); 0..1024  */
+  double fslr_kappa;  /* FSLR excludes points whose patch spread exceeds kappa * sigma_est
+                         (kappa = 2 in Sec. 2.4); <= 0 disables FSLR (all points used)            */
+  double sigma_g;     /* Gaussian bandwidth of eq. 4; <= 0 means the mean edge length (Sec. 2.2) */
+} fgbd_params;
+
+/* A fixed-K neighbour graph in device memory (CSR with K slots per row).
+ * Row i lists its neighbours in increasing (squared distance, index) order;
+ * unused slots have col = -1, dist2 = 0, p = 0.  p[i][k] is the row-normalised
+ * weight w_ik / deg_i of eq. 4, so (T x)_i = x_i / 2 + sum_k p[i][k] x[col[i][k]] / 2
+ * is the filter operator D_g^{-1} W_g of eq. 5. */
+typedef struct {
+  int32_t *col;   /* device int32 [n][k] */
+  int32_t *dist2; /* device int32 [n][k], exact integer squared distances */
+  float *p;       /* device float32 [n][k] */
+  int64_t n;
+  int32_t k;
+  int32_t pad_;
+} fgbd_graph;
+
+/* Per-frame results, written to DEVICE memory by the calls (48 bytes). */
+typedef struct {
+  double sigma_est; /* NE-GBP noise level on the 0..255 scale (Sec. 2.3)           */
+  double sigma_g;   /* bandwidth used in eq. 4                                     */
+  double loss;      /* |sigma_est^2 - E(q)| at the selected q (eq. 6)              */
+  int32_t q;        /* number of filter sweeps applied (selected or fixed)         */
+  int32_t n_fslr;   /* points entering eq. 6 after FSLR (Sec. 2.4)                 */
+  int32_t n_eff;    /* points with a complete patch (entered the covariance)       */
+  int32_t status;   /* FGBD_ST_* bits                                              */
+  int32_t sweeps;   /* filter sweeps computed before the selection stopped        */
+  int32_t m;        /* index m of the first eigenvalue in the noise tail (Sec. 2.3) */
+} fgbd_result;
+
+typedef struct fgbd_ctx_s *fgbd_ctx;
+
+/* ABI version compiled into the library (FGBD_ABI_VERSION). */
+int32_t fgbd_abi_version(void);
+
+/* Fill *p with the defaults: bits 10, num_dirs 8, window 4, k 8, patch 0 (= k),
+ * q_max 32, fslr_kappa 2.0, sigma_g 0 (mean edge length).  p: host. */
+fgbd_status fgbd_default_params(fgbd_params *p);
+
+/* Create a context bound to HIP device `hip_device`.  No device memory is
+ * touched until the first compute call.  out: host. */
+fgbd_status fgbd_create(fgbd_ctx *out, int32_t hip_device);
+
+/* Free the context and any workspace it allocated itself.  NULL is allowed. */
+fgbd_status fgbd_destroy(fgbd_ctx ctx);
+
+/* Device workspace in bytes that fgbd_denoise needs for clouds of up to n_max
+ * points (the other calls need no more).  `batch` is reserved and must be 1.
+ * p, bytes: host. */
+fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t batch, size_t *bytes);
+
+/* Hand the context a caller-owned device buffer (256-byte aligned) to use as
+ * its workspace; afterwards no call allocates.  dev = NULL, bytes = 0 returns
+ * to self-allocation.  The buffer must outlive every call that uses it. */
+fgbd_status fgbd_set_workspace(fgbd_ctx ctx, void *dev, size_t bytes);
+
+/* Scan-line graph (Sec. 2.2).  For each of the first L directions, every
+ * point gets a scan-line code (eqs. 1-3; the diagonal directions replace two
+ * coordinates by line invariants); the codes are sorted by an LSD radix sort
+ * (equal codes keep index order); the w points before and after each point
+ * in every sorted order are its candidates; the first K distinct candidates by
+ * (squared distance, index) form its row.  Then sigma_g (params->sigma_g, or
+ * the mean Euclidean length of all edges) and the weights of eq. 4.
+ *   xyz: int32 [n][3];  n >= 0, n < 2^31;  g->col/dist2/p: outputs with n*k
+ *   slots each (g->n == n, g->k == params->k);  res: sigma_g and status are
+ *   written, every other field is zeroed. */
+fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_params *params,
+                           const fgbd_graph *g, fgbd_result *res, void *stream);
+
+/* NE-GBP (Sec. 2.3).  Patches of D = P + 1 entries per colour channel (the
+ * point, then its first P neighbours in row order, i.e. by distance) from
+ * every point with at least P neighbours; their covariance, pooled over the
+ * channels with each channel's mean removed; its eigenvalues in FP64; the
+ * noise level sqrt(tau) from the smallest m with tau_m <= median of the tail
+ * lambda_{m+1..D}, where tau_m is the tail mean.
+ *   g: graph from fgbd_build_slg;  rgb: float32 [n][3];
+ *   res: sigma_est, n_eff written, status bit FGBD_ST_NO_PATCH set or cleared;
+ *   patch_spread: optional output double [n], the FSLR spread
+ *     (sigma_R + sigma_G + sigma_B) / 3 of each patch (Sec. 2.4; +inf for an
+ *     incomplete patch), needed by fgbd_filter when FSLR is on;
+ *   eig3: optional output float32 [n][3], eigenvalues (descending) of each
+ *     point's 3x3 colour covariance over its patch, a diagnostic whose diagonal
+ *     the FSLR spread uses; 0 for incomplete patches. */
+fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb, const fgbd_params *params,
+                                fgbd_result *res, double *patch_spread, float *eig3, void *stream);
+
+/* Filter selection (FSLR, Sec. 2.4, eq. 6) and the low-pass filter (eq. 5).
+ * With `noise` non-NULL: x_0 = rgb_in, x_q = T x_{q-1}; E(q) is the mean over
+ * the FSLR subset and the channels of y^2 - x_q^2; sweeps stop at the first q
+ * with E(q) >= sigma_est^2 (or q_max) and the q in 0..that minimising
+ * |sigma_est^2 - E(q)| (ties to the smaller q) is applied.  The subset is the
+ * points whose patch_spread is <= fslr_kappa * sigma_est (all points when
+ * fslr_kappa <= 0 or the subset is empty).  With `noise` NULL: exactly
+ * q_fixed sweeps (q_fixed >= 0), no selection.
+ *   rgb_in, rgb_out: float32 [n][3], must not overlap;
+ *   noise: device fgbd_result holding sigma_est (may equal res);
+ *   patch_spread: double [n] from fgbd_estimate_noise, required when noise is
+ *     non-NULL and fslr_kappa > 0;
+ *   res: q, n_fslr, loss written and sigma_est copied from noise. */
+fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, const fgbd_params *params,
+                        const fgbd_result *noise, const double *patch_spread, int32_t q_fixed, float *rgb_out,
+                        fgbd_result *res, void *stream);
+
+/* The whole per-frame path of Fig. 1(b): build_slg, estimate_noise and filter
+ * with selection, with every intermediate in the workspace.
+ *   xyz: int32 [n][3]; rgb_in, rgb_out: float32 [n][3] (must not overlap);
+ *   res: every field written. */
+fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n,
+                         const fgbd_params *params, float *rgb_out, fgbd_result *res, void *stream);
+
+/* Message for the last non-OK status returned on the calling thread ("" if
+ * none).  Valid until the next call on this thread. */
+const char *fgbd_last_error(void);
+
+/* Kernel timing for measurement.  When enabled, the compute calls record a
+ * HIP event pair on their stream around every kernel launch;
+ * fgbd_profile_read waits for the work recorded so far and returns, per kernel
+ * kind, the summed milliseconds and the number of launches, then clears the
+ * counters.  Kinds:
+ *   0 radix upsweep (digit counts; pass 0 also makes the codes), 1 radix scan,
+ *   2 radix downsweep (stable scatter), 3 neighbour merge, 4 edge weights,
+ *   5 noise estimate, 6 filter sweep, 7 finalise.
+ * The event records add a little time of their own between launches.
+ * ms, launches: host arrays of `count` entries (count <= FGBD_NUM_KERNELS). */
+#define FGBD_NUM_KERNELS 8
+fgbd_status fgbd_profile_enable(fgbd_ctx ctx, int32_t enable);
+fgbd_status fgbd_profile_read(fgbd_ctx ctx, double *ms, int64_t *launches, int32_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGBD_H_ */

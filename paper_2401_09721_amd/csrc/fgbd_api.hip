@@ -1,0 +1,584 @@
+// Host side of the C ABI (include/fgbd.h): argument validation, workspace
+// planning, and the order of launches for each call.  No call blocks the
+// host; every launch goes to the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "fgbd_internal.h"
+
+using namespace fgbd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+fgbd_status fail(fgbd_status st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+fgbd_status ok() {
+  g_err[0] = '\0';
+  return FGBD_OK;
+}
+
+// The direction table: d0..d2 are the raster codes of eqs. 1-3; the rest are
+// diagonal scan lines.  Each entry is a primitive integer vector.
+const int kDirVec[kMaxDirs][3] = {
+    {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, -1, 0}, {0, 1, 1}, {0, 1, -1}, {1, 0, 1},
+    {1, 0, -1}, {1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {1, -1, -1}, {1, 2, 0}, {0, 1, 2}, {2, 0, 1},
+};
+
+int bit_length(int v) {
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+struct Record {
+  int kind;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct fgbd_ctx_s {
+  int device = 0;
+  void *own = nullptr;
+  size_t own_bytes = 0;
+  void *user = nullptr;
+  size_t user_bytes = 0;
+  bool profile = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<Record> pending;
+  double ms[FGBD_NUM_KERNELS] = {0};
+  int64_t launches[FGBD_NUM_KERNELS] = {0};
+};
+
+namespace fgbd {
+
+void make_dir_table(int bits, int num_dirs, DirTable *t) {
+  memset(t, 0, sizeof(*t));
+  t->bits = bits;
+  t->num_dirs = num_dirs;
+  for (int d = 0; d < num_dirs; ++d) {
+    int u[3] = {kDirVec[d][0], kDirVec[d][1], kDirVec[d][2]};
+    int a = 0;
+    while (abs(u[a]) != 1) ++a;
+    if (u[a] < 0)
+      for (int j = 0; j < 3; ++j) u[j] = -u[j];
+    const int h = (a + 2) % 3, m = (a + 1) % 3;
+    DirInfo &di = t->d[d];
+    di.a = (int8_t)a;
+    di.h = (int8_t)h;
+    di.m = (int8_t)m;
+    di.uh = (int8_t)u[h];
+    di.um = (int8_t)u[m];
+    di.wm_extra = (int8_t)bit_length(abs(u[m]));
+  }
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Plan make_plan(int64_t n, const fgbd_params &p) {
+  Plan pl;
+  memset(&pl, 0, sizeof(pl));
+  pl.n = n;
+  pl.L = p.num_dirs;
+  pl.K = p.k;
+  pl.P = p.patch > 0 ? p.patch : p.k;
+  pl.D = pl.P + 1;
+  pl.ntiles = (int32_t)((n + kSortTile - 1) / kSortTile);
+  pl.merge_blocks = (int32_t)((n + kBlock - 1) / kBlock);
+  pl.sweep_blocks = pl.merge_blocks;
+  const int TP = pl.D <= 17 ? 256 : 128;
+  const int64_t ptiles = (n + TP - 1) / TP;
+  pl.noise_blocks = (int32_t)(ptiles < kNoiseMaxBlocks ? ptiles : kNoiseMaxBlocks);
+  pl.npart_noise = 1 + pl.D * (pl.D + 1) / 2 + 3 * pl.D;
+  const size_t N = (size_t)(n > 0 ? n : 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  pl.off_items_a = take((size_t)pl.L * N * 8);
+  pl.off_items_b = take((size_t)pl.L * N * 8);
+  pl.off_hist = take((size_t)pl.L * (pl.ntiles > 0 ? pl.ntiles : 1) * 256 * 4);
+  pl.off_rank = take((size_t)pl.L * N * 4);
+  pl.off_col = take(N * pl.K * 4);
+  pl.off_dist2 = take(N * pl.K * 4);
+  pl.off_p = take(N * pl.K * 4);
+  pl.off_spread = take(N * 8);
+  pl.off_xbuf = take(3 * N * 16);
+  pl.off_merge_part = take((size_t)(pl.merge_blocks > 0 ? pl.merge_blocks : 1) * 2 * 8);
+  pl.off_noise_part = take((size_t)(pl.noise_blocks > 0 ? pl.noise_blocks : 1) * pl.npart_noise * 8);
+  pl.off_sweep_part = take((size_t)(pl.sweep_blocks > 0 ? pl.sweep_blocks : 1) * kSweepParts * 8);
+  pl.off_ctrl = take(sizeof(SweepCtrl));
+  pl.off_counters = take(sizeof(Counters));
+  pl.total = off;
+  return pl;
+}
+
+namespace {
+
+__global__ void k_init(fgbd_result *res, Counters *cnt, int zero_result) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (cnt) {
+      cnt->merge = 0;
+      cnt->noise = 0;
+      cnt->sweep = 0;
+      cnt->pad = 0;
+    }
+    if (zero_result && res) {
+      res->sigma_est = 0.0;
+      res->sigma_g = 0.0;
+      res->loss = 0.0;
+      res->q = 0;
+      res->n_fslr = 0;
+      res->n_eff = 0;
+      res->status = zero_result == 2 ? FGBD_ST_NO_PATCH : 0;
+      res->sweeps = 0;
+      res->m = 0;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_init(fgbd_result *res, Counters *cnt, int zero_result, hipStream_t stream) {
+  k_init<<<1, 64, 0, stream>>>(res, cnt, zero_result);
+  return hipGetLastError();
+}
+
+}  // namespace fgbd
+
+namespace {
+
+fgbd_status check_params(const fgbd_params *p) {
+  if (!p) return fail(FGBD_E_INVALID, "params is NULL");
+  if (p->bits < 1) return fail(FGBD_E_INVALID, "bits must be >= 1 (got %d)", p->bits);
+  if (p->bits > 10) return fail(FGBD_E_UNSUPPORTED, "bits > 10 needs codes wider than 32 bits (got %d)", p->bits);
+  if (p->num_dirs < 1 || p->num_dirs > kMaxDirs)
+    return fail(FGBD_E_INVALID, "num_dirs must be in 1..%d (got %d)", kMaxDirs, p->num_dirs);
+  if (p->window < 1 || p->window > 64) return fail(FGBD_E_INVALID, "window must be in 1..64 (got %d)", p->window);
+  if (p->k < 1 || p->k > kMaxK) return fail(FGBD_E_INVALID, "k must be in 1..%d (got %d)", kMaxK, p->k);
+  if (p->patch < 0 || p->patch > p->k)
+    return fail(FGBD_E_INVALID, "patch must be in 0..k (got %d with k=%d)", p->patch, p->k);
+  if (p->q_max < 0 || p->q_max > 1024) return fail(FGBD_E_INVALID, "q_max must be in 0..1024 (got %d)", p->q_max);
+  if (!isfinite(p->fslr_kappa)) return fail(FGBD_E_INVALID, "fslr_kappa must be finite");
+  if (!isfinite(p->sigma_g)) return fail(FGBD_E_INVALID, "sigma_g must be finite");
+  return FGBD_OK;
+}
+
+fgbd_status check_n(int64_t n) {
+  if (n < 0) return fail(FGBD_E_INVALID, "n must be >= 0 (got %lld)", (long long)n);
+  if (n > (int64_t)0x7fffffff - kSortTile) return fail(FGBD_E_INVALID, "n too large (got %lld)", (long long)n);
+  return FGBD_OK;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const char *pa = (const char *)a, *pb = (const char *)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) {
+      err = hipSetDevice(dev);
+      changed = err == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+fgbd_status hip_fail(hipError_t e, const char *what) {
+  return fail(FGBD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+fgbd_status get_workspace(fgbd_ctx ctx, size_t need, char **ws) {
+  if (ctx->user) {
+    if (ctx->user_bytes < need)
+      return fail(FGBD_E_WORKSPACE, "workspace has %zu bytes, call needs %zu", ctx->user_bytes, need);
+    *ws = (char *)ctx->user;
+    return FGBD_OK;
+  }
+  if (ctx->own_bytes < need) {
+    if (ctx->own) {
+      hipError_t e = hipDeviceSynchronize();  // the old buffer may still be in use
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      (void)hipFree(ctx->own);
+      ctx->own = nullptr;
+      ctx->own_bytes = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) return fail(FGBD_E_NOMEM, "hipMalloc(%zu) failed: %s", need, hipGetErrorString(e));
+    ctx->own = p;
+    ctx->own_bytes = need;
+  }
+  *ws = (char *)ctx->own;
+  return FGBD_OK;
+}
+
+// ------------------------------------------------------------ profiling
+// Records an event pair around every launch when the context has profiling on.
+struct EventProf final : Prof {
+  fgbd_ctx ctx;
+  hipStream_t stream;
+  int kind = -1;
+  hipEvent_t a = nullptr;
+  EventProf(fgbd_ctx c, hipStream_t s) : ctx(c), stream(s) {}
+  hipEvent_t take() {
+    if (ctx->pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  void pre(int k) override {
+    kind = k;
+    a = take();
+    if (a) (void)hipEventRecord(a, stream);
+  }
+  void post() override {
+    if (kind < 0 || !a) return;
+    hipEvent_t b = take();
+    if (b) {
+      (void)hipEventRecord(b, stream);
+      ctx->pending.push_back(Record{kind, a, b});
+    }
+    kind = -1;
+    a = nullptr;
+  }
+};
+
+struct Bufs {
+  uint64_t *items_a, *items_b;
+  uint32_t *hist, *rank;
+  int32_t *col, *dist2;
+  float *p;
+  double *spread;
+  float4 *xbuf;
+  double *merge_part, *noise_part, *sweep_part;
+  SweepCtrl *ctrl;
+  Counters *cnt;
+};
+
+Bufs carve(char *ws, const Plan &pl) {
+  Bufs b;
+  b.items_a = (uint64_t *)(ws + pl.off_items_a);
+  b.items_b = (uint64_t *)(ws + pl.off_items_b);
+  b.hist = (uint32_t *)(ws + pl.off_hist);
+  b.rank = (uint32_t *)(ws + pl.off_rank);
+  b.col = (int32_t *)(ws + pl.off_col);
+  b.dist2 = (int32_t *)(ws + pl.off_dist2);
+  b.p = (float *)(ws + pl.off_p);
+  b.spread = (double *)(ws + pl.off_spread);
+  b.xbuf = (float4 *)(ws + pl.off_xbuf);
+  b.merge_part = (double *)(ws + pl.off_merge_part);
+  b.noise_part = (double *)(ws + pl.off_noise_part);
+  b.sweep_part = (double *)(ws + pl.off_sweep_part);
+  b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
+  b.cnt = (Counters *)(ws + pl.off_counters);
+  return b;
+}
+
+#define HIP_TRY(expr, what)                 \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Graph construction into (col, dist2, p); sigma_g into res.
+fgbd_status run_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_params &prm, const Plan &pl,
+                    const Bufs &b, int32_t *col, int32_t *dist2, float *p, fgbd_result *res, hipStream_t s) {
+  DirTable dt;
+  make_dir_table(prm.bits, prm.num_dirs, &dt);
+  EventProf ep(ctx, s);
+  Prof *pf = ctx->profile ? &ep : nullptr;
+  const uint64_t *sorted = nullptr;
+  HIP_TRY(launch_sort(xyz, n, dt, pl, b.items_a, b.items_b, b.hist, b.rank, res, s, &sorted, pf),
+          "radix sort launch");
+  FGBD_PRE(pf, kMerge);
+  HIP_TRY(launch_merge(xyz, n, dt, prm.window, prm.k, sorted, b.rank, col, dist2, b.merge_part, pl.merge_blocks,
+                       b.cnt, prm.sigma_g, res, s),
+          "neighbour merge launch");
+  FGBD_POST(pf);
+  FGBD_PRE(pf, kWeights);
+  HIP_TRY(launch_weights(n, prm.k, col, dist2, res, p, s), "weights launch");
+  FGBD_POST(pf);
+  return FGBD_OK;
+}
+
+fgbd_status run_noise(fgbd_ctx ctx, int64_t n, const fgbd_params &prm, const Plan &pl, const Bufs &b,
+                      const int32_t *col, const float *rgb, double *spread, float *eig3, fgbd_result *res,
+                      hipStream_t s) {
+  EventProf ep(ctx, s);
+  Prof *pf = ctx->profile ? &ep : nullptr;
+  FGBD_PRE(pf, kNoise);
+  HIP_TRY(launch_noise(n, prm.k, pl.P, col, rgb, spread, eig3, b.noise_part, pl.noise_blocks, b.cnt, res, s),
+          "noise launch");
+  FGBD_POST(pf);
+  return FGBD_OK;
+}
+
+fgbd_status run_filter(fgbd_ctx ctx, int64_t n, const fgbd_params &prm, const Plan &pl, const Bufs &b,
+                       const int32_t *col, const float *p, const float *rgb_in, const double *spread,
+                       const fgbd_result *noise, int select, int q_limit, float *rgb_out, fgbd_result *res,
+                       hipStream_t s) {
+  EventProf ep(ctx, s);
+  Prof *pf = ctx->profile ? &ep : nullptr;
+  const int sweeps = q_limit > 0 ? q_limit : 1;
+  for (int q = 0; q < sweeps; ++q) {
+    FGBD_PRE(pf, kSweep);
+    HIP_TRY(launch_sweep(n, prm.k, col, p, rgb_in, b.xbuf, spread, noise, prm.fslr_kappa, select, q_limit, q == 0,
+                         b.sweep_part, pl.sweep_blocks, b.cnt, b.ctrl, s),
+            "sweep launch");
+    FGBD_POST(pf);
+  }
+  FGBD_PRE(pf, kFinalize);
+  HIP_TRY(launch_finalize(n, rgb_in, b.xbuf, b.ctrl, noise, 0, rgb_out, res, s), "finalize launch");
+  FGBD_POST(pf);
+  return FGBD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fgbd_abi_version(void) { return FGBD_ABI_VERSION; }
+
+const char *fgbd_last_error(void) { return g_err; }
+
+fgbd_status fgbd_default_params(fgbd_params *p) {
+  if (!p) return fail(FGBD_E_INVALID, "params is NULL");
+  p->bits = 10;
+  p->num_dirs = 8;
+  p->window = 4;
+  p->k = 8;
+  p->patch = 0;
+  p->q_max = 32;
+  p->fslr_kappa = 2.0;
+  p->sigma_g = 0.0;
+  return ok();
+}
+
+fgbd_status fgbd_create(fgbd_ctx *out, int32_t hip_device) {
+  if (!out) return fail(FGBD_E_INVALID, "out is NULL");
+  if (hip_device < 0) return fail(FGBD_E_INVALID, "hip_device must be >= 0");
+  fgbd_ctx c = new (std::nothrow) fgbd_ctx_s();
+  if (!c) return fail(FGBD_E_NOMEM, "host allocation failed");
+  c->device = hip_device;
+  *out = c;
+  return ok();
+}
+
+fgbd_status fgbd_destroy(fgbd_ctx ctx) {
+  if (!ctx) return ok();
+  if (ctx->own || !ctx->pool.empty() || !ctx->pending.empty()) {
+    DeviceGuard g(ctx->device);
+    if (ctx->own) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(ctx->own);
+    }
+    for (auto &r : ctx->pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+  return ok();
+}
+
+fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t batch, size_t *bytes) {
+  fgbd_status st = check_params(p);
+  if (st != FGBD_OK) return st;
+  if ((st = check_n(n_max)) != FGBD_OK) return st;
+  if (batch != 1) return fail(FGBD_E_INVALID, "batch must be 1");
+  if (!bytes) return fail(FGBD_E_INVALID, "bytes is NULL");
+  *bytes = make_plan(n_max, *p).total;
+  return ok();
+}
+
+fgbd_status fgbd_set_workspace(fgbd_ctx ctx, void *dev, size_t bytes) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  if ((dev == nullptr) != (bytes == 0)) return fail(FGBD_E_INVALID, "dev and bytes must both be set or both zero");
+  if (((uintptr_t)dev & 255) != 0) return fail(FGBD_E_INVALID, "workspace must be 256-byte aligned");
+  ctx->user = dev;
+  ctx->user_bytes = bytes;
+  return ok();
+}
+
+fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_params *params,
+                           const fgbd_graph *g, fgbd_result *res, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_params(params);
+  if (st != FGBD_OK) return st;
+  if ((st = check_n(n)) != FGBD_OK) return st;
+  if (!g) return fail(FGBD_E_INVALID, "graph is NULL");
+  if (g->n != n || g->k != params->k) return fail(FGBD_E_INVALID, "graph shape (%lld, %d) != (n, k)", (long long)g->n, g->k);
+  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
+  if (n > 0 && (!xyz || !g->col || !g->dist2 || !g->p)) return fail(FGBD_E_INVALID, "NULL input or graph array");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  const Plan pl = make_plan(n, *params);
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  const Bufs b = carve(ws, pl);
+  HIP_TRY(launch_init(res, b.cnt, 1, s), "init launch");
+  if (n == 0) return ok();
+  if ((st = run_slg(ctx, xyz, n, *params, pl, b, g->col, g->dist2, g->p, res, s)) != FGBD_OK) return st;
+  return ok();
+}
+
+fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb, const fgbd_params *params,
+                                fgbd_result *res, double *patch_spread, float *eig3, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_params(params);
+  if (st != FGBD_OK) return st;
+  if (!g) return fail(FGBD_E_INVALID, "graph is NULL");
+  if ((st = check_n(g->n)) != FGBD_OK) return st;
+  if (g->k != params->k) return fail(FGBD_E_INVALID, "graph k (%d) != params k (%d)", g->k, params->k);
+  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
+  const int64_t n = g->n;
+  if (n > 0 && (!rgb || !g->col)) return fail(FGBD_E_INVALID, "NULL colour or graph array");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  const Plan pl = make_plan(n, *params);
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  const Bufs b = carve(ws, pl);
+  HIP_TRY(launch_init(nullptr, b.cnt, 0, s), "init launch");
+  if (n == 0) {
+    HIP_TRY(launch_init(res, nullptr, 2, s), "init launch");
+    return ok();
+  }
+  if ((st = run_noise(ctx, n, *params, pl, b, g->col, rgb, patch_spread ? patch_spread : b.spread, eig3, res, s)) !=
+      FGBD_OK)
+    return st;
+  return ok();
+}
+
+fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, const fgbd_params *params,
+                        const fgbd_result *noise, const double *patch_spread, int32_t q_fixed, float *rgb_out,
+                        fgbd_result *res, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_params(params);
+  if (st != FGBD_OK) return st;
+  if (!g) return fail(FGBD_E_INVALID, "graph is NULL");
+  if ((st = check_n(g->n)) != FGBD_OK) return st;
+  if (g->k != params->k) return fail(FGBD_E_INVALID, "graph k (%d) != params k (%d)", g->k, params->k);
+  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
+  const int64_t n = g->n;
+  const int select = noise != nullptr;
+  if (!select && (q_fixed < 0 || q_fixed > 1024)) return fail(FGBD_E_INVALID, "q_fixed must be in 0..1024");
+  if (select && params->fslr_kappa > 0 && !patch_spread && n > 0)
+    return fail(FGBD_E_INVALID, "patch_spread is required when FSLR is on (fslr_kappa > 0)");
+  if (n > 0 && (!rgb_in || !rgb_out || !g->col || !g->p)) return fail(FGBD_E_INVALID, "NULL colour or graph array");
+  if (n > 0 && overlap(rgb_in, (size_t)n * 12, rgb_out, (size_t)n * 12))
+    return fail(FGBD_E_INVALID, "rgb_in and rgb_out overlap");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  const Plan pl = make_plan(n, *params);
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  const Bufs b = carve(ws, pl);
+  HIP_TRY(launch_init(nullptr, b.cnt, 0, s), "init launch");
+  if (n == 0) {
+    HIP_TRY(launch_init(res, nullptr, 1, s), "init launch");
+    return ok();
+  }
+  const int q_limit = select ? params->q_max : q_fixed;
+  if ((st = run_filter(ctx, n, *params, pl, b, g->col, g->p, rgb_in, patch_spread, noise, select, q_limit, rgb_out,
+                       res, s)) != FGBD_OK)
+    return st;
+  return ok();
+}
+
+fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n,
+                         const fgbd_params *params, float *rgb_out, fgbd_result *res, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_params(params);
+  if (st != FGBD_OK) return st;
+  if ((st = check_n(n)) != FGBD_OK) return st;
+  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
+  if (n > 0 && (!xyz || !rgb_in || !rgb_out)) return fail(FGBD_E_INVALID, "NULL input or output array");
+  if (n > 0 && overlap(rgb_in, (size_t)n * 12, rgb_out, (size_t)n * 12))
+    return fail(FGBD_E_INVALID, "rgb_in and rgb_out overlap");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  const Plan pl = make_plan(n, *params);
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  const Bufs b = carve(ws, pl);
+  HIP_TRY(launch_init(res, b.cnt, n == 0 ? 2 : 1, s), "init launch");
+  if (n == 0) return ok();
+  if ((st = run_slg(ctx, xyz, n, *params, pl, b, b.col, b.dist2, b.p, res, s)) != FGBD_OK) return st;
+  if ((st = run_noise(ctx, n, *params, pl, b, b.col, rgb_in, b.spread, nullptr, res, s)) != FGBD_OK) return st;
+  if ((st = run_filter(ctx, n, *params, pl, b, b.col, b.p, rgb_in, b.spread, res, 1, params->q_max, rgb_out, res,
+                       s)) != FGBD_OK)
+    return st;
+  return ok();
+}
+
+fgbd_status fgbd_profile_enable(fgbd_ctx ctx, int32_t enable) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  ctx->profile = enable != 0;
+  return ok();
+}
+
+fgbd_status fgbd_profile_read(fgbd_ctx ctx, double *ms, int64_t *launches, int32_t count) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  if (count < 0 || count > FGBD_NUM_KERNELS) return fail(FGBD_E_INVALID, "count must be in 0..%d", FGBD_NUM_KERNELS);
+  if (count > 0 && (!ms || !launches)) return fail(FGBD_E_INVALID, "NULL output array");
+  if (!ctx->pending.empty()) {
+    DeviceGuard dg(ctx->device);
+    if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+    for (auto &r : ctx->pending) {
+      HIP_TRY(hipEventSynchronize(r.b), "hipEventSynchronize");
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
+      ctx->ms[r.kind] += t;
+      ctx->launches[r.kind] += 1;
+      ctx->pool.push_back(r.a);
+      ctx->pool.push_back(r.b);
+    }
+    ctx->pending.clear();
+  }
+  for (int i = 0; i < count; ++i) {
+    ms[i] = ctx->ms[i];
+    launches[i] = ctx->launches[i];
+  }
+  for (int i = 0; i < FGBD_NUM_KERNELS; ++i) {
+    ctx->ms[i] = 0;
+    ctx->launches[i] = 0;
+  }
+  return ok();
+}
+
+}  // extern "C"

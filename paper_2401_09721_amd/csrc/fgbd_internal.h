@@ -1,0 +1,232 @@
+// Internal declarations shared by the HIP translation units of libfgbd.
+// Everything here is gfx950 (CDNA4, wave64) code; nothing is exported.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fgbd.h"
+
+namespace fgbd {
+
+constexpr int kWave = 64;
+constexpr int kMaxDirs = 16;
+constexpr int kMaxK = 32;
+constexpr int kMaxD = kMaxK + 1;
+
+// ---------------------------------------------------------------- directions
+// A scan direction u (a primitive integer vector) is described by its position
+// axis a (first axis with |u_a| = 1, u normalised to u_a = +1), the high and
+// middle axes h = (a+2)%3, m = (a+1)%3 replaced by line invariants
+// e_j = g_j - u_j g_a + max(u_j,0)(2^b-1), and the bit width of e_m.
+// The code is ((e_h << wm) + e_m) << b | g_a; d0..d2 are eqs. 1-3.
+struct DirInfo {
+  int8_t a, h, m, uh, um, wm_extra, pad0, pad1;  // wm = bits + wm_extra
+};
+struct DirTable {
+  DirInfo d[kMaxDirs];
+  int32_t bits;
+  int32_t num_dirs;
+};
+void make_dir_table(int bits, int num_dirs, DirTable *t);
+
+__device__ __forceinline__ uint32_t scan_code(int gx, int gy, int gz, const DirInfo &di, int bits) {
+  const int g[3] = {gx, gy, gz};
+  const uint32_t top = (1u << bits) - 1u;
+  const int ga = g[di.a];
+  const uint32_t eh = (uint32_t)(g[di.h] - di.uh * ga) + (di.uh > 0 ? (uint32_t)di.uh * top : 0u);
+  const uint32_t em = (uint32_t)(g[di.m] - di.um * ga) + (di.um > 0 ? (uint32_t)di.um * top : 0u);
+  const int wm = bits + di.wm_extra;
+  return (((eh << wm) + em) << bits) | (uint32_t)ga;
+}
+
+__device__ __forceinline__ void scan_decode(uint32_t code, const DirInfo &di, int bits, int g[3]) {
+  const uint32_t top = (1u << bits) - 1u;
+  const int wm = bits + di.wm_extra;
+  const int ga = (int)(code & top);
+  const int em = (int)((code >> bits) & ((1u << wm) - 1u));
+  const int eh = (int)(code >> (bits + wm));
+  g[di.a] = ga;
+  g[di.h] = eh + di.uh * ga - (di.uh > 0 ? di.uh * (int)top : 0);
+  g[di.m] = em + di.um * ga - (di.um > 0 ? di.um * (int)top : 0);
+}
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Fixed-order block reduction of NV doubles per thread (blockDim.x == 256).
+// Result valid in thread 0.  s_buf: >= 256 * NV doubles of LDS... uses a
+// wave shuffle tree then a 4-entry combine, so the order never changes.
+template <int NV>
+__device__ __forceinline__ void block_sum_f64(double (&v)[NV], double *s_buf) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] += __shfl_down(v[j], o, kWave);
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s_buf[w * NV + j] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      double acc = s_buf[j];
+      for (int ww = 1; ww < nw; ++ww) acc += s_buf[ww * NV + j];
+      v[j] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Exclusive scan of one uint32 per thread over a 256-thread block; also
+// returns the block total.  s_tmp: 4 uint32 of LDS.
+__device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_t *s_tmp, uint32_t *total) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == kWave - 1) s_tmp[w] = x;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int ww = 0; ww < w; ++ww) base += s_tmp[ww];
+  uint32_t tot = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// Last-block-done detection.  Every block calls it once after writing its
+// partial results; exactly one block (the last to arrive) gets true and may
+// then read all partials.  The counter is reset by that block.
+__device__ __forceinline__ bool last_block_arrival(unsigned *counter, unsigned nblocks) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == nblocks - 1u);
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+  }
+  return last;
+}
+
+// ---------------------------------------------------------------- control
+// Selection state of the filter sweeps, kept in the workspace.
+struct SweepCtrl {
+  double sigma_est;
+  double target;     // sigma_est^2
+  double y2_sel;     // sum over the FSLR subset of |y|^2
+  double best_loss;
+  double last_energy;
+  int32_t n_sel;     // |S| (all points when FSLR is off or S is empty)
+  int32_t use_all;
+  int32_t q;         // sweeps completed
+  int32_t best_q;
+  int32_t in_buf;    // buffer holding x_q (3 = caller input)
+  int32_t best_buf;  // buffer holding x_{best_q}
+  int32_t done;
+  int32_t select;    // 1: eq. 6 selection, 0: fixed q
+  int32_t q_limit;   // q_max (select) or q_fixed
+  int32_t pad;
+};
+
+// Counters used for last-block-done reductions (one per kernel kind).
+struct Counters {
+  unsigned merge;
+  unsigned noise;
+  unsigned sweep;
+  unsigned pad;
+};
+
+// ----------------------------------------------------------- workspace plan
+struct Plan {
+  int64_t n;
+  int32_t L, K, P, D;
+  int32_t ntiles;          // radix-sort tiles per direction
+  int32_t merge_blocks;
+  int32_t noise_blocks;
+  int32_t sweep_blocks;
+  int32_t npart_noise;     // doubles per noise partial
+  // byte offsets into the workspace
+  size_t off_items_a, off_items_b, off_hist, off_rank;
+  size_t off_col, off_dist2, off_p;
+  size_t off_spread, off_xbuf, off_merge_part, off_noise_part, off_sweep_part;
+  size_t off_ctrl, off_counters;
+  size_t total;
+};
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
+constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit codes
+
+constexpr int kBlock = 256;
+constexpr int kNoiseMaxBlocks = 1024;
+constexpr int kSweepParts = 5;  // doubles per sweep partial
+
+Plan make_plan(int64_t n, const fgbd_params &p);
+
+// ------------------------------------------------------------- profiling
+enum Kind { kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kSweep, kFinalize, kNumKinds };
+// Optional per-launch timing hook (events around each launch).
+struct Prof {
+  virtual void pre(int kind) = 0;
+  virtual void post() = 0;
+  virtual ~Prof() {}
+};
+#define FGBD_PRE(pf, kind) \
+  do {                     \
+    if (pf) (pf)->pre(kind); \
+  } while (0)
+#define FGBD_POST(pf)  \
+  do {                 \
+    if (pf) (pf)->post(); \
+  } while (0)
+
+// ------------------------------------------------------------- launchers
+// All launchers enqueue on `stream` and return hipSuccess or the launch error.
+hipError_t launch_init(fgbd_result *res, Counters *cnt, int zero_result, hipStream_t stream);
+
+hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const Plan &pl, uint64_t *items_a,
+                       uint64_t *items_b, uint32_t *hist, uint32_t *rank, fgbd_result *res, hipStream_t stream,
+                       const uint64_t **sorted_out, Prof *pf);
+
+hipError_t launch_merge(const int32_t *xyz, int64_t n, const DirTable &dt, int window, int k, const uint64_t *sorted,
+                        const uint32_t *rank, int32_t *col, int32_t *dist2, double *part, int nblocks,
+                        Counters *cnt, double sigma_g_fixed, fgbd_result *res, hipStream_t stream);
+
+hipError_t launch_weights(int64_t n, int k, const int32_t *col, const int32_t *dist2, const fgbd_result *res,
+                          float *p, hipStream_t stream);
+
+hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float *rgb, double *spread, float *eig3,
+                        double *part, int nblocks, Counters *cnt, fgbd_result *res, hipStream_t stream);
+
+hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, const float *rgb_in,
+                        float4 *xbuf, const double *spread, const fgbd_result *noise, double kappa, int select,
+                        int q_limit, int first, double *part, int nblocks, Counters *cnt, SweepCtrl *ctrl,
+                        hipStream_t stream);
+
+hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, const SweepCtrl *ctrl,
+                           const fgbd_result *noise, int q_none, float *rgb_out, fgbd_result *res,
+                           hipStream_t stream);
+
+}  // namespace fgbd

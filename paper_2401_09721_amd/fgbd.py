@@ -1,0 +1,329 @@
+"""Python binding of libfgbd (include/fgbd.h): argument marshalling only.
+
+Every step of the denoising path runs in the HIP library; this module turns
+torch device tensors into pointers, allocates outputs and the workspace with
+torch, and passes torch's current stream.  Loading fails loudly if the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfgbd.so")
+
+FGBD_OK = 0
+FGBD_E_INVALID = -1
+FGBD_E_NOMEM = -2
+FGBD_E_HIP = -3
+FGBD_E_WORKSPACE = -4
+FGBD_E_UNSUPPORTED = -5
+FGBD_ST_COORD_RANGE = 1
+FGBD_ST_NO_PATCH = 2
+NUM_KERNELS = 8
+KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "sweep", "finalize")
+
+
+class FgbdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"fgbd status {status}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("bits", ctypes.c_int32),
+        ("num_dirs", ctypes.c_int32),
+        ("window", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("patch", ctypes.c_int32),
+        ("q_max", ctypes.c_int32),
+        ("fslr_kappa", ctypes.c_double),
+        ("sigma_g", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [
+        ("col", ctypes.c_void_p),
+        ("dist2", ctypes.c_void_p),
+        ("p", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("k", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+
+RESULT_DTYPE = np.dtype([("sigma_est", "<f8"), ("sigma_g", "<f8"), ("loss", "<f8"), ("q", "<i4"),
+                         ("n_fslr", "<i4"), ("n_eff", "<i4"), ("status", "<i4"), ("sweeps", "<i4"), ("m", "<i4")])
+RESULT_BYTES = RESULT_DTYPE.itemsize  # 48
+
+_lib = None
+
+_SIGNATURES = {
+    "fgbd_abi_version": (ctypes.c_int32, []),
+    "fgbd_default_params": (ctypes.c_int, [ctypes.POINTER(Params)]),
+    "fgbd_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
+    "fgbd_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "fgbd_workspace_size": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+    "fgbd_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "fgbd_build_slg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Params),
+                                      ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_estimate_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p,
+                                           ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.POINTER(Params),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_denoise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_last_error": (ctypes.c_char_p, []),
+    "fgbd_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "fgbd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libfgbd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2401_09721_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != FGBD_OK:
+        raise FgbdError(status, lib().fgbd_last_error().decode())
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    _check(lib().fgbd_default_params(ctypes.byref(p)))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def as_params(params) -> Params:
+    if params is None:
+        return default_params()
+    if isinstance(params, Params):
+        return params
+    return default_params(**dict(params))
+
+
+def workspace_size(params, n_max: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().fgbd_workspace_size(ctypes.byref(as_params(params)), int(n_max), 1, ctypes.byref(out)))
+    return int(out.value)
+
+
+# ---------------------------------------------------------------- contexts
+def _torch():
+    import torch
+
+    return torch
+
+
+class Context:
+    """A library context bound to one GPU, with a torch-allocated workspace."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        dev = torch.device(device if device is not None else "cuda")
+        idx = dev.index if dev.index is not None else torch.cuda.current_device()
+        self.device = torch.device("cuda", idx)
+        h = ctypes.c_void_p()
+        _check(lib().fgbd_create(ctypes.byref(h), idx))
+        self.handle = h
+        self._ws = None
+        self._ws_bytes = 0
+
+    def reserve(self, params, n: int) -> None:
+        """Make sure the workspace covers clouds of n points."""
+        need = workspace_size(params, n)
+        if need > self._ws_bytes:
+            torch = _torch()
+            ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+            if ws.data_ptr() % 256:
+                raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
+            _check(lib().fgbd_set_workspace(self.handle, ctypes.c_void_p(ws.data_ptr()), need))
+            self._ws, self._ws_bytes = ws, need
+
+    def profile(self, enable: bool) -> None:
+        _check(lib().fgbd_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel kind: (summed ms, launches)} since the last read."""
+        ms = (ctypes.c_double * NUM_KERNELS)()
+        nl = (ctypes.c_int64 * NUM_KERNELS)()
+        _check(lib().fgbd_profile_read(self.handle, ms, nl, NUM_KERNELS))
+        return {KERNELS[i]: (ms[i], nl[i]) for i in range(NUM_KERNELS)}
+
+    def close(self) -> None:
+        if self.handle:
+            lib().fgbd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_contexts: dict = {}
+
+
+def default_context(device=None) -> Context:
+    torch = _torch()
+    dev = torch.device(device if device is not None else "cuda")
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx not in _contexts:
+        _contexts[idx] = Context(torch.device("cuda", idx))
+    return _contexts[idx]
+
+
+# ---------------------------------------------------------------- helpers
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0) if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(ctx: Context, stream=None) -> ctypes.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(ctx.device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape_tail, name, device):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [n, {', '.join(map(str, shape_tail))}]")
+
+
+def new_result(device) -> "object":
+    """A zeroed device fgbd_result (40 bytes as uint8)."""
+    torch = _torch()
+    return torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+
+
+def read_result(res) -> dict:
+    """Copy a device fgbd_result to the host (synchronises) and decode it."""
+    raw = res.detach().cpu().numpy().tobytes()
+    rec = np.frombuffer(raw, dtype=RESULT_DTYPE)[0]
+    return {name: rec[name].item() for name in RESULT_DTYPE.names}
+
+
+class SLGraph:
+    """Device CSR graph returned by build_slg."""
+
+    def __init__(self, col, dist2, p, result):
+        self.col, self.dist2, self.p, self.result = col, dist2, p, result
+
+    @property
+    def n(self) -> int:
+        return int(self.col.shape[0])
+
+    @property
+    def k(self) -> int:
+        return int(self.col.shape[1])
+
+    def c_struct(self) -> Graph:
+        return Graph(_ptr(self.col).value, _ptr(self.dist2).value, _ptr(self.p).value, self.n, self.k, 0)
+
+
+# ------------------------------------------------------------- the ABI calls
+def build_slg(xyz, params=None, ctx: Optional[Context] = None, stream=None) -> SLGraph:
+    """Scan-line graph of int32 [n, 3] device coordinates (Sec. 2.2)."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(xyz.device)
+    _need(xyz, torch.int32, (3,), "xyz", ctx.device)
+    n = int(xyz.shape[0])
+    ctx.reserve(prm, n)
+    col = torch.empty((n, prm.k), dtype=torch.int32, device=ctx.device)
+    dist2 = torch.empty((n, prm.k), dtype=torch.int32, device=ctx.device)
+    p = torch.empty((n, prm.k), dtype=torch.float32, device=ctx.device)
+    res = new_result(ctx.device)
+    g = SLGraph(col, dist2, p, res)
+    gs = g.c_struct()
+    _check(lib().fgbd_build_slg(ctx.handle, _ptr(xyz), n, ctypes.byref(prm), ctypes.byref(gs), _ptr(res),
+                                _stream(ctx, stream)))
+    return g
+
+
+def estimate_noise(graph: SLGraph, rgb, params=None, ctx: Optional[Context] = None, want_spread: bool = True,
+                   want_eig3: bool = False, stream=None):
+    """NE-GBP (Sec. 2.3).  Returns (result tensor, spread or None, eig3 or None)."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(rgb.device)
+    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    n = graph.n
+    if rgb.shape[0] != n:
+        raise ValueError("rgb and graph sizes differ")
+    ctx.reserve(prm, n)
+    res = new_result(ctx.device)
+    spread = torch.empty(n, dtype=torch.float64, device=ctx.device) if want_spread else None
+    eig3 = torch.empty((n, 3), dtype=torch.float32, device=ctx.device) if want_eig3 else None
+    gs = graph.c_struct()
+    _check(lib().fgbd_estimate_noise(ctx.handle, ctypes.byref(gs), _ptr(rgb), ctypes.byref(prm), _ptr(res),
+                                     _ptr(spread), _ptr(eig3), _stream(ctx, stream)))
+    return res, spread, eig3
+
+
+def filter(graph: SLGraph, rgb, params=None, noise=None, spread=None, q_fixed: int = 0,
+           ctx: Optional[Context] = None, stream=None):
+    """FSLR selection and the eq. 5 filter (noise given) or q_fixed sweeps.
+    Returns (rgb_out, result tensor)."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(rgb.device)
+    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    n = graph.n
+    ctx.reserve(prm, n)
+    out = torch.empty_like(rgb)
+    res = new_result(ctx.device)
+    gs = graph.c_struct()
+    _check(lib().fgbd_filter(ctx.handle, ctypes.byref(gs), _ptr(rgb), ctypes.byref(prm), _ptr(noise), _ptr(spread),
+                             int(q_fixed), _ptr(out), _ptr(res), _stream(ctx, stream)))
+    return out, res
+
+
+def denoise(xyz, rgb, params=None, ctx: Optional[Context] = None, out=None, res=None, stream=None):
+    """The whole per-frame path (Fig. 1(b)).  Returns (rgb_out, result tensor)."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(xyz.device)
+    _need(xyz, torch.int32, (3,), "xyz", ctx.device)
+    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    n = int(xyz.shape[0])
+    if rgb.shape[0] != n:
+        raise ValueError("xyz and rgb sizes differ")
+    ctx.reserve(prm, n)
+    out = torch.empty_like(rgb) if out is None else out
+    res = new_result(ctx.device) if res is None else res
+    _check(lib().fgbd_denoise(ctx.handle, _ptr(xyz), _ptr(rgb), n, ctypes.byref(prm), _ptr(out), _ptr(res),
+                              _stream(ctx, stream)))
+    return out, res

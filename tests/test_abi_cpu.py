@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function the header declares, and rejects bad arguments with the
+documented status before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2401_09721_amd import fgbd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fgbd.h")
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fgbd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = fgbd.lib()
+    names = declared_functions()
+    assert "fgbd_denoise" in names and len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(fgbd._SIGNATURES)
+
+
+def test_version_and_defaults():
+    assert fgbd.lib().fgbd_abi_version() == 1
+    p = fgbd.default_params()
+    assert (p.bits, p.num_dirs, p.window, p.k, p.patch, p.q_max) == (10, 8, 4, 8, 0, 32)
+    assert p.fslr_kappa == 2.0 and p.sigma_g == 0.0
+
+
+def test_workspace_size_grows_with_n():
+    p = fgbd.default_params()
+    a = fgbd.workspace_size(p, 1000)
+    b = fgbd.workspace_size(p, 1_000_000)
+    assert 0 < a < b
+    # at least the sort ping-pong buffers: 2 x L x n x 8 bytes
+    assert b >= 2 * 8 * 1_000_000 * 8
+    assert fgbd.workspace_size(p, 0) > 0
+
+
+@pytest.fixture()
+def ctx():
+    h = ctypes.c_void_p()
+    assert fgbd.lib().fgbd_create(ctypes.byref(h), 0) == 0
+    yield h
+    assert fgbd.lib().fgbd_destroy(h) == 0
+
+
+BAD_PARAMS = [
+    dict(bits=0), dict(bits=-3), dict(num_dirs=0), dict(num_dirs=17), dict(window=0), dict(window=65),
+    dict(k=0), dict(k=33), dict(patch=-1), dict(patch=9), dict(q_max=-1), dict(q_max=5000),
+    dict(fslr_kappa=float("nan")), dict(sigma_g=float("inf")),
+]
+
+
+@pytest.mark.parametrize("bad", BAD_PARAMS)
+def test_invalid_params_rejected(ctx, bad):
+    lib = fgbd.lib()
+    p = fgbd.default_params(**bad)
+    res = FAKE
+    st = lib.fgbd_denoise(ctx, FAKE, FAKE, 100, ctypes.byref(p), ctypes.c_void_p(0x900000), res, None)
+    assert st == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_last_error().decode()
+    out = ctypes.c_size_t()
+    assert lib.fgbd_workspace_size(ctypes.byref(p), 10, 1, ctypes.byref(out)) == fgbd.FGBD_E_INVALID
+
+
+def test_bits_above_10_unsupported(ctx):
+    p = fgbd.default_params(bits=11)
+    st = fgbd.lib().fgbd_denoise(ctx, FAKE, FAKE, 100, ctypes.byref(p), ctypes.c_void_p(0x900000), FAKE, None)
+    assert st == fgbd.FGBD_E_UNSUPPORTED
+
+
+def test_null_and_size_errors(ctx):
+    lib = fgbd.lib()
+    p = fgbd.default_params()
+    far = ctypes.c_void_p(0x900000)
+    null = ctypes.c_void_p(0)
+    E = fgbd.FGBD_E_INVALID
+    assert lib.fgbd_denoise(None, FAKE, FAKE, 10, ctypes.byref(p), far, FAKE, None) == E
+    assert lib.fgbd_denoise(ctx, null, FAKE, 10, ctypes.byref(p), far, FAKE, None) == E
+    assert lib.fgbd_denoise(ctx, FAKE, null, 10, ctypes.byref(p), far, FAKE, None) == E
+    assert lib.fgbd_denoise(ctx, FAKE, FAKE, 10, ctypes.byref(p), null, FAKE, None) == E
+    assert lib.fgbd_denoise(ctx, FAKE, FAKE, 10, ctypes.byref(p), far, null, None) == E
+    assert lib.fgbd_denoise(ctx, FAKE, FAKE, -1, ctypes.byref(p), far, FAKE, None) == E
+    assert lib.fgbd_denoise(ctx, FAKE, FAKE, 1 << 40, ctypes.byref(p), far, FAKE, None) == E
+    assert lib.fgbd_denoise(ctx, FAKE, FAKE, 10, None, far, FAKE, None) == E
+    # overlapping input and output colours
+    assert lib.fgbd_denoise(ctx, FAKE, FAKE, 10, ctypes.byref(p), ctypes.c_void_p(0x1000 + 60), FAKE, None) == E
+    assert "overlap" in lib.fgbd_last_error().decode()
+
+
+def test_graph_call_errors(ctx):
+    lib = fgbd.lib()
+    p = fgbd.default_params()
+    E = fgbd.FGBD_E_INVALID
+    g = fgbd.Graph(0x1000, 0x2000, 0x3000, 10, 8, 0)
+    bad_k = fgbd.Graph(0x1000, 0x2000, 0x3000, 10, 6, 0)
+    assert lib.fgbd_build_slg(ctx, FAKE, 11, ctypes.byref(p), ctypes.byref(g), FAKE, None) == E  # n mismatch
+    assert lib.fgbd_build_slg(ctx, FAKE, 10, ctypes.byref(p), ctypes.byref(bad_k), FAKE, None) == E
+    assert lib.fgbd_build_slg(ctx, FAKE, 10, ctypes.byref(p), None, FAKE, None) == E
+    assert lib.fgbd_estimate_noise(ctx, ctypes.byref(bad_k), FAKE, ctypes.byref(p), FAKE, None, None, None) == E
+    assert lib.fgbd_estimate_noise(ctx, ctypes.byref(g), None, ctypes.byref(p), FAKE, None, None, None) == E
+    # selection with FSLR needs the patch spread
+    far = ctypes.c_void_p(0x900000)
+    assert lib.fgbd_filter(ctx, ctypes.byref(g), FAKE, ctypes.byref(p), FAKE, None, 0, far, FAKE, None) == E
+    assert "patch_spread" in lib.fgbd_last_error().decode()
+    assert lib.fgbd_filter(ctx, ctypes.byref(g), FAKE, ctypes.byref(p), None, None, -2, far, FAKE, None) == E
+
+
+def test_workspace_setting(ctx):
+    lib = fgbd.lib()
+    assert lib.fgbd_set_workspace(ctx, ctypes.c_void_p(0x1001), 100) == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_set_workspace(ctx, ctypes.c_void_p(0x1000), 0) == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_set_workspace(ctx, None, 0) == 0
+    assert lib.fgbd_set_workspace(None, None, 0) == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_create(None, 0) == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_destroy(None) == 0
+
+
+def test_profile_calls(ctx):
+    lib = fgbd.lib()
+    ms = (ctypes.c_double * 8)()
+    nl = (ctypes.c_int64 * 8)()
+    assert lib.fgbd_profile_enable(ctx, 1) == 0
+    assert lib.fgbd_profile_read(ctx, ms, nl, 8) == 0
+    assert list(nl) == [0] * 8
+    assert lib.fgbd_profile_read(ctx, ms, nl, 9) == fgbd.FGBD_E_INVALID
