@@ -99,11 +99,12 @@ Plan make_plan(int64_t n, const fgbd_params &p) {
   pl.P = p.patch > 0 ? p.patch : p.k;
   pl.D = pl.P + 1;
   pl.ntiles = (int32_t)((n + kSortTile - 1) / kSortTile);
-  pl.merge_blocks = (int32_t)((n + kBlock - 1) / kBlock);
+  const int64_t chunks = (n + kBlock - 1) / kBlock;
+  pl.merge_blocks = (int32_t)(chunks < 1 ? 1 : (chunks < kMaxGrid ? chunks : kMaxGrid));
   pl.sweep_blocks = pl.merge_blocks;
   const int TP = pl.D <= 17 ? 256 : 128;
   const int64_t ptiles = (n + TP - 1) / TP;
-  pl.noise_blocks = (int32_t)(ptiles < kNoiseMaxBlocks ? ptiles : kNoiseMaxBlocks);
+  pl.noise_blocks = (int32_t)(ptiles < 1 ? 1 : (ptiles < kMaxGrid ? ptiles : kMaxGrid));
   pl.npart_noise = 1 + pl.D * (pl.D + 1) / 2 + 3 * pl.D;
   const size_t N = (size_t)(n > 0 ? n : 1);
   size_t off = 0;
@@ -123,23 +124,16 @@ Plan make_plan(int64_t n, const fgbd_params &p) {
   pl.off_xbuf = take(3 * N * 16);
   pl.off_merge_part = take((size_t)(pl.merge_blocks > 0 ? pl.merge_blocks : 1) * 2 * 8);
   pl.off_noise_part = take((size_t)(pl.noise_blocks > 0 ? pl.noise_blocks : 1) * pl.npart_noise * 8);
-  pl.off_sweep_part = take((size_t)(pl.sweep_blocks > 0 ? pl.sweep_blocks : 1) * kSweepParts * 8);
-  pl.off_ctrl = take(sizeof(SweepCtrl));
-  pl.off_counters = take(sizeof(Counters));
+  pl.off_sweep_part = take((size_t)2 * pl.sweep_blocks * kSweepParts * 8);
+  pl.off_ctrl = take(2 * sizeof(SweepCtrl));
   pl.total = off;
   return pl;
 }
 
 namespace {
 
-__global__ void k_init(fgbd_result *res, Counters *cnt, int zero_result) {
+__global__ void k_init(fgbd_result *res, int zero_result) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (cnt) {
-      cnt->merge = 0;
-      cnt->noise = 0;
-      cnt->sweep = 0;
-      cnt->pad = 0;
-    }
     if (zero_result && res) {
       res->sigma_est = 0.0;
       res->sigma_g = 0.0;
@@ -156,8 +150,8 @@ __global__ void k_init(fgbd_result *res, Counters *cnt, int zero_result) {
 
 }  // namespace
 
-hipError_t launch_init(fgbd_result *res, Counters *cnt, int zero_result, hipStream_t stream) {
-  k_init<<<1, 64, 0, stream>>>(res, cnt, zero_result);
+hipError_t launch_init(fgbd_result *res, int zero_result, hipStream_t stream) {
+  k_init<<<1, 64, 0, stream>>>(res, zero_result);
   return hipGetLastError();
 }
 
@@ -280,8 +274,7 @@ struct Bufs {
   double *spread;
   float4 *xbuf;
   double *merge_part, *noise_part, *sweep_part;
-  SweepCtrl *ctrl;
-  Counters *cnt;
+  SweepCtrl *ctrl;  // two states (ping-pong)
 };
 
 Bufs carve(char *ws, const Plan &pl) {
@@ -299,7 +292,6 @@ Bufs carve(char *ws, const Plan &pl) {
   b.noise_part = (double *)(ws + pl.off_noise_part);
   b.sweep_part = (double *)(ws + pl.off_sweep_part);
   b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
-  b.cnt = (Counters *)(ws + pl.off_counters);
   return b;
 }
 
@@ -320,12 +312,13 @@ fgbd_status run_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_para
   HIP_TRY(launch_sort(xyz, n, dt, pl, b.items_a, b.items_b, b.hist, b.rank, res, s, &sorted, pf),
           "radix sort launch");
   FGBD_PRE(pf, kMerge);
-  HIP_TRY(launch_merge(xyz, n, dt, prm.window, prm.k, sorted, b.rank, col, dist2, b.merge_part, pl.merge_blocks,
-                       b.cnt, prm.sigma_g, res, s),
+  HIP_TRY(launch_merge(xyz, n, dt, prm.window, prm.k, sorted, b.rank, col, dist2, b.merge_part, pl.merge_blocks, s),
           "neighbour merge launch");
   FGBD_POST(pf);
   FGBD_PRE(pf, kWeights);
-  HIP_TRY(launch_weights(n, prm.k, col, dist2, res, p, s), "weights launch");
+  HIP_TRY(launch_weights(n, prm.k, col, dist2, b.merge_part, pl.merge_blocks, prm.sigma_g, res, p, pl.merge_blocks,
+                         s),
+          "weights launch");
   FGBD_POST(pf);
   return FGBD_OK;
 }
@@ -336,8 +329,10 @@ fgbd_status run_noise(fgbd_ctx ctx, int64_t n, const fgbd_params &prm, const Pla
   EventProf ep(ctx, s);
   Prof *pf = ctx->profile ? &ep : nullptr;
   FGBD_PRE(pf, kNoise);
-  HIP_TRY(launch_noise(n, prm.k, pl.P, col, rgb, spread, eig3, b.noise_part, pl.noise_blocks, b.cnt, res, s),
-          "noise launch");
+  HIP_TRY(launch_noise(n, prm.k, pl.P, col, rgb, spread, eig3, b.noise_part, pl.noise_blocks, s), "noise launch");
+  FGBD_POST(pf);
+  FGBD_PRE(pf, kNoiseSolve);
+  HIP_TRY(launch_noise_solve(pl.P, b.noise_part, pl.noise_blocks, res, s), "noise solve launch");
   FGBD_POST(pf);
   return FGBD_OK;
 }
@@ -349,15 +344,16 @@ fgbd_status run_filter(fgbd_ctx ctx, int64_t n, const fgbd_params &prm, const Pl
   EventProf ep(ctx, s);
   Prof *pf = ctx->profile ? &ep : nullptr;
   const int sweeps = q_limit > 0 ? q_limit : 1;
-  for (int q = 0; q < sweeps; ++q) {
+  for (int q = 1; q <= sweeps; ++q) {
     FGBD_PRE(pf, kSweep);
-    HIP_TRY(launch_sweep(n, prm.k, col, p, rgb_in, b.xbuf, spread, noise, prm.fslr_kappa, select, q_limit, q == 0,
-                         b.sweep_part, pl.sweep_blocks, b.cnt, b.ctrl, s),
+    HIP_TRY(launch_sweep(n, prm.k, col, p, rgb_in, b.xbuf, spread, noise, prm.fslr_kappa, select, q_limit, q,
+                         b.sweep_part, pl.sweep_blocks, b.ctrl, s),
             "sweep launch");
     FGBD_POST(pf);
   }
   FGBD_PRE(pf, kFinalize);
-  HIP_TRY(launch_finalize(n, rgb_in, b.xbuf, b.ctrl, noise, 0, rgb_out, res, s), "finalize launch");
+  HIP_TRY(launch_finalize(n, rgb_in, b.xbuf, sweeps, b.sweep_part, pl.sweep_blocks, b.ctrl, noise, rgb_out, res, s),
+          "finalize launch");
   FGBD_POST(pf);
   return FGBD_OK;
 }
@@ -447,7 +443,7 @@ fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fg
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(res, b.cnt, 1, s), "init launch");
+  HIP_TRY(launch_init(res, 1, s), "init launch");
   if (n == 0) return ok();
   if ((st = run_slg(ctx, xyz, n, *params, pl, b, g->col, g->dist2, g->p, res, s)) != FGBD_OK) return st;
   return ok();
@@ -471,9 +467,8 @@ fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(nullptr, b.cnt, 0, s), "init launch");
   if (n == 0) {
-    HIP_TRY(launch_init(res, nullptr, 2, s), "init launch");
+    HIP_TRY(launch_init(res, 2, s), "init launch");
     return ok();
   }
   if ((st = run_noise(ctx, n, *params, pl, b, g->col, rgb, patch_spread ? patch_spread : b.spread, eig3, res, s)) !=
@@ -507,9 +502,8 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(nullptr, b.cnt, 0, s), "init launch");
   if (n == 0) {
-    HIP_TRY(launch_init(res, nullptr, 1, s), "init launch");
+    HIP_TRY(launch_init(res, 1, s), "init launch");
     return ok();
   }
   const int q_limit = select ? params->q_max : q_fixed;
@@ -536,7 +530,7 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(res, b.cnt, n == 0 ? 2 : 1, s), "init launch");
+  HIP_TRY(launch_init(res, n == 0 ? 2 : 1, s), "init launch");
   if (n == 0) return ok();
   if ((st = run_slg(ctx, xyz, n, *params, pl, b, b.col, b.dist2, b.p, res, s)) != FGBD_OK) return st;
   if ((st = run_noise(ctx, n, *params, pl, b, b.col, rgb_in, b.spread, nullptr, res, s)) != FGBD_OK) return st;

@@ -109,24 +109,81 @@ __device__ __forceinline__ uint32_t block_exclusive_scan_256(uint32_t v, uint32_
   return base + x - v;
 }
 
-// Last-block-done detection.  Every block calls it once after writing its
-// partial results; exactly one block (the last to arrive) gets true and may
-// then read all partials.  The counter is reset by that block.
-__device__ __forceinline__ bool last_block_arrival(unsigned *counter, unsigned nblocks) {
-  __shared__ int s_last;
-  __threadfence();
+// Exclusive scan of one uint32 per thread over a block of blockDim.x threads
+// (a multiple of 64, at most 1024).  s_tmp: 16 uint32 of LDS.  Returns the
+// exclusive prefix; *total receives the block total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp, uint32_t *total) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == kWave - 1) s_tmp[w] = x;
   __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (int ww = 0; ww < nw; ++ww) {
+    const uint32_t c = s_tmp[ww];
+    base += ww < w ? c : 0u;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// Totals of per-block partial sums (nparts rows of `stride` doubles, first NV
+// used).  Every block that calls this sums the same rows in the same order,
+// so all blocks obtain bit-identical totals without any inter-block
+// synchronisation inside a kernel: the partials were written by an earlier
+// launch on the same stream.  s_buf: >= 4 * NV doubles of LDS.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int nparts, int stride,
+                                                double (&out)[NV], double *s_buf) {
+  double v[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) v[j] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] += part[(size_t)b * stride + j];
+  }
+  block_sum_f64<NV>(v, s_buf);
   if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == nblocks - 1u);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) s_buf[j] = v[j];
   }
   __syncthreads();
-  const bool last = s_last != 0;
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-  }
-  return last;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) out[j] = s_buf[j];
+  __syncthreads();
+}
+
+// XCD-aware work split for grid-stride kernels over n points.  Workgroups are
+// dispatched to the 8 XCDs round-robin by block index, and each XCD has its
+// own L2; giving each XCD one contiguous share of the points keeps the
+// neighbour gathers of spatially ordered clouds inside one L2.  Block b works
+// on XCD share b % 8, as block b / 8 of the blocks of that share.
+constexpr int kXcds = 8;
+struct Share {
+  int64_t begin, end;  // points of this block's XCD share
+  int64_t first;       // first chunk start for this block
+  int64_t step;        // chunk stride
+};
+__device__ __forceinline__ Share xcd_share(int64_t n, int chunk) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int nx = G < kXcds ? G : kXcds;
+  const int x = b % nx;
+  const int nb = (G - x + nx - 1) / nx;
+  const int lb = b / nx;
+  Share s;
+  s.begin = n * x / nx;
+  s.end = n * (x + 1) / nx;
+  s.first = s.begin + (int64_t)lb * chunk;
+  s.step = (int64_t)nb * chunk;
+  return s;
 }
 
 // ---------------------------------------------------------------- control
@@ -146,16 +203,9 @@ struct SweepCtrl {
   int32_t done;
   int32_t select;    // 1: eq. 6 selection, 0: fixed q
   int32_t q_limit;   // q_max (select) or q_fixed
-  int32_t pad;
+  int32_t fslr;      // FSLR subset in use (select and kappa > 0)
 };
 
-// Counters used for last-block-done reductions (one per kernel kind).
-struct Counters {
-  unsigned merge;
-  unsigned noise;
-  unsigned sweep;
-  unsigned pad;
-};
 
 // ----------------------------------------------------------- workspace plan
 struct Plan {
@@ -170,7 +220,7 @@ struct Plan {
   size_t off_items_a, off_items_b, off_hist, off_rank;
   size_t off_col, off_dist2, off_p;
   size_t off_spread, off_xbuf, off_merge_part, off_noise_part, off_sweep_part;
-  size_t off_ctrl, off_counters;
+  size_t off_ctrl;
   size_t total;
 };
 
@@ -180,13 +230,14 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
 constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit codes
 
 constexpr int kBlock = 256;
-constexpr int kNoiseMaxBlocks = 1024;
+constexpr int kMaxGrid = 1024;  // grid of the grid-stride kernels
 constexpr int kSweepParts = 5;  // doubles per sweep partial
+constexpr int kScanThreads = 1024;
 
 Plan make_plan(int64_t n, const fgbd_params &p);
 
 // ------------------------------------------------------------- profiling
-enum Kind { kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kSweep, kFinalize, kNumKinds };
+enum Kind { kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kNoiseSolve, kSweep, kFinalize, kNumKinds };
 // Optional per-launch timing hook (events around each launch).
 struct Prof {
   virtual void pre(int kind) = 0;
@@ -204,29 +255,34 @@ struct Prof {
 
 // ------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
-hipError_t launch_init(fgbd_result *res, Counters *cnt, int zero_result, hipStream_t stream);
+hipError_t launch_init(fgbd_result *res, int zero_result, hipStream_t stream);
 
 hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const Plan &pl, uint64_t *items_a,
                        uint64_t *items_b, uint32_t *hist, uint32_t *rank, fgbd_result *res, hipStream_t stream,
                        const uint64_t **sorted_out, Prof *pf);
 
+// neighbour selection; writes per-block edge-length partials (2 doubles)
 hipError_t launch_merge(const int32_t *xyz, int64_t n, const DirTable &dt, int window, int k, const uint64_t *sorted,
                         const uint32_t *rank, int32_t *col, int32_t *dist2, double *part, int nblocks,
-                        Counters *cnt, double sigma_g_fixed, fgbd_result *res, hipStream_t stream);
-
-hipError_t launch_weights(int64_t n, int k, const int32_t *col, const int32_t *dist2, const fgbd_result *res,
-                          float *p, hipStream_t stream);
-
-hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float *rgb, double *spread, float *eig3,
-                        double *part, int nblocks, Counters *cnt, fgbd_result *res, hipStream_t stream);
-
-hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, const float *rgb_in,
-                        float4 *xbuf, const double *spread, const fgbd_result *noise, double kappa, int select,
-                        int q_limit, int first, double *part, int nblocks, Counters *cnt, SweepCtrl *ctrl,
                         hipStream_t stream);
 
-hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, const SweepCtrl *ctrl,
-                           const fgbd_result *noise, int q_none, float *rgb_out, fgbd_result *res,
-                           hipStream_t stream);
+// sigma_g from the merge partials (or the fixed value) and eq. 4 weights
+hipError_t launch_weights(int64_t n, int k, const int32_t *col, const int32_t *dist2, const double *merge_part,
+                          int merge_blocks, double sigma_g_fixed, fgbd_result *res, float *p, int nblocks,
+                          hipStream_t stream);
+
+hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float *rgb, double *spread, float *eig3,
+                        double *part, int nblocks, hipStream_t stream);
+
+hipError_t launch_noise_solve(int P, const double *part, int nblocks, fgbd_result *res, hipStream_t stream);
+
+// Sweep number q (1-based) of q_launches; reads ctrl/part[(q-1)&1], writes [q&1].
+hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf,
+                        const double *spread, const fgbd_result *noise, double kappa, int select, int q_limit,
+                        int q, double *part2, int nblocks, SweepCtrl *ctrl2, hipStream_t stream);
+
+hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, int q_launches, const double *part2,
+                           int nblocks, const SweepCtrl *ctrl2, const fgbd_result *noise, float *rgb_out,
+                           fgbd_result *res, hipStream_t stream);
 
 }  // namespace fgbd

@@ -16,7 +16,8 @@
 // D(D+1)/2 entries) and of the per-channel sums, and walks a fixed set of
 // rows, so all sums have a fixed order (products of two floats are exact in
 // FP64).  Incomplete patches contribute zero rows and are not counted.
-// The last block to finish reduces the block partials in block order, forms
+// Each block writes its partial sums; k_noise_solve (one block) reduces them
+// in block order, forms
 //   Sigma = (S2 - sum_c s1_c s1_c^T / N) / (3 N),
 // finds its eigenvalues with a parallel cyclic Jacobi method (round-robin
 // pair ordering, FP64), and applies the tail rule: the smallest m with
@@ -136,13 +137,10 @@ __device__ void jacobi_eigs(double *A, int Dp, double *s_c, double *s_s, int *s_
 
 __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__restrict__ col,
                                                   const float *__restrict__ rgb, double *__restrict__ spread,
-                                                  float *__restrict__ eig3, double *__restrict__ part,
-                                                  Counters *__restrict__ cnt, fgbd_result *__restrict__ res) {
+                                                  float *__restrict__ eig3, double *__restrict__ part) {
   extern __shared__ float s_v[];  // [3 * TP][D] patch rows of the current tile
   __shared__ uint16_t s_pair[kMaxD * (kMaxD + 1) / 2];
   __shared__ double s_red[8];
-  __shared__ double s_jc[kMaxD], s_js[kMaxD];
-  __shared__ int s_jp[kMaxD], s_jq[kMaxD], s_flag;
 
   const int t = threadIdx.x;
   const int D = a.D, P = a.P, K = a.K, TP = a.TP;
@@ -161,15 +159,15 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   const int rows = 3 * TP;
   __syncthreads();
 
-  const int64_t ntile = ((int64_t)a.n + TP - 1) / TP;
-  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+  const Share sh = xcd_share(a.n, TP);
+  for (int64_t tbase = sh.first; tbase < sh.end; tbase += sh.step) {
     if (t < TP) {
-      const int64_t i = tile * TP + t;
+      const int64_t i = tbase + t;
       float *r0 = s_v + (size_t)(3 * t + 0) * D;
       float *r1 = s_v + (size_t)(3 * t + 1) * D;
       float *r2 = s_v + (size_t)(3 * t + 2) * D;
       bool complete = false;
-      if (i < a.n) complete = col[i * K + (P - 1)] >= 0;
+      if (i < sh.end) complete = col[i * K + (P - 1)] >= 0;
       if (complete) {
         r0[0] = rgb[3 * i + 0];
         r1[0] = rgb[3 * i + 1];
@@ -218,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
           r1[k] = 0.0f;
           r2[k] = 0.0f;
         }
-        if (i < a.n) {
+        if (i < sh.end) {
           spread[i] = __builtin_huge_val();
           if (a.want_eig3) {
             eig3[3 * i + 0] = 0.0f;
@@ -270,23 +268,29 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   } else {
     for (int e = t; e < a.E; e += kBlock) dst[e] = scratch[3 * (e % kBlock) + e / kBlock];
   }
-  __syncthreads();
+}
 
-  if (!last_block_arrival(&cnt->noise, gridDim.x)) return;
-
-  // ---- last block: reduce partials over blocks in block order
-  const int nb = gridDim.x;
+// One block: sum the k_noise partials in block order, form Sigma, find its
+// eigenvalues (parallel Jacobi, FP64) and apply the tail rule.
+__global__ __launch_bounds__(kBlock) void k_noise_solve(NoiseArgs a, const double *__restrict__ part, int nb,
+                                                        fgbd_result *__restrict__ res) {
+  __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
+  __shared__ double s_jc[kMaxD], s_js[kMaxD];
+  __shared__ int s_jp[kMaxD], s_jq[kMaxD], s_flag;
+  const int t = threadIdx.x;
+  const int D = a.D;
   const int stride = 1 + a.E;
-  double *tot = scratch;  // [1 + E]
+  double *tot = s_buf;
   for (int e = t; e < stride; e += kBlock) {
     double s = 0.0;
+#pragma unroll 16
     for (int b = 0; b < nb; ++b) s += part[(size_t)b * stride + e];
     tot[e] = s;
   }
   __syncthreads();
   const double n_eff = tot[0];
   const int Dp = D + (D & 1);
-  double *A = tot + stride + (stride & 1);  // Dp x Dp, 8-byte aligned
+  double *A = tot + stride + (stride & 1);  // Dp x Dp
   if (n_eff > 0.0) {
     const double *S2 = tot + 1;
     const double *S1 = tot + 1 + a.E2;
@@ -338,10 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   }
 }
 
-}  // namespace
-
-hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float *rgb, double *spread, float *eig3,
-                        double *part, int nblocks, Counters *cnt, fgbd_result *res, hipStream_t stream) {
+NoiseArgs make_args(int64_t n, int k, int P, bool want_eig3) {
   NoiseArgs a;
   a.n = (int32_t)n;
   a.K = k;
@@ -351,9 +352,23 @@ hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float
   a.E2 = a.D * (a.D + 1) / 2;
   a.E = a.E2 + 3 * a.D;
   a.groups = a.E <= kBlock ? kBlock / a.E : 1;
-  a.want_eig3 = eig3 != nullptr;
+  a.want_eig3 = want_eig3;
+  return a;
+}
+
+}  // namespace
+
+hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float *rgb, double *spread, float *eig3,
+                        double *part, int nblocks, hipStream_t stream) {
+  const NoiseArgs a = make_args(n, k, P, eig3 != nullptr);
   const size_t lds = (size_t)3 * a.TP * a.D * sizeof(float);
-  k_noise<<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part, cnt, res);
+  k_noise<<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_noise_solve(int P, const double *part, int nblocks, fgbd_result *res, hipStream_t stream) {
+  const NoiseArgs a = make_args(0, P, P, false);
+  k_noise_solve<<<1, kBlock, 0, stream>>>(a, part, nblocks, res);
   return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@
 // because every pass is stable.
 //
 // Per 8-bit digit pass (4 passes for 32-bit codes):
-//   upsweep   per tile digit histogram            -> hist[dir][tile][256]
+//   upsweep   per tile digit histogram            -> hist[dir][digit][tile]
 //   scan      exclusive prefix over (digit, tile)  -> global offsets, in place
 //   downsweep stable rank inside the tile (wave-level match of digits with
 //             64-bit ballots, per-wave counters in LDS), stage in LDS in digit
@@ -64,24 +64,38 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
   }
   if (bad && d == 0) atomicOr(&res->status, FGBD_ST_COORD_RANGE);
   __syncthreads();
-  hist[((size_t)d * a.ntiles + tile) * 256 + t] = s_h[t];
+  hist[((size_t)d * 256 + t) * a.ntiles + tile] = s_h[t];
 }
 
-// Exclusive prefix over (digit major, tile minor) per direction; one block per
-// direction, thread = digit, tiles walked in order (coalesced rows of 256).
-__global__ __launch_bounds__(256) void k_sort_scan(int ntiles, uint32_t *__restrict__ hist) {
-  __shared__ uint32_t s_tmp[4];
+// Exclusive prefix over the digit-major histogram of one direction (one block
+// per direction, 1024 threads, chunks of 8 consecutive counts per thread with
+// a running carry), which turns the count of (digit, tile) into its global
+// output offset.
+constexpr int kScanItems = 8;
+__global__ __launch_bounds__(kScanThreads) void k_sort_scan(int ntiles, uint32_t *__restrict__ hist) {
+  __shared__ uint32_t s_tmp[16];
   const int d = blockIdx.x;
   const int t = threadIdx.x;
-  uint32_t *h = hist + (size_t)d * ntiles * 256;
-  uint32_t sum = 0;
-  for (int tile = 0; tile < ntiles; ++tile) sum += h[(size_t)tile * 256 + t];
-  uint32_t total;
-  uint32_t run = block_exclusive_scan_256(sum, s_tmp, &total);
-  for (int tile = 0; tile < ntiles; ++tile) {
-    const uint32_t v = h[(size_t)tile * 256 + t];
-    h[(size_t)tile * 256 + t] = run;
-    run += v;
+  const int64_t total = (int64_t)256 * ntiles;
+  uint32_t *h = hist + (size_t)d * total;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < total; base += (int64_t)kScanThreads * kScanItems) {
+    const int64_t i0 = base + (int64_t)t * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      v[j] = (i0 + j < total) ? h[i0 + j] : 0u;
+      sum += v[j];
+    }
+    uint32_t chunk_total;
+    uint32_t run = carry + block_exclusive_scan(sum, s_tmp, &chunk_total);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      if (i0 + j < total) h[i0 + j] = run;
+      run += v[j];
+    }
+    carry += chunk_total;
   }
 }
 
@@ -108,7 +122,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   s_wh[1][t] = 0;
   s_wh[2][t] = 0;
   s_wh[3][t] = 0;
-  s_off[t] = hist[((size_t)d * a.ntiles + tile) * 256 + t];
+  s_off[t] = hist[((size_t)d * 256 + t) * a.ntiles + tile];
 
   uint64_t item[kSortItems];
   const int base = tile0 + wave * kWave * kSortItems + lane;
@@ -192,7 +206,7 @@ hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const 
     k_sort_upsweep<<<grid, kSortThreads, 0, stream>>>(a, xyz, src, hist, res);
     FGBD_POST(pf);
     FGBD_PRE(pf, kScan);
-    k_sort_scan<<<dt.num_dirs, 256, 0, stream>>>(pl.ntiles, hist);
+    k_sort_scan<<<dt.num_dirs, kScanThreads, 0, stream>>>(pl.ntiles, hist);
     FGBD_POST(pf);
     FGBD_PRE(pf, kDownsweep);
     k_sort_downsweep<<<grid, kSortThreads, 0, stream>>>(a, xyz, src, dst, hist, rank);

@@ -23,8 +23,9 @@ FGBD_E_WORKSPACE = -4
 FGBD_E_UNSUPPORTED = -5
 FGBD_ST_COORD_RANGE = 1
 FGBD_ST_NO_PATCH = 2
-NUM_KERNELS = 8
-KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "sweep", "finalize")
+NUM_KERNELS = 9
+KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
+           "finalize")
 
 
 class FgbdError(RuntimeError):

@@ -129,9 +129,9 @@ def test_workspace_setting(ctx):
 
 def test_profile_calls(ctx):
     lib = fgbd.lib()
-    ms = (ctypes.c_double * 8)()
-    nl = (ctypes.c_int64 * 8)()
+    ms = (ctypes.c_double * 9)()
+    nl = (ctypes.c_int64 * 9)()
     assert lib.fgbd_profile_enable(ctx, 1) == 0
-    assert lib.fgbd_profile_read(ctx, ms, nl, 8) == 0
-    assert list(nl) == [0] * 8
-    assert lib.fgbd_profile_read(ctx, ms, nl, 9) == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_profile_read(ctx, ms, nl, 9) == 0
+    assert list(nl) == [0] * 9
+    assert lib.fgbd_profile_read(ctx, ms, nl, 10) == fgbd.FGBD_E_INVALID
