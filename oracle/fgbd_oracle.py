@@ -477,4 +477,6 @@ def poly_filter_grads(col, dist2, x, coef, sigma_g: float, grad_out):
         out = out + ct[k] * xk
     g = torch.as_tensor(np.asarray(grad_out, np.float64))
     (out * g).sum().backward()
-    return xt.grad.numpy(), ct.grad.numpy(), float(st.grad)
+    # with one coefficient the output c_0 x does not involve T, so d/dsigma_g = 0
+    gs = float(st.grad) if st.grad is not None else 0.0
+    return xt.grad.numpy(), ct.grad.numpy(), gs

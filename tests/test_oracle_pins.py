@@ -436,3 +436,16 @@ def test_poly_grads_central_differences():
         e[i, ch] = h
         assert math.isclose(gx[i, ch], (f(x + e, coef, sg) - f(x - e, coef, sg)) / (2 * h),
                             rel_tol=1e-6, abs_tol=1e-9)
+
+
+def test_poly_grads_single_coefficient():
+    """out = c_0 x does not involve T: d/dsigma_g = 0 and d/dx = c_0 g."""
+    rng = np.random.default_rng(9)
+    g = np.unique(_rand_cloud(rng, 100, 4), axis=0)
+    col, d2 = O.slg_graph(g, 4, 3, 1, 6)
+    x = rng.uniform(0, 255, size=(g.shape[0], 3))
+    go = rng.standard_normal(x.shape)
+    gx, gc, gs = O.poly_filter_grads(col, d2, x, np.array([0.7]), 1.3, go)
+    assert gs == 0.0
+    assert np.allclose(gx, 0.7 * go)
+    assert math.isclose(gc[0], float(np.sum(go * x)), rel_tol=1e-12)
