@@ -155,6 +155,28 @@ def main() -> int:
                             "us_per_launch": kernels[dom]["us_per_launch"]}
         print(f"# kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
+        # Active sweeps alone (the filter at a fixed q: every launch computes a
+        # sweep), the kernel the bandwidth target is set on.
+        g = fgbd.build_slg(xyz, prm, ctx=ctx)
+        qf = 8
+        fgbd.filter(g, rgb, prm, q_fixed=qf, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        for _ in range(args.steps):
+            fgbd.filter(g, rgb, prm, q_fixed=qf, ctx=ctx)
+        torch.cuda.synchronize()
+        sp = ctx.profile_read()
+        ctx.profile(False)
+        ms, launches = sp["sweep"]
+        per_launch = ms / launches
+        b = algorithmic_bytes("sweep", n, prm.num_dirs, prm.k, P)
+        line["roofline_sweep"] = {"kernel": "sweep (fixed q, every launch active)", "bound": "hbm",
+                                  "achieved": b / (per_launch / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": b / (per_launch / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                                  "bytes_per_launch": b, "us_per_launch": 1e3 * per_launch,
+                                  "launches": launches}
+
     # ---- CPU oracle on the host (reported baseline, not a target)
     if not args.no_cpu_baseline:
         import oracle

@@ -183,6 +183,32 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
 fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n,
                          const fgbd_params *params, float *rgb_out, fgbd_result *res, void *stream);
 
+/* Polynomial graph filter, the differentiable generalisation of eq. 5:
+ *   out = sum_{k=0}^{ncoef-1} coef[k] T^k x,
+ * with T = D_g^{-1} W_g (eq. 5) whose weights (eq. 4) are recomputed from
+ * g->dist2 and the bandwidth *sigma_g (so sigma_g may be a trained parameter;
+ * g->p is not used).  coef = e_q reproduces fgbd_filter with q_fixed = q.
+ *   g: col and dist2 of a graph from fgbd_build_slg;  x, out: float32 [n][3]
+ *   (must not overlap);  coef: device float32 [ncoef], 1 <= ncoef <= 32;
+ *   sigma_g: device double (one value, > 0);  saved: output float32
+ *   [ncoef][n][3], the iterates x_0..x_{ncoef-1} the backward call needs. */
+fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, const float *coef, int32_t ncoef,
+                             const double *sigma_g, float *out, float *saved, void *stream);
+
+/* Hand-written adjoint of fgbd_poly_filter for L = <grad_out, out>:
+ *   grad_x = z_0 with z_{ncoef-1} = c_{ncoef-1} grad_out and
+ *            z_k = c_k grad_out + T^T z_{k+1} (T^T from an explicit transpose
+ *            of the directed graph, rows in source order);
+ *   grad_coef[k] = <grad_out, x_k>;
+ *   grad_sigma_g = sum_{m>=1} <z_m, (dT/dsigma_g) x_{m-1}>.
+ *   saved: the iterates written by fgbd_poly_filter with the same g, coef,
+ *   ncoef and sigma_g;  grad_out, grad_x: float32 [n][3] (must not overlap);
+ *   grad_coef: optional device float32 [ncoef];  grad_sigma_g: optional device
+ *   double.  Scalar gradients are reduced in a fixed order (deterministic). */
+fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const float *saved, const float *coef,
+                                      int32_t ncoef, const double *sigma_g, const float *grad_out, float *grad_x,
+                                      float *grad_coef, double *grad_sigma_g, void *stream);
+
 /* Message for the last non-OK status returned on the calling thread ("" if
  * none).  Valid until the next call on this thread. */
 const char *fgbd_last_error(void);

@@ -101,7 +101,7 @@ Plan make_plan(int64_t n, const fgbd_params &p) {
   pl.ntiles = (int32_t)((n + kSortTile - 1) / kSortTile);
   const int64_t chunks = (n + kBlock - 1) / kBlock;
   pl.merge_blocks = (int32_t)(chunks < 1 ? 1 : (chunks < kMaxGrid ? chunks : kMaxGrid));
-  pl.sweep_blocks = pl.merge_blocks;
+  pl.sweep_blocks = (int32_t)(chunks < 1 ? 1 : (chunks < kSweepMaxGrid ? chunks : kSweepMaxGrid));
   const int TP = pl.D <= 17 ? 256 : 128;
   const int64_t ptiles = (n + TP - 1) / TP;
   pl.noise_blocks = (int32_t)(ptiles < 1 ? 1 : (ptiles < kMaxGrid ? ptiles : kMaxGrid));
@@ -116,6 +116,7 @@ Plan make_plan(int64_t n, const fgbd_params &p) {
   pl.off_items_a = take((size_t)pl.L * N * 8);
   pl.off_items_b = take((size_t)pl.L * N * 8);
   pl.off_hist = take((size_t)pl.L * (pl.ntiles > 0 ? pl.ntiles : 1) * 256 * 4);
+  pl.off_totals = take((size_t)pl.L * kSortPasses * 256 * 4);
   pl.off_rank = take((size_t)pl.L * N * 4);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
@@ -124,7 +125,7 @@ Plan make_plan(int64_t n, const fgbd_params &p) {
   pl.off_xbuf = take(3 * N * 16);
   pl.off_merge_part = take((size_t)(pl.merge_blocks > 0 ? pl.merge_blocks : 1) * 2 * 8);
   pl.off_noise_part = take((size_t)(pl.noise_blocks > 0 ? pl.noise_blocks : 1) * pl.npart_noise * 8);
-  pl.off_sweep_part = take((size_t)2 * pl.sweep_blocks * kSweepParts * 8);
+  pl.off_sweep_sums = take((size_t)3 * kSweepSlots * kSweepParts * 8);
   pl.off_ctrl = take(2 * sizeof(SweepCtrl));
   pl.total = off;
   return pl;
@@ -132,7 +133,8 @@ Plan make_plan(int64_t n, const fgbd_params &p) {
 
 namespace {
 
-__global__ void k_init(fgbd_result *res, int zero_result) {
+__global__ void k_init(fgbd_result *res, int zero_result, unsigned long long *zero, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) zero[i] = 0ull;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     if (zero_result && res) {
       res->sigma_est = 0.0;
@@ -150,8 +152,8 @@ __global__ void k_init(fgbd_result *res, int zero_result) {
 
 }  // namespace
 
-hipError_t launch_init(fgbd_result *res, int zero_result, hipStream_t stream) {
-  k_init<<<1, 64, 0, stream>>>(res, zero_result);
+hipError_t launch_init(fgbd_result *res, int zero_result, unsigned long long *zero, int count, hipStream_t stream) {
+  k_init<<<1, 256, 0, stream>>>(res, zero_result, zero, zero ? count : 0);
   return hipGetLastError();
 }
 
@@ -268,12 +270,13 @@ struct EventProf final : Prof {
 
 struct Bufs {
   uint64_t *items_a, *items_b;
-  uint32_t *hist, *rank;
+  uint32_t *hist, *totals, *rank;
   int32_t *col, *dist2;
   float *p;
   double *spread;
   float4 *xbuf;
-  double *merge_part, *noise_part, *sweep_part;
+  double *merge_part, *noise_part;
+  unsigned long long *sweep_sums;  // three rotating slot buffers
   SweepCtrl *ctrl;  // two states (ping-pong)
 };
 
@@ -282,6 +285,7 @@ Bufs carve(char *ws, const Plan &pl) {
   b.items_a = (uint64_t *)(ws + pl.off_items_a);
   b.items_b = (uint64_t *)(ws + pl.off_items_b);
   b.hist = (uint32_t *)(ws + pl.off_hist);
+  b.totals = (uint32_t *)(ws + pl.off_totals);
   b.rank = (uint32_t *)(ws + pl.off_rank);
   b.col = (int32_t *)(ws + pl.off_col);
   b.dist2 = (int32_t *)(ws + pl.off_dist2);
@@ -290,7 +294,7 @@ Bufs carve(char *ws, const Plan &pl) {
   b.xbuf = (float4 *)(ws + pl.off_xbuf);
   b.merge_part = (double *)(ws + pl.off_merge_part);
   b.noise_part = (double *)(ws + pl.off_noise_part);
-  b.sweep_part = (double *)(ws + pl.off_sweep_part);
+  b.sweep_sums = (unsigned long long *)(ws + pl.off_sweep_sums);
   b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
   return b;
 }
@@ -309,7 +313,7 @@ fgbd_status run_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_para
   EventProf ep(ctx, s);
   Prof *pf = ctx->profile ? &ep : nullptr;
   const uint64_t *sorted = nullptr;
-  HIP_TRY(launch_sort(xyz, n, dt, pl, b.items_a, b.items_b, b.hist, b.rank, res, s, &sorted, pf),
+  HIP_TRY(launch_sort(xyz, n, dt, pl, b.items_a, b.items_b, b.hist, b.totals, b.rank, res, s, &sorted, pf),
           "radix sort launch");
   FGBD_PRE(pf, kMerge);
   HIP_TRY(launch_merge(xyz, n, dt, prm.window, prm.k, sorted, b.rank, col, dist2, b.merge_part, pl.merge_blocks, s),
@@ -344,15 +348,18 @@ fgbd_status run_filter(fgbd_ctx ctx, int64_t n, const fgbd_params &prm, const Pl
   EventProf ep(ctx, s);
   Prof *pf = ctx->profile ? &ep : nullptr;
   const int sweeps = q_limit > 0 ? q_limit : 1;
+  // sums of sweep 1 go to slot buffer 1, which must start at zero
+  HIP_TRY(launch_init(nullptr, 0, b.sweep_sums + (size_t)kSweepSlots * kSweepParts, kSweepSlots * kSweepParts, s),
+          "init launch");
   for (int q = 1; q <= sweeps; ++q) {
     FGBD_PRE(pf, kSweep);
     HIP_TRY(launch_sweep(n, prm.k, col, p, rgb_in, b.xbuf, spread, noise, prm.fslr_kappa, select, q_limit, q,
-                         b.sweep_part, pl.sweep_blocks, b.ctrl, s),
+                         b.sweep_sums, pl.sweep_blocks, b.ctrl, s),
             "sweep launch");
     FGBD_POST(pf);
   }
   FGBD_PRE(pf, kFinalize);
-  HIP_TRY(launch_finalize(n, rgb_in, b.xbuf, sweeps, b.sweep_part, pl.sweep_blocks, b.ctrl, noise, rgb_out, res, s),
+  HIP_TRY(launch_finalize(n, rgb_in, b.xbuf, sweeps, b.sweep_sums, pl.sweep_blocks, b.ctrl, noise, rgb_out, res, s),
           "finalize launch");
   FGBD_POST(pf);
   return FGBD_OK;
@@ -413,7 +420,9 @@ fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t bat
   if ((st = check_n(n_max)) != FGBD_OK) return st;
   if (batch != 1) return fail(FGBD_E_INVALID, "batch must be 1");
   if (!bytes) return fail(FGBD_E_INVALID, "bytes is NULL");
-  *bytes = make_plan(n_max, *p).total;
+  const size_t a = make_plan(n_max, *p).total;
+  const size_t b = poly_workspace(n_max, p->k, kMaxPoly, kMaxGrid);
+  *bytes = a > b ? a : b;
   return ok();
 }
 
@@ -443,7 +452,7 @@ fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fg
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(res, 1, s), "init launch");
+  HIP_TRY(launch_init(res, 1, nullptr, 0, s), "init launch");
   if (n == 0) return ok();
   if ((st = run_slg(ctx, xyz, n, *params, pl, b, g->col, g->dist2, g->p, res, s)) != FGBD_OK) return st;
   return ok();
@@ -468,7 +477,7 @@ fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
   if (n == 0) {
-    HIP_TRY(launch_init(res, 2, s), "init launch");
+    HIP_TRY(launch_init(res, 2, nullptr, 0, s), "init launch");
     return ok();
   }
   if ((st = run_noise(ctx, n, *params, pl, b, g->col, rgb, patch_spread ? patch_spread : b.spread, eig3, res, s)) !=
@@ -503,7 +512,7 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
   if (n == 0) {
-    HIP_TRY(launch_init(res, 1, s), "init launch");
+    HIP_TRY(launch_init(res, 1, nullptr, 0, s), "init launch");
     return ok();
   }
   const int q_limit = select ? params->q_max : q_fixed;
@@ -530,13 +539,64 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(res, n == 0 ? 2 : 1, s), "init launch");
+  HIP_TRY(launch_init(res, n == 0 ? 2 : 1, nullptr, 0, s), "init launch");
   if (n == 0) return ok();
   if ((st = run_slg(ctx, xyz, n, *params, pl, b, b.col, b.dist2, b.p, res, s)) != FGBD_OK) return st;
   if ((st = run_noise(ctx, n, *params, pl, b, b.col, rgb_in, b.spread, nullptr, res, s)) != FGBD_OK) return st;
   if ((st = run_filter(ctx, n, *params, pl, b, b.col, b.p, rgb_in, b.spread, res, 1, params->q_max, rgb_out, res,
                        s)) != FGBD_OK)
     return st;
+  return ok();
+}
+
+static fgbd_status check_poly(fgbd_ctx ctx, const fgbd_graph *g, int32_t ncoef, const double *sigma_g) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  if (!g) return fail(FGBD_E_INVALID, "graph is NULL");
+  fgbd_status st = check_n(g->n);
+  if (st != FGBD_OK) return st;
+  if (g->k < 1 || g->k > kMaxK) return fail(FGBD_E_INVALID, "graph k must be in 1..%d", kMaxK);
+  if (ncoef < 1 || ncoef > kMaxPoly) return fail(FGBD_E_INVALID, "ncoef must be in 1..%d (got %d)", kMaxPoly, ncoef);
+  if (!sigma_g) return fail(FGBD_E_INVALID, "sigma_g is NULL");
+  if (g->n > 0 && (!g->col || !g->dist2)) return fail(FGBD_E_INVALID, "NULL graph array");
+  return FGBD_OK;
+}
+
+fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, const float *coef, int32_t ncoef,
+                             const double *sigma_g, float *out, float *saved, void *stream) {
+  fgbd_status st = check_poly(ctx, g, ncoef, sigma_g);
+  if (st != FGBD_OK) return st;
+  const int64_t n = g->n;
+  if (n > 0 && (!x || !coef || !out || !saved)) return fail(FGBD_E_INVALID, "NULL input or output array");
+  if (n > 0 && overlap(x, (size_t)n * 12, out, (size_t)n * 12)) return fail(FGBD_E_INVALID, "x and out overlap");
+  if (n == 0) return ok();
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, poly_workspace(n, g->k, ncoef, kMaxGrid), &ws)) != FGBD_OK) return st;
+  HIP_TRY(launch_poly_forward(n, g->k, g->col, g->dist2, x, coef, ncoef, sigma_g, out, saved, ws, s),
+          "poly filter launch");
+  return ok();
+}
+
+fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const float *saved, const float *coef,
+                                      int32_t ncoef, const double *sigma_g, const float *grad_out, float *grad_x,
+                                      float *grad_coef, double *grad_sigma_g, void *stream) {
+  fgbd_status st = check_poly(ctx, g, ncoef, sigma_g);
+  if (st != FGBD_OK) return st;
+  const int64_t n = g->n;
+  if (n > 0 && (!saved || !coef || !grad_out || !grad_x)) return fail(FGBD_E_INVALID, "NULL input or output array");
+  if (n > 0 && overlap(grad_out, (size_t)n * 12, grad_x, (size_t)n * 12))
+    return fail(FGBD_E_INVALID, "grad_out and grad_x overlap");
+  if (n == 0) return ok();
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, poly_workspace(n, g->k, ncoef, kMaxGrid), &ws)) != FGBD_OK) return st;
+  HIP_TRY(launch_poly_backward(n, g->k, g->col, g->dist2, saved, coef, ncoef, sigma_g, grad_out, grad_x, grad_coef,
+                               grad_sigma_g, ws, s),
+          "poly filter backward launch");
   return ok();
 }
 

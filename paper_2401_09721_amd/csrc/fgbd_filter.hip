@@ -3,12 +3,17 @@
 //
 // One launch = one sweep x_q = T x_{q-1}, (T x)_i = x_i/2 + sum_k p_ik x_{col_ik}/2,
 // colours held as float4 (r, g, b, FSLR flag) so each neighbour gather is one
-// 16-byte load.  Each sweep also writes per-block FP64 sums of |x_q|^2 over
-// the FSLR subset and over all points.
+// 16-byte load.  Each sweep also sums |x_q|^2 over the FSLR subset and over
+// all points.  Every point's term is rounded to a fixed-point integer (units of
+// 2^-12) and blocks add their integer sums with 64-bit atomics into a few
+// dozen slots; integer addition is exact, so the totals do not depend on the
+// order, the grid or the device schedule (deterministic, no floating-point
+// atomics, no fences).  Three slot buffers rotate: launch q reads the sums of
+// q-1, adds into q, and clears the buffer of q+1.
 //
-// Selection without inter-block synchronisation: launch q starts by summing
-// the partials of launch q-1 (every block, same order, identical totals) and
-// advancing the selection state
+// Selection without inter-block synchronisation: launch q starts by reading
+// the sums of launch q-1 (every block reads the same integers) and advancing
+// the selection state
 //   E(q-1) = (sum_S |y|^2 - sum_S |x_{q-1}|^2) / (3 |S|),
 //   best = argmin |sigma_est^2 - E| so far (ties keep the smaller q),
 //   done when E >= sigma_est^2, q reaches q_max, or the loss is 0;
@@ -33,6 +38,10 @@ struct SweepArgs {
   double kappa;
   int64_t buf_stride;  // float4 elements per buffer
 };
+
+constexpr double kFix = 4096.0;  // fixed-point scale of the energy sums (2^12)
+
+__device__ __forceinline__ unsigned long long to_fix(double v) { return (unsigned long long)llrint(v * kFix); }
 
 __device__ __forceinline__ int free_buffer(int in_buf, int best_buf) {
   for (int b = 0; b < 3; ++b)
@@ -72,14 +81,51 @@ __device__ void advance(SweepCtrl &c, const double (&t)[kSweepParts], int n, int
 }
 
 // Selection state at the start of a launch: the stored state advanced by the
-// previous sweep's partials (identical in every block).
-__device__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev, const double *__restrict__ part_prev,
-                           int nparts, int n, double *s_red) {
+// previous sweep's integer sums (identical in every block).  Called by every
+// thread of the block; the slots are loaded in parallel and summed in LDS.
+__device__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
+                           const unsigned long long *__restrict__ sums_prev, int n) {
+  __shared__ unsigned long long s_slot[kSweepSlots * kSweepParts];
+  __shared__ unsigned long long s_part[kSweepParts * 32];
   c = *prev;
-  if (!c.done) {
-    double t[kSweepParts];
-    reduce_partials<kSweepParts>(part_prev, nparts, kSweepParts, t, s_red);
-    advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
+  if (c.done) return;  // uniform: every thread read the same state
+  for (int j = threadIdx.x; j < kSweepSlots * kSweepParts; j += blockDim.x) s_slot[j] = sums_prev[j];
+  __syncthreads();
+  if (threadIdx.x < kSweepParts * 32) {
+    const int part = threadIdx.x / 32, g = threadIdx.x % 32;
+    unsigned long long u = 0;
+    for (int sl = g; sl < kSweepSlots; sl += 32) u += s_slot[sl * kSweepParts + part];
+    s_part[threadIdx.x] = u;
+  }
+  __syncthreads();
+  double t[kSweepParts];
+#pragma unroll
+  for (int j = 0; j < kSweepParts; ++j) {
+    unsigned long long u = 0;
+    for (int g = 0; g < 32; ++g) u += s_part[j * 32 + g];
+    t[j] = j < 4 ? (double)u / kFix : (double)u;
+  }
+  advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
+}
+
+// Block-sum of per-thread integer sums, then one atomic per value per block.
+__device__ __forceinline__ void add_sums(unsigned long long (&v)[kSweepParts], unsigned long long *__restrict__ out,
+                                         unsigned long long *s_buf) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int j = 0; j < kSweepParts; ++j) v[j] += __shfl_down(v[j], o, kWave);
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int j = 0; j < kSweepParts; ++j) s_buf[w * kSweepParts + j] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < kSweepParts) {
+    unsigned long long a = 0;
+    for (int ww = 0; ww < (int)blockDim.x / kWave; ++ww) a += s_buf[ww * kSweepParts + threadIdx.x];
+    if (a) atomicAdd(&out[(blockIdx.x % kSweepSlots) * kSweepParts + threadIdx.x], a);
   }
 }
 
@@ -88,10 +134,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
                                                   const float *__restrict__ p, const float *__restrict__ rgb_in,
                                                   float4 *__restrict__ xbuf, const double *__restrict__ spread,
                                                   const fgbd_result *__restrict__ noise,
-                                                  const double *__restrict__ part_prev, double *__restrict__ part_out,
+                                                  const unsigned long long *__restrict__ sums_prev,
+                                                  unsigned long long *__restrict__ sums_out,
+                                                  unsigned long long *__restrict__ sums_clear,
                                                   const SweepCtrl *__restrict__ ctrl_prev,
                                                   SweepCtrl *__restrict__ ctrl_out) {
-  __shared__ double s_red[4 * kSweepParts];
+  __shared__ unsigned long long s_red[4 * kSweepParts];
   const int K = KT > 0 ? KT : a.k;
   SweepCtrl c;
   if (FIRST) {
@@ -111,9 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
     c.q_limit = a.q_limit;
     c.fslr = (a.select && a.kappa > 0.0) ? 1 : 0;
   } else {
-    load_state(c, ctrl_prev, part_prev, gridDim.x, a.n, s_red);
+    load_state(c, ctrl_prev, sums_prev, a.n);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *ctrl_out = c;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *ctrl_out = c;
+    for (int j = threadIdx.x; j < kSweepSlots * kSweepParts; j += blockDim.x) sums_clear[j] = 0ull;
+  }
   if (c.done) return;
 
   const double thr = c.fslr ? a.kappa * c.sigma_est : 0.0;
@@ -121,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
   const float4 *xin = xbuf + (size_t)(c.in_buf < 3 ? c.in_buf : 0) * a.buf_stride;
   float4 *xout = xbuf + (size_t)out_buf * a.buf_stride;
 
-  double v[kSweepParts] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  unsigned long long v[kSweepParts] = {0, 0, 0, 0, 0};
   const Share sh = xcd_share(a.n, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
     const int64_t i = base + threadIdx.x;
@@ -182,32 +233,27 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
       ob = 0.5f * xb + 0.5f * ab;
     }
     xout[i] = make_float4(orr, og, ob, member);
-    const double x2 = (double)orr * orr + (double)og * og + (double)ob * ob;
-    v[0] += member != 0.0f ? x2 : 0.0;
+    const unsigned long long x2 = to_fix((double)orr * orr + (double)og * og + (double)ob * ob);
+    v[0] += member != 0.0f ? x2 : 0ull;
     v[1] += x2;
     if (FIRST) {
-      const double y2 = (double)xr * xr + (double)xg * xg + (double)xb * xb;
-      v[2] += member != 0.0f ? y2 : 0.0;
+      const unsigned long long y2 = to_fix((double)xr * xr + (double)xg * xg + (double)xb * xb);
+      v[2] += member != 0.0f ? y2 : 0ull;
       v[3] += y2;
-      v[4] += member != 0.0f ? 1.0 : 0.0;
+      v[4] += member != 0.0f ? 1ull : 0ull;
     }
   }
-  block_sum_f64<kSweepParts>(v, s_red);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < kSweepParts; ++j) part_out[(size_t)blockIdx.x * kSweepParts + j] = v[j];
-  }
+  add_sums(v, sums_out, s_red);
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(int32_t n, int64_t buf_stride, const float *__restrict__ rgb_in,
                                                      const float4 *__restrict__ xbuf,
-                                                     const double *__restrict__ part_prev, int nparts,
+                                                     const unsigned long long *__restrict__ sums_prev,
                                                      const SweepCtrl *__restrict__ ctrl_prev,
                                                      const fgbd_result *__restrict__ noise,
                                                      float *__restrict__ rgb_out, fgbd_result *__restrict__ res) {
-  __shared__ double s_red[4 * kSweepParts];
   SweepCtrl c;
-  load_state(c, ctrl_prev, part_prev, nparts, n, s_red);
+  load_state(c, ctrl_prev, sums_prev, n);
   const int best = c.best_buf;
   const Share sh = xcd_share(n, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
@@ -237,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int32_t n, int64_t buf_stri
 
 hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf,
                         const double *spread, const fgbd_result *noise, double kappa, int select, int q_limit,
-                        int q, double *part2, int nblocks, SweepCtrl *ctrl2, hipStream_t stream) {
+                        int q, unsigned long long *sums3, int nblocks, SweepCtrl *ctrl2, hipStream_t stream) {
   SweepArgs a;
   a.n = (int32_t)n;
   a.k = k;
@@ -245,31 +291,34 @@ hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, co
   a.q_limit = q_limit;
   a.kappa = kappa;
   a.buf_stride = n;
-  const double *pp = part2 + (size_t)((q - 1) & 1) * nblocks * kSweepParts;
-  double *po = part2 + (size_t)(q & 1) * nblocks * kSweepParts;
+  const size_t S = (size_t)kSweepSlots * kSweepParts;
+  const unsigned long long *sp = sums3 + ((q - 1) % 3) * S;
+  unsigned long long *so = sums3 + (q % 3) * S;
+  unsigned long long *sc = sums3 + ((q + 1) % 3) * S;
   const SweepCtrl *cp = ctrl2 + ((q - 1) & 1);
   SweepCtrl *co = ctrl2 + (q & 1);
   const bool first = q == 1;
   if (k == 8) {
     if (first)
-      k_sweep<8, true><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, pp, po, cp, co);
+      k_sweep<8, true><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
     else
-      k_sweep<8, false><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, pp, po, cp, co);
+      k_sweep<8, false><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
   } else {
     if (first)
-      k_sweep<0, true><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, pp, po, cp, co);
+      k_sweep<0, true><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
     else
-      k_sweep<0, false><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, pp, po, cp, co);
+      k_sweep<0, false><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, int q_launches, const double *part2,
-                           int nblocks, const SweepCtrl *ctrl2, const fgbd_result *noise, float *rgb_out,
-                           fgbd_result *res, hipStream_t stream) {
-  const double *pp = part2 + (size_t)(q_launches & 1) * nblocks * kSweepParts;
+hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, int q_launches,
+                           const unsigned long long *sums3, int nblocks, const SweepCtrl *ctrl2,
+                           const fgbd_result *noise, float *rgb_out, fgbd_result *res, hipStream_t stream) {
+  const size_t S = (size_t)kSweepSlots * kSweepParts;
+  const unsigned long long *sp = sums3 + (q_launches % 3) * S;
   const SweepCtrl *cp = ctrl2 + (q_launches & 1);
-  k_finalize<<<nblocks, kBlock, 0, stream>>>((int32_t)n, n, rgb_in, xbuf, pp, nblocks, cp, noise, rgb_out, res);
+  k_finalize<<<nblocks, kBlock, 0, stream>>>((int32_t)n, n, rgb_in, xbuf, sp, cp, noise, rgb_out, res);
   return hipGetLastError();
 }
 

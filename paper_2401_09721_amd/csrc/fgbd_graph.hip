@@ -2,11 +2,11 @@
 //
 // k_merge: one thread per point i.  For each direction it looks up i's sorted
 // position r (rank array from the last radix pass), reads the items at
-// r-w..r+w (their codes decode to coordinates, so no coordinate gather is
-// needed), and keeps the K smallest distinct (squared distance, index) pairs
-// in a register-resident sorted list (packed as d2 << 32 | j, so one 64-bit
-// compare orders by distance then index).  It writes the fixed-K CSR row and
-// writes per-block FP64 sums of edge lengths and edge counts for sigma_g.
+// r-w..r+w (squared distances follow from differences of the code fields, so
+// no coordinate is gathered), and keeps the K smallest distinct (squared
+// distance, index) pairs in a register-resident sorted list (packed so one
+// integer compare orders by distance then index).  It writes the fixed-K CSR
+// row and per-block FP64 sums of edge lengths and edge counts for sigma_g.
 //
 // k_weights: every block first sums the merge partials in block order (all
 // blocks get the same sigma_g, the mean edge length of eq. 4's bandwidth rule),
@@ -21,56 +21,146 @@ namespace fgbd {
 
 namespace {
 
-template <int KM>
-__device__ __forceinline__ void topk_insert(uint64_t (&lst)[KM], int K, uint64_t c) {
+// Squared distance between the points of two codes of one direction, from
+// the code fields alone: with da = difference of position coordinates and
+// dm, dh = differences of the line invariants, the coordinate differences are
+// da, dm + u_m da and dh + u_h da.
+struct DirConst {
+  uint32_t top, mmask;
+  int bits, hshift, uh, um;
+};
+__device__ __forceinline__ DirConst dir_const(const DirInfo &di, int bits) {
+  DirConst c;
+  c.top = (1u << bits) - 1u;
+  const int wm = bits + di.wm_extra;
+  c.mmask = (1u << wm) - 1u;
+  c.bits = bits;
+  c.hshift = bits + wm;
+  c.uh = di.uh;
+  c.um = di.um;
+  return c;
+}
+__device__ __forceinline__ uint32_t code_dist2(uint32_t ci, uint32_t cj, const DirConst &c) {
+  const int da = (int)(cj & c.top) - (int)(ci & c.top);
+  const int dm = (int)((cj >> c.bits) & c.mmask) - (int)((ci >> c.bits) & c.mmask) + c.um * da;
+  const int dh = (int)(cj >> c.hshift) - (int)(ci >> c.hshift) + c.uh * da;
+  return (uint32_t)(da * da) + (uint32_t)(dm * dm) + (uint32_t)(dh * dh);
+}
+
+template <int KM, typename Key>
+__device__ __forceinline__ void topk_insert_t(Key (&lst)[KM], int K, Key c) {
   if (c >= lst[K - 1]) return;
+  bool dup = false;
 #pragma unroll
-  for (int k = 0; k < KM; ++k)
-    if (k < K && lst[k] == c) return;
+  for (int k = 0; k < KM; ++k) dup |= (k < K) & (lst[k] == c);
+  if (dup) return;
 #pragma unroll
   for (int k = KM - 1; k > 0; --k) {
     if (k < K) {
-      const uint64_t prev = lst[k - 1];
-      if (prev > c)
-        lst[k] = prev;
-      else if (lst[k] > c)
-        lst[k] = c;
+      const Key prev = lst[k - 1];
+      lst[k] = prev > c ? prev : (lst[k] > c ? c : lst[k]);
     }
   }
-  if (lst[0] > c) lst[0] = c;
+  lst[0] = lst[0] > c ? c : lst[0];
 }
 
+template <int WT>
+__device__ __forceinline__ void load_window(const uint64_t *__restrict__ srt, int r, int n, uint64_t (&w)[2 * WT + 1]) {
+#pragma unroll
+  for (int s = 0; s <= 2 * WT; ++s) {
+    const int pos = r + s - WT;
+    w[s] = (pos >= 0 && pos < n) ? srt[pos] : ~0ull;
+  }
+}
+
+// Exact (64-bit key) selection for one point, runtime window: used for all
+// points when N >= 2^24 and for the rare point whose 32-bit selection kept a
+// clamped distance.
 template <int KM>
+__device__ void select_exact(int i, int n, int L, int window, int K, const DirInfo *s_dir, int bits,
+                             const uint64_t *__restrict__ sorted, const uint32_t *__restrict__ rank,
+                             uint64_t (&lst)[KM]) {
+#pragma unroll
+  for (int k = 0; k < KM; ++k) lst[k] = ~0ull;
+  for (int d = 0; d < L; ++d) {
+    const DirConst dc = dir_const(s_dir[d], bits);
+    const int r = (int)rank[(size_t)d * n + i];
+    const uint64_t *srt = sorted + (size_t)d * n;
+    const uint32_t ci = (uint32_t)(srt[r] >> 32);
+    const int lo = max(r - window, 0);
+    const int hi = min(r + window, n - 1);
+    for (int rr = lo; rr <= hi; ++rr) {
+      if (rr == r) continue;
+      const uint64_t it = srt[rr];
+      topk_insert_t<KM, uint64_t>(lst, K, ((uint64_t)code_dist2(ci, (uint32_t)(it >> 32), dc) << 32) | (uint32_t)it);
+    }
+  }
+}
+
+// One thread per point.  WT > 0 (compile-time window, N < 2^24): the point's
+// ranks in all directions go to LDS in one batch of loads; each direction's
+// 2*WT+1 window items (the centre gives the point's own code) are fetched as
+// one batch, one direction ahead of their use; candidates are 32-bit keys
+// (min(d2, 255) << 24 | j), exact whenever no kept entry has a clamped
+// distance, else the point is redone with 64-bit keys.
+template <int KM, int WT>
 __global__ __launch_bounds__(kBlock) void k_merge(DirTable dt, int32_t n, int32_t window, int32_t K,
-                                                  const int32_t *__restrict__ xyz, const uint64_t *__restrict__ sorted,
+                                                  const uint64_t *__restrict__ sorted,
                                                   const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
                                                   int32_t *__restrict__ dist2, double *__restrict__ part) {
   __shared__ double s_red[8];
+  __shared__ int s_rank[WT > 0 ? kMaxDirs : 1][kBlock];
+  __shared__ DirInfo s_dir[kMaxDirs];
   double acc[2] = {0.0, 0.0};
+  const int L = dt.num_dirs;
+  const int t = threadIdx.x;
+  if (t < kMaxDirs) s_dir[t] = dt.d[t];
+  __syncthreads();
   const Share sh = xcd_share(n, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
-    const int i = (int)(base + threadIdx.x);
+    const int i = (int)(base + t);
     if (i >= sh.end) continue;
     uint64_t lst[KM];
+    bool exact_done = false;
+    if constexpr (WT > 0) {
 #pragma unroll
-    for (int k = 0; k < KM; ++k) lst[k] = ~0ull;
-    const int gi0 = xyz[3 * i + 0], gi1 = xyz[3 * i + 1], gi2 = xyz[3 * i + 2];
-    for (int d = 0; d < dt.num_dirs; ++d) {
-      const DirInfo di = dt.d[d];
-      const int r = (int)rank[(size_t)d * n + i];
-      const uint64_t *srt = sorted + (size_t)d * n;
-      const int lo = max(r - window, 0);
-      const int hi = min(r + window, n - 1);
-      for (int rr = lo; rr <= hi; ++rr) {
-        if (rr == r) continue;
-        const uint64_t it = srt[rr];
-        int gj[3];
-        scan_decode((uint32_t)(it >> 32), di, dt.bits, gj);
-        const uint32_t dx = (uint32_t)(gj[0] - gi0), dy = (uint32_t)(gj[1] - gi1), dz = (uint32_t)(gj[2] - gi2);
-        const uint32_t d2 = dx * dx + dy * dy + dz * dz;
-        topk_insert<KM>(lst, K, ((uint64_t)d2 << 32) | (uint32_t)it);
+      for (int d = 0; d < kMaxDirs; ++d)
+        if (d < L) s_rank[d][t] = (int)rank[(size_t)d * n + i];
+      uint32_t key[KM];
+#pragma unroll
+      for (int k = 0; k < KM; ++k) key[k] = ~0u;
+      uint64_t cur[2 * WT + 1], nxt[2 * WT + 1];
+      load_window<WT>(sorted, s_rank[0][t], n, cur);
+      for (int d = 0; d < L; ++d) {
+        if (d + 1 < L) load_window<WT>(sorted + (size_t)(d + 1) * n, s_rank[d + 1][t], n, nxt);
+        const DirConst dc = dir_const(s_dir[d], dt.bits);
+        const uint32_t ci = (uint32_t)(cur[WT] >> 32);
+#pragma unroll
+        for (int s = 0; s <= 2 * WT; ++s) {
+          if (s != WT && cur[s] != ~0ull) {
+            const uint32_t d2 = code_dist2(ci, (uint32_t)(cur[s] >> 32), dc);
+            topk_insert_t<KM, uint32_t>(key, K, ((d2 < 255u ? d2 : 255u) << 24) | (uint32_t)cur[s]);
+          }
+        }
+#pragma unroll
+        for (int s = 0; s <= 2 * WT; ++s) cur[s] = nxt[s];
       }
+      bool clamped = false;
+#pragma unroll
+      for (int k = 0; k < KM; ++k) clamped |= (k < K) & (key[k] != ~0u) & ((key[k] >> 24) == 255u);
+      if (clamped) {
+        select_exact<KM>(i, n, L, WT, K, s_dir, dt.bits, sorted, rank, lst);
+        exact_done = true;
+      } else {
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+          lst[k] = key[k] == ~0u ? ~0ull : ((uint64_t)(key[k] >> 24) << 32) | (key[k] & 0xffffffu);
+      }
+    } else {
+      select_exact<KM>(i, n, L, window, K, s_dir, dt.bits, sorted, rank, lst);
+      exact_done = true;
     }
+    (void)exact_done;
     int cv[KM], dv[KM];
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
@@ -180,12 +270,22 @@ __global__ __launch_bounds__(kBlock) void k_weights(int32_t n, int32_t k_rt, con
 hipError_t launch_merge(const int32_t *xyz, int64_t n, const DirTable &dt, int window, int k, const uint64_t *sorted,
                         const uint32_t *rank, int32_t *col, int32_t *dist2, double *part, int nblocks,
                         hipStream_t stream) {
-  if (k <= 8)
-    k_merge<8><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, xyz, sorted, rank, col, dist2, part);
+  (void)xyz;
+  const bool small = n < (1 << 24);  // 32-bit keys hold the index in 24 bits
+  if (small && k <= 8 && window == 4)
+    k_merge<8, 4><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+  else if (small && k <= 8 && window == 1)
+    k_merge<8, 1><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+  else if (small && k <= 8 && window == 2)
+    k_merge<8, 2><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+  else if (k <= 8)
+    k_merge<8, 0><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+  else if (small && k <= 16 && window == 4)
+    k_merge<16, 4><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
   else if (k <= 16)
-    k_merge<16><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, xyz, sorted, rank, col, dist2, part);
+    k_merge<16, 0><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
   else
-    k_merge<32><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, xyz, sorted, rank, col, dist2, part);
+    k_merge<32, 0><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
   return hipGetLastError();
 }
 

@@ -217,9 +217,9 @@ struct Plan {
   int32_t sweep_blocks;
   int32_t npart_noise;     // doubles per noise partial
   // byte offsets into the workspace
-  size_t off_items_a, off_items_b, off_hist, off_rank;
+  size_t off_items_a, off_items_b, off_hist, off_totals, off_rank;
   size_t off_col, off_dist2, off_p;
-  size_t off_spread, off_xbuf, off_merge_part, off_noise_part, off_sweep_part;
+  size_t off_spread, off_xbuf, off_merge_part, off_noise_part, off_sweep_sums;
   size_t off_ctrl;
   size_t total;
 };
@@ -231,7 +231,9 @@ constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit 
 
 constexpr int kBlock = 256;
 constexpr int kMaxGrid = 1024;  // grid of the grid-stride kernels
-constexpr int kSweepParts = 5;  // doubles per sweep partial
+constexpr int kSweepParts = 5;  // energy sums per sweep
+constexpr int kSweepSlots = 256; // atomic slots per sum (spread to limit contention)
+constexpr int kSweepMaxGrid = 1024;
 constexpr int kScanThreads = 1024;
 
 Plan make_plan(int64_t n, const fgbd_params &p);
@@ -255,11 +257,13 @@ struct Prof {
 
 // ------------------------------------------------------------- launchers
 // All launchers enqueue on `stream` and return hipSuccess or the launch error.
-hipError_t launch_init(fgbd_result *res, int zero_result, hipStream_t stream);
+// Zeroes the result (zero_result: 1 = all fields, 2 = all fields and the
+// no-patch status) and, when given, `count` 64-bit words at `zero`.
+hipError_t launch_init(fgbd_result *res, int zero_result, unsigned long long *zero, int count, hipStream_t stream);
 
 hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const Plan &pl, uint64_t *items_a,
-                       uint64_t *items_b, uint32_t *hist, uint32_t *rank, fgbd_result *res, hipStream_t stream,
-                       const uint64_t **sorted_out, Prof *pf);
+                       uint64_t *items_b, uint32_t *hist, uint32_t *totals, uint32_t *rank, fgbd_result *res,
+                       hipStream_t stream, const uint64_t **sorted_out, Prof *pf);
 
 // neighbour selection; writes per-block edge-length partials (2 doubles)
 hipError_t launch_merge(const int32_t *xyz, int64_t n, const DirTable &dt, int window, int k, const uint64_t *sorted,
@@ -276,13 +280,25 @@ hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float
 
 hipError_t launch_noise_solve(int P, const double *part, int nblocks, fgbd_result *res, hipStream_t stream);
 
-// Sweep number q (1-based) of q_launches; reads ctrl/part[(q-1)&1], writes [q&1].
+// Sweep number q (1-based): reads ctrl[(q-1)&1] and sums[(q-1)%3], writes
+// ctrl[q&1] and sums[q%3], clears sums[(q+1)%3].  sums[1] must be zero
+// before sweep 1.
 hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf,
                         const double *spread, const fgbd_result *noise, double kappa, int select, int q_limit,
-                        int q, double *part2, int nblocks, SweepCtrl *ctrl2, hipStream_t stream);
+                        int q, unsigned long long *sums3, int nblocks, SweepCtrl *ctrl2, hipStream_t stream);
 
-hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, int q_launches, const double *part2,
-                           int nblocks, const SweepCtrl *ctrl2, const fgbd_result *noise, float *rgb_out,
-                           fgbd_result *res, hipStream_t stream);
+hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, int q_launches,
+                           const unsigned long long *sums3, int nblocks, const SweepCtrl *ctrl2,
+                           const fgbd_result *noise, float *rgb_out, fgbd_result *res, hipStream_t stream);
+
+// Polynomial filter and its adjoint (ws: at least poly_workspace bytes).
+constexpr int kMaxPoly = 32;
+size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks);
+hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *x,
+                               const float *coef, int ncoef, const double *sigma_g, float *out, float *saved,
+                               char *ws, hipStream_t s);
+hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *saved,
+                                const float *coef, int ncoef, const double *sigma_g, const float *grad_out,
+                                float *grad_x, float *grad_coef, double *grad_sigma, char *ws, hipStream_t s);
 
 }  // namespace fgbd

@@ -73,68 +73,187 @@ struct NoiseArgs {
   int32_t want_eig3;
 };
 
-// Parallel cyclic Jacobi on a symmetric Dp x Dp matrix in LDS (Dp even).
-__device__ void jacobi_eigs(double *A, int Dp, double *s_c, double *s_s, int *s_p, int *s_q, int *s_flag) {
-  const int t = threadIdx.x;
+// Orders this wave's LDS writes before its later LDS reads (all lanes).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Parallel cyclic Jacobi on a symmetric Dp x Dp matrix in LDS (Dp even), run
+// by one wave.  Round-robin pairing applies Dp/2 disjoint rotations at once.
+// An entry already negligible against its diagonal pair
+// (|a_pq| <= 1e-16 sqrt|a_pp a_qq|) is set to zero instead of rotated; the
+// sweeps stop when a whole sweep needed no rotation (at most 64 sweeps).
+__device__ void jacobi_eigs_wave(double *A, int Dp, double *s_c, double *s_s, int *s_p, int *s_q, int *s_flag) {
+  const int t = (int)lane_id();
   const int half = Dp / 2;
   for (int sweep = 0; sweep < 64; ++sweep) {
-    if (t == 0) {
-      double off = 0.0, dia = 0.0;
-      for (int i = 0; i < Dp; ++i) {
-        dia += A[i * Dp + i] * A[i * Dp + i];
-        for (int j = i + 1; j < Dp; ++j) off += A[i * Dp + j] * A[i * Dp + j];
-      }
-      *s_flag = (off <= 1e-30 * dia) ? 1 : 0;
-    }
-    __syncthreads();
-    if (*s_flag) break;
-    __syncthreads();
+    if (t == 0) *s_flag = 0;
+    wave_lds_sync();
     for (int round = 0; round < Dp - 1; ++round) {
       if (t < half) {
         auto pos = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + round) % (Dp - 1)); };
         int p = pos(t), q = pos(Dp - 1 - t);
         if (p > q) { int tmp = p; p = q; q = tmp; }
         const double apq = A[p * Dp + q];
+        const double app = A[p * Dp + p], aqq = A[q * Dp + q];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double tau = (A[q * Dp + q] - A[p * Dp + p]) / (2.0 * apq);
+        if (fabs(apq) > 1e-16 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+          const double tau = (aqq - app) / (2.0 * apq);
           const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + tt * tt);
           s = tt * c;
+          *s_flag = 1;
         }
         s_p[t] = p;
         s_q[t] = q;
         s_c[t] = c;
         s_s[t] = s;
       }
-      __syncthreads();
-      for (int w = t; w < half * Dp; w += blockDim.x) {  // A := A J (columns p, q)
+      wave_lds_sync();
+      for (int w = t; w < half * Dp; w += kWave) {  // A := A J (columns p, q)
         const int pr = w / Dp, k = w % Dp;
+        if (s_s[pr] == 0.0) continue;
         const int p = s_p[pr], q = s_q[pr];
         const double c = s_c[pr], s = s_s[pr];
         const double akp = A[k * Dp + p], akq = A[k * Dp + q];
         A[k * Dp + p] = c * akp - s * akq;
         A[k * Dp + q] = s * akp + c * akq;
       }
-      __syncthreads();
-      for (int w = t; w < half * Dp; w += blockDim.x) {  // A := J^T A (rows p, q)
+      wave_lds_sync();
+      for (int w = t; w < half * Dp; w += kWave) {  // A := J^T A (rows p, q)
         const int pr = w / Dp, k = w % Dp;
+        if (s_s[pr] == 0.0) continue;
         const int p = s_p[pr], q = s_q[pr];
         const double c = s_c[pr], s = s_s[pr];
         const double apk = A[p * Dp + k], aqk = A[q * Dp + k];
         A[p * Dp + k] = c * apk - s * aqk;
         A[q * Dp + k] = s * apk + c * aqk;
       }
-      __syncthreads();
+      wave_lds_sync();
       if (t < half) {  // the rotation annihilates the pair entry; drop its rounding residue
         A[s_p[t] * Dp + s_q[t]] = 0.0;
         A[s_q[t] * Dp + s_p[t]] = 0.0;
       }
-      __syncthreads();
+      wave_lds_sync();
     }
+    const int any = *s_flag;
+    wave_lds_sync();
+    if (any == 0) break;
   }
 }
 
+// Per-point work of one tile slot: gather the patch into three LDS rows,
+// compute the FSLR spread (and optionally the 3x3 eigenvalues) in FP64.
+// PT > 0: the patch size is a compile-time constant (values in registers,
+// every gather issued before any is used).
+template <int PT, bool EIG3>
+__device__ __forceinline__ bool patch_point(const NoiseArgs &a, int64_t i, const int32_t *__restrict__ col,
+                                            const float *__restrict__ rgb, float *r0, float *r1, float *r2,
+                                            double *__restrict__ spread, float *__restrict__ eig3) {
+  const int D = a.D, P = a.P, K = a.K;
+  if (col[i * K + (P - 1)] < 0) return false;
+  double mean[3], cov[6] = {0, 0, 0, 0, 0, 0};
+  if constexpr (PT > 0) {
+    int cj[PT];
+    if (PT % 4 == 0 && (K % 4) == 0) {
+#pragma unroll
+      for (int q = 0; q < PT / 4; ++q) {
+        const int4 c4 = reinterpret_cast<const int4 *>(col + i * K)[q];
+        cj[4 * q + 0] = c4.x;
+        cj[4 * q + 1] = c4.y;
+        cj[4 * q + 2] = c4.z;
+        cj[4 * q + 3] = c4.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PT; ++k) cj[k] = col[i * K + k];
+    }
+    float v[3][PT + 1];
+    v[0][0] = rgb[3 * i + 0];
+    v[1][0] = rgb[3 * i + 1];
+    v[2][0] = rgb[3 * i + 2];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int64_t j = cj[k];
+      v[0][1 + k] = rgb[3 * j + 0];
+      v[1][1 + k] = rgb[3 * j + 1];
+      v[2][1 + k] = rgb[3 * j + 2];
+    }
+#pragma unroll
+    for (int k = 0; k <= PT; ++k) {
+      r0[k] = v[0][k];
+      r1[k] = v[1][k];
+      r2[k] = v[2][k];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k <= PT; ++k) s += (double)v[c][k];
+      mean[c] = s / (double)(PT + 1);
+    }
+#pragma unroll
+    for (int k = 0; k <= PT; ++k) {
+      const double d0 = (double)v[0][k] - mean[0];
+      const double d1 = (double)v[1][k] - mean[1];
+      const double d2 = (double)v[2][k] - mean[2];
+      cov[0] += d0 * d0;
+      cov[3] += d1 * d1;
+      cov[5] += d2 * d2;
+      if (EIG3) {
+        cov[1] += d0 * d1;
+        cov[2] += d0 * d2;
+        cov[4] += d1 * d2;
+      }
+    }
+  } else {
+    r0[0] = rgb[3 * i + 0];
+    r1[0] = rgb[3 * i + 1];
+    r2[0] = rgb[3 * i + 2];
+    for (int k = 0; k < P; ++k) {
+      const int64_t j = col[i * K + k];
+      r0[1 + k] = rgb[3 * j + 0];
+      r1[1 + k] = rgb[3 * j + 1];
+      r2[1 + k] = rgb[3 * j + 2];
+    }
+    const float *rr[3] = {r0, r1, r2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < D; ++k) s += (double)rr[c][k];
+      mean[c] = s / (double)D;
+    }
+    for (int k = 0; k < D; ++k) {
+      const double d0 = (double)r0[k] - mean[0];
+      const double d1 = (double)r1[k] - mean[1];
+      const double d2 = (double)r2[k] - mean[2];
+      cov[0] += d0 * d0;
+      cov[3] += d1 * d1;
+      cov[5] += d2 * d2;
+      if (EIG3) {
+        cov[1] += d0 * d1;
+        cov[2] += d0 * d2;
+        cov[4] += d1 * d2;
+      }
+    }
+  }
+  const double invD = 1.0 / (double)D;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) cov[m] *= invD;
+  spread[i] = (sqrt(cov[0]) + sqrt(cov[3]) + sqrt(cov[5])) / 3.0;
+  if (EIG3) {
+    double ev[3];
+    eig3_sym(cov[0], cov[1], cov[2], cov[3], cov[4], cov[5], ev);
+    eig3[3 * i + 0] = (float)ev[0];
+    eig3[3 * i + 1] = (float)ev[1];
+    eig3[3 * i + 2] = (float)ev[2];
+  }
+  return true;
+}
+
+template <int PT, bool EIG3>
 __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__restrict__ col,
                                                   const float *__restrict__ rgb, double *__restrict__ spread,
                                                   float *__restrict__ eig3, double *__restrict__ part) {
@@ -143,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   __shared__ double s_red[8];
 
   const int t = threadIdx.x;
-  const int D = a.D, P = a.P, K = a.K, TP = a.TP;
+  const int D = a.D, TP = a.TP;
   for (int e = t; e < a.E2; e += kBlock) {
     int k = 0, rem = e;
     while (rem >= D - k) { rem -= D - k; ++k; }
@@ -154,7 +273,12 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   const int Eg = (G > 1) ? a.E : kBlock;
   const int grp = (G > 1) ? t / a.E : 0;
   const bool owner = (G > 1) ? (t < G * a.E) : true;
-  double acc[3] = {0.0, 0.0, 0.0};
+  // entries per thread: one when the patch size is compile-time (D <= 19 gives
+  // E <= 256), up to three otherwise
+  constexpr int NE = PT > 0 ? 1 : 3;
+  double acc[NE][4];
+#pragma unroll
+  for (int m = 0; m < NE; ++m) acc[m][0] = acc[m][1] = acc[m][2] = acc[m][3] = 0.0;
   double count = 0.0;
   const int rows = 3 * TP;
   __syncthreads();
@@ -167,49 +291,9 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
       float *r1 = s_v + (size_t)(3 * t + 1) * D;
       float *r2 = s_v + (size_t)(3 * t + 2) * D;
       bool complete = false;
-      if (i < sh.end) complete = col[i * K + (P - 1)] >= 0;
+      if (i < sh.end) complete = patch_point<PT, EIG3>(a, i, col, rgb, r0, r1, r2, spread, eig3);
       if (complete) {
-        r0[0] = rgb[3 * i + 0];
-        r1[0] = rgb[3 * i + 1];
-        r2[0] = rgb[3 * i + 2];
-        for (int k = 0; k < P; ++k) {
-          const int64_t j = col[i * K + k];
-          r0[1 + k] = rgb[3 * j + 0];
-          r1[1 + k] = rgb[3 * j + 1];
-          r2[1 + k] = rgb[3 * j + 2];
-        }
         count += 1.0;
-        // per-channel mean and population variance over the patch (FP64)
-        double mean[3], cov[6] = {0, 0, 0, 0, 0, 0};
-        const float *rr[3] = {r0, r1, r2};
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          double s = 0.0;
-          for (int k = 0; k < D; ++k) s += (double)rr[c][k];
-          mean[c] = s / (double)D;
-        }
-        for (int k = 0; k < D; ++k) {
-          const double d0 = (double)r0[k] - mean[0];
-          const double d1 = (double)r1[k] - mean[1];
-          const double d2 = (double)r2[k] - mean[2];
-          cov[0] += d0 * d0;
-          cov[1] += d0 * d1;
-          cov[2] += d0 * d2;
-          cov[3] += d1 * d1;
-          cov[4] += d1 * d2;
-          cov[5] += d2 * d2;
-        }
-        const double invD = 1.0 / (double)D;
-#pragma unroll
-        for (int m = 0; m < 6; ++m) cov[m] *= invD;
-        spread[i] = (sqrt(cov[0]) + sqrt(cov[3]) + sqrt(cov[5])) / 3.0;
-        if (a.want_eig3) {
-          double ev[3];
-          eig3_sym(cov[0], cov[1], cov[2], cov[3], cov[4], cov[5], ev);
-          eig3[3 * i + 0] = (float)ev[0];
-          eig3[3 * i + 1] = (float)ev[1];
-          eig3[3 * i + 2] = (float)ev[2];
-        }
       } else {
         for (int k = 0; k < D; ++k) {
           r0[k] = 0.0f;
@@ -218,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
         }
         if (i < sh.end) {
           spread[i] = __builtin_huge_val();
-          if (a.want_eig3) {
+          if (EIG3) {
             eig3[3 * i + 0] = 0.0f;
             eig3[3 * i + 1] = 0.0f;
             eig3[3 * i + 2] = 0.0f;
@@ -229,63 +313,103 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
     __syncthreads();
     if (owner) {
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
+      for (int m = 0; m < NE; ++m) {
         const int e = (G > 1 ? t % a.E : t) + m * Eg;
         if (e < a.E && (G > 1 ? m == 0 : true)) {
-          double s = acc[m];
+          // four independent accumulators over the rows keep the FP64 adds
+          // from forming one long dependency chain
+          double s0 = acc[m][0], s1 = acc[m][1], s2 = acc[m][2], s3 = acc[m][3];
           if (e < a.E2) {
             const int kk = s_pair[e] >> 8, ll = s_pair[e] & 255;
-            for (int r = grp; r < rows; r += G) s += (double)s_v[r * D + kk] * (double)s_v[r * D + ll];
+            int r = grp;
+            for (; r + 3 * G < rows; r += 4 * G) {
+              s0 += (double)s_v[r * D + kk] * (double)s_v[r * D + ll];
+              s1 += (double)s_v[(r + G) * D + kk] * (double)s_v[(r + G) * D + ll];
+              s2 += (double)s_v[(r + 2 * G) * D + kk] * (double)s_v[(r + 2 * G) * D + ll];
+              s3 += (double)s_v[(r + 3 * G) * D + kk] * (double)s_v[(r + 3 * G) * D + ll];
+            }
+            for (; r < rows; r += G) s0 += (double)s_v[r * D + kk] * (double)s_v[r * D + ll];
           } else {
             const int c = (e - a.E2) / D, kk = (e - a.E2) % D;
-            for (int p = grp; p < TP; p += G) s += (double)s_v[(3 * p + c) * D + kk];
+            int p = grp;
+            for (; p + 3 * G < TP; p += 4 * G) {
+              s0 += (double)s_v[(3 * p + c) * D + kk];
+              s1 += (double)s_v[(3 * (p + G) + c) * D + kk];
+              s2 += (double)s_v[(3 * (p + 2 * G) + c) * D + kk];
+              s3 += (double)s_v[(3 * (p + 3 * G) + c) * D + kk];
+            }
+            for (; p < TP; p += G) s0 += (double)s_v[(3 * p + c) * D + kk];
           }
-          acc[m] = s;
+          acc[m][0] = s0;
+          acc[m][1] = s1;
+          acc[m][2] = s2;
+          acc[m][3] = s3;
         }
       }
     }
     __syncthreads();
   }
 
-  // combine row groups (fixed order) and write this block's partial
+  // combine accumulators and row groups (fixed order); write this block's
+  // partials entry-major: part[e * nblocks + block], entry 0 = patch count
   double *scratch = reinterpret_cast<double *>(s_v);  // >= 768 doubles available
+  const int nb = gridDim.x;
   {
     double cv[1] = {count};
     block_sum_f64<1>(cv, s_red);
-    if (t == 0) part[(size_t)blockIdx.x * (1 + a.E)] = cv[0];
+    if (t == 0) part[blockIdx.x] = cv[0];
   }
-  scratch[3 * t + 0] = acc[0];
-  scratch[3 * t + 1] = acc[1];
-  scratch[3 * t + 2] = acc[2];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) scratch[3 * t + m] = m < NE ? (acc[m < NE ? m : 0][0] + acc[m < NE ? m : 0][1]) +
+                                                                (acc[m < NE ? m : 0][2] + acc[m < NE ? m : 0][3])
+                                                          : 0.0;
   __syncthreads();
-  double *dst = part + (size_t)blockIdx.x * (1 + a.E) + 1;
   if (G > 1) {
     for (int e = t; e < a.E; e += kBlock) {
       double s = 0.0;
       for (int g = 0; g < G; ++g) s += scratch[3 * (g * a.E + e) + 0];
-      dst[e] = s;
+      part[(size_t)(1 + e) * nb + blockIdx.x] = s;
     }
   } else {
-    for (int e = t; e < a.E; e += kBlock) dst[e] = scratch[3 * (e % kBlock) + e / kBlock];
+    for (int e = t; e < a.E; e += kBlock) part[(size_t)(1 + e) * nb + blockIdx.x] = scratch[3 * (e % kBlock) + e / kBlock];
   }
 }
 
 // One block: sum the k_noise partials in block order, form Sigma, find its
 // eigenvalues (parallel Jacobi, FP64) and apply the tail rule.
-__global__ __launch_bounds__(kBlock) void k_noise_solve(NoiseArgs a, const double *__restrict__ part, int nb,
-                                                        fgbd_result *__restrict__ res) {
+constexpr int kSolveThreads = 1024;
+
+// One block: sum the k_noise partials (one wave per entry row, lanes stride
+// the blocks, fixed shuffle tree), form Sigma, then wave 0 alone finds its
+// eigenvalues (Jacobi, FP64) and applies the tail rule.
+__global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, const double *__restrict__ part, int nb,
+                                                               fgbd_result *__restrict__ res) {
   __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
   __shared__ double s_jc[kMaxD], s_js[kMaxD];
   __shared__ int s_jp[kMaxD], s_jq[kMaxD], s_flag;
+  __shared__ double s_lam[kMaxD + 1];
   const int t = threadIdx.x;
+  const int lane = (int)lane_id();
+  const int wave = t / kWave;
+  const int nwaves = blockDim.x / kWave;
   const int D = a.D;
   const int stride = 1 + a.E;
   double *tot = s_buf;
-  for (int e = t; e < stride; e += kBlock) {
-    double s = 0.0;
-#pragma unroll 16
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * stride + e];
-    tot[e] = s;
+  for (int e = wave; e < stride; e += nwaves) {
+    const double *row = part + (size_t)e * nb;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = lane;
+    for (; b + 3 * kWave < nb; b += 4 * kWave) {
+      s0 += row[b];
+      s1 += row[b + kWave];
+      s2 += row[b + 2 * kWave];
+      s3 += row[b + 3 * kWave];
+    }
+    for (; b < nb; b += kWave) s0 += row[b];
+    double v = (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+    if (lane == 0) tot[e] = v;
   }
   __syncthreads();
   const double n_eff = tot[0];
@@ -294,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_noise_solve(NoiseArgs a, const doubl
   if (n_eff > 0.0) {
     const double *S2 = tot + 1;
     const double *S1 = tot + 1 + a.E2;
-    for (int w = t; w < Dp * Dp; w += kBlock) {
+    for (int w = t; w < Dp * Dp; w += blockDim.x) {
       const int k = w / Dp, l = w % Dp;
       double v = 0.0;
       if (k < D && l < D) {
@@ -306,15 +430,15 @@ __global__ __launch_bounds__(kBlock) void k_noise_solve(NoiseArgs a, const doubl
       }
       A[w] = v;
     }
-    __syncthreads();
-    jacobi_eigs(A, Dp, s_jc, s_js, s_jp, s_jq, &s_flag);
   }
   __syncthreads();
+  if (wave != 0) return;  // no block barrier follows
+  if (n_eff > 0.0) jacobi_eigs_wave(A, Dp, s_jc, s_js, s_jp, s_jq, &s_flag);
   if (t == 0) {
     double sigma = 0.0;
     int m_star = 0;
     if (n_eff > 0.0) {
-      double lam[kMaxD + 1];
+      double *lam = s_lam;  // LDS, not a private array (would live in scratch)
       for (int k = 0; k < D; ++k) lam[k] = A[k * Dp + k];
       for (int k = 1; k < D; ++k) {  // descending insertion sort
         const double v = lam[k];
@@ -362,13 +486,20 @@ hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float
                         double *part, int nblocks, hipStream_t stream) {
   const NoiseArgs a = make_args(n, k, P, eig3 != nullptr);
   const size_t lds = (size_t)3 * a.TP * a.D * sizeof(float);
-  k_noise<<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+  if (P == 8 && eig3 == nullptr)
+    k_noise<8, false><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+  else if (P == 8)
+    k_noise<8, true><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+  else if (eig3 == nullptr)
+    k_noise<0, false><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+  else
+    k_noise<0, true><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
   return hipGetLastError();
 }
 
 hipError_t launch_noise_solve(int P, const double *part, int nblocks, fgbd_result *res, hipStream_t stream) {
   const NoiseArgs a = make_args(0, P, P, false);
-  k_noise_solve<<<1, kBlock, 0, stream>>>(a, part, nblocks, res);
+  k_noise_solve<<<1, kSolveThreads, 0, stream>>>(a, part, nblocks, res);
   return hipGetLastError();
 }
 

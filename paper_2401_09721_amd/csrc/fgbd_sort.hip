@@ -42,12 +42,18 @@ __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const int32_t *
 __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const int32_t *__restrict__ xyz,
                                                                const uint64_t *__restrict__ src,
                                                                uint32_t *__restrict__ hist,
+                                                               uint32_t *__restrict__ totals,
                                                                fgbd_result *__restrict__ res) {
   __shared__ uint32_t s_h[256];
+  __shared__ uint32_t s_all[kSortPasses][256];
   const int d = blockIdx.y;
   const int tile = blockIdx.x;
   const int t = threadIdx.x;
   s_h[t] = 0;
+  if (a.pass == 0) {
+#pragma unroll
+    for (int q = 0; q < kSortPasses; ++q) s_all[q][t] = 0;
+  }
   __syncthreads();
   const int wave = t / kWave;
   const int lane = (int)lane_id();
@@ -60,42 +66,55 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
       const uint64_t it = load_item(a, xyz, src, d, pos, &bad);
       const uint32_t digit = (uint32_t)(it >> (32 + a.shift)) & 255u;
       atomicAdd(&s_h[digit], 1u);
+      if (a.pass == 0) {  // digit totals of every pass, for the offset scan
+#pragma unroll
+        for (int q = 1; q < kSortPasses; ++q) atomicAdd(&s_all[q][(uint32_t)(it >> (32 + 8 * q)) & 255u], 1u);
+      }
     }
   }
   if (bad && d == 0) atomicOr(&res->status, FGBD_ST_COORD_RANGE);
   __syncthreads();
   hist[((size_t)d * 256 + t) * a.ntiles + tile] = s_h[t];
+  if (a.pass == 0) {
+    uint32_t *tot = totals + (size_t)d * kSortPasses * 256;
+    if (s_h[t]) atomicAdd(&tot[t], s_h[t]);
+#pragma unroll
+    for (int q = 1; q < kSortPasses; ++q)
+      if (s_all[q][t]) atomicAdd(&tot[q * 256 + t], s_all[q][t]);
+  }
 }
 
-// Exclusive prefix over the digit-major histogram of one direction (one block
-// per direction, 1024 threads, chunks of 8 consecutive counts per thread with
-// a running carry), which turns the count of (digit, tile) into its global
-// output offset.
-constexpr int kScanItems = 8;
-__global__ __launch_bounds__(kScanThreads) void k_sort_scan(int ntiles, uint32_t *__restrict__ hist) {
-  __shared__ uint32_t s_tmp[16];
-  const int d = blockIdx.x;
-  const int t = threadIdx.x;
-  const int64_t total = (int64_t)256 * ntiles;
-  uint32_t *h = hist + (size_t)d * total;
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < total; base += (int64_t)kScanThreads * kScanItems) {
-    const int64_t i0 = base + (int64_t)t * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t sum = 0;
+// Global offsets: one wave per (direction, digit) row of tile counts.  The
+// row's base is the sum of the direction's totals of all smaller digits; the
+// row is then scanned 64 tiles at a time with a wave prefix sum.
+__global__ __launch_bounds__(256) void k_sort_scan(int ntiles, int num_dirs, int pass, uint32_t *__restrict__ hist,
+                                                   const uint32_t *__restrict__ totals) {
+  const int row = blockIdx.x * 4 + threadIdx.x / kWave;
+  if (row >= num_dirs * 256) return;
+  const int d = row / 256, digit = row % 256;
+  const uint32_t lane = lane_id();
+  const uint32_t *tot = totals + ((size_t)d * kSortPasses + pass) * 256;
+  uint32_t b = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      v[j] = (i0 + j < total) ? h[i0 + j] : 0u;
-      sum += v[j];
-    }
-    uint32_t chunk_total;
-    uint32_t run = carry + block_exclusive_scan(sum, s_tmp, &chunk_total);
+  for (int j = 0; j < 4; ++j) {
+    const int dg = (int)lane + 64 * j;
+    b += dg < digit ? tot[dg] : 0u;
+  }
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      if (i0 + j < total) h[i0 + j] = run;
-      run += v[j];
+  for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, kWave);
+  uint32_t carry = b;
+  uint32_t *h = hist + (size_t)row * ntiles;
+  for (int t0 = 0; t0 < ntiles; t0 += kWave) {
+    const int tile = t0 + (int)lane;
+    const uint32_t v = tile < ntiles ? h[tile] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, kWave);
+      if (lane >= (uint32_t)o) x += y;
     }
-    carry += chunk_total;
+    if (tile < ntiles) h[tile] = carry + x - v;
+    carry += __shfl(x, kWave - 1, kWave);
   }
 }
 
@@ -188,9 +207,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
 
 }  // namespace
 
+__global__ void k_zero(uint32_t *__restrict__ p, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
 hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const Plan &pl, uint64_t *items_a,
-                       uint64_t *items_b, uint32_t *hist, uint32_t *rank, fgbd_result *res, hipStream_t stream,
-                       const uint64_t **sorted_out, Prof *pf) {
+                       uint64_t *items_b, uint32_t *hist, uint32_t *totals, uint32_t *rank, fgbd_result *res,
+                       hipStream_t stream, const uint64_t **sorted_out, Prof *pf) {
   SortArgs a;
   a.dt = dt;
   a.n = (int32_t)n;
@@ -198,15 +221,18 @@ hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const 
   const dim3 grid(pl.ntiles, dt.num_dirs);
   const uint64_t *src = nullptr;
   uint64_t *bufs[2] = {items_a, items_b};
+  FGBD_PRE(pf, kUpsweep);
+  k_zero<<<1, 256, 0, stream>>>(totals, dt.num_dirs * kSortPasses * 256);
+  FGBD_POST(pf);
   for (int pass = 0; pass < kSortPasses; ++pass) {
     a.pass = pass;
     a.shift = 8 * pass;
     uint64_t *dst = bufs[pass & 1];
     FGBD_PRE(pf, kUpsweep);
-    k_sort_upsweep<<<grid, kSortThreads, 0, stream>>>(a, xyz, src, hist, res);
+    k_sort_upsweep<<<grid, kSortThreads, 0, stream>>>(a, xyz, src, hist, totals, res);
     FGBD_POST(pf);
     FGBD_PRE(pf, kScan);
-    k_sort_scan<<<dt.num_dirs, kScanThreads, 0, stream>>>(pl.ntiles, hist);
+    k_sort_scan<<<(dt.num_dirs * 256 + 3) / 4, 256, 0, stream>>>(pl.ntiles, dt.num_dirs, pass, hist, totals);
     FGBD_POST(pf);
     FGBD_PRE(pf, kDownsweep);
     k_sort_downsweep<<<grid, kSortThreads, 0, stream>>>(a, xyz, src, dst, hist, rank);

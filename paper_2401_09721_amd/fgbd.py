@@ -85,6 +85,12 @@ _SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_denoise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_poly_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "fgbd_poly_filter_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_last_error": (ctypes.c_char_p, []),
     "fgbd_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "fgbd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -328,3 +334,78 @@ def denoise(xyz, rgb, params=None, ctx: Optional[Context] = None, out=None, res=
     _check(lib().fgbd_denoise(ctx.handle, _ptr(xyz), _ptr(rgb), n, ctypes.byref(prm), _ptr(out), _ptr(res),
                               _stream(ctx, stream)))
     return out, res
+
+
+# ------------------------------------------------------- polynomial filter
+def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None, stream=None):
+    """out = sum_k coef[k] T^k x with eq. 4 weights at the device bandwidth
+    sigma_g (float64 scalar tensor).  Returns (out, saved iterates)."""
+    torch = _torch()
+    ctx = ctx or default_context(x.device)
+    _need(x, torch.float32, (3,), "x", ctx.device)
+    if coef.dtype != torch.float32 or coef.device != ctx.device or coef.dim() != 1:
+        raise ValueError("coef must be a 1-D float32 device tensor")
+    if sigma_g.dtype != torch.float64 or sigma_g.device != ctx.device or sigma_g.numel() != 1:
+        raise ValueError("sigma_g must be a float64 device scalar")
+    n, nc = graph.n, int(coef.numel())
+    coef = coef.contiguous()
+    sigma_g = sigma_g.contiguous()
+    out = torch.empty_like(x)
+    saved = torch.empty((nc, n, 3), dtype=torch.float32, device=ctx.device)
+    gs = graph.c_struct()
+    _check(lib().fgbd_poly_filter(ctx.handle, ctypes.byref(gs), _ptr(x), _ptr(coef), nc, _ptr(sigma_g), _ptr(out),
+                                  _ptr(saved), _stream(ctx, stream)))
+    return out, saved
+
+
+def poly_filter_backward(graph: SLGraph, saved, coef, sigma_g, grad_out, ctx: Optional[Context] = None,
+                         stream=None):
+    """Adjoint of poly_filter.  Returns (grad_x, grad_coef, grad_sigma_g)."""
+    torch = _torch()
+    ctx = ctx or default_context(grad_out.device)
+    grad_out = grad_out.contiguous()
+    _need(grad_out, torch.float32, (3,), "grad_out", ctx.device)
+    nc = int(coef.numel())
+    gx = torch.empty_like(grad_out)
+    gc = torch.empty(nc, dtype=torch.float32, device=ctx.device)
+    gsig = torch.empty((), dtype=torch.float64, device=ctx.device)
+    gs = graph.c_struct()
+    _check(lib().fgbd_poly_filter_backward(ctx.handle, ctypes.byref(gs), _ptr(saved), _ptr(coef.contiguous()), nc,
+                                           _ptr(sigma_g.contiguous()), _ptr(grad_out), _ptr(gx), _ptr(gc),
+                                           _ptr(gsig), _stream(ctx, stream)))
+    return gx, gc, gsig
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class FgbdPolyFilter(torch.autograd.Function):
+        """Differentiable polynomial graph filter: gradients with respect to the
+        colours, the coefficients and the bandwidth come from the library's
+        hand-written adjoint."""
+
+        @staticmethod
+        def forward(fctx, x, coef, sigma_g, graph, ctx=None):
+            out, saved = poly_filter(graph, x.detach().contiguous(), coef.detach(), sigma_g.detach(), ctx=ctx)
+            fctx.graph, fctx.lib_ctx = graph, ctx
+            fctx.save_for_backward(saved, coef.detach(), sigma_g.detach())
+            return out
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            saved, coef, sigma_g = fctx.saved_tensors
+            gx, gc, gs = poly_filter_backward(fctx.graph, saved, coef, sigma_g, grad_out, ctx=fctx.lib_ctx)
+            return gx, gc, gs.reshape(sigma_g.shape), None, None
+
+    return FgbdPolyFilter
+
+
+_poly_fn = None
+
+
+def poly_filter_autograd(x, coef, sigma_g, graph: SLGraph, ctx: Optional[Context] = None):
+    """FgbdPolyFilter.apply: differentiable in x, coef and sigma_g."""
+    global _poly_fn
+    if _poly_fn is None:
+        _poly_fn = _make_autograd()
+    return _poly_fn.apply(x, coef, sigma_g, graph, ctx)

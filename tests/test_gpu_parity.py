@@ -261,3 +261,66 @@ def test_denoise_large_frame(large_cloud):
     assert r["n_eff"] == c.n
     g, col, d2, p, _ = gpu_graph(c.xyz, fgbd.default_params())
     assert np.array_equal(col, o["col"]) and np.array_equal(d2, o["dist2"])
+
+
+# ------------------------------------------------------- polynomial filter
+
+def _poly_case(seed, ncoef=8):
+    c = synth.tiny_cloud(0)
+    prm = fgbd.default_params(bits=8)
+    g = fgbd.build_slg(dev(c.xyz, torch.int32), prm)
+    rng = np.random.default_rng(seed)
+    coef = rng.uniform(-0.5, 1.0, size=ncoef)
+    sg = 1.7
+    go = rng.standard_normal((c.n, 3))
+    return c, g, coef, sg, go
+
+
+@pytest.mark.parametrize("ncoef", [1, 2, 8])
+def test_poly_filter_forward_and_adjoint(ncoef):
+    c, g, coef, sg, go = _poly_case(ncoef, ncoef)
+    x = dev(c.noisy, torch.float32)
+    ct = dev(coef, torch.float32)
+    st = torch.tensor(sg, dtype=torch.float64, device="cuda")
+    out, saved = fgbd.poly_filter(g, x, ct, st)
+    gx, gc, gs = fgbd.poly_filter_backward(g, saved, ct, st, dev(go, torch.float32))
+    torch.cuda.synchronize()
+    col, d2 = g.col.cpu().numpy(), g.dist2.cpu().numpy()
+    coef32 = coef.astype(np.float32).astype(np.float64)
+    ref = O.poly_filter(col, d2, c.noisy, coef32, sg)
+    assert np.max(np.abs(out.cpu().numpy() - ref)) <= COLOUR_TOL
+    rx, rc, rs = O.poly_filter_grads(col, d2, c.noisy, coef32, sg, go.astype(np.float32))
+    gxn = gx.cpu().numpy()
+    assert np.max(np.abs(gxn - rx)) <= 1e-3 * max(1.0, np.max(np.abs(rx)))
+    assert np.allclose(gc.cpu().numpy(), rc, rtol=1e-3, atol=1e-3 * np.max(np.abs(rc)))
+    assert math.isclose(float(gs), rs, rel_tol=1e-3, abs_tol=1e-3 * max(1.0, abs(rs)))
+
+
+def test_poly_filter_e_q_is_eq5():
+    c, g, _, _, _ = _poly_case(0)
+    prm = fgbd.default_params(bits=8)
+    x = dev(c.noisy, torch.float32)
+    sg = fgbd.read_result(g.result)["sigma_g"]
+    st = torch.tensor(sg, dtype=torch.float64, device="cuda")
+    for q in (0, 3):
+        coef = torch.zeros(5, dtype=torch.float32, device="cuda")
+        coef[q] = 1.0
+        out, _ = fgbd.poly_filter(g, x, coef, st)
+        ref, _ = fgbd.filter(g, x, prm, q_fixed=q)
+        torch.cuda.synchronize()
+        assert torch.max(torch.abs(out - ref)).item() <= 1e-4
+
+
+def test_poly_autograd_function():
+    c, g, coef, sg, go = _poly_case(3)
+    x = dev(c.noisy, torch.float32).requires_grad_(True)
+    ct = dev(coef, torch.float32).requires_grad_(True)
+    st = torch.tensor(sg, dtype=torch.float64, device="cuda", requires_grad=True)
+    out = fgbd.poly_filter_autograd(x, ct, st, g)
+    (out * dev(go, torch.float32)).sum().backward()
+    torch.cuda.synchronize()
+    col, d2 = g.col.cpu().numpy(), g.dist2.cpu().numpy()
+    rx, rc, rs = O.poly_filter_grads(col, d2, c.noisy, coef.astype(np.float32), sg, go.astype(np.float32))
+    assert np.max(np.abs(x.grad.cpu().numpy() - rx)) <= 1e-3 * max(1.0, np.max(np.abs(rx)))
+    assert np.allclose(ct.grad.cpu().numpy(), rc, rtol=1e-3, atol=1e-3 * np.max(np.abs(rc)))
+    assert math.isclose(float(st.grad), rs, rel_tol=1e-3)
