@@ -53,6 +53,8 @@ def main() -> int:
     ap.add_argument("--points", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel profiled pass")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -176,6 +178,14 @@ def main() -> int:
                                   "frac": b / (per_launch / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                                   "bytes_per_launch": b, "us_per_launch": 1e3 * per_launch,
                                   "launches": launches}
+
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": src.numel() * 4, "written": dst.numel() * 4, "launches": 3}
 
     # ---- CPU oracle on the host (reported baseline, not a target)
     if not args.no_cpu_baseline:

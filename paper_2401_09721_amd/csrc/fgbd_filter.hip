@@ -82,29 +82,35 @@ __device__ void advance(SweepCtrl &c, const double (&t)[kSweepParts], int n, int
 
 // Selection state at the start of a launch: the stored state advanced by the
 // previous sweep's integer sums (identical in every block).  Called by every
-// thread of the block; the slots are loaded in parallel and summed in LDS.
+// thread of the block; wave 0 loads the slots (one per lane) and reduces them
+// with shuffles.
 __device__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
                            const unsigned long long *__restrict__ sums_prev, int n) {
-  __shared__ unsigned long long s_slot[kSweepSlots * kSweepParts];
-  __shared__ unsigned long long s_part[kSweepParts * 32];
+  __shared__ unsigned long long s_tot[kSweepParts];
   c = *prev;
   if (c.done) return;  // uniform: every thread read the same state
-  for (int j = threadIdx.x; j < kSweepSlots * kSweepParts; j += blockDim.x) s_slot[j] = sums_prev[j];
-  __syncthreads();
-  if (threadIdx.x < kSweepParts * 32) {
-    const int part = threadIdx.x / 32, g = threadIdx.x % 32;
-    unsigned long long u = 0;
-    for (int sl = g; sl < kSweepSlots; sl += 32) u += s_slot[sl * kSweepParts + part];
-    s_part[threadIdx.x] = u;
+  if (threadIdx.x < kWave) {
+    unsigned long long u[kSweepParts];
+#pragma unroll
+    for (int j = 0; j < kSweepParts; ++j) u[j] = 0;
+    for (int sl = (int)threadIdx.x; sl < kSweepSlots; sl += kWave) {
+#pragma unroll
+      for (int j = 0; j < kSweepParts; ++j) u[j] += sums_prev[sl * kSweepParts + j];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int j = 0; j < kSweepParts; ++j) u[j] += __shfl_xor(u[j], o, kWave);
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < kSweepParts; ++j) s_tot[j] = u[j];
+    }
   }
   __syncthreads();
   double t[kSweepParts];
 #pragma unroll
-  for (int j = 0; j < kSweepParts; ++j) {
-    unsigned long long u = 0;
-    for (int g = 0; g < 32; ++g) u += s_part[j * 32 + g];
-    t[j] = j < 4 ? (double)u / kFix : (double)u;
-  }
+  for (int j = 0; j < kSweepParts; ++j) t[j] = j < 4 ? (double)s_tot[j] / kFix : (double)s_tot[j];
   advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
 }
 
@@ -208,22 +214,22 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
         ww[k] = k < K ? p[i * K + k] : 0.0f;
       }
     }
+    // Branch-free gathers: an empty slot (col = -1, weight 0) reads the point
+    // itself, so every load is issued before any is consumed.
     float ar = 0.f, ag = 0.f, ab = 0.f;
 #pragma unroll
     for (int k = 0; k < (KT > 0 ? KT : kMaxK); ++k) {
-      const int cj = cc[k];
-      if (cj >= 0) {
-        const float w = ww[k];
-        if (FIRST) {
-          ar = fmaf(w, rgb_in[3 * (size_t)cj + 0], ar);
-          ag = fmaf(w, rgb_in[3 * (size_t)cj + 1], ag);
-          ab = fmaf(w, rgb_in[3 * (size_t)cj + 2], ab);
-        } else {
-          const float4 xc = xin[cj];
-          ar = fmaf(w, xc.x, ar);
-          ag = fmaf(w, xc.y, ag);
-          ab = fmaf(w, xc.z, ab);
-        }
+      const int64_t cj = cc[k] >= 0 ? (int64_t)cc[k] : i;
+      const float w = cc[k] >= 0 ? ww[k] : 0.0f;
+      if (FIRST) {
+        ar = fmaf(w, rgb_in[3 * cj + 0], ar);
+        ag = fmaf(w, rgb_in[3 * cj + 1], ag);
+        ab = fmaf(w, rgb_in[3 * cj + 2], ab);
+      } else {
+        const float4 xc = xin[cj];
+        ar = fmaf(w, xc.x, ar);
+        ag = fmaf(w, xc.y, ag);
+        ab = fmaf(w, xc.z, ab);
       }
     }
     float orr = xr, og = xg, ob = xb;

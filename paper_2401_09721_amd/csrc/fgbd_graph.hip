@@ -64,12 +64,19 @@ __device__ __forceinline__ void topk_insert_t(Key (&lst)[KM], int K, Key c) {
   lst[0] = lst[0] > c ? c : lst[0];
 }
 
+// Window items r-WT..r+WT; positions outside 0..n-1 load a clamped position
+// (branch-free, all loads in flight together) and are then marked empty.
 template <int WT>
 __device__ __forceinline__ void load_window(const uint64_t *__restrict__ srt, int r, int n, uint64_t (&w)[2 * WT + 1]) {
 #pragma unroll
   for (int s = 0; s <= 2 * WT; ++s) {
     const int pos = r + s - WT;
-    w[s] = (pos >= 0 && pos < n) ? srt[pos] : ~0ull;
+    w[s] = srt[min(max(pos, 0), n - 1)];
+  }
+#pragma unroll
+  for (int s = 0; s <= 2 * WT; ++s) {
+    const int pos = r + s - WT;
+    if (pos < 0 || pos >= n) w[s] = ~0ull;
   }
 }
 

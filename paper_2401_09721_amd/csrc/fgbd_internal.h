@@ -232,7 +232,7 @@ constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit 
 constexpr int kBlock = 256;
 constexpr int kMaxGrid = 1024;  // grid of the grid-stride kernels
 constexpr int kSweepParts = 5;  // energy sums per sweep
-constexpr int kSweepSlots = 256; // atomic slots per sum (spread to limit contention)
+constexpr int kSweepSlots = 64;  // atomic slots per sum (spread to limit contention)
 constexpr int kSweepMaxGrid = 1024;
 constexpr int kScanThreads = 1024;
 

@@ -82,12 +82,20 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Parallel cyclic Jacobi on a symmetric Dp x Dp matrix in LDS (Dp even), run
 // by one wave.  Round-robin pairing applies Dp/2 disjoint rotations at once.
-// An entry already negligible against its diagonal pair
-// (|a_pq| <= 1e-16 sqrt|a_pp a_qq|) is set to zero instead of rotated; the
-// sweeps stop when a whole sweep needed no rotation (at most 64 sweeps).
+// An entry already negligible (|a_pq| <= 1e-15 |A|_F, or against its diagonal
+// pair) is set to zero instead of rotated; the sweeps stop when a whole sweep
+// needed no rotation (at most 64 sweeps).  Eigenvalues are then accurate to
+// about 1e-15 |A|_F.
 __device__ void jacobi_eigs_wave(double *A, int Dp, double *s_c, double *s_s, int *s_p, int *s_q, int *s_flag) {
   const int t = (int)lane_id();
   const int half = Dp / 2;
+  // Frobenius norm (invariant under the rotations): entries below eps * |A|
+  // are rounding residue and are not rotated
+  double f = 0.0;
+  for (int w = t; w < Dp * Dp; w += kWave) f += A[w] * A[w];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, kWave);
+  const double tiny = 1e-15 * sqrt(f);
   for (int sweep = 0; sweep < 64; ++sweep) {
     if (t == 0) *s_flag = 0;
     wave_lds_sync();
@@ -99,7 +107,7 @@ __device__ void jacobi_eigs_wave(double *A, int Dp, double *s_c, double *s_s, in
         const double apq = A[p * Dp + q];
         const double app = A[p * Dp + p], aqq = A[q * Dp + q];
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-16 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+        if (fabs(apq) > tiny && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + tt * tt);
@@ -397,16 +405,16 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, cons
   double *tot = s_buf;
   for (int e = wave; e < stride; e += nwaves) {
     const double *row = part + (size_t)e * nb;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int b = lane;
-    for (; b + 3 * kWave < nb; b += 4 * kWave) {
-      s0 += row[b];
-      s1 += row[b + kWave];
-      s2 += row[b + 2 * kWave];
-      s3 += row[b + 3 * kWave];
+    // nb <= kMaxGrid: every lane's loads of the row are issued together
+    double vals[kMaxGrid / kWave];
+#pragma unroll
+    for (int u = 0; u < kMaxGrid / kWave; ++u) {
+      const int b = lane + u * kWave;
+      vals[u] = b < nb ? row[b] : 0.0;
     }
-    for (; b < nb; b += kWave) s0 += row[b];
-    double v = (s0 + s1) + (s2 + s3);
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < kMaxGrid / kWave; ++u) v += vals[u];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
     if (lane == 0) tot[e] = v;

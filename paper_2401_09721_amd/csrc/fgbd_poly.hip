@@ -132,13 +132,11 @@ __global__ __launch_bounds__(kBlock) void k_poly_step(int32_t n, int32_t K, int 
       const float *pr = p + i * K;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
       for (int kk = 0; kk < K; ++kk) {
-        const int j = cr[kk];
-        if (j >= 0) {
-          const float w = pr[kk];
-          a0 = fmaf(w, xp[3 * (size_t)j + 0], a0);
-          a1 = fmaf(w, xp[3 * (size_t)j + 1], a1);
-          a2 = fmaf(w, xp[3 * (size_t)j + 2], a2);
-        }
+        const int64_t j = cr[kk] >= 0 ? (int64_t)cr[kk] : i;  // empty slot: weight 0, read self
+        const float w = cr[kk] >= 0 ? pr[kk] : 0.0f;
+        a0 = fmaf(w, xp[3 * j + 0], a0);
+        a1 = fmaf(w, xp[3 * j + 1], a1);
+        a2 = fmaf(w, xp[3 * j + 2], a2);
       }
       const float s0 = xp[3 * i + 0], s1 = xp[3 * i + 1], s2 = xp[3 * i + 2];
       if (cr[0] >= 0) {
