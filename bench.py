@@ -43,6 +43,44 @@ def algorithmic_bytes(kind: str, n: int, L: int, K: int, P: int) -> float:
     return 0.0
 
 
+# Source files each kernel kind is compiled from: a traffic figure measured
+# with hardware counters is only reported while these are unchanged.
+KIND_SOURCES = {
+    "radix_upsweep": ("fgbd_sort.hip",), "radix_scan": ("fgbd_sort.hip",), "radix_downsweep": ("fgbd_sort.hip",),
+    "merge": ("fgbd_graph.hip",), "weights": ("fgbd_graph.hip",),
+    "noise": ("fgbd_noise.hip",), "noise_solve": ("fgbd_noise.hip",),
+    "sweep": ("fgbd_filter.hip",), "finalize": ("fgbd_filter.hip",),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fgbd_1M_frame.md")
+
+
+def source_digest(kind: str) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KIND_SOURCES[kind] + ("fgbd_internal.h",):
+        with open(os.path.join(ROOT, "paper_2401_09721_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kind: str, config: dict):
+    """HBM bytes per launch of `kind` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    plain device copy), or None when the summary is missing, was taken on
+    another workload, or the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kind)
+    if not k or rec.get("config") != config or k.get("source_sha256") != source_digest(kind):
+        return None
+    return k["hbm_bytes_per_launch"]
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,8 +189,10 @@ def main() -> int:
         dom = max((k for k in kernels if algorithmic_bytes(k, n, prm.num_dirs, prm.k, P) > 0),
                   key=lambda k: kernels[k]["ms_per_step"])
         gbs = kernels[dom]["algo_GBs"]
+        tcfg = {"n_points": n, "num_dirs": prm.num_dirs, "window": prm.window, "k": prm.k, "patch": P,
+                "sigma": args.sigma}
         line["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                            "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom, tcfg),
                             "bytes_per_launch": algorithmic_bytes(dom, n, prm.num_dirs, prm.k, P),
                             "us_per_launch": kernels[dom]["us_per_launch"]}
         print(f"# kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
@@ -175,7 +215,8 @@ def main() -> int:
         b = algorithmic_bytes("sweep", n, prm.num_dirs, prm.k, P)
         line["roofline_sweep"] = {"kernel": "sweep (fixed q, every launch active)", "bound": "hbm",
                                   "achieved": b / (per_launch / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": b / (per_launch / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                                  "frac": b / (per_launch / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                  "traffic": measured_traffic("sweep", tcfg),
                                   "bytes_per_launch": b, "us_per_launch": 1e3 * per_launch,
                                   "launches": launches}
 

@@ -11,6 +11,8 @@
  *   fgbd_filter          FSLR filter selection and the low-pass filter, Sec. 2.4,
  *                        eqs. 5-6
  *   fgbd_denoise         all four steps in one call
+ *   fgbd_denoise_batched all four steps for several clouds of different sizes
+ *                        in one launch sequence, sizes read from device memory
  *
  * Conventions shared by every call
  *   - Every pointer named in a call is a DEVICE pointer on the context's GPU
@@ -43,7 +45,10 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 1
+#define FGBD_ABI_VERSION 2
+
+/* Largest number of clouds in one fgbd_denoise_batched call. */
+#define FGBD_MAX_BATCH 64
 
 typedef enum {
   FGBD_OK = 0,
@@ -57,6 +62,8 @@ typedef enum {
 /* Device-detected conditions, OR-ed into fgbd_result.status. */
 #define FGBD_ST_COORD_RANGE 1 /* a coordinate was outside 0 .. 2^bits - 1 (graph undefined)  */
 #define FGBD_ST_NO_PATCH 2    /* no point had P neighbours: sigma_est set to 0 (Sec. 2.3)    */
+#define FGBD_ST_BAD_OFFSETS 4 /* batched offsets did not start at 0, decreased, or exceeded
+                                 n_total: they were clamped into range before use           */
 
 /* Parameters of one run.  fgbd_default_params gives the values used for 1M-point
  * frames (b = 10, L = 8, w = 4, K = 8). */
@@ -119,9 +126,10 @@ fgbd_status fgbd_create(fgbd_ctx *out, int32_t hip_device);
 /* Free the context and any workspace it allocated itself.  NULL is allowed. */
 fgbd_status fgbd_destroy(fgbd_ctx ctx);
 
-/* Device workspace in bytes that fgbd_denoise needs for clouds of up to n_max
- * points (the other calls need no more).  `batch` is reserved and must be 1.
- * p, bytes: host. */
+/* Device workspace in bytes that a call needs for up to n_max points in
+ * `batch` clouds: batch = 1 covers fgbd_denoise and every single-cloud call,
+ * batch = B covers fgbd_denoise_batched with B clouds totalling at most n_max
+ * points (1 <= batch <= FGBD_MAX_BATCH).  p, bytes: host. */
 fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t batch, size_t *bytes);
 
 /* Hand the context a caller-owned device buffer (256-byte aligned) to use as
@@ -182,6 +190,24 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
  *   res: every field written. */
 fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n,
                          const fgbd_params *params, float *rgb_out, fgbd_result *res, void *stream);
+
+/* The per-frame path for B clouds stored back to back, each denoised on its
+ * own (own graph, sigma_g, sigma_est, FSLR subset and q, exactly as
+ * fgbd_denoise would on that cloud alone, up to rounding order), in one
+ * launch sequence whose grids are sized from n_total and B only: the cloud
+ * sizes are read from device memory, so one captured sequence serves any
+ * sizes up to n_total (streaming frames of varying size: B = 1).
+ *   xyz: int32 [n_total][3]; rgb_in, rgb_out: float32 [n_total][3] (must not
+ *   overlap);  offsets: device int64 [batch + 1]: cloud s owns the points
+ *   offsets[s] .. offsets[s+1]-1.  offsets[0] must be 0, the entries
+ *   non-decreasing and offsets[batch] <= n_total; otherwise each entry is
+ *   clamped into that form and FGBD_ST_BAD_OFFSETS is set in every result.
+ *   Points from offsets[batch] on are left untouched.
+ *   1 <= batch <= FGBD_MAX_BATCH;  res: device fgbd_result [batch], every
+ *   field written.  Neighbours never cross clouds. */
+fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                                 const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
+                                 fgbd_result *res, void *stream);
 
 /* Polynomial graph filter, the differentiable generalisation of eq. 5:
  *   out = sum_{k=0}^{ncoef-1} coef[k] T^k x,

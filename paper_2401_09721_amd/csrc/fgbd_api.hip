@@ -90,70 +90,167 @@ void make_dir_table(int bits, int num_dirs, DirTable *t) {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Plan make_plan(int64_t n, const fgbd_params &p) {
+Plan make_plan(int64_t n_cap, int B, const fgbd_params &p) {
   Plan pl;
   memset(&pl, 0, sizeof(pl));
-  pl.n = n;
+  pl.n_cap = n_cap;
+  pl.B = B;
   pl.L = p.num_dirs;
   pl.K = p.k;
   pl.P = p.patch > 0 ? p.patch : p.k;
   pl.D = pl.P + 1;
-  pl.ntiles = (int32_t)((n + kSortTile - 1) / kSortTile);
-  const int64_t chunks = (n + kBlock - 1) / kBlock;
-  pl.merge_blocks = (int32_t)(chunks < 1 ? 1 : (chunks < kMaxGrid ? chunks : kMaxGrid));
-  pl.sweep_blocks = (int32_t)(chunks < 1 ? 1 : (chunks < kSweepMaxGrid ? chunks : kSweepMaxGrid));
-  const int TP = pl.D <= 17 ? 256 : 128;
-  const int64_t ptiles = (n + TP - 1) / TP;
-  pl.noise_blocks = (int32_t)(ptiles < 1 ? 1 : (ptiles < kMaxGrid ? ptiles : kMaxGrid));
-  pl.npart_noise = 1 + pl.D * (pl.D + 1) / 2 + 3 * pl.D;
-  const size_t N = (size_t)(n > 0 ? n : 1);
+  pl.TP = pl.D <= 17 ? 256 : 128;
+  // tiles never straddle clouds: sum over clouds of ceil(n_s / tile) is at
+  // most ceil(n / tile) + B - 1
+  const int64_t tiles = (n_cap + kSortTile - 1) / kSortTile + B - 1;
+  pl.ntiles_cap = (int32_t)(tiles < 1 ? 1 : tiles);
+  auto grid_for = [&](int64_t units) {
+    int64_t g = units < 1 ? 1 : (units < kMaxGrid ? units : kMaxGrid);
+    return (int32_t)(g < B ? B : g);
+  };
+  pl.grid[kGridMerge] = grid_for((n_cap + kBlock - 1) / kBlock);
+  pl.grid[kGridSweep] = grid_for((n_cap + kBlock - 1) / kBlock);
+  pl.grid[kGridNoise] = grid_for((n_cap + pl.TP - 1) / pl.TP);
+  pl.E1 = 1 + pl.D * (pl.D + 1) / 2 + 3 * pl.D;
+  const size_t N = (size_t)(n_cap > 0 ? n_cap : 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align256(off + bytes);
     return o;
   };
+  pl.off_segs = take(sizeof(Segs));
   pl.off_items_a = take((size_t)pl.L * N * 8);
   pl.off_items_b = take((size_t)pl.L * N * 8);
-  pl.off_hist = take((size_t)pl.L * (pl.ntiles > 0 ? pl.ntiles : 1) * 256 * 4);
-  pl.off_totals = take((size_t)pl.L * kSortPasses * 256 * 4);
+  pl.off_hist = take((size_t)pl.L * pl.ntiles_cap * 256 * 4);
+  pl.off_totals = take((size_t)pl.L * kSortPasses * B * 256 * 4);
   pl.off_rank = take((size_t)pl.L * N * 4);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
   pl.off_p = take(N * pl.K * 4);
   pl.off_spread = take(N * 8);
   pl.off_xbuf = take(3 * N * 16);
-  pl.off_merge_part = take((size_t)(pl.merge_blocks > 0 ? pl.merge_blocks : 1) * 2 * 8);
-  pl.off_noise_part = take((size_t)(pl.noise_blocks > 0 ? pl.noise_blocks : 1) * pl.npart_noise * 8);
-  pl.off_sweep_sums = take((size_t)3 * kSweepSlots * kSweepParts * 8);
-  pl.off_ctrl = take(2 * sizeof(SweepCtrl));
+  pl.off_merge_part = take((size_t)pl.grid[kGridMerge] * 2 * 8);
+  pl.off_noise_part = take((size_t)pl.grid[kGridNoise] * pl.E1 * 8);
+  pl.off_ctrl = take((size_t)2 * B * sizeof(SweepCtrl));
+  pl.off_sweep_sums = take((size_t)3 * B * kSweepSlots * kSweepParts * 8);
   pl.total = off;
   return pl;
 }
 
+Bufs carve(char *ws, const Plan &pl) {
+  Bufs b;
+  b.segs = (Segs *)(ws + pl.off_segs);
+  b.items_a = (uint64_t *)(ws + pl.off_items_a);
+  b.items_b = (uint64_t *)(ws + pl.off_items_b);
+  b.hist = (uint32_t *)(ws + pl.off_hist);
+  b.totals = (uint32_t *)(ws + pl.off_totals);
+  b.rank = (uint32_t *)(ws + pl.off_rank);
+  b.col = (int32_t *)(ws + pl.off_col);
+  b.dist2 = (int32_t *)(ws + pl.off_dist2);
+  b.p = (float *)(ws + pl.off_p);
+  b.spread = (double *)(ws + pl.off_spread);
+  b.xbuf = (float4 *)(ws + pl.off_xbuf);
+  b.merge_part = (double *)(ws + pl.off_merge_part);
+  b.noise_part = (double *)(ws + pl.off_noise_part);
+  b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
+  b.sums = (unsigned long long *)(ws + pl.off_sweep_sums);
+  return b;
+}
+
 namespace {
 
-__global__ void k_init(fgbd_result *res, int zero_result, unsigned long long *zero, int count) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) zero[i] = 0ull;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (zero_result && res) {
-      res->sigma_est = 0.0;
-      res->sigma_g = 0.0;
-      res->loss = 0.0;
-      res->q = 0;
-      res->n_fslr = 0;
-      res->n_eff = 0;
-      res->status = zero_result == 2 ? FGBD_ST_NO_PATCH : 0;
-      res->sweeps = 0;
-      res->m = 0;
+struct SetupArgs {
+  const int64_t *offsets;  // device, B + 1 entries, or NULL
+  int64_t n_host;          // the one cloud's size when offsets is NULL
+  int64_t n_cap;
+  int32_t B;
+  int32_t grid[kNumGrids];
+  int32_t zero_result;
+  int32_t tot_count;   // digit totals to clear (uint32)
+  int32_t sums_count;  // first sweep's sums to clear (uint64)
+};
+
+// All blocks clear the accumulators; block 0 builds the segment table:
+// offsets clamped into a valid form (start[0] = 0, non-decreasing, at most
+// n_cap), radix tiles per cloud, and each per-cloud grid's block ranges
+// first(s) = floor(start[s] (G - B) / n) + s (at least one block per cloud).
+__global__ __launch_bounds__(256) void k_setup(SetupArgs a, Segs *__restrict__ sg, uint32_t *__restrict__ totals,
+                                               unsigned long long *__restrict__ sums1, fgbd_result *__restrict__ res) {
+  __shared__ int64_t s_raw[kMaxSeg + 1];
+  __shared__ int32_t s_start[kMaxSeg + 1], s_tf[kMaxSeg + 1];
+  __shared__ int32_t s_bad;
+  const int t = threadIdx.x;
+  for (int i = blockIdx.x * blockDim.x + t; i < a.tot_count; i += gridDim.x * blockDim.x) totals[i] = 0u;
+  for (int i = blockIdx.x * blockDim.x + t; i < a.sums_count; i += gridDim.x * blockDim.x) sums1[i] = 0ull;
+  if (blockIdx.x != 0) return;  // uniform over the block
+  const int B = a.B;
+  if (t <= B) s_raw[t] = a.offsets ? a.offsets[t] : (t == 0 ? 0 : a.n_host);
+  __syncthreads();
+  if (t == 0) {
+    int bad = s_raw[0] != 0;
+    int64_t prev = 0;
+    int32_t tiles = 0;
+    s_start[0] = 0;
+    for (int s = 1; s <= B; ++s) {
+      int64_t v = s_raw[s];
+      v = v < prev ? prev : v;
+      v = v > a.n_cap ? a.n_cap : v;
+      bad |= v != s_raw[s];
+      s_start[s] = (int32_t)v;
+      s_tf[s - 1] = tiles;
+      tiles += (int32_t)((v - prev + kSortTile - 1) / kSortTile);
+      prev = v;
     }
+    s_tf[B] = tiles;
+    s_bad = bad;
+    sg->B = B;
+    sg->n = s_start[B];
+    sg->ntiles = tiles;
+    sg->status = bad ? FGBD_ST_BAD_OFFSETS : 0;
+  }
+  __syncthreads();
+  if (t <= B) {
+    sg->start[t] = s_start[t];
+    sg->tile_first[t] = s_tf[t];
+    const int64_t n = s_start[B];
+#pragma unroll
+    for (int g = 0; g < kNumGrids; ++g) {
+      const int G = a.grid[g];
+      sg->blk_first[g][t] = t == B ? G : (n > 0 ? (int32_t)((int64_t)s_start[t] * (G - B) / n) + t : t);
+    }
+  }
+  if (t < B && res && a.zero_result) {
+    fgbd_result *r = res + t;
+    r->sigma_est = 0.0;
+    r->sigma_g = 0.0;
+    r->loss = 0.0;
+    r->q = 0;
+    r->n_fslr = 0;
+    r->n_eff = 0;
+    r->status = (s_bad ? FGBD_ST_BAD_OFFSETS : 0) | (a.zero_result == 2 ? FGBD_ST_NO_PATCH : 0);
+    r->sweeps = 0;
+    r->m = 0;
   }
 }
 
 }  // namespace
 
-hipError_t launch_init(fgbd_result *res, int zero_result, unsigned long long *zero, int count, hipStream_t stream) {
-  k_init<<<1, 256, 0, stream>>>(res, zero_result, zero, zero ? count : 0);
+hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result) {
+  SetupArgs a;
+  a.offsets = offsets;
+  a.n_host = n_host;
+  a.n_cap = r.pl.n_cap;
+  a.B = r.pl.B;
+  for (int g = 0; g < kNumGrids; ++g) a.grid[g] = r.pl.grid[g];
+  a.zero_result = zero_result;
+  a.tot_count = r.pl.L * kSortPasses * r.pl.B * 256;
+  a.sums_count = r.pl.B * kSweepSlots * kSweepParts;
+  const int work = a.tot_count > a.sums_count ? a.tot_count : a.sums_count;
+  int blocks = (work + 256 * 8 - 1) / (256 * 8);
+  blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
+  // the first sweep adds into sums buffer 1 (see launch_sweep)
+  k_setup<<<blocks, 256, 0, r.stream>>>(a, r.b.segs, r.b.totals, r.b.sums + (size_t)a.sums_count, res);
   return hipGetLastError();
 }
 
@@ -268,100 +365,64 @@ struct EventProf final : Prof {
   }
 };
 
-struct Bufs {
-  uint64_t *items_a, *items_b;
-  uint32_t *hist, *totals, *rank;
-  int32_t *col, *dist2;
-  float *p;
-  double *spread;
-  float4 *xbuf;
-  double *merge_part, *noise_part;
-  unsigned long long *sweep_sums;  // three rotating slot buffers
-  SweepCtrl *ctrl;  // two states (ping-pong)
-};
-
-Bufs carve(char *ws, const Plan &pl) {
-  Bufs b;
-  b.items_a = (uint64_t *)(ws + pl.off_items_a);
-  b.items_b = (uint64_t *)(ws + pl.off_items_b);
-  b.hist = (uint32_t *)(ws + pl.off_hist);
-  b.totals = (uint32_t *)(ws + pl.off_totals);
-  b.rank = (uint32_t *)(ws + pl.off_rank);
-  b.col = (int32_t *)(ws + pl.off_col);
-  b.dist2 = (int32_t *)(ws + pl.off_dist2);
-  b.p = (float *)(ws + pl.off_p);
-  b.spread = (double *)(ws + pl.off_spread);
-  b.xbuf = (float4 *)(ws + pl.off_xbuf);
-  b.merge_part = (double *)(ws + pl.off_merge_part);
-  b.noise_part = (double *)(ws + pl.off_noise_part);
-  b.sweep_sums = (unsigned long long *)(ws + pl.off_sweep_sums);
-  b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
-  return b;
-}
-
 #define HIP_TRY(expr, what)                 \
   do {                                      \
     hipError_t e_ = (expr);                 \
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+Run make_run(fgbd_ctx ctx, const Plan &pl, char *ws, const fgbd_params &prm, int64_t n_fixed, hipStream_t s,
+             Prof *pf) {
+  Run r;
+  r.pl = pl;
+  r.b = carve(ws, pl);
+  r.sa.segs = r.b.segs;
+  r.sa.B = pl.B;
+  r.sa.n_fixed = (int32_t)n_fixed;
+  make_dir_table(prm.bits, prm.num_dirs, &r.dt);
+  r.prm = prm;
+  r.stream = s;
+  r.pf = ctx->profile ? pf : nullptr;
+  return r;
+}
+
 // Graph construction into (col, dist2, p); sigma_g into res.
-fgbd_status run_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_params &prm, const Plan &pl,
-                    const Bufs &b, int32_t *col, int32_t *dist2, float *p, fgbd_result *res, hipStream_t s) {
-  DirTable dt;
-  make_dir_table(prm.bits, prm.num_dirs, &dt);
-  EventProf ep(ctx, s);
-  Prof *pf = ctx->profile ? &ep : nullptr;
+fgbd_status run_slg(const Run &r, const int32_t *xyz, int32_t *col, int32_t *dist2, float *p, fgbd_result *res) {
   const uint64_t *sorted = nullptr;
-  HIP_TRY(launch_sort(xyz, n, dt, pl, b.items_a, b.items_b, b.hist, b.totals, b.rank, res, s, &sorted, pf),
-          "radix sort launch");
-  FGBD_PRE(pf, kMerge);
-  HIP_TRY(launch_merge(xyz, n, dt, prm.window, prm.k, sorted, b.rank, col, dist2, b.merge_part, pl.merge_blocks, s),
-          "neighbour merge launch");
-  FGBD_POST(pf);
-  FGBD_PRE(pf, kWeights);
-  HIP_TRY(launch_weights(n, prm.k, col, dist2, b.merge_part, pl.merge_blocks, prm.sigma_g, res, p, pl.merge_blocks,
-                         s),
-          "weights launch");
-  FGBD_POST(pf);
+  HIP_TRY(launch_sort(r, xyz, res, &sorted), "radix sort launch");
+  FGBD_PRE(r.pf, kMerge);
+  HIP_TRY(launch_merge(r, sorted, col, dist2), "neighbour merge launch");
+  FGBD_POST(r.pf);
+  FGBD_PRE(r.pf, kWeights);
+  HIP_TRY(launch_weights(r, col, dist2, res, p), "weights launch");
+  FGBD_POST(r.pf);
   return FGBD_OK;
 }
 
-fgbd_status run_noise(fgbd_ctx ctx, int64_t n, const fgbd_params &prm, const Plan &pl, const Bufs &b,
-                      const int32_t *col, const float *rgb, double *spread, float *eig3, fgbd_result *res,
-                      hipStream_t s) {
-  EventProf ep(ctx, s);
-  Prof *pf = ctx->profile ? &ep : nullptr;
-  FGBD_PRE(pf, kNoise);
-  HIP_TRY(launch_noise(n, prm.k, pl.P, col, rgb, spread, eig3, b.noise_part, pl.noise_blocks, s), "noise launch");
-  FGBD_POST(pf);
-  FGBD_PRE(pf, kNoiseSolve);
-  HIP_TRY(launch_noise_solve(pl.P, b.noise_part, pl.noise_blocks, res, s), "noise solve launch");
-  FGBD_POST(pf);
+fgbd_status run_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3,
+                      fgbd_result *res) {
+  FGBD_PRE(r.pf, kNoise);
+  HIP_TRY(launch_noise(r, col, rgb, spread, eig3), "noise launch");
+  FGBD_POST(r.pf);
+  FGBD_PRE(r.pf, kNoiseSolve);
+  HIP_TRY(launch_noise_solve(r, res), "noise solve launch");
+  FGBD_POST(r.pf);
   return FGBD_OK;
 }
 
-fgbd_status run_filter(fgbd_ctx ctx, int64_t n, const fgbd_params &prm, const Plan &pl, const Bufs &b,
-                       const int32_t *col, const float *p, const float *rgb_in, const double *spread,
-                       const fgbd_result *noise, int select, int q_limit, float *rgb_out, fgbd_result *res,
-                       hipStream_t s) {
-  EventProf ep(ctx, s);
-  Prof *pf = ctx->profile ? &ep : nullptr;
+// Sweeps and the final copy.  The first sweep's sums buffer was cleared by
+// the call's setup launch.
+fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const float *rgb_in, const double *spread,
+                       const fgbd_result *noise, int select, int q_limit, float *rgb_out, fgbd_result *res) {
   const int sweeps = q_limit > 0 ? q_limit : 1;
-  // sums of sweep 1 go to slot buffer 1, which must start at zero
-  HIP_TRY(launch_init(nullptr, 0, b.sweep_sums + (size_t)kSweepSlots * kSweepParts, kSweepSlots * kSweepParts, s),
-          "init launch");
   for (int q = 1; q <= sweeps; ++q) {
-    FGBD_PRE(pf, kSweep);
-    HIP_TRY(launch_sweep(n, prm.k, col, p, rgb_in, b.xbuf, spread, noise, prm.fslr_kappa, select, q_limit, q,
-                         b.sweep_sums, pl.sweep_blocks, b.ctrl, s),
-            "sweep launch");
-    FGBD_POST(pf);
+    FGBD_PRE(r.pf, kSweep);
+    HIP_TRY(launch_sweep(r, col, p, rgb_in, spread, noise, select, q_limit, q), "sweep launch");
+    FGBD_POST(r.pf);
   }
-  FGBD_PRE(pf, kFinalize);
-  HIP_TRY(launch_finalize(n, rgb_in, b.xbuf, sweeps, b.sweep_sums, pl.sweep_blocks, b.ctrl, noise, rgb_out, res, s),
-          "finalize launch");
-  FGBD_POST(pf);
+  FGBD_PRE(r.pf, kFinalize);
+  HIP_TRY(launch_finalize(r, rgb_in, sweeps, noise, rgb_out, res), "finalize launch");
+  FGBD_POST(r.pf);
   return FGBD_OK;
 }
 
@@ -418,9 +479,9 @@ fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t bat
   fgbd_status st = check_params(p);
   if (st != FGBD_OK) return st;
   if ((st = check_n(n_max)) != FGBD_OK) return st;
-  if (batch != 1) return fail(FGBD_E_INVALID, "batch must be 1");
+  if (batch < 1 || batch > kMaxSeg) return fail(FGBD_E_INVALID, "batch must be in 1..%d (got %d)", kMaxSeg, batch);
   if (!bytes) return fail(FGBD_E_INVALID, "bytes is NULL");
-  const size_t a = make_plan(n_max, *p).total;
+  const size_t a = make_plan(n_max, batch, *p).total;
   const size_t b = poly_workspace(n_max, p->k, kMaxPoly, kMaxGrid);
   *bytes = a > b ? a : b;
   return ok();
@@ -448,13 +509,14 @@ fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fg
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, *params);
+  const Plan pl = make_plan(n, 1, *params);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
-  const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(res, 1, nullptr, 0, s), "init launch");
+  EventProf ep(ctx, s);
+  const Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  HIP_TRY(launch_setup(r, nullptr, n, res, 1), "setup launch");
   if (n == 0) return ok();
-  if ((st = run_slg(ctx, xyz, n, *params, pl, b, g->col, g->dist2, g->p, res, s)) != FGBD_OK) return st;
+  if ((st = run_slg(r, xyz, g->col, g->dist2, g->p, res)) != FGBD_OK) return st;
   return ok();
 }
 
@@ -472,17 +534,17 @@ fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, *params);
+  const Plan pl = make_plan(n, 1, *params);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
-  const Bufs b = carve(ws, pl);
+  EventProf ep(ctx, s);
+  const Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
   if (n == 0) {
-    HIP_TRY(launch_init(res, 2, nullptr, 0, s), "init launch");
+    HIP_TRY(launch_setup(r, nullptr, 0, res, 2), "setup launch");
     return ok();
   }
-  if ((st = run_noise(ctx, n, *params, pl, b, g->col, rgb, patch_spread ? patch_spread : b.spread, eig3, res, s)) !=
-      FGBD_OK)
-    return st;
+  // one cloud of host-known size: the kernels do not read the segment table
+  if ((st = run_noise(r, g->col, rgb, patch_spread ? patch_spread : r.b.spread, eig3, res)) != FGBD_OK) return st;
   return ok();
 }
 
@@ -507,19 +569,27 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, *params);
+  const Plan pl = make_plan(n, 1, *params);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
-  const Bufs b = carve(ws, pl);
-  if (n == 0) {
-    HIP_TRY(launch_init(res, 1, nullptr, 0, s), "init launch");
-    return ok();
-  }
+  EventProf ep(ctx, s);
+  const Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  HIP_TRY(launch_setup(r, nullptr, n, res, n == 0 ? 1 : 0), "setup launch");
+  if (n == 0) return ok();
   const int q_limit = select ? params->q_max : q_fixed;
-  if ((st = run_filter(ctx, n, *params, pl, b, g->col, g->p, rgb_in, patch_spread, noise, select, q_limit, rgb_out,
-                       res, s)) != FGBD_OK)
+  if ((st = run_filter(r, g->col, g->p, rgb_in, patch_spread, noise, select, q_limit, rgb_out, res)) != FGBD_OK)
     return st;
   return ok();
+}
+
+// The fused path over the call's segments (one cloud of host-known size, or
+// B clouds from device offsets).
+static fgbd_status run_denoise(const Run &r, const int32_t *xyz, const float *rgb_in, float *rgb_out,
+                               fgbd_result *res) {
+  fgbd_status st;
+  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, r.b.p, res)) != FGBD_OK) return st;
+  if ((st = run_noise(r, r.b.col, rgb_in, r.b.spread, nullptr, res)) != FGBD_OK) return st;
+  return run_filter(r, r.b.col, r.b.p, rgb_in, r.b.spread, res, 1, r.prm.q_max, rgb_out, res);
 }
 
 fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n,
@@ -535,17 +605,41 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, *params);
+  const Plan pl = make_plan(n, 1, *params);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
-  const Bufs b = carve(ws, pl);
-  HIP_TRY(launch_init(res, n == 0 ? 2 : 1, nullptr, 0, s), "init launch");
+  EventProf ep(ctx, s);
+  const Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  HIP_TRY(launch_setup(r, nullptr, n, res, n == 0 ? 2 : 1), "setup launch");
   if (n == 0) return ok();
-  if ((st = run_slg(ctx, xyz, n, *params, pl, b, b.col, b.dist2, b.p, res, s)) != FGBD_OK) return st;
-  if ((st = run_noise(ctx, n, *params, pl, b, b.col, rgb_in, b.spread, nullptr, res, s)) != FGBD_OK) return st;
-  if ((st = run_filter(ctx, n, *params, pl, b, b.col, b.p, rgb_in, b.spread, res, 1, params->q_max, rgb_out, res,
-                       s)) != FGBD_OK)
-    return st;
+  if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
+  return ok();
+}
+
+fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                                 const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
+                                 fgbd_result *res, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_params(params);
+  if (st != FGBD_OK) return st;
+  if ((st = check_n(n_total)) != FGBD_OK) return st;
+  if (batch < 1 || batch > kMaxSeg) return fail(FGBD_E_INVALID, "batch must be in 1..%d (got %d)", kMaxSeg, batch);
+  if (!offsets) return fail(FGBD_E_INVALID, "offsets is NULL");
+  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
+  if (n_total > 0 && (!xyz || !rgb_in || !rgb_out)) return fail(FGBD_E_INVALID, "NULL input or output array");
+  if (n_total > 0 && overlap(rgb_in, (size_t)n_total * 12, rgb_out, (size_t)n_total * 12))
+    return fail(FGBD_E_INVALID, "rgb_in and rgb_out overlap");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  const Plan pl = make_plan(n_total, batch, *params);
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  EventProf ep(ctx, s);
+  const Run r = make_run(ctx, pl, ws, *params, -1, s, &ep);
+  HIP_TRY(launch_setup(r, offsets, 0, res, n_total == 0 ? 2 : 1), "setup launch");
+  if (n_total == 0) return ok();
+  if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
   return ok();
 }
 

@@ -6,10 +6,11 @@
 // 16-byte load.  Each sweep also sums |x_q|^2 over the FSLR subset and over
 // all points.  Every point's term is rounded to a fixed-point integer (units of
 // 2^-12) and blocks add their integer sums with 64-bit atomics into a few
-// dozen slots; integer addition is exact, so the totals do not depend on the
-// order, the grid or the device schedule (deterministic, no floating-point
+// slots per cloud; integer addition is exact, so the totals do not depend on
+// the order, the grid or the device schedule (deterministic, no floating-point
 // atomics, no fences).  Three slot buffers rotate: launch q reads the sums of
-// q-1, adds into q, and clears the buffer of q+1.
+// q-1, adds into q, and clears the buffer of q+1.  Every block works on one
+// cloud, and every cloud has its own selection state.
 //
 // Selection without inter-block synchronisation: launch q starts by reading
 // the sums of launch q-1 (every block reads the same integers) and advancing
@@ -17,7 +18,7 @@
 //   E(q-1) = (sum_S |y|^2 - sum_S |x_{q-1}|^2) / (3 |S|),
 //   best = argmin |sigma_est^2 - E| so far (ties keep the smaller q),
 //   done when E >= sigma_est^2, q reaches q_max, or the loss is 0;
-// block 0 stores the state for the next launch (ping-pong buffers, so no
+// the first block of each cloud stores the state for the next launch (ping-pong buffers, so no
 // block reads a state another block of the same launch is writing).  A launch
 // that finds the state done returns at once, so the host enqueues up to q_max
 // launches without reading anything back.  Three rotating float4 buffers hold
@@ -33,11 +34,14 @@ namespace fgbd {
 namespace {
 
 struct SweepArgs {
-  int32_t n, k;
+  SegArgs sa;
+  int32_t k;
   int32_t select, q_limit;
   double kappa;
   int64_t buf_stride;  // float4 elements per buffer
 };
+
+constexpr int kSlotVals = kSweepSlots * kSweepParts;  // integers per cloud and sweep
 
 constexpr double kFix = 4096.0;  // fixed-point scale of the energy sums (2^12)
 
@@ -91,12 +95,9 @@ __device__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
   if (c.done) return;  // uniform: every thread read the same state
   if (threadIdx.x < kWave) {
     unsigned long long u[kSweepParts];
+    const int sl = (int)threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < kSweepParts; ++j) u[j] = 0;
-    for (int sl = (int)threadIdx.x; sl < kSweepSlots; sl += kWave) {
-#pragma unroll
-      for (int j = 0; j < kSweepParts; ++j) u[j] += sums_prev[sl * kSweepParts + j];
-    }
+    for (int j = 0; j < kSweepParts; ++j) u[j] = sl < kSweepSlots ? sums_prev[sl * kSweepParts + j] : 0ull;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
@@ -114,9 +115,10 @@ __device__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
   advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
 }
 
-// Block-sum of per-thread integer sums, then one atomic per value per block.
+// Block-sum of per-thread integer sums, then one atomic per value per block
+// into slot `slot` of the cloud's sums.
 __device__ __forceinline__ void add_sums(unsigned long long (&v)[kSweepParts], unsigned long long *__restrict__ out,
-                                         unsigned long long *s_buf) {
+                                         int slot, unsigned long long *s_buf) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
@@ -131,7 +133,7 @@ __device__ __forceinline__ void add_sums(unsigned long long (&v)[kSweepParts], u
   if (threadIdx.x < kSweepParts) {
     unsigned long long a = 0;
     for (int ww = 0; ww < (int)blockDim.x / kWave; ++ww) a += s_buf[ww * kSweepParts + threadIdx.x];
-    if (a) atomicAdd(&out[(blockIdx.x % kSweepSlots) * kSweepParts + threadIdx.x], a);
+    if (a) atomicAdd(&out[slot * kSweepParts + threadIdx.x], a);
   }
 }
 
@@ -147,9 +149,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
                                                   SweepCtrl *__restrict__ ctrl_out) {
   __shared__ unsigned long long s_red[4 * kSweepParts];
   const int K = KT > 0 ? KT : a.k;
+  const SegBlock sb = seg_block(a.sa, kGridSweep);
+  sums_prev += (size_t)sb.s * kSlotVals;
+  sums_out += (size_t)sb.s * kSlotVals;
+  sums_clear += (size_t)sb.s * kSlotVals;
   SweepCtrl c;
   if (FIRST) {
-    c.sigma_est = a.select ? noise->sigma_est : 0.0;
+    c.sigma_est = a.select ? noise[sb.s].sigma_est : 0.0;
     c.target = c.sigma_est * c.sigma_est;
     c.y2_sel = 0.0;
     c.best_loss = c.target;
@@ -165,11 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
     c.q_limit = a.q_limit;
     c.fslr = (a.select && a.kappa > 0.0) ? 1 : 0;
   } else {
-    load_state(c, ctrl_prev, sums_prev, a.n);
+    load_state(c, ctrl_prev + sb.s, sums_prev, (int)(sb.end - sb.begin));
   }
-  if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) *ctrl_out = c;
-    for (int j = threadIdx.x; j < kSweepSlots * kSweepParts; j += blockDim.x) sums_clear[j] = 0ull;
+  if (sb.lb == 0) {
+    if (threadIdx.x == 0) ctrl_out[sb.s] = c;
+    for (int j = threadIdx.x; j < kSlotVals; j += blockDim.x) sums_clear[j] = 0ull;
   }
   if (c.done) return;
 
@@ -179,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
   float4 *xout = xbuf + (size_t)out_buf * a.buf_stride;
 
   unsigned long long v[kSweepParts] = {0, 0, 0, 0, 0};
-  const Share sh = xcd_share(a.n, kBlock);
+  const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
     const int64_t i = base + threadIdx.x;
     if (i >= sh.end) continue;
@@ -249,19 +255,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
       v[4] += member != 0.0f ? 1ull : 0ull;
     }
   }
-  add_sums(v, sums_out, s_red);
+  add_sums(v, sums_out, sb.lb % kSweepSlots, s_red);
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(int32_t n, int64_t buf_stride, const float *__restrict__ rgb_in,
+__global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_stride, const float *__restrict__ rgb_in,
                                                      const float4 *__restrict__ xbuf,
                                                      const unsigned long long *__restrict__ sums_prev,
                                                      const SweepCtrl *__restrict__ ctrl_prev,
                                                      const fgbd_result *__restrict__ noise,
                                                      float *__restrict__ rgb_out, fgbd_result *__restrict__ res) {
+  const SegBlock sb = seg_block(sa, kGridSweep);
   SweepCtrl c;
-  load_state(c, ctrl_prev, sums_prev, n);
+  load_state(c, ctrl_prev + sb.s, sums_prev + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
   const int best = c.best_buf;
-  const Share sh = xcd_share(n, kBlock);
+  const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
     const int64_t i = base + threadIdx.x;
     if (i >= sh.end) continue;
@@ -276,55 +283,59 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int32_t n, int64_t buf_stri
       rgb_out[3 * i + 2] = x.z;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    res->q = c.best_q;
-    res->loss = c.best_loss;
-    res->n_fslr = c.n_sel;
-    res->sweeps = c.q;
-    if (noise != nullptr && noise != res) res->sigma_est = noise->sigma_est;
+  if (sb.lb == 0 && threadIdx.x == 0) {
+    fgbd_result *r = res + sb.s;
+    r->q = c.best_q;
+    r->loss = c.best_loss;
+    r->n_fslr = c.n_sel;
+    r->sweeps = c.q;
+    if (noise != nullptr && noise != res) r->sigma_est = noise[sb.s].sigma_est;
   }
 }
 
 }  // namespace
 
-hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf,
-                        const double *spread, const fgbd_result *noise, double kappa, int select, int q_limit,
-                        int q, unsigned long long *sums3, int nblocks, SweepCtrl *ctrl2, hipStream_t stream) {
+hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const float *rgb_in, const double *spread,
+                        const fgbd_result *noise, int select, int q_limit, int q) {
   SweepArgs a;
-  a.n = (int32_t)n;
-  a.k = k;
+  a.sa = r.sa;
+  a.k = r.prm.k;
   a.select = select;
   a.q_limit = q_limit;
-  a.kappa = kappa;
-  a.buf_stride = n;
-  const size_t S = (size_t)kSweepSlots * kSweepParts;
+  a.kappa = r.prm.fslr_kappa;
+  a.buf_stride = r.pl.n_cap;
+  const size_t S = (size_t)r.pl.B * kSlotVals;
+  unsigned long long *sums3 = r.b.sums;
   const unsigned long long *sp = sums3 + ((q - 1) % 3) * S;
   unsigned long long *so = sums3 + (q % 3) * S;
   unsigned long long *sc = sums3 + ((q + 1) % 3) * S;
-  const SweepCtrl *cp = ctrl2 + ((q - 1) & 1);
-  SweepCtrl *co = ctrl2 + (q & 1);
+  const SweepCtrl *cp = r.b.ctrl + ((q - 1) & 1) * r.pl.B;
+  SweepCtrl *co = r.b.ctrl + (q & 1) * r.pl.B;
+  float4 *xbuf = r.b.xbuf;
+  const int nb = r.pl.grid[kGridSweep];
+  hipStream_t st = r.stream;
   const bool first = q == 1;
-  if (k == 8) {
+  if (a.k == 8) {
     if (first)
-      k_sweep<8, true><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
+      k_sweep<8, true><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
     else
-      k_sweep<8, false><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
+      k_sweep<8, false><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
   } else {
     if (first)
-      k_sweep<0, true><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
+      k_sweep<0, true><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
     else
-      k_sweep<0, false><<<nblocks, kBlock, 0, stream>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
+      k_sweep<0, false><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, int q_launches,
-                           const unsigned long long *sums3, int nblocks, const SweepCtrl *ctrl2,
-                           const fgbd_result *noise, float *rgb_out, fgbd_result *res, hipStream_t stream) {
-  const size_t S = (size_t)kSweepSlots * kSweepParts;
-  const unsigned long long *sp = sums3 + (q_launches % 3) * S;
-  const SweepCtrl *cp = ctrl2 + (q_launches & 1);
-  k_finalize<<<nblocks, kBlock, 0, stream>>>((int32_t)n, n, rgb_in, xbuf, sp, cp, noise, rgb_out, res);
+hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,
+                           float *rgb_out, fgbd_result *res) {
+  const size_t S = (size_t)r.pl.B * kSlotVals;
+  const unsigned long long *sp = r.b.sums + (q_launches % 3) * S;
+  const SweepCtrl *cp = r.b.ctrl + (q_launches & 1) * r.pl.B;
+  k_finalize<<<r.pl.grid[kGridSweep], kBlock, 0, r.stream>>>(r.sa, r.pl.n_cap, rgb_in, r.b.xbuf, sp, cp, noise,
+                                                              rgb_out, res);
   return hipGetLastError();
 }
 

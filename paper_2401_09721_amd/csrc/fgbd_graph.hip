@@ -2,14 +2,17 @@
 //
 // k_merge: one thread per point i.  For each direction it looks up i's sorted
 // position r (rank array from the last radix pass), reads the items at
-// r-w..r+w (squared distances follow from differences of the code fields, so
-// no coordinate is gathered), and keeps the K smallest distinct (squared
-// distance, index) pairs in a register-resident sorted list (packed so one
-// integer compare orders by distance then index).  It writes the fixed-K CSR
-// row and per-block FP64 sums of edge lengths and edge counts for sigma_g.
+// r-w..r+w inside the cloud's range of positions (squared distances follow
+// from differences of the code fields, so no coordinate is gathered), and
+// keeps the K smallest distinct (squared distance, index) pairs in a
+// register-resident sorted list (packed so one integer compare orders by
+// distance then index).  It writes the fixed-K CSR row and per-block FP64
+// sums of edge lengths and edge counts for sigma_g; every block works on one
+// cloud.
 //
-// k_weights: every block first sums the merge partials in block order (all
-// blocks get the same sigma_g, the mean edge length of eq. 4's bandwidth rule),
+// k_weights: every block first sums the merge partials of its cloud's blocks
+// in block order (all blocks of a cloud get the same sigma_g, the mean edge
+// length of eq. 4's bandwidth rule),
 // then computes row-normalised Gaussian weights of eq. 4 in FP64 with the row's
 // smallest squared distance subtracted in the exponent (same ratio, no
 // underflow of the whole row), stored as float.  Squared-distance gaps are
@@ -64,89 +67,121 @@ __device__ __forceinline__ void topk_insert_t(Key (&lst)[KM], int K, Key c) {
   lst[0] = lst[0] > c ? c : lst[0];
 }
 
-// Window items r-WT..r+WT; positions outside 0..n-1 load a clamped position
+// Branch-free insertion for a compile-time list length K: a candidate that is
+// already present or not below the current K-th key becomes the all-ones
+// sentinel, which the insertion network leaves without effect.
+template <int K>
+__device__ __forceinline__ void topk_insert_fixed(uint32_t (&lst)[K], uint32_t c) {
+  bool drop = c >= lst[K - 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) drop |= lst[k] == c;
+  c = drop ? ~0u : c;
+#pragma unroll
+  for (int k = K - 1; k > 0; --k) lst[k] = lst[k - 1] > c ? lst[k - 1] : (lst[k] > c ? c : lst[k]);
+  lst[0] = lst[0] > c ? c : lst[0];
+}
+
+// Window items r-WT..r+WT; positions outside lo..hi load a clamped position
 // (branch-free, all loads in flight together) and are then marked empty.
 template <int WT>
-__device__ __forceinline__ void load_window(const uint64_t *__restrict__ srt, int r, int n, uint64_t (&w)[2 * WT + 1]) {
+__device__ __forceinline__ void load_window(const uint64_t *__restrict__ srt, int r, int lo, int hi,
+                                            uint64_t (&w)[2 * WT + 1]) {
 #pragma unroll
   for (int s = 0; s <= 2 * WT; ++s) {
     const int pos = r + s - WT;
-    w[s] = srt[min(max(pos, 0), n - 1)];
+    w[s] = srt[min(max(pos, lo), hi)];
   }
 #pragma unroll
   for (int s = 0; s <= 2 * WT; ++s) {
     const int pos = r + s - WT;
-    if (pos < 0 || pos >= n) w[s] = ~0ull;
+    if (pos < lo || pos > hi) w[s] = ~0ull;
   }
 }
 
-// Exact (64-bit key) selection for one point, runtime window: used for all
-// points when N >= 2^24 and for the rare point whose 32-bit selection kept a
-// clamped distance.
+struct MergeArgs {
+  DirTable dt;
+  SegArgs sa;
+  int64_t stride;  // items per direction (capacity)
+  int32_t window, K;
+};
+
+// Exact (64-bit key) selection for one point, runtime window over positions
+// lo..hi: used for all points when the capacity reaches 2^24 and for the rare
+// point whose 32-bit selection kept a clamped distance.
 template <int KM>
-__device__ void select_exact(int i, int n, int L, int window, int K, const DirInfo *s_dir, int bits,
+__device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int window, const DirInfo *s_dir,
                              const uint64_t *__restrict__ sorted, const uint32_t *__restrict__ rank,
                              uint64_t (&lst)[KM]) {
 #pragma unroll
   for (int k = 0; k < KM; ++k) lst[k] = ~0ull;
-  for (int d = 0; d < L; ++d) {
-    const DirConst dc = dir_const(s_dir[d], bits);
-    const int r = (int)rank[(size_t)d * n + i];
-    const uint64_t *srt = sorted + (size_t)d * n;
+  for (int d = 0; d < a.dt.num_dirs; ++d) {
+    const DirConst dc = dir_const(s_dir[d], a.dt.bits);
+    const int r = (int)rank[(size_t)d * a.stride + i];
+    const uint64_t *srt = sorted + (size_t)d * a.stride;
     const uint32_t ci = (uint32_t)(srt[r] >> 32);
-    const int lo = max(r - window, 0);
-    const int hi = min(r + window, n - 1);
-    for (int rr = lo; rr <= hi; ++rr) {
+    const int l = max(r - window, lo);
+    const int h = min(r + window, hi);
+    for (int rr = l; rr <= h; ++rr) {
       if (rr == r) continue;
       const uint64_t it = srt[rr];
-      topk_insert_t<KM, uint64_t>(lst, K, ((uint64_t)code_dist2(ci, (uint32_t)(it >> 32), dc) << 32) | (uint32_t)it);
+      topk_insert_t<KM, uint64_t>(lst, a.K, ((uint64_t)code_dist2(ci, (uint32_t)(it >> 32), dc) << 32) | (uint32_t)it);
     }
   }
 }
 
-// One thread per point.  WT > 0 (compile-time window, N < 2^24): the point's
-// ranks in all directions go to LDS in one batch of loads; each direction's
-// 2*WT+1 window items (the centre gives the point's own code) are fetched as
-// one batch, one direction ahead of their use; candidates are 32-bit keys
-// (min(d2, 255) << 24 | j), exact whenever no kept entry has a clamped
-// distance, else the point is redone with 64-bit keys.
+// One thread per point.  WT > 0 (compile-time window, capacity < 2^24): the
+// point's ranks in all directions go to LDS in one batch of loads; each
+// direction's 2*WT+1 window items (the centre gives the point's own code) are
+// fetched as one batch, one direction ahead of their use; candidates are
+// 32-bit keys (min(d2, 255) << 24 | j), exact whenever no kept entry has a
+// clamped distance, else the point is redone with 64-bit keys.
 template <int KM, int WT>
-__global__ __launch_bounds__(kBlock) void k_merge(DirTable dt, int32_t n, int32_t window, int32_t K,
-                                                  const uint64_t *__restrict__ sorted,
+__global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *__restrict__ sorted,
                                                   const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
                                                   int32_t *__restrict__ dist2, double *__restrict__ part) {
   __shared__ double s_red[8];
   __shared__ int s_rank[WT > 0 ? kMaxDirs : 1][kBlock];
   __shared__ DirInfo s_dir[kMaxDirs];
   double acc[2] = {0.0, 0.0};
-  const int L = dt.num_dirs;
+  const int L = a.dt.num_dirs;
+  const int K = a.K;
   const int t = threadIdx.x;
-  if (t < kMaxDirs) s_dir[t] = dt.d[t];
+  if (t < kMaxDirs) s_dir[t] = a.dt.d[t];
+  const SegBlock sb = seg_block(a.sa, kGridMerge);
+  const int lo = (int)sb.begin, hi = (int)sb.end - 1;
   __syncthreads();
-  const Share sh = xcd_share(n, kBlock);
+  const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
     const int i = (int)(base + t);
     if (i >= sh.end) continue;
     uint64_t lst[KM];
-    bool exact_done = false;
     if constexpr (WT > 0) {
 #pragma unroll
       for (int d = 0; d < kMaxDirs; ++d)
-        if (d < L) s_rank[d][t] = (int)rank[(size_t)d * n + i];
+        if (d < L) s_rank[d][t] = (int)rank[(size_t)d * a.stride + i];
       uint32_t key[KM];
 #pragma unroll
       for (int k = 0; k < KM; ++k) key[k] = ~0u;
       uint64_t cur[2 * WT + 1], nxt[2 * WT + 1];
-      load_window<WT>(sorted, s_rank[0][t], n, cur);
+      load_window<WT>(sorted, s_rank[0][t], lo, hi, cur);
       for (int d = 0; d < L; ++d) {
-        if (d + 1 < L) load_window<WT>(sorted + (size_t)(d + 1) * n, s_rank[d + 1][t], n, nxt);
-        const DirConst dc = dir_const(s_dir[d], dt.bits);
+        if (d + 1 < L) load_window<WT>(sorted + (size_t)(d + 1) * a.stride, s_rank[d + 1][t], lo, hi, nxt);
+        const DirConst dc = dir_const(s_dir[d], a.dt.bits);
         const uint32_t ci = (uint32_t)(cur[WT] >> 32);
 #pragma unroll
         for (int s = 0; s <= 2 * WT; ++s) {
-          if (s != WT && cur[s] != ~0ull) {
+          if (s != WT) {
             const uint32_t d2 = code_dist2(ci, (uint32_t)(cur[s] >> 32), dc);
-            topk_insert_t<KM, uint32_t>(key, K, ((d2 < 255u ? d2 : 255u) << 24) | (uint32_t)cur[s]);
+            // an empty window slot (all ones) yields the sentinel key
+            const uint32_t kc = cur[s] == ~0ull ? ~0u : (((d2 < 255u ? d2 : 255u) << 24) | (uint32_t)cur[s]);
+            if (KM == 8 && WT > 0) {
+              if (K == 8)
+                topk_insert_fixed<8>(reinterpret_cast<uint32_t(&)[8]>(key), kc);
+              else
+                topk_insert_t<KM, uint32_t>(key, K, kc);
+            } else {
+              topk_insert_t<KM, uint32_t>(key, K, kc);
+            }
           }
         }
 #pragma unroll
@@ -156,18 +191,15 @@ __global__ __launch_bounds__(kBlock) void k_merge(DirTable dt, int32_t n, int32_
 #pragma unroll
       for (int k = 0; k < KM; ++k) clamped |= (k < K) & (key[k] != ~0u) & ((key[k] >> 24) == 255u);
       if (clamped) {
-        select_exact<KM>(i, n, L, WT, K, s_dir, dt.bits, sorted, rank, lst);
-        exact_done = true;
+        select_exact<KM>(a, i, lo, hi, WT, s_dir, sorted, rank, lst);
       } else {
 #pragma unroll
         for (int k = 0; k < KM; ++k)
           lst[k] = key[k] == ~0u ? ~0ull : ((uint64_t)(key[k] >> 24) << 32) | (key[k] & 0xffffffu);
       }
     } else {
-      select_exact<KM>(i, n, L, window, K, s_dir, dt.bits, sorted, rank, lst);
-      exact_done = true;
+      select_exact<KM>(a, i, lo, hi, a.window, s_dir, sorted, rank, lst);
     }
-    (void)exact_done;
     int cv[KM], dv[KM];
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
@@ -206,28 +238,29 @@ __global__ __launch_bounds__(kBlock) void k_merge(DirTable dt, int32_t n, int32_
 
 constexpr int kExpTable = 256;
 
+// Runs on the merge grid: block b belongs to the same cloud as merge block b.
 template <int KT>
-__global__ __launch_bounds__(kBlock) void k_weights(int32_t n, int32_t k_rt, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kBlock) void k_weights(SegArgs sa, int32_t k_rt, const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ dist2,
-                                                    const double *__restrict__ merge_part, int merge_blocks,
-                                                    double sigma_g_fixed, fgbd_result *__restrict__ res,
-                                                    float *__restrict__ p) {
+                                                    const double *__restrict__ merge_part, double sigma_g_fixed,
+                                                    fgbd_result *__restrict__ res, float *__restrict__ p) {
   __shared__ double s_red[8];
   __shared__ double s_exp[kExpTable];
   const int K = KT > 0 ? KT : k_rt;
+  const SegBlock sb = seg_block(sa, kGridMerge);
   double sg = sigma_g_fixed;
   if (!(sg > 0.0)) {
     double t[2];
-    reduce_partials<2>(merge_part, merge_blocks, 2, t, s_red);
+    reduce_partials<2>(merge_part + 2 * ((int)blockIdx.x - sb.lb), sb.nb, 2, t, s_red);
     sg = t[1] > 0.0 ? t[0] / t[1] : 0.0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) res->sigma_g = sg;
+  if (sb.lb == 0 && threadIdx.x == 0) res[sb.s].sigma_g = sg;
   const double inv = sg > 0.0 ? 1.0 / (sg * sg) : 0.0;
   // squared-distance gaps are integers: tabulate exp(-gap / sigma_g^2) for small gaps
   for (int g = threadIdx.x; g < kExpTable; g += kBlock) s_exp[g] = sg > 0.0 ? exp(-(double)g * inv) : (g == 0 ? 1.0 : 0.0);
   __syncthreads();
   constexpr int KB = KT > 0 ? KT : kMaxK;
-  const Share sh = xcd_share(n, kBlock);
+  const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
     const int64_t i = base + threadIdx.x;
     if (i >= sh.end) continue;
@@ -274,37 +307,42 @@ __global__ __launch_bounds__(kBlock) void k_weights(int32_t n, int32_t k_rt, con
 
 }  // namespace
 
-hipError_t launch_merge(const int32_t *xyz, int64_t n, const DirTable &dt, int window, int k, const uint64_t *sorted,
-                        const uint32_t *rank, int32_t *col, int32_t *dist2, double *part, int nblocks,
-                        hipStream_t stream) {
-  (void)xyz;
-  const bool small = n < (1 << 24);  // 32-bit keys hold the index in 24 bits
+hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int32_t *dist2) {
+  MergeArgs a;
+  a.dt = r.dt;
+  a.sa = r.sa;
+  a.stride = r.pl.n_cap;
+  a.window = r.prm.window;
+  a.K = r.prm.k;
+  const int k = r.prm.k, window = r.prm.window;
+  const int nb = r.pl.grid[kGridMerge];
+  const uint32_t *rank = r.b.rank;
+  double *part = r.b.merge_part;
+  hipStream_t st = r.stream;
+  const bool small = r.pl.n_cap < (1 << 24);  // 32-bit keys hold the index in 24 bits
   if (small && k <= 8 && window == 4)
-    k_merge<8, 4><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+    k_merge<8, 4><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else if (small && k <= 8 && window == 1)
-    k_merge<8, 1><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+    k_merge<8, 1><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else if (small && k <= 8 && window == 2)
-    k_merge<8, 2><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+    k_merge<8, 2><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else if (k <= 8)
-    k_merge<8, 0><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+    k_merge<8, 0><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else if (small && k <= 16 && window == 4)
-    k_merge<16, 4><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+    k_merge<16, 4><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else if (k <= 16)
-    k_merge<16, 0><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+    k_merge<16, 0><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else
-    k_merge<32, 0><<<nblocks, kBlock, 0, stream>>>(dt, (int32_t)n, window, k, sorted, rank, col, dist2, part);
+    k_merge<32, 0><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   return hipGetLastError();
 }
 
-hipError_t launch_weights(int64_t n, int k, const int32_t *col, const int32_t *dist2, const double *merge_part,
-                          int merge_blocks, double sigma_g_fixed, fgbd_result *res, float *p, int nblocks,
-                          hipStream_t stream) {
-  if (k == 8)
-    k_weights<8><<<nblocks, kBlock, 0, stream>>>((int32_t)n, k, col, dist2, merge_part, merge_blocks, sigma_g_fixed,
-                                                 res, p);
+hipError_t launch_weights(const Run &r, const int32_t *col, const int32_t *dist2, fgbd_result *res, float *p) {
+  const int nb = r.pl.grid[kGridMerge];
+  if (r.prm.k == 8)
+    k_weights<8><<<nb, kBlock, 0, r.stream>>>(r.sa, 8, col, dist2, r.b.merge_part, r.prm.sigma_g, res, p);
   else
-    k_weights<0><<<nblocks, kBlock, 0, stream>>>((int32_t)n, k, col, dist2, merge_part, merge_blocks, sigma_g_fixed,
-                                                 res, p);
+    k_weights<0><<<nb, kBlock, 0, r.stream>>>(r.sa, r.prm.k, col, dist2, r.b.merge_part, r.prm.sigma_g, res, p);
   return hipGetLastError();
 }
 

@@ -161,28 +161,93 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
   __syncthreads();
 }
 
-// XCD-aware work split for grid-stride kernels over n points.  Workgroups are
-// dispatched to the 8 XCDs round-robin by block index, and each XCD has its
-// own L2; giving each XCD one contiguous share of the points keeps the
-// neighbour gathers of spatially ordered clouds inside one L2.  Block b works
-// on XCD share b % 8, as block b / 8 of the blocks of that share.
+// ------------------------------------------------------------- segments
+// A call covers B clouds stored back to back; cloud s owns the points
+// start[s] .. start[s+1]-1, and in every direction's sorted order it owns the
+// same positions.  A setup kernel writes the table from device offsets, so a
+// captured launch sequence serves any cloud sizes up to the planned capacity.
+// Every block of a per-cloud grid works on one cloud only: cloud s gets blocks
+// blk_first[g][s] .. blk_first[g][s+1]-1 (at least one, the rest in proportion
+// to its size), and radix tiles never straddle two clouds.
+constexpr int kMaxSeg = 64;
+enum GridKind { kGridMerge = 0, kGridNoise = 1, kGridSweep = 2, kNumGrids = 3 };
+struct Segs {
+  int32_t B;
+  int32_t n;       // start[B]
+  int32_t ntiles;  // radix tiles in use
+  int32_t status;  // FGBD_ST_BAD_OFFSETS when the offsets had to be clamped
+  int32_t start[kMaxSeg + 1];
+  int32_t tile_first[kMaxSeg + 1];
+  int32_t blk_first[kNumGrids][kMaxSeg + 1];
+};
+
+// How kernels find their cloud: n_fixed >= 0 means one cloud of n_fixed
+// points known on the host (the table is not read); otherwise B clouds from
+// the device table.
+struct SegArgs {
+  const Segs *segs;
+  int32_t B;
+  int32_t n_fixed;
+};
+
+// Largest s < B with first[s] <= x, for a non-decreasing table with
+// first[0] = 0 (one load per lane and a ballot; all 64 lanes must be active).
+__device__ __forceinline__ int seg_lookup(const int32_t *first, int B, int x) {
+  if (B <= 1) return 0;
+  const int l = (int)lane_id();
+  const bool c = l >= 1 && l < B && first[l] <= x;
+  return (int)__popcll(__builtin_amdgcn_ballot_w64(c));
+}
+
+struct SegBlock {
+  int s;              // cloud
+  int64_t begin, end; // its points
+  int lb, nb;         // this block's index among the cloud's blocks, and their count
+};
+__device__ __forceinline__ SegBlock seg_block(const SegArgs &a, int grid) {
+  SegBlock r;
+  if (a.n_fixed >= 0) {
+    r.s = 0;
+    r.begin = 0;
+    r.end = a.n_fixed;
+    r.lb = blockIdx.x;
+    r.nb = gridDim.x;
+    return r;
+  }
+  const Segs *sg = a.segs;
+  const int s = seg_lookup(sg->blk_first[grid], a.B, (int)blockIdx.x);
+  r.s = s;
+  r.begin = sg->start[s];
+  r.end = sg->start[s + 1];
+  const int f0 = sg->blk_first[grid][s];
+  r.lb = (int)blockIdx.x - f0;
+  r.nb = sg->blk_first[grid][s + 1] - f0;
+  return r;
+}
+
+// XCD-aware work split for grid-stride kernels.  Workgroups are dispatched to
+// the 8 XCDs round-robin by block index, and each XCD has its own L2; giving
+// each XCD one contiguous share of a cloud's points keeps the neighbour
+// gathers of spatially ordered clouds inside one L2.  The cloud's blocks are
+// consecutive, so local block b works on share b % 8 (all blocks of one share
+// sit on one XCD), as block b / 8 of the blocks of that share.
 constexpr int kXcds = 8;
 struct Share {
   int64_t begin, end;  // points of this block's XCD share
   int64_t first;       // first chunk start for this block
   int64_t step;        // chunk stride
 };
-__device__ __forceinline__ Share xcd_share(int64_t n, int chunk) {
-  const int G = gridDim.x, b = blockIdx.x;
-  const int nx = G < kXcds ? G : kXcds;
-  const int x = b % nx;
-  const int nb = (G - x + nx - 1) / nx;
-  const int lb = b / nx;
+__device__ __forceinline__ Share seg_share(const SegBlock &sb, int chunk) {
+  const int nx = sb.nb < kXcds ? sb.nb : kXcds;
+  const int x = sb.lb % nx;
+  const int nbx = (sb.nb - x + nx - 1) / nx;
+  const int lb = sb.lb / nx;
+  const int64_t len = sb.end - sb.begin;
   Share s;
-  s.begin = n * x / nx;
-  s.end = n * (x + 1) / nx;
+  s.begin = sb.begin + len * x / nx;
+  s.end = sb.begin + len * (x + 1) / nx;
   s.first = s.begin + (int64_t)lb * chunk;
-  s.step = (int64_t)nb * chunk;
+  s.step = (int64_t)nbx * chunk;
   return s;
 }
 
@@ -208,19 +273,17 @@ struct SweepCtrl {
 
 
 // ----------------------------------------------------------- workspace plan
+// Capacity of a call: up to n_cap points in B clouds.  Grids and buffers are
+// sized from the capacity; kernels take the actual sizes from SegArgs.
 struct Plan {
-  int64_t n;
-  int32_t L, K, P, D;
-  int32_t ntiles;          // radix-sort tiles per direction
-  int32_t merge_blocks;
-  int32_t noise_blocks;
-  int32_t sweep_blocks;
-  int32_t npart_noise;     // doubles per noise partial
-  // byte offsets into the workspace
-  size_t off_items_a, off_items_b, off_hist, off_totals, off_rank;
-  size_t off_col, off_dist2, off_p;
-  size_t off_spread, off_xbuf, off_merge_part, off_noise_part, off_sweep_sums;
-  size_t off_ctrl;
+  int64_t n_cap;
+  int32_t B, L, K, P, D, TP;
+  int32_t ntiles_cap;        // radix tiles: ceil(n_cap / tile) + B - 1
+  int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)
+  int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
+  size_t off_segs, off_items_a, off_items_b, off_hist, off_totals, off_rank;
+  size_t off_col, off_dist2, off_p, off_spread, off_xbuf;
+  size_t off_merge_part, off_noise_part, off_ctrl, off_sweep_sums;
   size_t total;
 };
 
@@ -232,11 +295,29 @@ constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit 
 constexpr int kBlock = 256;
 constexpr int kMaxGrid = 1024;  // grid of the grid-stride kernels
 constexpr int kSweepParts = 5;  // energy sums per sweep
-constexpr int kSweepSlots = 64;  // atomic slots per sum (spread to limit contention)
+constexpr int kSweepSlots = 64;  // atomic slots per cloud and sum (spread to limit contention)
 constexpr int kSweepMaxGrid = 1024;
 constexpr int kScanThreads = 1024;
 
-Plan make_plan(int64_t n, const fgbd_params &p);
+Plan make_plan(int64_t n_cap, int B, const fgbd_params &p);
+
+// Workspace views of a plan.
+struct Bufs {
+  Segs *segs;
+  uint64_t *items_a, *items_b;  // [L][n_cap]
+  uint32_t *hist;               // [L][256][ntiles_cap]
+  uint32_t *totals;             // [L][passes][B][256]
+  uint32_t *rank;               // [L][n_cap]
+  int32_t *col, *dist2;         // [n_cap][K]
+  float *p;                     // [n_cap][K]
+  double *spread;               // [n_cap]
+  float4 *xbuf;                 // [3][n_cap]
+  double *merge_part;           // [grid merge][2]
+  double *noise_part;           // [E1][grid noise]
+  SweepCtrl *ctrl;              // [2][B]
+  unsigned long long *sums;     // [3][B][slots][parts]
+};
+Bufs carve(char *ws, const Plan &pl);
 
 // ------------------------------------------------------------- profiling
 enum Kind { kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kNoiseSolve, kSweep, kFinalize, kNumKinds };
@@ -256,40 +337,45 @@ struct Prof {
   } while (0)
 
 // ------------------------------------------------------------- launchers
-// All launchers enqueue on `stream` and return hipSuccess or the launch error.
-// Zeroes the result (zero_result: 1 = all fields, 2 = all fields and the
-// no-patch status) and, when given, `count` 64-bit words at `zero`.
-hipError_t launch_init(fgbd_result *res, int zero_result, unsigned long long *zero, int count, hipStream_t stream);
+// Everything one call's launches need.  All launchers enqueue on r.stream
+// and return hipSuccess or the launch error.
+struct Run {
+  Plan pl;
+  Bufs b;
+  SegArgs sa;
+  DirTable dt;
+  fgbd_params prm;
+  hipStream_t stream;
+  Prof *pf;
+};
 
-hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const Plan &pl, uint64_t *items_a,
-                       uint64_t *items_b, uint32_t *hist, uint32_t *totals, uint32_t *rank, fgbd_result *res,
-                       hipStream_t stream, const uint64_t **sorted_out, Prof *pf);
+// Segment table from device offsets (B+1 entries) or, with offsets == NULL,
+// one cloud of n_host points; clears the digit totals and the first sweep's
+// sums.  zero_result: 0 leave res, 1 zero res[0..B-1], 2 zero and flag
+// FGBD_ST_NO_PATCH.
+hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result);
 
-// neighbour selection; writes per-block edge-length partials (2 doubles)
-hipError_t launch_merge(const int32_t *xyz, int64_t n, const DirTable &dt, int window, int k, const uint64_t *sorted,
-                        const uint32_t *rank, int32_t *col, int32_t *dist2, double *part, int nblocks,
-                        hipStream_t stream);
+hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const uint64_t **sorted_out);
 
-// sigma_g from the merge partials (or the fixed value) and eq. 4 weights
-hipError_t launch_weights(int64_t n, int k, const int32_t *col, const int32_t *dist2, const double *merge_part,
-                          int merge_blocks, double sigma_g_fixed, fgbd_result *res, float *p, int nblocks,
-                          hipStream_t stream);
+hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int32_t *dist2);
 
-hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float *rgb, double *spread, float *eig3,
-                        double *part, int nblocks, hipStream_t stream);
+// sigma_g of each cloud (the fixed value or the mean merge edge length, into
+// res[s].sigma_g) and the row-normalised weights p.
+hipError_t launch_weights(const Run &r, const int32_t *col, const int32_t *dist2, fgbd_result *res, float *p);
 
-hipError_t launch_noise_solve(int P, const double *part, int nblocks, fgbd_result *res, hipStream_t stream);
+hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3);
 
-// Sweep number q (1-based): reads ctrl[(q-1)&1] and sums[(q-1)%3], writes
-// ctrl[q&1] and sums[q%3], clears sums[(q+1)%3].  sums[1] must be zero
-// before sweep 1.
-hipError_t launch_sweep(int64_t n, int k, const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf,
-                        const double *spread, const fgbd_result *noise, double kappa, int select, int q_limit,
-                        int q, unsigned long long *sums3, int nblocks, SweepCtrl *ctrl2, hipStream_t stream);
+// One block per cloud: sigma_est, n_eff, m and the NO_PATCH flag into res[s].
+hipError_t launch_noise_solve(const Run &r, fgbd_result *res);
 
-hipError_t launch_finalize(int64_t n, const float *rgb_in, const float4 *xbuf, int q_launches,
-                           const unsigned long long *sums3, int nblocks, const SweepCtrl *ctrl2,
-                           const fgbd_result *noise, float *rgb_out, fgbd_result *res, hipStream_t stream);
+// Sweep number q (1-based): reads ctrl[(q-1)&1][.] and sums[(q-1)%3], writes
+// ctrl[q&1][.] and sums[q%3], clears sums[(q+1)%3].  noise: per-cloud
+// results holding sigma_est (select == 1).
+hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const float *rgb_in, const double *spread,
+                        const fgbd_result *noise, int select, int q_limit, int q);
+
+hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,
+                           float *rgb_out, fgbd_result *res);
 
 // Polynomial filter and its adjoint (ws: at least poly_workspace bytes).
 constexpr int kMaxPoly = 32;

@@ -16,8 +16,8 @@
 // D(D+1)/2 entries) and of the per-channel sums, and walks a fixed set of
 // rows, so all sums have a fixed order (products of two floats are exact in
 // FP64).  Incomplete patches contribute zero rows and are not counted.
-// Each block writes its partial sums; k_noise_solve (one block) reduces them
-// in block order, forms
+// Every block works on one cloud and writes its partial sums; k_noise_solve
+// (one block per cloud) reduces its cloud's partials in block order, forms
 //   Sigma = (S2 - sum_c s1_c s1_c^T / N) / (3 N),
 // finds its eigenvalues with a parallel cyclic Jacobi method (round-robin
 // pair ordering, FP64), and applies the tail rule: the smallest m with
@@ -67,7 +67,8 @@ __device__ void eig3_sym(double a00, double a01, double a02, double a11, double 
 }
 
 struct NoiseArgs {
-  int32_t n, K, P, D, TP;
+  SegArgs sa;
+  int32_t K, P, D, TP;
   int32_t E2, E;       // D(D+1)/2 and E2 + 3D
   int32_t groups;      // row groups per entry
   int32_t want_eig3;
@@ -291,7 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   const int rows = 3 * TP;
   __syncthreads();
 
-  const Share sh = xcd_share(a.n, TP);
+  const SegBlock sb = seg_block(a.sa, kGridNoise);
+  const Share sh = seg_share(sb, TP);
   for (int64_t tbase = sh.first; tbase < sh.end; tbase += sh.step) {
     if (t < TP) {
       const int64_t i = tbase + t;
@@ -387,11 +389,11 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
 // eigenvalues (parallel Jacobi, FP64) and apply the tail rule.
 constexpr int kSolveThreads = 1024;
 
-// One block: sum the k_noise partials (one wave per entry row, lanes stride
-// the blocks, fixed shuffle tree), form Sigma, then wave 0 alone finds its
-// eigenvalues (Jacobi, FP64) and applies the tail rule.
+// One block per cloud: sum the cloud's k_noise partials (one wave per entry
+// row, lanes stride the blocks, fixed shuffle tree), form Sigma, then wave 0
+// alone finds its eigenvalues (Jacobi, FP64) and applies the tail rule.
 __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, const double *__restrict__ part, int nb,
-                                                               fgbd_result *__restrict__ res) {
+                                                               fgbd_result *__restrict__ res_all) {
   __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
   __shared__ double s_jc[kMaxD], s_js[kMaxD];
   __shared__ int s_jp[kMaxD], s_jq[kMaxD], s_flag;
@@ -402,15 +404,19 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, cons
   const int nwaves = blockDim.x / kWave;
   const int D = a.D;
   const int stride = 1 + a.E;
+  const int seg = blockIdx.x;
+  fgbd_result *res = res_all + seg;
+  const int f0 = a.sa.n_fixed >= 0 ? 0 : a.sa.segs->blk_first[kGridNoise][seg];
+  const int nbs = (a.sa.n_fixed >= 0 ? nb : a.sa.segs->blk_first[kGridNoise][seg + 1]) - f0;
   double *tot = s_buf;
   for (int e = wave; e < stride; e += nwaves) {
-    const double *row = part + (size_t)e * nb;
-    // nb <= kMaxGrid: every lane's loads of the row are issued together
+    const double *row = part + (size_t)e * nb + f0;
+    // nbs <= kMaxGrid: every lane's loads of the row are issued together
     double vals[kMaxGrid / kWave];
 #pragma unroll
     for (int u = 0; u < kMaxGrid / kWave; ++u) {
       const int b = lane + u * kWave;
-      vals[u] = b < nb ? row[b] : 0.0;
+      vals[u] = b < nbs ? row[b] : 0.0;
     }
     double v = 0.0;
 #pragma unroll
@@ -474,9 +480,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, cons
   }
 }
 
-NoiseArgs make_args(int64_t n, int k, int P, bool want_eig3) {
+NoiseArgs make_args(const SegArgs &sa, int k, int P, bool want_eig3) {
   NoiseArgs a;
-  a.n = (int32_t)n;
+  a.sa = sa;
   a.K = k;
   a.P = P;
   a.D = P + 1;
@@ -490,24 +496,26 @@ NoiseArgs make_args(int64_t n, int k, int P, bool want_eig3) {
 
 }  // namespace
 
-hipError_t launch_noise(int64_t n, int k, int P, const int32_t *col, const float *rgb, double *spread, float *eig3,
-                        double *part, int nblocks, hipStream_t stream) {
-  const NoiseArgs a = make_args(n, k, P, eig3 != nullptr);
+hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3) {
+  const NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, eig3 != nullptr);
   const size_t lds = (size_t)3 * a.TP * a.D * sizeof(float);
-  if (P == 8 && eig3 == nullptr)
-    k_noise<8, false><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
-  else if (P == 8)
-    k_noise<8, true><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+  const int nb = r.pl.grid[kGridNoise];
+  double *part = r.b.noise_part;
+  hipStream_t st = r.stream;
+  if (a.P == 8 && eig3 == nullptr)
+    k_noise<8, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
+  else if (a.P == 8)
+    k_noise<8, true><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else if (eig3 == nullptr)
-    k_noise<0, false><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+    k_noise<0, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else
-    k_noise<0, true><<<nblocks, kBlock, lds, stream>>>(a, col, rgb, spread, eig3, part);
+    k_noise<0, true><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   return hipGetLastError();
 }
 
-hipError_t launch_noise_solve(int P, const double *part, int nblocks, fgbd_result *res, hipStream_t stream) {
-  const NoiseArgs a = make_args(0, P, P, false);
-  k_noise_solve<<<1, kSolveThreads, 0, stream>>>(a, part, nblocks, res);
+hipError_t launch_noise_solve(const Run &r, fgbd_result *res) {
+  const NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, false);
+  k_noise_solve<<<r.pl.B, kSolveThreads, 0, r.stream>>>(a, r.b.noise_part, r.pl.grid[kGridNoise], res);
   return hipGetLastError();
 }
 

@@ -13,6 +13,13 @@
 // Pass 0 computes the codes from the int32 coordinates on the fly; the last
 // pass also writes rank[dir][index] = sorted position, which the neighbour
 // search uses to find each point's place in every order.
+//
+// Several clouds are sorted in the same launches, each inside its own range
+// of positions: tiles never straddle two clouds, pass 0 counts every pass's
+// digits per cloud, the scan runs over all tiles of a row, and each tile's
+// output offset for digit c is
+//   start[s] + (digits < c in cloud s) + (prefix at this tile - prefix at the
+//   cloud's first tile).
 #include "fgbd_internal.h"
 
 namespace fgbd {
@@ -21,11 +28,45 @@ namespace {
 
 struct SortArgs {
   DirTable dt;
-  int32_t n;
-  int32_t ntiles;
-  int32_t shift;  // digit shift of this pass
+  SegArgs sa;
+  int64_t stride;     // items per direction (capacity)
+  int32_t ntiles_cap; // hist row length
+  int32_t shift;      // digit shift of this pass
   int32_t pass;
 };
+
+// The tile's cloud and point range; false for a tile beyond the last one.
+struct TileInfo {
+  int s;
+  int begin, end;  // points of the tile
+  int first;       // first tile of the cloud
+  int seg_start;   // first point of the cloud
+};
+__device__ __forceinline__ bool tile_info(const SortArgs &a, int tile, TileInfo &ti) {
+  if (a.sa.n_fixed >= 0) {
+    const int n = a.sa.n_fixed;
+    if (tile * kSortTile >= n) return false;
+    ti.s = 0;
+    ti.first = 0;
+    ti.seg_start = 0;
+    ti.begin = tile * kSortTile;
+    ti.end = min(ti.begin + kSortTile, n);
+    return true;
+  }
+  const Segs *sg = a.sa.segs;
+  if (tile >= sg->ntiles) return false;
+  const int s = seg_lookup(sg->tile_first, a.sa.B, tile);
+  ti.s = s;
+  ti.first = sg->tile_first[s];
+  ti.seg_start = sg->start[s];
+  ti.begin = ti.seg_start + (tile - ti.first) * kSortTile;
+  ti.end = min(ti.begin + kSortTile, (int)sg->start[s + 1]);
+  return true;
+}
+
+__device__ __forceinline__ int num_tiles(const SortArgs &a) {
+  return a.sa.n_fixed >= 0 ? (a.sa.n_fixed + kSortTile - 1) / kSortTile : a.sa.segs->ntiles;
+}
 
 __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const int32_t *__restrict__ xyz,
                                               const uint64_t *__restrict__ src, int d, int pos, int *bad) {
@@ -36,7 +77,12 @@ __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const int32_t *
     const uint32_t code = scan_code(gx, gy, gz, a.dt.d[d], a.dt.bits);
     return ((uint64_t)code << 32) | (uint32_t)pos;
   }
-  return src[(size_t)d * a.n + pos];
+  return src[(size_t)d * a.stride + pos];
+}
+
+// Offset of the digit totals of pass q for direction d and cloud s.
+__device__ __forceinline__ size_t totals_row(const SortArgs &a, int d, int q, int s) {
+  return (((size_t)d * kSortPasses + q) * a.sa.B + s) * 256;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const int32_t *__restrict__ xyz,
@@ -48,6 +94,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
   __shared__ uint32_t s_all[kSortPasses][256];
   const int d = blockIdx.y;
   const int tile = blockIdx.x;
+  TileInfo ti;
+  if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
   s_h[t] = 0;
   if (a.pass == 0) {
@@ -57,53 +105,41 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
   __syncthreads();
   const int wave = t / kWave;
   const int lane = (int)lane_id();
-  const int base = tile * kSortTile + wave * kWave * kSortItems + lane;
+  const int base = ti.begin + wave * kWave * kSortItems + lane;
   int bad = 0;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const int pos = base + j * kWave;
-    if (pos < a.n) {
+    if (pos < ti.end) {
       const uint64_t it = load_item(a, xyz, src, d, pos, &bad);
       const uint32_t digit = (uint32_t)(it >> (32 + a.shift)) & 255u;
       atomicAdd(&s_h[digit], 1u);
-      if (a.pass == 0) {  // digit totals of every pass, for the offset scan
+      if (a.pass == 0) {  // digit totals of every pass, for the offsets
 #pragma unroll
         for (int q = 1; q < kSortPasses; ++q) atomicAdd(&s_all[q][(uint32_t)(it >> (32 + 8 * q)) & 255u], 1u);
       }
     }
   }
-  if (bad && d == 0) atomicOr(&res->status, FGBD_ST_COORD_RANGE);
+  if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
   __syncthreads();
-  hist[((size_t)d * 256 + t) * a.ntiles + tile] = s_h[t];
+  hist[((size_t)d * 256 + t) * a.ntiles_cap + tile] = s_h[t];
   if (a.pass == 0) {
-    uint32_t *tot = totals + (size_t)d * kSortPasses * 256;
-    if (s_h[t]) atomicAdd(&tot[t], s_h[t]);
+    if (s_h[t]) atomicAdd(&totals[totals_row(a, d, 0, ti.s) + t], s_h[t]);
 #pragma unroll
     for (int q = 1; q < kSortPasses; ++q)
-      if (s_all[q][t]) atomicAdd(&tot[q * 256 + t], s_all[q][t]);
+      if (s_all[q][t]) atomicAdd(&totals[totals_row(a, d, q, ti.s) + t], s_all[q][t]);
   }
 }
 
-// Global offsets: one wave per (direction, digit) row of tile counts.  The
-// row's base is the sum of the direction's totals of all smaller digits; the
-// row is then scanned 64 tiles at a time with a wave prefix sum.
-__global__ __launch_bounds__(256) void k_sort_scan(int ntiles, int num_dirs, int pass, uint32_t *__restrict__ hist,
-                                                   const uint32_t *__restrict__ totals) {
+// Exclusive prefix of every (direction, digit) row of tile counts: one wave
+// per row, 64 tiles at a time with a wave prefix sum.
+__global__ __launch_bounds__(256) void k_sort_scan(SortArgs a, uint32_t *__restrict__ hist) {
   const int row = blockIdx.x * 4 + threadIdx.x / kWave;
-  if (row >= num_dirs * 256) return;
-  const int d = row / 256, digit = row % 256;
+  if (row >= a.dt.num_dirs * 256) return;
+  const int ntiles = num_tiles(a);
   const uint32_t lane = lane_id();
-  const uint32_t *tot = totals + ((size_t)d * kSortPasses + pass) * 256;
-  uint32_t b = 0;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int dg = (int)lane + 64 * j;
-    b += dg < digit ? tot[dg] : 0u;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, kWave);
-  uint32_t carry = b;
-  uint32_t *h = hist + (size_t)row * ntiles;
+  uint32_t carry = 0;
+  uint32_t *h = hist + (size_t)row * a.ntiles_cap;
   for (int t0 = 0; t0 < ntiles; t0 += kWave) {
     const int tile = t0 + (int)lane;
     const uint32_t v = tile < ntiles ? h[tile] : 0u;
@@ -118,46 +154,77 @@ __global__ __launch_bounds__(256) void k_sort_scan(int ntiles, int num_dirs, int
   }
 }
 
+// Exclusive scans of two uint32 per thread over a 256-thread block.
+__device__ __forceinline__ void block_exclusive_scan2_256(uint32_t &v0, uint32_t &v1, uint32_t (*s_tmp)[4]) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  uint32_t x0 = v0, x1 = v1;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y0 = __shfl_up(x0, o, kWave), y1 = __shfl_up(x1, o, kWave);
+    if (lane >= (uint32_t)o) {
+      x0 += y0;
+      x1 += y1;
+    }
+  }
+  if (lane == kWave - 1) {
+    s_tmp[0][w] = x0;
+    s_tmp[1][w] = x1;
+  }
+  __syncthreads();
+  uint32_t b0 = 0, b1 = 0;
+  for (int ww = 0; ww < w; ++ww) {
+    b0 += s_tmp[0][ww];
+    b1 += s_tmp[1][ww];
+  }
+  v0 = b0 + x0 - v0;
+  v1 = b1 + x1 - v1;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, const int32_t *__restrict__ xyz,
                                                                  const uint64_t *__restrict__ src,
                                                                  uint64_t *__restrict__ dst,
                                                                  const uint32_t *__restrict__ hist,
+                                                                 const uint32_t *__restrict__ totals,
                                                                  uint32_t *__restrict__ rank) {
   __shared__ uint32_t s_wh[4][256];
   __shared__ uint32_t s_off[256];
   __shared__ uint32_t s_base[256];
-  __shared__ uint32_t s_tmp[4];
+  __shared__ uint32_t s_tmp[2][4];
   __shared__ uint64_t s_stage[kSortTile];
 
   const int d = blockIdx.y;
   const int tile = blockIdx.x;
+  TileInfo ti;
+  if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
   const int wave = t / kWave;
   const int lane = (int)lane_id();
-  const int tile0 = tile * kSortTile;
-  const int valid = min(kSortTile, a.n - tile0);
+  const int valid = ti.end - ti.begin;
 
   s_wh[0][t] = 0;
   s_wh[1][t] = 0;
   s_wh[2][t] = 0;
   s_wh[3][t] = 0;
-  s_off[t] = hist[((size_t)d * 256 + t) * a.ntiles + tile];
+  const uint32_t *hrow = hist + ((size_t)d * 256 + t) * a.ntiles_cap;
+  // digit t's offset inside the cloud's range: tile prefix minus the prefix
+  // at the cloud's first tile (zero for the first cloud)
+  uint32_t off_t = hrow[tile] - (ti.first > 0 ? hrow[ti.first] : 0u);
+  uint32_t below_t = totals[totals_row(a, d, a.pass, ti.s) + t];
 
   uint64_t item[kSortItems];
-  const int base = tile0 + wave * kWave * kSortItems + lane;
+  const int base = ti.begin + wave * kWave * kSortItems + lane;
   int bad = 0;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const int pos = base + j * kWave;
-    item[j] = (pos < a.n) ? load_item(a, xyz, src, d, pos, &bad) : ~0ull;
+    item[j] = (pos < ti.end) ? load_item(a, xyz, src, d, pos, &bad) : ~0ull;
   }
   __syncthreads();
 
   // Stable rank of each item among the equal digits of its wave: items are
   // visited in tile order (j major, lane minor within the wave).
   uint32_t rk[kSortItems];
-  const uint64_t below_mask = (1ull << lane) - 1ull;
-  (void)below_mask;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const uint32_t digit = (uint32_t)(item[j] >> (32 + a.shift)) & 255u;
@@ -176,14 +243,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   __syncthreads();
 
   // per digit: exclusive over waves, then exclusive over digits in the tile
+  // and (for the global offset) over the cloud's digit totals
   {
     const uint32_t c0 = s_wh[0][t], c1 = s_wh[1][t], c2 = s_wh[2][t], c3 = s_wh[3][t];
     s_wh[0][t] = 0;
     s_wh[1][t] = c0;
     s_wh[2][t] = c0 + c1;
     s_wh[3][t] = c0 + c1 + c2;
-    uint32_t total;
-    s_base[t] = block_exclusive_scan_256(c0 + c1 + c2 + c3, s_tmp, &total);
+    uint32_t in_tile = c0 + c1 + c2 + c3;
+    block_exclusive_scan2_256(in_tile, below_t, s_tmp);
+    s_base[t] = in_tile;
+    s_off[t] = (uint32_t)ti.seg_start + below_t + off_t;
   }
   __syncthreads();
 
@@ -195,48 +265,41 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   __syncthreads();
 
   const bool last_pass = (a.pass == kSortPasses - 1);
-  uint64_t *out = dst + (size_t)d * a.n;
+  uint64_t *out = dst + (size_t)d * a.stride;
   for (int s = t; s < valid; s += kSortThreads) {
     const uint64_t it = s_stage[s];
     const uint32_t digit = (uint32_t)(it >> (32 + a.shift)) & 255u;
     const uint32_t gpos = s_off[digit] + (uint32_t)s - s_base[digit];
     out[gpos] = it;
-    if (last_pass) rank[(size_t)d * a.n + (uint32_t)it] = gpos;
+    if (last_pass) rank[(size_t)d * a.stride + (uint32_t)it] = gpos;
   }
 }
 
 }  // namespace
 
-__global__ void k_zero(uint32_t *__restrict__ p, int count) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0u;
-}
-
-hipError_t launch_sort(const int32_t *xyz, int64_t n, const DirTable &dt, const Plan &pl, uint64_t *items_a,
-                       uint64_t *items_b, uint32_t *hist, uint32_t *totals, uint32_t *rank, fgbd_result *res,
-                       hipStream_t stream, const uint64_t **sorted_out, Prof *pf) {
+hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const uint64_t **sorted_out) {
   SortArgs a;
-  a.dt = dt;
-  a.n = (int32_t)n;
-  a.ntiles = pl.ntiles;
-  const dim3 grid(pl.ntiles, dt.num_dirs);
+  a.dt = r.dt;
+  a.sa = r.sa;
+  a.stride = r.pl.n_cap;
+  a.ntiles_cap = r.pl.ntiles_cap;
+  const int ntiles = r.sa.n_fixed >= 0 ? (r.sa.n_fixed + kSortTile - 1) / kSortTile : r.pl.ntiles_cap;
+  const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
   const uint64_t *src = nullptr;
-  uint64_t *bufs[2] = {items_a, items_b};
-  FGBD_PRE(pf, kUpsweep);
-  k_zero<<<1, 256, 0, stream>>>(totals, dt.num_dirs * kSortPasses * 256);
-  FGBD_POST(pf);
+  uint64_t *bufs[2] = {r.b.items_a, r.b.items_b};
   for (int pass = 0; pass < kSortPasses; ++pass) {
     a.pass = pass;
     a.shift = 8 * pass;
     uint64_t *dst = bufs[pass & 1];
-    FGBD_PRE(pf, kUpsweep);
-    k_sort_upsweep<<<grid, kSortThreads, 0, stream>>>(a, xyz, src, hist, totals, res);
-    FGBD_POST(pf);
-    FGBD_PRE(pf, kScan);
-    k_sort_scan<<<(dt.num_dirs * 256 + 3) / 4, 256, 0, stream>>>(pl.ntiles, dt.num_dirs, pass, hist, totals);
-    FGBD_POST(pf);
-    FGBD_PRE(pf, kDownsweep);
-    k_sort_downsweep<<<grid, kSortThreads, 0, stream>>>(a, xyz, src, dst, hist, rank);
-    FGBD_POST(pf);
+    FGBD_PRE(r.pf, kUpsweep);
+    k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, r.b.hist, r.b.totals, res);
+    FGBD_POST(r.pf);
+    FGBD_PRE(r.pf, kScan);
+    k_sort_scan<<<(r.dt.num_dirs * 256 + 3) / 4, 256, 0, r.stream>>>(a, r.b.hist);
+    FGBD_POST(r.pf);
+    FGBD_PRE(r.pf, kDownsweep);
+    k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.totals, r.b.rank);
+    FGBD_POST(r.pf);
     src = dst;
   }
   *sorted_out = src;

@@ -24,6 +24,8 @@ FGBD_E_UNSUPPORTED = -5
 FGBD_ST_COORD_RANGE = 1
 FGBD_ST_NO_PATCH = 2
 NUM_KERNELS = 9
+ABI_VERSION = 2
+MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
            "finalize")
 
@@ -85,6 +87,9 @@ _SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_denoise": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_denoise_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_poly_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -109,6 +114,9 @@ def lib() -> ctypes.CDLL:
             fn = getattr(handle, name)
             fn.restype = res
             fn.argtypes = args
+        if handle.fgbd_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {handle.fgbd_abi_version()}, the binding expects "
+                              f"{ABI_VERSION}: rebuild it")
         _lib = handle
     return _lib
 
@@ -136,9 +144,10 @@ def as_params(params) -> Params:
     return default_params(**dict(params))
 
 
-def workspace_size(params, n_max: int) -> int:
+def workspace_size(params, n_max: int, batch: int = 1) -> int:
+    """Workspace bytes for up to n_max points in `batch` clouds."""
     out = ctypes.c_size_t()
-    _check(lib().fgbd_workspace_size(ctypes.byref(as_params(params)), int(n_max), 1, ctypes.byref(out)))
+    _check(lib().fgbd_workspace_size(ctypes.byref(as_params(params)), int(n_max), int(batch), ctypes.byref(out)))
     return int(out.value)
 
 
@@ -163,9 +172,10 @@ class Context:
         self._ws = None
         self._ws_bytes = 0
 
-    def reserve(self, params, n: int) -> None:
-        """Make sure the workspace covers clouds of n points."""
-        need = workspace_size(params, n)
+    def reserve(self, params, n: int, batch: int = 1) -> None:
+        """Make sure the workspace covers n points in `batch` clouds (call it
+        before capturing a graph: a capture must not allocate)."""
+        need = workspace_size(params, n, batch)
         if need > self._ws_bytes:
             torch = _torch()
             ws = torch.empty(need, dtype=torch.uint8, device=self.device)
@@ -229,17 +239,22 @@ def _need(t, dtype, shape_tail, name, device):
         raise ValueError(f"{name} must have shape [n, {', '.join(map(str, shape_tail))}]")
 
 
-def new_result(device) -> "object":
-    """A zeroed device fgbd_result (40 bytes as uint8)."""
+def new_result(device, count: int = 1) -> "object":
+    """`count` zeroed device fgbd_result records (48 bytes each, as uint8)."""
     torch = _torch()
-    return torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+    return torch.zeros(RESULT_BYTES * count, dtype=torch.uint8, device=device)
+
+
+def read_results(res) -> list:
+    """Copy device fgbd_result records to the host (synchronises) and decode them."""
+    raw = res.detach().cpu().numpy().tobytes()
+    recs = np.frombuffer(raw, dtype=RESULT_DTYPE)
+    return [{name: rec[name].item() for name in RESULT_DTYPE.names} for rec in recs]
 
 
 def read_result(res) -> dict:
-    """Copy a device fgbd_result to the host (synchronises) and decode it."""
-    raw = res.detach().cpu().numpy().tobytes()
-    rec = np.frombuffer(raw, dtype=RESULT_DTYPE)[0]
-    return {name: rec[name].item() for name in RESULT_DTYPE.names}
+    """The first fgbd_result of a device buffer, decoded (synchronises)."""
+    return read_results(res[:RESULT_BYTES])[0]
 
 
 class SLGraph:
@@ -333,6 +348,34 @@ def denoise(xyz, rgb, params=None, ctx: Optional[Context] = None, out=None, res=
     res = new_result(ctx.device) if res is None else res
     _check(lib().fgbd_denoise(ctx.handle, _ptr(xyz), _ptr(rgb), n, ctypes.byref(prm), _ptr(out), _ptr(res),
                               _stream(ctx, stream)))
+    return out, res
+
+
+def denoise_batched(xyz, rgb, offsets, params=None, ctx: Optional[Context] = None, out=None, res=None,
+                    stream=None):
+    """The per-frame path for B clouds stored back to back (cloud s owns rows
+    offsets[s] .. offsets[s+1]-1; offsets: int64 device tensor [B+1]).  The
+    sizes stay on the device, so a captured call serves any sizes up to
+    xyz.shape[0].  Returns (rgb_out, results: uint8 device tensor [B * 48])."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(xyz.device)
+    _need(xyz, torch.int32, (3,), "xyz", ctx.device)
+    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64 or offsets.device != ctx.device \
+            or offsets.dim() != 1 or not offsets.is_contiguous():
+        raise ValueError(f"offsets must be a contiguous 1-D int64 tensor on {ctx.device}")
+    n = int(xyz.shape[0])
+    if rgb.shape[0] != n:
+        raise ValueError("xyz and rgb sizes differ")
+    batch = int(offsets.numel()) - 1
+    ctx.reserve(prm, n, max(batch, 1))
+    out = torch.empty_like(rgb) if out is None else out
+    res = new_result(ctx.device, max(batch, 1)) if res is None else res
+    if res.numel() < RESULT_BYTES * max(batch, 1):
+        raise ValueError("res holds fewer than batch results")
+    _check(lib().fgbd_denoise_batched(ctx.handle, _ptr(xyz), _ptr(rgb), n, _ptr(offsets), batch,
+                                      ctypes.byref(prm), _ptr(out), _ptr(res), _stream(ctx, stream)))
     return out, res
 
 

@@ -279,3 +279,14 @@ def moved_body_frame(seed: int, frame: int, bits: int = 10, target: int = 1_000_
     noisy = add_noise(clean, sigma, np.random.default_rng(seed * 1000 + 13 + frame))
     cloud = Cloud(np.ascontiguousarray(xyz, np.int32), clean, noisy, float(sigma), bits, seed + frame)
     return cloud, scale
+
+
+def batched_specs(seed: int = 2000, count: int = 8, lo: int = 200_000, hi: int = 1_200_000,
+                  sigma_lo: float = 5.0, sigma_hi: float = 35.0) -> list[dict]:
+    """Arguments of ``body_cloud`` for a batch of independently seeded clouds
+    whose sizes are uniform in [lo, hi] and noise levels uniform in
+    [sigma_lo, sigma_hi]."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(lo, hi + 1, size=count)
+    sigmas = rng.uniform(sigma_lo, sigma_hi, size=count)
+    return [dict(seed=seed + 100 * (s + 1), target=int(sizes[s]), sigma=float(sigmas[s])) for s in range(count)]

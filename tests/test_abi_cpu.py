@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_version_and_defaults():
-    assert fgbd.lib().fgbd_abi_version() == 1
+    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 2
     p = fgbd.default_params()
     assert (p.bits, p.num_dirs, p.window, p.k, p.patch, p.q_max) == (10, 8, 4, 8, 0, 32)
     assert p.fslr_kappa == 2.0 and p.sigma_g == 0.0
@@ -45,6 +45,17 @@ def test_workspace_size_grows_with_n():
     # at least the sort ping-pong buffers: 2 x L x n x 8 bytes
     assert b >= 2 * 8 * 1_000_000 * 8
     assert fgbd.workspace_size(p, 0) > 0
+
+
+def test_workspace_size_batch():
+    p = fgbd.default_params()
+    one = fgbd.workspace_size(p, 100_000)
+    many = fgbd.workspace_size(p, 100_000, fgbd.MAX_BATCH)
+    assert many > one  # per-cloud digit totals, selection states and sums
+    out = ctypes.c_size_t()
+    lib = fgbd.lib()
+    for bad in (0, -1, fgbd.MAX_BATCH + 1):
+        assert lib.fgbd_workspace_size(ctypes.byref(p), 10, bad, ctypes.byref(out)) == fgbd.FGBD_E_INVALID
 
 
 @pytest.fixture()
@@ -115,6 +126,35 @@ def test_graph_call_errors(ctx):
     assert lib.fgbd_filter(ctx, ctypes.byref(g), FAKE, ctypes.byref(p), FAKE, None, 0, far, FAKE, None) == E
     assert "patch_spread" in lib.fgbd_last_error().decode()
     assert lib.fgbd_filter(ctx, ctypes.byref(g), FAKE, ctypes.byref(p), None, None, -2, far, FAKE, None) == E
+
+
+def test_batched_call_errors(ctx):
+    lib = fgbd.lib()
+    p = fgbd.default_params()
+    far = ctypes.c_void_p(0x900000)
+    E = fgbd.FGBD_E_INVALID
+    ok_args = (FAKE, FAKE, 10, FAKE, 2, ctypes.byref(p), far, FAKE, None)
+    for batch in (0, -3, fgbd.MAX_BATCH + 1):
+        a = list(ok_args)
+        a[4] = batch
+        assert lib.fgbd_denoise_batched(ctx, *a) == E
+        assert "batch" in lib.fgbd_last_error().decode()
+    for idx in (0, 1, 3, 6, 7):  # xyz, rgb_in, offsets, rgb_out, res
+        a = list(ok_args)
+        a[idx] = ctypes.c_void_p(0)
+        assert lib.fgbd_denoise_batched(ctx, *a) == E, idx
+    a = list(ok_args)
+    a[2] = -1
+    assert lib.fgbd_denoise_batched(ctx, *a) == E
+    a = list(ok_args)
+    a[6] = ctypes.c_void_p(0x1000 + 60)  # rgb_out overlaps rgb_in
+    assert lib.fgbd_denoise_batched(ctx, *a) == E
+    assert "overlap" in lib.fgbd_last_error().decode()
+    assert lib.fgbd_denoise_batched(None, *ok_args) == E
+    bad = fgbd.default_params(k=0)
+    a = list(ok_args)
+    a[5] = ctypes.byref(bad)
+    assert lib.fgbd_denoise_batched(ctx, *a) == E
 
 
 def test_workspace_setting(ctx):

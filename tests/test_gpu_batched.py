@@ -1,0 +1,188 @@
+"""GPU parity of the batched path: several clouds of different sizes stored
+back to back and denoised in one launch sequence, each cloud against the
+oracle run on that cloud alone; and the same call captured once in a HIP graph
+and replayed on streamed frames of varying size (sizes read from device
+memory), every replay against an eager call."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2401_09721_amd import fgbd, synth  # noqa: E402
+
+from gpu_helpers import COLOUR_TOL, compare_denoise, dev, oracle_params  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def small_cloud(n, seed, bits=8):
+    """n random points (duplicates allowed) with uniform colours."""
+    rng = np.random.default_rng(seed)
+    xyz = rng.integers(0, 1 << bits, size=(n, 3)).astype(np.int32)
+    rgb = rng.uniform(0, 255, size=(n, 3)).astype(np.float32)
+    return xyz, rgb
+
+
+def shape_cloud(seed, target, sigma=20.0):
+    c = synth.random_shapes_cloud(seed, bits=8, n_ellipsoids=3, target=target, sigma=sigma)
+    return c.xyz, c.noisy
+
+
+def run_batched(clouds, prm, extra=0, offsets=None, ctx=None):
+    """Concatenate the clouds (plus `extra` padding rows) and run the batched
+    call.  Returns host outputs, decoded results and the offsets used."""
+    xyz = np.concatenate([c[0] for c in clouds] + [np.zeros((extra, 3), np.int32)])
+    rgb = np.concatenate([c[1] for c in clouds] + [np.full((extra, 3), -7.0, np.float32)])
+    if offsets is None:
+        offsets = np.concatenate([[0], np.cumsum([len(c[0]) for c in clouds])]).astype(np.int64)
+    out0 = torch.full((len(xyz), 3), -7.0, dtype=torch.float32, device="cuda")
+    out, res = fgbd.denoise_batched(dev(xyz, torch.int32), dev(rgb, torch.float32), dev(offsets, torch.int64), prm,
+                                    ctx=ctx, out=out0)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), fgbd.read_results(res), offsets
+
+
+def check_each(clouds, out, results, offsets, prm, status_mask=~0):
+    assert len(results) == len(clouds)
+    for s, (xyz, rgb) in enumerate(clouds):
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        assert b - a == len(xyz)
+        compare_denoise(out[a:b], results[s], xyz, rgb, prm, status_mask=status_mask)
+
+
+def test_uneven_batch_matches_oracle_per_cloud():
+    prm = fgbd.default_params(bits=8)
+    clouds = [shape_cloud(11, 16000), small_cloud(1, 1), small_cloud(0, 2), shape_cloud(12, 5000),
+              small_cloud(9, 3), shape_cloud(13, 30000, sigma=30.0), small_cloud(4097, 4)]
+    out, results, offsets = run_batched(clouds, prm)
+    check_each(clouds, out, results, offsets, prm)
+    assert results[2]["status"] & fgbd.FGBD_ST_NO_PATCH and results[2]["sigma_est"] == 0.0
+
+
+@pytest.mark.parametrize("kw", [dict(num_dirs=3, window=1, k=6), dict(fslr_kappa=0.0), dict(k=12, patch=6),
+                                dict(q_max=1), dict(sigma_g=2.0)])
+def test_batch_variants(kw):
+    prm = fgbd.default_params(bits=8, **kw)
+    clouds = [shape_cloud(21, 8000), shape_cloud(22, 3000, sigma=10.0), small_cloud(300, 5)]
+    out, results, offsets = run_batched(clouds, prm)
+    check_each(clouds, out, results, offsets, prm)
+
+
+def test_batch_equals_single_calls():
+    """Each cloud of a batch gets what fgbd_denoise gives it alone (the block
+    split differs, so sums may round differently: colours within 1e-4)."""
+    prm = fgbd.default_params(bits=8)
+    clouds = [shape_cloud(31, 12000), shape_cloud(32, 7000), shape_cloud(33, 20000, sigma=25.0)]
+    out, results, offsets = run_batched(clouds, prm)
+    for s, (xyz, rgb) in enumerate(clouds):
+        o1, r1 = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm)
+        r1 = fgbd.read_result(r1)
+        rb = results[s]
+        for key in ("q", "n_fslr", "n_eff", "m", "status", "sweeps"):
+            assert rb[key] == r1[key], key
+        assert math.isclose(rb["sigma_est"], r1["sigma_est"], rel_tol=1e-12)
+        assert math.isclose(rb["sigma_g"], r1["sigma_g"], rel_tol=1e-12)
+        a, b = int(offsets[s]), int(offsets[s + 1])
+        assert np.max(np.abs(out[a:b] - o1.cpu().numpy())) <= 1e-4
+
+
+def test_max_batch_of_small_clouds():
+    prm = fgbd.default_params(bits=6)
+    rng = np.random.default_rng(9)
+    sizes = rng.integers(0, 400, fgbd.MAX_BATCH)
+    sizes[[3, 17, 40]] = 0
+    clouds = [small_cloud(int(n), 100 + s, bits=6) for s, n in enumerate(sizes)]
+    out, results, offsets = run_batched(clouds, prm)
+    check_each(clouds, out, results, offsets, prm)
+
+
+def test_capacity_tail_is_untouched():
+    prm = fgbd.default_params(bits=8)
+    clouds = [shape_cloud(41, 6000), small_cloud(50, 6)]
+    out, results, offsets = run_batched(clouds, prm, extra=3000)
+    check_each(clouds, out, results, offsets, prm)
+    assert np.all(out[int(offsets[-1]):] == -7.0)
+
+
+def test_bad_offsets_are_clamped_and_flagged():
+    """offsets [0, 500, 300, n + 100] become [0, 500, 500, n]: cloud 1 is
+    empty, cloud 2 holds the rest; every result carries the flag."""
+    prm = fgbd.default_params(bits=8)
+    xyz, rgb = shape_cloud(51, 3000)
+    n = len(xyz)
+    bad = np.array([0, 500, 300, n + 100], np.int64)
+    out, results, _ = run_batched([(xyz, rgb)], prm, offsets=bad)
+    for r in results:
+        assert r["status"] & fgbd.FGBD_ST_BAD_OFFSETS
+    used = np.array([0, 500, 500, n])
+    parts = [(xyz[0:500], rgb[0:500]), (xyz[500:500], rgb[500:500]), (xyz[500:], rgb[500:])]
+    check_each(parts, out, results, used, prm, status_mask=~fgbd.FGBD_ST_BAD_OFFSETS)
+
+
+def test_batched_deterministic_repeat():
+    prm = fgbd.default_params(bits=8)
+    clouds = [shape_cloud(61, 9000), shape_cloud(62, 4000)]
+    a, ra, _ = run_batched(clouds, prm)
+    b, rb, _ = run_batched(clouds, prm)
+    assert np.array_equal(a, b) and ra == rb
+
+
+def test_graph_captured_stream_of_frames():
+    """One capture of the batched call (one cloud, capacity 20000) replayed on
+    frames of different sizes copied into the same buffers: every replay equals
+    an eager call with the same capacity bit for bit, and the first frame also
+    matches the oracle."""
+    prm = fgbd.default_params(bits=8)
+    cap = 20000
+    ctx = fgbd.Context("cuda")
+    ctx.reserve(prm, cap, 1)
+    xyz_s = torch.zeros((cap, 3), dtype=torch.int32, device="cuda")
+    rgb_s = torch.zeros((cap, 3), dtype=torch.float32, device="cuda")
+    off_s = torch.zeros(2, dtype=torch.int64, device="cuda")
+    out_s = torch.zeros((cap, 3), dtype=torch.float32, device="cuda")
+    res_s = fgbd.new_result("cuda", 1)
+
+    def load(xyz, rgb):
+        n = len(xyz)
+        xyz_s.zero_()
+        rgb_s.zero_()
+        xyz_s[:n] = dev(xyz, torch.int32)
+        rgb_s[:n] = dev(rgb, torch.float32)
+        off_s.copy_(torch.tensor([0, n], dtype=torch.int64))
+
+    frames = [shape_cloud(70 + f, t) for f, t in enumerate([16000, 12000, 19000, 6000])]
+    frames = [f for f in frames if len(f[0]) <= cap]
+    assert len(frames) >= 3
+    load(*frames[0])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=out_s, res=res_s)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=out_s, res=res_s)
+    torch.cuda.synchronize()
+    for f, (xyz, rgb) in enumerate(frames + frames[:1]):
+        n = len(xyz)
+        load(xyz, rgb)
+        out_s.fill_(-7.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        got = out_s.cpu().numpy().copy()
+        got_r = fgbd.read_results(res_s)[0]
+        # eager reference with the same capacity and context, then restore
+        ref_out = torch.full((cap, 3), -7.0, dtype=torch.float32, device="cuda")
+        ref_res = fgbd.new_result("cuda", 1)
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=ref_out, res=ref_res)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref_out.cpu().numpy()), f"frame {f}: replay differs from eager"
+        assert got_r == fgbd.read_results(ref_res)[0]
+        assert np.all(got[n:] == -7.0)
+        if f == 0:
+            compare_denoise(got[:n], got_r, xyz, rgb, prm)
+    ctx.close()

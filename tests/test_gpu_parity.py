@@ -18,22 +18,13 @@ from paper_2401_09721_amd import fgbd, synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-COLOUR_TOL = 1e-3
-
-
-def dev(a, dtype):
-    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+from gpu_helpers import COLOUR_TOL, compare_denoise, dev, oracle_params  # noqa: E402
 
 
 def gpu_graph(xyz, prm):
     g = fgbd.build_slg(dev(xyz, torch.int32), prm)
     torch.cuda.synchronize()
     return g, g.col.cpu().numpy(), g.dist2.cpu().numpy(), g.p.cpu().numpy(), fgbd.read_result(g.result)
-
-
-def oracle_params(prm):
-    return dict(bits=prm.bits, num_dirs=prm.num_dirs, window=prm.window, k=prm.k, patch=prm.patch,
-                q_max=prm.q_max, fslr_kappa=prm.fslr_kappa, sigma_g=prm.sigma_g)
 
 
 def check_graph(xyz, prm):
@@ -51,28 +42,7 @@ def check_graph(xyz, prm):
 def check_denoise(xyz, rgb, prm, ores=None):
     out, res = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm)
     torch.cuda.synchronize()
-    out = out.cpu().numpy()
-    r = fgbd.read_result(res)
-    if ores is None:
-        ores = O.denoise(xyz, rgb, oracle_params(prm))
-    assert abs(r["sigma_est"] - ores["sigma_est"]) <= COLOUR_TOL
-    assert math.isclose(r["sigma_g"], ores["sigma_g"], rel_tol=1e-12, abs_tol=1e-300)
-    assert r["n_eff"] == ores["n_eff"]
-    assert r["status"] == ores["status"]
-    q = r["q"]
-    if q != ores["q"]:
-        en = ores["energies"]
-        target = ores["sigma_est"] ** 2
-        assert q < len(en), f"GPU q {q} beyond the oracle's stopping point"
-        lg, lo = abs(target - en[q]), abs(target - en[ores["q"]])
-        assert abs(lg - lo) <= 1e-5 * max(target, 1.0), f"q {q} vs oracle {ores['q']}: not a near-tie"
-        ref = O.filter_power(ores["col"], ores["p"], rgb, q)
-    else:
-        ref = ores["out"]
-        assert r["n_fslr"] == ores["n_fslr"]
-    err = float(np.max(np.abs(out - ref))) if out.size else 0.0
-    assert err <= COLOUR_TOL, f"max colour error {err}"
-    return out, r, ores
+    return compare_denoise(out.cpu().numpy(), fgbd.read_result(res), xyz, rgb, prm, ores)
 
 
 # ------------------------------------------------------------------ graph
