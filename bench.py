@@ -4,7 +4,11 @@ One step = one fgbd_denoise call (scan-line graph + noise estimate + filter
 selection and sweeps) on a synthetic 1M-point frame already resident in HBM.
 Prints one JSON line with points/s, frames/s, the roofline of the dominant
 kernel (per-kernel HIP event timing from a profiled pass over the same steps)
-and the CPU oracle timed on the host.
+and the CPU oracle timed on the host.  Beside the headline it reports the
+three usage patterns on their own workloads: a batch of 8 uneven clouds in one
+call, a stream of 30 moving frames replayed from one captured HIP graph
+(frames/s and p50/p99 frame latency), and forward+backward of the polynomial
+filter on 4 x 500k points inside 50 Adam steps.
 """
 import argparse
 import json
@@ -81,6 +85,213 @@ def measured_traffic(kind: str, config: dict):
     return k["hbm_bytes_per_launch"]
 
 
+def _gen(job):
+    from paper_2401_09721_amd import synth
+
+    kind, kw = job
+    if kind == "body":
+        return synth.body_cloud(**kw)
+    return synth.moved_body_frame(**kw)  # (cloud, fitted scale)
+
+
+def make_inputs(args, synth) -> dict:
+    """The headline frame plus the pattern workloads: 8 uneven clouds
+    (200k-1.2M points, sigma uniform in [5, 35]), a sequence of moving ~1M-point
+    frames (sigma 20) and 4 clouds of 500k points (sigma 25) with clean colours."""
+    import multiprocessing as mp
+
+    jobs = [("body", dict(seed=synth.config_seed(1), target=args.points, sigma=args.sigma))]
+    stream_seed = synth.config_seed(3)
+    if not args.no_patterns:
+        jobs += [("body", dict(bits=10, **kw)) for kw in synth.batched_specs(synth.config_seed(2), 8)]
+        jobs += [("body", dict(seed=synth.config_seed(4, c), target=500_000, sigma=25.0)) for c in range(4)]
+        jobs += [("frame", dict(seed=stream_seed, frame=0, target=args.points, sigma=20.0))]
+    workers = max(1, min(16, os.cpu_count() or 1, len(jobs) + args.stream_frames))
+    with mp.get_context("fork").Pool(workers) as pool:
+        clouds = pool.map(_gen, jobs, chunksize=1)
+        out = {"frame": clouds[0]}
+        if not args.no_patterns:
+            first, scale = clouds[13]  # later frames reuse the scale fitted on frame 0
+            rest = pool.map(_gen, [("frame", dict(seed=stream_seed, frame=f, target=args.points, sigma=20.0,
+                                                  scale=scale)) for f in range(1, args.stream_frames)],
+                            chunksize=1)
+            out["batch"] = clouds[1:9]
+            out["diff"] = clouds[9:13]
+            out["stream"] = [first] + [c for c, _ in rest]
+    return out
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def bench_batched(clouds, prm, dev, args, fgbd, torch) -> dict:
+    """One fgbd_denoise_batched call over 8 uneven clouds per step."""
+    import numpy as np
+
+    sizes = [c.n for c in clouds]
+    offsets = torch.as_tensor(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64), device=dev)
+    xyz = torch.as_tensor(np.concatenate([c.xyz for c in clouds]), device=dev)
+    rgb = torch.as_tensor(np.concatenate([c.noisy for c in clouds]), device=dev)
+    total = int(xyz.shape[0])
+    ctx = fgbd.Context(dev)
+    ctx.reserve(prm, total, len(clouds))
+    out = torch.empty_like(rgb)
+    res = fgbd.new_result(dev, len(clouds))
+    default = ctx.schedule()
+    fgbd.denoise_batched(xyz, rgb, offsets, prm, ctx=ctx, out=out, res=res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    schedule = ctx.autotune(xyz, rgb, offsets, prm, reps=2, out=out, res=res)
+    tune_s = time.perf_counter() - t0
+    for _ in range(max(1, args.warmup)):
+        fgbd.denoise_batched(xyz, rgb, offsets, prm, ctx=ctx, out=out, res=res)
+    steps = max(1, args.steps // 2)
+    e0, e1 = _events(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        fgbd.denoise_batched(xyz, rgb, offsets, prm, ctx=ctx, out=out, res=res)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rs = fgbd.read_results(res)
+    ctx.close()
+    return {"workload": f"{len(clouds)} body clouds of {min(sizes)}-{max(sizes)} points (sizes uniform in "
+                        f"200k-1.2M), noise sigma uniform in [5, 35], 2^10 grid, one batched call",
+            "n_points": total, "clouds": len(clouds), "sizes": sizes, "steps": steps,
+            "ms_per_batch": ms, "points_per_s": total / (ms / 1e3), "clouds_per_s": len(clouds) / (ms / 1e3),
+            "schedule": schedule, "default_schedule": default, "autotune_s": tune_s,
+            "q": [r["q"] for r in rs], "sigma_est": [round(r["sigma_est"], 3) for r in rs]}
+
+
+def bench_streaming(frames, prm, dev, fgbd, torch, np) -> dict:
+    """Frames resident in HBM; per frame a device copy into the static input
+    buffers and one replay of the captured per-frame graph (the frame size is
+    read from device memory).  Three passes over the sequence."""
+    cap = max(f.n for f in frames)
+    dxyz = [torch.as_tensor(f.xyz, device=dev) for f in frames]
+    drgb = [torch.as_tensor(f.noisy, device=dev) for f in frames]
+    doff = [torch.tensor([0, f.n], dtype=torch.int64, device=dev) for f in frames]
+    ctx = fgbd.Context(dev)
+    ctx.reserve(prm, cap, 1)
+    xyz_s = torch.zeros((cap, 3), dtype=torch.int32, device=dev)
+    rgb_s = torch.zeros((cap, 3), dtype=torch.float32, device=dev)
+    off_s = torch.zeros(2, dtype=torch.int64, device=dev)
+    out_s = torch.zeros((cap, 3), dtype=torch.float32, device=dev)
+    res_s = fgbd.new_result(dev, 1)
+
+    def load(f):
+        n = frames[f].n
+        xyz_s[:n].copy_(dxyz[f])
+        rgb_s[:n].copy_(drgb[f])
+        off_s.copy_(doff[f])
+
+    load(0)
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(side):
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=out_s, res=res_s)
+    torch.cuda.current_stream(dev).wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=out_s, res=res_s)
+    torch.cuda.synchronize()
+    for f in range(min(3, len(frames))):  # warm replays
+        load(f)
+        graph.replay()
+    torch.cuda.synchronize()
+    passes = 3
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(passes * len(frames) + 1)]
+    marks[0].record()
+    for p in range(passes):
+        for f in range(len(frames)):
+            load(f)
+            graph.replay()
+            marks[1 + p * len(frames) + f].record()
+    torch.cuda.synchronize()
+    lat = np.array([marks[i].elapsed_time(marks[i + 1]) for i in range(len(marks) - 1)])
+    total_ms = marks[0].elapsed_time(marks[-1])
+    npts = passes * sum(f.n for f in frames)
+    r = fgbd.read_results(res_s)[0]
+    ctx.close()
+    return {"workload": f"{len(frames)} frames of a rigidly moving body (~1M points each, "
+                        f"{min(f.n for f in frames)}-{cap}), noise sigma 20, one captured HIP graph replayed "
+                        f"per frame, frame size in device memory",
+            "frames": int(lat.size), "frames_per_s": lat.size / (total_ms / 1e3),
+            "points_per_s": npts / (total_ms / 1e3), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()),
+            "latency_includes": "device copy of the frame into the graph's input buffers + graph replay",
+            "last_q": r["q"]}
+
+
+def bench_fwd_bwd(clouds, dev, args, fgbd, torch) -> dict:
+    """Polynomial filter (8 coefficients, trained bandwidth) forward and
+    hand-written adjoint on 4 x 500k points, inside Adam steps fitting the
+    coefficients and the bandwidth to the clean colours (MSE)."""
+    import numpy as np
+
+    prm = fgbd.default_params()
+    ctx = fgbd.Context(dev)
+    graphs = []
+    for c in clouds:
+        ctx.reserve(prm, c.n)
+        graphs.append(fgbd.build_slg(torch.as_tensor(c.xyz, device=dev), prm, ctx=ctx))
+    offs = np.concatenate([[0], np.cumsum([c.n for c in clouds])])
+    col = torch.cat([torch.where(g.col >= 0, g.col + int(o), g.col) for g, o in zip(graphs, offs[:-1])])
+    g = fgbd.SLGraph(col.contiguous(), torch.cat([g.dist2 for g in graphs]).contiguous(),
+                     torch.cat([g.p for g in graphs]).contiguous(), graphs[0].result)
+    sg0 = float(np.mean([fgbd.read_result(gr.result)["sigma_g"] for gr in graphs]))
+    x = torch.as_tensor(np.concatenate([c.noisy for c in clouds]), device=dev)
+    clean = torch.as_tensor(np.concatenate([c.clean for c in clouds]).astype(np.float32), device=dev)
+    n = int(x.shape[0])
+    ctx.reserve(prm, n)
+    coef = torch.zeros(8, dtype=torch.float32, device=dev)
+    coef[2] = 1.0  # start from two sweeps of eq. 5
+    coef.requires_grad_(True)
+    sigma_g = torch.tensor(sg0, dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([coef, sigma_g], lr=1e-2)
+
+    def step():
+        out = fgbd.poly_filter_autograd(x, coef, sigma_g, g, ctx=ctx)
+        loss = torch.mean((out - clean) ** 2)
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        return loss
+
+    mse_noisy = float(torch.mean((x - clean) ** 2))
+    mse0 = float(step())  # also the warm-up
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    loss = None
+    for _ in range(args.adam_steps):
+        loss = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.adam_steps
+    # the filter's own forward+backward, without the optimiser and loss
+    out, saved = fgbd.poly_filter(g, x, coef.detach(), sigma_g.detach(), ctx=ctx)
+    go = torch.ones_like(out)
+    e0.record()
+    for _ in range(args.adam_steps):
+        out, saved = fgbd.poly_filter(g, x, coef.detach(), sigma_g.detach(), ctx=ctx)
+        fgbd.poly_filter_backward(g, saved, coef.detach(), sigma_g.detach(), go, ctx=ctx)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1) / args.adam_steps
+    ctx.close()
+    return {"workload": "4 body clouds x 500k points, noise sigma 25, polynomial filter with 8 coefficients "
+                        "and trained bandwidth, MSE to the clean colours, Adam (lr 1e-2)",
+            "n_points": n, "adam_steps": args.adam_steps, "ms_per_adam_step": ms,
+            "points_per_s": n / (ms_f / 1e3), "ms_fwd_bwd": ms_f,
+            "points_per_s_with_optimizer": n / (ms / 1e3),
+            "mse_noisy": mse_noisy, "mse_start": mse0, "mse_end": float(loss),
+            "coef": [round(v, 4) for v in coef.detach().cpu().tolist()], "sigma_g": float(sigma_g)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +302,10 @@ def main() -> int:
     ap.add_argument("--points", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel profiled pass")
+    ap.add_argument("--no-patterns", action="store_true",
+                    help="skip the batched, streaming and forward+backward measurements")
+    ap.add_argument("--stream-frames", type=int, default=30)
+    ap.add_argument("--adam-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -100,14 +315,20 @@ def main() -> int:
               "multi-GPU path (use --gpus 1).", file=sys.stderr)
         return 2
 
+    from paper_2401_09721_amd import synth
+
+    # Inputs are generated on the host before the GPU is touched, in worker
+    # processes (the generator is pure numpy).
+    t0 = time.time()
+    inputs = make_inputs(args, synth)
+    gen_s = time.time() - t0
+    cloud = inputs["frame"]
+
     import numpy as np
     import torch
 
-    from paper_2401_09721_amd import fgbd, synth
+    from paper_2401_09721_amd import fgbd
 
-    t0 = time.time()
-    cloud = synth.body_cloud(synth.config_seed(1), target=args.points, sigma=args.sigma)
-    gen_s = time.time() - t0
     n = cloud.n
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -219,6 +440,14 @@ def main() -> int:
                                   "traffic": measured_traffic("sweep", tcfg),
                                   "bytes_per_launch": b, "us_per_launch": 1e3 * per_launch,
                                   "launches": launches}
+
+    if not args.no_patterns:
+        line["batched"] = bench_batched(inputs["batch"], prm, dev, args, fgbd, torch)
+        print(f"# batched: {json.dumps(line['batched'])}", file=sys.stderr, flush=True)
+        line["streaming"] = bench_streaming(inputs["stream"], prm, dev, fgbd, torch, np)
+        print(f"# streaming: {json.dumps(line['streaming'])}", file=sys.stderr, flush=True)
+        line["fwd_bwd"] = bench_fwd_bwd(inputs["diff"], dev, args, fgbd, torch)
+        print(f"# fwd_bwd: {json.dumps(line['fwd_bwd'])}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB

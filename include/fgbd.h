@@ -209,6 +209,38 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
                                  const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
                                  fgbd_result *res, void *stream);
 
+/* Launch schedule of the per-cloud kernels: the largest grid, in blocks of
+ * 256 threads, of (merge_blocks) the neighbour merge and edge weights,
+ * (noise_blocks) the patch statistics and (sweep_blocks) the filter sweeps
+ * and finalise.  Defaults 1024 each.  A schedule changes no result beyond
+ * the rounding order of FP64 sums (block partials); it is a property of the
+ * context and applies to every later call on it.  Valid ranges:
+ * merge_blocks and sweep_blocks 64..4096, noise_blocks 64..1024. */
+typedef struct {
+  int32_t merge_blocks;
+  int32_t noise_blocks;
+  int32_t sweep_blocks;
+  int32_t pad_;
+} fgbd_schedule;
+
+/* out, s: host. */
+fgbd_status fgbd_get_schedule(fgbd_ctx ctx, fgbd_schedule *out);
+fgbd_status fgbd_set_schedule(fgbd_ctx ctx, const fgbd_schedule *s);
+
+/* Autotuner of the launch schedule.  Runs fgbd_denoise_batched on the given
+ * inputs (same arguments and rules as that call; the outputs hold the last
+ * run) under candidate grid sizes, one kernel group at a time (merge and
+ * weights, then patch statistics and the noise solve, then sweeps and
+ * finalise), `reps` timed
+ * runs per candidate after one warm-up, times every kernel with HIP events,
+ * and keeps the fastest sizes in the context.  Blocks the host until the runs
+ * finish, so it must not be captured; tune once per workload shape, then
+ * capture or stream.  The caller's own profiling counters are kept.
+ * reps: 1..100;  chosen: optional host output of the selected schedule. */
+fgbd_status fgbd_autotune(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                          const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
+                          fgbd_result *res, int32_t reps, fgbd_schedule *chosen, void *stream);
+
 /* Polynomial graph filter, the differentiable generalisation of eq. 5:
  *   out = sum_{k=0}^{ncoef-1} coef[k] T^k x,
  * with T = D_g^{-1} W_g (eq. 5) whose weights (eq. 4) are recomputed from

@@ -59,6 +59,7 @@ struct fgbd_ctx_s {
   void *user = nullptr;
   size_t user_bytes = 0;
   bool profile = false;
+  Tune tune = kDefaultTune;
   std::vector<hipEvent_t> pool;
   std::vector<Record> pending;
   double ms[FGBD_NUM_KERNELS] = {0};
@@ -90,7 +91,7 @@ void make_dir_table(int bits, int num_dirs, DirTable *t) {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Plan make_plan(int64_t n_cap, int B, const fgbd_params &p) {
+Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   Plan pl;
   memset(&pl, 0, sizeof(pl));
   pl.n_cap = n_cap;
@@ -104,13 +105,13 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p) {
   // most ceil(n / tile) + B - 1
   const int64_t tiles = (n_cap + kSortTile - 1) / kSortTile + B - 1;
   pl.ntiles_cap = (int32_t)(tiles < 1 ? 1 : tiles);
-  auto grid_for = [&](int64_t units) {
-    int64_t g = units < 1 ? 1 : (units < kMaxGrid ? units : kMaxGrid);
+  auto grid_for = [&](int64_t units, int cap) {
+    int64_t g = units < 1 ? 1 : (units < cap ? units : cap);
     return (int32_t)(g < B ? B : g);
   };
-  pl.grid[kGridMerge] = grid_for((n_cap + kBlock - 1) / kBlock);
-  pl.grid[kGridSweep] = grid_for((n_cap + kBlock - 1) / kBlock);
-  pl.grid[kGridNoise] = grid_for((n_cap + pl.TP - 1) / pl.TP);
+  pl.grid[kGridMerge] = grid_for((n_cap + kBlock - 1) / kBlock, tune.cap[kGridMerge]);
+  pl.grid[kGridSweep] = grid_for((n_cap + kBlock - 1) / kBlock, tune.cap[kGridSweep]);
+  pl.grid[kGridNoise] = grid_for((n_cap + pl.TP - 1) / pl.TP, tune.cap[kGridNoise]);
   pl.E1 = 1 + pl.D * (pl.D + 1) / 2 + 3 * pl.D;
   const size_t N = (size_t)(n_cap > 0 ? n_cap : 1);
   size_t off = 0;
@@ -371,6 +372,21 @@ struct EventProf final : Prof {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// Waits for the recorded event pairs and adds their times per kernel kind.
+fgbd_status drain(fgbd_ctx ctx, double *ms, int64_t *launches) {
+  for (auto &r : ctx->pending) {
+    HIP_TRY(hipEventSynchronize(r.b), "hipEventSynchronize");
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
+    ms[r.kind] += t;
+    launches[r.kind] += 1;
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->pending.clear();
+  return FGBD_OK;
+}
+
 Run make_run(fgbd_ctx ctx, const Plan &pl, char *ws, const fgbd_params &prm, int64_t n_fixed, hipStream_t s,
              Prof *pf) {
   Run r;
@@ -481,7 +497,9 @@ fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t bat
   if ((st = check_n(n_max)) != FGBD_OK) return st;
   if (batch < 1 || batch > kMaxSeg) return fail(FGBD_E_INVALID, "batch must be in 1..%d (got %d)", kMaxSeg, batch);
   if (!bytes) return fail(FGBD_E_INVALID, "bytes is NULL");
-  const size_t a = make_plan(n_max, batch, *p).total;
+  // sized for the largest schedule, so any later fgbd_set_schedule fits
+  const Tune widest = {{kGridCapMax, kNoiseGridCapMax, kGridCapMax}};
+  const size_t a = make_plan(n_max, batch, *p, widest).total;
   const size_t b = poly_workspace(n_max, p->k, kMaxPoly, kMaxGrid);
   *bytes = a > b ? a : b;
   return ok();
@@ -509,7 +527,7 @@ fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fg
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, 1, *params);
+  const Plan pl = make_plan(n, 1, *params, ctx->tune);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
@@ -534,7 +552,7 @@ fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, 1, *params);
+  const Plan pl = make_plan(n, 1, *params, ctx->tune);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
@@ -569,7 +587,7 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, 1, *params);
+  const Plan pl = make_plan(n, 1, *params, ctx->tune);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
@@ -605,7 +623,7 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, 1, *params);
+  const Plan pl = make_plan(n, 1, *params, ctx->tune);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
@@ -616,9 +634,9 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   return ok();
 }
 
-fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
-                                 const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
-                                 fgbd_result *res, void *stream) {
+static fgbd_status check_batched(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                                 const int64_t *offsets, int32_t batch, const fgbd_params *params,
+                                 const float *rgb_out, const fgbd_result *res) {
   if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
   fgbd_status st = check_params(params);
   if (st != FGBD_OK) return st;
@@ -629,10 +647,18 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
   if (n_total > 0 && (!xyz || !rgb_in || !rgb_out)) return fail(FGBD_E_INVALID, "NULL input or output array");
   if (n_total > 0 && overlap(rgb_in, (size_t)n_total * 12, rgb_out, (size_t)n_total * 12))
     return fail(FGBD_E_INVALID, "rgb_in and rgb_out overlap");
+  return FGBD_OK;
+}
+
+fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                                 const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
+                                 fgbd_result *res, void *stream) {
+  fgbd_status st = check_batched(ctx, xyz, rgb_in, n_total, offsets, batch, params, rgb_out, res);
+  if (st != FGBD_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n_total, batch, *params);
+  const Plan pl = make_plan(n_total, batch, *params, ctx->tune);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
@@ -640,6 +666,100 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
   HIP_TRY(launch_setup(r, offsets, 0, res, n_total == 0 ? 2 : 1), "setup launch");
   if (n_total == 0) return ok();
   if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
+  return ok();
+}
+
+static fgbd_status check_schedule(const fgbd_schedule *s) {
+  if (!s) return fail(FGBD_E_INVALID, "schedule is NULL");
+  if (s->merge_blocks < kGridCapMin || s->merge_blocks > kGridCapMax || s->sweep_blocks < kGridCapMin ||
+      s->sweep_blocks > kGridCapMax)
+    return fail(FGBD_E_INVALID, "merge_blocks and sweep_blocks must be in %d..%d", kGridCapMin, kGridCapMax);
+  if (s->noise_blocks < kGridCapMin || s->noise_blocks > kNoiseGridCapMax)
+    return fail(FGBD_E_INVALID, "noise_blocks must be in %d..%d", kGridCapMin, kNoiseGridCapMax);
+  return FGBD_OK;
+}
+
+fgbd_status fgbd_get_schedule(fgbd_ctx ctx, fgbd_schedule *out) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  if (!out) return fail(FGBD_E_INVALID, "out is NULL");
+  out->merge_blocks = ctx->tune.cap[kGridMerge];
+  out->noise_blocks = ctx->tune.cap[kGridNoise];
+  out->sweep_blocks = ctx->tune.cap[kGridSweep];
+  out->pad_ = 0;
+  return ok();
+}
+
+fgbd_status fgbd_set_schedule(fgbd_ctx ctx, const fgbd_schedule *s) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_schedule(s);
+  if (st != FGBD_OK) return st;
+  ctx->tune.cap[kGridMerge] = s->merge_blocks;
+  ctx->tune.cap[kGridNoise] = s->noise_blocks;
+  ctx->tune.cap[kGridSweep] = s->sweep_blocks;
+  return ok();
+}
+
+fgbd_status fgbd_autotune(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                          const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
+                          fgbd_result *res, int32_t reps, fgbd_schedule *chosen, void *stream) {
+  if (reps < 1 || reps > 100) return fail(FGBD_E_INVALID, "reps must be in 1..100 (got %d)", reps);
+  fgbd_status st = check_batched(ctx, xyz, rgb_in, n_total, offsets, batch, params, rgb_out, res);
+  if (st != FGBD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  // the caller's pending timings go to its counters first; tuning uses its own
+  st = drain(ctx, ctx->ms, ctx->launches);
+  if (st != FGBD_OK) return st;
+  const bool was_profiling = ctx->profile;
+  ctx->profile = true;
+  {  // argument checks of the batched call, and a warm-up
+    double w[FGBD_NUM_KERNELS] = {0};
+    int64_t wl[FGBD_NUM_KERNELS] = {0};
+    st = fgbd_denoise_batched(ctx, xyz, rgb_in, n_total, offsets, batch, params, rgb_out, res, stream);
+    fgbd_status st2 = drain(ctx, w, wl);
+    if (st == FGBD_OK) st = st2;
+    if (st != FGBD_OK) {
+      ctx->profile = was_profiling;
+      return st;
+    }
+  }
+  static const int kMergeCand[] = {256, 512, 1024, 2048, 4096};
+  static const int kNoiseCand[] = {256, 512, 1024};
+  static const int kSweepCand[] = {256, 512, 1024, 2048, 4096};
+  const int *cands[kNumGrids] = {kMergeCand, kNoiseCand, kSweepCand};
+  const int ncand[kNumGrids] = {5, 3, 5};
+  // kernel kinds whose time each grid kind decides
+  const int kinds[kNumGrids][2] = {{kMerge, kWeights}, {kNoise, kNoiseSolve}, {kSweep, kFinalize}};
+  Tune best = ctx->tune;
+  for (int g = 0; g < kNumGrids && st == FGBD_OK; ++g) {
+    double best_ms = 1e300;
+    for (int c = 0; c < ncand[g] && st == FGBD_OK; ++c) {
+      ctx->tune = best;
+      ctx->tune.cap[g] = cands[g][c];
+      double ms[FGBD_NUM_KERNELS] = {0};
+      int64_t nl[FGBD_NUM_KERNELS] = {0};
+      for (int r = 0; r <= reps && st == FGBD_OK; ++r) {  // run 0 warms up
+        st = fgbd_denoise_batched(ctx, xyz, rgb_in, n_total, offsets, batch, params, rgb_out, res, stream);
+        if (st == FGBD_OK && r == 0) {
+          double w[FGBD_NUM_KERNELS] = {0};
+          int64_t wl[FGBD_NUM_KERNELS] = {0};
+          st = drain(ctx, w, wl);
+        }
+      }
+      if (st == FGBD_OK) st = drain(ctx, ms, nl);
+      const double t = ms[kinds[g][0]] + ms[kinds[g][1]];
+      if (st == FGBD_OK && t < best_ms) {
+        best_ms = t;
+        best.cap[g] = cands[g][c];
+      }
+    }
+  }
+  ctx->tune = best;
+  ctx->profile = was_profiling;
+  if (st != FGBD_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (chosen) (void)fgbd_get_schedule(ctx, chosen);
   return ok();
 }
 
@@ -707,16 +827,8 @@ fgbd_status fgbd_profile_read(fgbd_ctx ctx, double *ms, int64_t *launches, int32
   if (!ctx->pending.empty()) {
     DeviceGuard dg(ctx->device);
     if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-    for (auto &r : ctx->pending) {
-      HIP_TRY(hipEventSynchronize(r.b), "hipEventSynchronize");
-      float t = 0.f;
-      HIP_TRY(hipEventElapsedTime(&t, r.a, r.b), "hipEventElapsedTime");
-      ctx->ms[r.kind] += t;
-      ctx->launches[r.kind] += 1;
-      ctx->pool.push_back(r.a);
-      ctx->pool.push_back(r.b);
-    }
-    ctx->pending.clear();
+    fgbd_status st = drain(ctx, ctx->ms, ctx->launches);
+    if (st != FGBD_OK) return st;
   }
   for (int i = 0; i < count; ++i) {
     ms[i] = ctx->ms[i];

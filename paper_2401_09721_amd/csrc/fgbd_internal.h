@@ -293,13 +293,22 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
 constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit codes
 
 constexpr int kBlock = 256;
-constexpr int kMaxGrid = 1024;  // grid of the grid-stride kernels
+constexpr int kMaxGrid = 1024;  // default grid cap of the grid-stride kernels
+constexpr int kGridCapMin = 64;
+constexpr int kGridCapMax = 4096;       // merge and sweep grids
+constexpr int kNoiseGridCapMax = 1024;  // the noise solve reduces at most this many partials per cloud
 constexpr int kSweepParts = 5;  // energy sums per sweep
 constexpr int kSweepSlots = 64;  // atomic slots per cloud and sum (spread to limit contention)
 constexpr int kSweepMaxGrid = 1024;
 constexpr int kScanThreads = 1024;
 
-Plan make_plan(int64_t n_cap, int B, const fgbd_params &p);
+// Largest grid (blocks) of each per-cloud grid kind; chosen by the autotuner.
+struct Tune {
+  int32_t cap[kNumGrids];
+};
+constexpr Tune kDefaultTune = {{kMaxGrid, kMaxGrid, kMaxGrid}};
+
+Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune = kDefaultTune);
 
 // Workspace views of a plan.
 struct Bufs {

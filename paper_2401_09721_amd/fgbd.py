@@ -63,6 +63,17 @@ class Graph(ctypes.Structure):
     ]
 
 
+class Schedule(ctypes.Structure):
+    """fgbd_schedule: largest grids of the per-cloud kernels."""
+
+    _fields_ = [("merge_blocks", ctypes.c_int32), ("noise_blocks", ctypes.c_int32),
+                ("sweep_blocks", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"merge_blocks": self.merge_blocks, "noise_blocks": self.noise_blocks,
+                "sweep_blocks": self.sweep_blocks}
+
+
 RESULT_DTYPE = np.dtype([("sigma_est", "<f8"), ("sigma_g", "<f8"), ("loss", "<f8"), ("q", "<i4"),
                          ("n_fslr", "<i4"), ("n_eff", "<i4"), ("status", "<i4"), ("sweeps", "<i4"), ("m", "<i4")])
 RESULT_BYTES = RESULT_DTYPE.itemsize  # 48
@@ -90,6 +101,11 @@ _SIGNATURES = {
     "fgbd_denoise_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_get_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Schedule)]),
+    "fgbd_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Schedule)]),
+    "fgbd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Schedule), ctypes.c_void_p]),
     "fgbd_poly_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -183,6 +199,30 @@ class Context:
                 raise RuntimeError("torch returned a workspace that is not 256-byte aligned")
             _check(lib().fgbd_set_workspace(self.handle, ctypes.c_void_p(ws.data_ptr()), need))
             self._ws, self._ws_bytes = ws, need
+
+    def schedule(self) -> dict:
+        """The context's launch schedule (largest grid of each per-cloud kernel group)."""
+        sc = Schedule()
+        _check(lib().fgbd_get_schedule(self.handle, ctypes.byref(sc)))
+        return sc.as_dict()
+
+    def set_schedule(self, merge_blocks: int, noise_blocks: int, sweep_blocks: int) -> None:
+        sc = Schedule(int(merge_blocks), int(noise_blocks), int(sweep_blocks), 0)
+        _check(lib().fgbd_set_schedule(self.handle, ctypes.byref(sc)))
+
+    def autotune(self, xyz, rgb, offsets, params=None, reps: int = 3, out=None, res=None) -> dict:
+        """Time candidate launch schedules on this batch (blocking) and keep
+        the fastest in the context.  Returns the chosen schedule."""
+        torch = _torch()
+        prm = as_params(params)
+        xyz, rgb, offsets, batch, n = _batched_args(self, xyz, rgb, offsets)
+        self.reserve(prm, n, max(batch, 1))
+        out = torch.empty_like(rgb) if out is None else out
+        res = new_result(self.device, max(batch, 1)) if res is None else res
+        sc = Schedule()
+        _check(lib().fgbd_autotune(self.handle, _ptr(xyz), _ptr(rgb), n, _ptr(offsets), batch, ctypes.byref(prm),
+                                   _ptr(out), _ptr(res), int(reps), ctypes.byref(sc), _stream(self)))
+        return sc.as_dict()
 
     def profile(self, enable: bool) -> None:
         _check(lib().fgbd_profile_enable(self.handle, 1 if enable else 0))
@@ -351,6 +391,19 @@ def denoise(xyz, rgb, params=None, ctx: Optional[Context] = None, out=None, res=
     return out, res
 
 
+def _batched_args(ctx, xyz, rgb, offsets):
+    torch = _torch()
+    _need(xyz, torch.int32, (3,), "xyz", ctx.device)
+    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64 or offsets.device != ctx.device \
+            or offsets.dim() != 1 or not offsets.is_contiguous():
+        raise ValueError(f"offsets must be a contiguous 1-D int64 tensor on {ctx.device}")
+    n = int(xyz.shape[0])
+    if rgb.shape[0] != n:
+        raise ValueError("xyz and rgb sizes differ")
+    return xyz, rgb, offsets, int(offsets.numel()) - 1, n
+
+
 def denoise_batched(xyz, rgb, offsets, params=None, ctx: Optional[Context] = None, out=None, res=None,
                     stream=None):
     """The per-frame path for B clouds stored back to back (cloud s owns rows
@@ -360,15 +413,7 @@ def denoise_batched(xyz, rgb, offsets, params=None, ctx: Optional[Context] = Non
     torch = _torch()
     prm = as_params(params)
     ctx = ctx or default_context(xyz.device)
-    _need(xyz, torch.int32, (3,), "xyz", ctx.device)
-    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
-    if not isinstance(offsets, torch.Tensor) or offsets.dtype != torch.int64 or offsets.device != ctx.device \
-            or offsets.dim() != 1 or not offsets.is_contiguous():
-        raise ValueError(f"offsets must be a contiguous 1-D int64 tensor on {ctx.device}")
-    n = int(xyz.shape[0])
-    if rgb.shape[0] != n:
-        raise ValueError("xyz and rgb sizes differ")
-    batch = int(offsets.numel()) - 1
+    xyz, rgb, offsets, batch, n = _batched_args(ctx, xyz, rgb, offsets)
     ctx.reserve(prm, n, max(batch, 1))
     out = torch.empty_like(rgb) if out is None else out
     res = new_result(ctx.device, max(batch, 1)) if res is None else res

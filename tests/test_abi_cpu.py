@@ -157,6 +157,39 @@ def test_batched_call_errors(ctx):
     assert lib.fgbd_denoise_batched(ctx, *a) == E
 
 
+def test_schedule_get_set(ctx):
+    lib = fgbd.lib()
+    sc = fgbd.Schedule()
+    assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
+    assert sc.as_dict() == {"merge_blocks": 1024, "noise_blocks": 1024, "sweep_blocks": 1024}
+    new = fgbd.Schedule(2048, 512, 256, 0)
+    assert lib.fgbd_set_schedule(ctx, ctypes.byref(new)) == 0
+    assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
+    assert sc.as_dict() == {"merge_blocks": 2048, "noise_blocks": 512, "sweep_blocks": 256}
+    E = fgbd.FGBD_E_INVALID
+    for bad in [(32, 512, 512), (8192, 512, 512), (512, 2048, 512), (512, 512, 63), (512, 16, 512)]:
+        assert lib.fgbd_set_schedule(ctx, ctypes.byref(fgbd.Schedule(*bad, 0))) == E, bad
+    assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
+    assert sc.as_dict() == {"merge_blocks": 2048, "noise_blocks": 512, "sweep_blocks": 256}
+    assert lib.fgbd_set_schedule(ctx, None) == E
+    assert lib.fgbd_get_schedule(None, ctypes.byref(sc)) == E
+    # the workspace query covers every valid schedule
+    p = fgbd.default_params()
+    assert fgbd.workspace_size(p, 10_000) == fgbd.workspace_size(p, 10_000)
+
+
+def test_autotune_argument_errors(ctx):
+    lib = fgbd.lib()
+    p = fgbd.default_params()
+    far = ctypes.c_void_p(0x900000)
+    E = fgbd.FGBD_E_INVALID
+    for reps in (0, 101):
+        assert lib.fgbd_autotune(ctx, FAKE, FAKE, 10, FAKE, 1, ctypes.byref(p), far, FAKE, reps, None, None) == E
+    assert lib.fgbd_autotune(ctx, FAKE, FAKE, 10, None, 1, ctypes.byref(p), far, FAKE, 3, None, None) == E
+    assert lib.fgbd_autotune(ctx, FAKE, FAKE, 10, FAKE, 0, ctypes.byref(p), far, FAKE, 3, None, None) == E
+    assert lib.fgbd_autotune(None, FAKE, FAKE, 10, FAKE, 1, ctypes.byref(p), far, FAKE, 3, None, None) == E
+
+
 def test_workspace_setting(ctx):
     lib = fgbd.lib()
     assert lib.fgbd_set_workspace(ctx, ctypes.c_void_p(0x1001), 100) == fgbd.FGBD_E_INVALID

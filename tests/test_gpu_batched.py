@@ -130,6 +130,31 @@ def test_batched_deterministic_repeat():
     assert np.array_equal(a, b) and ra == rb
 
 
+def test_autotuned_schedule_keeps_parity():
+    """The autotuner picks a valid schedule, keeps it in the context, and the
+    batched call under it still matches the oracle cloud by cloud."""
+    prm = fgbd.default_params(bits=8)
+    clouds = [shape_cloud(91, 14000), small_cloud(700, 7), shape_cloud(92, 6000, sigma=12.0)]
+    xyz = np.concatenate([c[0] for c in clouds])
+    rgb = np.concatenate([c[1] for c in clouds])
+    offsets = np.concatenate([[0], np.cumsum([len(c[0]) for c in clouds])]).astype(np.int64)
+    ctx = fgbd.Context("cuda")
+    ctx.profile(True)
+    sched = ctx.autotune(dev(xyz, torch.int32), dev(rgb, torch.float32), dev(offsets, torch.int64), prm, reps=1)
+    assert ctx.schedule() == sched
+    assert sched["merge_blocks"] in (256, 512, 1024, 2048, 4096)
+    assert sched["noise_blocks"] in (256, 512, 1024)
+    assert sched["sweep_blocks"] in (256, 512, 1024, 2048, 4096)
+    assert all(v == (0.0, 0) for v in ctx.profile_read().values())  # tuning runs are not the caller's
+    ctx.profile(False)
+    out, results, _ = run_batched(clouds, prm, ctx=ctx)
+    check_each(clouds, out, results, offsets, prm)
+    ctx.set_schedule(256, 256, 256)
+    out2, results2, _ = run_batched(clouds, prm, ctx=ctx)
+    check_each(clouds, out2, results2, offsets, prm)
+    ctx.close()
+
+
 def test_graph_captured_stream_of_frames():
     """One capture of the batched call (one cloud, capacity 20000) replayed on
     frames of different sizes copied into the same buffers: every replay equals
