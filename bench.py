@@ -302,6 +302,8 @@ def main() -> int:
     ap.add_argument("--points", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel profiled pass")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library's autotuner pick the launch schedule of the headline frame first")
     ap.add_argument("--no-patterns", action="store_true",
                     help="skip the batched, streaming and forward+backward measurements")
     ap.add_argument("--stream-frames", type=int, default=30)
@@ -345,6 +347,12 @@ def main() -> int:
     for _ in range(args.warmup):
         fgbd.denoise(xyz, rgb, prm, ctx=ctx, out=out, res=res)
     torch.cuda.synchronize()
+    if args.autotune:  # the library's own tuner picks the launch schedule for this frame
+        one = torch.tensor([0, n], dtype=torch.int64, device=dev)
+        ctx.autotune(xyz, rgb, one, prm, reps=3, out=out, res=res)
+        for _ in range(args.warmup):
+            fgbd.denoise(xyz, rgb, prm, ctx=ctx, out=out, res=res)
+        torch.cuda.synchronize()
     print(f"# warmup done ({args.warmup} steps), n={n}, generation {gen_s:.1f}s", file=sys.stderr, flush=True)
 
     # ---- timed region (headline): K steps, no per-kernel events
@@ -384,6 +392,7 @@ def main() -> int:
             "fslr_kappa": prm.fslr_kappa,
         },
         "frames_per_s": 1e3 / ms_step,
+        "schedule": ctx.schedule(),
         "result": {k: r[k] for k in ("sigma_est", "sigma_g", "q", "sweeps", "n_fslr", "n_eff", "m")},
     }
 
@@ -407,39 +416,52 @@ def main() -> int:
                              "algo_GBs": (b / (per_launch / 1e3) / 1e9) if b else None}
         line["kernels"] = kernels
         line["profiled_ms_per_step"] = sum(v["ms_per_step"] for v in kernels.values())
+        # Bytes each kind moves per step: its algorithmic bytes per launch for
+        # every launch that computes; of the sweep launches only r["sweeps"]
+        # compute (the later ones return after reading the stopped selection).
+        def step_bytes(kind):
+            b = algorithmic_bytes(kind, n, prm.num_dirs, prm.k, P)
+            if kind == "sweep":
+                return b * r["sweeps"]
+            return b * kernels[kind]["launches_per_step"]
+
         dom = max((k for k in kernels if algorithmic_bytes(k, n, prm.num_dirs, prm.k, P) > 0),
                   key=lambda k: kernels[k]["ms_per_step"])
-        gbs = kernels[dom]["algo_GBs"]
+        gbs = step_bytes(dom) / (kernels[dom]["ms_per_step"] / 1e3) / 1e9
         tcfg = {"n_points": n, "num_dirs": prm.num_dirs, "window": prm.window, "k": prm.k, "patch": P,
                 "sigma": args.sigma}
         line["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom, tcfg),
-                            "bytes_per_launch": algorithmic_bytes(dom, n, prm.num_dirs, prm.k, P),
-                            "us_per_launch": kernels[dom]["us_per_launch"]}
+                            "bytes_per_step": step_bytes(dom), "ms_per_step": kernels[dom]["ms_per_step"],
+                            "launches_per_step": kernels[dom]["launches_per_step"],
+                            "timing": "HIP events around each launch on the library's stream"}
         print(f"# kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
-        # Active sweeps alone (the filter at a fixed q: every launch computes a
-        # sweep), the kernel the bandwidth target is set on.
+        # Active sweeps alone, the kernel the bandwidth target is set on: the
+        # filter at a fixed q computes a sweep in every launch; one event pair
+        # around q = 32 and one around q = 0 (same setup and final copy), so
+        # the difference is 32 sweeps with no per-launch event in between.
         g = fgbd.build_slg(xyz, prm, ctx=ctx)
-        qf = 8
+        qf = 32
         fgbd.filter(g, rgb, prm, q_fixed=qf, ctx=ctx)
         torch.cuda.synchronize()
-        ctx.profile(True)
-        ctx.profile_read()
-        for _ in range(args.steps):
-            fgbd.filter(g, rgb, prm, q_fixed=qf, ctx=ctx)
-        torch.cuda.synchronize()
-        sp = ctx.profile_read()
-        ctx.profile(False)
-        ms, launches = sp["sweep"]
-        per_launch = ms / launches
+        times = {}
+        for q in (qf, 0):
+            e0, e1 = _events(torch)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fgbd.filter(g, rgb, prm, q_fixed=q, ctx=ctx)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times[q] = e0.elapsed_time(e1) / args.steps
+        per_launch = (times[qf] - times[0]) / qf
         b = algorithmic_bytes("sweep", n, prm.num_dirs, prm.k, P)
         line["roofline_sweep"] = {"kernel": "sweep (fixed q, every launch active)", "bound": "hbm",
                                   "achieved": b / (per_launch / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": b / (per_launch / 1e3) / 1e9 / HBM_PEAK_GBS,
                                   "traffic": measured_traffic("sweep", tcfg),
                                   "bytes_per_launch": b, "us_per_launch": 1e3 * per_launch,
-                                  "launches": launches}
+                                  "timing": f"(filter at q={qf} - filter at q=0) / {qf}, one event pair each"}
 
     if not args.no_patterns:
         line["batched"] = bench_batched(inputs["batch"], prm, dev, args, fgbd, torch)

@@ -23,6 +23,7 @@ FGBD_E_WORKSPACE = -4
 FGBD_E_UNSUPPORTED = -5
 FGBD_ST_COORD_RANGE = 1
 FGBD_ST_NO_PATCH = 2
+FGBD_ST_BAD_OFFSETS = 4
 NUM_KERNELS = 9
 ABI_VERSION = 2
 MAX_BATCH = 64

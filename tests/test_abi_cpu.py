@@ -30,6 +30,17 @@ def test_library_exports_every_declared_function():
     assert set(names) == set(fgbd._SIGNATURES)
 
 
+def test_status_constants_match_header():
+    text = open(HEADER).read()
+    defines = dict(re.findall(r"#define (FGBD_ST_[A-Z_]+) (\d+)", text))
+    enums = dict(re.findall(r"(FGBD_(?:OK|E_[A-Z]+)) = (-?\d+)", text))
+    assert len(defines) >= 3 and len(enums) >= 6
+    for name, val in {**defines, **enums}.items():
+        assert getattr(fgbd, name) == int(val), name
+    assert fgbd.MAX_BATCH == int(re.search(r"#define FGBD_MAX_BATCH (\d+)", text).group(1))
+    assert fgbd.NUM_KERNELS == int(re.search(r"#define FGBD_NUM_KERNELS (\d+)", text).group(1))
+
+
 def test_version_and_defaults():
     assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 2
     p = fgbd.default_params()
