@@ -95,6 +95,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   Plan pl;
   memset(&pl, 0, sizeof(pl));
   pl.n_cap = n_cap;
+  pl.stride = ((n_cap > 0 ? n_cap : 1) + 63) / 64 * 64;  // keeps every direction's items 512-byte aligned
   pl.B = B;
   pl.L = p.num_dirs;
   pl.K = p.k;
@@ -121,11 +122,11 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
     return o;
   };
   pl.off_segs = take(sizeof(Segs));
-  pl.off_items_a = take((size_t)pl.L * N * 8);
-  pl.off_items_b = take((size_t)pl.L * N * 8);
+  pl.off_items_a = take((size_t)pl.L * pl.stride * 8);
+  pl.off_items_b = take((size_t)pl.L * pl.stride * 8);
   pl.off_hist = take((size_t)pl.L * pl.ntiles_cap * 256 * 4);
   pl.off_totals = take((size_t)pl.L * kSortPasses * B * 256 * 4);
-  pl.off_rank = take((size_t)pl.L * N * 4);
+  pl.off_rank = take((size_t)pl.L * pl.stride * 4);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
   pl.off_p = take(N * pl.K * 4);

@@ -174,14 +174,10 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
             const uint32_t d2 = code_dist2(ci, (uint32_t)(cur[s] >> 32), dc);
             // an empty window slot (all ones) yields the sentinel key
             const uint32_t kc = cur[s] == ~0ull ? ~0u : (((d2 < 255u ? d2 : 255u) << 24) | (uint32_t)cur[s]);
-            if (KM == 8 && WT > 0) {
-              if (K == 8)
-                topk_insert_fixed<8>(reinterpret_cast<uint32_t(&)[8]>(key), kc);
-              else
-                topk_insert_t<KM, uint32_t>(key, K, kc);
-            } else {
+            if (KM == 8 && K == 8)
+              topk_insert_fixed<8>(reinterpret_cast<uint32_t(&)[8]>(key), kc);
+            else
               topk_insert_t<KM, uint32_t>(key, K, kc);
-            }
           }
         }
 #pragma unroll
@@ -311,7 +307,7 @@ hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int3
   MergeArgs a;
   a.dt = r.dt;
   a.sa = r.sa;
-  a.stride = r.pl.n_cap;
+  a.stride = r.pl.stride;
   a.window = r.prm.window;
   a.K = r.prm.k;
   const int k = r.prm.k, window = r.prm.window;

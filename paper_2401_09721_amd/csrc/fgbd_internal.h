@@ -277,6 +277,7 @@ struct SweepCtrl {
 // sized from the capacity; kernels take the actual sizes from SegArgs.
 struct Plan {
   int64_t n_cap;
+  int64_t stride;            // per-direction length of the sort items and ranks (n_cap rounded up to 64)
   int32_t B, L, K, P, D, TP;
   int32_t ntiles_cap;        // radix tiles: ceil(n_cap / tile) + B - 1
   int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)

@@ -19,8 +19,8 @@
 // Every block works on one cloud and writes its partial sums; k_noise_solve
 // (one block per cloud) reduces its cloud's partials in block order, forms
 //   Sigma = (S2 - sum_c s1_c s1_c^T / N) / (3 N),
-// finds its eigenvalues with a parallel cyclic Jacobi method (round-robin
-// pair ordering, FP64), and applies the tail rule: the smallest m with
+// finds its eigenvalues (FP64: Householder tridiagonalisation, then Sturm
+// multisection), and applies the tail rule: the smallest m with
 // mean(lambda_{m+1..D}) <= median(lambda_{m+1..D}); sigma_est = sqrt(mean).
 #include "fgbd_internal.h"
 
@@ -81,76 +81,128 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Parallel cyclic Jacobi on a symmetric Dp x Dp matrix in LDS (Dp even), run
-// by one wave.  Round-robin pairing applies Dp/2 disjoint rotations at once.
-// An entry already negligible (|a_pq| <= 1e-15 |A|_F, or against its diagonal
-// pair) is set to zero instead of rotated; the sweeps stop when a whole sweep
-// needed no rotation (at most 64 sweeps).  Eigenvalues are then accurate to
-// about 1e-15 |A|_F.
-__device__ void jacobi_eigs_wave(double *A, int Dp, double *s_c, double *s_s, int *s_p, int *s_q, int *s_flag) {
-  const int t = (int)lane_id();
-  const int half = Dp / 2;
-  // Frobenius norm (invariant under the rotations): entries below eps * |A|
-  // are rounding residue and are not rotated
-  double f = 0.0;
-  for (int w = t; w < Dp * Dp; w += kWave) f += A[w] * A[w];
+// Sum over the wave (every lane receives the total; fixed xor tree).
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o, kWave);
-  const double tiny = 1e-15 * sqrt(f);
-  for (int sweep = 0; sweep < 64; ++sweep) {
-    if (t == 0) *s_flag = 0;
-    wave_lds_sync();
-    for (int round = 0; round < Dp - 1; ++round) {
-      if (t < half) {
-        auto pos = [&](int k) { return k == 0 ? 0 : 1 + ((k - 1 + round) % (Dp - 1)); };
-        int p = pos(t), q = pos(Dp - 1 - t);
-        if (p > q) { int tmp = p; p = q; q = tmp; }
-        const double apq = A[p * Dp + q];
-        const double app = A[p * Dp + p], aqq = A[q * Dp + q];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > tiny && fabs(apq) > 1e-16 * sqrt(fabs(app * aqq))) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-          *s_flag = 1;
-        }
-        s_p[t] = p;
-        s_q[t] = q;
-        s_c[t] = c;
-        s_s[t] = s;
-      }
-      wave_lds_sync();
-      for (int w = t; w < half * Dp; w += kWave) {  // A := A J (columns p, q)
-        const int pr = w / Dp, k = w % Dp;
-        if (s_s[pr] == 0.0) continue;
-        const int p = s_p[pr], q = s_q[pr];
-        const double c = s_c[pr], s = s_s[pr];
-        const double akp = A[k * Dp + p], akq = A[k * Dp + q];
-        A[k * Dp + p] = c * akp - s * akq;
-        A[k * Dp + q] = s * akp + c * akq;
-      }
-      wave_lds_sync();
-      for (int w = t; w < half * Dp; w += kWave) {  // A := J^T A (rows p, q)
-        const int pr = w / Dp, k = w % Dp;
-        if (s_s[pr] == 0.0) continue;
-        const int p = s_p[pr], q = s_q[pr];
-        const double c = s_c[pr], s = s_s[pr];
-        const double apk = A[p * Dp + k], aqk = A[q * Dp + k];
-        A[p * Dp + k] = c * apk - s * aqk;
-        A[q * Dp + k] = s * apk + c * aqk;
-      }
-      wave_lds_sync();
-      if (t < half) {  // the rotation annihilates the pair entry; drop its rounding residue
-        A[s_p[t] * Dp + s_q[t]] = 0.0;
-        A[s_q[t] * Dp + s_p[t]] = 0.0;
-      }
-      wave_lds_sync();
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Eigenvalues of the symmetric D x D matrix in LDS (row stride ld), by one
+// wave, in two stages:
+//  1. Householder reduction to tridiagonal form (A is overwritten): at step
+//     k the column below the diagonal, x, is mapped onto alpha e_1 with
+//     H = I - beta v v^T, v = x - alpha e_1, alpha = -sign(x_1)|x|, and the
+//     trailing block is updated as A' - v q^T - q v^T with p = beta A' v,
+//     q = p - (beta/2)(v^T p) v (lanes own rows or entries; LDS vectors).
+//  2. Sturm-sequence multisection of the tridiagonal matrix (d, e): the count
+//     of eigenvalues below x follows from the signs of the pivots
+//     q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1}; each eigenvalue gets
+//     G = 64 / D lanes that evaluate the count at G interior points of its
+//     bracket per step, a fixed number of steps (enough for 56 bits), starting
+//     from the Gershgorin interval.
+// lam receives the eigenvalues in descending order.  Accurate to a few ulps
+// of the matrix norm, like any backward-stable symmetric eigen-solver.
+__device__ void eig_sym_wave(double *A, int D, int ld, double *s_v, double *s_p, double *s_d, double *s_e,
+                             double *s_x, int *s_c, double *lam) {
+  const int t = (int)lane_id();
+  for (int k = 0; k + 2 < D; ++k) {
+    const int m = D - k - 1;
+    double *Ab = A + (size_t)(k + 1) * ld + (k + 1);  // trailing block
+    const double xi = t < m ? A[(size_t)(k + 1 + t) * ld + k] : 0.0;
+    const double ss = wave_sum(xi * xi);
+    const double x0 = __shfl(xi, 0, kWave);
+    const double alpha = ss > 0.0 ? -copysign(sqrt(ss), x0) : 0.0;
+    const double vn2 = 2.0 * (ss - x0 * alpha);  // |x - alpha e_1|^2
+    if (t == 0) {
+      s_d[k] = A[(size_t)k * ld + k];
+      s_e[k] = alpha;
     }
-    const int any = *s_flag;
+    if (!(vn2 > 0.0)) continue;  // uniform: x = 0, nothing to reflect
+    const double beta = 2.0 / vn2;
+    const double vi = t < m ? (t == 0 ? xi - alpha : xi) : 0.0;
+    if (t < m) s_v[t] = vi;
     wave_lds_sync();
-    if (any == 0) break;
+    double pi = 0.0;
+    if (t < m) {
+      for (int j = 0; j < m; ++j) pi += Ab[(size_t)t * ld + j] * s_v[j];
+      pi *= beta;
+    }
+    const double kk = 0.5 * beta * wave_sum(vi * pi);
+    if (t < m) s_p[t] = pi - kk * vi;
+    wave_lds_sync();
+    for (int w = t; w < m * m; w += kWave) {
+      const int i = w / m, j = w % m;
+      Ab[(size_t)i * ld + j] -= s_v[i] * s_p[j] + s_p[i] * s_v[j];
+    }
+    wave_lds_sync();
   }
+  if (t == 0) {
+    if (D >= 2) {
+      s_d[D - 2] = A[(size_t)(D - 2) * ld + (D - 2)];
+      s_e[D - 2] = A[(size_t)(D - 1) * ld + (D - 2)];
+    }
+    s_d[D - 1] = A[(size_t)(D - 1) * ld + (D - 1)];
+  }
+  wave_lds_sync();
+
+  // Gershgorin interval and the pivot guard
+  double glo = 1e300, ghi = -1e300, emax = 0.0;
+  for (int i = t; i < D; i += kWave) {
+    const double r = (i > 0 ? fabs(s_e[i - 1]) : 0.0) + (i + 1 < D ? fabs(s_e[i]) : 0.0);
+    glo = fmin(glo, s_d[i] - r);
+    ghi = fmax(ghi, s_d[i] + r);
+    if (i + 1 < D) emax = fmax(emax, s_e[i] * s_e[i]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    glo = fmin(glo, __shfl_xor(glo, o, kWave));
+    ghi = fmax(ghi, __shfl_xor(ghi, o, kWave));
+    emax = fmax(emax, __shfl_xor(emax, o, kWave));
+  }
+  const double nrm = fmax(fabs(glo), fabs(ghi));
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax) * 4.0;
+  glo -= 4.0 * 2.220446049250313e-16 * nrm + pivmin;
+  ghi += 4.0 * 2.220446049250313e-16 * nrm + pivmin;
+
+  const int G = D < kWave ? kWave / D : 1;  // lanes per eigenvalue
+  const int ev = t / G, sub = t % G;         // eigenvalue (ascending) and point of this lane
+  const bool active = ev < D;
+  double lo = glo, hi = ghi;
+  int bits_per_step = 0;
+  for (int g = G + 1; g > 1; g >>= 1) ++bits_per_step;  // floor(log2(G + 1)) >= 1
+  const int steps = (56 + bits_per_step - 1) / bits_per_step;
+  for (int it = 0; it < steps; ++it) {
+    const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(G + 1);
+    int cnt = 0;
+    if (active) {
+      double q = s_d[0] - x;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt = q < 0.0;
+      for (int i = 1; i < D; ++i) {
+        q = s_d[i] - x - s_e[i - 1] * s_e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
+      }
+    }
+    s_x[t] = x;
+    s_c[t] = cnt;
+    wave_lds_sync();
+    if (active) {  // the group's new bracket: count(lo) <= ev < count(hi)
+      double nlo = lo, nhi = hi;
+      for (int j = 0; j < G; ++j) {
+        const double xj = s_x[ev * G + j];
+        const int cj = s_c[ev * G + j];
+        if (cj <= ev) nlo = fmax(nlo, xj);
+        else nhi = fmin(nhi, xj);
+      }
+      lo = nlo;
+      hi = nhi;
+    }
+    wave_lds_sync();
+  }
+  if (active && sub == 0) lam[D - 1 - ev] = 0.5 * (lo + hi);
+  wave_lds_sync();
 }
 
 // Per-point work of one tile slot: gather the patch into three LDS rows,
@@ -386,17 +438,17 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
 }
 
 // One block: sum the k_noise partials in block order, form Sigma, find its
-// eigenvalues (parallel Jacobi, FP64) and apply the tail rule.
+// eigenvalues (FP64) and apply the tail rule.
 constexpr int kSolveThreads = 1024;
 
 // One block per cloud: sum the cloud's k_noise partials (one wave per entry
 // row, lanes stride the blocks, fixed shuffle tree), form Sigma, then wave 0
-// alone finds its eigenvalues (Jacobi, FP64) and applies the tail rule.
+// alone finds its eigenvalues and applies the tail rule.
 __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, const double *__restrict__ part, int nb,
                                                                fgbd_result *__restrict__ res_all) {
   __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
-  __shared__ double s_jc[kMaxD], s_js[kMaxD];
-  __shared__ int s_jp[kMaxD], s_jq[kMaxD], s_flag;
+  __shared__ double s_v[kMaxD], s_p[kMaxD], s_d[kMaxD], s_e[kMaxD], s_x[kWave];
+  __shared__ int s_c[kWave];
   __shared__ double s_lam[kMaxD + 1];
   const int t = threadIdx.x;
   const int lane = (int)lane_id();
@@ -447,32 +499,29 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, cons
   }
   __syncthreads();
   if (wave != 0) return;  // no block barrier follows
-  if (n_eff > 0.0) jacobi_eigs_wave(A, Dp, s_jc, s_js, s_jp, s_jq, &s_flag);
-  if (t == 0) {
-    double sigma = 0.0;
-    int m_star = 0;
-    if (n_eff > 0.0) {
-      double *lam = s_lam;  // LDS, not a private array (would live in scratch)
-      for (int k = 0; k < D; ++k) lam[k] = A[k * Dp + k];
-      for (int k = 1; k < D; ++k) {  // descending insertion sort
-        const double v = lam[k];
-        int j = k - 1;
-        while (j >= 0 && lam[j] < v) { lam[j + 1] = lam[j]; --j; }
-        lam[j + 1] = v;
-      }
-      for (int m = 0; m < D; ++m) {
-        const int cntm = D - m;
-        double s = 0.0;
-        for (int k = m; k < D; ++k) s += lam[k];
-        const double tau = s / (double)cntm;
-        const double med = (cntm & 1) ? lam[m + cntm / 2] : 0.5 * (lam[m + cntm / 2 - 1] + lam[m + cntm / 2]);
-        if (tau <= med) {
-          sigma = sqrt(tau > 0.0 ? tau : 0.0);
-          m_star = m;
-          break;
-        }
-      }
+  double sigma = 0.0;
+  int m_star = 0;
+  if (n_eff > 0.0) {  // uniform over the wave
+    eig_sym_wave(A, D, Dp, s_v, s_p, s_d, s_e, s_x, s_c, s_lam);
+    // tail rule, every m at once (lane m): the smallest m whose tail mean is
+    // not above the tail median
+    const double *lam = s_lam;
+    bool ok = false;
+    double tau = 0.0;
+    if (lane < D) {
+      const int m = lane, cntm = D - m;
+      double sm = 0.0;
+      for (int k = m; k < D; ++k) sm += lam[k];
+      tau = sm / (double)cntm;
+      const double med = (cntm & 1) ? lam[m + cntm / 2] : 0.5 * (lam[m + cntm / 2 - 1] + lam[m + cntm / 2]);
+      ok = tau <= med;
     }
+    const uint64_t hits = __builtin_amdgcn_ballot_w64(ok);  // bit D-1 is always set
+    m_star = hits ? (int)__builtin_ctzll(hits) : D - 1;
+    const double tau_star = __shfl(tau, m_star, kWave);
+    sigma = sqrt(tau_star > 0.0 ? tau_star : 0.0);
+  }
+  if (lane == 0) {
     res->sigma_est = sigma;
     res->n_eff = (int32_t)n_eff;
     res->m = m_star;

@@ -281,7 +281,7 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
   SortArgs a;
   a.dt = r.dt;
   a.sa = r.sa;
-  a.stride = r.pl.n_cap;
+  a.stride = r.pl.stride;
   a.ntiles_cap = r.pl.ntiles_cap;
   const int ntiles = r.sa.n_fixed >= 0 ? (r.sa.n_fixed + kSortTile - 1) / kSortTile : r.pl.ntiles_cap;
   const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
