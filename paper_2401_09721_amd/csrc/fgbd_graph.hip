@@ -43,11 +43,13 @@ __device__ __forceinline__ DirConst dir_const(const DirInfo &di, int bits) {
   c.um = di.um;
   return c;
 }
+// Every factor is below 2^13 in magnitude (b <= 10, |u| <= 2), so the
+// products use the full-rate 24-bit multiplier.
 __device__ __forceinline__ uint32_t code_dist2(uint32_t ci, uint32_t cj, const DirConst &c) {
   const int da = (int)(cj & c.top) - (int)(ci & c.top);
-  const int dm = (int)((cj >> c.bits) & c.mmask) - (int)((ci >> c.bits) & c.mmask) + c.um * da;
-  const int dh = (int)(cj >> c.hshift) - (int)(ci >> c.hshift) + c.uh * da;
-  return (uint32_t)(da * da) + (uint32_t)(dm * dm) + (uint32_t)(dh * dh);
+  const int dm = (int)((cj >> c.bits) & c.mmask) - (int)((ci >> c.bits) & c.mmask) + __mul24(c.um, da);
+  const int dh = (int)(cj >> c.hshift) - (int)(ci >> c.hshift) + __mul24(c.uh, da);
+  return (uint32_t)__mul24(da, da) + (uint32_t)__mul24(dm, dm) + (uint32_t)__mul24(dh, dh);
 }
 
 template <int KM, typename Key>
@@ -67,18 +69,22 @@ __device__ __forceinline__ void topk_insert_t(Key (&lst)[KM], int K, Key c) {
   lst[0] = lst[0] > c ? c : lst[0];
 }
 
-// Branch-free insertion for a compile-time list length K: a candidate that is
-// already present or not below the current K-th key becomes the all-ones
-// sentinel, which the insertion network leaves without effect.
-template <int K>
-__device__ __forceinline__ void topk_insert_fixed(uint32_t (&lst)[K], uint32_t c) {
-  bool drop = c >= lst[K - 1];
+// Branch-free insertion into a sorted list of KM distinct keys (all-ones =
+// empty): the candidate is carried down the list, each slot keeping the
+// smaller of (slot, carried) and passing the larger on, and the largest falls
+// off the end.  A candidate equal to a slot is turned into the all-ones
+// sentinel when it meets that slot (earlier slots are smaller, so it meets it
+// before any swap), which leaves the list unchanged.  The first K slots are
+// then the K smallest distinct keys for any K <= KM.
+template <int KM>
+__device__ __forceinline__ void topk_insert_minmax(uint32_t (&lst)[KM], uint32_t c) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) drop |= lst[k] == c;
-  c = drop ? ~0u : c;
-#pragma unroll
-  for (int k = K - 1; k > 0; --k) lst[k] = lst[k - 1] > c ? lst[k - 1] : (lst[k] > c ? c : lst[k]);
-  lst[0] = lst[0] > c ? c : lst[0];
+  for (int k = 0; k < KM; ++k) {
+    c = lst[k] == c ? ~0u : c;
+    const uint32_t lo = min(lst[k], c), hi = max(lst[k], c);
+    lst[k] = lo;
+    c = hi;
+  }
 }
 
 // Window items r-WT..r+WT; positions outside lo..hi load a clamped position
@@ -174,10 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
             const uint32_t d2 = code_dist2(ci, (uint32_t)(cur[s] >> 32), dc);
             // an empty window slot (all ones) yields the sentinel key
             const uint32_t kc = cur[s] == ~0ull ? ~0u : (((d2 < 255u ? d2 : 255u) << 24) | (uint32_t)cur[s]);
-            if (KM == 8 && K == 8)
-              topk_insert_fixed<8>(reinterpret_cast<uint32_t(&)[8]>(key), kc);
-            else
-              topk_insert_t<KM, uint32_t>(key, K, kc);
+            topk_insert_minmax<KM>(key, kc);
           }
         }
 #pragma unroll
