@@ -124,8 +124,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_segs = take(sizeof(Segs));
   pl.off_items_a = take((size_t)pl.L * pl.stride * 8);
   pl.off_items_b = take((size_t)pl.L * pl.stride * 8);
-  pl.off_hist = take((size_t)pl.L * pl.ntiles_cap * 256 * 4);
-  pl.off_totals = take((size_t)pl.L * kSortPasses * B * 256 * 4);
+  pl.off_hist = take((size_t)pl.L * (pl.ntiles_cap + 1) * 256 * 4);
   pl.off_rank = take((size_t)pl.L * pl.stride * 4);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
@@ -146,7 +145,6 @@ Bufs carve(char *ws, const Plan &pl) {
   b.items_a = (uint64_t *)(ws + pl.off_items_a);
   b.items_b = (uint64_t *)(ws + pl.off_items_b);
   b.hist = (uint32_t *)(ws + pl.off_hist);
-  b.totals = (uint32_t *)(ws + pl.off_totals);
   b.rank = (uint32_t *)(ws + pl.off_rank);
   b.col = (int32_t *)(ws + pl.off_col);
   b.dist2 = (int32_t *)(ws + pl.off_dist2);
@@ -169,21 +167,19 @@ struct SetupArgs {
   int32_t B;
   int32_t grid[kNumGrids];
   int32_t zero_result;
-  int32_t tot_count;   // digit totals to clear (uint32)
   int32_t sums_count;  // first sweep's sums to clear (uint64)
 };
 
-// All blocks clear the accumulators; block 0 builds the segment table:
+// All blocks clear the first sweep's sums; block 0 builds the segment table:
 // offsets clamped into a valid form (start[0] = 0, non-decreasing, at most
 // n_cap), radix tiles per cloud, and each per-cloud grid's block ranges
 // first(s) = floor(start[s] (G - B) / n) + s (at least one block per cloud).
-__global__ __launch_bounds__(256) void k_setup(SetupArgs a, Segs *__restrict__ sg, uint32_t *__restrict__ totals,
+__global__ __launch_bounds__(256) void k_setup(SetupArgs a, Segs *__restrict__ sg,
                                                unsigned long long *__restrict__ sums1, fgbd_result *__restrict__ res) {
   __shared__ int64_t s_raw[kMaxSeg + 1];
   __shared__ int32_t s_start[kMaxSeg + 1], s_tf[kMaxSeg + 1];
   __shared__ int32_t s_bad;
   const int t = threadIdx.x;
-  for (int i = blockIdx.x * blockDim.x + t; i < a.tot_count; i += gridDim.x * blockDim.x) totals[i] = 0u;
   for (int i = blockIdx.x * blockDim.x + t; i < a.sums_count; i += gridDim.x * blockDim.x) sums1[i] = 0ull;
   if (blockIdx.x != 0) return;  // uniform over the block
   const int B = a.B;
@@ -246,13 +242,11 @@ hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fg
   a.B = r.pl.B;
   for (int g = 0; g < kNumGrids; ++g) a.grid[g] = r.pl.grid[g];
   a.zero_result = zero_result;
-  a.tot_count = r.pl.L * kSortPasses * r.pl.B * 256;
   a.sums_count = r.pl.B * kSweepSlots * kSweepParts;
-  const int work = a.tot_count > a.sums_count ? a.tot_count : a.sums_count;
-  int blocks = (work + 256 * 8 - 1) / (256 * 8);
+  int blocks = (a.sums_count + 256 * 8 - 1) / (256 * 8);
   blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
   // the first sweep adds into sums buffer 1 (see launch_sweep)
-  k_setup<<<blocks, 256, 0, r.stream>>>(a, r.b.segs, r.b.totals, r.b.sums + (size_t)a.sums_count, res);
+  k_setup<<<blocks, 256, 0, r.stream>>>(a, r.b.segs, r.b.sums + (size_t)a.sums_count, res);
   return hipGetLastError();
 }
 

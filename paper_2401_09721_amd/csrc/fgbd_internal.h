@@ -282,7 +282,7 @@ struct Plan {
   int32_t ntiles_cap;        // radix tiles: ceil(n_cap / tile) + B - 1
   int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)
   int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
-  size_t off_segs, off_items_a, off_items_b, off_hist, off_totals, off_rank;
+  size_t off_segs, off_items_a, off_items_b, off_hist, off_rank;
   size_t off_col, off_dist2, off_p, off_spread, off_xbuf;
   size_t off_merge_part, off_noise_part, off_ctrl, off_sweep_sums;
   size_t total;
@@ -315,8 +315,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune = kD
 struct Bufs {
   Segs *segs;
   uint64_t *items_a, *items_b;  // [L][n_cap]
-  uint32_t *hist;               // [L][256][ntiles_cap]
-  uint32_t *totals;             // [L][passes][B][256]
+  uint32_t *hist;               // [L][256][ntiles_cap + 1]
   uint32_t *rank;               // [L][n_cap]
   int32_t *col, *dist2;         // [n_cap][K]
   float *p;                     // [n_cap][K]
@@ -360,8 +359,7 @@ struct Run {
 };
 
 // Segment table from device offsets (B+1 entries) or, with offsets == NULL,
-// one cloud of n_host points; clears the digit totals and the first sweep's
-// sums.  zero_result: 0 leave res, 1 zero res[0..B-1], 2 zero and flag
+// one cloud of n_host points; clears the first sweep's sums.  zero_result: 0 leave res, 1 zero res[0..B-1], 2 zero and flag
 // FGBD_ST_NO_PATCH.
 hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result);
 

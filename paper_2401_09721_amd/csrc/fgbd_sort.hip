@@ -15,11 +15,11 @@
 // search uses to find each point's place in every order.
 //
 // Several clouds are sorted in the same launches, each inside its own range
-// of positions: tiles never straddle two clouds, pass 0 counts every pass's
-// digits per cloud, the scan runs over all tiles of a row, and each tile's
-// output offset for digit c is
-//   start[s] + (digits < c in cloud s) + (prefix at this tile - prefix at the
-//   cloud's first tile).
+// of positions: tiles never straddle two clouds, the scan runs over all tiles
+// of a row and also stores the row total after the last tile, and with P the
+// scanned row of digit c, the cloud's count of c is P[next cloud's first
+// tile] - P[its first tile], so each tile's output offset for digit c is
+//   start[s] + (digits < c in cloud s) + (P[this tile] - P[cloud's first tile]).
 #include "fgbd_internal.h"
 
 namespace fgbd {
@@ -30,7 +30,7 @@ struct SortArgs {
   DirTable dt;
   SegArgs sa;
   int64_t stride;     // items per direction (capacity)
-  int32_t ntiles_cap; // hist row length
+  int32_t row;        // hist row length (tile capacity + 1: the row total)
   int32_t shift;      // digit shift of this pass
   int32_t pass;
 };
@@ -40,6 +40,7 @@ struct TileInfo {
   int s;
   int begin, end;  // points of the tile
   int first;       // first tile of the cloud
+  int next_first;  // first tile of the next cloud (= tile count after the last)
   int seg_start;   // first point of the cloud
 };
 __device__ __forceinline__ bool tile_info(const SortArgs &a, int tile, TileInfo &ti) {
@@ -48,6 +49,7 @@ __device__ __forceinline__ bool tile_info(const SortArgs &a, int tile, TileInfo 
     if (tile * kSortTile >= n) return false;
     ti.s = 0;
     ti.first = 0;
+    ti.next_first = (n + kSortTile - 1) / kSortTile;
     ti.seg_start = 0;
     ti.begin = tile * kSortTile;
     ti.end = min(ti.begin + kSortTile, n);
@@ -58,6 +60,7 @@ __device__ __forceinline__ bool tile_info(const SortArgs &a, int tile, TileInfo 
   const int s = seg_lookup(sg->tile_first, a.sa.B, tile);
   ti.s = s;
   ti.first = sg->tile_first[s];
+  ti.next_first = sg->tile_first[s + 1];
   ti.seg_start = sg->start[s];
   ti.begin = ti.seg_start + (tile - ti.first) * kSortTile;
   ti.end = min(ti.begin + kSortTile, (int)sg->start[s + 1]);
@@ -80,28 +83,17 @@ __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const int32_t *
   return src[(size_t)d * a.stride + pos];
 }
 
-// Offset of the digit totals of pass q for direction d and cloud s.
-__device__ __forceinline__ size_t totals_row(const SortArgs &a, int d, int q, int s) {
-  return (((size_t)d * kSortPasses + q) * a.sa.B + s) * 256;
-}
-
 __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const int32_t *__restrict__ xyz,
                                                                const uint64_t *__restrict__ src,
                                                                uint32_t *__restrict__ hist,
-                                                               uint32_t *__restrict__ totals,
                                                                fgbd_result *__restrict__ res) {
   __shared__ uint32_t s_h[256];
-  __shared__ uint32_t s_all[kSortPasses][256];
   const int d = blockIdx.y;
   const int tile = blockIdx.x;
   TileInfo ti;
   if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
   s_h[t] = 0;
-  if (a.pass == 0) {
-#pragma unroll
-    for (int q = 0; q < kSortPasses; ++q) s_all[q][t] = 0;
-  }
   __syncthreads();
   const int wave = t / kWave;
   const int lane = (int)lane_id();
@@ -112,34 +104,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
     const int pos = base + j * kWave;
     if (pos < ti.end) {
       const uint64_t it = load_item(a, xyz, src, d, pos, &bad);
-      const uint32_t digit = (uint32_t)(it >> (32 + a.shift)) & 255u;
-      atomicAdd(&s_h[digit], 1u);
-      if (a.pass == 0) {  // digit totals of every pass, for the offsets
-#pragma unroll
-        for (int q = 1; q < kSortPasses; ++q) atomicAdd(&s_all[q][(uint32_t)(it >> (32 + 8 * q)) & 255u], 1u);
-      }
+      atomicAdd(&s_h[(uint32_t)(it >> (32 + a.shift)) & 255u], 1u);
     }
   }
   if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
   __syncthreads();
-  hist[((size_t)d * 256 + t) * a.ntiles_cap + tile] = s_h[t];
-  if (a.pass == 0) {
-    if (s_h[t]) atomicAdd(&totals[totals_row(a, d, 0, ti.s) + t], s_h[t]);
-#pragma unroll
-    for (int q = 1; q < kSortPasses; ++q)
-      if (s_all[q][t]) atomicAdd(&totals[totals_row(a, d, q, ti.s) + t], s_all[q][t]);
-  }
+  hist[((size_t)d * 256 + t) * a.row + tile] = s_h[t];
 }
 
-// Exclusive prefix of every (direction, digit) row of tile counts: one wave
-// per row, 64 tiles at a time with a wave prefix sum.
+// Exclusive prefix of every (direction, digit) row of tile counts, and the
+// row total after the last tile: one wave per row, 64 tiles at a time with a
+// wave prefix sum.
 __global__ __launch_bounds__(256) void k_sort_scan(SortArgs a, uint32_t *__restrict__ hist) {
   const int row = blockIdx.x * 4 + threadIdx.x / kWave;
   if (row >= a.dt.num_dirs * 256) return;
   const int ntiles = num_tiles(a);
   const uint32_t lane = lane_id();
   uint32_t carry = 0;
-  uint32_t *h = hist + (size_t)row * a.ntiles_cap;
+  uint32_t *h = hist + (size_t)row * a.row;
   for (int t0 = 0; t0 < ntiles; t0 += kWave) {
     const int tile = t0 + (int)lane;
     const uint32_t v = tile < ntiles ? h[tile] : 0u;
@@ -152,6 +134,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortArgs a, uint32_t *__restr
     if (tile < ntiles) h[tile] = carry + x - v;
     carry += __shfl(x, kWave - 1, kWave);
   }
+  if (lane == 0) h[ntiles] = carry;
 }
 
 // Exclusive scans of two uint32 per thread over a 256-thread block.
@@ -185,7 +168,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
                                                                  const uint64_t *__restrict__ src,
                                                                  uint64_t *__restrict__ dst,
                                                                  const uint32_t *__restrict__ hist,
-                                                                 const uint32_t *__restrict__ totals,
                                                                  uint32_t *__restrict__ rank) {
   __shared__ uint32_t s_wh[4][256];
   __shared__ uint32_t s_off[256];
@@ -206,11 +188,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   s_wh[1][t] = 0;
   s_wh[2][t] = 0;
   s_wh[3][t] = 0;
-  const uint32_t *hrow = hist + ((size_t)d * 256 + t) * a.ntiles_cap;
-  // digit t's offset inside the cloud's range: tile prefix minus the prefix
-  // at the cloud's first tile (zero for the first cloud)
-  uint32_t off_t = hrow[tile] - (ti.first > 0 ? hrow[ti.first] : 0u);
-  uint32_t below_t = totals[totals_row(a, d, a.pass, ti.s) + t];
+  // scanned row of digit t: the cloud's count of t and this tile's offset
+  // inside the cloud (the first cloud starts at column 0 with prefix 0)
+  const uint32_t *hrow = hist + ((size_t)d * 256 + t) * a.row;
+  const uint32_t p_first = ti.first > 0 ? hrow[ti.first] : 0u;
+  uint32_t off_t = hrow[tile] - p_first;
+  uint32_t below_t = hrow[ti.next_first] - p_first;  // becomes the exclusive prefix over digits
 
   uint64_t item[kSortItems];
   const int base = ti.begin + wave * kWave * kSortItems + lane;
@@ -282,7 +265,7 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
   a.dt = r.dt;
   a.sa = r.sa;
   a.stride = r.pl.stride;
-  a.ntiles_cap = r.pl.ntiles_cap;
+  a.row = r.pl.ntiles_cap + 1;
   const int ntiles = r.sa.n_fixed >= 0 ? (r.sa.n_fixed + kSortTile - 1) / kSortTile : r.pl.ntiles_cap;
   const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
   const uint64_t *src = nullptr;
@@ -292,13 +275,13 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
     a.shift = 8 * pass;
     uint64_t *dst = bufs[pass & 1];
     FGBD_PRE(r.pf, kUpsweep);
-    k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, r.b.hist, r.b.totals, res);
+    k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, r.b.hist, res);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kScan);
     k_sort_scan<<<(r.dt.num_dirs * 256 + 3) / 4, 256, 0, r.stream>>>(a, r.b.hist);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kDownsweep);
-    k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.totals, r.b.rank);
+    k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.rank);
     FGBD_POST(r.pf);
     src = dst;
   }
