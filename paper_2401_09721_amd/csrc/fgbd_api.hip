@@ -126,6 +126,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_items_b = take((size_t)pl.L * pl.stride * 8);
   pl.off_hist = take((size_t)pl.L * (pl.ntiles_cap + 1) * 256 * 4);
   pl.off_rank = take((size_t)pl.L * pl.stride * 4);
+  pl.off_digits = take((size_t)pl.L * pl.stride);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
   pl.off_p = take(N * pl.K * 4);
@@ -146,6 +147,7 @@ Bufs carve(char *ws, const Plan &pl) {
   b.items_b = (uint64_t *)(ws + pl.off_items_b);
   b.hist = (uint32_t *)(ws + pl.off_hist);
   b.rank = (uint32_t *)(ws + pl.off_rank);
+  b.digits = (uint8_t *)(ws + pl.off_digits);
   b.col = (int32_t *)(ws + pl.off_col);
   b.dist2 = (int32_t *)(ws + pl.off_dist2);
   b.p = (float *)(ws + pl.off_p);

@@ -282,7 +282,7 @@ struct Plan {
   int32_t ntiles_cap;        // radix tiles: ceil(n_cap / tile) + B - 1
   int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)
   int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
-  size_t off_segs, off_items_a, off_items_b, off_hist, off_rank;
+  size_t off_segs, off_items_a, off_items_b, off_hist, off_rank, off_digits;
   size_t off_col, off_dist2, off_p, off_spread, off_xbuf;
   size_t off_merge_part, off_noise_part, off_ctrl, off_sweep_sums;
   size_t total;
@@ -316,7 +316,8 @@ struct Bufs {
   Segs *segs;
   uint64_t *items_a, *items_b;  // [L][n_cap]
   uint32_t *hist;               // [L][256][ntiles_cap + 1]
-  uint32_t *rank;               // [L][n_cap]
+  uint32_t *rank;               // [L][stride]
+  uint8_t *digits;              // [L][stride]: the next radix pass's digit of each sorted item
   int32_t *col, *dist2;         // [n_cap][K]
   float *p;                     // [n_cap][K]
   double *spread;               // [n_cap]

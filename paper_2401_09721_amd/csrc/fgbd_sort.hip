@@ -83,8 +83,12 @@ __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const int32_t *
   return src[(size_t)d * a.stride + pos];
 }
 
+// Per-tile digit counts.  Pass 0 makes the codes from the coordinates;
+// later passes read only the byte array of this pass's digits that the
+// previous downsweep wrote beside the items (16 digits per thread, one
+// 16-byte load).
 __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const int32_t *__restrict__ xyz,
-                                                               const uint64_t *__restrict__ src,
+                                                               const uint8_t *__restrict__ digits,
                                                                uint32_t *__restrict__ hist,
                                                                fgbd_result *__restrict__ res) {
   __shared__ uint32_t s_h[256];
@@ -95,19 +99,35 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
   const int t = threadIdx.x;
   s_h[t] = 0;
   __syncthreads();
-  const int wave = t / kWave;
-  const int lane = (int)lane_id();
-  const int base = ti.begin + wave * kWave * kSortItems + lane;
-  int bad = 0;
+  if (a.pass == 0) {
+    const int wave = t / kWave;
+    const int lane = (int)lane_id();
+    const int base = ti.begin + wave * kWave * kSortItems + lane;
+    int bad = 0;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const int pos = base + j * kWave;
-    if (pos < ti.end) {
-      const uint64_t it = load_item(a, xyz, src, d, pos, &bad);
-      atomicAdd(&s_h[(uint32_t)(it >> (32 + a.shift)) & 255u], 1u);
+    for (int j = 0; j < kSortItems; ++j) {
+      const int pos = base + j * kWave;
+      if (pos < ti.end) {
+        const uint64_t it = load_item(a, xyz, nullptr, d, pos, &bad);
+        atomicAdd(&s_h[(uint32_t)(it >> 32) & 255u], 1u);
+      }
+    }
+    if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
+  } else {
+    // tile starts are multiples of 16 inside the direction's row (clouds
+    // start at any position, so only the bytes of the tile are counted)
+    const uint8_t *row = digits + (size_t)d * a.stride;
+    const int p0 = ti.begin + 16 * t;
+    if (p0 + 16 <= ti.end && (p0 & 15) == 0) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(row + p0);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 16; ++j) atomicAdd(&s_h[(w[j >> 2] >> (8 * (j & 3))) & 255u], 1u);
+    } else {
+      for (int j = 0; j < 16; ++j)
+        if (p0 + j < ti.end) atomicAdd(&s_h[row[p0 + j]], 1u);
     }
   }
-  if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
   __syncthreads();
   hist[((size_t)d * 256 + t) * a.row + tile] = s_h[t];
 }
@@ -168,6 +188,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
                                                                  const uint64_t *__restrict__ src,
                                                                  uint64_t *__restrict__ dst,
                                                                  const uint32_t *__restrict__ hist,
+                                                                 uint8_t *__restrict__ digits,
                                                                  uint32_t *__restrict__ rank) {
   __shared__ uint32_t s_wh[4][256];
   __shared__ uint32_t s_off[256];
@@ -249,12 +270,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
 
   const bool last_pass = (a.pass == kSortPasses - 1);
   uint64_t *out = dst + (size_t)d * a.stride;
+  uint8_t *dig = digits + (size_t)d * a.stride;
   for (int s = t; s < valid; s += kSortThreads) {
     const uint64_t it = s_stage[s];
     const uint32_t digit = (uint32_t)(it >> (32 + a.shift)) & 255u;
     const uint32_t gpos = s_off[digit] + (uint32_t)s - s_base[digit];
     out[gpos] = it;
-    if (last_pass) rank[(size_t)d * a.stride + (uint32_t)it] = gpos;
+    if (last_pass)
+      rank[(size_t)d * a.stride + (uint32_t)it] = gpos;
+    else
+      dig[gpos] = (uint8_t)(it >> (40 + a.shift));  // the next pass's digit
   }
 }
 
@@ -275,13 +300,13 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
     a.shift = 8 * pass;
     uint64_t *dst = bufs[pass & 1];
     FGBD_PRE(r.pf, kUpsweep);
-    k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, r.b.hist, res);
+    k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, r.b.digits, r.b.hist, res);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kScan);
     k_sort_scan<<<(r.dt.num_dirs * 256 + 3) / 4, 256, 0, r.stream>>>(a, r.b.hist);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kDownsweep);
-    k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.rank);
+    k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.digits, r.b.rank);
     FGBD_POST(r.pf);
     src = dst;
   }
