@@ -437,6 +437,102 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   }
 }
 
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+
+// The same statistics with the tile's patch moments as one 16 x 16 FP64 Gram
+// matrix on the matrix cores (D + 3 <= 16).  Each patch row (one channel of
+// one patch) becomes the 16-vector of its D colour entries, three channel
+// indicators (1 in the row's own channel, for complete patches only) and
+// zeros; G = sum over rows of v v^T then holds sum a a^T (the D x D block),
+// the per-channel sums (columns D .. D+2 of the first D rows) and the patch
+// count (G[D][D]).  v_mfma_f64_16x16x4f64 adds four rows per instruction:
+// lane l supplies feature l % 16 of row l / 16 as both operands, and its
+// accumulator register i holds G[4 i + l / 16][l % 16].  Products of floats
+// are exact in FP64; the accumulation order is fixed.
+template <int PT, bool EIG3>
+__global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
+                                                       const float *__restrict__ rgb, double *__restrict__ spread,
+                                                       float *__restrict__ eig3, double *__restrict__ part) {
+  constexpr int D = PT + 1;
+  static_assert(D + 3 <= 16, "the Gram matrix holds D colour features and three indicators");
+  extern __shared__ float s_v[];  // [3 * TP][D] patch rows of the current tile
+  __shared__ uint8_t s_ok[kBlock];
+  __shared__ double s_g[4][256];
+  const int t = threadIdx.x;
+  const int TP = a.TP;
+  const int wave = t / kWave, lane = (int)lane_id();
+  const int f = lane % 16, rsub = lane / 16;
+  const int groups = 3 * TP / 4;  // four rows per instruction
+  v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+
+  const SegBlock sb = seg_block(a.sa, kGridNoise);
+  const Share sh = seg_share(sb, TP);
+  for (int64_t tbase = sh.first; tbase < sh.end; tbase += sh.step) {
+    if (t < TP) {
+      const int64_t i = tbase + t;
+      float *r0 = s_v + (size_t)(3 * t + 0) * D;
+      float *r1 = s_v + (size_t)(3 * t + 1) * D;
+      float *r2 = s_v + (size_t)(3 * t + 2) * D;
+      bool complete = false;
+      if (i < sh.end) complete = patch_point<PT, EIG3>(a, i, col, rgb, r0, r1, r2, spread, eig3);
+      s_ok[t] = complete ? 1 : 0;
+      if (!complete) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          r0[k] = 0.0f;
+          r1[k] = 0.0f;
+          r2[k] = 0.0f;
+        }
+        if (i < sh.end) {
+          spread[i] = __builtin_huge_val();
+          if (EIG3) {
+            eig3[3 * i + 0] = 0.0f;
+            eig3[3 * i + 1] = 0.0f;
+            eig3[3 * i + 2] = 0.0f;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int g = wave; g < groups; g += kBlock / kWave) {
+      const int r = 4 * g + rsub;
+      const int pt = r / 3, ch = r - 3 * pt;
+      const float x = f < D ? s_v[r * D + (f < D ? f : 0)] : 0.0f;
+      const double v = f < D ? (double)x : ((f < D + 3 && s_ok[pt] && ch == f - D) ? 1.0 : 0.0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // the block's Gram matrix, then its partials entry-major:
+  // part[e * nblocks + block], entry 0 = patch count
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s_g[wave][(4 * i + rsub) * 16 + f] = acc[i];
+  __syncthreads();
+  const double gsum = (s_g[0][t] + s_g[1][t]) + (s_g[2][t] + s_g[3][t]);
+  __syncthreads();
+  s_g[0][t] = gsum;
+  __syncthreads();
+  const int nb = gridDim.x;
+  for (int e = t; e < 1 + a.E; e += kBlock) {
+    double v;
+    if (e == 0) {
+      v = s_g[0][D * 16 + D];
+    } else if (e - 1 < a.E2) {
+      int k = 0, rem = e - 1;
+      while (rem >= D - k) {
+        rem -= D - k;
+        ++k;
+      }
+      v = s_g[0][k * 16 + (k + rem)];
+    } else {
+      const int q = e - 1 - a.E2;
+      v = s_g[0][(q % D) * 16 + D + q / D];
+    }
+    part[(size_t)e * nb + blockIdx.x] = v;
+  }
+}
+
 // One block: sum the k_noise partials in block order, form Sigma, find its
 // eigenvalues (FP64) and apply the tail rule.
 constexpr int kSolveThreads = 1024;
@@ -552,9 +648,9 @@ hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, doub
   double *part = r.b.noise_part;
   hipStream_t st = r.stream;
   if (a.P == 8 && eig3 == nullptr)
-    k_noise<8, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
+    k_noise_mfma<8, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else if (a.P == 8)
-    k_noise<8, true><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
+    k_noise_mfma<8, true><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else if (eig3 == nullptr)
     k_noise<0, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else
