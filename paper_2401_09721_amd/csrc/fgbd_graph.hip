@@ -138,9 +138,11 @@ __device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int wind
 // One thread per point.  WT > 0 (compile-time window, capacity < 2^24): the
 // point's ranks in all directions go to LDS in one batch of loads; each
 // direction's 2*WT+1 window items (the centre gives the point's own code) are
-// fetched as one batch, one direction ahead of their use; candidates are
-// 32-bit keys (min(d2, 255) << 24 | j), exact whenever no kept entry has a
-// clamped distance, else the point is redone with 64-bit keys.
+// then loaded as one batch and consumed (prefetching the next direction's
+// window would raise the register count from 83 to 109 and the occupancy from
+// six to four waves per SIMD, which measured slower); candidates are 32-bit
+// keys (min(d2, 255) << 24 | j), exact whenever no kept entry has a clamped
+// distance, else the point is redone with 64-bit keys.
 template <int KM, int WT>
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *__restrict__ sorted,
                                                   const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
@@ -168,23 +170,19 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
       uint32_t key[KM];
 #pragma unroll
       for (int k = 0; k < KM; ++k) key[k] = ~0u;
-      uint64_t cur[2 * WT + 1], nxt[2 * WT + 1];
-      load_window<WT>(sorted, s_rank[0][t], lo, hi, cur);
       for (int d = 0; d < L; ++d) {
-        if (d + 1 < L) load_window<WT>(sorted + (size_t)(d + 1) * a.stride, s_rank[d + 1][t], lo, hi, nxt);
+        uint64_t cur[2 * WT + 1];
+        load_window<WT>(sorted + (size_t)d * a.stride, s_rank[d][t], lo, hi, cur);
         const DirConst dc = dir_const(s_dir[d], a.dt.bits);
         const uint32_t ci = (uint32_t)(cur[WT] >> 32);
 #pragma unroll
         for (int s = 0; s <= 2 * WT; ++s) {
           if (s != WT) {
             const uint32_t d2 = code_dist2(ci, (uint32_t)(cur[s] >> 32), dc);
-            // an empty window slot (all ones) yields the sentinel key
             const uint32_t kc = cur[s] == ~0ull ? ~0u : (((d2 < 255u ? d2 : 255u) << 24) | (uint32_t)cur[s]);
             topk_insert_minmax<KM>(key, kc);
           }
         }
-#pragma unroll
-        for (int s = 0; s <= 2 * WT; ++s) cur[s] = nxt[s];
       }
       bool clamped = false;
 #pragma unroll
