@@ -88,23 +88,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Eigenvalues of the symmetric D x D matrix in LDS (row stride ld), by one
-// wave, in two stages:
-//  1. Householder reduction to tridiagonal form (A is overwritten): at step
-//     k the column below the diagonal, x, is mapped onto alpha e_1 with
-//     H = I - beta v v^T, v = x - alpha e_1, alpha = -sign(x_1)|x|, and the
-//     trailing block is updated as A' - v q^T - q v^T with p = beta A' v,
-//     q = p - (beta/2)(v^T p) v (lanes own rows or entries; LDS vectors).
-//  2. Sturm-sequence multisection of the tridiagonal matrix (d, e): the count
-//     of eigenvalues below x follows from the signs of the pivots
-//     q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1}; each eigenvalue gets
-//     G = 64 / D lanes that evaluate the count at G interior points of its
-//     bracket per step, a fixed number of steps (enough for 56 bits), starting
-//     from the Gershgorin interval.
-// lam receives the eigenvalues in descending order.  Accurate to a few ulps
-// of the matrix norm, like any backward-stable symmetric eigen-solver.
-__device__ void eig_sym_wave(double *A, int D, int ld, double *s_v, double *s_p, double *s_d, double *s_e,
-                             double *s_x, int *s_c, double *lam) {
+// Eigenvalues of the symmetric D x D matrix in LDS (row stride ld), in two
+// stages:
+//  1. (one wave) Householder reduction to tridiagonal form (A is
+//     overwritten): at step k the column below the diagonal, x, is mapped
+//     onto alpha e_1 with H = I - beta v v^T, v = x - alpha e_1,
+//     alpha = -sign(x_1)|x|, and the trailing block is updated as
+//     A' - v q^T - q v^T with p = beta A' v, q = p - (beta/2)(v^T p) v (lanes
+//     own rows or entries; LDS vectors).  The diagonal and off-diagonal go to
+//     s_d, s_e.
+//  2. (every wave, one eigenvalue at a time) Sturm-sequence multisection of
+//     the tridiagonal matrix: the count of eigenvalues below x follows from
+//     the signs of the pivots q_0 = d_0 - x, q_i = d_i - x - e_{i-1}^2 / q_{i-1};
+//     the 64 lanes evaluate the count at 64 interior points of the bracket
+//     of eigenvalue k (ascending), which keeps count(lo) <= k < count(hi) and
+//     shrinks 65-fold per step; eight steps from the Gershgorin interval give
+//     about 48 bits of it (eigenvalues to ~3e-15 of the norm).
+// Accurate to a few ulps of the matrix norm, like any backward-stable
+// symmetric eigen-solver.
+__device__ void householder_wave(double *A, int D, int ld, double *s_v, double *s_p, double *s_d, double *s_e) {
   const int t = (int)lane_id();
   for (int k = 0; k + 2 < D; ++k) {
     const int m = D - k - 1;
@@ -144,9 +146,11 @@ __device__ void eig_sym_wave(double *A, int D, int ld, double *s_v, double *s_p,
     }
     s_d[D - 1] = A[(size_t)(D - 1) * ld + (D - 1)];
   }
-  wave_lds_sync();
+}
 
-  // Gershgorin interval and the pivot guard
+// Eigenvalue k (ascending) of the tridiagonal (s_d, s_e), by one wave.
+__device__ double tridiag_eig_wave(const double *s_d, const double *s_e, int D, int k) {
+  const int t = (int)lane_id();
   double glo = 1e300, ghi = -1e300, emax = 0.0;
   for (int i = t; i < D; i += kWave) {
     const double r = (i > 0 ? fabs(s_e[i - 1]) : 0.0) + (i + 1 < D ? fabs(s_e[i]) : 0.0);
@@ -162,47 +166,32 @@ __device__ void eig_sym_wave(double *A, int D, int ld, double *s_v, double *s_p,
   }
   const double nrm = fmax(fabs(glo), fabs(ghi));
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax) * 4.0;
-  glo -= 4.0 * 2.220446049250313e-16 * nrm + pivmin;
-  ghi += 4.0 * 2.220446049250313e-16 * nrm + pivmin;
-
-  const int G = D < kWave ? kWave / D : 1;  // lanes per eigenvalue
-  const int ev = t / G, sub = t % G;         // eigenvalue (ascending) and point of this lane
-  const bool active = ev < D;
-  double lo = glo, hi = ghi;
-  int bits_per_step = 0;
-  for (int g = G + 1; g > 1; g >>= 1) ++bits_per_step;  // floor(log2(G + 1)) >= 1
-  const int steps = (56 + bits_per_step - 1) / bits_per_step;
-  for (int it = 0; it < steps; ++it) {
-    const double x = lo + (hi - lo) * (double)(sub + 1) / (double)(G + 1);
-    int cnt = 0;
-    if (active) {
-      double q = s_d[0] - x;
+  double lo = glo - (4.0 * 2.220446049250313e-16 * nrm + pivmin);
+  double hi = ghi + (4.0 * 2.220446049250313e-16 * nrm + pivmin);
+  for (int it = 0; it < 8; ++it) {
+    const double step = (hi - lo) / (double)(kWave + 1);
+    const double x = lo + step * (double)(t + 1);
+    double q = s_d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+    for (int i = 1; i < D; ++i) {
+      // 1 / q from the hardware reciprocal and one Newton step (the count
+      // needs only the sign of each pivot)
+      double r = __builtin_amdgcn_rcp(q);
+      r = fma(r, fma(-q, r, 1.0), r);
+      q = fma(-s_e[i - 1] * s_e[i - 1], r, s_d[i] - x);
       if (fabs(q) < pivmin) q = -pivmin;
-      cnt = q < 0.0;
-      for (int i = 1; i < D; ++i) {
-        q = s_d[i] - x - s_e[i - 1] * s_e[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += q < 0.0;
-      }
+      cnt += q < 0.0;
     }
-    s_x[t] = x;
-    s_c[t] = cnt;
-    wave_lds_sync();
-    if (active) {  // the group's new bracket: count(lo) <= ev < count(hi)
-      double nlo = lo, nhi = hi;
-      for (int j = 0; j < G; ++j) {
-        const double xj = s_x[ev * G + j];
-        const int cj = s_c[ev * G + j];
-        if (cj <= ev) nlo = fmax(nlo, xj);
-        else nhi = fmin(nhi, xj);
-      }
-      lo = nlo;
-      hi = nhi;
-    }
-    wave_lds_sync();
+    // the count grows with x, so the lanes with count <= k are the first j:
+    // the new bracket is (x_{j-1}, x_j) with x_{-1} = lo and x_64 = hi
+    const int j = (int)__popcll(__builtin_amdgcn_ballot_w64(cnt <= k));
+    const double nlo = j > 0 ? lo + step * (double)j : lo;
+    const double nhi = j < kWave ? lo + step * (double)(j + 1) : hi;
+    lo = nlo;
+    hi = nhi;
   }
-  if (active && sub == 0) lam[D - 1 - ev] = 0.5 * (lo + hi);
-  wave_lds_sync();
+  return 0.5 * (lo + hi);
 }
 
 // Per-point work of one tile slot: gather the patch into three LDS rows,
@@ -543,8 +532,7 @@ constexpr int kSolveThreads = 1024;
 __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, const double *__restrict__ part, int nb,
                                                                fgbd_result *__restrict__ res_all) {
   __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
-  __shared__ double s_v[kMaxD], s_p[kMaxD], s_d[kMaxD], s_e[kMaxD], s_x[kWave];
-  __shared__ int s_c[kWave];
+  __shared__ double s_v[kMaxD], s_p[kMaxD], s_d[kMaxD], s_e[kMaxD];
   __shared__ double s_lam[kMaxD + 1];
   const int t = threadIdx.x;
   const int lane = (int)lane_id();
@@ -557,21 +545,30 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, cons
   const int f0 = a.sa.n_fixed >= 0 ? 0 : a.sa.segs->blk_first[kGridNoise][seg];
   const int nbs = (a.sa.n_fixed >= 0 ? nb : a.sa.segs->blk_first[kGridNoise][seg + 1]) - f0;
   double *tot = s_buf;
-  for (int e = wave; e < stride; e += nwaves) {
-    const double *row = part + (size_t)e * nb + f0;
-    // nbs <= kMaxGrid: every lane's loads of the row are issued together
-    double vals[kMaxGrid / kWave];
+  // two rows per wave at a time: 32 loads per lane in flight
+  constexpr int RW = 2;
+  for (int e = wave; e < stride; e += RW * nwaves) {
+    double vals[RW][kMaxGrid / kWave];
 #pragma unroll
-    for (int u = 0; u < kMaxGrid / kWave; ++u) {
-      const int b = lane + u * kWave;
-      vals[u] = b < nbs ? row[b] : 0.0;
+    for (int j = 0; j < RW; ++j) {
+      const int ej = e + j * nwaves;
+      const double *row = part + (size_t)(ej < stride ? ej : e) * nb + f0;
+#pragma unroll
+      for (int u = 0; u < kMaxGrid / kWave; ++u) {
+        const int b = lane + u * kWave;
+        vals[j][u] = b < nbs ? row[b] : 0.0;
+      }
     }
-    double v = 0.0;
 #pragma unroll
-    for (int u = 0; u < kMaxGrid / kWave; ++u) v += vals[u];
+    for (int j = 0; j < RW; ++j) {
+      double v = 0.0;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
-    if (lane == 0) tot[e] = v;
+      for (int u = 0; u < kMaxGrid / kWave; ++u) v += vals[j][u];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+      const int ej = e + j * nwaves;
+      if (lane == 0 && ej < stride) tot[ej] = v;
+    }
   }
   __syncthreads();
   const double n_eff = tot[0];
@@ -594,11 +591,21 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, cons
     }
   }
   __syncthreads();
+  // eigenvalues: wave 0 tridiagonalises, then each wave brackets its own
+  // eigenvalues (k = wave, wave + 16, ...), stored descending
+  if (n_eff > 0.0 && wave == 0) householder_wave(A, D, Dp, s_v, s_p, s_d, s_e);
+  __syncthreads();
+  if (n_eff > 0.0) {
+    for (int k = wave; k < D; k += nwaves) {
+      const double ev = tridiag_eig_wave(s_d, s_e, D, k);
+      if (lane == 0) s_lam[D - 1 - k] = ev;
+    }
+  }
+  __syncthreads();
   if (wave != 0) return;  // no block barrier follows
   double sigma = 0.0;
   int m_star = 0;
   if (n_eff > 0.0) {  // uniform over the wave
-    eig_sym_wave(A, D, Dp, s_v, s_p, s_d, s_e, s_x, s_c, s_lam);
     // tail rule, every m at once (lane m): the smallest m whose tail mean is
     // not above the tail median
     const double *lam = s_lam;
