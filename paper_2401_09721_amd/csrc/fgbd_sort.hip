@@ -67,6 +67,19 @@ __device__ __forceinline__ bool tile_info(const SortArgs &a, int tile, TileInfo 
   return true;
 }
 
+// (direction, tile) of a downsweep block: workgroups go to the 8 XCDs round
+// robin, so block b runs on XCD b % 8; each XCD gets one contiguous range of
+// the (direction, tile) sequence, so the runs that consecutive tiles write
+// side by side for each digit meet in one L2 before they are written back.
+__device__ __forceinline__ void xcd_tile(int &d, int &tile) {
+  const int nb = (int)(gridDim.x * gridDim.y);
+  const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int x = b % kXcds, k = b / kXcds;
+  const int g = x * (nb / kXcds) + min(x, nb % kXcds) + k;
+  d = g / (int)gridDim.x;
+  tile = g % (int)gridDim.x;
+}
+
 __device__ __forceinline__ int num_tiles(const SortArgs &a) {
   return a.sa.n_fixed >= 0 ? (a.sa.n_fixed + kSortTile - 1) / kSortTile : a.sa.segs->ntiles;
 }
@@ -196,8 +209,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   __shared__ uint32_t s_tmp[2][4];
   __shared__ uint64_t s_stage[kSortTile];
 
-  const int d = blockIdx.y;
-  const int tile = blockIdx.x;
+  int d, tile;
+  xcd_tile(d, tile);
   TileInfo ti;
   if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
