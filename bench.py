@@ -27,13 +27,14 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(kind: str, n: int, L: int, K: int, P: int) -> float:
     """Compulsory HBM bytes per launch of each kernel kind: every array a launch
     must read or write, read or written once, neighbour gathers counted as cache
-    hits.  Radix kernels: averaged over the 4 passes (pass 0 reads int32 xyz and
-    makes the codes, passes 1-3 read 8-byte items, the last pass also writes the
-    4-byte rank)."""
+    hits.  Radix kernels are averaged over the 4 passes: pass 0 reads the int32
+    coordinates once (12 B/point for all L directions); each downsweep moves the
+    8-byte items (read and write) and writes the next pass's 1-byte digit, the
+    last one the 4-byte rank instead; upsweeps 1-3 read the 1-byte digits."""
     if kind == "radix_upsweep":
-        return (12 + 3 * 8) / 4 * L * n
+        return (12 * n + 3 * L * n) / 4
     if kind == "radix_downsweep":
-        return ((12 + 8) + 2 * (8 + 8) + (8 + 8 + 4)) / 4 * L * n
+        return (12 * n + 9 * L * n + 2 * 17 * L * n + 20 * L * n) / 4
     if kind == "merge":     # xyz, rank, sorted items once, col + dist2 out
         return (12 + 4 * L + 8 * L + 8 * K) * n
     if kind == "weights":   # col + dist2 in, p out
