@@ -129,7 +129,6 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_digits = take((size_t)pl.L * pl.stride);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
-  pl.off_p = take(N * pl.K * 4);
   pl.off_spread = take(N * 8);
   pl.off_xbuf = take(3 * N * 16);
   pl.off_merge_part = take((size_t)pl.grid[kGridMerge] * 2 * 8);
@@ -150,7 +149,6 @@ Bufs carve(char *ws, const Plan &pl) {
   b.digits = (uint8_t *)(ws + pl.off_digits);
   b.col = (int32_t *)(ws + pl.off_col);
   b.dist2 = (int32_t *)(ws + pl.off_dist2);
-  b.p = (float *)(ws + pl.off_p);
   b.spread = (double *)(ws + pl.off_spread);
   b.xbuf = (float4 *)(ws + pl.off_xbuf);
   b.merge_part = (double *)(ws + pl.off_merge_part);
@@ -399,13 +397,15 @@ Run make_run(fgbd_ctx ctx, const Plan &pl, char *ws, const fgbd_params &prm, int
   return r;
 }
 
-// Graph construction into (col, dist2, p); sigma_g into res.
+// Graph construction into (col, dist2, p); sigma_g into res.  p == NULL
+// stops after the merge: the sweeps then derive sigma_g and the weights.
 fgbd_status run_slg(const Run &r, const int32_t *xyz, int32_t *col, int32_t *dist2, float *p, fgbd_result *res) {
   const uint64_t *sorted = nullptr;
   HIP_TRY(launch_sort(r, xyz, res, &sorted), "radix sort launch");
   FGBD_PRE(r.pf, kMerge);
   HIP_TRY(launch_merge(r, sorted, col, dist2), "neighbour merge launch");
   FGBD_POST(r.pf);
+  if (p == nullptr) return FGBD_OK;
   FGBD_PRE(r.pf, kWeights);
   HIP_TRY(launch_weights(r, col, dist2, res, p), "weights launch");
   FGBD_POST(r.pf);
@@ -424,13 +424,16 @@ fgbd_status run_noise(const Run &r, const int32_t *col, const float *rgb, double
 }
 
 // Sweeps and the final copy.  The first sweep's sums buffer was cleared by
-// the call's setup launch.
-fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const float *rgb_in, const double *spread,
-                       const fgbd_result *noise, int select, int q_limit, float *rgb_out, fgbd_result *res) {
+// the call's setup launch.  With dist2 given (p unused) the sweeps compute
+// the weights from the squared distances and the first one writes sigma_g
+// into res.
+fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const int32_t *dist2, const float *rgb_in,
+                       const double *spread, const fgbd_result *noise, int select, int q_limit, float *rgb_out,
+                       fgbd_result *res) {
   const int sweeps = q_limit > 0 ? q_limit : 1;
   for (int q = 1; q <= sweeps; ++q) {
     FGBD_PRE(r.pf, kSweep);
-    HIP_TRY(launch_sweep(r, col, p, rgb_in, spread, noise, select, q_limit, q), "sweep launch");
+    HIP_TRY(launch_sweep(r, col, p, dist2, rgb_in, spread, noise, res, select, q_limit, q), "sweep launch");
     FGBD_POST(r.pf);
   }
   FGBD_PRE(r.pf, kFinalize);
@@ -592,19 +595,22 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
   HIP_TRY(launch_setup(r, nullptr, n, res, n == 0 ? 1 : 0), "setup launch");
   if (n == 0) return ok();
   const int q_limit = select ? params->q_max : q_fixed;
-  if ((st = run_filter(r, g->col, g->p, rgb_in, patch_spread, noise, select, q_limit, rgb_out, res)) != FGBD_OK)
+  if ((st = run_filter(r, g->col, g->p, nullptr, rgb_in, patch_spread, noise, select, q_limit, rgb_out, res)) !=
+      FGBD_OK)
     return st;
   return ok();
 }
 
 // The fused path over the call's segments (one cloud of host-known size, or
-// B clouds from device offsets).
+// B clouds from device offsets).  The weights are never stored: the sweeps
+// compute them from the squared distances (the noise estimate needs only
+// the neighbour lists).
 static fgbd_status run_denoise(const Run &r, const int32_t *xyz, const float *rgb_in, float *rgb_out,
                                fgbd_result *res) {
   fgbd_status st;
-  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, r.b.p, res)) != FGBD_OK) return st;
+  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
   if ((st = run_noise(r, r.b.col, rgb_in, r.b.spread, nullptr, res)) != FGBD_OK) return st;
-  return run_filter(r, r.b.col, r.b.p, rgb_in, r.b.spread, res, 1, r.prm.q_max, rgb_out, res);
+  return run_filter(r, r.b.col, nullptr, r.b.dist2, rgb_in, r.b.spread, res, 1, r.prm.q_max, rgb_out, res);
 }
 
 fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n,

@@ -39,6 +39,14 @@ struct SweepArgs {
   int32_t select, q_limit;
   double kappa;
   int64_t buf_stride;  // float4 elements per buffer
+  // weights computed in the sweep (the fused per-frame path): squared
+  // distances, the merge launch's partials, its grid size, a fixed sigma_g
+  // (<= 0: the mean edge length), and the results that receive sigma_g
+  const int32_t *dist2;
+  const double *merge_part;
+  int32_t merge_grid;
+  double sigma_g_fixed;
+  fgbd_result *res;
 };
 
 constexpr int kSlotVals = kSweepSlots * kSweepParts;  // integers per cloud and sweep
@@ -137,7 +145,9 @@ __device__ __forceinline__ void add_sums(unsigned long long (&v)[kSweepParts], u
   }
 }
 
-template <int KT, bool FIRST>
+// D2: the row weights come from the squared distances (eq. 4, the graph
+// builder's own arithmetic) instead of a stored p.
+template <int KT, bool FIRST, bool D2>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__restrict__ col,
                                                   const float *__restrict__ p, const float *__restrict__ rgb_in,
                                                   float4 *__restrict__ xbuf, const double *__restrict__ spread,
@@ -148,13 +158,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
                                                   const SweepCtrl *__restrict__ ctrl_prev,
                                                   SweepCtrl *__restrict__ ctrl_out) {
   __shared__ unsigned long long s_red[4 * kSweepParts];
+  __shared__ double s_exp[D2 ? kExpTable : 1];
+  __shared__ double s_dred[8];
   const int K = KT > 0 ? KT : a.k;
+  constexpr int KB = KT > 0 ? KT : kMaxK;  // slots per row held in registers
   const SegBlock sb = seg_block(a.sa, kGridSweep);
   sums_prev += (size_t)sb.s * kSlotVals;
   sums_out += (size_t)sb.s * kSlotVals;
   sums_clear += (size_t)sb.s * kSlotVals;
   SweepCtrl c;
   if (FIRST) {
+    c.sigma_g = 0.0;
+    if (D2) {
+      int mf, mc;
+      seg_blocks_of(a.sa, kGridMerge, sb.s, a.merge_grid, &mf, &mc);
+      c.sigma_g = cloud_sigma_g(a.merge_part + 2 * mf, mc, a.sigma_g_fixed, s_dred);
+      if (sb.lb == 0 && threadIdx.x == 0) a.res[sb.s].sigma_g = c.sigma_g;
+    }
     c.sigma_est = a.select ? noise[sb.s].sigma_est : 0.0;
     c.target = c.sigma_est * c.sigma_est;
     c.y2_sel = 0.0;
@@ -178,6 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
     for (int j = threadIdx.x; j < kSlotVals; j += blockDim.x) sums_clear[j] = 0ull;
   }
   if (c.done) return;
+  if (D2) {
+    fill_exp_table(c.sigma_g, s_exp);
+    __syncthreads();
+  }
 
   const double thr = c.fslr ? a.kappa * c.sigma_est : 0.0;
   const int out_buf = free_buffer(c.in_buf, c.best_buf);
@@ -204,7 +228,25 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
     }
     int cc[KT > 0 ? KT : kMaxK];
     float ww[KT > 0 ? KT : kMaxK];
-    if (KT == 8) {
+    if (D2) {
+      int dv[KB];
+      if (KT == 8) {
+        const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
+        const int4 *dr = reinterpret_cast<const int4 *>(a.dist2 + i * 8);
+        const int4 c0 = cr[0], c1 = cr[1], e0 = dr[0], e1 = dr[1];
+        cc[0] = c0.x; cc[1] = c0.y; cc[2] = c0.z; cc[3] = c0.w;
+        cc[4] = c1.x; cc[5] = c1.y; cc[6] = c1.z; cc[7] = c1.w;
+        dv[0] = e0.x; dv[1] = e0.y; dv[2] = e0.z; dv[3] = e0.w;
+        dv[4] = e1.x; dv[5] = e1.y; dv[6] = e1.z; dv[7] = e1.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < (KT > 0 ? KT : kMaxK); ++k) {
+          cc[k] = k < K ? col[i * K + k] : -1;
+          dv[k] = k < K ? a.dist2[i * K + k] : 0;
+        }
+      }
+      row_weights<KB>(cc, dv, c.sigma_g, s_exp, ww);
+    } else if (KT == 8) {
       const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
       const float4 *pr = reinterpret_cast<const float4 *>(p + i * 8);
       const int4 c0 = cr[0], c1 = cr[1];
@@ -295,8 +337,17 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
 
 }  // namespace
 
-hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const float *rgb_in, const double *spread,
-                        const fgbd_result *noise, int select, int q_limit, int q) {
+template <int KT, bool FIRST, bool D2>
+void sweep_kernel(int nb, hipStream_t st, const SweepArgs &a, const int32_t *col, const float *p,
+                  const float *rgb_in, float4 *xbuf, const double *spread, const fgbd_result *noise,
+                  const unsigned long long *sp, unsigned long long *so, unsigned long long *sc,
+                  const SweepCtrl *cp, SweepCtrl *co) {
+  k_sweep<KT, FIRST, D2><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
+}
+
+hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
+                        const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
+                        int select, int q_limit, int q) {
   SweepArgs a;
   a.sa = r.sa;
   a.k = r.prm.k;
@@ -304,6 +355,11 @@ hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const 
   a.q_limit = q_limit;
   a.kappa = r.prm.fslr_kappa;
   a.buf_stride = r.pl.n_cap;
+  a.dist2 = dist2;
+  a.merge_part = r.b.merge_part;
+  a.merge_grid = r.pl.grid[kGridMerge];
+  a.sigma_g_fixed = r.prm.sigma_g;
+  a.res = res;
   const size_t S = (size_t)r.pl.B * kSlotVals;
   unsigned long long *sums3 = r.b.sums;
   const unsigned long long *sp = sums3 + ((q - 1) % 3) * S;
@@ -314,18 +370,16 @@ hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const 
   float4 *xbuf = r.b.xbuf;
   const int nb = r.pl.grid[kGridSweep];
   hipStream_t st = r.stream;
-  const bool first = q == 1;
-  if (a.k == 8) {
-    if (first)
-      k_sweep<8, true><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
-    else
-      k_sweep<8, false><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
-  } else {
-    if (first)
-      k_sweep<0, true><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
-    else
-      k_sweep<0, false><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
-  }
+  const bool first = q == 1, d2 = dist2 != nullptr;
+  using Fn = void (*)(int, hipStream_t, const SweepArgs &, const int32_t *, const float *, const float *, float4 *,
+                      const double *, const fgbd_result *, const unsigned long long *, unsigned long long *,
+                      unsigned long long *, const SweepCtrl *, SweepCtrl *);
+  static const Fn table[2][2][2] = {
+      {{sweep_kernel<0, false, false>, sweep_kernel<0, false, true>},
+       {sweep_kernel<0, true, false>, sweep_kernel<0, true, true>}},
+      {{sweep_kernel<8, false, false>, sweep_kernel<8, false, true>},
+       {sweep_kernel<8, true, false>, sweep_kernel<8, true, true>}}};
+  table[a.k == 8][first][d2](nb, st, a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
   return hipGetLastError();
 }
 

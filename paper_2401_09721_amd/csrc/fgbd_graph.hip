@@ -233,8 +233,6 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
   }
 }
 
-constexpr int kExpTable = 256;
-
 // Runs on the merge grid: block b belongs to the same cloud as merge block b.
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_weights(SegArgs sa, int32_t k_rt, const int32_t *__restrict__ col,
@@ -245,16 +243,9 @@ __global__ __launch_bounds__(kBlock) void k_weights(SegArgs sa, int32_t k_rt, co
   __shared__ double s_exp[kExpTable];
   const int K = KT > 0 ? KT : k_rt;
   const SegBlock sb = seg_block(sa, kGridMerge);
-  double sg = sigma_g_fixed;
-  if (!(sg > 0.0)) {
-    double t[2];
-    reduce_partials<2>(merge_part + 2 * ((int)blockIdx.x - sb.lb), sb.nb, 2, t, s_red);
-    sg = t[1] > 0.0 ? t[0] / t[1] : 0.0;
-  }
+  const double sg = cloud_sigma_g(merge_part + 2 * ((int)blockIdx.x - sb.lb), sb.nb, sigma_g_fixed, s_red);
   if (sb.lb == 0 && threadIdx.x == 0) res[sb.s].sigma_g = sg;
-  const double inv = sg > 0.0 ? 1.0 / (sg * sg) : 0.0;
-  // squared-distance gaps are integers: tabulate exp(-gap / sigma_g^2) for small gaps
-  for (int g = threadIdx.x; g < kExpTable; g += kBlock) s_exp[g] = sg > 0.0 ? exp(-(double)g * inv) : (g == 0 ? 1.0 : 0.0);
+  fill_exp_table(sg, s_exp);
   __syncthreads();
   constexpr int KB = KT > 0 ? KT : kMaxK;
   const Share sh = seg_share(sb, kBlock);
@@ -277,27 +268,16 @@ __global__ __launch_bounds__(kBlock) void k_weights(SegArgs sa, int32_t k_rt, co
         dv[k] = k < K ? dist2[i * K + k] : 0;
       }
     }
-    double w[KB];
-    double s = 0.0;
-    const int d0 = dv[0];
-#pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      w[k] = 0.0;
-      if (cv[k] >= 0) {
-        const int gap = dv[k] - d0;
-        w[k] = gap < kExpTable ? s_exp[gap] : (sg > 0.0 ? exp(-(double)gap * inv) : 0.0);
-        s += w[k];
-      }
-    }
-    const double rs = s > 0.0 ? 1.0 / s : 0.0;
+    float pw[KB];
+    row_weights<KB>(cv, dv, sg, s_exp, pw);
     if (KT == 8) {
       float4 *pr = reinterpret_cast<float4 *>(p + i * 8);
-      pr[0] = make_float4((float)(w[0] * rs), (float)(w[1] * rs), (float)(w[2] * rs), (float)(w[3] * rs));
-      pr[1] = make_float4((float)(w[4] * rs), (float)(w[5] * rs), (float)(w[6] * rs), (float)(w[7] * rs));
+      pr[0] = make_float4(pw[0], pw[1], pw[2], pw[3]);
+      pr[1] = make_float4(pw[4], pw[5], pw[6], pw[7]);
     } else {
 #pragma unroll
       for (int k = 0; k < KB; ++k)
-        if (k < K) p[i * K + k] = (float)(w[k] * rs);
+        if (k < K) p[i * K + k] = pw[k];
     }
   }
 }

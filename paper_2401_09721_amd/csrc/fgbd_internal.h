@@ -251,6 +251,69 @@ __device__ __forceinline__ Share seg_share(const SegBlock &sb, int chunk) {
   return s;
 }
 
+// Blocks of per-cloud grid `grid` that belong to cloud s: *first, *count.
+// grid_size is that grid's size, which a single host-sized cloud owns whole.
+__device__ __forceinline__ void seg_blocks_of(const SegArgs &a, int grid, int s, int grid_size, int *first,
+                                              int *count) {
+  if (a.n_fixed >= 0) {
+    *first = 0;
+    *count = grid_size;
+    return;
+  }
+  const int f0 = a.segs->blk_first[grid][s];
+  *first = f0;
+  *count = a.segs->blk_first[grid][s + 1] - f0;
+}
+
+// ------------------------------------------------------------ edge weights
+// Eq. 4 on the integer squared distances of a CSR row: w_k = exp(-(d_k -
+// d_0) / sigma_g^2) over the valid slots (d_0 is the nearest neighbour's, so
+// the largest term is exactly 1 and nothing underflows), normalised to sum 1
+// and rounded to float32.  The graph builder stores these weights; the fused
+// per-frame path recomputes them inside the filter sweeps from the same code,
+// so both obtain the same bits.  Gaps are integers: exp of the small ones
+// comes from a table in LDS.
+constexpr int kExpTable = 256;
+
+// sigma_g of one cloud: the fixed value when positive, else the mean merge
+// edge length from the merge launch's per-block partials (sum, count) of
+// that cloud.  Called by every thread of the block.
+__device__ __forceinline__ double cloud_sigma_g(const double *__restrict__ part, int nparts, double fixed,
+                                                double *s_red) {
+  if (fixed > 0.0) return fixed;
+  double t[2];
+  reduce_partials<2>(part, nparts, 2, t, s_red);
+  return t[1] > 0.0 ? t[0] / t[1] : 0.0;
+}
+
+// Fills s_exp[g] = exp(-g / sigma_g^2); the caller synchronises the block.
+__device__ __forceinline__ void fill_exp_table(double sg, double *s_exp) {
+  const double inv = sg > 0.0 ? 1.0 / (sg * sg) : 0.0;
+  for (int g = threadIdx.x; g < kExpTable; g += blockDim.x)
+    s_exp[g] = sg > 0.0 ? exp(-(double)g * inv) : (g == 0 ? 1.0 : 0.0);
+}
+
+template <int KB>
+__device__ __forceinline__ void row_weights(const int (&cv)[KB], const int (&dv)[KB], double sg,
+                                            const double *s_exp, float (&pw)[KB]) {
+  const double inv = sg > 0.0 ? 1.0 / (sg * sg) : 0.0;
+  double w[KB];
+  double s = 0.0;
+  const int d0 = dv[0];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    w[k] = 0.0;
+    if (cv[k] >= 0) {
+      const int gap = dv[k] - d0;
+      w[k] = gap < kExpTable ? s_exp[gap] : (sg > 0.0 ? exp(-(double)gap * inv) : 0.0);
+      s += w[k];
+    }
+  }
+  const double rs = s > 0.0 ? 1.0 / s : 0.0;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) pw[k] = (float)(w[k] * rs);
+}
+
 // ---------------------------------------------------------------- control
 // Selection state of the filter sweeps, kept in the workspace.
 struct SweepCtrl {
@@ -269,6 +332,8 @@ struct SweepCtrl {
   int32_t select;    // 1: eq. 6 selection, 0: fixed q
   int32_t q_limit;   // q_max (select) or q_fixed
   int32_t fslr;      // FSLR subset in use (select and kappa > 0)
+  int32_t pad_;
+  double sigma_g;    // of the cloud, when the sweeps compute the weights themselves
 };
 
 
@@ -283,7 +348,7 @@ struct Plan {
   int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)
   int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
   size_t off_segs, off_items_a, off_items_b, off_hist, off_rank, off_digits;
-  size_t off_col, off_dist2, off_p, off_spread, off_xbuf;
+  size_t off_col, off_dist2, off_spread, off_xbuf;
   size_t off_merge_part, off_noise_part, off_ctrl, off_sweep_sums;
   size_t total;
 };
@@ -319,7 +384,6 @@ struct Bufs {
   uint32_t *rank;               // [L][stride]
   uint8_t *digits;              // [L][stride]: the next radix pass's digit of each sorted item
   int32_t *col, *dist2;         // [n_cap][K]
-  float *p;                     // [n_cap][K]
   double *spread;               // [n_cap]
   float4 *xbuf;                 // [3][n_cap]
   double *merge_part;           // [grid merge][2]
@@ -379,9 +443,12 @@ hipError_t launch_noise_solve(const Run &r, fgbd_result *res);
 
 // Sweep number q (1-based): reads ctrl[(q-1)&1][.] and sums[(q-1)%3], writes
 // ctrl[q&1][.] and sums[q%3], clears sums[(q+1)%3].  noise: per-cloud
-// results holding sigma_est (select == 1).
-hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const float *rgb_in, const double *spread,
-                        const fgbd_result *noise, int select, int q_limit, int q);
+// results holding sigma_est (select == 1).  dist2 != NULL: the weights come
+// from the squared distances and sigma_g from the merge partials (p unused),
+// and the first sweep stores sigma_g into res[s].
+hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
+                        const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
+                        int select, int q_limit, int q);
 
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,
                            float *rgb_out, fgbd_result *res);
