@@ -43,13 +43,31 @@ __device__ __forceinline__ DirConst dir_const(const DirInfo &di, int bits) {
   c.um = di.um;
   return c;
 }
-// Every factor is below 2^13 in magnitude (b <= 10, |u| <= 2), so the
-// products use the full-rate 24-bit multiplier.
+// a * b + c on the full-rate 24-bit multiplier (operands within +-2^23).
+// Written out because the compiler otherwise folds a 24-bit product and an
+// add into a 64-bit multiply-add.
+__device__ __forceinline__ int mad_i24(int a, int b, int c) {
+  int d;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+// The fields of one code (position coordinate, middle and high invariants).
+struct CodeFields {
+  int a, m, h;
+};
+__device__ __forceinline__ CodeFields code_fields(uint32_t ci, const DirConst &c) {
+  return {(int)(ci & c.top), (int)((ci >> c.bits) & c.mmask), (int)(ci >> c.hshift)};
+}
+// Every factor is below 2^13 in magnitude (b <= 10, |u| <= 2) and the sum
+// below 2^28.
+__device__ __forceinline__ uint32_t code_dist2(const CodeFields &fi, uint32_t cj, const DirConst &c) {
+  const int da = (int)(cj & c.top) - fi.a;
+  const int dm = mad_i24(c.um, da, (int)((cj >> c.bits) & c.mmask) - fi.m);
+  const int dh = mad_i24(c.uh, da, (int)(cj >> c.hshift) - fi.h);
+  return (uint32_t)mad_i24(da, da, mad_i24(dm, dm, __mul24(dh, dh)));
+}
 __device__ __forceinline__ uint32_t code_dist2(uint32_t ci, uint32_t cj, const DirConst &c) {
-  const int da = (int)(cj & c.top) - (int)(ci & c.top);
-  const int dm = (int)((cj >> c.bits) & c.mmask) - (int)((ci >> c.bits) & c.mmask) + __mul24(c.um, da);
-  const int dh = (int)(cj >> c.hshift) - (int)(ci >> c.hshift) + __mul24(c.uh, da);
-  return (uint32_t)__mul24(da, da) + (uint32_t)__mul24(dm, dm) + (uint32_t)__mul24(dh, dh);
+  return code_dist2(code_fields(ci, c), cj, c);
 }
 
 template <int KM, typename Key>
@@ -124,13 +142,13 @@ __device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int wind
     const DirConst dc = dir_const(s_dir[d], a.dt.bits);
     const int r = (int)rank[(size_t)d * a.stride + i];
     const uint64_t *srt = sorted + (size_t)d * a.stride;
-    const uint32_t ci = (uint32_t)(srt[r] >> 32);
+    const CodeFields fi = code_fields((uint32_t)(srt[r] >> 32), dc);
     const int l = max(r - window, lo);
     const int h = min(r + window, hi);
     for (int rr = l; rr <= h; ++rr) {
       if (rr == r) continue;
       const uint64_t it = srt[rr];
-      topk_insert_t<KM, uint64_t>(lst, a.K, ((uint64_t)code_dist2(ci, (uint32_t)(it >> 32), dc) << 32) | (uint32_t)it);
+      topk_insert_t<KM, uint64_t>(lst, a.K, ((uint64_t)code_dist2(fi, (uint32_t)(it >> 32), dc) << 32) | (uint32_t)it);
     }
   }
 }
@@ -171,16 +189,35 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
 #pragma unroll
       for (int k = 0; k < KM; ++k) key[k] = ~0u;
       for (int d = 0; d < L; ++d) {
-        uint64_t cur[2 * WT + 1];
-        load_window<WT>(sorted + (size_t)d * a.stride, s_rank[d][t], lo, hi, cur);
+        const uint64_t *srt = sorted + (size_t)d * a.stride;
+        const int r = s_rank[d][t];
         const DirConst dc = dir_const(s_dir[d], a.dt.bits);
-        const uint32_t ci = (uint32_t)(cur[WT] >> 32);
+        uint64_t cur[2 * WT + 1];
+        // Wave-uniform: when every window of the wave lies inside the
+        // cloud, the items load from one base address with no clamping and
+        // no empty slots.
+        if (__builtin_amdgcn_ballot_w64(r - WT < lo || r + WT > hi) == 0) {
+          const uint64_t *wp = srt + (r - WT);
 #pragma unroll
-        for (int s = 0; s <= 2 * WT; ++s) {
-          if (s != WT) {
-            const uint32_t d2 = code_dist2(ci, (uint32_t)(cur[s] >> 32), dc);
-            const uint32_t kc = cur[s] == ~0ull ? ~0u : (((d2 < 255u ? d2 : 255u) << 24) | (uint32_t)cur[s]);
-            topk_insert_minmax<KM>(key, kc);
+          for (int s = 0; s <= 2 * WT; ++s) cur[s] = wp[s];
+          const CodeFields fi = code_fields((uint32_t)(cur[WT] >> 32), dc);
+#pragma unroll
+          for (int s = 0; s <= 2 * WT; ++s) {
+            if (s != WT) {
+              const uint32_t d2 = code_dist2(fi, (uint32_t)(cur[s] >> 32), dc);
+              topk_insert_minmax<KM>(key, (min(d2, 255u) << 24) | (uint32_t)cur[s]);
+            }
+          }
+        } else {
+          load_window<WT>(srt, r, lo, hi, cur);
+          const CodeFields fi = code_fields((uint32_t)(cur[WT] >> 32), dc);
+#pragma unroll
+          for (int s = 0; s <= 2 * WT; ++s) {
+            if (s != WT) {
+              const uint32_t d2 = code_dist2(fi, (uint32_t)(cur[s] >> 32), dc);
+              const uint32_t kc = cur[s] == ~0ull ? ~0u : ((min(d2, 255u) << 24) | (uint32_t)cur[s]);
+              topk_insert_minmax<KM>(key, kc);
+            }
           }
         }
       }
