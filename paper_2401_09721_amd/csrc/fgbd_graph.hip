@@ -30,7 +30,7 @@ namespace {
 // da, dm + u_m da and dh + u_h da.
 struct DirConst {
   uint32_t top, mmask;
-  int bits, hshift, uh, um;
+  int bits, wm, hshift, uh, um;
 };
 __device__ __forceinline__ DirConst dir_const(const DirInfo &di, int bits) {
   DirConst c;
@@ -38,6 +38,7 @@ __device__ __forceinline__ DirConst dir_const(const DirInfo &di, int bits) {
   const int wm = bits + di.wm_extra;
   c.mmask = (1u << wm) - 1u;
   c.bits = bits;
+  c.wm = wm;
   c.hshift = bits + wm;
   c.uh = di.uh;
   c.um = di.um;
@@ -56,13 +57,13 @@ struct CodeFields {
   int a, m, h;
 };
 __device__ __forceinline__ CodeFields code_fields(uint32_t ci, const DirConst &c) {
-  return {(int)(ci & c.top), (int)((ci >> c.bits) & c.mmask), (int)(ci >> c.hshift)};
+  return {(int)(ci & c.top), (int)__builtin_amdgcn_ubfe(ci, c.bits, c.wm), (int)(ci >> c.hshift)};
 }
 // Every factor is below 2^13 in magnitude (b <= 10, |u| <= 2) and the sum
 // below 2^28.
 __device__ __forceinline__ uint32_t code_dist2(const CodeFields &fi, uint32_t cj, const DirConst &c) {
   const int da = (int)(cj & c.top) - fi.a;
-  const int dm = mad_i24(c.um, da, (int)((cj >> c.bits) & c.mmask) - fi.m);
+  const int dm = mad_i24(c.um, da, (int)__builtin_amdgcn_ubfe(cj, c.bits, c.wm) - fi.m);
   const int dh = mad_i24(c.uh, da, (int)(cj >> c.hshift) - fi.h);
   return (uint32_t)mad_i24(da, da, mad_i24(dm, dm, __mul24(dh, dh)));
 }
@@ -87,21 +88,43 @@ __device__ __forceinline__ void topk_insert_t(Key (&lst)[KM], int K, Key c) {
   lst[0] = lst[0] > c ? c : lst[0];
 }
 
-// Branch-free insertion into a sorted list of KM distinct keys (all-ones =
-// empty): the candidate is carried down the list, each slot keeping the
-// smaller of (slot, carried) and passing the larger on, and the largest falls
-// off the end.  A candidate equal to a slot is turned into the all-ones
-// sentinel when it meets that slot (earlier slots are smaller, so it meets it
-// before any swap), which leaves the list unchanged.  The first K slots are
-// then the K smallest distinct keys for any K <= KM.
+// |a - b| - 1, all ones exactly when a == b (keys below 2^31 or all ones).
+__device__ __forceinline__ uint32_t absdiff_m1(uint32_t a, uint32_t b) {
+  uint32_t d;
+  asm("v_sad_u32 %0, %1, %2, -1" : "=v"(d) : "v"(a), "v"(b));
+  return d;
+}
+
+// Branch-free insertion into a sorted list of KM distinct keys (keys below
+// 2^31; all ones = empty): the candidate is carried down the list, each slot
+// keeping the smaller of (slot, carried) and passing the larger on, and the
+// largest falls off the end.  A candidate equal to a slot is turned into the
+// all-ones sentinel when it meets that slot (earlier slots are smaller, so it
+// meets it before any swap), which leaves the list unchanged: the carried
+// value is max(slot, carried, |slot - carried| - 1), and the third term is
+// all ones only for equal keys and below the larger key otherwise.  Three
+// instructions per slot.  The first K slots are then the K smallest
+// distinct keys for any K <= KM.
 template <int KM>
 __device__ __forceinline__ void topk_insert_minmax(uint32_t (&lst)[KM], uint32_t c) {
 #pragma unroll
   for (int k = 0; k < KM; ++k) {
-    c = lst[k] == c ? ~0u : c;
-    const uint32_t lo = min(lst[k], c), hi = max(lst[k], c);
-    lst[k] = lo;
-    c = hi;
+    const uint32_t l = lst[k];
+    const uint32_t e = absdiff_m1(l, c);
+    lst[k] = min(l, c);
+    c = max(max(l, c), e);
+  }
+}
+
+// Sorts 8 keys ascending (a 19-comparator network of depth 6).
+__device__ __forceinline__ void sort8(uint32_t (&v)[8]) {
+  constexpr int net[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
+                              {4, 5}, {6, 7}, {2, 4}, {3, 5}, {1, 4}, {3, 6}, {1, 2}, {3, 4}, {5, 6}};
+#pragma unroll
+  for (int c = 0; c < 19; ++c) {
+    const uint32_t x = v[net[c][0]], y = v[net[c][1]];
+    v[net[c][0]] = min(x, y);
+    v[net[c][1]] = max(x, y);
   }
 }
 
@@ -121,6 +144,8 @@ __device__ __forceinline__ void load_window(const uint64_t *__restrict__ srt, in
     if (pos < lo || pos > hi) w[s] = ~0ull;
   }
 }
+
+constexpr uint32_t kKeyD2Max = 127;  // squared-distance field of the 31-bit keys
 
 struct MergeArgs {
   DirTable dt;
@@ -158,9 +183,11 @@ __device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int wind
 // direction's 2*WT+1 window items (the centre gives the point's own code) are
 // then loaded as one batch and consumed (prefetching the next direction's
 // window would raise the register count from 83 to 109 and the occupancy from
-// six to four waves per SIMD, which measured slower); candidates are 32-bit
-// keys (min(d2, 255) << 24 | j), exact whenever no kept entry has a clamped
-// distance, else the point is redone with 64-bit keys.
+// six to four waves per SIMD, which measured slower); candidates are 31-bit
+// keys (min(d2, 127) << 24 | j), exact whenever no kept entry has a clamped
+// distance, else the point is redone with 64-bit keys.  The first
+// direction's candidates are distinct points and the list is still empty, so
+// with w = 4 they are sorted by a network instead of inserted one by one.
 template <int KM, int WT>
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *__restrict__ sorted,
                                                   const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
@@ -193,6 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
         const int r = s_rank[d][t];
         const DirConst dc = dir_const(s_dir[d], a.dt.bits);
         uint64_t cur[2 * WT + 1];
+        uint32_t kc[2 * WT];
         // Wave-uniform: when every window of the wave lies inside the
         // cloud, the items load from one base address with no clamping and
         // no empty slots.
@@ -202,28 +230,35 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
           for (int s = 0; s <= 2 * WT; ++s) cur[s] = wp[s];
           const CodeFields fi = code_fields((uint32_t)(cur[WT] >> 32), dc);
 #pragma unroll
-          for (int s = 0; s <= 2 * WT; ++s) {
-            if (s != WT) {
-              const uint32_t d2 = code_dist2(fi, (uint32_t)(cur[s] >> 32), dc);
-              topk_insert_minmax<KM>(key, (min(d2, 255u) << 24) | (uint32_t)cur[s]);
-            }
+          for (int s = 0; s < 2 * WT; ++s) {
+            const uint64_t it = cur[s < WT ? s : s + 1];
+            const uint32_t d2 = code_dist2(fi, (uint32_t)(it >> 32), dc);
+            kc[s] = (min(d2, kKeyD2Max) << 24) | (uint32_t)it;
           }
         } else {
           load_window<WT>(srt, r, lo, hi, cur);
           const CodeFields fi = code_fields((uint32_t)(cur[WT] >> 32), dc);
 #pragma unroll
-          for (int s = 0; s <= 2 * WT; ++s) {
-            if (s != WT) {
-              const uint32_t d2 = code_dist2(fi, (uint32_t)(cur[s] >> 32), dc);
-              const uint32_t kc = cur[s] == ~0ull ? ~0u : ((min(d2, 255u) << 24) | (uint32_t)cur[s]);
-              topk_insert_minmax<KM>(key, kc);
-            }
+          for (int s = 0; s < 2 * WT; ++s) {
+            const uint64_t it = cur[s < WT ? s : s + 1];
+            const uint32_t d2 = code_dist2(fi, (uint32_t)(it >> 32), dc);
+            kc[s] = it == ~0ull ? ~0u : ((min(d2, kKeyD2Max) << 24) | (uint32_t)it);
           }
         }
+        if constexpr (WT == 4) {
+          if (d == 0) {
+            sort8(kc);
+#pragma unroll
+            for (int k = 0; k < 8 && k < KM; ++k) key[k] = kc[k];
+            continue;
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 2 * WT; ++s) topk_insert_minmax<KM>(key, kc[s]);
       }
       bool clamped = false;
 #pragma unroll
-      for (int k = 0; k < KM; ++k) clamped |= (k < K) & (key[k] != ~0u) & ((key[k] >> 24) == 255u);
+      for (int k = 0; k < KM; ++k) clamped |= (k < K) & (key[k] != ~0u) & ((key[k] >> 24) == kKeyD2Max);
       if (clamped) {
         select_exact<KM>(a, i, lo, hi, WT, s_dir, sorted, rank, lst);
       } else {
