@@ -185,9 +185,11 @@ __device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int wind
 // window would raise the register count from 83 to 109 and the occupancy from
 // six to four waves per SIMD, which measured slower); candidates are 31-bit
 // keys (min(d2, 127) << 24 | j), exact whenever no kept entry has a clamped
-// distance, else the point is redone with 64-bit keys.  The first
-// direction's candidates are distinct points and the list is still empty, so
-// with w = 4 they are sorted by a network instead of inserted one by one.
+// distance, else the point is redone with 64-bit keys.  With w = 4 each
+// direction's 8 candidates are first sorted by a network: the first
+// direction's (distinct points, empty list) are the list, and later ones are
+// inserted in ascending order until no lane of the wave has one left that
+// could enter its list.
 template <int KM, int WT>
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *__restrict__ sorted,
                                                   const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
@@ -246,15 +248,24 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
           }
         }
         if constexpr (WT == 4) {
+          sort8(kc);
           if (d == 0) {
-            sort8(kc);
 #pragma unroll
             for (int k = 0; k < 8 && k < KM; ++k) key[k] = kc[k];
             continue;
           }
-        }
+          // Sorted candidates: once no lane's next one is below its last
+          // slot, none of the rest can enter any list (the slots only
+          // decrease).
 #pragma unroll
-        for (int s = 0; s < 2 * WT; ++s) topk_insert_minmax<KM>(key, kc[s]);
+          for (int s = 0; s < 8; ++s) {
+            if (__builtin_amdgcn_ballot_w64(kc[s] < key[KM - 1]) == 0) break;
+            topk_insert_minmax<KM>(key, kc[s]);
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < 2 * WT; ++s) topk_insert_minmax<KM>(key, kc[s]);
+        }
       }
       bool clamped = false;
 #pragma unroll
