@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 2
+#define FGBD_ABI_VERSION 3
 
 /* Largest number of clouds in one fgbd_denoise_batched call. */
 #define FGBD_MAX_BATCH 64
@@ -64,6 +64,9 @@ typedef enum {
 #define FGBD_ST_NO_PATCH 2    /* no point had P neighbours: sigma_est set to 0 (Sec. 2.3)    */
 #define FGBD_ST_BAD_OFFSETS 4 /* batched offsets did not start at 0, decreased, or exceeded
                                  n_total: they were clamped into range before use           */
+#define FGBD_ST_SWEEP_STALL 8 /* the sweeps run inside one launch waited over half a second
+                                 for each other (the GPU was shared with work that kept
+                                 blocks from starting): rgb_out is not valid               */
 
 /* Parameters of one run.  fgbd_default_params gives the values used for 1M-point
  * frames (b = 10, L = 8, w = 4, K = 8). */
@@ -212,15 +215,24 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
 /* Launch schedule of the per-cloud kernels: the largest grid, in blocks of
  * 256 threads, of (merge_blocks) the neighbour merge and edge weights,
  * (noise_blocks) the patch statistics and (sweep_blocks) the filter sweeps
- * and finalise.  Defaults 1024 each.  A schedule changes no result beyond
- * the rounding order of FP64 sums (block partials); it is a property of the
- * context and applies to every later call on it.  Valid ranges:
- * merge_blocks and sweep_blocks 64..4096, noise_blocks 64..1024. */
+ * and finalise; and (sweep_launches) how many of the up to q_max filter
+ * sweeps of eq. 6 are enqueued as launches of their own.  The sweeps after
+ * those run in one launch whose blocks wait for each other between sweeps
+ * (the grid is sized to be resident on the device at once), which returns at
+ * once when every cloud's selection has already finished (a launch that
+ * finds the selection finished still costs about two microseconds; waiting
+ * for all blocks costs far more than a launch boundary, so the count should
+ * cover the sweeps a workload usually needs).  When the sweep grid cannot be
+ * resident on the device at once, every sweep is a launch of its own.  Defaults 1024, 1024, 1024 and 8.  A schedule changes no result
+ * beyond the rounding order of FP64 sums (block partials); it is a property
+ * of the context and applies to every later call on it.  Valid ranges:
+ * merge_blocks and sweep_blocks 64..4096, noise_blocks 64..1024,
+ * sweep_launches 1..1024. */
 typedef struct {
   int32_t merge_blocks;
   int32_t noise_blocks;
   int32_t sweep_blocks;
-  int32_t pad_;
+  int32_t sweep_launches;
 } fgbd_schedule;
 
 /* out, s: host. */
@@ -233,7 +245,8 @@ fgbd_status fgbd_set_schedule(fgbd_ctx ctx, const fgbd_schedule *s);
  * weights, then patch statistics and the noise solve, then sweeps and
  * finalise), `reps` timed
  * runs per candidate after one warm-up, times every kernel with HIP events,
- * and keeps the fastest sizes in the context.  Blocks the host until the runs
+ * then times whole calls for each candidate count of separate sweep
+ * launches, and keeps the fastest schedule in the context.  Blocks the host until the runs
  * finish, so it must not be captured; tune once per workload shape, then
  * capture or stream.  The caller's own profiling counters are kept.
  * reps: 1..100;  chosen: optional host output of the selected schedule. */

@@ -206,6 +206,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a, Segs *__restrict__ s
     sg->n = s_start[B];
     sg->ntiles = tiles;
     sg->status = bad ? FGBD_ST_BAD_OFFSETS : 0;
+    sg->sweep_barrier = 0u;
   }
   __syncthreads();
   if (t <= B) {
@@ -394,6 +395,7 @@ Run make_run(fgbd_ctx ctx, const Plan &pl, char *ws, const fgbd_params &prm, int
   r.prm = prm;
   r.stream = s;
   r.pf = ctx->profile ? pf : nullptr;
+  r.sweep_launches = ctx->tune.sweep_launches;
   return r;
 }
 
@@ -431,7 +433,22 @@ fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const i
                        const double *spread, const fgbd_result *noise, int select, int q_limit, float *rgb_out,
                        fgbd_result *res) {
   const int sweeps = q_limit > 0 ? q_limit : 1;
-  for (int q = 1; q <= sweeps; ++q) {
+  // with fixed q every sweep computes: all of them are separate launches
+  const int separate = (!select || sweeps < r.sweep_launches) ? sweeps : r.sweep_launches;
+  for (int q = 1; q <= separate; ++q) {
+    FGBD_PRE(r.pf, kSweep);
+    HIP_TRY(launch_sweep(r, col, p, dist2, rgb_in, spread, noise, res, select, q_limit, q), "sweep launch");
+    FGBD_POST(r.pf);
+  }
+  bool tail = separate < sweeps && sweep_tail_fits(r, dist2 != nullptr);
+  if (tail) {
+    FGBD_PRE(r.pf, kSweep);
+    const hipError_t e =
+        launch_sweep_tail(r, col, p, dist2, rgb_in, spread, noise, res, select, q_limit, separate + 1, sweeps);
+    FGBD_POST(r.pf);
+    HIP_TRY(e, "sweep loop launch");
+  }
+  for (int q = tail ? sweeps + 1 : separate + 1; q <= sweeps; ++q) {
     FGBD_PRE(r.pf, kSweep);
     HIP_TRY(launch_sweep(r, col, p, dist2, rgb_in, spread, noise, res, select, q_limit, q), "sweep launch");
     FGBD_POST(r.pf);
@@ -498,7 +515,7 @@ fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t bat
   if (batch < 1 || batch > kMaxSeg) return fail(FGBD_E_INVALID, "batch must be in 1..%d (got %d)", kMaxSeg, batch);
   if (!bytes) return fail(FGBD_E_INVALID, "bytes is NULL");
   // sized for the largest schedule, so any later fgbd_set_schedule fits
-  const Tune widest = {{kGridCapMax, kNoiseGridCapMax, kGridCapMax}};
+  const Tune widest = {{kGridCapMax, kNoiseGridCapMax, kGridCapMax}, kDefaultSweepLaunches};
   const size_t a = make_plan(n_max, batch, *p, widest).total;
   const size_t b = poly_workspace(n_max, p->k, kMaxPoly, kMaxGrid);
   *bytes = a > b ? a : b;
@@ -679,6 +696,8 @@ static fgbd_status check_schedule(const fgbd_schedule *s) {
     return fail(FGBD_E_INVALID, "merge_blocks and sweep_blocks must be in %d..%d", kGridCapMin, kGridCapMax);
   if (s->noise_blocks < kGridCapMin || s->noise_blocks > kNoiseGridCapMax)
     return fail(FGBD_E_INVALID, "noise_blocks must be in %d..%d", kGridCapMin, kNoiseGridCapMax);
+  if (s->sweep_launches < 1 || s->sweep_launches > kMaxSweepLaunches)
+    return fail(FGBD_E_INVALID, "sweep_launches must be in 1..%d", kMaxSweepLaunches);
   return FGBD_OK;
 }
 
@@ -688,7 +707,7 @@ fgbd_status fgbd_get_schedule(fgbd_ctx ctx, fgbd_schedule *out) {
   out->merge_blocks = ctx->tune.cap[kGridMerge];
   out->noise_blocks = ctx->tune.cap[kGridNoise];
   out->sweep_blocks = ctx->tune.cap[kGridSweep];
-  out->pad_ = 0;
+  out->sweep_launches = ctx->tune.sweep_launches;
   return ok();
 }
 
@@ -699,6 +718,7 @@ fgbd_status fgbd_set_schedule(fgbd_ctx ctx, const fgbd_schedule *s) {
   ctx->tune.cap[kGridMerge] = s->merge_blocks;
   ctx->tune.cap[kGridNoise] = s->noise_blocks;
   ctx->tune.cap[kGridSweep] = s->sweep_blocks;
+  ctx->tune.sweep_launches = s->sweep_launches;
   return ok();
 }
 
@@ -758,6 +778,32 @@ fgbd_status fgbd_autotune(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in,
       }
     }
   }
+  // separate sweep launches: a launch costs little, so it is timed over
+  // whole calls (profiling off) rather than per kernel
+  ctx->profile = false;
+  static const int kLaunchCand[] = {2, 4, 6, 8, 12, 16, 32};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (st == FGBD_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    st = fail(FGBD_E_HIP, "hipEventCreate failed");
+  double best_ms = 1e300;
+  for (int c = 0; c < 7 && st == FGBD_OK; ++c) {
+    ctx->tune = best;
+    ctx->tune.sweep_launches = kLaunchCand[c];
+    st = fgbd_denoise_batched(ctx, xyz, rgb_in, n_total, offsets, batch, params, rgb_out, res, stream);  // warm-up
+    if (st == FGBD_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(FGBD_E_HIP, "hipEventRecord failed");
+    for (int r = 0; r < reps && st == FGBD_OK; ++r)
+      st = fgbd_denoise_batched(ctx, xyz, rgb_in, n_total, offsets, batch, params, rgb_out, res, stream);
+    float t = 0.f;
+    if (st == FGBD_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      st = fail(FGBD_E_HIP, "timing the sweep launch count failed");
+    if (st == FGBD_OK && t < best_ms) {
+      best_ms = t;
+      best.sweep_launches = kLaunchCand[c];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   ctx->tune = best;
   ctx->profile = was_profiling;
   if (st != FGBD_OK) return st;

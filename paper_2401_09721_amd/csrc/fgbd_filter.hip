@@ -27,6 +27,20 @@
 // FSLR membership (spread_i <= kappa * sigma_est) in the fourth lane; its
 // partials also carry sum |y|^2 and |S|.  The finalising launch applies the
 // last sweep's partials the same way and writes the chosen iterate out.
+//
+// Launch count: a launch that finds the selection done still costs about two
+// microseconds, and q_max of them are enqueued.  So only the first few sweeps
+// (the schedule's sweep_launches) are launches of their own; the rest, if the
+// selection has not finished by then, run in one launch that loops over the
+// remaining sweeps, its blocks waiting for each other between sweeps (a
+// counter in device memory; the grid is sized to be resident at once).  That
+// launch first reads the done flags the last separate launch stored and
+// returns at once when every cloud is done, which is the usual case.  The
+// wait between sweeps costs far more than a kernel boundary on this GPU (it
+// writes back and invalidates the L2 of every XCD), so the loop is the
+// fallback, not the main path.  A plain launch is used because a cooperative
+// launch measured about 40 us of overhead even when it returned at once.
+// With fixed q the host knows the sweep count and launches every sweep.
 #include "fgbd_internal.h"
 
 namespace fgbd {
@@ -39,6 +53,8 @@ struct SweepArgs {
   int32_t select, q_limit;
   double kappa;
   int64_t buf_stride;  // float4 elements per buffer
+  unsigned long long *sums3;  // [3][B][slots][parts], rotating by sweep
+  SweepCtrl *ctrl;            // [2][B], ping-pong by sweep
   // weights computed in the sweep (the fused per-frame path): squared
   // distances, the merge launch's partials, its grid size, a fixed sigma_g
   // (<= 0: the mean edge length), and the results that receive sigma_g
@@ -50,6 +66,20 @@ struct SweepArgs {
 };
 
 constexpr int kSlotVals = kSweepSlots * kSweepParts;  // integers per cloud and sweep
+
+// The rotating buffers of sweep q (1-based): it reads the sums and state of
+// q-1, adds into the sums of q, clears the sums of q+1 and stores its state.
+struct SweepIO {
+  const unsigned long long *sums_prev;
+  unsigned long long *sums_out, *sums_clear;
+  const SweepCtrl *ctrl_prev;
+  SweepCtrl *ctrl_out;
+};
+__device__ __forceinline__ SweepIO sweep_io(const SweepArgs &a, int q) {
+  const size_t S = (size_t)a.sa.B * kSlotVals;
+  return {a.sums3 + ((q - 1) % 3) * S, a.sums3 + (q % 3) * S, a.sums3 + ((q + 1) % 3) * S,
+          a.ctrl + ((q - 1) & 1) * a.sa.B, a.ctrl + (q & 1) * a.sa.B};
+}
 
 constexpr double kFix = 4096.0;  // fixed-point scale of the energy sums (2^12)
 
@@ -145,34 +175,37 @@ __device__ __forceinline__ void add_sums(unsigned long long (&v)[kSweepParts], u
   }
 }
 
+template <bool D2>
+struct SweepLds {
+  unsigned long long red[4 * kSweepParts];
+  double exp[D2 ? kExpTable : 1];
+  double dred[8];
+};
+
+// One sweep (number q, buffers io) by one block of cloud sb.s.  Every thread
+// of the block calls it; it returns without touching the colours when the
+// cloud's selection is already done (uniform over the block).
 // D2: the row weights come from the squared distances (eq. 4, the graph
 // builder's own arithmetic) instead of a stored p.
 template <int KT, bool FIRST, bool D2>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__restrict__ col,
-                                                  const float *__restrict__ p, const float *__restrict__ rgb_in,
-                                                  float4 *__restrict__ xbuf, const double *__restrict__ spread,
-                                                  const fgbd_result *__restrict__ noise,
-                                                  const unsigned long long *__restrict__ sums_prev,
-                                                  unsigned long long *__restrict__ sums_out,
-                                                  unsigned long long *__restrict__ sums_clear,
-                                                  const SweepCtrl *__restrict__ ctrl_prev,
-                                                  SweepCtrl *__restrict__ ctrl_out) {
-  __shared__ unsigned long long s_red[4 * kSweepParts];
-  __shared__ double s_exp[D2 ? kExpTable : 1];
-  __shared__ double s_dred[8];
+__device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &sb, const SweepIO &io,
+                                           const int32_t *__restrict__ col, const float *__restrict__ p,
+                                           const float *__restrict__ rgb_in, float4 *__restrict__ xbuf,
+                                           const double *__restrict__ spread, const fgbd_result *__restrict__ noise,
+                                           SweepLds<D2> &lds) {
   const int K = KT > 0 ? KT : a.k;
   constexpr int KB = KT > 0 ? KT : kMaxK;  // slots per row held in registers
-  const SegBlock sb = seg_block(a.sa, kGridSweep);
-  sums_prev += (size_t)sb.s * kSlotVals;
-  sums_out += (size_t)sb.s * kSlotVals;
-  sums_clear += (size_t)sb.s * kSlotVals;
+  const unsigned long long *sums_prev = io.sums_prev + (size_t)sb.s * kSlotVals;
+  unsigned long long *sums_out = io.sums_out + (size_t)sb.s * kSlotVals;
+  unsigned long long *sums_clear = io.sums_clear + (size_t)sb.s * kSlotVals;
+  SweepCtrl *ctrl_out = io.ctrl_out;
   SweepCtrl c;
   if (FIRST) {
     c.sigma_g = 0.0;
     if (D2) {
       int mf, mc;
       seg_blocks_of(a.sa, kGridMerge, sb.s, a.merge_grid, &mf, &mc);
-      c.sigma_g = cloud_sigma_g(a.merge_part + 2 * mf, mc, a.sigma_g_fixed, s_dred);
+      c.sigma_g = cloud_sigma_g(a.merge_part + 2 * mf, mc, a.sigma_g_fixed, lds.dred);
       if (sb.lb == 0 && threadIdx.x == 0) a.res[sb.s].sigma_g = c.sigma_g;
     }
     c.sigma_est = a.select ? noise[sb.s].sigma_est : 0.0;
@@ -191,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
     c.q_limit = a.q_limit;
     c.fslr = (a.select && a.kappa > 0.0) ? 1 : 0;
   } else {
-    load_state(c, ctrl_prev + sb.s, sums_prev, (int)(sb.end - sb.begin));
+    load_state(c, io.ctrl_prev + sb.s, sums_prev, (int)(sb.end - sb.begin));
   }
   if (sb.lb == 0) {
     if (threadIdx.x == 0) ctrl_out[sb.s] = c;
@@ -199,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
   }
   if (c.done) return;
   if (D2) {
-    fill_exp_table(c.sigma_g, s_exp);
+    fill_exp_table(c.sigma_g, lds.exp);
     __syncthreads();
   }
 
@@ -245,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
           dv[k] = k < K ? a.dist2[i * K + k] : 0;
         }
       }
-      row_weights<KB>(cc, dv, c.sigma_g, s_exp, ww);
+      row_weights<KB>(cc, dv, c.sigma_g, lds.exp, ww);
     } else if (KT == 8) {
       const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
       const float4 *pr = reinterpret_cast<const float4 *>(p + i * 8);
@@ -297,7 +330,85 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, const int32_t *__
       v[4] += member != 0.0f ? 1ull : 0ull;
     }
   }
-  add_sums(v, sums_out, sb.lb % kSweepSlots, s_red);
+  add_sums(v, sums_out, sb.lb % kSweepSlots, lds.red);
+}
+
+template <int KT, bool FIRST, bool D2>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int q, const int32_t *__restrict__ col,
+                                                  const float *__restrict__ p, const float *__restrict__ rgb_in,
+                                                  float4 *__restrict__ xbuf, const double *__restrict__ spread,
+                                                  const fgbd_result *__restrict__ noise) {
+  __shared__ SweepLds<D2> lds;
+  const SegBlock sb = seg_block(a.sa, kGridSweep);
+  sweep_step<KT, FIRST, D2>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
+}
+
+// Waits until every block of the grid has arrived `epoch` times at this
+// barrier (count starts at 0 for the launch), with this block's writes
+// released before its arrival and the others' acquired after.  The wait is
+// bounded by `limit` ticks of the constant-rate clock; false when it gave up.
+__device__ bool grid_barrier(uint32_t *count, uint32_t epoch, long long limit, int *s_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = epoch * gridDim.x;
+    const long long t0 = wall_clock64();
+    int ok = 1;
+    while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (wall_clock64() - t0 > limit) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// True when the selection of every cloud is done in states[0..B).  Each wave
+// reads the B flags (one per lane) and votes, so the answer is uniform.
+__device__ __forceinline__ bool all_clouds_done(const SweepCtrl *states, int B) {
+  const int l = (int)lane_id();
+  const bool open = l < B && !states[l].done;
+  return __builtin_amdgcn_ballot_w64(open) == 0;
+}
+
+// Sweeps q0..q_last in one launch (same grid and block-to-cloud map as the
+// separate launches; all blocks resident), every block waiting for all
+// others after each sweep.  States are left where the finalising launch looks
+// for them: in the buffer of q_last.  If a wait gives up, every block's cloud
+// is flagged FGBD_ST_SWEEP_STALL and the loop ends.
+template <int KT, bool D2>
+__global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int q_last, uint32_t *barrier,
+                                                       long long wait_limit, const int32_t *__restrict__ col,
+                                                       const float *__restrict__ p, const float *__restrict__ rgb_in,
+                                                       float4 *__restrict__ xbuf, const double *__restrict__ spread,
+                                                       const fgbd_result *__restrict__ noise) {
+  __shared__ SweepLds<D2> lds;
+  __shared__ int s_flag;
+  const SegBlock sb = seg_block(a.sa, kGridSweep);
+  const int B = a.sa.B;
+  // state at the start of the last separate sweep, written by that launch
+  const SweepCtrl *last = a.ctrl + ((q0 - 1) & 1) * B;
+  int q = q0;
+  bool done = all_clouds_done(last, B);
+  uint32_t epoch = 0;
+  while (!done && q <= q_last) {
+    sweep_step<KT, false, D2>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
+    if (!grid_barrier(barrier, ++epoch, wait_limit, &s_flag)) {
+      if (threadIdx.x == 0) atomicOr(&a.res[sb.s].status, FGBD_ST_SWEEP_STALL);
+      return;
+    }
+    last = a.ctrl + (q & 1) * B;
+    done = all_clouds_done(last, B);
+    ++q;
+  }
+  // finished early: the finalising launch reads the states of q_last
+  if (done && sb.lb == 0 && threadIdx.x == 0) a.ctrl[(q_last & 1) * B + sb.s] = last[sb.s];
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_stride, const float *__restrict__ rgb_in,
@@ -335,19 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
   }
 }
 
-}  // namespace
-
-template <int KT, bool FIRST, bool D2>
-void sweep_kernel(int nb, hipStream_t st, const SweepArgs &a, const int32_t *col, const float *p,
-                  const float *rgb_in, float4 *xbuf, const double *spread, const fgbd_result *noise,
-                  const unsigned long long *sp, unsigned long long *so, unsigned long long *sc,
-                  const SweepCtrl *cp, SweepCtrl *co) {
-  k_sweep<KT, FIRST, D2><<<nb, kBlock, 0, st>>>(a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
-}
-
-hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
-                        const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
-                        int select, int q_limit, int q) {
+SweepArgs sweep_args(const Run &r, const int32_t *dist2, fgbd_result *res, int select, int q_limit) {
   SweepArgs a;
   a.sa = r.sa;
   a.k = r.prm.k;
@@ -355,32 +454,100 @@ hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const 
   a.q_limit = q_limit;
   a.kappa = r.prm.fslr_kappa;
   a.buf_stride = r.pl.n_cap;
+  a.sums3 = r.b.sums;
+  a.ctrl = r.b.ctrl;
   a.dist2 = dist2;
   a.merge_part = r.b.merge_part;
   a.merge_grid = r.pl.grid[kGridMerge];
   a.sigma_g_fixed = r.prm.sigma_g;
   a.res = res;
-  const size_t S = (size_t)r.pl.B * kSlotVals;
-  unsigned long long *sums3 = r.b.sums;
-  const unsigned long long *sp = sums3 + ((q - 1) % 3) * S;
-  unsigned long long *so = sums3 + (q % 3) * S;
-  unsigned long long *sc = sums3 + ((q + 1) % 3) * S;
-  const SweepCtrl *cp = r.b.ctrl + ((q - 1) & 1) * r.pl.B;
-  SweepCtrl *co = r.b.ctrl + (q & 1) * r.pl.B;
-  float4 *xbuf = r.b.xbuf;
+  return a;
+}
+
+template <int KT, bool FIRST, bool D2>
+void sweep_kernel(int nb, hipStream_t st, const SweepArgs &a, int q, const int32_t *col, const float *p,
+                  const float *rgb_in, float4 *xbuf, const double *spread, const fgbd_result *noise) {
+  k_sweep<KT, FIRST, D2><<<nb, kBlock, 0, st>>>(a, q, col, p, rgb_in, xbuf, spread, noise);
+}
+
+// Per device: blocks of k_sweep_tail<KT, D2> resident at once, and ticks of
+// the constant-rate clock in half a second.
+constexpr int kMaxDevices = 64;
+template <int KT, bool D2>
+int tail_capacity() {
+  static int cap[kMaxDevices];  // 0: not yet queried
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+  if (cap[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_sweep_tail<KT, D2>, kBlock, 0) !=
+            hipSuccess)
+      cap[dev] = -1;
+    else
+      cap[dev] = cus * per_cu > 0 ? cus * per_cu : -1;
+  }
+  return cap[dev];
+}
+long long half_second_ticks() {
+  static long long ticks[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 50000000ll;
+  if (ticks[dev] == 0) {
+    int khz = 0;
+    ticks[dev] = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0
+                     ? (long long)khz * 500
+                     : 50000000ll;
+  }
+  return ticks[dev];
+}
+
+template <int KT, bool D2>
+hipError_t tail_kernel(int nb, hipStream_t st, const SweepArgs &a, int q0, int q_last, uint32_t *barrier,
+                       const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf, const double *spread,
+                       const fgbd_result *noise) {
+  k_sweep_tail<KT, D2><<<nb, kBlock, 0, st>>>(a, q0, q_last, barrier, half_second_ticks(), col, p, rgb_in, xbuf,
+                                              spread, noise);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
+                        const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
+                        int select, int q_limit, int q) {
+  const SweepArgs a = sweep_args(r, dist2, res, select, q_limit);
   const int nb = r.pl.grid[kGridSweep];
-  hipStream_t st = r.stream;
   const bool first = q == 1, d2 = dist2 != nullptr;
-  using Fn = void (*)(int, hipStream_t, const SweepArgs &, const int32_t *, const float *, const float *, float4 *,
-                      const double *, const fgbd_result *, const unsigned long long *, unsigned long long *,
-                      unsigned long long *, const SweepCtrl *, SweepCtrl *);
+  using Fn = void (*)(int, hipStream_t, const SweepArgs &, int, const int32_t *, const float *, const float *,
+                      float4 *, const double *, const fgbd_result *);
   static const Fn table[2][2][2] = {
       {{sweep_kernel<0, false, false>, sweep_kernel<0, false, true>},
        {sweep_kernel<0, true, false>, sweep_kernel<0, true, true>}},
       {{sweep_kernel<8, false, false>, sweep_kernel<8, false, true>},
        {sweep_kernel<8, true, false>, sweep_kernel<8, true, true>}}};
-  table[a.k == 8][first][d2](nb, st, a, col, p, rgb_in, xbuf, spread, noise, sp, so, sc, cp, co);
+  table[a.k == 8][first][d2](nb, r.stream, a, q, col, p, rgb_in, r.b.xbuf, spread, noise);
   return hipGetLastError();
+}
+
+bool sweep_tail_fits(const Run &r, bool d2) {
+  using Fn = int (*)();
+  static const Fn table[2][2] = {{tail_capacity<0, false>, tail_capacity<0, true>},
+                                 {tail_capacity<8, false>, tail_capacity<8, true>}};
+  return table[r.prm.k == 8][d2]() >= r.pl.grid[kGridSweep];
+}
+
+hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
+                             const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
+                             int select, int q_limit, int q0, int q_last) {
+  const SweepArgs a = sweep_args(r, dist2, res, select, q_limit);
+  const int nb = r.pl.grid[kGridSweep];
+  using Fn = hipError_t (*)(int, hipStream_t, const SweepArgs &, int, int, uint32_t *, const int32_t *,
+                            const float *, const float *, float4 *, const double *, const fgbd_result *);
+  static const Fn table[2][2] = {{tail_kernel<0, false>, tail_kernel<0, true>},
+                                 {tail_kernel<8, false>, tail_kernel<8, true>}};
+  return table[a.k == 8][dist2 != nullptr](nb, r.stream, a, q0, q_last, &r.b.segs->sweep_barrier, col, p, rgb_in,
+                                           r.b.xbuf, spread, noise);
 }
 
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,

@@ -176,6 +176,8 @@ struct Segs {
   int32_t n;       // start[B]
   int32_t ntiles;  // radix tiles in use
   int32_t status;  // FGBD_ST_BAD_OFFSETS when the offsets had to be clamped
+  uint32_t sweep_barrier;  // arrival counter of the in-launch sweep loop (0 at setup)
+  uint32_t pad_[3];
   int32_t start[kMaxSeg + 1];
   int32_t tile_first[kMaxSeg + 1];
   int32_t blk_first[kNumGrids][kMaxSeg + 1];
@@ -368,11 +370,16 @@ constexpr int kSweepSlots = 64;  // atomic slots per cloud and sum (spread to li
 constexpr int kSweepMaxGrid = 1024;
 constexpr int kScanThreads = 1024;
 
-// Largest grid (blocks) of each per-cloud grid kind; chosen by the autotuner.
+// Largest grid (blocks) of each per-cloud grid kind, and the number of
+// filter sweeps enqueued as launches of their own (the rest run in one
+// cooperative launch); chosen by the autotuner.
 struct Tune {
   int32_t cap[kNumGrids];
+  int32_t sweep_launches;
 };
-constexpr Tune kDefaultTune = {{kMaxGrid, kMaxGrid, kMaxGrid}};
+constexpr int kDefaultSweepLaunches = 8;
+constexpr int kMaxSweepLaunches = 1024;
+constexpr Tune kDefaultTune = {{kMaxGrid, kMaxGrid, kMaxGrid}, kDefaultSweepLaunches};
 
 Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune = kDefaultTune);
 
@@ -421,6 +428,7 @@ struct Run {
   fgbd_params prm;
   hipStream_t stream;
   Prof *pf;
+  int32_t sweep_launches;  // sweeps enqueued as launches of their own
 };
 
 // Segment table from device offsets (B+1 entries) or, with offsets == NULL,
@@ -449,6 +457,19 @@ hipError_t launch_noise_solve(const Run &r, fgbd_result *res);
 hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
                         const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
                         int select, int q_limit, int q);
+
+// Whether the sweep grid of r fits on the current device at once, as the
+// in-launch sweep loop below needs (d2: the weights come from dist2).
+bool sweep_tail_fits(const Run &r, bool d2);
+
+// Sweeps q0..q_last in one launch whose blocks wait for each other between
+// sweeps, after separate launches of sweeps 1..q0-1 (same arguments as
+// launch_sweep); returns at once when every cloud's selection was done at the
+// start of sweep q0-1.  Uses the segment table's barrier counter (zeroed by
+// the setup launch of the call).
+hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
+                             const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
+                             int select, int q_limit, int q0, int q_last);
 
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,
                            float *rgb_out, fgbd_result *res);

@@ -24,8 +24,9 @@ FGBD_E_UNSUPPORTED = -5
 FGBD_ST_COORD_RANGE = 1
 FGBD_ST_NO_PATCH = 2
 FGBD_ST_BAD_OFFSETS = 4
+FGBD_ST_SWEEP_STALL = 8
 NUM_KERNELS = 9
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
            "finalize")
@@ -65,14 +66,15 @@ class Graph(ctypes.Structure):
 
 
 class Schedule(ctypes.Structure):
-    """fgbd_schedule: largest grids of the per-cloud kernels."""
+    """fgbd_schedule: largest grids of the per-cloud kernels and the number of
+    filter sweeps enqueued as launches of their own."""
 
     _fields_ = [("merge_blocks", ctypes.c_int32), ("noise_blocks", ctypes.c_int32),
-                ("sweep_blocks", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("sweep_blocks", ctypes.c_int32), ("sweep_launches", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"merge_blocks": self.merge_blocks, "noise_blocks": self.noise_blocks,
-                "sweep_blocks": self.sweep_blocks}
+                "sweep_blocks": self.sweep_blocks, "sweep_launches": self.sweep_launches}
 
 
 RESULT_DTYPE = np.dtype([("sigma_est", "<f8"), ("sigma_g", "<f8"), ("loss", "<f8"), ("q", "<i4"),
@@ -207,8 +209,12 @@ class Context:
         _check(lib().fgbd_get_schedule(self.handle, ctypes.byref(sc)))
         return sc.as_dict()
 
-    def set_schedule(self, merge_blocks: int, noise_blocks: int, sweep_blocks: int) -> None:
-        sc = Schedule(int(merge_blocks), int(noise_blocks), int(sweep_blocks), 0)
+    def set_schedule(self, merge_blocks: int, noise_blocks: int, sweep_blocks: int,
+                     sweep_launches: int | None = None) -> None:
+        """Set the launch schedule; sweep_launches None keeps the current count."""
+        if sweep_launches is None:
+            sweep_launches = self.schedule()["sweep_launches"]
+        sc = Schedule(int(merge_blocks), int(noise_blocks), int(sweep_blocks), int(sweep_launches))
         _check(lib().fgbd_set_schedule(self.handle, ctypes.byref(sc)))
 
     def autotune(self, xyz, rgb, offsets, params=None, reps: int = 3, out=None, res=None) -> dict:

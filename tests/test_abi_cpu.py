@@ -42,7 +42,7 @@ def test_status_constants_match_header():
 
 
 def test_version_and_defaults():
-    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 2
+    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 3
     p = fgbd.default_params()
     assert (p.bits, p.num_dirs, p.window, p.k, p.patch, p.q_max) == (10, 8, 4, 8, 0, 32)
     assert p.fslr_kappa == 2.0 and p.sigma_g == 0.0
@@ -172,16 +172,18 @@ def test_schedule_get_set(ctx):
     lib = fgbd.lib()
     sc = fgbd.Schedule()
     assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
-    assert sc.as_dict() == {"merge_blocks": 1024, "noise_blocks": 1024, "sweep_blocks": 1024}
-    new = fgbd.Schedule(2048, 512, 256, 0)
+    assert sc.as_dict() == {"merge_blocks": 1024, "noise_blocks": 1024, "sweep_blocks": 1024, "sweep_launches": 8}
+    new = fgbd.Schedule(2048, 512, 256, 5)
     assert lib.fgbd_set_schedule(ctx, ctypes.byref(new)) == 0
     assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
-    assert sc.as_dict() == {"merge_blocks": 2048, "noise_blocks": 512, "sweep_blocks": 256}
+    want = {"merge_blocks": 2048, "noise_blocks": 512, "sweep_blocks": 256, "sweep_launches": 5}
+    assert sc.as_dict() == want
     E = fgbd.FGBD_E_INVALID
-    for bad in [(32, 512, 512), (8192, 512, 512), (512, 2048, 512), (512, 512, 63), (512, 16, 512)]:
-        assert lib.fgbd_set_schedule(ctx, ctypes.byref(fgbd.Schedule(*bad, 0))) == E, bad
+    for bad in [(32, 512, 512, 8), (8192, 512, 512, 8), (512, 2048, 512, 8), (512, 512, 63, 8), (512, 16, 512, 8),
+                (512, 512, 512, 0), (512, 512, 512, 1025), (512, 512, 512, -3)]:
+        assert lib.fgbd_set_schedule(ctx, ctypes.byref(fgbd.Schedule(*bad))) == E, bad
     assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
-    assert sc.as_dict() == {"merge_blocks": 2048, "noise_blocks": 512, "sweep_blocks": 256}
+    assert sc.as_dict() == want
     assert lib.fgbd_set_schedule(ctx, None) == E
     assert lib.fgbd_get_schedule(None, ctypes.byref(sc)) == E
     # the workspace query covers every valid schedule

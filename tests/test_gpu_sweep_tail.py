@@ -1,0 +1,166 @@
+"""The filter sweeps after the schedule's separate launches run in one launch
+whose blocks wait for each other between sweeps.  Sums are integers and
+every point's arithmetic is the same, so any split of the sweeps between the
+two gives the same bits: checked for one cloud and for a batch whose clouds
+stop at different q, for the filter on a stored graph, for the generic K path
+(where the looping grid may not fit on the device and the sweeps fall back to
+separate launches), and for a captured graph."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2401_09721_amd import fgbd, synth  # noqa: E402
+
+from gpu_helpers import compare_denoise, dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def cloud(seed, target, sigma):
+    c = synth.random_shapes_cloud(seed, bits=8, n_ellipsoids=3, target=target, sigma=sigma)
+    return c.xyz, c.noisy
+
+
+def denoise_with(ctx, xyz, rgb, prm, launches, sweep_blocks=1024):
+    ctx.set_schedule(1024, 1024, sweep_blocks, launches)
+    out, res = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm, ctx=ctx)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), fgbd.read_result(res)
+
+
+def test_single_cloud_every_split_same_bits():
+    prm = fgbd.default_params(bits=8)
+    xyz, rgb = cloud(81, 20000, 35.0)
+    ctx = fgbd.Context("cuda")
+    ref, rr = denoise_with(ctx, xyz, rgb, prm, 1024)
+    assert rr["sweeps"] >= 4, rr  # enough sweeps for the splits below to reach the in-launch loop
+    for launches in (1, 2, 3, rr["sweeps"], rr["sweeps"] + 1):
+        out, r = denoise_with(ctx, xyz, rgb, prm, launches)
+        assert np.array_equal(out, ref), launches
+        assert r == rr, launches
+    out, r = denoise_with(ctx, xyz, rgb, prm, 1)
+    compare_denoise(out, r, xyz, rgb, prm)
+    ctx.close()
+
+
+def test_batch_clouds_stop_at_different_q():
+    prm = fgbd.default_params(bits=8)
+    clouds = [cloud(91, 12000, 35.0), cloud(92, 3000, 5.0), cloud(93, 8000, 20.0), cloud(94, 500, 30.0)]
+    xyz = np.concatenate([c[0] for c in clouds])
+    rgb = np.concatenate([c[1] for c in clouds])
+    offs = np.concatenate([[0], np.cumsum([len(c[0]) for c in clouds])]).astype(np.int64)
+    ctx = fgbd.Context("cuda")
+
+    def run(launches):
+        ctx.set_schedule(1024, 1024, 1024, launches)
+        out, res = fgbd.denoise_batched(dev(xyz, torch.int32), dev(rgb, torch.float32), dev(offs, torch.int64), prm,
+                                        ctx=ctx)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), fgbd.read_results(res)
+
+    ref, rr = run(1024)
+    assert len({r["sweeps"] for r in rr}) > 1, rr  # the clouds really stop at different sweeps
+    for launches in (1, 2, 4):
+        out, r = run(launches)
+        assert np.array_equal(out, ref), launches
+        assert r == rr, launches
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [8, 6])
+def test_filter_on_stored_graph_split(k):
+    """fgbd_filter on a stored graph (weights read from p): the selected
+    filter under every split, and fixed q (always one launch per sweep)."""
+    prm = fgbd.default_params(bits=8, k=k)
+    xyz, rgb = cloud(101, 15000, 35.0)
+    ctx = fgbd.Context("cuda")
+    g = fgbd.build_slg(dev(xyz, torch.int32), prm, ctx=ctx)
+    x = dev(rgb, torch.float32)
+    noise, spread, _ = fgbd.estimate_noise(g, x, prm, ctx=ctx)
+    sel, fixed = [], []
+    for launches in (1024, 1, 3):
+        ctx.set_schedule(1024, 1024, 1024, launches)
+        out, res = fgbd.filter(g, x, prm, noise=noise, spread=spread, ctx=ctx)
+        torch.cuda.synchronize()
+        sel.append((out.cpu().numpy(), fgbd.read_result(res)))
+        out, res = fgbd.filter(g, x, prm, q_fixed=7, ctx=ctx)
+        torch.cuda.synchronize()
+        r = fgbd.read_result(res)
+        assert r["q"] == 7 and r["sweeps"] == 7
+        fixed.append(out.cpu().numpy())
+    assert sel[0][1]["sweeps"] >= 4, sel[0][1]
+    for out, r in sel[1:]:
+        assert np.array_equal(out, sel[0][0]) and r == sel[0][1]
+    assert np.array_equal(fixed[0], fixed[1]) and np.array_equal(fixed[0], fixed[2])
+    ctx.close()
+
+
+@pytest.mark.parametrize("sweep_blocks", [1024, 256])
+def test_generic_k_split(sweep_blocks):
+    """K = 6 (the generic kernel, more registers): with 1024 sweep blocks the
+    looping grid may not fit and every sweep is a launch of its own; with 256
+    it fits.  Same bits either way."""
+    prm = fgbd.default_params(bits=8, k=6)
+    xyz, rgb = cloud(111, 12000, 35.0)
+    ctx = fgbd.Context("cuda")
+    ref, rr = denoise_with(ctx, xyz, rgb, prm, 1024, sweep_blocks)
+    out, r = denoise_with(ctx, xyz, rgb, prm, 1, sweep_blocks)
+    assert np.array_equal(out, ref) and r == rr
+    compare_denoise(out, r, xyz, rgb, prm)
+    ctx.close()
+
+
+def test_captured_graph_with_looped_sweeps():
+    """One capture with 2 separate sweep launches, replayed on frames that need
+    more sweeps than that: every replay equals the eager call."""
+    prm = fgbd.default_params(bits=8)
+    cap = 20000
+    ctx = fgbd.Context("cuda")
+    ctx.reserve(prm, cap, 1)
+    ctx.set_schedule(1024, 1024, 1024, 2)
+    xyz_s = torch.zeros((cap, 3), dtype=torch.int32, device="cuda")
+    rgb_s = torch.zeros((cap, 3), dtype=torch.float32, device="cuda")
+    off_s = torch.zeros(2, dtype=torch.int64, device="cuda")
+    out_s = torch.zeros((cap, 3), dtype=torch.float32, device="cuda")
+    res_s = fgbd.new_result("cuda", 1)
+
+    def load(xyz, rgb):
+        n = len(xyz)
+        xyz_s.zero_()
+        rgb_s.zero_()
+        xyz_s[:n] = dev(xyz, torch.int32)
+        rgb_s[:n] = dev(rgb, torch.float32)
+        off_s.copy_(torch.tensor([0, n], dtype=torch.int64))
+
+    frames = [cloud(121 + f, t, s) for f, (t, s) in enumerate([(16000, 35.0), (9000, 20.0), (19000, 30.0)])]
+    frames = [f for f in frames if len(f[0]) <= cap]
+    assert len(frames) >= 2
+    load(*frames[0])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=out_s, res=res_s)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=out_s, res=res_s)
+    torch.cuda.synchronize()
+    saw_tail = False
+    for f, (xyz, rgb) in enumerate(frames + frames[:1]):
+        load(xyz, rgb)
+        out_s.fill_(-7.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        got = out_s.cpu().numpy().copy()
+        got_r = fgbd.read_results(res_s)[0]
+        saw_tail |= got_r["sweeps"] > 2
+        ref_out = torch.full((cap, 3), -7.0, dtype=torch.float32, device="cuda")
+        ref_res = fgbd.new_result("cuda", 1)
+        fgbd.denoise_batched(xyz_s, rgb_s, off_s, prm, ctx=ctx, out=ref_out, res=ref_res)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, ref_out.cpu().numpy()), f"frame {f}: replay differs from eager"
+        assert got_r == fgbd.read_results(ref_res)[0]
+    assert saw_tail
+    ctx.close()
