@@ -99,19 +99,23 @@ __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const int32_t *
 // Per-tile digit counts.  Pass 0 makes the codes from the coordinates;
 // later passes read only the byte array of this pass's digits that the
 // previous downsweep wrote beside the items (16 digits per thread, one
-// 16-byte load).
+// 16-byte load).  The counts go to 8 LDS sub-histograms picked by lane
+// (rows 257 words apart), so lanes of one atomic instruction that share a
+// digit, or a bank, mostly hit different words; the 8 are summed at the end.
 __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const int32_t *__restrict__ xyz,
                                                                const uint8_t *__restrict__ digits,
                                                                uint32_t *__restrict__ hist,
                                                                fgbd_result *__restrict__ res) {
-  __shared__ uint32_t s_h[256];
+  constexpr int kSub = 8, kSubStride = 257;
+  __shared__ uint32_t s_hs[kSub * kSubStride];
   const int d = blockIdx.y;
   const int tile = blockIdx.x;
   TileInfo ti;
   if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
-  s_h[t] = 0;
+  for (int i = t; i < kSub * kSubStride; i += kSortThreads) s_hs[i] = 0;
   __syncthreads();
+  uint32_t *s_h = s_hs + (lane_id() & (kSub - 1)) * kSubStride;
   if (a.pass == 0) {
     const int wave = t / kWave;
     const int lane = (int)lane_id();
@@ -142,12 +146,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
     }
   }
   __syncthreads();
-  hist[((size_t)d * 256 + t) * a.row + tile] = s_h[t];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kSub; ++k) c += s_hs[k * kSubStride + t];
+  hist[((size_t)d * 256 + t) * a.row + tile] = c;
 }
 
 // Exclusive prefix of every (direction, digit) row of tile counts, and the
-// row total after the last tile: one wave per row, 64 tiles at a time with a
-// wave prefix sum.
+// row total after the last tile: one wave per row.  Lane l owns kScanRun
+// consecutive tiles of each 64 * kScanRun chunk; all of a chunk's loads are
+// issued before any is used (one memory round trip per chunk), then the
+// lane's run sum goes through a wave prefix sum.
+constexpr int kScanRun = 8;
 __global__ __launch_bounds__(256) void k_sort_scan(SortArgs a, uint32_t *__restrict__ hist) {
   const int row = blockIdx.x * 4 + threadIdx.x / kWave;
   if (row >= a.dt.num_dirs * 256) return;
@@ -155,16 +165,27 @@ __global__ __launch_bounds__(256) void k_sort_scan(SortArgs a, uint32_t *__restr
   const uint32_t lane = lane_id();
   uint32_t carry = 0;
   uint32_t *h = hist + (size_t)row * a.row;
-  for (int t0 = 0; t0 < ntiles; t0 += kWave) {
-    const int tile = t0 + (int)lane;
-    const uint32_t v = tile < ntiles ? h[tile] : 0u;
-    uint32_t x = v;
+  for (int t0 = 0; t0 < ntiles; t0 += kWave * kScanRun) {
+    const int first = t0 + (int)lane * kScanRun;
+    uint32_t v[kScanRun];
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      v[j] = first + j < ntiles ? h[first + j] : 0u;
+      run += v[j];
+    }
+    uint32_t x = run;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t y = __shfl_up(x, o, kWave);
       if (lane >= (uint32_t)o) x += y;
     }
-    if (tile < ntiles) h[tile] = carry + x - v;
+    uint32_t pre = carry + x - run;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+      if (first + j < ntiles) h[first + j] = pre;
+      pre += v[j];
+    }
     carry += __shfl(x, kWave - 1, kWave);
   }
   if (lane == 0) h[ntiles] = carry;
