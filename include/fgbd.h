@@ -223,9 +223,10 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
  * finds the selection finished still costs about two microseconds; waiting
  * for all blocks costs far more than a launch boundary, so the count should
  * cover the sweeps a workload usually needs).  When the sweep grid cannot be
- * resident on the device at once, every sweep is a launch of its own.  Defaults 1024, 1024, 1024 and 8.  A schedule changes no result
- * beyond the rounding order of FP64 sums (block partials); it is a property
- * of the context and applies to every later call on it.  Valid ranges:
+ * resident on the device at once, every sweep is a launch of its own.
+ * Defaults 2048, 1024, 1024 and 8.  A schedule changes no result beyond the
+ * rounding order of FP64 sums (block partials); it is a property of the
+ * context and applies to every later call on it.  Valid ranges:
  * merge_blocks and sweep_blocks 64..4096, noise_blocks 64..1024,
  * sweep_launches 1..1024. */
 typedef struct {

@@ -27,6 +27,10 @@ HIPFLAGS = [
     f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: otherwise the compiler keeps
+    # loop-carried accumulators in VGPRs and copies them to and from AGPRs
+    # around every MFMA, which serialises the loop on each result
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",

@@ -379,7 +379,8 @@ struct Tune {
 };
 constexpr int kDefaultSweepLaunches = 8;
 constexpr int kMaxSweepLaunches = 1024;
-constexpr Tune kDefaultTune = {{kMaxGrid, kMaxGrid, kMaxGrid}, kDefaultSweepLaunches};
+constexpr int kDefaultMergeGrid = 2048;  // the merge gains from more blocks than the other kernels
+constexpr Tune kDefaultTune = {{kDefaultMergeGrid, kMaxGrid, kMaxGrid}, kDefaultSweepLaunches};
 
 Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune = kDefaultTune);
 

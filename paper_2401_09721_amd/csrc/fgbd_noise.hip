@@ -430,73 +430,86 @@ typedef double v4f64 __attribute__((ext_vector_type(4)));
 
 // The same statistics with the tile's patch moments as one 16 x 16 FP64 Gram
 // matrix on the matrix cores (D + 3 <= 16).  Each patch row (one channel of
-// one patch) becomes the 16-vector of its D colour entries, three channel
-// indicators (1 in the row's own channel, for complete patches only) and
-// zeros; G = sum over rows of v v^T then holds sum a a^T (the D x D block),
-// the per-channel sums (columns D .. D+2 of the first D rows) and the patch
-// count (G[D][D]).  v_mfma_f64_16x16x4f64 adds four rows per instruction:
-// lane l supplies feature l % 16 of row l / 16 as both operands, and its
-// accumulator register i holds G[4 i + l / 16][l % 16].  Products of floats
-// are exact in FP64; the accumulation order is fixed.
+// one patch) becomes the vector of its D colour entries and three channel
+// indicators (1 in the row's own channel, for complete patches only), stored
+// in LDS as W = D + 3 floats; features W..15 are zero.  G = sum over rows of
+// v v^T then holds sum a a^T (the D x D block), the per-channel sums (columns
+// D .. D+2 of the first D rows) and the patch count (G[D][D]).
+// v_mfma_f64_16x16x4f64 adds four rows per instruction: lane l supplies
+// feature l % 16 of row l / 16 as both operands, and its accumulator register
+// i holds G[4 i + l / 16][l % 16].  Each wave keeps four accumulators and
+// issues four independent instructions per step (one instruction's result
+// is not waited for by the next), reading their operands from LDS without
+// branches; the four are added in a fixed order at the end.  Products of
+// floats are exact in FP64; the accumulation order is fixed.
 template <int PT, bool EIG3>
 __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
                                                        const float *__restrict__ rgb, double *__restrict__ spread,
                                                        float *__restrict__ eig3, double *__restrict__ part) {
   constexpr int D = PT + 1;
-  static_assert(D + 3 <= 16, "the Gram matrix holds D colour features and three indicators");
-  extern __shared__ float s_v[];  // [3 * TP][D] patch rows of the current tile
-  __shared__ uint8_t s_ok[kBlock];
-  __shared__ double s_g[4][256];
+  constexpr int W = D + 3;  // floats per LDS row
+  static_assert(W <= 16, "the Gram matrix holds D colour features and three indicators");
+  extern __shared__ float s_v[];  // [3 * TP][W] patch rows of the current tile; then the Gram sums
   const int t = threadIdx.x;
   const int TP = a.TP;
-  const int wave = t / kWave, lane = (int)lane_id();
+  // wave-uniform in a scalar register, so the row-group loop below is
+  // uniform and the accumulators stay in place across its iterations
+  const int wave = __builtin_amdgcn_readfirstlane(t / kWave), lane = (int)lane_id();
   const int f = lane % 16, rsub = lane / 16;
-  const int groups = 3 * TP / 4;  // four rows per instruction
-  v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+  const int fi = f < W ? f : W - 1;  // in-row feature read by this lane (zeroed when f >= W)
+  const int groups = 3 * TP / 4;     // four rows per instruction; a multiple of 16
+  constexpr int kWaves = kBlock / kWave;
+  v4f64 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = v4f64{0.0, 0.0, 0.0, 0.0};
 
   const SegBlock sb = seg_block(a.sa, kGridNoise);
   const Share sh = seg_share(sb, TP);
   for (int64_t tbase = sh.first; tbase < sh.end; tbase += sh.step) {
     if (t < TP) {
       const int64_t i = tbase + t;
-      float *r0 = s_v + (size_t)(3 * t + 0) * D;
-      float *r1 = s_v + (size_t)(3 * t + 1) * D;
-      float *r2 = s_v + (size_t)(3 * t + 2) * D;
+      float *r[3] = {s_v + (size_t)(3 * t + 0) * W, s_v + (size_t)(3 * t + 1) * W, s_v + (size_t)(3 * t + 2) * W};
       bool complete = false;
-      if (i < sh.end) complete = patch_point<PT, EIG3>(a, i, col, rgb, r0, r1, r2, spread, eig3);
-      s_ok[t] = complete ? 1 : 0;
-      if (!complete) {
+      if (i < sh.end) complete = patch_point<PT, EIG3>(a, i, col, rgb, r[0], r[1], r[2], spread, eig3);
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          r0[k] = 0.0f;
-          r1[k] = 0.0f;
-          r2[k] = 0.0f;
+      for (int c = 0; c < 3; ++c) {
+        if (!complete) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) r[c][k] = 0.0f;
         }
-        if (i < sh.end) {
-          spread[i] = __builtin_huge_val();
-          if (EIG3) {
-            eig3[3 * i + 0] = 0.0f;
-            eig3[3 * i + 1] = 0.0f;
-            eig3[3 * i + 2] = 0.0f;
-          }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r[c][D + k] = (complete && k == c) ? 1.0f : 0.0f;
+      }
+      if (!complete && i < sh.end) {
+        spread[i] = __builtin_huge_val();
+        if (EIG3) {
+          eig3[3 * i + 0] = 0.0f;
+          eig3[3 * i + 1] = 0.0f;
+          eig3[3 * i + 2] = 0.0f;
         }
       }
     }
     __syncthreads();
-    for (int g = wave; g < groups; g += kBlock / kWave) {
-      const int r = 4 * g + rsub;
-      const int pt = r / 3, ch = r - 3 * pt;
-      const float x = f < D ? s_v[r * D + (f < D ? f : 0)] : 0.0f;
-      const double v = f < D ? (double)x : ((f < D + 3 && s_ok[pt] && ch == f - D) ? 1.0 : 0.0);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    for (int g = wave; g < groups; g += 4 * kWaves) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float x = s_v[(4 * (g + u * kWaves) + rsub) * W + fi];
+        v[u] = f < W ? (double)x : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc[u], 0, 0, 0);
     }
     __syncthreads();
   }
 
   // the block's Gram matrix, then its partials entry-major:
-  // part[e * nblocks + block], entry 0 = patch count
+  // part[e * nblocks + block], entry 0 = patch count.  The sums reuse the
+  // row storage (4 waves x 256 doubles fit in 3 * TP * W floats).
+  double(*s_g)[256] = reinterpret_cast<double(*)[256]>(s_v);
+  const v4f64 tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) s_g[wave][(4 * i + rsub) * 16 + f] = acc[i];
+  for (int i = 0; i < 4; ++i) s_g[wave][(4 * i + rsub) * 16 + f] = tot[i];
   __syncthreads();
   const double gsum = (s_g[0][t] + s_g[1][t]) + (s_g[2][t] + s_g[3][t]);
   __syncthreads();
@@ -650,7 +663,11 @@ NoiseArgs make_args(const SegArgs &sa, int k, int P, bool want_eig3) {
 
 hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3) {
   const NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, eig3 != nullptr);
-  const size_t lds = (size_t)3 * a.TP * a.D * sizeof(float);
+  // k_noise: rows of D floats; k_noise_mfma: rows of D + 3 floats, and at
+  // least the 8 KB of its final sums
+  const size_t lds_rows = (size_t)3 * a.TP * a.D * sizeof(float);
+  const size_t lds_mfma = (size_t)3 * a.TP * (a.D + 3) * sizeof(float);
+  const size_t lds = a.P == 8 ? (lds_mfma > 8192 ? lds_mfma : 8192) : lds_rows;
   const int nb = r.pl.grid[kGridNoise];
   double *part = r.b.noise_part;
   hipStream_t st = r.stream;
