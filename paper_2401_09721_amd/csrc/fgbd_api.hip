@@ -129,10 +129,11 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_digits = take((size_t)pl.L * pl.stride);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
+  pl.off_p = take(N * pl.K * 4);
   pl.off_spread = take(N * 8);
   pl.off_xbuf = take(3 * N * 16);
   pl.off_merge_part = take((size_t)pl.grid[kGridMerge] * 2 * 8);
-  pl.off_noise_part = take((size_t)pl.grid[kGridNoise] * pl.E1 * 8);
+  pl.off_noise_acc = take((size_t)B * pl.E1 * kNoiseSlots * 8);
   pl.off_ctrl = take((size_t)2 * B * sizeof(SweepCtrl));
   pl.off_sweep_sums = take((size_t)3 * B * kSweepSlots * kSweepParts * 8);
   pl.total = off;
@@ -149,10 +150,11 @@ Bufs carve(char *ws, const Plan &pl) {
   b.digits = (uint8_t *)(ws + pl.off_digits);
   b.col = (int32_t *)(ws + pl.off_col);
   b.dist2 = (int32_t *)(ws + pl.off_dist2);
+  b.p = (float *)(ws + pl.off_p);
   b.spread = (double *)(ws + pl.off_spread);
   b.xbuf = (float4 *)(ws + pl.off_xbuf);
   b.merge_part = (double *)(ws + pl.off_merge_part);
-  b.noise_part = (double *)(ws + pl.off_noise_part);
+  b.noise_acc = (unsigned long long *)(ws + pl.off_noise_acc);
   b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
   b.sums = (unsigned long long *)(ws + pl.off_sweep_sums);
   return b;
@@ -168,9 +170,12 @@ struct SetupArgs {
   int32_t grid[kNumGrids];
   int32_t zero_result;
   int32_t sums_count;  // first sweep's sums to clear (uint64)
+  int32_t noise_count;  // noise moment accumulators to clear (uint64)
+  unsigned long long *noise_acc;
 };
 
-// All blocks clear the first sweep's sums; block 0 builds the segment table:
+// All blocks clear the first sweep's sums and the noise moment accumulators;
+// block 0 builds the segment table:
 // offsets clamped into a valid form (start[0] = 0, non-decreasing, at most
 // n_cap), radix tiles per cloud, and each per-cloud grid's block ranges
 // first(s) = floor(start[s] (G - B) / n) + s (at least one block per cloud).
@@ -181,6 +186,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a, Segs *__restrict__ s
   __shared__ int32_t s_bad;
   const int t = threadIdx.x;
   for (int i = blockIdx.x * blockDim.x + t; i < a.sums_count; i += gridDim.x * blockDim.x) sums1[i] = 0ull;
+  for (int i = blockIdx.x * blockDim.x + t; i < a.noise_count; i += gridDim.x * blockDim.x) a.noise_acc[i] = 0ull;
   if (blockIdx.x != 0) return;  // uniform over the block
   const int B = a.B;
   if (t <= B) s_raw[t] = a.offsets ? a.offsets[t] : (t == 0 ? 0 : a.n_host);
@@ -244,7 +250,10 @@ hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fg
   for (int g = 0; g < kNumGrids; ++g) a.grid[g] = r.pl.grid[g];
   a.zero_result = zero_result;
   a.sums_count = r.pl.B * kSweepSlots * kSweepParts;
-  int blocks = (a.sums_count + 256 * 8 - 1) / (256 * 8);
+  a.noise_count = r.pl.B * r.pl.E1 * kNoiseSlots;
+  a.noise_acc = r.b.noise_acc;
+  const int most = a.sums_count > a.noise_count ? a.sums_count : a.noise_count;
+  int blocks = (most + 256 * 8 - 1) / (256 * 8);
   blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
   // the first sweep adds into sums buffer 1 (see launch_sweep)
   k_setup<<<blocks, 256, 0, r.stream>>>(a, r.b.segs, r.b.sums + (size_t)a.sums_count, res);
@@ -426,9 +435,9 @@ fgbd_status run_noise(const Run &r, const int32_t *col, const float *rgb, double
 }
 
 // Sweeps and the final copy.  The first sweep's sums buffer was cleared by
-// the call's setup launch.  With dist2 given (p unused) the sweeps compute
-// the weights from the squared distances and the first one writes sigma_g
-// into res.
+// the call's setup launch.  With dist2 given, the first sweep derives sigma_g
+// (into res) and the weights from the squared distances and stores the
+// weights into p, which the later sweeps read.
 fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const int32_t *dist2, const float *rgb_in,
                        const double *spread, const fgbd_result *noise, int select, int q_limit, float *rgb_out,
                        fgbd_result *res) {
@@ -437,20 +446,21 @@ fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const i
   const int separate = (!select || sweeps < r.sweep_launches) ? sweeps : r.sweep_launches;
   for (int q = 1; q <= separate; ++q) {
     FGBD_PRE(r.pf, kSweep);
-    HIP_TRY(launch_sweep(r, col, p, dist2, rgb_in, spread, noise, res, select, q_limit, q), "sweep launch");
+    HIP_TRY(launch_sweep(r, col, p, q == 1 ? dist2 : nullptr, rgb_in, spread, noise, res, select, q_limit, q),
+            "sweep launch");
     FGBD_POST(r.pf);
   }
-  bool tail = separate < sweeps && sweep_tail_fits(r, dist2 != nullptr);
+  bool tail = separate < sweeps && sweep_tail_fits(r);
   if (tail) {
     FGBD_PRE(r.pf, kSweep);
     const hipError_t e =
-        launch_sweep_tail(r, col, p, dist2, rgb_in, spread, noise, res, select, q_limit, separate + 1, sweeps);
+        launch_sweep_tail(r, col, p, rgb_in, spread, noise, res, select, q_limit, separate + 1, sweeps);
     FGBD_POST(r.pf);
     HIP_TRY(e, "sweep loop launch");
   }
   for (int q = tail ? sweeps + 1 : separate + 1; q <= sweeps; ++q) {
     FGBD_PRE(r.pf, kSweep);
-    HIP_TRY(launch_sweep(r, col, p, dist2, rgb_in, spread, noise, res, select, q_limit, q), "sweep launch");
+    HIP_TRY(launch_sweep(r, col, p, nullptr, rgb_in, spread, noise, res, select, q_limit, q), "sweep launch");
     FGBD_POST(r.pf);
   }
   FGBD_PRE(r.pf, kFinalize);
@@ -578,7 +588,9 @@ fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *
     HIP_TRY(launch_setup(r, nullptr, 0, res, 2), "setup launch");
     return ok();
   }
-  // one cloud of host-known size: the kernels do not read the segment table
+  // one cloud of host-known size: the kernels do not read the segment table;
+  // the setup launch clears the moment accumulators
+  HIP_TRY(launch_setup(r, nullptr, n, nullptr, 0), "setup launch");
   if ((st = run_noise(r, g->col, rgb, patch_spread ? patch_spread : r.b.spread, eig3, res)) != FGBD_OK) return st;
   return ok();
 }
@@ -619,15 +631,16 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
 }
 
 // The fused path over the call's segments (one cloud of host-known size, or
-// B clouds from device offsets).  The weights are never stored: the sweeps
-// compute them from the squared distances (the noise estimate needs only
+// B clouds from device offsets).  No separate weights launch: the first sweep
+// derives sigma_g and turns the squared distances into the weights as it uses
+// them, and stores them for the later sweeps (the noise estimate needs only
 // the neighbour lists).
 static fgbd_status run_denoise(const Run &r, const int32_t *xyz, const float *rgb_in, float *rgb_out,
                                fgbd_result *res) {
   fgbd_status st;
   if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
   if ((st = run_noise(r, r.b.col, rgb_in, r.b.spread, nullptr, res)) != FGBD_OK) return st;
-  return run_filter(r, r.b.col, nullptr, r.b.dist2, rgb_in, r.b.spread, res, 1, r.prm.q_max, rgb_out, res);
+  return run_filter(r, r.b.col, r.b.p, r.b.dist2, rgb_in, r.b.spread, res, 1, r.prm.q_max, rgb_out, res);
 }
 
 fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n,

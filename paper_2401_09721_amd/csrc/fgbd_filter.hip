@@ -55,14 +55,16 @@ struct SweepArgs {
   int64_t buf_stride;  // float4 elements per buffer
   unsigned long long *sums3;  // [3][B][slots][parts], rotating by sweep
   SweepCtrl *ctrl;            // [2][B], ping-pong by sweep
-  // weights computed in the sweep (the fused per-frame path): squared
-  // distances, the merge launch's partials, its grid size, a fixed sigma_g
-  // (<= 0: the mean edge length), and the results that receive sigma_g
+  // weights derived by the first sweep (the fused per-frame path): the
+  // squared distances, the merge launch's partials, its grid size, a fixed
+  // sigma_g (<= 0: the mean edge length), the results that receive sigma_g,
+  // and where to store the weights for the later sweeps
   const int32_t *dist2;
   const double *merge_part;
   int32_t merge_grid;
   double sigma_g_fixed;
   fgbd_result *res;
+  float *p_out;
 };
 
 constexpr int kSlotVals = kSweepSlots * kSweepParts;  // integers per cloud and sweep
@@ -92,7 +94,7 @@ __device__ __forceinline__ int free_buffer(int in_buf, int best_buf) {
 }
 
 // Apply the sums of the sweep that produced x_{c.q+1} (written to out_buf).
-__device__ void advance(SweepCtrl &c, const double (&t)[kSweepParts], int n, int out_buf) {
+__device__ __forceinline__ void advance(SweepCtrl &c, const double (&t)[kSweepParts], int n, int out_buf) {
   if (c.q == 0) {  // partials of the first sweep also carry |y|^2 and |S|
     const int n_sel = (int)t[4];
     c.use_all = (!c.fslr || n_sel == 0) ? 1 : 0;
@@ -126,7 +128,7 @@ __device__ void advance(SweepCtrl &c, const double (&t)[kSweepParts], int n, int
 // previous sweep's integer sums (identical in every block).  Called by every
 // thread of the block; wave 0 loads the slots (one per lane) and reduces them
 // with shuffles.
-__device__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
+__device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
                            const unsigned long long *__restrict__ sums_prev, int n) {
   __shared__ unsigned long long s_tot[kSweepParts];
   c = *prev;
@@ -179,14 +181,16 @@ template <bool D2>
 struct SweepLds {
   unsigned long long red[4 * kSweepParts];
   double exp[D2 ? kExpTable : 1];
-  double dred[8];
+  double dred[D2 ? 8 : 1];
 };
 
 // One sweep (number q, buffers io) by one block of cloud sb.s.  Every thread
 // of the block calls it; it returns without touching the colours when the
 // cloud's selection is already done (uniform over the block).
-// D2: the row weights come from the squared distances (eq. 4, the graph
-// builder's own arithmetic) instead of a stored p.
+// D2 (first sweep only): sigma_g and the row weights come from the merge
+// partials and the squared distances (eq. 4, the graph builder's own
+// arithmetic) instead of a stored p; sigma_g goes to the results and the
+// weights into p_out for the later sweeps.
 template <int KT, bool FIRST, bool D2>
 __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &sb, const SweepIO &io,
                                            const int32_t *__restrict__ col, const float *__restrict__ p,
@@ -200,6 +204,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
   unsigned long long *sums_clear = io.sums_clear + (size_t)sb.s * kSlotVals;
   SweepCtrl *ctrl_out = io.ctrl_out;
   SweepCtrl c;
+  static_assert(FIRST || !D2, "only the first sweep derives the weights");
   if (FIRST) {
     c.sigma_g = 0.0;
     if (D2) {
@@ -279,6 +284,15 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
         }
       }
       row_weights<KB>(cc, dv, c.sigma_g, lds.exp, ww);
+      if (KT == 8) {
+        float4 *pr = reinterpret_cast<float4 *>(a.p_out + i * 8);
+        pr[0] = make_float4(ww[0], ww[1], ww[2], ww[3]);
+        pr[1] = make_float4(ww[4], ww[5], ww[6], ww[7]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+          if (k < K) a.p_out[i * K + k] = ww[k];
+      }
     } else if (KT == 8) {
       const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
       const float4 *pr = reinterpret_cast<const float4 *>(p + i * 8);
@@ -296,22 +310,29 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
       }
     }
     // Branch-free gathers: an empty slot (col = -1, weight 0) reads the point
-    // itself, so every load is issued before any is consumed.
-    float ar = 0.f, ag = 0.f, ab = 0.f;
+    // itself.  All neighbour loads are issued before any is consumed.
+    float gx[KB], gy[KB], gz[KB];
 #pragma unroll
-    for (int k = 0; k < (KT > 0 ? KT : kMaxK); ++k) {
+    for (int k = 0; k < KB; ++k) {
       const int64_t cj = cc[k] >= 0 ? (int64_t)cc[k] : i;
-      const float w = cc[k] >= 0 ? ww[k] : 0.0f;
       if (FIRST) {
-        ar = fmaf(w, rgb_in[3 * cj + 0], ar);
-        ag = fmaf(w, rgb_in[3 * cj + 1], ag);
-        ab = fmaf(w, rgb_in[3 * cj + 2], ab);
+        gx[k] = rgb_in[3 * cj + 0];
+        gy[k] = rgb_in[3 * cj + 1];
+        gz[k] = rgb_in[3 * cj + 2];
       } else {
         const float4 xc = xin[cj];
-        ar = fmaf(w, xc.x, ar);
-        ag = fmaf(w, xc.y, ag);
-        ab = fmaf(w, xc.z, ab);
+        gx[k] = xc.x;
+        gy[k] = xc.y;
+        gz[k] = xc.z;
       }
+    }
+    float ar = 0.f, ag = 0.f, ab = 0.f;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const float w = cc[k] >= 0 ? ww[k] : 0.0f;
+      ar = fmaf(w, gx[k], ar);
+      ag = fmaf(w, gy[k], ag);
+      ab = fmaf(w, gz[k], ab);
     }
     float orr = xr, og = xg, ob = xb;
     if (cc[0] >= 0) {
@@ -382,13 +403,13 @@ __device__ __forceinline__ bool all_clouds_done(const SweepCtrl *states, int B) 
 // others after each sweep.  States are left where the finalising launch looks
 // for them: in the buffer of q_last.  If a wait gives up, every block's cloud
 // is flagged FGBD_ST_SWEEP_STALL and the loop ends.
-template <int KT, bool D2>
+template <int KT>
 __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int q_last, uint32_t *barrier,
                                                        long long wait_limit, const int32_t *__restrict__ col,
                                                        const float *__restrict__ p, const float *__restrict__ rgb_in,
                                                        float4 *__restrict__ xbuf, const double *__restrict__ spread,
                                                        const fgbd_result *__restrict__ noise) {
-  __shared__ SweepLds<D2> lds;
+  __shared__ SweepLds<false> lds;
   __shared__ int s_flag;
   const SegBlock sb = seg_block(a.sa, kGridSweep);
   const int B = a.sa.B;
@@ -398,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
   bool done = all_clouds_done(last, B);
   uint32_t epoch = 0;
   while (!done && q <= q_last) {
-    sweep_step<KT, false, D2>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
+    sweep_step<KT, false, false>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
     if (!grid_barrier(barrier, ++epoch, wait_limit, &s_flag)) {
       if (threadIdx.x == 0) atomicOr(&a.res[sb.s].status, FGBD_ST_SWEEP_STALL);
       return;
@@ -446,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
   }
 }
 
-SweepArgs sweep_args(const Run &r, const int32_t *dist2, fgbd_result *res, int select, int q_limit) {
+SweepArgs sweep_args(const Run &r, const int32_t *dist2, float *p_out, fgbd_result *res, int select, int q_limit) {
   SweepArgs a;
   a.sa = r.sa;
   a.k = r.prm.k;
@@ -461,6 +482,7 @@ SweepArgs sweep_args(const Run &r, const int32_t *dist2, fgbd_result *res, int s
   a.merge_grid = r.pl.grid[kGridMerge];
   a.sigma_g_fixed = r.prm.sigma_g;
   a.res = res;
+  a.p_out = p_out;
   return a;
 }
 
@@ -470,10 +492,10 @@ void sweep_kernel(int nb, hipStream_t st, const SweepArgs &a, int q, const int32
   k_sweep<KT, FIRST, D2><<<nb, kBlock, 0, st>>>(a, q, col, p, rgb_in, xbuf, spread, noise);
 }
 
-// Per device: blocks of k_sweep_tail<KT, D2> resident at once, and ticks of
-// the constant-rate clock in half a second.
+// Per device: blocks of k_sweep_tail<KT> resident at once, and ticks of the
+// constant-rate clock in half a second.
 constexpr int kMaxDevices = 64;
-template <int KT, bool D2>
+template <int KT>
 int tail_capacity() {
   static int cap[kMaxDevices];  // 0: not yet queried
   int dev = 0;
@@ -481,7 +503,7 @@ int tail_capacity() {
   if (cap[dev] == 0) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_sweep_tail<KT, D2>, kBlock, 0) !=
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_sweep_tail<KT>, kBlock, 0) !=
             hipSuccess)
       cap[dev] = -1;
     else
@@ -502,12 +524,12 @@ long long half_second_ticks() {
   return ticks[dev];
 }
 
-template <int KT, bool D2>
+template <int KT>
 hipError_t tail_kernel(int nb, hipStream_t st, const SweepArgs &a, int q0, int q_last, uint32_t *barrier,
                        const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf, const double *spread,
                        const fgbd_result *noise) {
-  k_sweep_tail<KT, D2><<<nb, kBlock, 0, st>>>(a, q0, q_last, barrier, half_second_ticks(), col, p, rgb_in, xbuf,
-                                              spread, noise);
+  k_sweep_tail<KT><<<nb, kBlock, 0, st>>>(a, q0, q_last, barrier, half_second_ticks(), col, p, rgb_in, xbuf, spread,
+                                          noise);
   return hipGetLastError();
 }
 
@@ -516,38 +538,35 @@ hipError_t tail_kernel(int nb, hipStream_t st, const SweepArgs &a, int q0, int q
 hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
                         const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
                         int select, int q_limit, int q) {
-  const SweepArgs a = sweep_args(r, dist2, res, select, q_limit);
-  const int nb = r.pl.grid[kGridSweep];
   const bool first = q == 1, d2 = dist2 != nullptr;
+  if (d2 && !first) return hipErrorInvalidValue;  // only the first sweep derives the weights
+  // the first sweep of the fused path stores the weights it derives into p
+  const SweepArgs a = sweep_args(r, dist2, d2 ? const_cast<float *>(p) : nullptr, res, select, q_limit);
+  const int nb = r.pl.grid[kGridSweep];
   using Fn = void (*)(int, hipStream_t, const SweepArgs &, int, const int32_t *, const float *, const float *,
                       float4 *, const double *, const fgbd_result *);
-  static const Fn table[2][2][2] = {
-      {{sweep_kernel<0, false, false>, sweep_kernel<0, false, true>},
-       {sweep_kernel<0, true, false>, sweep_kernel<0, true, true>}},
-      {{sweep_kernel<8, false, false>, sweep_kernel<8, false, true>},
-       {sweep_kernel<8, true, false>, sweep_kernel<8, true, true>}}};
-  table[a.k == 8][first][d2](nb, r.stream, a, q, col, p, rgb_in, r.b.xbuf, spread, noise);
+  // [k == 8][later sweep, first sweep, first sweep deriving the weights]
+  static const Fn table[2][3] = {
+      {sweep_kernel<0, false, false>, sweep_kernel<0, true, false>, sweep_kernel<0, true, true>},
+      {sweep_kernel<8, false, false>, sweep_kernel<8, true, false>, sweep_kernel<8, true, true>}};
+  table[a.k == 8][first ? (d2 ? 2 : 1) : 0](nb, r.stream, a, q, col, p, rgb_in, r.b.xbuf, spread, noise);
   return hipGetLastError();
 }
 
-bool sweep_tail_fits(const Run &r, bool d2) {
-  using Fn = int (*)();
-  static const Fn table[2][2] = {{tail_capacity<0, false>, tail_capacity<0, true>},
-                                 {tail_capacity<8, false>, tail_capacity<8, true>}};
-  return table[r.prm.k == 8][d2]() >= r.pl.grid[kGridSweep];
+bool sweep_tail_fits(const Run &r) {
+  return (r.prm.k == 8 ? tail_capacity<8>() : tail_capacity<0>()) >= r.pl.grid[kGridSweep];
 }
 
-hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
-                             const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
-                             int select, int q_limit, int q0, int q_last) {
-  const SweepArgs a = sweep_args(r, dist2, res, select, q_limit);
+hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const float *rgb_in,
+                             const double *spread, const fgbd_result *noise, fgbd_result *res, int select,
+                             int q_limit, int q0, int q_last) {
+  const SweepArgs a = sweep_args(r, nullptr, nullptr, res, select, q_limit);
   const int nb = r.pl.grid[kGridSweep];
   using Fn = hipError_t (*)(int, hipStream_t, const SweepArgs &, int, int, uint32_t *, const int32_t *,
                             const float *, const float *, float4 *, const double *, const fgbd_result *);
-  static const Fn table[2][2] = {{tail_kernel<0, false>, tail_kernel<0, true>},
-                                 {tail_kernel<8, false>, tail_kernel<8, true>}};
-  return table[a.k == 8][dist2 != nullptr](nb, r.stream, a, q0, q_last, &r.b.segs->sweep_barrier, col, p, rgb_in,
-                                           r.b.xbuf, spread, noise);
+  static const Fn table[2] = {tail_kernel<0>, tail_kernel<8>};
+  return table[a.k == 8](nb, r.stream, a, q0, q_last, &r.b.segs->sweep_barrier, col, p, rgb_in, r.b.xbuf, spread,
+                         noise);
 }
 
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,

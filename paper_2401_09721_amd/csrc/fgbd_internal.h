@@ -146,9 +146,24 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ part,
   double v[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) v[j] = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+  // eight rows per thread in flight, added in row order (the same sums as a
+  // plain strided loop)
+  constexpr int U = 8;
+  for (int b0 = threadIdx.x; b0 < nparts; b0 += U * blockDim.x) {
+    double w[U][NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] += part[(size_t)b * stride + j];
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * (int)blockDim.x;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) w[u][j] = b < nparts ? part[(size_t)b * stride + j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (b0 + u * (int)blockDim.x < nparts) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] += w[u][j];
+      }
+    }
   }
   block_sum_f64<NV>(v, s_buf);
   if (threadIdx.x == 0) {
@@ -324,6 +339,7 @@ struct SweepCtrl {
   double y2_sel;     // sum over the FSLR subset of |y|^2
   double best_loss;
   double last_energy;
+  double sigma_g;    // of the cloud, when the sweeps compute the weights themselves
   int32_t n_sel;     // |S| (all points when FSLR is off or S is empty)
   int32_t use_all;
   int32_t q;         // sweeps completed
@@ -334,9 +350,12 @@ struct SweepCtrl {
   int32_t select;    // 1: eq. 6 selection, 0: fixed q
   int32_t q_limit;   // q_max (select) or q_fixed
   int32_t fslr;      // FSLR subset in use (select and kappa > 0)
-  int32_t pad_;
-  double sigma_g;    // of the cloud, when the sweeps compute the weights themselves
+  int32_t pad_[2];
 };
+// No implicit padding: a copy of the struct then splits into its fields and
+// stays in registers (padding bytes inside a 16-byte chunk made the compiler
+// keep the chunk in memory, which it placed in LDS at 16 bytes per thread).
+static_assert(sizeof(SweepCtrl) == 6 * 8 + 12 * 4, "SweepCtrl has no implicit padding");
 
 
 // ----------------------------------------------------------- workspace plan
@@ -350,8 +369,8 @@ struct Plan {
   int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)
   int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
   size_t off_segs, off_items_a, off_items_b, off_hist, off_rank, off_digits;
-  size_t off_col, off_dist2, off_spread, off_xbuf;
-  size_t off_merge_part, off_noise_part, off_ctrl, off_sweep_sums;
+  size_t off_col, off_dist2, off_p, off_spread, off_xbuf;
+  size_t off_merge_part, off_noise_acc, off_ctrl, off_sweep_sums;
   size_t total;
 };
 
@@ -368,6 +387,12 @@ constexpr int kNoiseGridCapMax = 1024;  // the noise solve reduces at most this 
 constexpr int kSweepParts = 5;  // energy sums per sweep
 constexpr int kSweepSlots = 64;  // atomic slots per cloud and sum (spread to limit contention)
 constexpr int kSweepMaxGrid = 1024;
+// Patch moments of the noise estimate: every block adds its FP64 partial sums,
+// rounded to multiples of 1 / kNoiseFix, into int64 accumulators (slot = the
+// block's index in its cloud mod kNoiseSlots), so the totals are exact sums of
+// the rounded partials in any order.
+constexpr int kNoiseSlots = 64;
+constexpr double kNoiseFix = 4096.0;
 constexpr int kScanThreads = 1024;
 
 // Largest grid (blocks) of each per-cloud grid kind, and the number of
@@ -392,10 +417,11 @@ struct Bufs {
   uint32_t *rank;               // [L][stride]
   uint8_t *digits;              // [L][stride]: the next radix pass's digit of each sorted item
   int32_t *col, *dist2;         // [n_cap][K]
+  float *p;                     // [n_cap][K] weights the fused path's first sweep stores
   double *spread;               // [n_cap]
   float4 *xbuf;                 // [3][n_cap]
   double *merge_part;           // [grid merge][2]
-  double *noise_part;           // [E1][grid noise]
+  unsigned long long *noise_acc;  // [B][E1][kNoiseSlots] fixed-point patch moments
   SweepCtrl *ctrl;              // [2][B]
   unsigned long long *sums;     // [3][B][slots][parts]
 };
@@ -452,25 +478,25 @@ hipError_t launch_noise_solve(const Run &r, fgbd_result *res);
 
 // Sweep number q (1-based): reads ctrl[(q-1)&1][.] and sums[(q-1)%3], writes
 // ctrl[q&1][.] and sums[q%3], clears sums[(q+1)%3].  noise: per-cloud
-// results holding sigma_est (select == 1).  dist2 != NULL: the weights come
-// from the squared distances and sigma_g from the merge partials (p unused),
-// and the first sweep stores sigma_g into res[s].
+// results holding sigma_est (select == 1).  dist2 != NULL (first sweep only):
+// the weights come from the squared distances and res[s].sigma_g and are
+// stored into p (which is then an output).
 hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
                         const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
                         int select, int q_limit, int q);
 
 // Whether the sweep grid of r fits on the current device at once, as the
-// in-launch sweep loop below needs (d2: the weights come from dist2).
-bool sweep_tail_fits(const Run &r, bool d2);
+// in-launch sweep loop below needs.
+bool sweep_tail_fits(const Run &r);
 
 // Sweeps q0..q_last in one launch whose blocks wait for each other between
 // sweeps, after separate launches of sweeps 1..q0-1 (same arguments as
 // launch_sweep); returns at once when every cloud's selection was done at the
 // start of sweep q0-1.  Uses the segment table's barrier counter (zeroed by
 // the setup launch of the call).
-hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
-                             const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
-                             int select, int q_limit, int q0, int q_last);
+hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const float *rgb_in,
+                             const double *spread, const fgbd_result *noise, fgbd_result *res, int select,
+                             int q_limit, int q0, int q_last);
 
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,
                            float *rgb_out, fgbd_result *res);

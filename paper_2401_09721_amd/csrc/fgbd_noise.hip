@@ -16,8 +16,10 @@
 // D(D+1)/2 entries) and of the per-channel sums, and walks a fixed set of
 // rows, so all sums have a fixed order (products of two floats are exact in
 // FP64).  Incomplete patches contribute zero rows and are not counted.
-// Every block works on one cloud and writes its partial sums; k_noise_solve
-// (one block per cloud) reduces its cloud's partials in block order, forms
+// Every block works on one cloud and adds its partial sums, rounded to
+// multiples of 2^-12, into its cloud's int64 accumulators (integer addition:
+// the totals do not depend on the order of the blocks); k_noise_solve
+// (one block per cloud) sums the accumulator slots, forms
 //   Sigma = (S2 - sum_c s1_c s1_c^T / N) / (3 N),
 // finds its eigenvalues (FP64: Householder tridiagonalisation, then Sturm
 // multisection), and applies the tail rule: the smallest m with
@@ -73,6 +75,12 @@ struct NoiseArgs {
   int32_t groups;      // row groups per entry
   int32_t want_eig3;
 };
+
+// Adds entry e of a block's patch moments into its cloud's accumulators
+// (acc: the cloud's [E1][kNoiseSlots] array).
+__device__ __forceinline__ void add_moment(unsigned long long *acc, int e, int slot, double v) {
+  atomicAdd(&acc[(size_t)e * kNoiseSlots + slot], (unsigned long long)llrint(v * kNoiseFix));
+}
 
 // Orders this wave's LDS writes before its later LDS reads (all lanes).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -306,7 +314,7 @@ __device__ __forceinline__ bool patch_point(const NoiseArgs &a, int64_t i, const
 template <int PT, bool EIG3>
 __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__restrict__ col,
                                                   const float *__restrict__ rgb, double *__restrict__ spread,
-                                                  float *__restrict__ eig3, double *__restrict__ part) {
+                                                  float *__restrict__ eig3, unsigned long long *__restrict__ acc_all) {
   extern __shared__ float s_v[];  // [3 * TP][D] patch rows of the current tile
   __shared__ uint16_t s_pair[kMaxD * (kMaxD + 1) / 2];
   __shared__ double s_red[8];
@@ -401,14 +409,15 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
     __syncthreads();
   }
 
-  // combine accumulators and row groups (fixed order); write this block's
-  // partials entry-major: part[e * nblocks + block], entry 0 = patch count
+  // combine accumulators and row groups (fixed order); add this block's
+  // moments into its cloud's accumulators, entry 0 = patch count
   double *scratch = reinterpret_cast<double *>(s_v);  // >= 768 doubles available
-  const int nb = gridDim.x;
+  unsigned long long *acc_c = acc_all + (size_t)sb.s * (1 + a.E) * kNoiseSlots;
+  const int slot = sb.lb % kNoiseSlots;
   {
     double cv[1] = {count};
     block_sum_f64<1>(cv, s_red);
-    if (t == 0) part[blockIdx.x] = cv[0];
+    if (t == 0) add_moment(acc_c, 0, slot, cv[0]);
   }
 #pragma unroll
   for (int m = 0; m < 3; ++m) scratch[3 * t + m] = m < NE ? (acc[m < NE ? m : 0][0] + acc[m < NE ? m : 0][1]) +
@@ -419,14 +428,15 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
     for (int e = t; e < a.E; e += kBlock) {
       double s = 0.0;
       for (int g = 0; g < G; ++g) s += scratch[3 * (g * a.E + e) + 0];
-      part[(size_t)(1 + e) * nb + blockIdx.x] = s;
+      add_moment(acc_c, 1 + e, slot, s);
     }
   } else {
-    for (int e = t; e < a.E; e += kBlock) part[(size_t)(1 + e) * nb + blockIdx.x] = scratch[3 * (e % kBlock) + e / kBlock];
+    for (int e = t; e < a.E; e += kBlock) add_moment(acc_c, 1 + e, slot, scratch[3 * (e % kBlock) + e / kBlock]);
   }
 }
 
 typedef double v4f64 __attribute__((ext_vector_type(4)));
+
 
 // The same statistics with the tile's patch moments as one 16 x 16 FP64 Gram
 // matrix on the matrix cores (D + 3 <= 16).  Each patch row (one channel of
@@ -445,7 +455,8 @@ typedef double v4f64 __attribute__((ext_vector_type(4)));
 template <int PT, bool EIG3>
 __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
                                                        const float *__restrict__ rgb, double *__restrict__ spread,
-                                                       float *__restrict__ eig3, double *__restrict__ part) {
+                                                       float *__restrict__ eig3,
+                                                       unsigned long long *__restrict__ acc_all) {
   constexpr int D = PT + 1;
   constexpr int W = D + 3;  // floats per LDS row
   static_assert(W <= 16, "the Gram matrix holds D colour features and three indicators");
@@ -503,9 +514,9 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
     __syncthreads();
   }
 
-  // the block's Gram matrix, then its partials entry-major:
-  // part[e * nblocks + block], entry 0 = patch count.  The sums reuse the
-  // row storage (4 waves x 256 doubles fit in 3 * TP * W floats).
+  // the block's Gram matrix, then its moments into the cloud's accumulators,
+  // entry 0 = patch count.  The sums reuse the row storage (4 waves x 256
+  // doubles fit in 3 * TP * W floats).
   double(*s_g)[256] = reinterpret_cast<double(*)[256]>(s_v);
   const v4f64 tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
@@ -515,7 +526,8 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
   __syncthreads();
   s_g[0][t] = gsum;
   __syncthreads();
-  const int nb = gridDim.x;
+  unsigned long long *acc_c = acc_all + (size_t)sb.s * (1 + a.E) * kNoiseSlots;
+  const int slot = sb.lb % kNoiseSlots;
   for (int e = t; e < 1 + a.E; e += kBlock) {
     double v;
     if (e == 0) {
@@ -531,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
       const int q = e - 1 - a.E2;
       v = s_g[0][(q % D) * 16 + D + q / D];
     }
-    part[(size_t)e * nb + blockIdx.x] = v;
+    add_moment(acc_c, e, slot, v);
   }
 }
 
@@ -539,10 +551,12 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
 // eigenvalues (FP64) and apply the tail rule.
 constexpr int kSolveThreads = 1024;
 
-// One block per cloud: sum the cloud's k_noise partials (one wave per entry
-// row, lanes stride the blocks, fixed shuffle tree), form Sigma, then wave 0
-// alone finds its eigenvalues and applies the tail rule.
-__global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, const double *__restrict__ part, int nb,
+// One block per cloud: sum the cloud's moment accumulators (one wave per
+// entry, one lane per slot, integer shuffle sums), form Sigma, then wave 0
+// alone tridiagonalises and every wave brackets eigenvalues; wave 0 applies
+// the tail rule.
+__global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a,
+                                                               const unsigned long long *__restrict__ acc_all,
                                                                fgbd_result *__restrict__ res_all) {
   __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
   __shared__ double s_v[kMaxD], s_p[kMaxD], s_d[kMaxD], s_e[kMaxD];
@@ -555,32 +569,25 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a, cons
   const int stride = 1 + a.E;
   const int seg = blockIdx.x;
   fgbd_result *res = res_all + seg;
-  const int f0 = a.sa.n_fixed >= 0 ? 0 : a.sa.segs->blk_first[kGridNoise][seg];
-  const int nbs = (a.sa.n_fixed >= 0 ? nb : a.sa.segs->blk_first[kGridNoise][seg + 1]) - f0;
+  const unsigned long long *acc = acc_all + (size_t)seg * stride * kNoiseSlots;
   double *tot = s_buf;
-  // two rows per wave at a time: 32 loads per lane in flight
-  constexpr int RW = 2;
+  // up to eight entries per wave in flight (one load per lane each)
+  static_assert(kNoiseSlots == kWave, "one accumulator slot per lane");
+  constexpr int RW = 8;
   for (int e = wave; e < stride; e += RW * nwaves) {
-    double vals[RW][kMaxGrid / kWave];
+    unsigned long long u[RW];
 #pragma unroll
     for (int j = 0; j < RW; ++j) {
       const int ej = e + j * nwaves;
-      const double *row = part + (size_t)(ej < stride ? ej : e) * nb + f0;
-#pragma unroll
-      for (int u = 0; u < kMaxGrid / kWave; ++u) {
-        const int b = lane + u * kWave;
-        vals[j][u] = b < nbs ? row[b] : 0.0;
-      }
+      u[j] = ej < stride ? acc[(size_t)ej * kNoiseSlots + lane] : 0ull;
     }
 #pragma unroll
     for (int j = 0; j < RW; ++j) {
-      double v = 0.0;
+      unsigned long long v = u[j];
 #pragma unroll
-      for (int u = 0; u < kMaxGrid / kWave; ++u) v += vals[j][u];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
       const int ej = e + j * nwaves;
-      if (lane == 0 && ej < stride) tot[ej] = v;
+      if (lane == 0 && ej < stride) tot[ej] = (double)(long long)v / kNoiseFix;
     }
   }
   __syncthreads();
@@ -669,7 +676,7 @@ hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, doub
   const size_t lds_mfma = (size_t)3 * a.TP * (a.D + 3) * sizeof(float);
   const size_t lds = a.P == 8 ? (lds_mfma > 8192 ? lds_mfma : 8192) : lds_rows;
   const int nb = r.pl.grid[kGridNoise];
-  double *part = r.b.noise_part;
+  unsigned long long *part = r.b.noise_acc;
   hipStream_t st = r.stream;
   if (a.P == 8 && eig3 == nullptr)
     k_noise_mfma<8, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
@@ -684,7 +691,7 @@ hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, doub
 
 hipError_t launch_noise_solve(const Run &r, fgbd_result *res) {
   const NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, false);
-  k_noise_solve<<<r.pl.B, kSolveThreads, 0, r.stream>>>(a, r.b.noise_part, r.pl.grid[kGridNoise], res);
+  k_noise_solve<<<r.pl.B, kSolveThreads, 0, r.stream>>>(a, r.b.noise_acc, res);
   return hipGetLastError();
 }
 

@@ -73,7 +73,9 @@ def test_batch_variants(kw):
 
 def test_batch_equals_single_calls():
     """Each cloud of a batch gets what fgbd_denoise gives it alone (the block
-    split differs, so sums may round differently: colours within 1e-4)."""
+    split differs, so sums may round differently: colours within 1e-4; the
+    noise moments are block partials rounded to multiples of 2^-12, so
+    sigma_est agrees to about 1e-11 relative, checked at 1e-9)."""
     prm = fgbd.default_params(bits=8)
     clouds = [shape_cloud(31, 12000), shape_cloud(32, 7000), shape_cloud(33, 20000, sigma=25.0)]
     out, results, offsets = run_batched(clouds, prm)
@@ -83,7 +85,7 @@ def test_batch_equals_single_calls():
         rb = results[s]
         for key in ("q", "n_fslr", "n_eff", "m", "status", "sweeps"):
             assert rb[key] == r1[key], key
-        assert math.isclose(rb["sigma_est"], r1["sigma_est"], rel_tol=1e-12)
+        assert math.isclose(rb["sigma_est"], r1["sigma_est"], rel_tol=1e-9)
         assert math.isclose(rb["sigma_g"], r1["sigma_g"], rel_tol=1e-12)
         a, b = int(offsets[s]), int(offsets[s + 1])
         assert np.max(np.abs(out[a:b] - o1.cpu().numpy())) <= 1e-4
