@@ -413,7 +413,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune = kD
 struct Bufs {
   Segs *segs;
   uint64_t *items_a, *items_b;  // [L][n_cap]
-  uint32_t *hist;               // [L][256][ntiles_cap + 1]
+  uint32_t *hist;               // [L][ntiles_cap + 1][256]
   uint32_t *rank;               // [L][stride]
   uint8_t *digits;              // [L][stride]: the next radix pass's digit of each sorted item
   int32_t *col, *dist2;         // [n_cap][K]

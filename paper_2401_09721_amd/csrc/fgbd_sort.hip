@@ -5,7 +5,7 @@
 // because every pass is stable.
 //
 // Per 8-bit digit pass (4 passes for 32-bit codes):
-//   upsweep   per tile digit histogram            -> hist[dir][digit][tile]
+//   upsweep   per tile digit histogram            -> hist[dir][tile][digit]
 //   scan      exclusive prefix over (digit, tile)  -> global offsets, in place
 //   downsweep stable rank inside the tile (wave-level match of digits with
 //             64-bit ballots, per-wave counters in LDS), stage in LDS in digit
@@ -16,8 +16,8 @@
 //
 // Several clouds are sorted in the same launches, each inside its own range
 // of positions: tiles never straddle two clouds, the scan runs over all tiles
-// of a row and also stores the row total after the last tile, and with P the
-// scanned row of digit c, the cloud's count of c is P[next cloud's first
+// of each digit and also stores the total after the last tile, and with P the
+// scanned counts of digit c, the cloud's count of c is P[next cloud's first
 // tile] - P[its first tile], so each tile's output offset for digit c is
 //   start[s] + (digits < c in cloud s) + (P[this tile] - P[cloud's first tile]).
 #include "fgbd_internal.h"
@@ -149,46 +149,54 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < kSub; ++k) c += s_hs[k * kSubStride + t];
-  hist[((size_t)d * 256 + t) * a.row + tile] = c;
+  hist[((size_t)d * a.row + tile) * 256 + t] = c;  // one 1 KB row per tile
 }
 
-// Exclusive prefix of every (direction, digit) row of tile counts, and the
-// row total after the last tile: one wave per row.  Lane l owns kScanRun
-// consecutive tiles of each 64 * kScanRun chunk; all of a chunk's loads are
-// issued before any is used (one memory round trip per chunk), then the
-// lane's run sum goes through a wave prefix sum.
-constexpr int kScanRun = 8;
-__global__ __launch_bounds__(256) void k_sort_scan(SortArgs a, uint32_t *__restrict__ hist) {
-  const int row = blockIdx.x * 4 + threadIdx.x / kWave;
-  if (row >= a.dt.num_dirs * 256) return;
+// Exclusive prefix over tiles of every (direction, digit) count, and the
+// total after the last tile (row ntiles).  The counts are stored tile-major,
+// one 256-digit row per tile, so every access is a contiguous row segment.
+// One block per (direction, 64 digits): lane = digit, the 16 waves split the
+// tiles into 16 consecutive ranges; each wave sums its range with all loads
+// of a chunk in flight, the waves' sums are scanned in LDS, and each wave
+// writes its range's prefixes starting from the sums of the waves before it.
+constexpr int kScanWaves = 16;
+constexpr int kScanChunk = 16;  // tiles per wave per round trip
+__global__ __launch_bounds__(kScanWaves * 64) void k_sort_scan(SortArgs a, uint32_t *__restrict__ hist) {
+  __shared__ uint32_t s_sum[kScanWaves][kWave];
+  const int d = blockIdx.x / 4;
+  const int digit = (blockIdx.x % 4) * kWave + (int)lane_id();
+  const int w = threadIdx.x / kWave;
   const int ntiles = num_tiles(a);
-  const uint32_t lane = lane_id();
-  uint32_t carry = 0;
-  uint32_t *h = hist + (size_t)row * a.row;
-  for (int t0 = 0; t0 < ntiles; t0 += kWave * kScanRun) {
-    const int first = t0 + (int)lane * kScanRun;
-    uint32_t v[kScanRun];
-    uint32_t run = 0;
+  const int per = (ntiles + kScanWaves - 1) / kScanWaves;
+  const int t0 = w * per, t1 = min(t0 + per, ntiles);
+  uint32_t *h = hist + (size_t)d * a.row * 256 + digit;  // h[tile * 256]
+  uint32_t sum = 0;
+  for (int c0 = t0; c0 < t1; c0 += kScanChunk) {
+    uint32_t v[kScanChunk];
 #pragma unroll
-    for (int j = 0; j < kScanRun; ++j) {
-      v[j] = first + j < ntiles ? h[first + j] : 0u;
+    for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < t1 ? h[(size_t)(c0 + j) * 256] : 0u;
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) sum += v[j];
+  }
+  s_sum[w][lane_id()] = sum;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+  for (int ww = 0; ww < kScanWaves; ++ww) {
+    const uint32_t x = s_sum[ww][lane_id()];
+    run += ww < w ? x : 0u;
+    total += x;
+  }
+  for (int c0 = t0; c0 < t1; c0 += kScanChunk) {
+    uint32_t v[kScanChunk];
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < t1 ? h[(size_t)(c0 + j) * 256] : 0u;
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) {
+      if (c0 + j < t1) h[(size_t)(c0 + j) * 256] = run;
       run += v[j];
     }
-    uint32_t x = run;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, kWave);
-      if (lane >= (uint32_t)o) x += y;
-    }
-    uint32_t pre = carry + x - run;
-#pragma unroll
-    for (int j = 0; j < kScanRun; ++j) {
-      if (first + j < ntiles) h[first + j] = pre;
-      pre += v[j];
-    }
-    carry += __shfl(x, kWave - 1, kWave);
   }
-  if (lane == 0) h[ntiles] = carry;
+  if (w == kScanWaves - 1) h[(size_t)ntiles * 256] = total;
 }
 
 // Exclusive scans of two uint32 per thread over a 256-thread block.
@@ -243,12 +251,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   s_wh[1][t] = 0;
   s_wh[2][t] = 0;
   s_wh[3][t] = 0;
-  // scanned row of digit t: the cloud's count of t and this tile's offset
+  // scanned counts of digit t: the cloud's count of t and this tile's offset
   // inside the cloud (the first cloud starts at column 0 with prefix 0)
-  const uint32_t *hrow = hist + ((size_t)d * 256 + t) * a.row;
-  const uint32_t p_first = ti.first > 0 ? hrow[ti.first] : 0u;
-  uint32_t off_t = hrow[tile] - p_first;
-  uint32_t below_t = hrow[ti.next_first] - p_first;  // becomes the exclusive prefix over digits
+  const uint32_t *hd = hist + (size_t)d * a.row * 256 + t;  // hd[tile * 256]: digit t of a tile row
+  const uint32_t p_first = ti.first > 0 ? hd[(size_t)ti.first * 256] : 0u;
+  uint32_t off_t = hd[(size_t)tile * 256] - p_first;
+  uint32_t below_t = hd[(size_t)ti.next_first * 256] - p_first;  // becomes the exclusive prefix over digits
 
   uint64_t item[kSortItems];
   const int base = ti.begin + wave * kWave * kSortItems + lane;
@@ -337,7 +345,7 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
     k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, r.b.digits, r.b.hist, res);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kScan);
-    k_sort_scan<<<(r.dt.num_dirs * 256 + 3) / 4, 256, 0, r.stream>>>(a, r.b.hist);
+    k_sort_scan<<<r.dt.num_dirs * 4, kScanWaves * kWave, 0, r.stream>>>(a, r.b.hist);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kDownsweep);
     k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.digits, r.b.rank);
