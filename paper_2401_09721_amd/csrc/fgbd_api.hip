@@ -64,6 +64,17 @@ struct fgbd_ctx_s {
   std::vector<Record> pending;
   double ms[FGBD_NUM_KERNELS] = {0};
   int64_t launches[FGBD_NUM_KERNELS] = {0};
+  // Sweep counts of recent eager calls, read back without waiting: the last
+  // finalising launch stores each cloud's count into host-mapped memory and
+  // an event marks it; a later call reads it once the event has completed.
+  int32_t *hint_host = nullptr;  // [kMaxSeg], hipHostMalloc'ed
+  int32_t *hint_dev = nullptr;   // its device address
+  hipEvent_t hint_ev = nullptr;
+  bool hint_failed = false;      // could not set up: no adaptation
+  bool hint_pending = false;
+  int hint_B = 0;
+  int hint_recent[8] = {0};      // ring of the last counts read (max over clouds)
+  int hint_count = 0;
 };
 
 namespace fgbd {
@@ -502,8 +513,13 @@ fgbd_status fgbd_create(fgbd_ctx *out, int32_t hip_device) {
 
 fgbd_status fgbd_destroy(fgbd_ctx ctx) {
   if (!ctx) return ok();
-  if (ctx->own || !ctx->pool.empty() || !ctx->pending.empty()) {
+  if (ctx->own || !ctx->pool.empty() || !ctx->pending.empty() || ctx->hint_host || ctx->hint_ev) {
     DeviceGuard g(ctx->device);
+    if (ctx->hint_ev) {
+      (void)hipEventSynchronize(ctx->hint_ev);
+      (void)hipEventDestroy(ctx->hint_ev);
+    }
+    if (ctx->hint_host) (void)hipHostFree(ctx->hint_host);
     if (ctx->own) {
       (void)hipDeviceSynchronize();
       (void)hipFree(ctx->own);
@@ -630,6 +646,61 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
   return ok();
 }
 
+// Separate sweep launches for an eager call: the schedule's count, lowered to
+// one more than the most sweeps any of the last eight read-back calls needed
+// (the extra launch is the one that finds the selection stopped, so the
+// in-launch loop after it returns at once).  Captured calls keep the
+// schedule's count.  *hint receives where this call's finalising launch
+// should store its sweep counts (NULL: no read-back requested).
+static int adaptive_sweep_launches(fgbd_ctx ctx, hipStream_t s, int32_t **hint) {
+  *hint = nullptr;
+  const int cap = ctx->tune.sweep_launches;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone || ctx->hint_failed) return cap;
+  if (!ctx->hint_host) {
+    void *dev = nullptr;
+    if (hipHostMalloc((void **)&ctx->hint_host, kMaxSeg * sizeof(int32_t),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer(&dev, ctx->hint_host, 0) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->hint_ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->hint_failed = true;
+      return cap;
+    }
+    ctx->hint_dev = (int32_t *)dev;
+  }
+  if (ctx->hint_pending) {
+    const hipError_t q = hipEventQuery(ctx->hint_ev);
+    if (q == hipSuccess) {
+      int m = 0;
+      for (int i = 0; i < ctx->hint_B; ++i) m = ctx->hint_host[i] > m ? ctx->hint_host[i] : m;
+      ctx->hint_recent[ctx->hint_count % 8] = m;
+      ++ctx->hint_count;
+      ctx->hint_pending = false;
+    } else if (q != hipErrorNotReady) {
+      (void)hipGetLastError();
+      ctx->hint_failed = true;
+      return cap;
+    }
+  }
+  if (!ctx->hint_pending) *hint = ctx->hint_dev;
+  if (ctx->hint_count == 0) return cap;
+  int m = 0;
+  for (int i = 0; i < 8 && i < ctx->hint_count; ++i) m = ctx->hint_recent[i] > m ? ctx->hint_recent[i] : m;
+  return m + 1 < cap ? m + 1 : cap;
+}
+
+// After the launches of an eager call that asked for a read-back: mark it.
+static void request_hint(fgbd_ctx ctx, hipStream_t s, int B) {
+  if (hipEventRecord(ctx->hint_ev, s) == hipSuccess) {
+    ctx->hint_pending = true;
+    ctx->hint_B = B;
+  } else {
+    (void)hipGetLastError();
+    ctx->hint_failed = true;
+  }
+}
+
 // The fused path over the call's segments (one cloud of host-known size, or
 // B clouds from device offsets).  No separate weights launch: the first sweep
 // derives sigma_g and turns the squared distances into the weights as it uses
@@ -660,10 +731,12 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
-  const Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
   HIP_TRY(launch_setup(r, nullptr, n, res, n == 0 ? 2 : 1), "setup launch");
   if (n == 0) return ok();
+  r.sweep_launches = adaptive_sweep_launches(ctx, s, &r.hint);
   if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
+  if (r.hint) request_hint(ctx, s, 1);
   return ok();
 }
 
@@ -695,10 +768,12 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
-  const Run r = make_run(ctx, pl, ws, *params, -1, s, &ep);
+  Run r = make_run(ctx, pl, ws, *params, -1, s, &ep);
   HIP_TRY(launch_setup(r, offsets, 0, res, n_total == 0 ? 2 : 1), "setup launch");
   if (n_total == 0) return ok();
+  r.sweep_launches = adaptive_sweep_launches(ctx, s, &r.hint);
   if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
+  if (r.hint) request_hint(ctx, s, batch);
   return ok();
 }
 

@@ -437,7 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
                                                      const unsigned long long *__restrict__ sums_prev,
                                                      const SweepCtrl *__restrict__ ctrl_prev,
                                                      const fgbd_result *__restrict__ noise,
-                                                     float *__restrict__ rgb_out, fgbd_result *__restrict__ res) {
+                                                     float *__restrict__ rgb_out, fgbd_result *__restrict__ res,
+                                                     int32_t *hint) {
   const SegBlock sb = seg_block(sa, kGridSweep);
   SweepCtrl c;
   load_state(c, ctrl_prev + sb.s, sums_prev + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
@@ -464,6 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
     r->n_fslr = c.n_sel;
     r->sweeps = c.q;
     if (noise != nullptr && noise != res) r->sigma_est = noise[sb.s].sigma_est;
+    if (hint != nullptr) hint[sb.s] = c.q;
   }
 }
 
@@ -575,7 +577,7 @@ hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, co
   const unsigned long long *sp = r.b.sums + (q_launches % 3) * S;
   const SweepCtrl *cp = r.b.ctrl + (q_launches & 1) * r.pl.B;
   k_finalize<<<r.pl.grid[kGridSweep], kBlock, 0, r.stream>>>(r.sa, r.pl.n_cap, rgb_in, r.b.xbuf, sp, cp, noise,
-                                                              rgb_out, res);
+                                                              rgb_out, res, r.hint);
   return hipGetLastError();
 }
 

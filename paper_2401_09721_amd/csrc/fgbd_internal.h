@@ -456,6 +456,7 @@ struct Run {
   hipStream_t stream;
   Prof *pf;
   int32_t sweep_launches;  // sweeps enqueued as launches of their own
+  int32_t *hint = nullptr;  // host-mapped: the finalising launch stores each cloud's sweep count here
 };
 
 // Segment table from device offsets (B+1 entries) or, with offsets == NULL,
@@ -498,6 +499,7 @@ hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, c
                              const double *spread, const fgbd_result *noise, fgbd_result *res, int select,
                              int q_limit, int q0, int q_last);
 
+// r.hint != NULL: block 0 of each cloud also stores its sweep count there.
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,
                            float *rgb_out, fgbd_result *res);
 

@@ -164,3 +164,30 @@ def test_captured_graph_with_looped_sweeps():
         assert got_r == fgbd.read_results(ref_res)[0]
     assert saw_tail
     ctx.close()
+
+
+def test_adaptive_launch_count_keeps_bits():
+    """Eager calls lower their separate sweep launches to what recent calls
+    needed (read back without waiting); a frame that needs more sweeps than
+    that runs the rest in the looping launch.  A stream of frames whose
+    sweep counts jump up and down gives, frame by frame, the bits of a fresh
+    context (no history) on the same frame."""
+    prm = fgbd.default_params(bits=8)
+    frames = [cloud(131, 15000, 5.0), cloud(132, 15000, 5.0), cloud(133, 15000, 35.0), cloud(134, 15000, 20.0),
+              cloud(135, 15000, 5.0), cloud(136, 15000, 35.0)]
+    ctx = fgbd.Context("cuda")
+    seen = set()
+    for rep in range(3):
+        for f, (xyz, rgb) in enumerate(frames):
+            out, res = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm, ctx=ctx)
+            torch.cuda.synchronize()  # lets the next call read this call's sweep count
+            r = fgbd.read_result(res)
+            fresh = fgbd.Context("cuda")
+            ref, rres = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm, ctx=fresh)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy()), (rep, f)
+            assert r == fgbd.read_result(rres), (rep, f)
+            fresh.close()
+            seen.add(r["sweeps"])
+    assert max(seen) - min(seen) >= 2, seen  # the counts really vary
+    ctx.close()
