@@ -202,6 +202,101 @@ __device__ double tridiag_eig_wave(const double *s_d, const double *s_e, int D, 
   return 0.5 * (lo + hi);
 }
 
+// The same two stages for a matrix of compile-time size DT held in
+// registers: every lane of the wave runs the identical Householder sequence
+// on its own copy of the lower triangle (no cross-lane traffic, no LDS round
+// trips between the dependent steps), so every lane ends with the same
+// tridiagonal matrix.  Sums run in index order.
+template <int DT>
+__device__ __forceinline__ void householder_regs(double (&A)[DT][DT], double (&d)[DT], double (&e)[DT]) {
+#pragma unroll
+  for (int k = 0; k + 2 < DT; ++k) {
+    const int m = DT - k - 1;
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < DT; ++i)
+      if (i < m) ss = fma(A[k + 1 + i][k], A[k + 1 + i][k], ss);
+    const double x0 = A[k + 1][k];
+    const double alpha = ss > 0.0 ? -copysign(sqrt(ss), x0) : 0.0;
+    const double vn2 = 2.0 * (ss - x0 * alpha);
+    d[k] = A[k][k];
+    e[k] = alpha;
+    if (!(vn2 > 0.0)) continue;  // x = 0: nothing to reflect
+    const double beta = 2.0 / vn2;
+    double v[DT], q[DT];
+#pragma unroll
+    for (int i = 0; i < DT; ++i) v[i] = i < m ? (i == 0 ? x0 - alpha : A[k + 1 + i][k]) : 0.0;
+    double vp = 0.0;
+#pragma unroll
+    for (int i = 0; i < DT; ++i) {
+      if (i >= m) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < DT; ++j) {
+        if (j >= m) continue;
+        const int r = k + 1 + (i > j ? i : j), c = k + 1 + (i > j ? j : i);
+        s = fma(A[r][c], v[j], s);
+      }
+      q[i] = beta * s;  // p = beta A' v
+      vp = fma(v[i], q[i], vp);
+    }
+    const double kk = 0.5 * beta * vp;
+#pragma unroll
+    for (int i = 0; i < DT; ++i)
+      if (i < m) q[i] = q[i] - kk * v[i];
+#pragma unroll
+    for (int i = 0; i < DT; ++i)
+#pragma unroll
+      for (int j = 0; j < DT; ++j)
+        if (i < m && j <= i) A[k + 1 + i][k + 1 + j] -= v[i] * q[j] + q[i] * v[j];
+  }
+  d[DT - 2] = A[DT - 2][DT - 2];
+  e[DT - 2] = A[DT - 1][DT - 2];
+  d[DT - 1] = A[DT - 1][DT - 1];
+}
+
+// Eigenvalue k (ascending) of the tridiagonal (d, e) held in registers, by
+// one wave: the multisection of tridiag_eig_wave with every pivot operand in
+// registers (the same operations, so the same bits for the same d, e).
+template <int DT>
+__device__ double tridiag_eig_regs(const double (&d)[DT], const double (&e)[DT], int k) {
+  const int t = (int)lane_id();
+  double glo = 1e300, ghi = -1e300, emax = 0.0, e2[DT];
+#pragma unroll
+  for (int i = 0; i < DT; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < DT ? fabs(e[i]) : 0.0);
+    glo = fmin(glo, d[i] - r);
+    ghi = fmax(ghi, d[i] + r);
+    e2[i] = e[i] * e[i];
+    if (i + 1 < DT) emax = fmax(emax, e2[i]);
+  }
+  const double nrm = fmax(fabs(glo), fabs(ghi));
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax) * 4.0;
+  double lo = glo - (4.0 * 2.220446049250313e-16 * nrm + pivmin);
+  double hi = ghi + (4.0 * 2.220446049250313e-16 * nrm + pivmin);
+  for (int it = 0; it < 8; ++it) {
+    const double step = (hi - lo) / (double)(kWave + 1);
+    const double x = lo + step * (double)(t + 1);
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int cnt = q < 0.0;
+#pragma unroll
+    for (int i = 1; i < DT; ++i) {
+      double r = __builtin_amdgcn_rcp(q);
+      r = fma(r, fma(-q, r, 1.0), r);
+      q = fma(-e2[i - 1], r, d[i] - x);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+    const int j = (int)__popcll(__builtin_amdgcn_ballot_w64(cnt <= k));
+    const double nlo = j > 0 ? lo + step * (double)j : lo;
+    const double nhi = j < kWave ? lo + step * (double)(j + 1) : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  return 0.5 * (lo + hi);
+}
+
 // Per-point work of one tile slot: gather the patch into three LDS rows,
 // compute the FSLR spread (and optionally the 3x3 eigenvalues) in FP64.
 // PT > 0: the patch size is a compile-time constant (values in registers,
@@ -550,14 +645,22 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
 // One block: sum the k_noise partials in block order, form Sigma, find its
 // eigenvalues (FP64) and apply the tail rule.
 constexpr int kSolveThreads = 1024;
+// DT > 0: one wave per eigenvalue (and the register budget of three waves
+// per SIMD, which holds the whole triangle without spilling)
+template <int DT>
+constexpr int solve_threads() {
+  return DT > 0 ? DT * kWave : kSolveThreads;
+}
 
 // One block per cloud: sum the cloud's moment accumulators (one wave per
 // entry, one lane per slot, integer shuffle sums), form Sigma, then wave 0
 // alone tridiagonalises and every wave brackets eigenvalues; wave 0 applies
-// the tail rule.
-__global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a,
-                                                               const unsigned long long *__restrict__ acc_all,
-                                                               fgbd_result *__restrict__ res_all) {
+// the tail rule.  DT > 0: D = DT, and Sigma, the reduction and the pivots
+// live in registers; DT = 0: any D, through LDS.
+template <int DT>
+__global__ __launch_bounds__(solve_threads<DT>()) void k_noise_solve(NoiseArgs a,
+                                                                     const unsigned long long *__restrict__ acc_all,
+                                                                     fgbd_result *__restrict__ res_all) {
   __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
   __shared__ double s_v[kMaxD], s_p[kMaxD], s_d[kMaxD], s_e[kMaxD];
   __shared__ double s_lam[kMaxD + 1];
@@ -571,9 +674,9 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a,
   fgbd_result *res = res_all + seg;
   const unsigned long long *acc = acc_all + (size_t)seg * stride * kNoiseSlots;
   double *tot = s_buf;
-  // up to eight entries per wave in flight (one load per lane each)
+  // RW entries per wave in flight (one load per lane each)
   static_assert(kNoiseSlots == kWave, "one accumulator slot per lane");
-  constexpr int RW = 8;
+  constexpr int RW = DT > 0 ? (DT * (DT + 1) / 2 + 3 * DT + DT) / DT : 8;  // every entry in one round for DT > 0
   for (int e = wave; e < stride; e += RW * nwaves) {
     unsigned long long u[RW];
 #pragma unroll
@@ -592,33 +695,72 @@ __global__ __launch_bounds__(kSolveThreads) void k_noise_solve(NoiseArgs a,
   }
   __syncthreads();
   const double n_eff = tot[0];
-  const int Dp = D + (D & 1);
-  double *A = tot + stride + (stride & 1);  // Dp x Dp
-  if (n_eff > 0.0) {
-    const double *S2 = tot + 1;
-    const double *S1 = tot + 1 + a.E2;
-    for (int w = t; w < Dp * Dp; w += blockDim.x) {
-      const int k = w / Dp, l = w % Dp;
-      double v = 0.0;
-      if (k < D && l < D) {
-        const int kk = min(k, l), ll = max(k, l);
-        const int e = kk * D - kk * (kk - 1) / 2 + (ll - kk);
-        double m = 0.0;
-        for (int c = 0; c < 3; ++c) m += S1[c * D + kk] * S1[c * D + ll];
-        v = (S2[e] - m / n_eff) / (3.0 * n_eff);
+  const double *S2 = tot + 1;
+  const double *S1 = tot + 1 + a.E2;
+  if constexpr (DT > 0) {
+    // wave 0: Sigma (every lane the whole lower triangle) and its
+    // tridiagonal form; lane 0 publishes d, e
+    if (n_eff > 0.0 && wave == 0) {
+      double A[DT][DT], d[DT], e[DT];
+#pragma unroll
+      for (int k = 0; k < DT; ++k)
+#pragma unroll
+        for (int l = 0; l <= k; ++l) {
+          const int ee = l * DT - l * (l - 1) / 2 + (k - l);
+          double m = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) m += S1[c * DT + l] * S1[c * DT + k];
+          A[k][l] = (S2[ee] - m / n_eff) / (3.0 * n_eff);
+        }
+      householder_regs<DT>(A, d, e);
+      if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < DT; ++i) {
+          s_d[i] = d[i];
+          s_e[i] = e[i];
+        }
       }
-      A[w] = v;
     }
-  }
-  __syncthreads();
-  // eigenvalues: wave 0 tridiagonalises, then each wave brackets its own
-  // eigenvalues (k = wave, wave + 16, ...), stored descending
-  if (n_eff > 0.0 && wave == 0) householder_wave(A, D, Dp, s_v, s_p, s_d, s_e);
-  __syncthreads();
-  if (n_eff > 0.0) {
-    for (int k = wave; k < D; k += nwaves) {
-      const double ev = tridiag_eig_wave(s_d, s_e, D, k);
-      if (lane == 0) s_lam[D - 1 - k] = ev;
+    __syncthreads();
+    if (n_eff > 0.0) {
+      for (int k = wave; k < DT; k += nwaves) {
+        double d[DT], e[DT];
+#pragma unroll
+        for (int i = 0; i < DT; ++i) {
+          d[i] = s_d[i];
+          e[i] = s_e[i];
+        }
+        const double ev = tridiag_eig_regs<DT>(d, e, k);
+        if (lane == 0) s_lam[DT - 1 - k] = ev;
+      }
+    }
+  } else {
+    const int Dp = D + (D & 1);
+    double *A = tot + stride + (stride & 1);  // Dp x Dp
+    if (n_eff > 0.0) {
+      for (int w = t; w < Dp * Dp; w += blockDim.x) {
+        const int k = w / Dp, l = w % Dp;
+        double v = 0.0;
+        if (k < D && l < D) {
+          const int kk = min(k, l), ll = max(k, l);
+          const int e = kk * D - kk * (kk - 1) / 2 + (ll - kk);
+          double m = 0.0;
+          for (int c = 0; c < 3; ++c) m += S1[c * D + kk] * S1[c * D + ll];
+          v = (S2[e] - m / n_eff) / (3.0 * n_eff);
+        }
+        A[w] = v;
+      }
+    }
+    __syncthreads();
+    // eigenvalues: wave 0 tridiagonalises, then each wave brackets its own
+    // eigenvalues (k = wave, wave + 16, ...), stored descending
+    if (n_eff > 0.0 && wave == 0) householder_wave(A, D, Dp, s_v, s_p, s_d, s_e);
+    __syncthreads();
+    if (n_eff > 0.0) {
+      for (int k = wave; k < D; k += nwaves) {
+        const double ev = tridiag_eig_wave(s_d, s_e, D, k);
+        if (lane == 0) s_lam[D - 1 - k] = ev;
+      }
     }
   }
   __syncthreads();
@@ -691,7 +833,10 @@ hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, doub
 
 hipError_t launch_noise_solve(const Run &r, fgbd_result *res) {
   const NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, false);
-  k_noise_solve<<<r.pl.B, kSolveThreads, 0, r.stream>>>(a, r.b.noise_acc, res);
+  if (a.D == 9)
+    k_noise_solve<9><<<r.pl.B, solve_threads<9>(), 0, r.stream>>>(a, r.b.noise_acc, res);
+  else
+    k_noise_solve<0><<<r.pl.B, solve_threads<0>(), 0, r.stream>>>(a, r.b.noise_acc, res);
   return hipGetLastError();
 }
 

@@ -199,6 +199,19 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_sort_scan(SortArgs a, uint3
   if (w == kScanWaves - 1) h[(size_t)ntiles * 256] = total;
 }
 
+// This pass's digit of an item (code << 32 | index).
+__device__ __forceinline__ uint32_t digit_of(uint64_t item, int shift) {
+  return __builtin_amdgcn_ubfe((uint32_t)(item >> 32), (uint32_t)shift, 8u);
+}
+// Bit b of x spread over the word: 0 or all ones.  Written out so the
+// compiler keeps one sign-extending field extract instead of rebuilding the
+// mask from compares.
+__device__ __forceinline__ int32_t bit_mask(uint32_t x, int b) {
+  int32_t m;
+  asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(m) : "v"(x), "i"(b));
+  return m;
+}
+
 // Exclusive scans of two uint32 per thread over a 256-thread block.
 __device__ __forceinline__ void block_exclusive_scan2_256(uint32_t &v0, uint32_t &v1, uint32_t (*s_tmp)[4]) {
   const uint32_t lane = lane_id();
@@ -269,17 +282,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   __syncthreads();
 
   // Stable rank of each item among the equal digits of its wave: items are
-  // visited in tile order (j major, lane minor within the wave).
+  // visited in tile order (j major, lane minor within the wave).  The lanes
+  // holding the same digit are those that agree with it on all 8 ballots:
+  // with m = bit b of the digit spread over the word (0 or all ones), a lane
+  // keeps ~(vote ^ m), a pattern the compiler folds into 3-input bit
+  // operations.
   uint32_t rk[kSortItems];
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const uint32_t digit = (uint32_t)(item[j] >> (32 + a.shift)) & 255u;
-    uint64_t peers = ~0ull;
+    const uint32_t digit = digit_of(item[j], a.shift);
+    uint32_t plo = ~0u, phi = ~0u;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const uint64_t vote = __builtin_amdgcn_ballot_w64((digit >> b) & 1u);
-      peers &= ((digit >> b) & 1u) ? vote : ~vote;
+      const int32_t m = bit_mask(digit, b);
+      const uint64_t vote = __builtin_amdgcn_ballot_w64(m != 0);
+      plo &= ~((uint32_t)vote ^ (uint32_t)m);
+      phi &= ~((uint32_t)(vote >> 32) ^ (uint32_t)m);
     }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
     const uint32_t before = count_below(peers);
     const uint32_t cnt = (uint32_t)__popcll(peers);
     const uint32_t cur = s_wh[wave][digit];
@@ -305,7 +325,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
 
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
-    const uint32_t digit = (uint32_t)(item[j] >> (32 + a.shift)) & 255u;
+    const uint32_t digit = digit_of(item[j], a.shift);
     s_stage[s_base[digit] + s_wh[wave][digit] + rk[j]] = item[j];
   }
   __syncthreads();
@@ -315,7 +335,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   uint8_t *dig = digits + (size_t)d * a.stride;
   for (int s = t; s < valid; s += kSortThreads) {
     const uint64_t it = s_stage[s];
-    const uint32_t digit = (uint32_t)(it >> (32 + a.shift)) & 255u;
+    const uint32_t digit = digit_of(it, a.shift);
     const uint32_t gpos = s_off[digit] + (uint32_t)s - s_base[digit];
     out[gpos] = it;
     if (last_pass)
