@@ -389,8 +389,9 @@ constexpr int kSweepSlots = 64;  // atomic slots per cloud and sum (spread to li
 constexpr int kSweepMaxGrid = 1024;
 // Patch moments of the noise estimate: every block adds its FP64 partial sums,
 // rounded to multiples of 1 / kNoiseFix, into int64 accumulators (slot = the
-// block's index in its cloud mod kNoiseSlots), so the totals are exact sums of
-// the rounded partials in any order.
+// block's index in its cloud mod kNoiseSlots; slot-major, so one block's
+// entries are contiguous), so the totals are exact sums of the rounded
+// partials in any order.
 constexpr int kNoiseSlots = 64;
 constexpr double kNoiseFix = 4096.0;
 constexpr int kScanThreads = 1024;
@@ -421,7 +422,7 @@ struct Bufs {
   double *spread;               // [n_cap]
   float4 *xbuf;                 // [3][n_cap]
   double *merge_part;           // [grid merge][2]
-  unsigned long long *noise_acc;  // [B][E1][kNoiseSlots] fixed-point patch moments
+  unsigned long long *noise_acc;  // [B][kNoiseSlots][E1] fixed-point patch moments
   SweepCtrl *ctrl;              // [2][B]
   unsigned long long *sums;     // [3][B][slots][parts]
 };

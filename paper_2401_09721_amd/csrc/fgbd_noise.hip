@@ -77,9 +77,9 @@ struct NoiseArgs {
 };
 
 // Adds entry e of a block's patch moments into its cloud's accumulators
-// (acc: the cloud's [E1][kNoiseSlots] array).
-__device__ __forceinline__ void add_moment(unsigned long long *acc, int e, int slot, double v) {
-  atomicAdd(&acc[(size_t)e * kNoiseSlots + slot], (unsigned long long)llrint(v * kNoiseFix));
+// (acc: the row of the block's slot in the cloud's [kNoiseSlots][E1] array).
+__device__ __forceinline__ void add_moment(unsigned long long *acc, int e, double v) {
+  atomicAdd(&acc[e], (unsigned long long)llrint(v * kNoiseFix));
 }
 
 // Orders this wave's LDS writes before its later LDS reads (all lanes).
@@ -255,12 +255,24 @@ __device__ __forceinline__ void householder_regs(double (&A)[DT][DT], double (&d
   d[DT - 1] = A[DT - 1][DT - 1];
 }
 
-// Eigenvalue k (ascending) of the tridiagonal (d, e) held in registers, by
-// one wave: the multisection of tridiag_eig_wave with every pivot operand in
-// registers (the same operations, so the same bits for the same d, e).
-template <int DT>
-__device__ double tridiag_eig_regs(const double (&d)[DT], const double (&e)[DT], int k) {
+// Eigenvalues k0 .. k0 + G - 1 (ascending) of the tridiagonal (d, e) held in
+// registers, by one wave split into G groups of GL = 64 / G lanes, one
+// eigenvalue per group (lanes past G * GL follow the last group and take no
+// part in its votes).  The multisection of tridiag_eig_wave with GL interior
+// points per step, so each step shrinks a bracket (GL + 1)-fold and ITERS
+// steps give at least 48 bits.  Fewer lanes per eigenvalue but fewer waves:
+// the waves of a block share the CU's four SIMDs, so one wave doing three
+// eigenvalues in 11 steps finishes well before three waves doing one each
+// in 8 steps on the same SIMD.  Returns this lane's group's eigenvalue.
+template <int DT, int G>
+__device__ double tridiag_eig_groups(const double (&d)[DT], const double (&e)[DT], int k0) {
+  constexpr int GL = kWave / G;
+  constexpr int ITERS = GL >= 63 ? 8 : GL >= 31 ? 10 : GL >= 21 ? 11 : GL >= 15 ? 12 : 48;
   const int t = (int)lane_id();
+  const int g = min(t / GL, G - 1);
+  const int sub = t - g * GL;  // point of the group (GL for a spare lane)
+  const int k = k0 + g;
+  const uint64_t gmask = (((uint64_t)1 << GL) - 1) << (g * GL);
   double glo = 1e300, ghi = -1e300, emax = 0.0, e2[DT];
 #pragma unroll
   for (int i = 0; i < DT; ++i) {
@@ -274,9 +286,9 @@ __device__ double tridiag_eig_regs(const double (&d)[DT], const double (&e)[DT],
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax) * 4.0;
   double lo = glo - (4.0 * 2.220446049250313e-16 * nrm + pivmin);
   double hi = ghi + (4.0 * 2.220446049250313e-16 * nrm + pivmin);
-  for (int it = 0; it < 8; ++it) {
-    const double step = (hi - lo) / (double)(kWave + 1);
-    const double x = lo + step * (double)(t + 1);
+  for (int it = 0; it < ITERS; ++it) {
+    const double step = (hi - lo) / (double)(GL + 1);
+    const double x = lo + step * (double)(sub + 1);
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     int cnt = q < 0.0;
@@ -288,9 +300,10 @@ __device__ double tridiag_eig_regs(const double (&d)[DT], const double (&e)[DT],
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
     }
-    const int j = (int)__popcll(__builtin_amdgcn_ballot_w64(cnt <= k));
+    // the group's points with count <= k are its first j
+    const int j = (int)__popcll(__builtin_amdgcn_ballot_w64(cnt <= k) & gmask);
     const double nlo = j > 0 ? lo + step * (double)j : lo;
-    const double nhi = j < kWave ? lo + step * (double)(j + 1) : hi;
+    const double nhi = j < GL ? lo + step * (double)(j + 1) : hi;
     lo = nlo;
     hi = nhi;
   }
@@ -507,12 +520,11 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   // combine accumulators and row groups (fixed order); add this block's
   // moments into its cloud's accumulators, entry 0 = patch count
   double *scratch = reinterpret_cast<double *>(s_v);  // >= 768 doubles available
-  unsigned long long *acc_c = acc_all + (size_t)sb.s * (1 + a.E) * kNoiseSlots;
-  const int slot = sb.lb % kNoiseSlots;
+  unsigned long long *acc_c = acc_all + ((size_t)sb.s * kNoiseSlots + sb.lb % kNoiseSlots) * (1 + a.E);
   {
     double cv[1] = {count};
     block_sum_f64<1>(cv, s_red);
-    if (t == 0) add_moment(acc_c, 0, slot, cv[0]);
+    if (t == 0) add_moment(acc_c, 0, cv[0]);
   }
 #pragma unroll
   for (int m = 0; m < 3; ++m) scratch[3 * t + m] = m < NE ? (acc[m < NE ? m : 0][0] + acc[m < NE ? m : 0][1]) +
@@ -523,10 +535,10 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
     for (int e = t; e < a.E; e += kBlock) {
       double s = 0.0;
       for (int g = 0; g < G; ++g) s += scratch[3 * (g * a.E + e) + 0];
-      add_moment(acc_c, 1 + e, slot, s);
+      add_moment(acc_c, 1 + e, s);
     }
   } else {
-    for (int e = t; e < a.E; e += kBlock) add_moment(acc_c, 1 + e, slot, scratch[3 * (e % kBlock) + e / kBlock]);
+    for (int e = t; e < a.E; e += kBlock) add_moment(acc_c, 1 + e, scratch[3 * (e % kBlock) + e / kBlock]);
   }
 }
 
@@ -621,8 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
   __syncthreads();
   s_g[0][t] = gsum;
   __syncthreads();
-  unsigned long long *acc_c = acc_all + (size_t)sb.s * (1 + a.E) * kNoiseSlots;
-  const int slot = sb.lb % kNoiseSlots;
+  unsigned long long *acc_c = acc_all + ((size_t)sb.s * kNoiseSlots + sb.lb % kNoiseSlots) * (1 + a.E);
   for (int e = t; e < 1 + a.E; e += kBlock) {
     double v;
     if (e == 0) {
@@ -638,19 +649,19 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
       const int q = e - 1 - a.E2;
       v = s_g[0][(q % D) * 16 + D + q / D];
     }
-    add_moment(acc_c, e, slot, v);
+    add_moment(acc_c, e, v);
   }
 }
 
 // One block: sum the k_noise partials in block order, form Sigma, find its
 // eigenvalues (FP64) and apply the tail rule.
 constexpr int kSolveThreads = 1024;
-// DT > 0: one wave per eigenvalue (and the register budget of three waves
-// per SIMD, which holds the whole triangle without spilling)
+// DT > 0: one wave per SIMD (the eigenvalues go three to a wave)
 template <int DT>
 constexpr int solve_threads() {
-  return DT > 0 ? DT * kWave : kSolveThreads;
+  return DT > 0 ? 4 * kWave : kSolveThreads;
 }
+constexpr int kEigGroups = 3;  // eigenvalues per wave in the register path
 
 // One block per cloud: sum the cloud's moment accumulators (one wave per
 // entry, one lane per slot, integer shuffle sums), form Sigma, then wave 0
@@ -664,6 +675,8 @@ __global__ __launch_bounds__(solve_threads<DT>()) void k_noise_solve(NoiseArgs a
   __shared__ double s_buf[1 + kMaxD * (kMaxD + 1) / 2 + 3 * kMaxD + 1 + (kMaxD + 1) * (kMaxD + 1)];
   __shared__ double s_v[kMaxD], s_p[kMaxD], s_d[kMaxD], s_e[kMaxD];
   __shared__ double s_lam[kMaxD + 1];
+  __shared__ double s_tri[DT > 0 ? DT * (DT + 1) / 2 : 1];
+  __shared__ unsigned long long s_part[solve_threads<DT>()];
   const int t = threadIdx.x;
   const int lane = (int)lane_id();
   const int wave = t / kWave;
@@ -672,25 +685,37 @@ __global__ __launch_bounds__(solve_threads<DT>()) void k_noise_solve(NoiseArgs a
   const int stride = 1 + a.E;
   const int seg = blockIdx.x;
   fgbd_result *res = res_all + seg;
-  const unsigned long long *acc = acc_all + (size_t)seg * stride * kNoiseSlots;
+  const unsigned long long *acc = acc_all + (size_t)seg * kNoiseSlots * stride;
   double *tot = s_buf;
-  // RW entries per wave in flight (one load per lane each)
-  static_assert(kNoiseSlots == kWave, "one accumulator slot per lane");
-  constexpr int RW = DT > 0 ? (DT * (DT + 1) / 2 + 3 * DT + DT) / DT : 8;  // every entry in one round for DT > 0
-  for (int e = wave; e < stride; e += RW * nwaves) {
-    unsigned long long u[RW];
+  // Thread t sums entry t % stride over every C-th slot from t / stride
+  // (C = threads per entry, up to kNoiseSlots): reads of consecutive threads
+  // are consecutive entries of one slot row, all of a thread's loads are in
+  // flight together, and no value crosses lanes; then the C partial sums of
+  // each entry are added from LDS.  Integer sums, so the order is free.
+  {
+    constexpr int NT = solve_threads<DT>();
+    const int C = min(NT / stride, kNoiseSlots);  // stride <= NT
+    const int e = t % stride, c = t / stride;
+    if (c < C) {
+      constexpr int U = 16;
+      unsigned long long sum = 0;
+      for (int s0 = c; s0 < kNoiseSlots; s0 += U * C) {
+        unsigned long long u[U];
 #pragma unroll
-    for (int j = 0; j < RW; ++j) {
-      const int ej = e + j * nwaves;
-      u[j] = ej < stride ? acc[(size_t)ej * kNoiseSlots + lane] : 0ull;
+        for (int j = 0; j < U; ++j) {
+          const int sl = s0 + j * C;
+          u[j] = sl < kNoiseSlots ? acc[(size_t)sl * stride + e] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) sum += u[j];
+      }
+      s_part[c * stride + e] = sum;
     }
-#pragma unroll
-    for (int j = 0; j < RW; ++j) {
-      unsigned long long v = u[j];
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-      const int ej = e + j * nwaves;
-      if (lane == 0 && ej < stride) tot[ej] = (double)(long long)v / kNoiseFix;
+    __syncthreads();
+    if (t < stride) {
+      unsigned long long v = 0;
+      for (int cc = 0; cc < C; ++cc) v += s_part[cc * stride + t];
+      tot[t] = (double)(long long)v / kNoiseFix;
     }
   }
   __syncthreads();
@@ -698,20 +723,31 @@ __global__ __launch_bounds__(solve_threads<DT>()) void k_noise_solve(NoiseArgs a
   const double *S2 = tot + 1;
   const double *S1 = tot + 1 + a.E2;
   if constexpr (DT > 0) {
-    // wave 0: Sigma (every lane the whole lower triangle) and its
-    // tridiagonal form; lane 0 publishes d, e
+    static_assert(DT <= 4 * kEigGroups, "four waves of kEigGroups eigenvalues");
+    constexpr int NT = DT * (DT + 1) / 2;
+    static_assert(NT <= kWave, "one lane per entry of the triangle");
+    // wave 0: one lane per entry of Sigma's upper triangle (row l, column
+    // k >= l, the moment order), then every lane reads the whole triangle and
+    // reduces it to tridiagonal form; lane 0 publishes d, e
     if (n_eff > 0.0 && wave == 0) {
+      if (lane < NT) {
+        int l = 0, rem = lane;
+        while (rem >= DT - l) {
+          rem -= DT - l;
+          ++l;
+        }
+        const int k = l + rem;
+        double m = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m += S1[c * DT + l] * S1[c * DT + k];
+        s_tri[lane] = (S2[lane] - m / n_eff) / (3.0 * n_eff);
+      }
+      wave_lds_sync();
       double A[DT][DT], d[DT], e[DT];
 #pragma unroll
       for (int k = 0; k < DT; ++k)
 #pragma unroll
-        for (int l = 0; l <= k; ++l) {
-          const int ee = l * DT - l * (l - 1) / 2 + (k - l);
-          double m = 0.0;
-#pragma unroll
-          for (int c = 0; c < 3; ++c) m += S1[c * DT + l] * S1[c * DT + k];
-          A[k][l] = (S2[ee] - m / n_eff) / (3.0 * n_eff);
-        }
+        for (int l = 0; l <= k; ++l) A[k][l] = s_tri[l * DT - l * (l - 1) / 2 + (k - l)];
       householder_regs<DT>(A, d, e);
       if (lane == 0) {
 #pragma unroll
@@ -722,17 +758,18 @@ __global__ __launch_bounds__(solve_threads<DT>()) void k_noise_solve(NoiseArgs a
       }
     }
     __syncthreads();
-    if (n_eff > 0.0) {
-      for (int k = wave; k < DT; k += nwaves) {
-        double d[DT], e[DT];
+    if (n_eff > 0.0 && wave * kEigGroups < DT) {
+      double d[DT], e[DT];
 #pragma unroll
-        for (int i = 0; i < DT; ++i) {
-          d[i] = s_d[i];
-          e[i] = s_e[i];
-        }
-        const double ev = tridiag_eig_regs<DT>(d, e, k);
-        if (lane == 0) s_lam[DT - 1 - k] = ev;
+      for (int i = 0; i < DT; ++i) {
+        d[i] = s_d[i];
+        e[i] = s_e[i];
       }
+      const int k0 = wave * kEigGroups;
+      const double ev = tridiag_eig_groups<DT, kEigGroups>(d, e, k0);
+      constexpr int GL = kWave / kEigGroups;
+      const int g = lane / GL;
+      if (lane % GL == 0 && g < kEigGroups && k0 + g < DT) s_lam[DT - 1 - (k0 + g)] = ev;
     }
   } else {
     const int Dp = D + (D & 1);
