@@ -67,17 +67,21 @@ __device__ __forceinline__ bool tile_info(const SortArgs &a, int tile, TileInfo 
   return true;
 }
 
-// (direction, tile) of a downsweep block: workgroups go to the 8 XCDs round
-// robin, so block b runs on XCD b % 8; each XCD gets one contiguous range of
-// the (direction, tile) sequence, so the runs that consecutive tiles write
-// side by side for each digit meet in one L2 before they are written back.
+// (direction, tile) of a block (grid.x = tiles, grid.y = directions):
+// workgroups go to the 8 XCDs round robin, so block b runs on XCD b % 8; each
+// XCD gets one contiguous range of the tile-major sequence (tile, direction),
+// so it works on a contiguous range of tiles in every direction.  The L
+// directions of one tile run back to back on one XCD, so pass 0 reads the
+// tile's coordinates from memory once and from L2 after, and the runs that
+// consecutive tiles write side by side for each digit meet in one L2 before
+// they are written back.
 __device__ __forceinline__ void xcd_tile(int &d, int &tile) {
   const int nb = (int)(gridDim.x * gridDim.y);
   const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
   const int x = b % kXcds, k = b / kXcds;
   const int g = x * (nb / kXcds) + min(x, nb % kXcds) + k;
-  d = g / (int)gridDim.x;
-  tile = g % (int)gridDim.x;
+  d = g % (int)gridDim.y;
+  tile = g / (int)gridDim.y;
 }
 
 __device__ __forceinline__ int num_tiles(const SortArgs &a) {
@@ -108,8 +112,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
                                                                fgbd_result *__restrict__ res) {
   constexpr int kSub = 8, kSubStride = 257;
   __shared__ uint32_t s_hs[kSub * kSubStride];
-  const int d = blockIdx.y;
-  const int tile = blockIdx.x;
+  int d, tile;
+  xcd_tile(d, tile);
   TileInfo ti;
   if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
