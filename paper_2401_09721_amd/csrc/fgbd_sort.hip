@@ -84,18 +84,61 @@ __device__ __forceinline__ void xcd_tile(int &d, int &tile) {
   tile = g / (int)gridDim.y;
 }
 
+// The last pass instead gives each XCD one contiguous range of the
+// direction-major sequence (direction, tile): with 8 directions each XCD
+// sorts one direction, so its scattered rank writes land in one array of
+// 4 bytes per point (measured slightly faster than the tile-major ranges).
+__device__ __forceinline__ void xcd_tile_last(int &d, int &tile) {
+  const int nb = (int)(gridDim.x * gridDim.y);
+  const int b = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+  const int x = b % kXcds, k = b / kXcds;
+  const int g = x * (nb / kXcds) + min(x, nb % kXcds) + k;
+  d = g / (int)gridDim.x;
+  tile = g % (int)gridDim.x;
+}
+
 __device__ __forceinline__ int num_tiles(const SortArgs &a) {
   return a.sa.n_fixed >= 0 ? (a.sa.n_fixed + kSortTile - 1) / kSortTile : a.sa.segs->ntiles;
 }
 
-__device__ __forceinline__ uint64_t load_item(const SortArgs &a, const int32_t *__restrict__ xyz,
+// The scan-line code of one direction (the same integers as scan_code), with
+// the direction's constants read once per block: inside the item loops a
+// reload from the argument segment would wait on the LDS atomics too.
+struct CodeGen {
+  int ia, ih, im, uh, um, wm, bits;
+  uint32_t oh, om;
+};
+__device__ __forceinline__ CodeGen code_gen(const DirTable &dt, int d) {
+  const DirInfo di = dt.d[d];
+  const uint32_t top = (1u << dt.bits) - 1u;
+  CodeGen c;
+  c.ia = di.a;
+  c.ih = di.h;
+  c.im = di.m;
+  c.uh = di.uh;
+  c.um = di.um;
+  c.oh = di.uh > 0 ? (uint32_t)di.uh * top : 0u;
+  c.om = di.um > 0 ? (uint32_t)di.um * top : 0u;
+  c.wm = dt.bits + di.wm_extra;
+  c.bits = dt.bits;
+  return c;
+}
+__device__ __forceinline__ uint32_t gen_code(const CodeGen &c, int gx, int gy, int gz) {
+  const int ga = c.ia == 0 ? gx : (c.ia == 1 ? gy : gz);
+  const int gh = c.ih == 0 ? gx : (c.ih == 1 ? gy : gz);
+  const int gm = c.im == 0 ? gx : (c.im == 1 ? gy : gz);
+  const uint32_t eh = (uint32_t)(gh - c.uh * ga) + c.oh;
+  const uint32_t em = (uint32_t)(gm - c.um * ga) + c.om;
+  return (((eh << c.wm) + em) << c.bits) | (uint32_t)ga;
+}
+
+__device__ __forceinline__ uint64_t load_item(const SortArgs &a, const CodeGen &cg, const int32_t *__restrict__ xyz,
                                               const uint64_t *__restrict__ src, int d, int pos, int *bad) {
   if (a.pass == 0) {
     const int gx = xyz[3 * pos + 0], gy = xyz[3 * pos + 1], gz = xyz[3 * pos + 2];
     const int top = (1 << a.dt.bits) - 1;
     if ((unsigned)gx > (unsigned)top || (unsigned)gy > (unsigned)top || (unsigned)gz > (unsigned)top) *bad = 1;
-    const uint32_t code = scan_code(gx, gy, gz, a.dt.d[d], a.dt.bits);
-    return ((uint64_t)code << 32) | (uint32_t)pos;
+    return ((uint64_t)gen_code(cg, gx, gy, gz) << 32) | (uint32_t)pos;
   }
   return src[(size_t)d * a.stride + pos];
 }
@@ -121,18 +164,40 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
   __syncthreads();
   uint32_t *s_h = s_hs + (lane_id() & (kSub - 1)) * kSubStride;
   if (a.pass == 0) {
+    // every coordinate load of the thread is issued before the first count
+    // (the LDS atomics would otherwise wait for each load in turn)
     const int wave = t / kWave;
     const int lane = (int)lane_id();
     const int base = ti.begin + wave * kWave * kSortItems + lane;
-    int bad = 0;
+    int g[kSortItems][3];
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-      const int pos = base + j * kWave;
-      if (pos < ti.end) {
-        const uint64_t it = load_item(a, xyz, nullptr, d, pos, &bad);
-        atomicAdd(&s_h[(uint32_t)(it >> 32) & 255u], 1u);
+      const int pos = min(base + j * kWave, ti.end - 1);  // a tile holds at least one point
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g[j][c] = xyz[3 * pos + c];
+    }
+    // Runs of equal digits are counted in registers and added once: with
+    // the input in a raster order, the digit (low bits of the position
+    // along the line) is often the same for a thread's items, and for every
+    // lane of the wave, whose atomics on one word would serialise.
+    const uint32_t top = (1u << a.dt.bits) - 1u;
+    const CodeGen cg = code_gen(a.dt, d);
+    int bad = 0;
+    uint32_t run_digit = 0, run_count = 0;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      if (base + j * kWave < ti.end) {
+        if ((uint32_t)g[j][0] > top || (uint32_t)g[j][1] > top || (uint32_t)g[j][2] > top) bad = 1;
+        const uint32_t digit = gen_code(cg, g[j][0], g[j][1], g[j][2]) & 255u;
+        if (run_count != 0 && digit != run_digit) {
+          atomicAdd(&s_h[run_digit], run_count);
+          run_count = 0;
+        }
+        run_digit = digit;
+        ++run_count;
       }
     }
+    if (run_count != 0) atomicAdd(&s_h[run_digit], run_count);
     if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
   } else {
     // tile starts are multiples of 16 inside the direction's row (clouds
@@ -142,8 +207,19 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
     if (p0 + 16 <= ti.end && (p0 & 15) == 0) {
       const uint4 q = *reinterpret_cast<const uint4 *>(row + p0);
       const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+      // runs of equal digits among the 16 consecutive items add once
+      uint32_t rd = w[0] & 255u, rc = 0;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) atomicAdd(&s_h[(w[j >> 2] >> (8 * (j & 3))) & 255u], 1u);
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t dg = (w[j >> 2] >> (8 * (j & 3))) & 255u;
+        if (dg != rd) {
+          atomicAdd(&s_h[rd], rc);
+          rc = 0;
+        }
+        rd = dg;
+        ++rc;
+      }
+      atomicAdd(&s_h[rd], rc);
     } else {
       for (int j = 0; j < 16; ++j)
         if (p0 + j < ti.end) atomicAdd(&s_h[row[p0 + j]], 1u);
@@ -174,6 +250,29 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_sort_scan(SortArgs a, uint3
   const int per = (ntiles + kScanWaves - 1) / kScanWaves;
   const int t0 = w * per, t1 = min(t0 + per, ntiles);
   uint32_t *h = hist + (size_t)d * a.row * 256 + digit;  // h[tile * 256]
+  if (per <= kScanChunk) {  // (up to 256 tiles) one round trip: the counts stay in registers
+    uint32_t v[kScanChunk];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) v[j] = t0 + j < t1 ? h[(size_t)(t0 + j) * 256] : 0u;
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) sum += v[j];
+    s_sum[w][lane_id()] = sum;
+    __syncthreads();
+    uint32_t run = 0, total = 0;
+    for (int ww = 0; ww < kScanWaves; ++ww) {
+      const uint32_t x = s_sum[ww][lane_id()];
+      run += ww < w ? x : 0u;
+      total += x;
+    }
+#pragma unroll
+    for (int j = 0; j < kScanChunk; ++j) {
+      if (t0 + j < t1) h[(size_t)(t0 + j) * 256] = run;
+      run += v[j];
+    }
+    if (w == kScanWaves - 1) h[(size_t)ntiles * 256] = total;
+    return;
+  }
   uint32_t sum = 0;
   for (int c0 = t0; c0 < t1; c0 += kScanChunk) {
     uint32_t v[kScanChunk];
@@ -256,7 +355,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   __shared__ uint64_t s_stage[kSortTile];
 
   int d, tile;
-  xcd_tile(d, tile);
+  if (a.pass == kSortPasses - 1)
+    xcd_tile_last(d, tile);
+  else
+    xcd_tile(d, tile);
   TileInfo ti;
   if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
@@ -276,12 +378,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   uint32_t below_t = hd[(size_t)ti.next_first * 256] - p_first;  // becomes the exclusive prefix over digits
 
   uint64_t item[kSortItems];
+  const CodeGen cg = code_gen(a.dt, d);
   const int base = ti.begin + wave * kWave * kSortItems + lane;
   int bad = 0;
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const int pos = base + j * kWave;
-    item[j] = (pos < ti.end) ? load_item(a, xyz, src, d, pos, &bad) : ~0ull;
+    item[j] = (pos < ti.end) ? load_item(a, cg, xyz, src, d, pos, &bad) : ~0ull;
   }
   __syncthreads();
 
