@@ -542,23 +542,25 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   }
 }
 
-typedef double v4f64 __attribute__((ext_vector_type(4)));
 
-
-// The same statistics with the tile's patch moments as one 16 x 16 FP64 Gram
-// matrix on the matrix cores (D + 3 <= 16).  Each patch row (one channel of
-// one patch) becomes the vector of its D colour entries and three channel
-// indicators (1 in the row's own channel, for complete patches only), stored
-// in LDS as W = D + 3 floats; features W..15 are zero.  G = sum over rows of
-// v v^T then holds sum a a^T (the D x D block), the per-channel sums (columns
-// D .. D+2 of the first D rows) and the patch count (G[D][D]).
-// v_mfma_f64_16x16x4f64 adds four rows per instruction: lane l supplies
-// feature l % 16 of row l / 16 as both operands, and its accumulator register
-// i holds G[4 i + l / 16][l % 16].  Each wave keeps four accumulators and
-// issues four independent instructions per step (one instruction's result
-// is not waited for by the next), reading their operands from LDS without
-// branches; the four are added in a fixed order at the end.  Products of
-// floats are exact in FP64; the accumulation order is fixed.
+// The same statistics with the tile's patch moments as one FP64 Gram matrix
+// on the matrix cores.  Each patch row (one channel of one patch) becomes the
+// vector of its D = 9 colour entries and three channel indicators (1 in the
+// row's own channel, for complete patches only), stored in LDS as W = 12
+// floats.  G = sum over rows of v v^T then holds sum a a^T (the D x D block),
+// the per-channel sums (columns D .. D+2 of the first D rows) and the patch
+// count (G[D][D]).  G is built from 4 x 4 sub-blocks (p, q), p <= q, of
+// feature groups 4p..4p+3, with v_mfma_f64_4x4x4_4b_f64: four independent
+// 4 x 4 products per instruction, each summing four rows.  In block b of an
+// instruction, lane l supplies A[i][k] and B[k][j] with b = (l / 4) % 4,
+// i = j = l % 4, k = l / 16 (the row), and holds C[l / 16][l % 4] (layout
+// checked on the device with one-hot operands).  Per pair of row groups
+// (8 rows): one instruction each for blocks (0,0), (0,1), (0,2), (1,1), and
+// one for (1,2), (2,2) of both groups, so 3 instructions instead of the 2
+// that a 16 x 16 product would need at six times the cost per instruction
+// on this GPU (measured).  Independent accumulators, operands read from LDS
+// without branches, and the partial sums added in a fixed order.  Products
+// of floats are exact in FP64; the accumulation order is fixed.
 template <int PT, bool EIG3>
 __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
                                                        const float *__restrict__ rgb, double *__restrict__ spread,
@@ -566,20 +568,22 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
                                                        unsigned long long *__restrict__ acc_all) {
   constexpr int D = PT + 1;
   constexpr int W = D + 3;  // floats per LDS row
-  static_assert(W <= 16, "the Gram matrix holds D colour features and three indicators");
+  static_assert(W == 12, "three feature groups of four: D = 9 colours and three indicators");
   extern __shared__ float s_v[];  // [3 * TP][W] patch rows of the current tile; then the Gram sums
   const int t = threadIdx.x;
   const int TP = a.TP;
-  // wave-uniform in a scalar register, so the row-group loop below is
-  // uniform and the accumulators stay in place across its iterations
+  // wave-uniform in a scalar register, so the row loop below is uniform and
+  // the accumulators stay in place across its iterations
   const int wave = __builtin_amdgcn_readfirstlane(t / kWave), lane = (int)lane_id();
-  const int f = lane % 16, rsub = lane / 16;
-  const int fi = f < W ? f : W - 1;  // in-row feature read by this lane (zeroed when f >= W)
-  const int groups = 3 * TP / 4;     // four rows per instruction; a multiple of 16
+  const int bsel = (lane >> 2) & 3, inner = lane & 3, krow = lane >> 4;
+  // instruction 1 (per row group): blocks (0,0), (0,1), (0,2), (1,1)
+  const int p1 = bsel == 3 ? 1 : 0, q1 = bsel == 3 ? 1 : bsel;
+  // instruction 2 (per pair of groups): blocks (1,2), (2,2) of group 2P and of group 2P + 1
+  const int p2 = (bsel & 1) ? 2 : 1, g2 = bsel >> 1;
+  const int fa1 = 4 * p1 + inner, fb1 = 4 * q1 + inner, fa2 = 4 * p2 + inner, fb2 = 8 + inner;
+  const int pairs = 3 * TP / 8;  // pairs of four-row groups
   constexpr int kWaves = kBlock / kWave;
-  v4f64 acc[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = v4f64{0.0, 0.0, 0.0, 0.0};
+  double c1[4] = {0.0, 0.0, 0.0, 0.0}, c2[2] = {0.0, 0.0};
 
   const SegBlock sb = seg_block(a.sa, kGridNoise);
   const Share sh = seg_share(sb, TP);
@@ -608,26 +612,36 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
       }
     }
     __syncthreads();
-    for (int g = wave; g < groups; g += 4 * kWaves) {
-      double v[4];
+    // two pairs of row groups per step (P and P + kWaves), six independent
+    // instructions
+    for (int pp = wave; pp < pairs; pp += 2 * kWaves) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const float x = s_v[(4 * (g + u * kWaves) + rsub) * W + fi];
-        v[u] = f < W ? (double)x : 0.0;
+      for (int u = 0; u < 2; ++u) {
+        const int P = pp + u * kWaves;
+        if (P < pairs) {  // uniform over the wave
+          const float *r0 = s_v + (size_t)(8 * P + krow) * W;  // group 2P
+          const float *r1 = r0 + 4 * W;                        // group 2P + 1
+          const float *r2 = r0 + (size_t)(4 * g2) * W;         // group 2P + g2
+          const double a0 = r0[fa1], b0 = r0[fb1], a1 = r1[fa1], b1 = r1[fb1], a2 = r2[fa2], b2 = r2[fb2];
+          c1[2 * u] = __builtin_amdgcn_mfma_f64_4x4x4f64(a0, b0, c1[2 * u], 0, 0, 0);
+          c1[2 * u + 1] = __builtin_amdgcn_mfma_f64_4x4x4f64(a1, b1, c1[2 * u + 1], 0, 0, 0);
+          c2[u] = __builtin_amdgcn_mfma_f64_4x4x4f64(a2, b2, c2[u], 0, 0, 0);
+        }
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc[u], 0, 0, 0);
     }
     __syncthreads();
   }
 
-  // the block's Gram matrix, then its moments into the cloud's accumulators,
-  // entry 0 = patch count.  The sums reuse the row storage (4 waves x 256
-  // doubles fit in 3 * TP * W floats).
+  // the block's Gram matrix (16 x 16 storage, only the computed sub-blocks
+  // are read), then its moments into the cloud's accumulators, entry 0 =
+  // patch count.  The sums reuse the row storage (4 waves x 256 doubles fit
+  // in 3 * TP * W floats).
   double(*s_g)[256] = reinterpret_cast<double(*)[256]>(s_v);
-  const v4f64 tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) s_g[wave][(4 * i + rsub) * 16 + f] = tot[i];
+  const double tot1 = (c1[0] + c1[1]) + (c1[2] + c1[3]);
+  const double tot2h = c2[0] + c2[1];
+  const double tot2 = tot2h + __shfl_xor(tot2h, 8, kWave);  // the two groups' halves of (1,2), (2,2)
+  s_g[wave][(4 * p1 + krow) * 16 + 4 * q1 + inner] = tot1;
+  if (bsel < 2) s_g[wave][(4 * p2 + krow) * 16 + 8 + inner] = tot2;
   __syncthreads();
   const double gsum = (s_g[0][t] + s_g[1][t]) + (s_g[2][t] + s_g[3][t]);
   __syncthreads();
