@@ -143,7 +143,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_p = take(N * pl.K * 4);
   pl.off_spread = take(N * 8);
   pl.off_xbuf = take(3 * N * 16);
-  pl.off_merge_part = take((size_t)pl.grid[kGridMerge] * 2 * 8);
+  pl.off_edge_acc = take((size_t)B * kEdgeSlots * kEdgeVals * 8);
   pl.off_noise_acc = take((size_t)B * pl.E1 * kNoiseSlots * 8);
   pl.off_ctrl = take((size_t)2 * B * sizeof(SweepCtrl));
   pl.off_sweep_sums = take((size_t)3 * B * kSweepSlots * kSweepParts * 8);
@@ -164,7 +164,7 @@ Bufs carve(char *ws, const Plan &pl) {
   b.p = (float *)(ws + pl.off_p);
   b.spread = (double *)(ws + pl.off_spread);
   b.xbuf = (float4 *)(ws + pl.off_xbuf);
-  b.merge_part = (double *)(ws + pl.off_merge_part);
+  b.edge_acc = (unsigned long long *)(ws + pl.off_edge_acc);
   b.noise_acc = (unsigned long long *)(ws + pl.off_noise_acc);
   b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
   b.sums = (unsigned long long *)(ws + pl.off_sweep_sums);
@@ -182,6 +182,8 @@ struct SetupArgs {
   int32_t zero_result;
   int32_t sums_count;  // first sweep's sums to clear (uint64)
   int32_t noise_count;  // noise moment accumulators to clear (uint64)
+  unsigned long long *edge_acc;
+  int32_t edge_count;   // edge-length sums to clear (uint64)
   unsigned long long *noise_acc;
 };
 
@@ -198,6 +200,7 @@ __global__ __launch_bounds__(256) void k_setup(SetupArgs a, Segs *__restrict__ s
   const int t = threadIdx.x;
   for (int i = blockIdx.x * blockDim.x + t; i < a.sums_count; i += gridDim.x * blockDim.x) sums1[i] = 0ull;
   for (int i = blockIdx.x * blockDim.x + t; i < a.noise_count; i += gridDim.x * blockDim.x) a.noise_acc[i] = 0ull;
+  for (int i = blockIdx.x * blockDim.x + t; i < a.edge_count; i += gridDim.x * blockDim.x) a.edge_acc[i] = 0ull;
   if (blockIdx.x != 0) return;  // uniform over the block
   const int B = a.B;
   if (t <= B) s_raw[t] = a.offsets ? a.offsets[t] : (t == 0 ? 0 : a.n_host);
@@ -263,6 +266,8 @@ hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fg
   a.sums_count = r.pl.B * kSweepSlots * kSweepParts;
   a.noise_count = r.pl.B * r.pl.E1 * kNoiseSlots;
   a.noise_acc = r.b.noise_acc;
+  a.edge_count = r.pl.B * kEdgeSlots * kEdgeVals;
+  a.edge_acc = r.b.edge_acc;
   const int most = a.sums_count > a.noise_count ? a.sums_count : a.noise_count;
   int blocks = (most + 256 * 8 - 1) / (256 * 8);
   blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
@@ -462,12 +467,13 @@ fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const i
     FGBD_POST(r.pf);
   }
   bool tail = separate < sweeps && sweep_tail_fits(r);
-  if (tail) {
+  if (tail) {  // the loop launch also finalises
     FGBD_PRE(r.pf, kSweep);
     const hipError_t e =
-        launch_sweep_tail(r, col, p, rgb_in, spread, noise, res, select, q_limit, separate + 1, sweeps);
+        launch_sweep_tail(r, col, p, rgb_in, spread, noise, res, select, q_limit, separate + 1, sweeps, rgb_out);
     FGBD_POST(r.pf);
     HIP_TRY(e, "sweep loop launch");
+    return FGBD_OK;
   }
   for (int q = tail ? sweeps + 1 : separate + 1; q <= sweeps; ++q) {
     FGBD_PRE(r.pf, kSweep);

@@ -34,13 +34,15 @@
 // selection has not finished by then, run in one launch that loops over the
 // remaining sweeps, its blocks waiting for each other between sweeps (a
 // counter in device memory; the grid is sized to be resident at once).  That
-// launch first reads the done flags the last separate launch stored and
-// returns at once when every cloud is done, which is the usual case.  The
+// launch first reads the done flags the last separate launch stored and skips
+// the loop when every cloud is done, which is the usual case; either way it
+// then does the finalising work (so no separate launch follows it).  The
 // wait between sweeps costs far more than a kernel boundary on this GPU (it
 // writes back and invalidates the L2 of every XCD), so the loop is the
 // fallback, not the main path.  A plain launch is used because a cooperative
 // launch measured about 40 us of overhead even when it returned at once.
-// With fixed q the host knows the sweep count and launches every sweep.
+// With fixed q the host knows the sweep count and launches every sweep, then
+// the finalising launch.
 #include "fgbd_internal.h"
 
 namespace fgbd {
@@ -56,12 +58,11 @@ struct SweepArgs {
   unsigned long long *sums3;  // [3][B][slots][parts], rotating by sweep
   SweepCtrl *ctrl;            // [2][B], ping-pong by sweep
   // weights derived by the first sweep (the fused per-frame path): the
-  // squared distances, the merge launch's partials, its grid size, a fixed
-  // sigma_g (<= 0: the mean edge length), the results that receive sigma_g,
-  // and where to store the weights for the later sweeps
+  // squared distances, the merge launch's edge-length sums, a fixed sigma_g
+  // (<= 0: the mean edge length), the results that receive sigma_g, and
+  // where to store the weights for the later sweeps
   const int32_t *dist2;
-  const double *merge_part;
-  int32_t merge_grid;
+  const unsigned long long *edge_acc;
   double sigma_g_fixed;
   fgbd_result *res;
   float *p_out;
@@ -181,14 +182,14 @@ template <bool D2>
 struct SweepLds {
   unsigned long long red[4 * kSweepParts];
   double exp[D2 ? kExpTable : 1];
-  double dred[D2 ? 8 : 1];
+  unsigned long long eu[D2 ? kEdgeVals : 1];
 };
 
 // One sweep (number q, buffers io) by one block of cloud sb.s.  Every thread
 // of the block calls it; it returns without touching the colours when the
 // cloud's selection is already done (uniform over the block).
-// D2 (first sweep only): sigma_g and the row weights come from the merge
-// partials and the squared distances (eq. 4, the graph builder's own
+// D2 (first sweep only): sigma_g and the row weights come from the merge's
+// edge-length sums and the squared distances (eq. 4, the graph builder's own
 // arithmetic) instead of a stored p; sigma_g goes to the results and the
 // weights into p_out for the later sweeps.
 template <int KT, bool FIRST, bool D2>
@@ -208,9 +209,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
   if (FIRST) {
     c.sigma_g = 0.0;
     if (D2) {
-      int mf, mc;
-      seg_blocks_of(a.sa, kGridMerge, sb.s, a.merge_grid, &mf, &mc);
-      c.sigma_g = cloud_sigma_g(a.merge_part + 2 * mf, mc, a.sigma_g_fixed, lds.dred);
+      c.sigma_g = cloud_sigma_g(a.edge_acc + (size_t)kEdgeSlots * kEdgeVals * sb.s, a.sigma_g_fixed, lds.eu);
       if (sb.lb == 0 && threadIdx.x == 0) a.res[sb.s].sigma_g = c.sigma_g;
     }
     c.sigma_est = a.select ? noise[sb.s].sigma_est : 0.0;
@@ -403,45 +402,13 @@ __device__ __forceinline__ bool all_clouds_done(const SweepCtrl *states, int B) 
 // others after each sweep.  States are left where the finalising launch looks
 // for them: in the buffer of q_last.  If a wait gives up, every block's cloud
 // is flagged FGBD_ST_SWEEP_STALL and the loop ends.
-template <int KT>
-__global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int q_last, uint32_t *barrier,
-                                                       long long wait_limit, const int32_t *__restrict__ col,
-                                                       const float *__restrict__ p, const float *__restrict__ rgb_in,
-                                                       float4 *__restrict__ xbuf, const double *__restrict__ spread,
-                                                       const fgbd_result *__restrict__ noise) {
-  __shared__ SweepLds<false> lds;
-  __shared__ int s_flag;
-  const SegBlock sb = seg_block(a.sa, kGridSweep);
-  const int B = a.sa.B;
-  // state at the start of the last separate sweep, written by that launch
-  const SweepCtrl *last = a.ctrl + ((q0 - 1) & 1) * B;
-  int q = q0;
-  bool done = all_clouds_done(last, B);
-  uint32_t epoch = 0;
-  while (!done && q <= q_last) {
-    sweep_step<KT, false, false>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
-    if (!grid_barrier(barrier, ++epoch, wait_limit, &s_flag)) {
-      if (threadIdx.x == 0) atomicOr(&a.res[sb.s].status, FGBD_ST_SWEEP_STALL);
-      return;
-    }
-    last = a.ctrl + (q & 1) * B;
-    done = all_clouds_done(last, B);
-    ++q;
-  }
-  // finished early: the finalising launch reads the states of q_last
-  if (done && sb.lb == 0 && threadIdx.x == 0) a.ctrl[(q_last & 1) * B + sb.s] = last[sb.s];
-}
-
-__global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_stride, const float *__restrict__ rgb_in,
-                                                     const float4 *__restrict__ xbuf,
-                                                     const unsigned long long *__restrict__ sums_prev,
-                                                     const SweepCtrl *__restrict__ ctrl_prev,
-                                                     const fgbd_result *__restrict__ noise,
-                                                     float *__restrict__ rgb_out, fgbd_result *__restrict__ res,
-                                                     int32_t *hint) {
-  const SegBlock sb = seg_block(sa, kGridSweep);
-  SweepCtrl c;
-  load_state(c, ctrl_prev + sb.s, sums_prev + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
+// The finalising work of one block, from the cloud's final state c: the
+// chosen iterate (or the input for q = 0) out, and block 0 of the cloud
+// writes its results (and its sweep count to hint when given).
+__device__ __forceinline__ void finalize_block(const SegBlock &sb, const SweepCtrl &c, int64_t buf_stride,
+                                               const float *__restrict__ rgb_in, const float4 *__restrict__ xbuf,
+                                               const fgbd_result *__restrict__ noise, float *__restrict__ rgb_out,
+                                               fgbd_result *__restrict__ res, int32_t *hint) {
   const int best = c.best_buf;
   const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
@@ -469,6 +436,58 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_stride, const float *__restrict__ rgb_in,
+                                                     const float4 *__restrict__ xbuf,
+                                                     const unsigned long long *__restrict__ sums_prev,
+                                                     const SweepCtrl *__restrict__ ctrl_prev,
+                                                     const fgbd_result *__restrict__ noise,
+                                                     float *__restrict__ rgb_out, fgbd_result *__restrict__ res,
+                                                     int32_t *hint) {
+  const SegBlock sb = seg_block(sa, kGridSweep);
+  SweepCtrl c;
+  load_state(c, ctrl_prev + sb.s, sums_prev + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
+  finalize_block(sb, c, buf_stride, rgb_in, xbuf, noise, rgb_out, res, hint);
+}
+
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int q_last, uint32_t *barrier,
+                                                       long long wait_limit, const int32_t *__restrict__ col,
+                                                       const float *__restrict__ p, const float *__restrict__ rgb_in,
+                                                       float4 *__restrict__ xbuf, const double *__restrict__ spread,
+                                                       const fgbd_result *__restrict__ noise,
+                                                       float *__restrict__ rgb_out, int32_t *hint) {
+  __shared__ SweepLds<false> lds;
+  __shared__ int s_flag;
+  const SegBlock sb = seg_block(a.sa, kGridSweep);
+  const int B = a.sa.B;
+  // state at the start of the last separate sweep, written by that launch
+  const SweepCtrl *last = a.ctrl + ((q0 - 1) & 1) * B;
+  int q = q0;
+  bool done = all_clouds_done(last, B);
+  uint32_t epoch = 0;
+  while (!done && q <= q_last) {
+    sweep_step<KT, false, false>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
+    if (!grid_barrier(barrier, ++epoch, wait_limit, &s_flag)) {
+      if (threadIdx.x == 0) atomicOr(&a.res[sb.s].status, FGBD_ST_SWEEP_STALL);
+      return;
+    }
+    last = a.ctrl + (q & 1) * B;
+    done = all_clouds_done(last, B);
+    ++q;
+  }
+  // Finalise.  Every sweep this launch computed ended at a grid barrier, and
+  // the earlier ones were launches of their own.  Stopped early: the last
+  // states read are final; else the states of q_last with its sums applied.
+  SweepCtrl c;
+  if (done) {
+    c = last[sb.s];
+  } else {
+    const unsigned long long *sums_last = a.sums3 + (size_t)(q_last % 3) * B * kSlotVals;
+    load_state(c, a.ctrl + (q_last & 1) * B + sb.s, sums_last + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
+  }
+  finalize_block(sb, c, a.buf_stride, rgb_in, xbuf, noise, rgb_out, a.res, hint);
+}
+
 SweepArgs sweep_args(const Run &r, const int32_t *dist2, float *p_out, fgbd_result *res, int select, int q_limit) {
   SweepArgs a;
   a.sa = r.sa;
@@ -480,8 +499,7 @@ SweepArgs sweep_args(const Run &r, const int32_t *dist2, float *p_out, fgbd_resu
   a.sums3 = r.b.sums;
   a.ctrl = r.b.ctrl;
   a.dist2 = dist2;
-  a.merge_part = r.b.merge_part;
-  a.merge_grid = r.pl.grid[kGridMerge];
+  a.edge_acc = r.b.edge_acc;
   a.sigma_g_fixed = r.prm.sigma_g;
   a.res = res;
   a.p_out = p_out;
@@ -529,9 +547,9 @@ long long half_second_ticks() {
 template <int KT>
 hipError_t tail_kernel(int nb, hipStream_t st, const SweepArgs &a, int q0, int q_last, uint32_t *barrier,
                        const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf, const double *spread,
-                       const fgbd_result *noise) {
+                       const fgbd_result *noise, float *rgb_out, int32_t *hint) {
   k_sweep_tail<KT><<<nb, kBlock, 0, st>>>(a, q0, q_last, barrier, half_second_ticks(), col, p, rgb_in, xbuf, spread,
-                                          noise);
+                                          noise, rgb_out, hint);
   return hipGetLastError();
 }
 
@@ -561,14 +579,15 @@ bool sweep_tail_fits(const Run &r) {
 
 hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const float *rgb_in,
                              const double *spread, const fgbd_result *noise, fgbd_result *res, int select,
-                             int q_limit, int q0, int q_last) {
+                             int q_limit, int q0, int q_last, float *rgb_out) {
   const SweepArgs a = sweep_args(r, nullptr, nullptr, res, select, q_limit);
   const int nb = r.pl.grid[kGridSweep];
   using Fn = hipError_t (*)(int, hipStream_t, const SweepArgs &, int, int, uint32_t *, const int32_t *,
-                            const float *, const float *, float4 *, const double *, const fgbd_result *);
+                            const float *, const float *, float4 *, const double *, const fgbd_result *, float *,
+                            int32_t *);
   static const Fn table[2] = {tail_kernel<0>, tail_kernel<8>};
   return table[a.k == 8](nb, r.stream, a, q0, q_last, &r.b.segs->sweep_barrier, col, p, rgb_in, r.b.xbuf, spread,
-                         noise);
+                         noise, rgb_out, r.hint);
 }
 
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,

@@ -6,13 +6,12 @@
 // from differences of the code fields, so no coordinate is gathered), and
 // keeps the K smallest distinct (squared distance, index) pairs in a
 // register-resident sorted list (packed so one integer compare orders by
-// distance then index).  It writes the fixed-K CSR row and per-block FP64
-// sums of edge lengths and edge counts for sigma_g; every block works on one
-// cloud.
+// distance then index).  It writes the fixed-K CSR row, and each block adds
+// its FP64 sum of edge lengths and its edge count into its cloud's exact
+// integer sums for sigma_g; every block works on one cloud.
 //
-// k_weights: every block first sums the merge partials of its cloud's blocks
-// in block order (all blocks of a cloud get the same sigma_g, the mean edge
-// length of eq. 4's bandwidth rule),
+// k_weights: every block reads its cloud's sigma_g (the mean edge length of
+// eq. 4's bandwidth rule) from those sums,
 // then computes row-normalised Gaussian weights of eq. 4 in FP64 with the row's
 // smallest squared distance subtracted in the exponent (same ratio, no
 // underflow of the whole row), stored as float.  Squared-distance gaps are
@@ -193,7 +192,8 @@ __device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int wind
 template <int KM, int WT>
 __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *__restrict__ sorted,
                                                   const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
-                                                  int32_t *__restrict__ dist2, double *__restrict__ part) {
+                                                  int32_t *__restrict__ dist2,
+                                                  unsigned long long *__restrict__ edge_acc) {
   __shared__ double s_red[8];
   __shared__ int s_rank[WT > 0 ? kMaxDirs : 1][kBlock];
   __shared__ DirInfo s_dir[kMaxDirs];
@@ -311,8 +311,11 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
   }
   block_sum_f64<2>(acc, s_red);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x + 0] = acc[0];
-    part[2 * blockIdx.x + 1] = acc[1];
+    unsigned long long *e = edge_acc + ((size_t)sb.s * kEdgeSlots + sb.lb % kEdgeSlots) * kEdgeVals;
+    const double whole = floor(acc[0]);  // acc[0] >= 0; the fraction below is exact
+    atomicAdd(&e[0], (unsigned long long)whole);
+    atomicAdd(&e[1], (unsigned long long)llrint((acc[0] - whole) * kEdgeFrac));
+    atomicAdd(&e[2], (unsigned long long)acc[1]);
   }
 }
 
@@ -320,13 +323,15 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_weights(SegArgs sa, int32_t k_rt, const int32_t *__restrict__ col,
                                                     const int32_t *__restrict__ dist2,
-                                                    const double *__restrict__ merge_part, double sigma_g_fixed,
+                                                    const unsigned long long *__restrict__ edge_acc,
+                                                    double sigma_g_fixed,
                                                     fgbd_result *__restrict__ res, float *__restrict__ p) {
   __shared__ double s_red[8];
   __shared__ double s_exp[kExpTable];
   const int K = KT > 0 ? KT : k_rt;
   const SegBlock sb = seg_block(sa, kGridMerge);
-  const double sg = cloud_sigma_g(merge_part + 2 * ((int)blockIdx.x - sb.lb), sb.nb, sigma_g_fixed, s_red);
+  const double sg = cloud_sigma_g(edge_acc + (size_t)kEdgeSlots * kEdgeVals * sb.s, sigma_g_fixed,
+                                  reinterpret_cast<unsigned long long *>(s_red));
   if (sb.lb == 0 && threadIdx.x == 0) res[sb.s].sigma_g = sg;
   fill_exp_table(sg, s_exp);
   __syncthreads();
@@ -377,7 +382,7 @@ hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int3
   const int k = r.prm.k, window = r.prm.window;
   const int nb = r.pl.grid[kGridMerge];
   const uint32_t *rank = r.b.rank;
-  double *part = r.b.merge_part;
+  unsigned long long *part = r.b.edge_acc;
   hipStream_t st = r.stream;
   const bool small = r.pl.n_cap < (1 << 24);  // 32-bit keys hold the index in 24 bits
   if (small && k <= 8 && window == 4)
@@ -400,9 +405,9 @@ hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int3
 hipError_t launch_weights(const Run &r, const int32_t *col, const int32_t *dist2, fgbd_result *res, float *p) {
   const int nb = r.pl.grid[kGridMerge];
   if (r.prm.k == 8)
-    k_weights<8><<<nb, kBlock, 0, r.stream>>>(r.sa, 8, col, dist2, r.b.merge_part, r.prm.sigma_g, res, p);
+    k_weights<8><<<nb, kBlock, 0, r.stream>>>(r.sa, 8, col, dist2, r.b.edge_acc, r.prm.sigma_g, res, p);
   else
-    k_weights<0><<<nb, kBlock, 0, r.stream>>>(r.sa, r.prm.k, col, dist2, r.b.merge_part, r.prm.sigma_g, res, p);
+    k_weights<0><<<nb, kBlock, 0, r.stream>>>(r.sa, r.prm.k, col, dist2, r.b.edge_acc, r.prm.sigma_g, res, p);
   return hipGetLastError();
 }
 

@@ -135,47 +135,6 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
   return base + x - v;
 }
 
-// Totals of per-block partial sums (nparts rows of `stride` doubles, first NV
-// used).  Every block that calls this sums the same rows in the same order,
-// so all blocks obtain bit-identical totals without any inter-block
-// synchronisation inside a kernel: the partials were written by an earlier
-// launch on the same stream.  s_buf: >= 4 * NV doubles of LDS.
-template <int NV>
-__device__ __forceinline__ void reduce_partials(const double *__restrict__ part, int nparts, int stride,
-                                                double (&out)[NV], double *s_buf) {
-  double v[NV];
-#pragma unroll
-  for (int j = 0; j < NV; ++j) v[j] = 0.0;
-  // eight rows per thread in flight, added in row order (the same sums as a
-  // plain strided loop)
-  constexpr int U = 8;
-  for (int b0 = threadIdx.x; b0 < nparts; b0 += U * blockDim.x) {
-    double w[U][NV];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int b = b0 + u * (int)blockDim.x;
-#pragma unroll
-      for (int j = 0; j < NV; ++j) w[u][j] = b < nparts ? part[(size_t)b * stride + j] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (b0 + u * (int)blockDim.x < nparts) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] += w[u][j];
-      }
-    }
-  }
-  block_sum_f64<NV>(v, s_buf);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int j = 0; j < NV; ++j) s_buf[j] = v[j];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < NV; ++j) out[j] = s_buf[j];
-  __syncthreads();
-}
-
 // ------------------------------------------------------------- segments
 // A call covers B clouds stored back to back; cloud s owns the points
 // start[s] .. start[s+1]-1, and in every direction's sorted order it owns the
@@ -268,20 +227,6 @@ __device__ __forceinline__ Share seg_share(const SegBlock &sb, int chunk) {
   return s;
 }
 
-// Blocks of per-cloud grid `grid` that belong to cloud s: *first, *count.
-// grid_size is that grid's size, which a single host-sized cloud owns whole.
-__device__ __forceinline__ void seg_blocks_of(const SegArgs &a, int grid, int s, int grid_size, int *first,
-                                              int *count) {
-  if (a.n_fixed >= 0) {
-    *first = 0;
-    *count = grid_size;
-    return;
-  }
-  const int f0 = a.segs->blk_first[grid][s];
-  *first = f0;
-  *count = a.segs->blk_first[grid][s + 1] - f0;
-}
-
 // ------------------------------------------------------------ edge weights
 // Eq. 4 on the integer squared distances of a CSR row: w_k = exp(-(d_k -
 // d_0) / sigma_g^2) over the valid slots (d_0 is the nearest neighbour's, so
@@ -292,15 +237,40 @@ __device__ __forceinline__ void seg_blocks_of(const SegArgs &a, int grid, int s,
 // comes from a table in LDS.
 constexpr int kExpTable = 256;
 
+// Edge lengths for sigma_g: every merge block adds its FP64 sum of edge
+// lengths into integers of its cloud as the integer part and the fraction in
+// units of 2^-40, and its edge count (exact integer sums in any order; each
+// block's sum is rounded by at most 2^-41).  Blocks spread their atomics over
+// kEdgeSlots slots (block index mod kEdgeSlots): thousands of blocks adding
+// into one word serialise.
+constexpr int kEdgeVals = 3;  // integer part, fraction * 2^40, count
+constexpr int kEdgeSlots = 64;
+constexpr double kEdgeFrac = 1099511627776.0;  // 2^40
+
 // sigma_g of one cloud: the fixed value when positive, else the mean merge
-// edge length from the merge launch's per-block partials (sum, count) of
-// that cloud.  Called by every thread of the block.
-__device__ __forceinline__ double cloud_sigma_g(const double *__restrict__ part, int nparts, double fixed,
-                                                double *s_red) {
+// edge length from the cloud's edge sums (acc: its [kEdgeSlots][kEdgeVals]
+// integers; the first wave adds the slots).  Called by every thread of the
+// block; s_u: kEdgeVals integers of LDS.
+__device__ __forceinline__ double cloud_sigma_g(const unsigned long long *__restrict__ acc, double fixed,
+                                                unsigned long long *s_u) {
   if (fixed > 0.0) return fixed;
-  double t[2];
-  reduce_partials<2>(part, nparts, 2, t, s_red);
-  return t[1] > 0.0 ? t[0] / t[1] : 0.0;
+  static_assert(kEdgeSlots == kWave, "one slot per lane");
+  if (threadIdx.x < kWave) {
+    unsigned long long v[kEdgeVals];
+#pragma unroll
+    for (int j = 0; j < kEdgeVals; ++j) v[j] = acc[threadIdx.x * kEdgeVals + j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int j = 0; j < kEdgeVals; ++j) v[j] += __shfl_xor(v[j], o, kWave);
+    }
+    if (threadIdx.x < kEdgeVals) s_u[threadIdx.x] = v[threadIdx.x];
+  }
+  __syncthreads();
+  const unsigned long long cnt = s_u[2];
+  const double total = (double)s_u[0] + (double)s_u[1] / kEdgeFrac;
+  __syncthreads();  // s_u may be reused
+  return cnt > 0 ? total / (double)cnt : 0.0;
 }
 
 // Fills s_exp[g] = exp(-g / sigma_g^2); the caller synchronises the block.
@@ -370,7 +340,7 @@ struct Plan {
   int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
   size_t off_segs, off_items_a, off_items_b, off_hist, off_rank, off_digits;
   size_t off_col, off_dist2, off_p, off_spread, off_xbuf;
-  size_t off_merge_part, off_noise_acc, off_ctrl, off_sweep_sums;
+  size_t off_edge_acc, off_noise_acc, off_ctrl, off_sweep_sums;
   size_t total;
 };
 
@@ -421,7 +391,7 @@ struct Bufs {
   float *p;                     // [n_cap][K] weights the fused path's first sweep stores
   double *spread;               // [n_cap]
   float4 *xbuf;                 // [3][n_cap]
-  double *merge_part;           // [grid merge][2]
+  unsigned long long *edge_acc;  // [B][kEdgeSlots][kEdgeVals] edge-length sums for sigma_g
   unsigned long long *noise_acc;  // [B][kNoiseSlots][E1] fixed-point patch moments
   SweepCtrl *ctrl;              // [2][B]
   unsigned long long *sums;     // [3][B][slots][parts]
@@ -493,12 +463,12 @@ bool sweep_tail_fits(const Run &r);
 
 // Sweeps q0..q_last in one launch whose blocks wait for each other between
 // sweeps, after separate launches of sweeps 1..q0-1 (same arguments as
-// launch_sweep); returns at once when every cloud's selection was done at the
-// start of sweep q0-1.  Uses the segment table's barrier counter (zeroed by
-// the setup launch of the call).
+// launch_sweep), then the work of launch_finalize; skips the sweeps when
+// every cloud's selection was done at the start of sweep q0-1.  Uses the
+// segment table's barrier counter (zeroed by the setup launch of the call).
 hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, const float *rgb_in,
                              const double *spread, const fgbd_result *noise, fgbd_result *res, int select,
-                             int q_limit, int q0, int q_last);
+                             int q_limit, int q0, int q_last, float *rgb_out);
 
 // r.hint != NULL: block 0 of each cloud also stores its sweep count there.
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,
