@@ -171,111 +171,6 @@ Bufs carve(char *ws, const Plan &pl) {
   return b;
 }
 
-namespace {
-
-struct SetupArgs {
-  const int64_t *offsets;  // device, B + 1 entries, or NULL
-  int64_t n_host;          // the one cloud's size when offsets is NULL
-  int64_t n_cap;
-  int32_t B;
-  int32_t grid[kNumGrids];
-  int32_t zero_result;
-  int32_t sums_count;  // first sweep's sums to clear (uint64)
-  int32_t noise_count;  // noise moment accumulators to clear (uint64)
-  unsigned long long *edge_acc;
-  int32_t edge_count;   // edge-length sums to clear (uint64)
-  unsigned long long *noise_acc;
-};
-
-// All blocks clear the first sweep's sums and the noise moment accumulators;
-// block 0 builds the segment table:
-// offsets clamped into a valid form (start[0] = 0, non-decreasing, at most
-// n_cap), radix tiles per cloud, and each per-cloud grid's block ranges
-// first(s) = floor(start[s] (G - B) / n) + s (at least one block per cloud).
-__global__ __launch_bounds__(256) void k_setup(SetupArgs a, Segs *__restrict__ sg,
-                                               unsigned long long *__restrict__ sums1, fgbd_result *__restrict__ res) {
-  __shared__ int64_t s_raw[kMaxSeg + 1];
-  __shared__ int32_t s_start[kMaxSeg + 1], s_tf[kMaxSeg + 1];
-  __shared__ int32_t s_bad;
-  const int t = threadIdx.x;
-  for (int i = blockIdx.x * blockDim.x + t; i < a.sums_count; i += gridDim.x * blockDim.x) sums1[i] = 0ull;
-  for (int i = blockIdx.x * blockDim.x + t; i < a.noise_count; i += gridDim.x * blockDim.x) a.noise_acc[i] = 0ull;
-  for (int i = blockIdx.x * blockDim.x + t; i < a.edge_count; i += gridDim.x * blockDim.x) a.edge_acc[i] = 0ull;
-  if (blockIdx.x != 0) return;  // uniform over the block
-  const int B = a.B;
-  if (t <= B) s_raw[t] = a.offsets ? a.offsets[t] : (t == 0 ? 0 : a.n_host);
-  __syncthreads();
-  if (t == 0) {
-    int bad = s_raw[0] != 0;
-    int64_t prev = 0;
-    int32_t tiles = 0;
-    s_start[0] = 0;
-    for (int s = 1; s <= B; ++s) {
-      int64_t v = s_raw[s];
-      v = v < prev ? prev : v;
-      v = v > a.n_cap ? a.n_cap : v;
-      bad |= v != s_raw[s];
-      s_start[s] = (int32_t)v;
-      s_tf[s - 1] = tiles;
-      tiles += (int32_t)((v - prev + kSortTile - 1) / kSortTile);
-      prev = v;
-    }
-    s_tf[B] = tiles;
-    s_bad = bad;
-    sg->B = B;
-    sg->n = s_start[B];
-    sg->ntiles = tiles;
-    sg->status = bad ? FGBD_ST_BAD_OFFSETS : 0;
-    sg->sweep_barrier = 0u;
-  }
-  __syncthreads();
-  if (t <= B) {
-    sg->start[t] = s_start[t];
-    sg->tile_first[t] = s_tf[t];
-    const int64_t n = s_start[B];
-#pragma unroll
-    for (int g = 0; g < kNumGrids; ++g) {
-      const int G = a.grid[g];
-      sg->blk_first[g][t] = t == B ? G : (n > 0 ? (int32_t)((int64_t)s_start[t] * (G - B) / n) + t : t);
-    }
-  }
-  if (t < B && res && a.zero_result) {
-    fgbd_result *r = res + t;
-    r->sigma_est = 0.0;
-    r->sigma_g = 0.0;
-    r->loss = 0.0;
-    r->q = 0;
-    r->n_fslr = 0;
-    r->n_eff = 0;
-    r->status = (s_bad ? FGBD_ST_BAD_OFFSETS : 0) | (a.zero_result == 2 ? FGBD_ST_NO_PATCH : 0);
-    r->sweeps = 0;
-    r->m = 0;
-  }
-}
-
-}  // namespace
-
-hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result) {
-  SetupArgs a;
-  a.offsets = offsets;
-  a.n_host = n_host;
-  a.n_cap = r.pl.n_cap;
-  a.B = r.pl.B;
-  for (int g = 0; g < kNumGrids; ++g) a.grid[g] = r.pl.grid[g];
-  a.zero_result = zero_result;
-  a.sums_count = r.pl.B * kSweepSlots * kSweepParts;
-  a.noise_count = r.pl.B * r.pl.E1 * kNoiseSlots;
-  a.noise_acc = r.b.noise_acc;
-  a.edge_count = r.pl.B * kEdgeSlots * kEdgeVals;
-  a.edge_acc = r.b.edge_acc;
-  const int most = a.sums_count > a.noise_count ? a.sums_count : a.noise_count;
-  int blocks = (most + 256 * 8 - 1) / (256 * 8);
-  blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
-  // the first sweep adds into sums buffer 1 (see launch_sweep)
-  k_setup<<<blocks, 256, 0, r.stream>>>(a, r.b.segs, r.b.sums + (size_t)a.sums_count, res);
-  return hipGetLastError();
-}
-
 }  // namespace fgbd
 
 namespace {
@@ -738,8 +633,13 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
   Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
-  HIP_TRY(launch_setup(r, nullptr, n, res, n == 0 ? 2 : 1), "setup launch");
-  if (n == 0) return ok();
+  if (n == 0) {
+    HIP_TRY(launch_setup(r, nullptr, n, res, 2), "setup launch");
+    return ok();
+  }
+  // the first radix launch does the setup
+  r.fold_setup = true;
+  r.setup = setup_args(r, nullptr, n, res, 1);
   r.sweep_launches = adaptive_sweep_launches(ctx, s, &r.hint);
   if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
   if (r.hint) request_hint(ctx, s, 1);

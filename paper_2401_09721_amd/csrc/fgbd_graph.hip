@@ -2,8 +2,9 @@
 //
 // k_merge: one thread per point i.  For each direction it looks up i's sorted
 // position r (rank array from the last radix pass), reads the items at
-// r-w..r+w inside the cloud's range of positions (squared distances follow
-// from differences of the code fields, so no coordinate is gathered), and
+// r-w..r+w inside the cloud's range of positions (the last pass stores each
+// item's packed coordinates in place of its code, so no coordinate is
+// gathered), and
 // keeps the K smallest distinct (squared distance, index) pairs in a
 // register-resident sorted list (packed so one integer compare orders by
 // distance then index).  It writes the fixed-K CSR row, and each block adds
@@ -23,51 +24,30 @@ namespace fgbd {
 
 namespace {
 
-// Squared distance between the points of two codes of one direction, from
-// the code fields alone: with da = difference of position coordinates and
-// dm, dh = differences of the line invariants, the coordinate differences are
-// da, dm + u_m da and dh + u_h da.
-struct DirConst {
-  uint32_t top, mmask;
-  int bits, wm, hshift, uh, um;
-};
-__device__ __forceinline__ DirConst dir_const(const DirInfo &di, int bits) {
-  DirConst c;
-  c.top = (1u << bits) - 1u;
-  const int wm = bits + di.wm_extra;
-  c.mmask = (1u << wm) - 1u;
-  c.bits = bits;
-  c.wm = wm;
-  c.hshift = bits + wm;
-  c.uh = di.uh;
-  c.um = di.um;
-  return c;
-}
-// a * b + c on the full-rate 24-bit multiplier (operands within +-2^23).
-// Written out because the compiler otherwise folds a 24-bit product and an
-// add into a 64-bit multiply-add.
+// Squared distance between two points from their packed coordinates
+// (x | y << b | z << 2b, b = grid bits <= 10), the form in which the last radix
+// pass stores the sorted items.  Every factor is below 2^11 in magnitude, so
+// the products run on the full-rate 24-bit multiplier.
+// a * b + c on the 24-bit multiplier (operands within +-2^23).  Written out
+// because the compiler otherwise folds a 24-bit product and an add into a
+// 64-bit multiply-add.
 __device__ __forceinline__ int mad_i24(int a, int b, int c) {
   int d;
   asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
   return d;
 }
-// The fields of one code (position coordinate, middle and high invariants).
-struct CodeFields {
-  int a, m, h;
+struct Pt {
+  int x, y, z;
 };
-__device__ __forceinline__ CodeFields code_fields(uint32_t ci, const DirConst &c) {
-  return {(int)(ci & c.top), (int)__builtin_amdgcn_ubfe(ci, c.bits, c.wm), (int)(ci >> c.hshift)};
+__device__ __forceinline__ Pt unpack_pt(uint32_t c, int bits) {
+  return {(int)__builtin_amdgcn_ubfe(c, 0u, (uint32_t)bits), (int)__builtin_amdgcn_ubfe(c, (uint32_t)bits, (uint32_t)bits),
+          (int)(c >> (2 * bits))};
 }
-// Every factor is below 2^13 in magnitude (b <= 10, |u| <= 2) and the sum
-// below 2^28.
-__device__ __forceinline__ uint32_t code_dist2(const CodeFields &fi, uint32_t cj, const DirConst &c) {
-  const int da = (int)(cj & c.top) - fi.a;
-  const int dm = mad_i24(c.um, da, (int)__builtin_amdgcn_ubfe(cj, c.bits, c.wm) - fi.m);
-  const int dh = mad_i24(c.uh, da, (int)(cj >> c.hshift) - fi.h);
-  return (uint32_t)mad_i24(da, da, mad_i24(dm, dm, __mul24(dh, dh)));
-}
-__device__ __forceinline__ uint32_t code_dist2(uint32_t ci, uint32_t cj, const DirConst &c) {
-  return code_dist2(code_fields(ci, c), cj, c);
+__device__ __forceinline__ uint32_t pt_dist2(const Pt &pi, uint32_t cj, int bits) {
+  const int dx = (int)__builtin_amdgcn_ubfe(cj, 0u, (uint32_t)bits) - pi.x;
+  const int dy = (int)__builtin_amdgcn_ubfe(cj, (uint32_t)bits, (uint32_t)bits) - pi.y;
+  const int dz = (int)(cj >> (2 * bits)) - pi.z;
+  return (uint32_t)mad_i24(dx, dx, mad_i24(dy, dy, __mul24(dz, dz)));
 }
 
 template <int KM, typename Key>
@@ -157,22 +137,21 @@ struct MergeArgs {
 // lo..hi: used for all points when the capacity reaches 2^24 and for the rare
 // point whose 32-bit selection kept a clamped distance.
 template <int KM>
-__device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int window, const DirInfo *s_dir,
+__device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int window,
                              const uint64_t *__restrict__ sorted, const uint32_t *__restrict__ rank,
                              uint64_t (&lst)[KM]) {
 #pragma unroll
   for (int k = 0; k < KM; ++k) lst[k] = ~0ull;
   for (int d = 0; d < a.dt.num_dirs; ++d) {
-    const DirConst dc = dir_const(s_dir[d], a.dt.bits);
     const int r = (int)rank[(size_t)d * a.stride + i];
     const uint64_t *srt = sorted + (size_t)d * a.stride;
-    const CodeFields fi = code_fields((uint32_t)(srt[r] >> 32), dc);
+    const Pt pi = unpack_pt((uint32_t)(srt[r] >> 32), a.dt.bits);
     const int l = max(r - window, lo);
     const int h = min(r + window, hi);
     for (int rr = l; rr <= h; ++rr) {
       if (rr == r) continue;
       const uint64_t it = srt[rr];
-      topk_insert_t<KM, uint64_t>(lst, a.K, ((uint64_t)code_dist2(fi, (uint32_t)(it >> 32), dc) << 32) | (uint32_t)it);
+      topk_insert_t<KM, uint64_t>(lst, a.K, ((uint64_t)pt_dist2(pi, (uint32_t)(it >> 32), a.dt.bits) << 32) | (uint32_t)it);
     }
   }
 }
@@ -196,12 +175,11 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
                                                   unsigned long long *__restrict__ edge_acc) {
   __shared__ double s_red[8];
   __shared__ int s_rank[WT > 0 ? kMaxDirs : 1][kBlock];
-  __shared__ DirInfo s_dir[kMaxDirs];
   double acc[2] = {0.0, 0.0};
   const int L = a.dt.num_dirs;
   const int K = a.K;
+  const int bits = a.dt.bits;
   const int t = threadIdx.x;
-  if (t < kMaxDirs) s_dir[t] = a.dt.d[t];
   const SegBlock sb = seg_block(a.sa, kGridMerge);
   const int lo = (int)sb.begin, hi = (int)sb.end - 1;
   __syncthreads();
@@ -220,7 +198,6 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
       for (int d = 0; d < L; ++d) {
         const uint64_t *srt = sorted + (size_t)d * a.stride;
         const int r = s_rank[d][t];
-        const DirConst dc = dir_const(s_dir[d], a.dt.bits);
         uint64_t cur[2 * WT + 1];
         uint32_t kc[2 * WT];
         // Wave-uniform: when every window of the wave lies inside the
@@ -230,20 +207,20 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
           const uint64_t *wp = srt + (r - WT);
 #pragma unroll
           for (int s = 0; s <= 2 * WT; ++s) cur[s] = wp[s];
-          const CodeFields fi = code_fields((uint32_t)(cur[WT] >> 32), dc);
+          const Pt pi = unpack_pt((uint32_t)(cur[WT] >> 32), bits);
 #pragma unroll
           for (int s = 0; s < 2 * WT; ++s) {
             const uint64_t it = cur[s < WT ? s : s + 1];
-            const uint32_t d2 = code_dist2(fi, (uint32_t)(it >> 32), dc);
+            const uint32_t d2 = pt_dist2(pi, (uint32_t)(it >> 32), bits);
             kc[s] = (min(d2, kKeyD2Max) << 24) | (uint32_t)it;
           }
         } else {
           load_window<WT>(srt, r, lo, hi, cur);
-          const CodeFields fi = code_fields((uint32_t)(cur[WT] >> 32), dc);
+          const Pt pi = unpack_pt((uint32_t)(cur[WT] >> 32), bits);
 #pragma unroll
           for (int s = 0; s < 2 * WT; ++s) {
             const uint64_t it = cur[s < WT ? s : s + 1];
-            const uint32_t d2 = code_dist2(fi, (uint32_t)(it >> 32), dc);
+            const uint32_t d2 = pt_dist2(pi, (uint32_t)(it >> 32), bits);
             kc[s] = it == ~0ull ? ~0u : ((min(d2, kKeyD2Max) << 24) | (uint32_t)it);
           }
         }
@@ -271,14 +248,14 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
 #pragma unroll
       for (int k = 0; k < KM; ++k) clamped |= (k < K) & (key[k] != ~0u) & ((key[k] >> 24) == kKeyD2Max);
       if (clamped) {
-        select_exact<KM>(a, i, lo, hi, WT, s_dir, sorted, rank, lst);
+        select_exact<KM>(a, i, lo, hi, WT, sorted, rank, lst);
       } else {
 #pragma unroll
         for (int k = 0; k < KM; ++k)
           lst[k] = key[k] == ~0u ? ~0ull : ((uint64_t)(key[k] >> 24) << 32) | (key[k] & 0xffffffu);
       }
     } else {
-      select_exact<KM>(a, i, lo, hi, a.window, s_dir, sorted, rank, lst);
+      select_exact<KM>(a, i, lo, hi, a.window, sorted, rank, lst);
     }
     int cv[KM], dv[KM];
 #pragma unroll

@@ -418,6 +418,25 @@ struct Prof {
 // ------------------------------------------------------------- launchers
 // Everything one call's launches need.  All launchers enqueue on r.stream
 // and return hipSuccess or the launch error.
+// The per-call setup: the segment table from device offsets (B + 1 entries)
+// or from one host-known size, the clears of the first sweep's sums and of
+// the moment and edge accumulators, and optionally zeroed results.
+struct SetupArgs {
+  const int64_t *offsets;  // device, B + 1 entries, or NULL
+  int64_t n_host;          // the one cloud's size when offsets is NULL
+  int64_t n_cap;
+  int32_t B;
+  int32_t grid[kNumGrids];
+  int32_t zero_result;  // 0 leave res, 1 zero res[0..B-1], 2 zero and flag FGBD_ST_NO_PATCH
+  int32_t sums_count;   // first sweep's sums to clear (uint64)
+  int32_t noise_count;  // noise moment accumulators to clear (uint64)
+  int32_t edge_count;   // edge-length sums to clear (uint64)
+  int32_t blocks;       // blocks that share the clears
+  unsigned long long *sums1, *noise_acc, *edge_acc;
+  Segs *sg;
+  fgbd_result *res;
+};
+
 struct Run {
   Plan pl;
   Bufs b;
@@ -428,12 +447,17 @@ struct Run {
   Prof *pf;
   int32_t sweep_launches;  // sweeps enqueued as launches of their own
   int32_t *hint = nullptr;  // host-mapped: the finalising launch stores each cloud's sweep count here
+  // set: the first radix launch also does the call's setup (one cloud of
+  // host-known size; saves a launch)
+  bool fold_setup = false;
+  SetupArgs setup;
 };
 
 // Segment table from device offsets (B+1 entries) or, with offsets == NULL,
 // one cloud of n_host points; clears the first sweep's sums.  zero_result: 0 leave res, 1 zero res[0..B-1], 2 zero and flag
 // FGBD_ST_NO_PATCH.
 hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result);
+SetupArgs setup_args(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result);
 
 hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const uint64_t **sorted_out);
 

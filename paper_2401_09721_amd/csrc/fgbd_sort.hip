@@ -12,7 +12,9 @@
 //             order, then write runs of equal digits to their global offsets.
 // Pass 0 computes the codes from the int32 coordinates on the fly; the last
 // pass also writes rank[dir][index] = sorted position, which the neighbour
-// search uses to find each point's place in every order.
+// search uses to find each point's place in every order, and stores each
+// sorted item with the point's packed coordinates (x | y << b | z << 2b) in
+// place of its code.
 //
 // Several clouds are sorted in the same launches, each inside its own range
 // of positions: tiles never straddle two clouds, the scan runs over all tiles
@@ -33,6 +35,8 @@ struct SortArgs {
   int32_t row;        // hist row length (tile capacity + 1: the row total)
   int32_t shift;      // digit shift of this pass
   int32_t pass;
+  int32_t fold;       // pass 0 only: the first blocks also do the call's setup
+  SetupArgs su;
 };
 
 // The tile's cloud and point range; false for a tile beyond the last one.
@@ -132,6 +136,20 @@ __device__ __forceinline__ uint32_t gen_code(const CodeGen &c, int gx, int gy, i
   return (((eh << c.wm) + em) << c.bits) | (uint32_t)ga;
 }
 
+// The inverse of gen_code, packed as x | y << b | z << 2b (b = grid bits).
+__device__ __forceinline__ uint32_t decode_packed(const CodeGen &c, uint32_t code) {
+  const uint32_t top = (1u << c.bits) - 1u;
+  const int ga = (int)(code & top);
+  const int em = (int)((code >> c.bits) & ((1u << c.wm) - 1u));
+  const int eh = (int)(code >> (c.bits + c.wm));
+  const int gm = em + c.um * ga - (int)c.om;
+  const int gh = eh + c.uh * ga - (int)c.oh;
+  const int gx = c.ia == 0 ? ga : (c.ih == 0 ? gh : gm);
+  const int gy = c.ia == 1 ? ga : (c.ih == 1 ? gh : gm);
+  const int gz = c.ia == 2 ? ga : (c.ih == 2 ? gh : gm);
+  return (uint32_t)gx | ((uint32_t)gy << c.bits) | ((uint32_t)gz << (2 * c.bits));
+}
+
 __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const CodeGen &cg, const int32_t *__restrict__ xyz,
                                               const uint64_t *__restrict__ src, int d, int pos, int *bad) {
   if (a.pass == 0) {
@@ -143,6 +161,77 @@ __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const CodeGen &
   return src[(size_t)d * a.stride + pos];
 }
 
+// All blocks clear the first sweep's sums and the noise moment accumulators;
+// block 0 builds the segment table:
+// offsets clamped into a valid form (start[0] = 0, non-decreasing, at most
+// n_cap), radix tiles per cloud, and each per-cloud grid's block ranges
+// first(s) = floor(start[s] (G - B) / n) + s (at least one block per cloud).
+__device__ __forceinline__ void setup_work(const SetupArgs &a, int block) {
+  Segs *__restrict__ sg = a.sg;
+  unsigned long long *__restrict__ sums1 = a.sums1;
+  fgbd_result *__restrict__ res = a.res;
+  __shared__ int64_t s_raw[kMaxSeg + 1];
+  __shared__ int32_t s_start[kMaxSeg + 1], s_tf[kMaxSeg + 1];
+  __shared__ int32_t s_bad;
+  const int t = threadIdx.x;
+  const int stride = a.blocks * (int)blockDim.x;
+  for (int i = block * blockDim.x + t; i < a.sums_count; i += stride) sums1[i] = 0ull;
+  for (int i = block * blockDim.x + t; i < a.noise_count; i += stride) a.noise_acc[i] = 0ull;
+  for (int i = block * blockDim.x + t; i < a.edge_count; i += stride) a.edge_acc[i] = 0ull;
+  if (block != 0) return;  // uniform over the block
+  const int B = a.B;
+  if (t <= B) s_raw[t] = a.offsets ? a.offsets[t] : (t == 0 ? 0 : a.n_host);
+  __syncthreads();
+  if (t == 0) {
+    int bad = s_raw[0] != 0;
+    int64_t prev = 0;
+    int32_t tiles = 0;
+    s_start[0] = 0;
+    for (int s = 1; s <= B; ++s) {
+      int64_t v = s_raw[s];
+      v = v < prev ? prev : v;
+      v = v > a.n_cap ? a.n_cap : v;
+      bad |= v != s_raw[s];
+      s_start[s] = (int32_t)v;
+      s_tf[s - 1] = tiles;
+      tiles += (int32_t)((v - prev + kSortTile - 1) / kSortTile);
+      prev = v;
+    }
+    s_tf[B] = tiles;
+    s_bad = bad;
+    sg->B = B;
+    sg->n = s_start[B];
+    sg->ntiles = tiles;
+    sg->status = bad ? FGBD_ST_BAD_OFFSETS : 0;
+    sg->sweep_barrier = 0u;
+  }
+  __syncthreads();
+  if (t <= B) {
+    sg->start[t] = s_start[t];
+    sg->tile_first[t] = s_tf[t];
+    const int64_t n = s_start[B];
+#pragma unroll
+    for (int g = 0; g < kNumGrids; ++g) {
+      const int G = a.grid[g];
+      sg->blk_first[g][t] = t == B ? G : (n > 0 ? (int32_t)((int64_t)s_start[t] * (G - B) / n) + t : t);
+    }
+  }
+  if (t < B && res && a.zero_result) {
+    fgbd_result *r = res + t;
+    r->sigma_est = 0.0;
+    r->sigma_g = 0.0;
+    r->loss = 0.0;
+    r->q = 0;
+    r->n_fslr = 0;
+    r->n_eff = 0;
+    r->status = (s_bad ? FGBD_ST_BAD_OFFSETS : 0) | (a.zero_result == 2 ? FGBD_ST_NO_PATCH : 0);
+    r->sweeps = 0;
+    r->m = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_setup(SetupArgs a) { setup_work(a, (int)blockIdx.x); }
+
 // Per-tile digit counts.  Pass 0 makes the codes from the coordinates;
 // later passes read only the byte array of this pass's digits that the
 // previous downsweep wrote beside the items (16 digits per thread, one
@@ -151,10 +240,13 @@ __device__ __forceinline__ uint64_t load_item(const SortArgs &a, const CodeGen &
 // digit, or a bank, mostly hit different words; the 8 are summed at the end.
 __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const int32_t *__restrict__ xyz,
                                                                const uint8_t *__restrict__ digits,
-                                                               uint32_t *__restrict__ hist,
-                                                               fgbd_result *__restrict__ res) {
+                                                               uint32_t *__restrict__ hist) {
   constexpr int kSub = 8, kSubStride = 257;
   __shared__ uint32_t s_hs[kSub * kSubStride];
+  if (a.fold) {  // the call's setup, by the first blocks (no other work of this launch reads it)
+    const int lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (lin < a.su.blocks) setup_work(a.su, lin);
+  }
   int d, tile;
   xcd_tile(d, tile);
   TileInfo ti;
@@ -180,14 +272,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
     // the input in a raster order, the digit (low bits of the position
     // along the line) is often the same for a thread's items, and for every
     // lane of the wave, whose atomics on one word would serialise.
-    const uint32_t top = (1u << a.dt.bits) - 1u;
     const CodeGen cg = code_gen(a.dt, d);
-    int bad = 0;
     uint32_t run_digit = 0, run_count = 0;
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       if (base + j * kWave < ti.end) {
-        if ((uint32_t)g[j][0] > top || (uint32_t)g[j][1] > top || (uint32_t)g[j][2] > top) bad = 1;
         const uint32_t digit = gen_code(cg, g[j][0], g[j][1], g[j][2]) & 255u;
         if (run_count != 0 && digit != run_digit) {
           atomicAdd(&s_h[run_digit], run_count);
@@ -198,7 +287,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
       }
     }
     if (run_count != 0) atomicAdd(&s_h[run_digit], run_count);
-    if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
   } else {
     // tile starts are multiples of 16 inside the direction's row (clouds
     // start at any position, so only the bytes of the tile are counted)
@@ -347,7 +435,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
                                                                  uint64_t *__restrict__ dst,
                                                                  const uint32_t *__restrict__ hist,
                                                                  uint8_t *__restrict__ digits,
-                                                                 uint32_t *__restrict__ rank) {
+                                                                 uint32_t *__restrict__ rank,
+                                                                 fgbd_result *__restrict__ res) {
   __shared__ uint32_t s_wh[4][256];
   __shared__ uint32_t s_off[256];
   __shared__ uint32_t s_base[256];
@@ -386,6 +475,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
     const int pos = base + j * kWave;
     item[j] = (pos < ti.end) ? load_item(a, cg, xyz, src, d, pos, &bad) : ~0ull;
   }
+  // pass 0: coordinates outside the grid (flagged once, by direction 0)
+  if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
   __syncthreads();
 
   // Stable rank of each item among the equal digits of its wave: items are
@@ -444,15 +535,47 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
     const uint64_t it = s_stage[s];
     const uint32_t digit = digit_of(it, a.shift);
     const uint32_t gpos = s_off[digit] + (uint32_t)s - s_base[digit];
-    out[gpos] = it;
-    if (last_pass)
+    if (last_pass) {
+      // the sorted item keeps its index and carries the point's packed
+      // coordinates instead of its code (the neighbour search's form)
+      out[gpos] = ((uint64_t)decode_packed(cg, (uint32_t)(it >> 32)) << 32) | (uint32_t)it;
       rank[(size_t)d * a.stride + (uint32_t)it] = gpos;
-    else
+    } else {
+      out[gpos] = it;
       dig[gpos] = (uint8_t)(it >> (40 + a.shift));  // the next pass's digit
+    }
   }
 }
 
 }  // namespace
+
+SetupArgs setup_args(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result) {
+  SetupArgs a;
+  a.offsets = offsets;
+  a.n_host = n_host;
+  a.n_cap = r.pl.n_cap;
+  a.B = r.pl.B;
+  for (int g = 0; g < kNumGrids; ++g) a.grid[g] = r.pl.grid[g];
+  a.zero_result = zero_result;
+  a.sums_count = r.pl.B * kSweepSlots * kSweepParts;
+  a.noise_count = r.pl.B * r.pl.E1 * kNoiseSlots;
+  a.edge_count = r.pl.B * kEdgeSlots * kEdgeVals;
+  const int most = a.sums_count > a.noise_count ? a.sums_count : a.noise_count;
+  int blocks = (most + 256 * 8 - 1) / (256 * 8);
+  a.blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
+  a.sums1 = r.b.sums + (size_t)a.sums_count;  // the first sweep adds into sums buffer 1 (see launch_sweep)
+  a.noise_acc = r.b.noise_acc;
+  a.edge_acc = r.b.edge_acc;
+  a.sg = r.b.segs;
+  a.res = res;
+  return a;
+}
+
+hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result) {
+  const SetupArgs a = setup_args(r, offsets, n_host, res, zero_result);
+  k_setup<<<a.blocks, 256, 0, r.stream>>>(a);
+  return hipGetLastError();
+}
 
 hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const uint64_t **sorted_out) {
   SortArgs a;
@@ -460,6 +583,8 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
   a.sa = r.sa;
   a.stride = r.pl.stride;
   a.row = r.pl.ntiles_cap + 1;
+  a.fold = 0;
+  a.su = r.setup;
   const int ntiles = r.sa.n_fixed >= 0 ? (r.sa.n_fixed + kSortTile - 1) / kSortTile : r.pl.ntiles_cap;
   const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
   const uint64_t *src = nullptr;
@@ -469,13 +594,15 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
     a.shift = 8 * pass;
     uint64_t *dst = bufs[pass & 1];
     FGBD_PRE(r.pf, kUpsweep);
-    k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, r.b.digits, r.b.hist, res);
+    a.fold = (pass == 0 && r.fold_setup) ? 1 : 0;
+    if (a.fold && a.su.blocks > (int)(grid.x * grid.y)) a.su.blocks = (int)(grid.x * grid.y);  // clears are strided
+    k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, r.b.digits, r.b.hist);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kScan);
     k_sort_scan<<<r.dt.num_dirs * 4, kScanWaves * kWave, 0, r.stream>>>(a, r.b.hist);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kDownsweep);
-    k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.digits, r.b.rank);
+    k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.digits, r.b.rank, res);
     FGBD_POST(r.pf);
     src = dst;
   }
