@@ -175,11 +175,15 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
                                                   unsigned long long *__restrict__ edge_acc) {
   __shared__ double s_red[8];
   __shared__ int s_rank[WT > 0 ? kMaxDirs : 1][kBlock];
+  // edge lengths sqrt(d2) of the small squared distances, each computed once
+  // per block (the same correctly rounded values as computing them inline)
+  __shared__ double s_sqrt[kKeyD2Max + 1];
   double acc[2] = {0.0, 0.0};
   const int L = a.dt.num_dirs;
   const int K = a.K;
   const int bits = a.dt.bits;
   const int t = threadIdx.x;
+  for (int v = t; v <= (int)kKeyD2Max; v += kBlock) s_sqrt[v] = sqrt((double)v);
   const SegBlock sb = seg_block(a.sa, kGridMerge);
   const int lo = (int)sb.begin, hi = (int)sb.end - 1;
   __syncthreads();
@@ -195,6 +199,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
       uint32_t key[KM];
 #pragma unroll
       for (int k = 0; k < KM; ++k) key[k] = ~0u;
+      // the point's own packed coordinates (the same item in every order)
+      const Pt pi = unpack_pt((uint32_t)(sorted[s_rank[0][t]] >> 32), bits);
       for (int d = 0; d < L; ++d) {
         const uint64_t *srt = sorted + (size_t)d * a.stride;
         const int r = s_rank[d][t];
@@ -206,8 +212,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
         if (__builtin_amdgcn_ballot_w64(r - WT < lo || r + WT > hi) == 0) {
           const uint64_t *wp = srt + (r - WT);
 #pragma unroll
-          for (int s = 0; s <= 2 * WT; ++s) cur[s] = wp[s];
-          const Pt pi = unpack_pt((uint32_t)(cur[WT] >> 32), bits);
+          for (int s = 0; s <= 2 * WT; ++s)
+            if (s != WT) cur[s] = wp[s];
 #pragma unroll
           for (int s = 0; s < 2 * WT; ++s) {
             const uint64_t it = cur[s < WT ? s : s + 1];
@@ -216,7 +222,6 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
           }
         } else {
           load_window<WT>(srt, r, lo, hi, cur);
-          const Pt pi = unpack_pt((uint32_t)(cur[WT] >> 32), bits);
 #pragma unroll
           for (int s = 0; s < 2 * WT; ++s) {
             const uint64_t it = cur[s < WT ? s : s + 1];
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
       cv[k] = ok ? (int32_t)(uint32_t)lst[k] : -1;
       dv[k] = ok ? (int32_t)d2 : 0;
       if (ok && k < K) {
-        acc[0] += sqrt((double)d2);
+        acc[0] += d2 <= kKeyD2Max ? s_sqrt[d2] : sqrt((double)d2);
         acc[1] += 1.0;
       }
     }
