@@ -334,10 +334,12 @@ fgbd_status run_slg(const Run &r, const int32_t *xyz, int32_t *col, int32_t *dis
   return FGBD_OK;
 }
 
+// fuse: the noise launch also computes the weights and the first sweep's
+// colours (the fused per-frame path, K = P = 8).
 fgbd_status run_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3,
-                      fgbd_result *res) {
+                      fgbd_result *res, bool fuse = false) {
   FGBD_PRE(r.pf, kNoise);
-  HIP_TRY(launch_noise(r, col, rgb, spread, eig3), "noise launch");
+  HIP_TRY(launch_noise(r, col, rgb, spread, eig3, fuse ? res : nullptr), "noise launch");
   FGBD_POST(r.pf);
   FGBD_PRE(r.pf, kNoiseSolve);
   HIP_TRY(launch_noise_solve(r, res), "noise solve launch");
@@ -351,13 +353,14 @@ fgbd_status run_noise(const Run &r, const int32_t *col, const float *rgb, double
 // weights into p, which the later sweeps read.
 fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const int32_t *dist2, const float *rgb_in,
                        const double *spread, const fgbd_result *noise, int select, int q_limit, float *rgb_out,
-                       fgbd_result *res) {
+                       fgbd_result *res, bool pre = false) {
   const int sweeps = q_limit > 0 ? q_limit : 1;
   // with fixed q every sweep computes: all of them are separate launches
   const int separate = (!select || sweeps < r.sweep_launches) ? sweeps : r.sweep_launches;
   for (int q = 1; q <= separate; ++q) {
     FGBD_PRE(r.pf, kSweep);
-    HIP_TRY(launch_sweep(r, col, p, q == 1 ? dist2 : nullptr, rgb_in, spread, noise, res, select, q_limit, q),
+    HIP_TRY(launch_sweep(r, col, p, q == 1 ? dist2 : nullptr, rgb_in, spread, noise, res, select, q_limit, q,
+                         pre && q == 1),
             "sweep launch");
     FGBD_POST(r.pf);
   }
@@ -611,6 +614,13 @@ static fgbd_status run_denoise(const Run &r, const int32_t *xyz, const float *rg
                                fgbd_result *res) {
   fgbd_status st;
   if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
+  if (r.prm.k == 8 && r.pl.P == 8) {
+    // the noise launch gathers each point's row and its neighbours' colours
+    // anyway: it also computes the weights and the first sweep's colours, and
+    // the first sweep launch only adds the FSLR flags and the sums
+    if ((st = run_noise(r, r.b.col, rgb_in, r.b.spread, nullptr, res, true)) != FGBD_OK) return st;
+    return run_filter(r, r.b.col, r.b.p, nullptr, rgb_in, r.b.spread, res, 1, r.prm.q_max, rgb_out, res, true);
+  }
   if ((st = run_noise(r, r.b.col, rgb_in, r.b.spread, nullptr, res)) != FGBD_OK) return st;
   return run_filter(r, r.b.col, r.b.p, r.b.dist2, rgb_in, r.b.spread, res, 1, r.prm.q_max, rgb_out, res);
 }

@@ -192,7 +192,7 @@ struct SweepLds {
 // edge-length sums and the squared distances (eq. 4, the graph builder's own
 // arithmetic) instead of a stored p; sigma_g goes to the results and the
 // weights into p_out for the later sweeps.
-template <int KT, bool FIRST, bool D2>
+template <int KT, bool FIRST, bool D2, bool PRE = false>
 __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &sb, const SweepIO &io,
                                            const int32_t *__restrict__ col, const float *__restrict__ p,
                                            const float *__restrict__ rgb_in, float4 *__restrict__ xbuf,
@@ -206,6 +206,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
   SweepCtrl *ctrl_out = io.ctrl_out;
   SweepCtrl c;
   static_assert(FIRST || !D2, "only the first sweep derives the weights");
+  static_assert(!PRE || (FIRST && !D2), "precomputed colours: first sweep, weights already stored");
   if (FIRST) {
     c.sigma_g = 0.0;
     if (D2) {
@@ -262,6 +263,18 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
       xg = xi.y;
       xb = xi.z;
       member = xi.w;
+    }
+    if (PRE) {  // x1 from the noise launch; the flag and the sums only
+      const float4 x1 = xout[i];
+      xout[i] = make_float4(x1.x, x1.y, x1.z, member);
+      const unsigned long long x2 = to_fix((double)x1.x * x1.x + (double)x1.y * x1.y + (double)x1.z * x1.z);
+      v[0] += member != 0.0f ? x2 : 0ull;
+      v[1] += x2;
+      const unsigned long long y2 = to_fix((double)xr * xr + (double)xg * xg + (double)xb * xb);
+      v[2] += member != 0.0f ? y2 : 0ull;
+      v[3] += y2;
+      v[4] += member != 0.0f ? 1ull : 0ull;
+      continue;
     }
     int cc[KT > 0 ? KT : kMaxK];
     float ww[KT > 0 ? KT : kMaxK];
@@ -353,14 +366,14 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
   add_sums(v, sums_out, sb.lb % kSweepSlots, lds.red);
 }
 
-template <int KT, bool FIRST, bool D2>
+template <int KT, bool FIRST, bool D2, bool PRE = false>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int q, const int32_t *__restrict__ col,
                                                   const float *__restrict__ p, const float *__restrict__ rgb_in,
                                                   float4 *__restrict__ xbuf, const double *__restrict__ spread,
                                                   const fgbd_result *__restrict__ noise) {
   __shared__ SweepLds<D2> lds;
   const SegBlock sb = seg_block(a.sa, kGridSweep);
-  sweep_step<KT, FIRST, D2>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
+  sweep_step<KT, FIRST, D2, PRE>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
 }
 
 // Waits until every block of the grid has arrived `epoch` times at this
@@ -506,10 +519,10 @@ SweepArgs sweep_args(const Run &r, const int32_t *dist2, float *p_out, fgbd_resu
   return a;
 }
 
-template <int KT, bool FIRST, bool D2>
+template <int KT, bool FIRST, bool D2, bool PRE = false>
 void sweep_kernel(int nb, hipStream_t st, const SweepArgs &a, int q, const int32_t *col, const float *p,
                   const float *rgb_in, float4 *xbuf, const double *spread, const fgbd_result *noise) {
-  k_sweep<KT, FIRST, D2><<<nb, kBlock, 0, st>>>(a, q, col, p, rgb_in, xbuf, spread, noise);
+  k_sweep<KT, FIRST, D2, PRE><<<nb, kBlock, 0, st>>>(a, q, col, p, rgb_in, xbuf, spread, noise);
 }
 
 // Per device: blocks of k_sweep_tail<KT> resident at once, and ticks of the
@@ -557,9 +570,16 @@ hipError_t tail_kernel(int nb, hipStream_t st, const SweepArgs &a, int q0, int q
 
 hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
                         const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
-                        int select, int q_limit, int q) {
+                        int select, int q_limit, int q, bool pre) {
   const bool first = q == 1, d2 = dist2 != nullptr;
   if (d2 && !first) return hipErrorInvalidValue;  // only the first sweep derives the weights
+  if (pre && (!first || d2 || r.prm.k != 8)) return hipErrorInvalidValue;
+  if (pre) {
+    const SweepArgs a = sweep_args(r, nullptr, nullptr, res, select, q_limit);
+    sweep_kernel<8, true, false, true>(r.pl.grid[kGridSweep], r.stream, a, q, col, p, rgb_in, r.b.xbuf, spread,
+                                       noise);
+    return hipGetLastError();
+  }
   // the first sweep of the fused path stores the weights it derives into p
   const SweepArgs a = sweep_args(r, dist2, d2 ? const_cast<float *>(p) : nullptr, res, select, q_limit);
   const int nb = r.pl.grid[kGridSweep];

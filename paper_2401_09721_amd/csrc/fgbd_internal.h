@@ -467,7 +467,11 @@ hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int3
 // res[s].sigma_g) and the row-normalised weights p.
 hipError_t launch_weights(const Run &r, const int32_t *col, const int32_t *dist2, fgbd_result *res, float *p);
 
-hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3);
+// fuse_res != NULL (K = P = 8, no eig3): the launch also derives sigma_g (into
+// fuse_res) and the weights p, and writes the first filter sweep's colours
+// into the first iterate buffer (see launch_sweep's pre).
+hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3,
+                        fgbd_result *fuse_res);
 
 // One block per cloud: sigma_est, n_eff, m and the NO_PATCH flag into res[s].
 hipError_t launch_noise_solve(const Run &r, fgbd_result *res);
@@ -476,10 +480,12 @@ hipError_t launch_noise_solve(const Run &r, fgbd_result *res);
 // ctrl[q&1][.] and sums[q%3], clears sums[(q+1)%3].  noise: per-cloud
 // results holding sigma_est (select == 1).  dist2 != NULL (first sweep only):
 // the weights come from the squared distances and res[s].sigma_g and are
-// stored into p (which is then an output).
+// stored into p (which is then an output).  pre (first sweep only, K = 8):
+// the noise launch already wrote the sweep's colours into the first iterate
+// buffer; this launch adds the FSLR flags and the sums.
 hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
                         const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
-                        int select, int q_limit, int q);
+                        int select, int q_limit, int q, bool pre = false);
 
 // Whether the sweep grid of r fits on the current device at once, as the
 // in-launch sweep loop below needs.

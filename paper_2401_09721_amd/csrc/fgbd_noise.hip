@@ -74,7 +74,62 @@ struct NoiseArgs {
   int32_t E2, E;       // D(D+1)/2 and E2 + 3D
   int32_t groups;      // row groups per entry
   int32_t want_eig3;
+  // the fused per-frame path (K = P = 8): the first filter sweep's colours
+  // x1 = T y with the eq. 4 weights, computed here from the same neighbour
+  // rows; the first sweep launch then only marks FSLR membership and sums
+  const int32_t *dist2;
+  const unsigned long long *edge_acc;
+  double sigma_g_fixed;
+  fgbd_result *res;  // receives sigma_g
+  float *p_out;      // the weights, for the later sweeps
+  float4 *x1;        // the first sweep's output buffer
 };
+
+// The fused first sweep for one point (K = 8): the row's weights from its
+// squared distances (row_weights, the graph builder's arithmetic) into p, and
+// x1 = y_i / 2 + sum_k p_ik y_jk / 2 with the first filter sweep's own
+// operation order; an empty row keeps y_i.  The fourth lane is left 0 for the
+// first sweep launch to fill with the FSLR flag.
+__device__ __forceinline__ void fused_first_sweep8(const NoiseArgs &a, int64_t i, const int32_t *__restrict__ col,
+                                                   const float *__restrict__ rgb, double sg, const double *s_exp) {
+  int cc[8], dv[8];
+  const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
+  const int4 *dr = reinterpret_cast<const int4 *>(a.dist2 + i * 8);
+  const int4 c0 = cr[0], c1 = cr[1], e0 = dr[0], e1 = dr[1];
+  cc[0] = c0.x; cc[1] = c0.y; cc[2] = c0.z; cc[3] = c0.w;
+  cc[4] = c1.x; cc[5] = c1.y; cc[6] = c1.z; cc[7] = c1.w;
+  dv[0] = e0.x; dv[1] = e0.y; dv[2] = e0.z; dv[3] = e0.w;
+  dv[4] = e1.x; dv[5] = e1.y; dv[6] = e1.z; dv[7] = e1.w;
+  float ww[8];
+  row_weights<8>(cc, dv, sg, s_exp, ww);
+  float4 *pr = reinterpret_cast<float4 *>(a.p_out + i * 8);
+  pr[0] = make_float4(ww[0], ww[1], ww[2], ww[3]);
+  pr[1] = make_float4(ww[4], ww[5], ww[6], ww[7]);
+  const float xr = rgb[3 * i + 0], xg = rgb[3 * i + 1], xb = rgb[3 * i + 2];
+  float gx[8], gy[8], gz[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int64_t cj = cc[k] >= 0 ? (int64_t)cc[k] : i;
+    gx[k] = rgb[3 * cj + 0];
+    gy[k] = rgb[3 * cj + 1];
+    gz[k] = rgb[3 * cj + 2];
+  }
+  float ar = 0.f, ag = 0.f, ab = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float w = cc[k] >= 0 ? ww[k] : 0.0f;
+    ar = fmaf(w, gx[k], ar);
+    ag = fmaf(w, gy[k], ag);
+    ab = fmaf(w, gz[k], ab);
+  }
+  float orr = xr, og = xg, ob = xb;
+  if (cc[0] >= 0) {
+    orr = 0.5f * xr + 0.5f * ar;
+    og = 0.5f * xg + 0.5f * ag;
+    ob = 0.5f * xb + 0.5f * ab;
+  }
+  a.x1[i] = make_float4(orr, og, ob, 0.0f);
+}
 
 // Adds entry e of a block's patch moments into its cloud's accumulators
 // (acc: the row of the block's slot in the cloud's [kNoiseSlots][E1] array).
@@ -561,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
 // on this GPU (measured).  Independent accumulators, operands read from LDS
 // without branches, and the partial sums added in a fixed order.  Products
 // of floats are exact in FP64; the accumulation order is fixed.
-template <int PT, bool EIG3>
+template <int PT, bool EIG3, bool FUSE>
 __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
                                                        const float *__restrict__ rgb, double *__restrict__ spread,
                                                        float *__restrict__ eig3,
@@ -586,6 +641,16 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
   double c1[4] = {0.0, 0.0, 0.0, 0.0}, c2[2] = {0.0, 0.0};
 
   const SegBlock sb = seg_block(a.sa, kGridNoise);
+  __shared__ double s_exp[FUSE ? kExpTable : 1];
+  __shared__ unsigned long long s_u[kEdgeVals];
+  double sg = 0.0;
+  if (FUSE) {
+    static_assert(!FUSE || PT == 8, "the fused first sweep is written for K = P = 8");
+    sg = cloud_sigma_g(a.edge_acc + (size_t)kEdgeSlots * kEdgeVals * sb.s, a.sigma_g_fixed, s_u);
+    if (sb.lb == 0 && t == 0) a.res[sb.s].sigma_g = sg;
+    fill_exp_table(sg, s_exp);
+    __syncthreads();
+  }
   const Share sh = seg_share(sb, TP);
   for (int64_t tbase = sh.first; tbase < sh.end; tbase += sh.step) {
     if (t < TP) {
@@ -593,6 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
       float *r[3] = {s_v + (size_t)(3 * t + 0) * W, s_v + (size_t)(3 * t + 1) * W, s_v + (size_t)(3 * t + 2) * W};
       bool complete = false;
       if (i < sh.end) complete = patch_point<PT, EIG3>(a, i, col, rgb, r[0], r[1], r[2], spread, eig3);
+      if (FUSE && i < sh.end) fused_first_sweep8(a, i, col, rgb, sg, s_exp);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         if (!complete) {
@@ -856,13 +922,30 @@ NoiseArgs make_args(const SegArgs &sa, int k, int P, bool want_eig3) {
   a.E = a.E2 + 3 * a.D;
   a.groups = a.E <= kBlock ? kBlock / a.E : 1;
   a.want_eig3 = want_eig3;
+  a.dist2 = nullptr;
+  a.edge_acc = nullptr;
+  a.sigma_g_fixed = 0.0;
+  a.res = nullptr;
+  a.p_out = nullptr;
+  a.x1 = nullptr;
   return a;
 }
 
 }  // namespace
 
-hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3) {
-  const NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, eig3 != nullptr);
+hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3,
+                        fgbd_result *fuse_res) {
+  NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, eig3 != nullptr);
+  const bool fuse = fuse_res != nullptr;
+  if (fuse) {
+    if (a.P != 8 || a.K != 8 || eig3 != nullptr) return hipErrorInvalidValue;
+    a.dist2 = r.b.dist2;
+    a.edge_acc = r.b.edge_acc;
+    a.sigma_g_fixed = r.prm.sigma_g;
+    a.res = fuse_res;
+    a.p_out = r.b.p;
+    a.x1 = r.b.xbuf;  // buffer 0: the first sweep's output
+  }
   // k_noise: rows of D floats; k_noise_mfma: rows of D + 3 floats, and at
   // least the 8 KB of its final sums
   const size_t lds_rows = (size_t)3 * a.TP * a.D * sizeof(float);
@@ -871,10 +954,12 @@ hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, doub
   const int nb = r.pl.grid[kGridNoise];
   unsigned long long *part = r.b.noise_acc;
   hipStream_t st = r.stream;
-  if (a.P == 8 && eig3 == nullptr)
-    k_noise_mfma<8, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
+  if (fuse)
+    k_noise_mfma<8, false, true><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
+  else if (a.P == 8 && eig3 == nullptr)
+    k_noise_mfma<8, false, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else if (a.P == 8)
-    k_noise_mfma<8, true><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
+    k_noise_mfma<8, true, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else if (eig3 == nullptr)
     k_noise<0, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else
