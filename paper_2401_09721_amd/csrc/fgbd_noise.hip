@@ -85,52 +85,6 @@ struct NoiseArgs {
   float4 *x1;        // the first sweep's output buffer
 };
 
-// The fused first sweep for one point (K = 8): the row's weights from its
-// squared distances (row_weights, the graph builder's arithmetic) into p, and
-// x1 = y_i / 2 + sum_k p_ik y_jk / 2 with the first filter sweep's own
-// operation order; an empty row keeps y_i.  The fourth lane is left 0 for the
-// first sweep launch to fill with the FSLR flag.
-__device__ __forceinline__ void fused_first_sweep8(const NoiseArgs &a, int64_t i, const int32_t *__restrict__ col,
-                                                   const float *__restrict__ rgb, double sg, const double *s_exp) {
-  int cc[8], dv[8];
-  const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
-  const int4 *dr = reinterpret_cast<const int4 *>(a.dist2 + i * 8);
-  const int4 c0 = cr[0], c1 = cr[1], e0 = dr[0], e1 = dr[1];
-  cc[0] = c0.x; cc[1] = c0.y; cc[2] = c0.z; cc[3] = c0.w;
-  cc[4] = c1.x; cc[5] = c1.y; cc[6] = c1.z; cc[7] = c1.w;
-  dv[0] = e0.x; dv[1] = e0.y; dv[2] = e0.z; dv[3] = e0.w;
-  dv[4] = e1.x; dv[5] = e1.y; dv[6] = e1.z; dv[7] = e1.w;
-  float ww[8];
-  row_weights<8>(cc, dv, sg, s_exp, ww);
-  float4 *pr = reinterpret_cast<float4 *>(a.p_out + i * 8);
-  pr[0] = make_float4(ww[0], ww[1], ww[2], ww[3]);
-  pr[1] = make_float4(ww[4], ww[5], ww[6], ww[7]);
-  const float xr = rgb[3 * i + 0], xg = rgb[3 * i + 1], xb = rgb[3 * i + 2];
-  float gx[8], gy[8], gz[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int64_t cj = cc[k] >= 0 ? (int64_t)cc[k] : i;
-    gx[k] = rgb[3 * cj + 0];
-    gy[k] = rgb[3 * cj + 1];
-    gz[k] = rgb[3 * cj + 2];
-  }
-  float ar = 0.f, ag = 0.f, ab = 0.f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const float w = cc[k] >= 0 ? ww[k] : 0.0f;
-    ar = fmaf(w, gx[k], ar);
-    ag = fmaf(w, gy[k], ag);
-    ab = fmaf(w, gz[k], ab);
-  }
-  float orr = xr, og = xg, ob = xb;
-  if (cc[0] >= 0) {
-    orr = 0.5f * xr + 0.5f * ar;
-    og = 0.5f * xg + 0.5f * ag;
-    ob = 0.5f * xb + 0.5f * ab;
-  }
-  a.x1[i] = make_float4(orr, og, ob, 0.0f);
-}
-
 // Adds entry e of a block's patch moments into its cloud's accumulators
 // (acc: the row of the block's slot in the cloud's [kNoiseSlots][E1] array).
 __device__ __forceinline__ void add_moment(unsigned long long *acc, int e, double v) {
@@ -365,6 +319,53 @@ __device__ double tridiag_eig_groups(const double (&d)[DT], const double (&e)[DT
   return 0.5 * (lo + hi);
 }
 
+// The FSLR spread (and optionally the 3x3 eigenvalues) of one complete patch
+// held in registers (channel c, entry k: the point, then its PT neighbours),
+// in FP64, after writing the patch's three rows to LDS.
+template <int PT, bool EIG3>
+__device__ __forceinline__ void patch_stats(int64_t i, const float (&v)[3][PT + 1], float *r0, float *r1, float *r2,
+                                            double *__restrict__ spread, float *__restrict__ eig3) {
+  double mean[3], cov[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k <= PT; ++k) {
+    r0[k] = v[0][k];
+    r1[k] = v[1][k];
+    r2[k] = v[2][k];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k <= PT; ++k) s += (double)v[c][k];
+    mean[c] = s / (double)(PT + 1);
+  }
+#pragma unroll
+  for (int k = 0; k <= PT; ++k) {
+    const double d0 = (double)v[0][k] - mean[0];
+    const double d1 = (double)v[1][k] - mean[1];
+    const double d2 = (double)v[2][k] - mean[2];
+    cov[0] += d0 * d0;
+    cov[3] += d1 * d1;
+    cov[5] += d2 * d2;
+    if (EIG3) {
+      cov[1] += d0 * d1;
+      cov[2] += d0 * d2;
+      cov[4] += d1 * d2;
+    }
+  }
+  const double invD = 1.0 / (double)(PT + 1);
+#pragma unroll
+  for (int m = 0; m < 6; ++m) cov[m] *= invD;
+  spread[i] = (sqrt(cov[0]) + sqrt(cov[3]) + sqrt(cov[5])) / 3.0;
+  if (EIG3) {
+    double ev[3];
+    eig3_sym(cov[0], cov[1], cov[2], cov[3], cov[4], cov[5], ev);
+    eig3[3 * i + 0] = (float)ev[0];
+    eig3[3 * i + 1] = (float)ev[1];
+    eig3[3 * i + 2] = (float)ev[2];
+  }
+}
+
 // Per-point work of one tile slot: gather the patch into three LDS rows,
 // compute the FSLR spread (and optionally the 3x3 eigenvalues) in FP64.
 // PT > 0: the patch size is a compile-time constant (values in registers,
@@ -375,7 +376,6 @@ __device__ __forceinline__ bool patch_point(const NoiseArgs &a, int64_t i, const
                                             double *__restrict__ spread, float *__restrict__ eig3) {
   const int D = a.D, P = a.P, K = a.K;
   if (col[i * K + (P - 1)] < 0) return false;
-  double mean[3], cov[6] = {0, 0, 0, 0, 0, 0};
   if constexpr (PT > 0) {
     int cj[PT];
     if (PT % 4 == 0 && (K % 4) == 0) {
@@ -402,34 +402,10 @@ __device__ __forceinline__ bool patch_point(const NoiseArgs &a, int64_t i, const
       v[1][1 + k] = rgb[3 * j + 1];
       v[2][1 + k] = rgb[3 * j + 2];
     }
-#pragma unroll
-    for (int k = 0; k <= PT; ++k) {
-      r0[k] = v[0][k];
-      r1[k] = v[1][k];
-      r2[k] = v[2][k];
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k <= PT; ++k) s += (double)v[c][k];
-      mean[c] = s / (double)(PT + 1);
-    }
-#pragma unroll
-    for (int k = 0; k <= PT; ++k) {
-      const double d0 = (double)v[0][k] - mean[0];
-      const double d1 = (double)v[1][k] - mean[1];
-      const double d2 = (double)v[2][k] - mean[2];
-      cov[0] += d0 * d0;
-      cov[3] += d1 * d1;
-      cov[5] += d2 * d2;
-      if (EIG3) {
-        cov[1] += d0 * d1;
-        cov[2] += d0 * d2;
-        cov[4] += d1 * d2;
-      }
-    }
+    patch_stats<PT, EIG3>(i, v, r0, r1, r2, spread, eig3);
+    return true;
   } else {
+    double mean[3], cov[6] = {0, 0, 0, 0, 0, 0};
     r0[0] = rgb[3 * i + 0];
     r1[0] = rgb[3 * i + 1];
     r2[0] = rgb[3 * i + 2];
@@ -459,18 +435,74 @@ __device__ __forceinline__ bool patch_point(const NoiseArgs &a, int64_t i, const
         cov[4] += d1 * d2;
       }
     }
-  }
-  const double invD = 1.0 / (double)D;
+    const double invD = 1.0 / (double)D;
 #pragma unroll
-  for (int m = 0; m < 6; ++m) cov[m] *= invD;
-  spread[i] = (sqrt(cov[0]) + sqrt(cov[3]) + sqrt(cov[5])) / 3.0;
-  if (EIG3) {
-    double ev[3];
-    eig3_sym(cov[0], cov[1], cov[2], cov[3], cov[4], cov[5], ev);
-    eig3[3 * i + 0] = (float)ev[0];
-    eig3[3 * i + 1] = (float)ev[1];
-    eig3[3 * i + 2] = (float)ev[2];
+    for (int m = 0; m < 6; ++m) cov[m] *= invD;
+    spread[i] = (sqrt(cov[0]) + sqrt(cov[3]) + sqrt(cov[5])) / 3.0;
+    if (EIG3) {
+      double ev[3];
+      eig3_sym(cov[0], cov[1], cov[2], cov[3], cov[4], cov[5], ev);
+      eig3[3 * i + 0] = (float)ev[0];
+      eig3[3 * i + 1] = (float)ev[1];
+      eig3[3 * i + 2] = (float)ev[2];
+    }
+    return true;
   }
+}
+
+// The fused per-frame path (K = P = 8), one point: the row's neighbour
+// colours are gathered once and serve both the patch (as in patch_point) and
+// the first filter sweep: the row's weights from its squared distances
+// (row_weights, the graph builder's arithmetic) into p, and x1 = y_i / 2 +
+// sum_k p_ik y_jk / 2 with the first filter sweep's own operation order (an
+// empty row keeps y_i) into the first iterate buffer, whose fourth lane the
+// first sweep launch fills with the FSLR flag.  Returns whether the patch
+// is complete.
+__device__ __forceinline__ bool fused_point8(const NoiseArgs &a, int64_t i, const int32_t *__restrict__ col,
+                                             const float *__restrict__ rgb, float *r0, float *r1, float *r2,
+                                             double *__restrict__ spread, double sg, const double *s_exp) {
+  int cc[8], dv[8];
+  const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
+  const int4 *dr = reinterpret_cast<const int4 *>(a.dist2 + i * 8);
+  const int4 c0 = cr[0], c1 = cr[1], e0 = dr[0], e1 = dr[1];
+  cc[0] = c0.x; cc[1] = c0.y; cc[2] = c0.z; cc[3] = c0.w;
+  cc[4] = c1.x; cc[5] = c1.y; cc[6] = c1.z; cc[7] = c1.w;
+  dv[0] = e0.x; dv[1] = e0.y; dv[2] = e0.z; dv[3] = e0.w;
+  dv[4] = e1.x; dv[5] = e1.y; dv[6] = e1.z; dv[7] = e1.w;
+  float v[3][9];
+  v[0][0] = rgb[3 * i + 0];
+  v[1][0] = rgb[3 * i + 1];
+  v[2][0] = rgb[3 * i + 2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // an empty slot reads the point itself (weight 0)
+    const int64_t cj = cc[k] >= 0 ? (int64_t)cc[k] : i;
+    v[0][1 + k] = rgb[3 * cj + 0];
+    v[1][1 + k] = rgb[3 * cj + 1];
+    v[2][1 + k] = rgb[3 * cj + 2];
+  }
+  float ww[8];
+  row_weights<8>(cc, dv, sg, s_exp, ww);
+  float4 *pr = reinterpret_cast<float4 *>(a.p_out + i * 8);
+  pr[0] = make_float4(ww[0], ww[1], ww[2], ww[3]);
+  pr[1] = make_float4(ww[4], ww[5], ww[6], ww[7]);
+  float ar = 0.f, ag = 0.f, ab = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float w = cc[k] >= 0 ? ww[k] : 0.0f;
+    ar = fmaf(w, v[0][1 + k], ar);
+    ag = fmaf(w, v[1][1 + k], ag);
+    ab = fmaf(w, v[2][1 + k], ab);
+  }
+  const float xr = v[0][0], xg = v[1][0], xb = v[2][0];
+  float orr = xr, og = xg, ob = xb;
+  if (cc[0] >= 0) {
+    orr = 0.5f * xr + 0.5f * ar;
+    og = 0.5f * xg + 0.5f * ag;
+    ob = 0.5f * xb + 0.5f * ab;
+  }
+  a.x1[i] = make_float4(orr, og, ob, 0.0f);
+  if (cc[7] < 0) return false;  // fewer than P neighbours: no patch
+  patch_stats<8, false>(i, v, r0, r1, r2, spread, nullptr);
   return true;
 }
 
@@ -617,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
 // without branches, and the partial sums added in a fixed order.  Products
 // of floats are exact in FP64; the accumulation order is fixed.
 template <int PT, bool EIG3, bool FUSE>
-__global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
+__global__ __launch_bounds__(kBlock, 4) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
                                                        const float *__restrict__ rgb, double *__restrict__ spread,
                                                        float *__restrict__ eig3,
                                                        unsigned long long *__restrict__ acc_all) {
@@ -657,8 +689,9 @@ __global__ __launch_bounds__(kBlock) void k_noise_mfma(NoiseArgs a, const int32_
       const int64_t i = tbase + t;
       float *r[3] = {s_v + (size_t)(3 * t + 0) * W, s_v + (size_t)(3 * t + 1) * W, s_v + (size_t)(3 * t + 2) * W};
       bool complete = false;
-      if (i < sh.end) complete = patch_point<PT, EIG3>(a, i, col, rgb, r[0], r[1], r[2], spread, eig3);
-      if (FUSE && i < sh.end) fused_first_sweep8(a, i, col, rgb, sg, s_exp);
+      if (i < sh.end)
+        complete = FUSE ? fused_point8(a, i, col, rgb, r[0], r[1], r[2], spread, sg, s_exp)
+                        : patch_point<PT, EIG3>(a, i, col, rgb, r[0], r[1], r[2], spread, eig3);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         if (!complete) {
