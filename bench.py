@@ -39,12 +39,12 @@ def algorithmic_bytes(kind: str, n: int, L: int, K: int, P: int) -> float:
         return (12 + 4 * L + 8 * L + 8 * K) * n
     if kind == "weights":   # col + dist2 in, p out
         return 12 * K * n
-    if kind == "noise":     # col (P), own colour, spread out
-        return (4 * K + 12 + 8) * n
+    if kind == "noise":     # fused per-frame path (K = P): col + dist2 in, own colour, spread, p and float4 x1 out
+        return (4 * K + 12 + 8 + 4 * K + 4 * K + 16) * n
     if kind == "sweep":     # col + p, float4 x in and out
         return (8 * K + 16 + 16) * n
-    if kind == "sweep_first_fused":  # col + dist2 in, p out; y (12 B) and spread in, float4 x out
-        return (12 * K + 12 + 8 + 16) * n
+    if kind == "sweep_first_fused":  # float4 x1 in and out (FSLR flag added), y (12 B) and spread in
+        return (16 + 16 + 12 + 8) * n
     if kind == "finalize":  # float4 in, float32 x3 out (plus the last sweep partials)
         return (16 + 12) * n
     return 0.0
