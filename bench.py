@@ -262,7 +262,7 @@ def bench_fwd_bwd(clouds, dev, args, fgbd, torch) -> dict:
         opt.zero_grad(set_to_none=True)
         loss.backward()
         opt.step()
-        return loss
+        return loss.detach()
 
     mse_noisy = float(torch.mean((x - clean) ** 2))
     mse0 = float(step())  # also the warm-up
