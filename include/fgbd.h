@@ -212,6 +212,21 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
                                  const int64_t *offsets, int32_t batch, const fgbd_params *params, float *rgb_out,
                                  fgbd_result *res, void *stream);
 
+/* The periodic mode of the per-frame path (Sec. 4: noise estimation and
+ * filter selection run once every few frames, the frames in between reuse
+ * the last selected q): fgbd_denoise_batched without the noise estimate and
+ * the selection, filtering every cloud with q_fixed sweeps of eq. 5 on its
+ * own graph (its own sigma_g and weights).  Same arguments and layout as
+ * fgbd_denoise_batched, plus
+ *   q_fixed: 0..1024 (the caller passes the q of the last full frame; 0
+ *     returns the input colours);
+ *   res: sigma_g, q = sweeps = q_fixed written; sigma_est, n_eff, m, n_fslr
+ *     and loss are 0.
+ * Errors as fgbd_denoise_batched, and FGBD_E_INVALID for q_fixed out of range. */
+fgbd_status fgbd_denoise_batched_fixed_q(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                                         const int64_t *offsets, int32_t batch, const fgbd_params *params,
+                                         int32_t q_fixed, float *rgb_out, fgbd_result *res, void *stream);
+
 /* Launch schedule of the per-cloud kernels: the largest grid, in blocks of
  * 256 threads, of (merge_blocks) the neighbour merge and edge weights,
  * (noise_blocks) the patch statistics and (sweep_blocks) the filter sweeps

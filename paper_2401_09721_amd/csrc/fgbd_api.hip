@@ -693,6 +693,28 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
   return ok();
 }
 
+fgbd_status fgbd_denoise_batched_fixed_q(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, int64_t n_total,
+                                         const int64_t *offsets, int32_t batch, const fgbd_params *params,
+                                         int32_t q_fixed, float *rgb_out, fgbd_result *res, void *stream) {
+  fgbd_status st = check_batched(ctx, xyz, rgb_in, n_total, offsets, batch, params, rgb_out, res);
+  if (st != FGBD_OK) return st;
+  if (q_fixed < 0 || q_fixed > 1024) return fail(FGBD_E_INVALID, "q_fixed must be in 0..1024 (got %d)", q_fixed);
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  const Plan pl = make_plan(n_total, batch, *params, ctx->tune);
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  EventProf ep(ctx, s);
+  Run r = make_run(ctx, pl, ws, *params, -1, s, &ep);
+  HIP_TRY(launch_setup(r, offsets, 0, res, n_total == 0 ? 2 : 1), "setup launch");
+  if (n_total == 0) return ok();
+  // SLG, then q_fixed sweeps whose first derives sigma_g and the weights;
+  // no noise estimate and no selection (every sweep is a launch of its own)
+  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
+  return run_filter(r, r.b.col, r.b.p, r.b.dist2, rgb_in, nullptr, nullptr, 0, q_fixed, rgb_out, res);
+}
+
 static fgbd_status check_schedule(const fgbd_schedule *s) {
   if (!s) return fail(FGBD_E_INVALID, "schedule is NULL");
   if (s->merge_blocks < kGridCapMin || s->merge_blocks > kGridCapMax || s->sweep_blocks < kGridCapMin ||

@@ -104,6 +104,10 @@ _SIGNATURES = {
     "fgbd_denoise_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_denoise_batched_fixed_q": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                                    ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_void_p,
+                                                    ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_get_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Schedule)]),
     "fgbd_set_schedule": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Schedule)]),
     "fgbd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -428,6 +432,27 @@ def denoise_batched(xyz, rgb, offsets, params=None, ctx: Optional[Context] = Non
         raise ValueError("res holds fewer than batch results")
     _check(lib().fgbd_denoise_batched(ctx.handle, _ptr(xyz), _ptr(rgb), n, _ptr(offsets), batch,
                                       ctypes.byref(prm), _ptr(out), _ptr(res), _stream(ctx, stream)))
+    return out, res
+
+
+def denoise_batched_fixed_q(xyz, rgb, offsets, q: int, params=None, ctx: Optional[Context] = None, out=None,
+                            res=None, stream=None):
+    """The periodic mode's in-between frames: like denoise_batched, but no
+    noise estimate and no selection; every cloud is filtered with q sweeps on
+    its own graph (q: the last full frame's selected q).  Returns (rgb_out,
+    results)."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(xyz.device)
+    xyz, rgb, offsets, batch, n = _batched_args(ctx, xyz, rgb, offsets)
+    ctx.reserve(prm, n, max(batch, 1))
+    out = torch.empty_like(rgb) if out is None else out
+    res = new_result(ctx.device, max(batch, 1)) if res is None else res
+    if res.numel() < RESULT_BYTES * max(batch, 1):
+        raise ValueError("res holds fewer than batch results")
+    _check(lib().fgbd_denoise_batched_fixed_q(ctx.handle, _ptr(xyz), _ptr(rgb), n, _ptr(offsets), batch,
+                                              ctypes.byref(prm), int(q), _ptr(out), _ptr(res),
+                                              _stream(ctx, stream)))
     return out, res
 
 

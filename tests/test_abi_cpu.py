@@ -168,6 +168,29 @@ def test_batched_call_errors(ctx):
     assert lib.fgbd_denoise_batched(ctx, *a) == E
 
 
+def test_fixed_q_batched_call_errors(ctx):
+    """The periodic mode's entry checks its arguments like the batched call,
+    and q_fixed against 0..1024, before touching the device."""
+    lib = fgbd.lib()
+    p = fgbd.default_params()
+    far = ctypes.c_void_p(0x900000)
+    E = fgbd.FGBD_E_INVALID
+    ok_args = (FAKE, FAKE, 10, FAKE, 2, ctypes.byref(p), 3, far, FAKE, None)
+    for q in (-1, 1025):
+        a = list(ok_args)
+        a[6] = q
+        assert lib.fgbd_denoise_batched_fixed_q(ctx, *a) == E
+        assert "q_fixed" in lib.fgbd_last_error().decode()
+    for idx in (0, 1, 3, 7, 8):  # xyz, rgb_in, offsets, rgb_out, res
+        a = list(ok_args)
+        a[idx] = ctypes.c_void_p(0)
+        assert lib.fgbd_denoise_batched_fixed_q(ctx, *a) == E, idx
+    a = list(ok_args)
+    a[4] = 0
+    assert lib.fgbd_denoise_batched_fixed_q(ctx, *a) == E
+    assert lib.fgbd_denoise_batched_fixed_q(None, *ok_args) == E
+
+
 def test_schedule_get_set(ctx):
     lib = fgbd.lib()
     sc = fgbd.Schedule()
