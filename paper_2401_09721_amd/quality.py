@@ -1,0 +1,185 @@
+"""Quality and ablation measurements of the GPU path on synthetic clean/noisy pairs.
+
+The synthetic counterparts of the paper's evaluation (Sec. 3):
+
+* E_ne = |sigma_est - sigma_act|, the noise-estimate error of Table 4, with
+  sigma_act the standard deviation the generator drew the noise with;
+* PSNR of the noisy and the denoised colours against the clean ones (Table 2).
+  The paper does not spell its PSNR out; here it is 10 log10(255^2 / MSE) over
+  all R, G and B samples of the frame;
+* FGBD with and without FSLR (Table 5): ``fslr_kappa = 0`` makes every point
+  take part in the selection of eq. 6.  FSLR only matters where colour edges
+  raise the patch spread, so the harness runs the benchmark frame's smooth
+  texture and the same frame with per-cell colour edges added;
+* the PSNR of the best fixed number of sweeps, found by trying every q up to
+  q_max against the clean colours: a bound that no selection rule without the
+  clean colours can beat;
+* SLG quality and time against an exact K-nearest-neighbour search on the CPU
+  (Table 3): recall@K on a sample of points, and the time of building the graph
+  on the GPU next to building and querying a k-d tree on the host cores.
+
+Recall counts ties correctly: a neighbour the graph returns is a hit when its
+squared distance is at most the K-th smallest squared distance to any other
+point, so that any of several equally near K-sets scores 1.
+
+Everything here calls the library through the binding; the exact KNN is scipy's
+k-d tree.  Run ``python -m paper_2401_09721_amd.quality`` on a machine with the
+GPU to print one JSON line per noise level and one for the graph.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def psnr(x, ref, peak: float = 255.0) -> float:
+    """10 log10(peak^2 / MSE) over every sample of ``x`` against ``ref`` (FP64)."""
+    d = np.asarray(x, np.float64) - np.asarray(ref, np.float64)
+    mse = float(np.mean(d * d))
+    return float("inf") if mse == 0.0 else 10.0 * np.log10(peak * peak / mse)
+
+
+def exact_kth_dist2(xyz, rows, k: int, workers: int = 1) -> np.ndarray:
+    """Squared distance from each point in ``rows`` to its k-th nearest other
+    point (exact, integer coordinates, k-d tree)."""
+    from scipy.spatial import cKDTree
+
+    pts = np.asarray(xyz, np.float64)
+    tree = cKDTree(pts)
+    d, _ = tree.query(pts[rows], k=k + 1, workers=workers)  # the point itself comes first
+    return np.rint(d[:, k] ** 2).astype(np.int64)
+
+
+def knn_recall(xyz, col, rows, k: int, kth_dist2=None) -> float:
+    """Tie-aware recall@k of the neighbour rows ``col[rows]`` (-1 = empty slot)."""
+    xyz = np.asarray(xyz, np.int64)
+    rows = np.asarray(rows)
+    c = np.asarray(col)[rows][:, :k].astype(np.int64)
+    if kth_dist2 is None:
+        kth_dist2 = exact_kth_dist2(xyz, rows, k)
+    valid = (c >= 0) & (c != rows[:, None])
+    diff = xyz[np.where(valid, c, 0)] - xyz[rows][:, None, :]
+    d2 = np.sum(diff * diff, axis=-1)
+    hits = valid & (d2 <= np.asarray(kth_dist2)[:, None])
+    return float(hits.sum()) / (k * len(rows))
+
+
+def _time_gpu(fn, torch, stream, reps: int) -> float:
+    """Milliseconds per call of ``fn`` (HIP events on ``stream``)."""
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def denoise_quality(cloud, params=None, ctx=None, reps: int = 5, scan_q: bool = True) -> dict:
+    """FGBD with and without FSLR on one frame, against its clean colours."""
+    import torch
+
+    from . import fgbd
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    prm = fgbd.as_params(params)
+    ctx = ctx or fgbd.Context(dev)
+    stream = torch.cuda.current_stream(dev)
+    xyz = torch.as_tensor(cloud.xyz, device=dev)
+    rgb = torch.as_tensor(cloud.noisy, device=dev)
+    out = torch.empty_like(rgb)
+    res = fgbd.new_result(dev)
+
+    row = {"sigma_act": cloud.sigma, "n_points": int(cloud.n), "psnr_noisy": psnr(cloud.noisy, cloud.clean)}
+    for tag, kappa in (("fgbd", prm.fslr_kappa), ("no_fslr", 0.0)):
+        p = fgbd.default_params(**{**prm.as_dict(), "fslr_kappa": kappa})
+        ms = _time_gpu(lambda: fgbd.denoise(xyz, rgb, p, ctx=ctx, out=out, res=res), torch, stream, reps)
+        r = fgbd.read_result(res)
+        row[tag] = {"psnr": psnr(out.cpu().numpy(), cloud.clean), "q": r["q"], "n_fslr": r["n_fslr"],
+                    "sigma_est": r["sigma_est"], "ms": ms}
+    row["e_ne"] = abs(row["fgbd"]["sigma_est"] - cloud.sigma)
+    row["gain_db"] = row["fgbd"]["psnr"] - row["psnr_noisy"]
+    if scan_q:
+        g = fgbd.build_slg(xyz, prm, ctx=ctx)
+        curve = []
+        for q in range(0, prm.q_max + 1):
+            o, _ = fgbd.filter(g, rgb, prm, q_fixed=q, ctx=ctx) if q > 0 else (rgb, None)
+            curve.append(psnr(o.cpu().numpy(), cloud.clean))
+        best = int(np.argmax(curve))
+        row["best_fixed_q"] = {"q": best, "psnr": curve[best]}
+        row["psnr_by_q"] = [round(v, 3) for v in curve]
+    return row
+
+
+def graph_quality(cloud, params=None, ctx=None, sample: int = 20000, reps: int = 10, seed: int = 0,
+                  cpu_workers: int = 16) -> dict:
+    """SLG recall@K on a sample of points, SLG time on the GPU and exact
+    k-d tree KNN time on the host."""
+    import torch
+
+    from . import fgbd
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    prm = fgbd.as_params(params)
+    ctx = ctx or fgbd.Context(dev)
+    stream = torch.cuda.current_stream(dev)
+    xyz = torch.as_tensor(cloud.xyz, device=dev)
+    ms = _time_gpu(lambda: fgbd.build_slg(xyz, prm, ctx=ctx), torch, stream, reps)
+    g = fgbd.build_slg(xyz, prm, ctx=ctx)
+    col = g.col.cpu().numpy()
+    rows = np.random.default_rng(seed).choice(cloud.n, size=min(sample, cloud.n), replace=False)
+    workers = max(1, min(cpu_workers, os.cpu_count() or 1))
+    kth = exact_kth_dist2(cloud.xyz, rows, prm.k, workers=workers)
+
+    from scipy.spatial import cKDTree
+
+    t0 = time.perf_counter()
+    pts = np.asarray(cloud.xyz, np.float64)
+    cKDTree(pts).query(pts, k=prm.k + 1, workers=workers)
+    cpu_s = time.perf_counter() - t0
+    return {"n_points": int(cloud.n), "k": prm.k, "num_dirs": prm.num_dirs, "window": prm.window,
+            "recall_at_k": knn_recall(cloud.xyz, col, rows, prm.k, kth), "sample": int(len(rows)),
+            "slg_ms": ms, "kdtree_cpu_ms": 1e3 * cpu_s, "kdtree_cpu_threads": workers}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--points", type=int, default=1_000_000)
+    ap.add_argument("--sigmas", type=float, nargs="+", default=[10.0, 20.0, 30.0])
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--textures", nargs="+", default=["smooth", "patched"], choices=["smooth", "patched"],
+                    help="smooth: the benchmark frame's colours; patched: the same plus colour edges")
+    ap.add_argument("--cell", type=int, default=32, help="patched texture: cell size in voxels")
+    ap.add_argument("--amp", type=float, default=48.0, help="patched texture: largest offset per channel")
+    ap.add_argument("--no-scan-q", action="store_true", help="skip the sweep over fixed q")
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from . import fgbd, synth
+
+    torch.cuda.set_device(0)
+    ctx = fgbd.Context(torch.device("cuda", 0))
+    make = {"smooth": synth.body_cloud,
+            "patched": lambda **kw: synth.patched_body_cloud(cell=args.cell, amp=args.amp, **kw)}
+    for tex in args.textures:
+        for s in args.sigmas:
+            cloud = make[tex](seed=args.seed, target=args.points, sigma=s)
+            row = {"texture": tex, **denoise_quality(cloud, ctx=ctx, scan_q=not args.no_scan_q)}
+            print(json.dumps({"denoise": row}), flush=True)
+    cloud = synth.body_cloud(seed=args.seed, target=args.points, sigma=args.sigmas[0])
+    for L in (4, 8):
+        print(json.dumps({"graph": graph_quality(cloud, fgbd.default_params(num_dirs=L), ctx=ctx)}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

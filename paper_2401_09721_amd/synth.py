@@ -14,6 +14,8 @@ input is generated from a seed with the same structure:
 * colour: per channel, 128 plus a sum of four random low-frequency 3-D
   sinusoids (frequencies in cycles per 256 voxels, so the texture scale is the
   same on 2^8 and 2^10 grids), rounded and clipped to 0..255;
+* patterned colour (quality measurements only): the smooth colour plus a
+  constant random offset per cubic cell, which adds sharp colour edges;
 * noise: i.i.d. Gaussian of a given sigma added to the clean colour and clipped
   to 0..255, kept in float32 without rounding.
 
@@ -248,6 +250,25 @@ def body_cloud(seed: int = 1000, bits: int = 10, target: int | None = 1_000_000,
     shapes = _body_shapes(rng)
     xyz, _ = _fit_scale(shapes, bits, target)
     return _finish(xyz, bits, sigma, seed, rng, shuffle)
+
+
+def patched_body_cloud(seed: int = 1000, bits: int = 10, target: int | None = 1_000_000, sigma: float = 20.0,
+                       cell: int = 32, amp: float = 48.0) -> Cloud:
+    """body_cloud's geometry and smooth colour plus a constant offset per cubic
+    cell of ``cell`` voxels (U[-amp, amp] per cell and channel), rounded and
+    clipped to 0..255.  The offsets put sharp colour edges on the cell faces,
+    like printed patterns on clothing, which the smooth texture alone lacks."""
+    rng = np.random.default_rng(seed)
+    shapes = _body_shapes(rng)
+    xyz, _ = _fit_scale(shapes, bits, target)
+    xyz = np.ascontiguousarray(xyz, np.int32)
+    clean = procedural_colour(xyz, rng).astype(np.float64)
+    g = -(-(1 << bits) // cell)
+    c = xyz.astype(np.int64) // cell
+    offs = rng.uniform(-amp, amp, size=(g * g * g, 3))
+    clean = np.clip(np.rint(clean + offs[(c[:, 0] * g + c[:, 1]) * g + c[:, 2]]), 0, 255).astype(np.uint8)
+    noisy = add_noise(clean, sigma, rng)
+    return Cloud(xyz, clean, noisy, float(sigma), bits, seed)
 
 
 def moved_body_frame(seed: int, frame: int, bits: int = 10, target: int = 1_000_000,
