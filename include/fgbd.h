@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 3
+#define FGBD_ABI_VERSION 4
 
 /* Largest number of clouds in one fgbd_denoise_batched call. */
 #define FGBD_MAX_BATCH 64
@@ -84,6 +84,11 @@ typedef struct {
   double fslr_kappa;  /* FSLR excludes points whose patch spread exceeds kappa * sigma_est
                          (kappa = 2 in Sec. 2.4); <= 0 disables FSLR (all points used)            */
   double sigma_g;     /* Gaussian bandwidth of eq. 4; <= 0 means the mean edge length (Sec. 2.2) */
+  int32_t patch_order; /* order of the D entries of a patch vector (Sec. 2.3): 0 = the point, then
+                         its neighbours by increasing distance (the method); 1 = the same points
+                         by increasing point index, the unsorted patch of the "NE-GBP w/o sort"
+                         ablation (Sec. 3, noise estimation).  1 runs a slower generic kernel.   */
+  int32_t pad_;       /* set to 0 */
 } fgbd_params;
 
 /* A fixed-K neighbour graph in device memory (CSR with K slots per row).
@@ -119,7 +124,7 @@ typedef struct fgbd_ctx_s *fgbd_ctx;
 int32_t fgbd_abi_version(void);
 
 /* Fill *p with the defaults: bits 10, num_dirs 8, window 4, k 8, patch 0 (= k),
- * q_max 32, fslr_kappa 2.0, sigma_g 0 (mean edge length).  p: host. */
+ * q_max 32, fslr_kappa 2.0, sigma_g 0 (mean edge length), patch_order 0.  p: host. */
 fgbd_status fgbd_default_params(fgbd_params *p);
 
 /* Create a context bound to HIP device `hip_device`.  No device memory is

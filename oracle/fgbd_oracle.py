@@ -3,7 +3,7 @@
 Watanabe et al., "Fast graph-based denoising for point cloud color information"
 (arXiv:2401.09721).  Each function states the passage it follows.  Integer steps
 are exact int64; floating point is float64 throughout.  Where the paper is
-silent or ambiguous the reading taken is stated in the docstring (readings R1..R12
+silent or ambiguous the reading taken is stated in the docstring (readings R1..R13
 below; the same list is kept with the design notes).
 
 Readings
@@ -34,6 +34,10 @@ Readings
       empty subset, or kappa <= 0, means all points.
   R11 the output is not clipped or rounded.
   R12 several results can be correct only at floating-point near-ties of q or m.
+  R13 the "w/o sort" patch of the noise-estimation ablation (Sec. 3) holds the
+      same D points as the sorted one (the point and its first P neighbours), in
+      increasing point index: the order the points have in the input, which is
+      what an unsorted patch keeps.
 """
 from __future__ import annotations
 
@@ -80,8 +84,9 @@ DIRECTIONS = (
 def default_params(**kw) -> dict:
     """Parameters of one run: bits b, directions L, window w, neighbours K,
     patch size P (0 means K), q_max, FSLR factor kappa (2 in Sec. 2.4), and a
-    fixed sigma_g (<= 0: mean edge length, Sec. 2.2)."""
-    p = dict(bits=10, num_dirs=8, window=4, k=8, patch=0, q_max=32, fslr_kappa=2.0, sigma_g=0.0)
+    fixed sigma_g (<= 0: mean edge length, Sec. 2.2), and the patch order
+    (0: by distance, Sec. 2.3; 1: by point index, R13)."""
+    p = dict(bits=10, num_dirs=8, window=4, k=8, patch=0, q_max=32, fslr_kappa=2.0, sigma_g=0.0, patch_order=0)
     p.update(kw)
     return p
 
@@ -256,11 +261,12 @@ def _patch_size(col, patch: int) -> int:
     return k if patch <= 0 else patch
 
 
-def patch_matrix(col, y, patch: int = 0):
+def patch_matrix(col, y, patch: int = 0, order: int = 0):
     """Graph-based patches (Sec. 2.3, R4, R10): for every point whose row has at
     least P neighbours, the patch of each channel is its own value followed by
     the values of its first P neighbours in CSR order (increasing distance,
-    index tie-break).  Returns (complete mask [N], A [N_eff, D, 3])."""
+    index tie-break).  ``order = 1`` lists the same D points by increasing
+    point index instead (R13).  Returns (complete mask [N], A [N_eff, D, 3])."""
     col = np.asarray(col)
     P = _patch_size(col, patch)
     y = np.asarray(y, np.float64)
@@ -268,15 +274,17 @@ def patch_matrix(col, y, patch: int = 0):
         raise ValueError("patch size exceeds K")
     complete = col[:, P - 1] >= 0 if P > 0 else np.ones(col.shape[0], bool)
     idx = np.concatenate([np.arange(col.shape[0])[:, None], col[:, :P]], axis=1)[complete]
+    if order:
+        idx = np.sort(idx, axis=1)
     return complete, y[idx]
 
 
-def patch_covariance(col, y, patch: int = 0):
+def patch_covariance(col, y, patch: int = 0, order: int = 0):
     """Sigma = (1/N) sum_i (a_i - mu)(a_i - mu)^T with mu the mean patch
     (Sec. 2.3), pooled over the three channels with each channel's own mean
     removed (R4): Sigma = (1/(3 N_eff)) sum_c sum_i (a_i^c - mu^c)(a_i^c - mu^c)^T.
     Returns (Sigma [D,D], N_eff)."""
-    complete, A = patch_matrix(col, y, patch)
+    complete, A = patch_matrix(col, y, patch, order)
     n_eff, D = A.shape[0], A.shape[1]
     if n_eff == 0:
         return np.zeros((D, D)), 0
@@ -305,10 +313,11 @@ def sigma_from_eigenvalues(lam):
     return 0.0, D  # D == 0
 
 
-def estimate_noise(col, y, patch: int = 0) -> dict:
+def estimate_noise(col, y, patch: int = 0, order: int = 0) -> dict:
     """NE-GBP (Sec. 2.3): patch covariance, its eigenvalues (LAPACK symmetric
-    solver), and the tail rule.  No complete patch gives sigma_est = 0."""
-    sigma, n_eff = patch_covariance(col, y, patch)
+    solver), and the tail rule.  No complete patch gives sigma_est = 0.
+    ``order`` as in patch_matrix."""
+    sigma, n_eff = patch_covariance(col, y, patch, order)
     if n_eff == 0:
         return dict(sigma_est=0.0, m=0, eigvals=np.zeros(sigma.shape[0]), cov=sigma, n_eff=0)
     lam = np.linalg.eigvalsh(sigma)[::-1]
@@ -404,7 +413,7 @@ def denoise(xyz, rgb, params: dict | None = None, q_fixed: int | None = None) ->
     col, dist2 = slg_graph(g, prm["bits"], prm["num_dirs"], prm["window"], prm["k"])
     sg = prm["sigma_g"] if prm["sigma_g"] > 0 else bandwidth(col, dist2)
     p = edge_weights(col, dist2, sg)
-    ne = estimate_noise(col, y, prm["patch"])
+    ne = estimate_noise(col, y, prm["patch"], prm["patch_order"])
     if ne["n_eff"] == 0:
         status |= 2
     spread = patch_spread(col, y, prm["patch"])

@@ -188,6 +188,8 @@ fgbd_status check_params(const fgbd_params *p) {
   if (p->q_max < 0 || p->q_max > 1024) return fail(FGBD_E_INVALID, "q_max must be in 0..1024 (got %d)", p->q_max);
   if (!isfinite(p->fslr_kappa)) return fail(FGBD_E_INVALID, "fslr_kappa must be finite");
   if (!isfinite(p->sigma_g)) return fail(FGBD_E_INVALID, "sigma_g must be finite");
+  if (p->patch_order != 0 && p->patch_order != 1)
+    return fail(FGBD_E_INVALID, "patch_order must be 0 or 1 (got %d)", p->patch_order);
   return FGBD_OK;
 }
 
@@ -402,6 +404,8 @@ fgbd_status fgbd_default_params(fgbd_params *p) {
   p->q_max = 32;
   p->fslr_kappa = 2.0;
   p->sigma_g = 0.0;
+  p->patch_order = 0;
+  p->pad_ = 0;
   return ok();
 }
 
@@ -614,7 +618,7 @@ static fgbd_status run_denoise(const Run &r, const int32_t *xyz, const float *rg
                                fgbd_result *res) {
   fgbd_status st;
   if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
-  if (r.prm.k == 8 && r.pl.P == 8) {
+  if (r.prm.k == 8 && r.pl.P == 8 && r.prm.patch_order == 0) {
     // the noise launch gathers each point's row and its neighbours' colours
     // anyway: it also computes the weights and the first sweep's colours, and
     // the first sweep launch only adds the FSLR flags and the sums

@@ -74,6 +74,7 @@ struct NoiseArgs {
   int32_t E2, E;       // D(D+1)/2 and E2 + 3D
   int32_t groups;      // row groups per entry
   int32_t want_eig3;
+  int32_t order;       // 1: patch entries by increasing point index (generic kernel only)
   // the fused per-frame path (K = P = 8): the first filter sweep's colours
   // x1 = T y with the eq. 4 weights, computed here from the same neighbour
   // rows; the first sweep launch then only marks FSLR membership and sums
@@ -406,14 +407,29 @@ __device__ __forceinline__ bool patch_point(const NoiseArgs &a, int64_t i, const
     return true;
   } else {
     double mean[3], cov[6] = {0, 0, 0, 0, 0, 0};
-    r0[0] = rgb[3 * i + 0];
-    r1[0] = rgb[3 * i + 1];
-    r2[0] = rgb[3 * i + 2];
-    for (int k = 0; k < P; ++k) {
-      const int64_t j = col[i * K + k];
-      r0[1 + k] = rgb[3 * j + 0];
-      r1[1 + k] = rgb[3 * j + 1];
-      r2[1 + k] = rgb[3 * j + 2];
+    if (a.order == 0) {
+      r0[0] = rgb[3 * i + 0];
+      r1[0] = rgb[3 * i + 1];
+      r2[0] = rgb[3 * i + 2];
+      for (int k = 0; k < P; ++k) {
+        const int64_t j = col[i * K + k];
+        r0[1 + k] = rgb[3 * j + 0];
+        r1[1 + k] = rgb[3 * j + 1];
+        r2[1 + k] = rgb[3 * j + 2];
+      }
+    } else {
+      // unsorted patch: member m (the point, then its P neighbours) goes to
+      // the slot of its rank among the D point indices, which are distinct
+      // (a row never repeats a neighbour or holds the point itself), so the
+      // ranks are a permutation of 0 .. D-1
+      for (int m = 0; m < D; ++m) {
+        const int64_t j = m == 0 ? i : (int64_t)col[i * K + m - 1];
+        int rank = (m != 0 && i < j) ? 1 : 0;
+        for (int l = 0; l < P; ++l) rank += (int64_t)col[i * K + l] < j ? 1 : 0;
+        r0[rank] = rgb[3 * j + 0];
+        r1[rank] = rgb[3 * j + 1];
+        r2[rank] = rgb[3 * j + 2];
+      }
     }
     const float *rr[3] = {r0, r1, r2};
 #pragma unroll
@@ -958,6 +974,7 @@ NoiseArgs make_args(const SegArgs &sa, int k, int P, bool want_eig3) {
   a.dist2 = nullptr;
   a.edge_acc = nullptr;
   a.sigma_g_fixed = 0.0;
+  a.order = 0;
   a.res = nullptr;
   a.p_out = nullptr;
   a.x1 = nullptr;
@@ -969,9 +986,10 @@ NoiseArgs make_args(const SegArgs &sa, int k, int P, bool want_eig3) {
 hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, double *spread, float *eig3,
                         fgbd_result *fuse_res) {
   NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, eig3 != nullptr);
+  a.order = r.prm.patch_order;
   const bool fuse = fuse_res != nullptr;
   if (fuse) {
-    if (a.P != 8 || a.K != 8 || eig3 != nullptr) return hipErrorInvalidValue;
+    if (a.P != 8 || a.K != 8 || eig3 != nullptr || a.order != 0) return hipErrorInvalidValue;
     a.dist2 = r.b.dist2;
     a.edge_acc = r.b.edge_acc;
     a.sigma_g_fixed = r.prm.sigma_g;
@@ -989,9 +1007,9 @@ hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, doub
   hipStream_t st = r.stream;
   if (fuse)
     k_noise_mfma<8, false, true><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
-  else if (a.P == 8 && eig3 == nullptr)
+  else if (a.P == 8 && a.order == 0 && eig3 == nullptr)
     k_noise_mfma<8, false, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
-  else if (a.P == 8)
+  else if (a.P == 8 && a.order == 0)
     k_noise_mfma<8, true, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);
   else if (eig3 == nullptr)
     k_noise<0, false><<<nb, kBlock, lds, st>>>(a, col, rgb, spread, eig3, part);

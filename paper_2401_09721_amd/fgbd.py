@@ -26,7 +26,7 @@ FGBD_ST_NO_PATCH = 2
 FGBD_ST_BAD_OFFSETS = 4
 FGBD_ST_SWEEP_STALL = 8
 NUM_KERNELS = 9
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
            "finalize")
@@ -48,10 +48,12 @@ class Params(ctypes.Structure):
         ("q_max", ctypes.c_int32),
         ("fslr_kappa", ctypes.c_double),
         ("sigma_g", ctypes.c_double),
+        ("patch_order", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
 
 
 class Graph(ctypes.Structure):

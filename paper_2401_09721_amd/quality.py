@@ -7,6 +7,9 @@ The synthetic counterparts of the paper's evaluation (Sec. 3):
 * PSNR of the noisy and the denoised colours against the clean ones (Table 2).
   The paper does not spell its PSNR out; here it is 10 log10(255^2 / MSE) over
   all R, G and B samples of the frame;
+* NE-GBP with its patch entries left in point-index order instead of distance
+  order (``patch_order = 1``, the "w/o sort" rows of Table 4), as E_ne and as
+  the PSNR of the whole path;
 * FGBD with and without FSLR (Table 5): ``fslr_kappa = 0`` makes every point
   take part in the selection of eq. 6.  FSLR only matters where colour edges
   raise the patch spread, so the harness runs the benchmark frame's smooth
@@ -84,7 +87,8 @@ def _time_gpu(fn, torch, stream, reps: int) -> float:
 
 
 def denoise_quality(cloud, params=None, ctx=None, reps: int = 5, scan_q: bool = True) -> dict:
-    """FGBD with and without FSLR on one frame, against its clean colours."""
+    """FGBD, FGBD without FSLR and FGBD with the unsorted patch on one frame,
+    against its clean colours."""
     import torch
 
     from . import fgbd
@@ -99,13 +103,15 @@ def denoise_quality(cloud, params=None, ctx=None, reps: int = 5, scan_q: bool = 
     res = fgbd.new_result(dev)
 
     row = {"sigma_act": cloud.sigma, "n_points": int(cloud.n), "psnr_noisy": psnr(cloud.noisy, cloud.clean)}
-    for tag, kappa in (("fgbd", prm.fslr_kappa), ("no_fslr", 0.0)):
-        p = fgbd.default_params(**{**prm.as_dict(), "fslr_kappa": kappa})
+    variants = (("fgbd", {}), ("no_fslr", {"fslr_kappa": 0.0}), ("no_sort", {"patch_order": 1}))
+    for tag, change in variants:
+        p = fgbd.default_params(**{**prm.as_dict(), **change})
         ms = _time_gpu(lambda: fgbd.denoise(xyz, rgb, p, ctx=ctx, out=out, res=res), torch, stream, reps)
         r = fgbd.read_result(res)
         row[tag] = {"psnr": psnr(out.cpu().numpy(), cloud.clean), "q": r["q"], "n_fslr": r["n_fslr"],
                     "sigma_est": r["sigma_est"], "ms": ms}
     row["e_ne"] = abs(row["fgbd"]["sigma_est"] - cloud.sigma)
+    row["e_ne_no_sort"] = abs(row["no_sort"]["sigma_est"] - cloud.sigma)
     row["gain_db"] = row["fgbd"]["psnr"] - row["psnr_noisy"]
     if scan_q:
         g = fgbd.build_slg(xyz, prm, ctx=ctx)

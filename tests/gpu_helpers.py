@@ -22,7 +22,7 @@ def dev(a, dtype):
 
 def oracle_params(prm):
     return dict(bits=prm.bits, num_dirs=prm.num_dirs, window=prm.window, k=prm.k, patch=prm.patch,
-                q_max=prm.q_max, fslr_kappa=prm.fslr_kappa, sigma_g=prm.sigma_g)
+                q_max=prm.q_max, fslr_kappa=prm.fslr_kappa, sigma_g=prm.sigma_g, patch_order=prm.patch_order)
 
 
 def compare_denoise(out, r, xyz, rgb, prm, ores=None, status_mask=~0):

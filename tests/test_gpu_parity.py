@@ -120,6 +120,27 @@ def test_noise_estimate_tiny(sigma, P):
     assert np.all(np.abs(ge - oe) <= 1e-5 * scale + 1e-4)
 
 
+@pytest.mark.parametrize("shuffle", [False, True])
+@pytest.mark.parametrize("P", [0, 3])
+def test_noise_estimate_unsorted_patch(shuffle, P):
+    # the "w/o sort" ablation: patch entries by point index (generic kernel,
+    # also for P = K = 8, where the sorted patch takes the MFMA kernel)
+    c = synth.random_shapes_cloud(7, bits=8, target=12000, shuffle=shuffle)
+    prm = fgbd.default_params(bits=8, patch=P, patch_order=1)
+    g, ocol, od2, op, sg = check_graph(c.xyz, prm)
+    res, spread, _ = fgbd.estimate_noise(g, dev(c.noisy, torch.float32), prm)
+    torch.cuda.synchronize()
+    r = fgbd.read_result(res)
+    ne = O.estimate_noise(ocol, c.noisy, P, order=1)
+    assert abs(r["sigma_est"] - ne["sigma_est"]) <= 1e-9 * ne["sigma_est"]
+    assert r["n_eff"] == ne["n_eff"] and r["m"] == ne["m"]
+    # the spread does not depend on the order
+    os_ = O.patch_spread(ocol, c.noisy, P)
+    gs = spread.cpu().numpy()
+    fin = np.isfinite(os_)
+    assert np.allclose(gs[fin], os_[fin], rtol=1e-12, atol=1e-12)
+
+
 def test_noise_constant_and_pure_noise():
     c = synth.tiny_cloud(0)
     prm = fgbd.default_params(bits=8)
@@ -180,15 +201,17 @@ def test_denoise_tiny(sigma):
 
 
 @pytest.mark.parametrize("kw", [dict(num_dirs=3, window=1, k=6), dict(fslr_kappa=0.0), dict(fslr_kappa=0.5),
-                                dict(q_max=1), dict(q_max=0), dict(num_dirs=16, k=12, patch=6)])
+                                dict(q_max=1), dict(q_max=0), dict(num_dirs=16, k=12, patch=6),
+                                dict(patch_order=1), dict(patch_order=1, k=12, patch=5)])
 def test_denoise_variants(kw):
     c = synth.tiny_cloud(0)
     check_denoise(c.xyz, c.noisy, fgbd.default_params(bits=8, **kw))
 
 
-def test_denoise_shuffled_order():
+@pytest.mark.parametrize("order", [0, 1])
+def test_denoise_shuffled_order(order):
     c = synth.random_shapes_cloud(5, bits=8, target=12000, shuffle=True)
-    check_denoise(c.xyz, c.noisy, fgbd.default_params(bits=8))
+    check_denoise(c.xyz, c.noisy, fgbd.default_params(bits=8, patch_order=order))
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 9, 4097])

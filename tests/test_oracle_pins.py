@@ -306,6 +306,46 @@ def test_eigenvalues_match_lapack_on_special_matrices():
 
 # ------------------------------------------------------------------- FSLR
 
+def test_unsorted_patch_lists_the_same_points_by_index():
+    # "NE-GBP w/o sort" (Sec. 3): the patch holds the point and its first P
+    # neighbours; only their order changes, to increasing point index
+    c = synth.random_shapes_cloud(2, bits=7, target=1500, shuffle=True)
+    col, _ = O.slg_graph(c.xyz, 7, 8, 4, 8)
+    for P in (3, 8):
+        ok0, A0 = O.patch_matrix(col, c.noisy, P, order=0)
+        ok1, A1 = O.patch_matrix(col, c.noisy, P, order=1)
+        assert np.array_equal(ok0, ok1)
+        for r, i in enumerate(np.flatnonzero(ok1)[:200]):
+            members = sorted({int(i)} | {int(j) for j in col[i, :P]})
+            assert len(members) == P + 1
+            assert np.array_equal(A1[r], c.noisy[members].astype(np.float64))
+            assert np.array_equal(A0[r, 0], c.noisy[i].astype(np.float64))
+
+
+def test_unsorted_patch_with_one_common_permutation_permutes_sigma():
+    # when every row's index order is the same permutation of its distance
+    # order, Sigma is that permutation applied on both sides and the
+    # eigenvalues (so sigma_est) are unchanged; otherwise the estimate moves
+    rng = np.random.default_rng(11)
+    n = 400
+    y = rng.normal(128.0, 20.0, size=(n, 3))
+    col = np.full((n, 2), -1, np.int64)
+    col[: n - 2, 0] = np.arange(2, n)  # distance order (i, i+2, i+1)
+    col[: n - 2, 1] = np.arange(1, n - 1)
+    s0, n0 = O.patch_covariance(col, y, 2, order=0)
+    s1, n1 = O.patch_covariance(col, y, 2, order=1)
+    perm = [0, 2, 1]  # index order (i, i+1, i+2) = positions 0, 2, 1 of the distance order
+    assert n0 == n1 == n - 2
+    assert np.allclose(s1, s0[np.ix_(perm, perm)], rtol=1e-13, atol=1e-9)
+    assert O.estimate_noise(col, y, 2, order=1)["sigma_est"] == pytest.approx(
+        O.estimate_noise(col, y, 2, order=0)["sigma_est"], rel=1e-12)
+    col[::2] = col[::2, ::-1]  # even rows now list (i+1, i+2): no common permutation
+    s2, _ = O.patch_covariance(col, y, 2, order=0)
+    s3, _ = O.patch_covariance(col, y, 2, order=1)
+    assert np.allclose(s3, s1)  # the index order does not see the row order
+    assert not np.allclose(np.linalg.eigvalsh(s2), np.linalg.eigvalsh(s3))
+
+
 def test_spread_matches_numpy_std_and_colour_eigs():
     c, col, d2, p = _tiny_graph()
     s = O.patch_spread(col, c.noisy)
