@@ -301,6 +301,32 @@ fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const f
                                       int32_t ncoef, const double *sigma_g, const float *grad_out, float *grad_x,
                                       float *grad_coef, double *grad_sigma_g, void *stream);
 
+/* Float coordinates onto the 2^bits integer grid that the scan-line graph
+ * takes (Sec. 2.2 assumes voxelised integer coordinates).  One scale for the
+ * three axes keeps the shape:
+ *   lo_c = min_i x_ic, ext = max over c of (max_i x_ic - lo_c), s = 2^bits / ext
+ *   (s = 0 when ext = 0), g_ic = min(floor((x_ic - lo_c) * s), 2^bits - 1),
+ * evaluated in FP64 with IEEE division, so the codes are exact.  Points that
+ * share a voxel are all kept (the graph links them at distance 0).  NaN
+ * coordinates take no part in the bounds and map to 0; an infinite one makes
+ * s = 0 (every code 0).
+ *   xyz:     device float32 [n][3], read only.
+ *   bits:    1..21 (the per-frame calls take 1..10).
+ *   xyz_out: device int32 [n][3], written; must not overlap xyz.
+ *   frame:   device double[4], written: lo_x, lo_y, lo_z, s, so a voxel g maps
+ *            back to lo + (g + 1/2) / s.  lo is NaN on an axis with no finite
+ *            value (and for n = 0).
+ * Uses 32 bytes of the context workspace.  Errors: FGBD_E_INVALID for a NULL
+ * pointer, bits out of range, n < 0 or overlapping buffers. */
+fgbd_status fgbd_quantize(fgbd_ctx ctx, const float *xyz, int64_t n, int32_t bits, int32_t *xyz_out, double *frame,
+                          void *stream);
+
+/* Colours to 8 bits after filtering: out = clip(round_half_even(rgb), 0, 255),
+ * NaN to 0 (the filter output is neither rounded nor clipped).
+ *   rgb: device float32 [n][3]; out: device uint8 [n][3], must not overlap rgb.
+ * Errors: FGBD_E_INVALID for a NULL pointer, n < 0 or overlapping buffers. */
+fgbd_status fgbd_round_u8(fgbd_ctx ctx, const float *rgb, int64_t n, uint8_t *out, void *stream);
+
 /* Message for the last non-OK status returned on the calling thread ("" if
  * none).  Valid until the next call on this thread. */
 const char *fgbd_last_error(void);

@@ -47,6 +47,8 @@ import numpy as np
 
 __all__ = [
     "DIRECTIONS",
+    "quantize",
+    "round_u8",
     "direction_frame",
     "scan_keys",
     "scan_orders",
@@ -426,6 +428,45 @@ def denoise(xyz, rgb, params: dict | None = None, q_fixed: int | None = None) ->
     return dict(out=sel["out"], sigma_est=ne["sigma_est"], sigma_g=sg, q=sel["q"], n_fslr=int(S.sum()),
                 n_eff=ne["n_eff"], status=status, col=col, dist2=dist2, p=p, spread=spread,
                 energies=sel["energies"], loss=sel["loss"], m=ne["m"], eigvals=ne["eigvals"])
+
+
+# ---------------------------------------------------------------------------
+# Steps on either side of the path: float coordinates onto the grid that
+# Sec. 2.2 assumes, and filtered colours back to 8 bits
+# ---------------------------------------------------------------------------
+
+def quantize(xyz, bits: int):
+    """Float coordinates to b-bit voxel codes with one scale for all axes
+    (Sec. 2.2 takes integer coordinates): lo_c = min x_c, ext = the largest
+    axis range, s = 2^b / ext (0 when ext = 0), g = min(floor((x - lo) s),
+    2^b - 1), in FP64.  NaN coordinates are left out of the bounds and map to
+    0.  Returns (int32 [N,3], (lo [3], s))."""
+    x = np.asarray(xyz, np.float32).astype(np.float64)
+    n = x.shape[0]
+    lo = np.full(3, np.nan)
+    ext = 0.0
+    for c in range(3):
+        finite = x[:, c][~np.isnan(x[:, c])]
+        if finite.size:
+            lo[c] = finite.min()
+            ext = max(ext, finite.max() - lo[c])
+    cells = float(2 ** bits)
+    s = cells / ext if ext > 0 else 0.0
+    g = np.zeros((n, 3), np.int64)
+    with np.errstate(invalid="ignore"):
+        v = (x - lo[None, :]) * s
+        ok = v >= 0
+        g[ok] = np.minimum(np.floor(np.minimum(v[ok], cells)), cells - 1).astype(np.int64)
+    return g.astype(np.int32), (lo, s)
+
+
+def round_u8(rgb):
+    """Colours to uint8: round half to even, clip to 0..255, NaN to 0."""
+    v = np.rint(np.asarray(rgb, np.float32))
+    out = np.zeros(v.shape, np.uint8)
+    ok = v >= 0
+    out[ok] = np.minimum(v[ok], 255).astype(np.uint8)
+    return out
 
 
 # ---------------------------------------------------------------------------

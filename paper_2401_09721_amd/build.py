@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfgbd.so")
 
-SOURCES = ["fgbd_api.hip", "fgbd_sort.hip", "fgbd_graph.hip", "fgbd_noise.hip", "fgbd_filter.hip", "fgbd_poly.hip"]
+SOURCES = ["fgbd_api.hip", "fgbd_sort.hip", "fgbd_graph.hip", "fgbd_noise.hip", "fgbd_filter.hip", "fgbd_poly.hip", "fgbd_io.hip"]
 
 ARCH = "gfx950"
 HIPFLAGS = [

@@ -893,6 +893,36 @@ fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const f
   return ok();
 }
 
+fgbd_status fgbd_quantize(fgbd_ctx ctx, const float *xyz, int64_t n, int32_t bits, int32_t *xyz_out, double *frame,
+                          void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_n(n);
+  if (st != FGBD_OK) return st;
+  if (bits < 1 || bits > 21) return fail(FGBD_E_INVALID, "bits must be in 1..21 (got %d)", bits);
+  if (!frame) return fail(FGBD_E_INVALID, "frame is NULL");
+  if (n > 0 && (!xyz || !xyz_out)) return fail(FGBD_E_INVALID, "NULL input or output array");
+  if (n > 0 && overlap(xyz, (size_t)n * 12, xyz_out, (size_t)n * 12)) return fail(FGBD_E_INVALID, "xyz and xyz_out overlap");
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, 256, &ws)) != FGBD_OK) return st;
+  HIP_TRY(launch_quantize(xyz, n, bits, xyz_out, frame, (uint32_t *)ws, (hipStream_t)stream), "quantize launch");
+  return ok();
+}
+
+fgbd_status fgbd_round_u8(fgbd_ctx ctx, const float *rgb, int64_t n, uint8_t *out, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_n(n);
+  if (st != FGBD_OK) return st;
+  if (n > 0 && (!rgb || !out)) return fail(FGBD_E_INVALID, "NULL input or output array");
+  if (n > 0 && overlap(rgb, (size_t)n * 12, out, (size_t)n * 3)) return fail(FGBD_E_INVALID, "rgb and out overlap");
+  if (n == 0) return ok();
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  HIP_TRY(launch_round_u8(rgb, 3 * n, out, (hipStream_t)stream), "round launch");
+  return ok();
+}
+
 fgbd_status fgbd_profile_enable(fgbd_ctx ctx, int32_t enable) {
   if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
   ctx->profile = enable != 0;

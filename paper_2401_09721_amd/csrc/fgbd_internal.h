@@ -507,6 +507,11 @@ hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, co
 // Polynomial filter and its adjoint (ws: at least poly_workspace bytes).
 constexpr int kMaxPoly = 32;
 size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks);
+// Float coordinates onto the 2^bits grid (keys: 6 words of scratch) and
+// colours to uint8 (fgbd_io.hip).
+hipError_t launch_quantize(const float *xyz, int64_t n, int32_t bits, int32_t *out, double *frame, uint32_t *keys,
+                           hipStream_t st);
+hipError_t launch_round_u8(const float *x, int64_t m, uint8_t *out, hipStream_t st);
 hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *x,
                                const float *coef, int ncoef, const double *sigma_g, float *out, float *saved,
                                char *ws, hipStream_t s);

@@ -115,6 +115,10 @@ _SIGNATURES = {
     "fgbd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Schedule), ctypes.c_void_p]),
+    "fgbd_quantize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_round_u8": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
     "fgbd_poly_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -459,6 +463,31 @@ def denoise_batched_fixed_q(xyz, rgb, offsets, q: int, params=None, ctx: Optiona
 
 
 # ------------------------------------------------------- polynomial filter
+def quantize(xyz, bits: int = 10, ctx: Optional[Context] = None, out=None, frame=None, stream=None):
+    """Float32 [n, 3] device coordinates onto the 2^bits grid with one scale for
+    the three axes (Sec. 2.2 takes voxel coordinates).  Returns (int32 [n, 3],
+    float64 [4] frame = lo_x, lo_y, lo_z, s)."""
+    torch = _torch()
+    ctx = ctx or default_context(xyz.device)
+    _need(xyz, torch.float32, (3,), "xyz", ctx.device)
+    n = int(xyz.shape[0])
+    out = torch.empty((n, 3), dtype=torch.int32, device=ctx.device) if out is None else out
+    frame = torch.empty(4, dtype=torch.float64, device=ctx.device) if frame is None else frame
+    _check(lib().fgbd_quantize(ctx.handle, _ptr(xyz), n, int(bits), _ptr(out), _ptr(frame), _stream(ctx, stream)))
+    return out, frame
+
+
+def round_u8(rgb, ctx: Optional[Context] = None, out=None, stream=None):
+    """Filtered float32 [n, 3] colours to uint8: round half to even, clip to 0..255."""
+    torch = _torch()
+    ctx = ctx or default_context(rgb.device)
+    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    n = int(rgb.shape[0])
+    out = torch.empty((n, 3), dtype=torch.uint8, device=ctx.device) if out is None else out
+    _check(lib().fgbd_round_u8(ctx.handle, _ptr(rgb), n, _ptr(out), _stream(ctx, stream)))
+    return out
+
+
 def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None, stream=None):
     """out = sum_k coef[k] T^k x with eq. 4 weights at the device bandwidth
     sigma_g (float64 scalar tensor).  Returns (out, saved iterates)."""

@@ -489,3 +489,49 @@ def test_poly_grads_single_coefficient():
     assert gs == 0.0
     assert np.allclose(gx, 0.7 * go)
     assert math.isclose(gc[0], float(np.sum(go * x)), rel_tol=1e-12)
+
+
+# ------------------------------------------------ quantisation and rounding
+
+def test_quantize_hand_example():
+    x = np.array([[0.0, 0.0, 0.0], [1.0, 0.5, 0.25], [0.75, 0.125, 0.0]], np.float32)
+    g, (lo, s) = O.quantize(x, 2)  # ext = 1 on x, s = 4
+    assert s == 4.0 and np.array_equal(lo, [0, 0, 0])
+    assert g.tolist() == [[0, 0, 0], [3, 2, 1], [3, 0, 0]]
+
+
+def test_quantize_invariants():
+    rng = np.random.default_rng(4)
+    x = (rng.integers(-4000, 4000, size=(3000, 3)) / 8.0).astype(np.float32)
+    x[:, 2] *= 0.25  # the x axis has the largest range
+    for bits in (1, 7, 10, 16):
+        g, (lo, s) = O.quantize(x, bits)
+        top = 2 ** bits - 1
+        assert g.min() == 0 and g.max() == top
+        assert np.array_equal(g.min(axis=0), [0, 0, 0])
+        assert g[:, 0].max() == top and g[:, 2].max() < top // 2 + 2
+        for c in range(3):  # monotone on every axis
+            o = np.argsort(x[:, c], kind="stable")
+            assert (np.diff(g[o, c]) >= 0).all()
+        # exact translation and power-of-two scaling leave the codes unchanged
+        assert np.array_equal(O.quantize(x + np.float32(64.0), bits)[0], g)
+        assert np.array_equal(O.quantize(x * np.float32(0.5), bits)[0], g)
+        # brute force: the code is the number of whole cells below each value
+        cell = 1.0 / s
+        ref = np.minimum(np.floor((x.astype(np.float64) - lo) / cell + 1e-12), top)
+        assert np.abs(ref - g).max() <= 1  # the 1e-12 guard only moves exact cell edges
+
+
+def test_quantize_degenerate_and_nan():
+    g, (lo, s) = O.quantize(np.full((5, 3), 7.5, np.float32), 10)
+    assert s == 0.0 and (g == 0).all() and np.array_equal(lo, [7.5] * 3)
+    x = np.array([[0, 0, 0], [np.nan, 2, 2], [4, 4, 4]], np.float32)
+    g, (lo, s) = O.quantize(x, 3)
+    assert s == 2.0 and g.tolist() == [[0, 0, 0], [0, 4, 4], [7, 7, 7]]
+    g, (lo, s) = O.quantize(np.zeros((0, 3), np.float32), 4)
+    assert g.shape == (0, 3) and s == 0.0 and np.isnan(lo).all()
+
+
+def test_round_u8_half_even_and_clip():
+    v = np.array([0.5, 1.5, 2.5, 3.49, -0.7, -0.5, 254.5, 255.4, 255.6, 300, np.nan, -np.inf, np.inf], np.float32)
+    assert O.round_u8(v).tolist() == [0, 2, 2, 3, 0, 0, 254, 255, 255, 255, 0, 0, 255]
