@@ -327,6 +327,20 @@ fgbd_status fgbd_quantize(fgbd_ctx ctx, const float *xyz, int64_t n, int32_t bit
  * Errors: FGBD_E_INVALID for a NULL pointer, n < 0 or overlapping buffers. */
 fgbd_status fgbd_round_u8(fgbd_ctx ctx, const float *rgb, int64_t n, uint8_t *out, void *stream);
 
+/* Geometry smoothing with the same graph and filter (the paper names applying
+ * them to coordinates as the next step, Secs. 1 and 4): the scan-line graph
+ * of the integer coordinates and its eq. 4 weights (Sec. 2.2), then q sweeps
+ * of eq. 5 applied to the coordinates themselves as a three-channel signal.
+ * No noise estimate and no selection: q is the caller's.
+ *   xyz:     device int32 [n][3] in 0 .. 2^bits - 1 (as for fgbd_denoise).
+ *   q:       0..1024 sweeps (0 returns the coordinates as float).
+ *   xyz_out: device float32 [n][3], written; must not overlap xyz.
+ *   res:     device fgbd_result: sigma_g, q and status are set.
+ * Uses the context workspace like fgbd_denoise.  Errors: FGBD_E_INVALID for
+ * NULL pointers, bad parameters, q out of range or overlapping buffers. */
+fgbd_status fgbd_smooth_geometry(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_params *params, int32_t q,
+                                 float *xyz_out, fgbd_result *res, void *stream);
+
 /* Message for the last non-OK status returned on the calling thread ("" if
  * none).  Valid until the next call on this thread. */
 const char *fgbd_last_error(void);

@@ -49,6 +49,7 @@ __all__ = [
     "DIRECTIONS",
     "quantize",
     "round_u8",
+    "smooth_geometry",
     "direction_frame",
     "scan_keys",
     "scan_orders",
@@ -458,6 +459,18 @@ def quantize(xyz, bits: int):
         ok = v >= 0
         g[ok] = np.minimum(np.floor(np.minimum(v[ok], cells)), cells - 1).astype(np.int64)
     return g.astype(np.int32), (lo, s)
+
+
+def smooth_geometry(xyz, q: int, params: dict | None = None) -> dict:
+    """The scan-line graph and eq. 4 weights of the coordinates (Sec. 2.2), then
+    q applications of eq. 5 to the coordinates as the signal.  Returns
+    dict(out [N,3] float64, sigma_g, col, p)."""
+    prm = default_params(**(params or {}))
+    g = np.asarray(xyz, np.int64)
+    col, dist2 = slg_graph(g, prm["bits"], prm["num_dirs"], prm["window"], prm["k"])
+    sg = prm["sigma_g"] if prm["sigma_g"] > 0 else bandwidth(col, dist2)
+    p = edge_weights(col, dist2, sg)
+    return dict(out=filter_power(col, p, g.astype(np.float64), q), sigma_g=sg, col=col, p=p)
 
 
 def round_u8(rgb):

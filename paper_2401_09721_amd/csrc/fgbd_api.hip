@@ -719,6 +719,35 @@ fgbd_status fgbd_denoise_batched_fixed_q(fgbd_ctx ctx, const int32_t *xyz, const
   return run_filter(r, r.b.col, r.b.p, r.b.dist2, rgb_in, nullptr, nullptr, 0, q_fixed, rgb_out, res);
 }
 
+fgbd_status fgbd_smooth_geometry(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_params *params, int32_t q,
+                                 float *xyz_out, fgbd_result *res, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_params(params);
+  if (st != FGBD_OK) return st;
+  if ((st = check_n(n)) != FGBD_OK) return st;
+  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
+  if (q < 0 || q > 1024) return fail(FGBD_E_INVALID, "q must be in 0..1024 (got %d)", q);
+  if (n > 0 && (!xyz || !xyz_out)) return fail(FGBD_E_INVALID, "NULL input or output array");
+  if (n > 0 && overlap(xyz, (size_t)n * 12, xyz_out, (size_t)n * 12))
+    return fail(FGBD_E_INVALID, "xyz and xyz_out overlap");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  const Plan pl = make_plan(n, 1, *params, ctx->tune);
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  EventProf ep(ctx, s);
+  Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  HIP_TRY(launch_setup(r, nullptr, n, res, n == 0 ? 2 : 1), "setup launch");
+  if (n == 0) return ok();
+  // the coordinates become the signal in the output buffer; with a fixed q
+  // the filter reads its input only in the first sweep and writes the output
+  // after the last, so it runs in place
+  HIP_TRY(launch_coords_f32(xyz, 3 * n, xyz_out, s), "coordinate launch");
+  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
+  return run_filter(r, r.b.col, r.b.p, r.b.dist2, xyz_out, nullptr, nullptr, 0, q, xyz_out, res);
+}
+
 static fgbd_status check_schedule(const fgbd_schedule *s) {
   if (!s) return fail(FGBD_E_INVALID, "schedule is NULL");
   if (s->merge_blocks < kGridCapMin || s->merge_blocks > kGridCapMax || s->sweep_blocks < kGridCapMin ||

@@ -512,6 +512,7 @@ size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks);
 hipError_t launch_quantize(const float *xyz, int64_t n, int32_t bits, int32_t *out, double *frame, uint32_t *keys,
                            hipStream_t st);
 hipError_t launch_round_u8(const float *x, int64_t m, uint8_t *out, hipStream_t st);
+hipError_t launch_coords_f32(const int32_t *g, int64_t m, float *out, hipStream_t st);
 hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *x,
                                const float *coef, int ncoef, const double *sigma_g, float *out, float *saved,
                                char *ws, hipStream_t s);

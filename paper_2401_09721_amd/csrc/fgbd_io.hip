@@ -11,6 +11,9 @@
 // maxima of order-preserving 32-bit keys, combined with integer atomics (exact
 // and order-free); NaN coordinates take no part in the bounds and map to 0.
 //
+// Geometry as the signal: the integer coordinates as float32, which the
+// filter then smooths like colours.
+//
 // Output rounding: colours to uint8 by round-half-to-even and clipping to
 // 0..255 (NaN to 0).
 #include "fgbd_internal.h"
@@ -109,6 +112,12 @@ __global__ __launch_bounds__(kBlock) void k_round_u8(const float *__restrict__ x
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_coords_f32(const int32_t *__restrict__ g, int64_t m,
+                                                       float *__restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m; e += stride) out[e] = (float)g[e];
+}
+
 int grid_for(int64_t items) {
   const int64_t b = (items + kBlock - 1) / kBlock;
   return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
@@ -124,6 +133,12 @@ hipError_t launch_quantize(const float *xyz, int64_t n, int32_t bits, int32_t *o
     k_bounds<<<gb, kBlock, 0, st>>>(xyz, n, keys);
   }
   k_quantize<<<grid_for(3 * n), kBlock, 0, st>>>(xyz, 3 * n, bits, keys, out, frame);
+  return hipGetLastError();
+}
+
+hipError_t launch_coords_f32(const int32_t *g, int64_t m, float *out, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  k_coords_f32<<<grid_for(m), kBlock, 0, st>>>(g, m, out);
   return hipGetLastError();
 }
 

@@ -117,6 +117,8 @@ _SIGNATURES = {
                                      ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Schedule), ctypes.c_void_p]),
     "fgbd_quantize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_smooth_geometry": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(Params),
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_round_u8": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p]),
     "fgbd_poly_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p,
@@ -475,6 +477,22 @@ def quantize(xyz, bits: int = 10, ctx: Optional[Context] = None, out=None, frame
     frame = torch.empty(4, dtype=torch.float64, device=ctx.device) if frame is None else frame
     _check(lib().fgbd_quantize(ctx.handle, _ptr(xyz), n, int(bits), _ptr(out), _ptr(frame), _stream(ctx, stream)))
     return out, frame
+
+
+def smooth_geometry(xyz, q: int, params=None, ctx: Optional[Context] = None, out=None, res=None, stream=None):
+    """The scan-line graph and q eq. 5 sweeps applied to the int32 [n, 3] device
+    coordinates themselves.  Returns (float32 [n, 3], result tensor)."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(xyz.device)
+    _need(xyz, torch.int32, (3,), "xyz", ctx.device)
+    n = int(xyz.shape[0])
+    ctx.reserve(prm, n)
+    out = torch.empty((n, 3), dtype=torch.float32, device=ctx.device) if out is None else out
+    res = new_result(ctx.device) if res is None else res
+    _check(lib().fgbd_smooth_geometry(ctx.handle, _ptr(xyz), n, ctypes.byref(prm), int(q), _ptr(out), _ptr(res),
+                                      _stream(ctx, stream)))
+    return out, res
 
 
 def round_u8(rgb, ctx: Optional[Context] = None, out=None, stream=None):

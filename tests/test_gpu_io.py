@@ -65,3 +65,20 @@ def test_round_u8_matches_oracle(n):
     out = fgbd.round_u8(dev(v, torch.float32))
     assert out.dtype == torch.uint8 and tuple(out.shape) == (n, 3)
     assert np.array_equal(out.cpu().numpy(), O.round_u8(v))
+
+
+@pytest.mark.parametrize("q", [0, 1, 4])
+@pytest.mark.parametrize("kind", ["tiny", "shapes"])
+def test_smooth_geometry_matches_oracle(q, kind):
+    c = synth.tiny_cloud(0) if kind == "tiny" else synth.random_shapes_cloud(8, bits=8, target=20000, shuffle=True)
+    prm = fgbd.default_params(bits=8)
+    out, res = fgbd.smooth_geometry(dev(c.xyz, torch.int32), q, prm)
+    torch.cuda.synchronize()
+    r = fgbd.read_result(res)
+    o = O.smooth_geometry(c.xyz, q, dict(bits=8))
+    assert r["q"] == q
+    assert abs(r["sigma_g"] - o["sigma_g"]) <= 1e-12 * o["sigma_g"]
+    # FP32 sweeps on coordinates below 2^8: a few units in the last place per sweep
+    tol = 2.0 ** 8 * 2.0 ** -20 * (q + 2)
+    err = float(np.max(np.abs(out.cpu().numpy() - o["out"])))
+    assert err <= tol, f"max coordinate error {err} > {tol}"

@@ -535,3 +535,22 @@ def test_quantize_degenerate_and_nan():
 def test_round_u8_half_even_and_clip():
     v = np.array([0.5, 1.5, 2.5, 3.49, -0.7, -0.5, 254.5, 255.4, 255.6, 300, np.nan, -np.inf, np.inf], np.float32)
     assert O.round_u8(v).tolist() == [0, 2, 2, 3, 0, 0, 254, 255, 255, 255, 0, 0, 255]
+
+
+# ------------------------------------------------ geometry as the signal
+
+def test_geometry_smoothing_translation_plane_and_q0():
+    c = synth.random_shapes_cloud(6, bits=8, target=3000)
+    prm = dict(bits=9)
+    base = O.smooth_geometry(c.xyz, 3, prm)["out"]
+    t = np.array([17, 40, 3], np.int32)  # the graph and its weights do not change under translation
+    moved = O.smooth_geometry(c.xyz + t, 3, prm)["out"]
+    assert np.allclose(moved - t, base, rtol=0, atol=1e-9)
+    assert np.array_equal(O.smooth_geometry(c.xyz, 0, prm)["out"], c.xyz.astype(np.float64))
+    # a flat sheet stays flat: eq. 5 is a convex combination per row
+    rng = np.random.default_rng(1)
+    sheet = np.unique(np.c_[rng.integers(0, 200, size=(4000, 2)), np.full(4000, 77)], axis=0).astype(np.int32)
+    out = O.smooth_geometry(sheet, 5, dict(bits=8))["out"]
+    assert np.allclose(out[:, 2], 77.0, rtol=0, atol=1e-9)
+    # smoothing moves points towards their neighbours: never outside the bounding box
+    assert (out[:, :2] >= sheet[:, :2].min(0) - 1e-9).all() and (out[:, :2] <= sheet[:, :2].max(0) + 1e-9).all()
