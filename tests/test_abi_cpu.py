@@ -80,7 +80,7 @@ def ctx():
 BAD_PARAMS = [
     dict(bits=0), dict(bits=-3), dict(num_dirs=0), dict(num_dirs=17), dict(window=0), dict(window=65),
     dict(k=0), dict(k=33), dict(patch=-1), dict(patch=9), dict(q_max=-1), dict(q_max=5000),
-    dict(fslr_kappa=float("nan")), dict(sigma_g=float("inf")),
+    dict(fslr_kappa=float("nan")), dict(sigma_g=float("inf")), dict(patch_order=-1), dict(patch_order=2),
 ]
 
 
@@ -189,6 +189,37 @@ def test_fixed_q_batched_call_errors(ctx):
     a[4] = 0
     assert lib.fgbd_denoise_batched_fixed_q(ctx, *a) == E
     assert lib.fgbd_denoise_batched_fixed_q(None, *ok_args) == E
+
+
+def test_front_end_geometry_and_rounding_call_errors(ctx):
+    """fgbd_quantize, fgbd_round_u8 and fgbd_smooth_geometry check their
+    arguments before touching the device."""
+    lib = fgbd.lib()
+    E = fgbd.FGBD_E_INVALID
+    far = ctypes.c_void_p(0x900000)
+    frame = ctypes.c_void_p(0x990000)
+    assert lib.fgbd_quantize(None, FAKE, 10, 10, far, frame, None) == E
+    for bits in (0, 22):
+        assert lib.fgbd_quantize(ctx, FAKE, 10, bits, far, frame, None) == E
+        assert "bits" in lib.fgbd_last_error().decode()
+    assert lib.fgbd_quantize(ctx, FAKE, -1, 10, far, frame, None) == E
+    assert lib.fgbd_quantize(ctx, FAKE, 10, 10, far, None, None) == E
+    assert lib.fgbd_quantize(ctx, None, 10, 10, far, frame, None) == E
+    assert lib.fgbd_quantize(ctx, FAKE, 10, 10, ctypes.c_void_p(0x1010), frame, None) == E  # overlap
+    assert "overlap" in lib.fgbd_last_error().decode()
+    assert lib.fgbd_round_u8(None, FAKE, 10, far, None) == E
+    assert lib.fgbd_round_u8(ctx, FAKE, 10, None, None) == E
+    assert lib.fgbd_round_u8(ctx, FAKE, 10, ctypes.c_void_p(0x1004), None) == E
+    assert lib.fgbd_round_u8(ctx, FAKE, -5, far, None) == E
+    p = fgbd.default_params()
+    for q in (-1, 1025):
+        assert lib.fgbd_smooth_geometry(ctx, FAKE, 10, ctypes.byref(p), q, far, frame, None) == E
+        assert "q must" in lib.fgbd_last_error().decode()
+    assert lib.fgbd_smooth_geometry(ctx, FAKE, 10, ctypes.byref(p), 2, far, None, None) == E
+    assert lib.fgbd_smooth_geometry(ctx, FAKE, 10, ctypes.byref(p), 2, FAKE, frame, None) == E
+    bad = fgbd.default_params(patch_order=2)
+    assert lib.fgbd_smooth_geometry(ctx, FAKE, 10, ctypes.byref(bad), 2, far, frame, None) == E
+    assert "patch_order" in lib.fgbd_last_error().decode()
 
 
 def test_schedule_get_set(ctx):
