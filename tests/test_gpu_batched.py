@@ -63,7 +63,7 @@ def test_uneven_batch_matches_oracle_per_cloud():
 
 
 @pytest.mark.parametrize("kw", [dict(num_dirs=3, window=1, k=6), dict(fslr_kappa=0.0), dict(k=12, patch=6),
-                                dict(q_max=1), dict(sigma_g=2.0)])
+                                dict(q_max=1), dict(sigma_g=2.0), dict(patch_order=1)])
 def test_batch_variants(kw):
     prm = fgbd.default_params(bits=8, **kw)
     clouds = [shape_cloud(21, 8000), shape_cloud(22, 3000, sigma=10.0), small_cloud(300, 5)]
