@@ -82,3 +82,19 @@ def test_smooth_geometry_matches_oracle(q, kind):
     tol = 2.0 ** 8 * 2.0 ** -20 * (q + 2)
     err = float(np.max(np.abs(out.cpu().numpy() - o["out"])))
     assert err <= tol, f"max coordinate error {err} > {tol}"
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 9, 4097])
+def test_smooth_geometry_edge_sizes(n):
+    rng = np.random.default_rng(n + 100)
+    g = rng.integers(0, 64, size=(n, 3)).astype(np.int32)
+    prm = fgbd.default_params(bits=6)
+    out, res = fgbd.smooth_geometry(dev(g, torch.int32), 2, prm)
+    torch.cuda.synchronize()
+    r = fgbd.read_result(res)
+    o = O.smooth_geometry(g, 2, dict(bits=6))
+    assert tuple(out.shape) == (n, 3)
+    assert abs(r["sigma_g"] - o["sigma_g"]) <= 1e-12 * max(o["sigma_g"], 1.0)
+    if n:
+        err = float(np.max(np.abs(out.cpu().numpy() - o["out"])))
+        assert err <= 2.0 ** 6 * 2.0 ** -20 * 4
