@@ -316,6 +316,47 @@ def bench_streaming_periodic(frames, prm, dev, fgbd, torch, np, period=10) -> di
             "latency_includes": "device copy of the frame + graph replay; full frames also the host read of q"}
 
 
+def bench_io(cloud, prm, dev, fgbd, torch, np, reps: int = 20) -> dict:
+    """The steps on either side of the path on the headline frame: its voxel
+    coordinates as float32 (voxel centres) quantised onto the 2^b grid, the
+    denoised colours rounded to uint8, and geometry smoothing (the graph and
+    four eq. 5 sweeps on the coordinates).  HIP events on the launch stream."""
+    n = cloud.n
+    stream = torch.cuda.current_stream(dev)
+    xf = torch.as_tensor(cloud.xyz.astype(np.float32) + np.float32(0.5), device=dev)
+    rgb = torch.as_tensor(cloud.noisy, device=dev)
+    xyz = torch.as_tensor(cloud.xyz, device=dev)
+    ctx = fgbd.Context(dev)
+    ctx.reserve(prm, n)
+    g = torch.empty((n, 3), dtype=torch.int32, device=dev)
+    frame = torch.empty(4, dtype=torch.float64, device=dev)
+    u8 = torch.empty((n, 3), dtype=torch.uint8, device=dev)
+    gout = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    gres = fgbd.new_result(dev)
+    calls = {
+        "quantize": (lambda: fgbd.quantize(xf, prm.bits, ctx=ctx, out=g, frame=frame), 36 * n),
+        "round_u8": (lambda: fgbd.round_u8(rgb, ctx=ctx, out=u8), 15 * n),
+        "smooth_geometry_q4": (lambda: fgbd.smooth_geometry(xyz, 4, prm, ctx=ctx, out=gout, res=gres), None),
+    }
+    out = {"workload": f"the headline frame ({n} points)"}
+    for name, (fn, nbytes) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        row = {"us": us}
+        if nbytes:
+            row["algorithmic_bytes"] = nbytes
+            row["GB_per_s"] = nbytes / us / 1e3
+        out[name] = row
+    return out
+
+
 def bench_fwd_bwd(clouds, dev, args, fgbd, torch) -> dict:
     """Polynomial filter (8 coefficients, trained bandwidth) forward and
     hand-written adjoint on 4 x 500k points, inside Adam steps fitting the
@@ -562,6 +603,8 @@ def main() -> int:
         print(f"# streaming_periodic: {json.dumps(line['streaming_periodic'])}", file=sys.stderr, flush=True)
         line["fwd_bwd"] = bench_fwd_bwd(inputs["diff"], dev, args, fgbd, torch)
         print(f"# fwd_bwd: {json.dumps(line['fwd_bwd'])}", file=sys.stderr, flush=True)
+        line["io"] = bench_io(cloud, prm, dev, fgbd, torch, np)
+        print(f"# io: {json.dumps(line['io'])}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB

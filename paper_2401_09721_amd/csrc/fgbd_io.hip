@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_bounds(const float *__restrict__ xyz
   else if (t < 6) atomicMax(&keys[t], s_k[t][0]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_quantize(const float *__restrict__ xyz, int64_t m, int bits,
+__global__ __launch_bounds__(kBlock) void k_quantize(const float *__restrict__ xyz, int64_t n, int bits,
                                                      const uint32_t *__restrict__ keys, int32_t *__restrict__ out,
                                                      double *__restrict__ frame) {
   double lo[3], ext = 0.0;
@@ -94,12 +94,14 @@ __global__ __launch_bounds__(kBlock) void k_quantize(const float *__restrict__ x
     frame[3] = s;
   }
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m; e += stride) {
-    const int c = (int)(e % 3);
-    const double v = ((double)xyz[e] - lo[c]) * s;
-    int32_t g = 0;
-    if (v >= 0.0) g = v < cells ? (int32_t)floor(v) : top;  // NaN fails the test: 0
-    out[e] = g < top ? g : top;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = ((double)xyz[3 * i + c] - lo[c]) * s;
+      int32_t g = 0;
+      if (v >= 0.0) g = v < cells ? (int32_t)floor(v) : top;  // NaN fails the test: 0
+      out[3 * i + c] = g < top ? g : top;
+    }
   }
 }
 
@@ -129,10 +131,11 @@ hipError_t launch_quantize(const float *xyz, int64_t n, int32_t bits, int32_t *o
                            hipStream_t st) {
   k_bounds_init<<<1, 64, 0, st>>>(keys);
   if (n > 0) {
-    const int gb = grid_for(n) < 1024 ? grid_for(n) : 1024;
+    // few blocks: each adds six atomics on the same six words
+    const int gb = grid_for(n) < 512 ? grid_for(n) : 512;
     k_bounds<<<gb, kBlock, 0, st>>>(xyz, n, keys);
   }
-  k_quantize<<<grid_for(3 * n), kBlock, 0, st>>>(xyz, 3 * n, bits, keys, out, frame);
+  k_quantize<<<grid_for(n), kBlock, 0, st>>>(xyz, n, bits, keys, out, frame);
   return hipGetLastError();
 }
 
