@@ -13,6 +13,14 @@
  *   fgbd_denoise         all four steps in one call
  *   fgbd_denoise_batched all four steps for several clouds of different sizes
  *                        in one launch sequence, sizes read from device memory
+ *   fgbd_denoise_batched_fixed_q  the frames between two full ones in the
+ *                        periodic mode of Sec. 4: graph and q given sweeps
+ *
+ * Around the path: fgbd_quantize (float coordinates onto the voxel grid),
+ * fgbd_round_u8 (colours to 8 bits), fgbd_smooth_geometry (the same graph and
+ * filter applied to the coordinates), fgbd_poly_filter and its adjoint (a
+ * polynomial in the filter operator with a trainable bandwidth), and the
+ * schedule, workspace and timing calls.
  *
  * Conventions shared by every call
  *   - Every pointer named in a call is a DEVICE pointer on the context's GPU
