@@ -197,6 +197,9 @@ def main(argv=None) -> int:
     ap.add_argument("--cell", type=int, default=32, help="patched texture: cell size in voxels")
     ap.add_argument("--amp", type=float, default=48.0, help="patched texture: largest offset per channel")
     ap.add_argument("--no-scan-q", action="store_true", help="skip the sweep over fixed q")
+    ap.add_argument("--graph", nargs=3, type=int, metavar=("L", "W", "K"), default=None,
+                    help="scan directions, window and neighbours of the denoising runs (default 8 4 8; "
+                         "the paper's own graph is 3 1 6)")
     args = ap.parse_args(argv)
 
     import torch
@@ -205,17 +208,22 @@ def main(argv=None) -> int:
 
     torch.cuda.set_device(0)
     ctx = fgbd.Context(torch.device("cuda", 0))
+    prm = fgbd.default_params()
+    if args.graph:
+        prm = fgbd.default_params(num_dirs=args.graph[0], window=args.graph[1], k=args.graph[2])
     make = {"smooth": synth.body_cloud,
             "patched": lambda **kw: synth.patched_body_cloud(cell=args.cell, amp=args.amp, **kw)}
     for tex in args.textures:
         for s in args.sigmas:
             cloud = make[tex](seed=args.seed, target=args.points, sigma=s)
-            row = {"texture": tex, **denoise_quality(cloud, ctx=ctx, scan_q=not args.no_scan_q)}
+            row = {"texture": tex, "num_dirs": prm.num_dirs, "window": prm.window, "k": prm.k,
+                   **denoise_quality(cloud, prm, ctx=ctx, scan_q=not args.no_scan_q)}
             print(json.dumps({"denoise": row}), flush=True)
     cloud = synth.body_cloud(seed=args.seed, target=args.points, sigma=args.sigmas[0])
-    for L in (4, 8):
-        print(json.dumps({"graph": graph_quality(cloud, fgbd.default_params(num_dirs=L), ctx=ctx)}), flush=True)
-    print(json.dumps({"geometry": geometry_quality(cloud, ctx=ctx)}), flush=True)
+    graphs = [fgbd.default_params(num_dirs=L) for L in (4, 8)] if not args.graph else [prm]
+    for g in graphs:
+        print(json.dumps({"graph": graph_quality(cloud, g, ctx=ctx)}), flush=True)
+    print(json.dumps({"geometry": geometry_quality(cloud, params=prm, ctx=ctx)}), flush=True)
     return 0
 
 

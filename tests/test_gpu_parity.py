@@ -202,7 +202,8 @@ def test_denoise_tiny(sigma):
 
 @pytest.mark.parametrize("kw", [dict(num_dirs=3, window=1, k=6), dict(fslr_kappa=0.0), dict(fslr_kappa=0.5),
                                 dict(q_max=1), dict(q_max=0), dict(num_dirs=16, k=12, patch=6),
-                                dict(patch_order=1), dict(patch_order=1, k=12, patch=5)])
+                                dict(patch_order=1), dict(patch_order=1, k=12, patch=5),
+                                dict(num_dirs=3, window=1, k=6, patch_order=1)])
 def test_denoise_variants(kw):
     c = synth.tiny_cloud(0)
     check_denoise(c.xyz, c.noisy, fgbd.default_params(bits=8, **kw))
