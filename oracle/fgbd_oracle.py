@@ -38,6 +38,9 @@ Readings
       same D points as the sorted one (the point and its first P neighbours), in
       increasing point index: the order the points have in the input, which is
       what an unsorted patch keeps.
+  R14 sigma_g = 0 (every edge of length 0, i.e. duplicate points only) takes
+      eq. 4 at its limit sigma_g -> 0+: a row's weight is shared evenly by its
+      entries at the row's smallest distance.
 """
 from __future__ import annotations
 
@@ -191,13 +194,26 @@ def slg_graph(xyz, bits: int, num_dirs: int, window: int, k: int):
 
 
 def knn_bruteforce(xyz, k: int):
-    """Exact K nearest neighbours by brute force, ordered by (dist2, index) and
-    excluding the point itself; O(N^2), small clouds only."""
+    """Exact K nearest neighbours by brute force (the textbook definition the
+    scan-line graph reduces to when the window covers every point, Sec. 2.2):
+    for each point i, every other point j ordered by (squared distance, index)
+    with a lexicographic sort, the first K kept, the rest of the row padded with
+    col = -1 and dist2 = 0.  Written independently of the scan-line graph's own
+    selection so that each checks the other.  O(N^2 log N); small clouds only."""
     g = np.asarray(xyz, np.int64)
     n = g.shape[0]
-    cand = np.tile(np.arange(n), (n, 1))
-    cand[np.arange(n), np.arange(n)] = -1
-    return _keep_nearest(g, cand, k)
+    col = np.full((n, k), -1, np.int64)
+    dist2 = np.zeros((n, k), np.int64)
+    for i in range(n):
+        others = np.array([j for j in range(n) if j != i], np.int64)
+        if others.size == 0:
+            continue
+        d2 = np.sum((g[others] - g[i]) ** 2, axis=1)
+        order = np.lexsort((others, d2))  # primary key d2, then the index
+        take = order[:k]
+        col[i, :take.size] = others[take]
+        dist2[i, :take.size] = d2[take]
+    return col, dist2
 
 
 def bandwidth(col, dist2) -> float:
@@ -213,8 +229,8 @@ def edge_weights(col, dist2, sigma_g: float) -> np.ndarray:
     """Row-normalised Gaussian weights p_ik = w_ik / deg_i with
     w_ij = exp(-|g_i - g_j|^2 / sigma_g^2) (eq. 4), written with the row's
     smallest squared distance subtracted in the exponent, which leaves the
-    ratio unchanged.  Padding entries get 0.  With sigma_g = 0 the weight is 1
-    at the smallest distance and 0 elsewhere."""
+    ratio unchanged.  Padding entries get 0.  With sigma_g = 0 (R14) the weight
+    is 1 at the smallest distance and 0 elsewhere before normalisation."""
     col = np.asarray(col)
     d2 = np.asarray(dist2, np.float64)
     valid = col >= 0

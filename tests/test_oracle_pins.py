@@ -96,6 +96,31 @@ def test_hand_example_b2():
 
 
 # ------------------------------------------------------------ neighbour graph
+def _check_truncation_golden():
+    gd = json.load(open(os.path.join(GOLD, "slg_truncation_b3.json")))
+    g = np.array(gd["xyz"])
+    keys = O.scan_keys(g, gd["bits"], gd["num_dirs"])
+    assert keys.tolist() == gd["keys"]
+    assert O.scan_orders(keys).tolist() == gd["orders"]
+    for k, ref in gd["slg"].items():
+        col, d2 = O.slg_graph(g, gd["bits"], gd["num_dirs"], gd["window"], int(k))
+        assert col.tolist() == ref["col"], f"slg col at K={k}"
+        assert d2.tolist() == ref["dist2"], f"slg dist2 at K={k}"
+    for k, ref in gd["knn"].items():
+        col, d2 = O.knn_bruteforce(g, int(k))
+        assert col.tolist() == ref["col"], f"knn col at K={k}"
+        assert d2.tolist() == ref["dist2"], f"knn dist2 at K={k}"
+        # a window covering every point turns the scan-line graph into exact KNN
+        col, d2 = O.slg_graph(g, gd["bits"], gd["num_dirs"], g.shape[0] - 1, int(k))
+        assert col.tolist() == ref["col"] and d2.tolist() == ref["dist2"]
+
+
+def test_hand_example_truncation():
+    """K smaller than the candidate set: the hand-worked rows (Sec. 2.2) where
+    the (distance, index) order decides which candidates are kept."""
+    _check_truncation_golden()
+
+
 
 @pytest.mark.parametrize("seed,n,bits,dup,L", [(3, 300, 4, 0, 3), (4, 500, 5, 40, 8), (5, 64, 2, 30, 16),
                                                (6, 2, 3, 0, 3), (7, 1, 3, 0, 3)])
@@ -107,6 +132,54 @@ def test_full_window_equals_bruteforce_knn(seed, n, bits, dup, L):
         bcol, bd2 = O.knn_bruteforce(g, k)
         assert np.array_equal(col, bcol)
         assert np.array_equal(d2, bd2)
+
+
+def _mutant_keep(xyz, cand, k, mode):
+    """A deliberately wrong version of the oracle's candidate selection, used
+    only to show that the graph pins catch such mistakes."""
+    g = np.asarray(xyz, np.int64)
+    n = g.shape[0]
+    col = np.full((n, k), -1, np.int64)
+    d2o = np.zeros((n, k), np.int64)
+    for i in range(n):
+        js = [int(j) for j in cand[i] if j >= 0]
+        if mode != "no_dedupe":
+            js = sorted(set(js))
+        axes = 2 if mode == "drop_z" else 3
+        rows = [(int(np.sum((g[j, :axes] - g[i, :axes]) ** 2)), j) for j in js]
+        if mode == "index_desc":
+            rows.sort(key=lambda t: (t[0], -t[1]))
+        else:
+            rows.sort()
+        if mode == "keep_last":
+            rows = rows[-k:]
+        for s, (d, j) in enumerate(rows[:k]):
+            col[i, s], d2o[i, s] = j, (int(np.sum((g[j] - g[i]) ** 2)))
+    return col, d2o
+
+
+def _graph_pins_pass() -> bool:
+    try:
+        _check_truncation_golden()
+        test_hand_example_b2()
+        rng = np.random.default_rng(41)
+        g = _rand_cloud(rng, 60, 3, dup=12)
+        for k in (1, 6, 13):
+            col, d2 = O.slg_graph(g, 3, 8, g.shape[0] - 1, k)
+            bcol, bd2 = O.knn_bruteforce(g, k)
+            assert np.array_equal(col, bcol) and np.array_equal(d2, bd2)
+    except AssertionError:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("mode", ["keep_last", "index_desc", "no_dedupe", "drop_z"])
+def test_graph_pins_catch_planted_selection_mistakes(mode, monkeypatch):
+    """Plant a mistake in the oracle's K-nearest selection (on the CPU) and
+    check that the pins above fail; with the real selection they pass."""
+    assert _graph_pins_pass()
+    monkeypatch.setattr(O.fgbd_oracle, "_keep_nearest", lambda xyz, cand, k: _mutant_keep(xyz, cand, k, mode))
+    assert not _graph_pins_pass()
 
 
 def _bruteforce_scan_neighbours(g, b):
@@ -182,6 +255,30 @@ def test_weights_closed_forms():
     assert col[1].tolist() == [0, 2]
     assert math.isclose(p[1, 0], 1.0 / (1.0 + math.exp(-3.0 / 2.25)), rel_tol=1e-14)
     assert math.isclose(p[1, 1], 1.0 / (1.0 + math.exp(3.0 / 2.25)), rel_tol=1e-14)
+
+
+def test_zero_bandwidth_reading():
+    """sigma_g = 0 happens when every edge has length 0 (a cloud of duplicate
+    points).  Eq. 4 is then read as its limit sigma_g -> 0+: the row's weight
+    goes uniformly to its nearest entries.  Pinned two ways: on an
+    all-duplicate cloud every row holds all other points with p = 1/(n-1), so
+    (T x)_i = x_i/2 + (sum_j x_j - x_i) / (2(n-1)); and on integer distances the
+    sigma_g = 0 weights equal the Gaussian ones at a tiny positive bandwidth."""
+    n = 7
+    g = np.tile(np.array([[3, 5, 1]]), (n, 1))
+    col, d2 = O.slg_graph(g, 3, 3, n - 1, 8)
+    assert O.bandwidth(col, d2) == 0.0
+    assert np.all((col >= 0).sum(axis=1) == n - 1)
+    p = O.edge_weights(col, d2, 0.0)
+    assert np.allclose(p[col >= 0], 1.0 / (n - 1), rtol=0, atol=1e-15)
+    x = np.random.default_rng(3).uniform(0, 255, (n, 3))
+    expect = 0.5 * x + (x.sum(axis=0) - x) / (2 * (n - 1))
+    assert np.allclose(O.filter_step(col, p, x), expect, rtol=0, atol=1e-12)
+    rng = np.random.default_rng(9)
+    g = _rand_cloud(rng, 200, 4, dup=30)
+    col, d2 = O.slg_graph(g, 4, 8, 4, 8)
+    lim = O.edge_weights(col, d2, 0.05)  # exp(-1/0.05^2) < 1e-170 for every unit of distance
+    assert np.allclose(O.edge_weights(col, d2, 0.0), lim, rtol=0, atol=1e-150)
 
 
 def _tiny_graph():
