@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 4
+#define FGBD_ABI_VERSION 5
 
 /* Largest number of clouds in one fgbd_denoise_batched call. */
 #define FGBD_MAX_BATCH 64
@@ -72,9 +72,13 @@ typedef enum {
 #define FGBD_ST_NO_PATCH 2    /* no point had P neighbours: sigma_est set to 0 (Sec. 2.3)    */
 #define FGBD_ST_BAD_OFFSETS 4 /* batched offsets did not start at 0, decreased, or exceeded
                                  n_total: they were clamped into range before use           */
-#define FGBD_ST_SWEEP_STALL 8 /* the sweeps run inside one launch waited over half a second
-                                 for each other (the GPU was shared with work that kept
-                                 blocks from starting): rgb_out is not valid               */
+#define FGBD_ST_SWEEP_STALL 8 /* the sweeps run inside one launch waited longer than their
+                                 bound (half a second by default, fgbd_set_sweep_wait) for
+                                 each other (the GPU was shared with work that kept blocks
+                                 from starting): the selection did not finish.  Every
+                                 point of rgb_out is still written, with either its input
+                                 colour or its filtered one, and q, loss, n_fslr and
+                                 sweeps of the result are not valid                          */
 
 /* Parameters of one run.  fgbd_default_params gives the values used for 1M-point
  * frames (b = 10, L = 8, w = 4, K = 8). */
@@ -348,6 +352,16 @@ fgbd_status fgbd_round_u8(fgbd_ctx ctx, const float *rgb, int64_t n, uint8_t *ou
  * NULL pointers, bad parameters, q out of range or overlapping buffers. */
 fgbd_status fgbd_smooth_geometry(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fgbd_params *params, int32_t q,
                                  float *xyz_out, fgbd_result *res, void *stream);
+
+/* Bound of each wait between two sweeps in the launch that runs the sweeps
+ * after the separate ones (see fgbd_schedule), in microseconds; negative
+ * restores the default of half a second.  A wait that reaches the bound ends
+ * that launch with FGBD_ST_SWEEP_STALL in the cloud's result instead of
+ * waiting on (FGBD_ST_SWEEP_STALL describes the output then).  0 gives up at
+ * the first wait that is not already over, which lets a test drive that path
+ * from the host.  A property of the context, for every later call.
+ * Errors: FGBD_E_INVALID for a NULL ctx or a bound above 10 s. */
+fgbd_status fgbd_set_sweep_wait(fgbd_ctx ctx, int64_t microseconds);
 
 /* Message for the last non-OK status returned on the calling thread ("" if
  * none).  Valid until the next call on this thread. */

@@ -75,6 +75,7 @@ struct fgbd_ctx_s {
   int hint_B = 0;
   int hint_recent[8] = {0};      // ring of the last counts read (max over clouds)
   int hint_count = 0;
+  int64_t wait_us = -1;  // fgbd_set_sweep_wait
 };
 
 namespace fgbd {
@@ -318,6 +319,7 @@ Run make_run(fgbd_ctx ctx, const Plan &pl, char *ws, const fgbd_params &prm, int
   r.stream = s;
   r.pf = ctx->profile ? pf : nullptr;
   r.sweep_launches = ctx->tune.sweep_launches;
+  r.wait_us = ctx->wait_us;
   return r;
 }
 
@@ -949,6 +951,13 @@ fgbd_status fgbd_round_u8(fgbd_ctx ctx, const float *rgb, int64_t n, uint8_t *ou
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   HIP_TRY(launch_round_u8(rgb, 3 * n, out, (hipStream_t)stream), "round launch");
+  return ok();
+}
+
+fgbd_status fgbd_set_sweep_wait(fgbd_ctx ctx, int64_t microseconds) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  if (microseconds > 10000000) return fail(FGBD_E_INVALID, "the wait bound is at most 10 s (10000000 us)");
+  ctx->wait_us = microseconds < 0 ? -1 : microseconds;
   return ok();
 }
 

@@ -481,7 +481,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
   while (!done && q <= q_last) {
     sweep_step<KT, false, false>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
     if (!grid_barrier(barrier, ++epoch, wait_limit, &s_flag)) {
+      // The selection cannot be completed: flag the cloud and leave every
+      // point of this block's share defined (its input colour).
       if (threadIdx.x == 0) atomicOr(&a.res[sb.s].status, FGBD_ST_SWEEP_STALL);
+      const Share sh = seg_share(sb, kBlock);
+      for (int64_t base = sh.first; base < sh.end; base += sh.step) {
+        const int64_t i = base + threadIdx.x;
+        if (i >= sh.end) continue;
+        rgb_out[3 * i + 0] = rgb_in[3 * i + 0];
+        rgb_out[3 * i + 1] = rgb_in[3 * i + 1];
+        rgb_out[3 * i + 2] = rgb_in[3 * i + 2];
+      }
       return;
     }
     last = a.ctrl + (q & 1) * B;
@@ -526,7 +536,7 @@ void sweep_kernel(int nb, hipStream_t st, const SweepArgs &a, int q, const int32
 }
 
 // Per device: blocks of k_sweep_tail<KT> resident at once, and ticks of the
-// constant-rate clock in half a second.
+// constant-rate clock in `us` microseconds (negative: half a second).
 constexpr int kMaxDevices = 64;
 template <int KT>
 int tail_capacity() {
@@ -544,25 +554,27 @@ int tail_capacity() {
   }
   return cap[dev];
 }
-long long half_second_ticks() {
-  static long long ticks[kMaxDevices];
+long long wait_ticks(int64_t us) {
+  static long long khz_of[kMaxDevices];  // 0: not yet queried
+  if (us < 0) us = 500000;
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 50000000ll;
-  if (ticks[dev] == 0) {
-    int khz = 0;
-    ticks[dev] = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0
-                     ? (long long)khz * 500
-                     : 50000000ll;
+  long long khz = 100000;  // 100 MHz when the rate cannot be read
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
+    if (khz_of[dev] == 0) {
+      int k = 0;
+      khz_of[dev] = hipDeviceGetAttribute(&k, hipDeviceAttributeWallClockRate, dev) == hipSuccess && k > 0 ? k : khz;
+    }
+    khz = khz_of[dev];
   }
-  return ticks[dev];
+  return (long long)(us > 10000000 ? 10000000 : us) * khz / 1000;
 }
 
 template <int KT>
 hipError_t tail_kernel(int nb, hipStream_t st, const SweepArgs &a, int q0, int q_last, uint32_t *barrier,
-                       const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf, const double *spread,
-                       const fgbd_result *noise, float *rgb_out, int32_t *hint) {
-  k_sweep_tail<KT><<<nb, kBlock, 0, st>>>(a, q0, q_last, barrier, half_second_ticks(), col, p, rgb_in, xbuf, spread,
-                                          noise, rgb_out, hint);
+                       long long ticks, const int32_t *col, const float *p, const float *rgb_in, float4 *xbuf,
+                       const double *spread, const fgbd_result *noise, float *rgb_out, int32_t *hint) {
+  k_sweep_tail<KT><<<nb, kBlock, 0, st>>>(a, q0, q_last, barrier, ticks, col, p, rgb_in, xbuf, spread, noise, rgb_out,
+                                          hint);
   return hipGetLastError();
 }
 
@@ -602,12 +614,12 @@ hipError_t launch_sweep_tail(const Run &r, const int32_t *col, const float *p, c
                              int q_limit, int q0, int q_last, float *rgb_out) {
   const SweepArgs a = sweep_args(r, nullptr, nullptr, res, select, q_limit);
   const int nb = r.pl.grid[kGridSweep];
-  using Fn = hipError_t (*)(int, hipStream_t, const SweepArgs &, int, int, uint32_t *, const int32_t *,
-                            const float *, const float *, float4 *, const double *, const fgbd_result *, float *,
-                            int32_t *);
+  using Fn = hipError_t (*)(int, hipStream_t, const SweepArgs &, int, int, uint32_t *, long long,
+                            const int32_t *, const float *, const float *, float4 *, const double *,
+                            const fgbd_result *, float *, int32_t *);
   static const Fn table[2] = {tail_kernel<0>, tail_kernel<8>};
-  return table[a.k == 8](nb, r.stream, a, q0, q_last, &r.b.segs->sweep_barrier, col, p, rgb_in, r.b.xbuf, spread,
-                         noise, rgb_out, r.hint);
+  return table[a.k == 8](nb, r.stream, a, q0, q_last, &r.b.segs->sweep_barrier, wait_ticks(r.wait_us), col, p,
+                         rgb_in, r.b.xbuf, spread, noise, rgb_out, r.hint);
 }
 
 hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, const fgbd_result *noise,

@@ -447,6 +447,9 @@ struct Run {
   Prof *pf;
   int32_t sweep_launches;  // sweeps enqueued as launches of their own
   int32_t *hint = nullptr;  // host-mapped: the finalising launch stores each cloud's sweep count here
+  // bound of each wait between sweeps in the in-launch sweep loop, in
+  // microseconds (negative: half a second)
+  int64_t wait_us = -1;
   // set: the first radix launch also does the call's setup (one cloud of
   // host-known size; saves a launch)
   bool fold_setup = false;

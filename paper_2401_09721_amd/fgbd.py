@@ -26,7 +26,7 @@ FGBD_ST_NO_PATCH = 2
 FGBD_ST_BAD_OFFSETS = 4
 FGBD_ST_SWEEP_STALL = 8
 NUM_KERNELS = 9
-ABI_VERSION = 4
+ABI_VERSION = 5
 MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
            "finalize")
@@ -36,6 +36,16 @@ class FgbdError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"fgbd status {status}: {message}")
         self.status = status
+
+
+class FgbdStallError(RuntimeError):
+    """A result carries FGBD_ST_SWEEP_STALL: the in-launch sweeps gave up
+    waiting for each other, so that cloud's output is not the method's."""
+
+    def __init__(self, clouds):
+        super().__init__(f"filter sweeps stalled for cloud(s) {clouds}: the output colours of those clouds are "
+                         "not the selected filter's (the GPU was shared with work that kept blocks from starting)")
+        self.clouds = clouds
 
 
 class Params(ctypes.Structure):
@@ -127,6 +137,7 @@ _SIGNATURES = {
     "fgbd_poly_filter_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_set_sweep_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "fgbd_last_error": (ctypes.c_char_p, []),
     "fgbd_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "fgbd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -235,6 +246,7 @@ class Context:
         torch = _torch()
         prm = as_params(params)
         xyz, rgb, offsets, batch, n = _batched_args(self, xyz, rgb, offsets)
+        _check_outputs(self, rgb, out, res, n, max(batch, 1))
         self.reserve(prm, n, max(batch, 1))
         out = torch.empty_like(rgb) if out is None else out
         res = new_result(self.device, max(batch, 1)) if res is None else res
@@ -242,6 +254,11 @@ class Context:
         _check(lib().fgbd_autotune(self.handle, _ptr(xyz), _ptr(rgb), n, _ptr(offsets), batch, ctypes.byref(prm),
                                    _ptr(out), _ptr(res), int(reps), ctypes.byref(sc), _stream(self)))
         return sc.as_dict()
+
+    def set_sweep_wait(self, microseconds: int) -> None:
+        """Bound of the waits between in-launch sweeps (negative: the default
+        half second); 0 makes such a launch give up at once (for tests)."""
+        _check(lib().fgbd_set_sweep_wait(self.handle, int(microseconds)))
 
     def profile(self, enable: bool) -> None:
         _check(lib().fgbd_profile_enable(self.handle, 1 if enable else 0))
@@ -298,22 +315,93 @@ def _need(t, dtype, shape_tail, name, device):
         raise ValueError(f"{name} must have shape [n, {', '.join(map(str, shape_tail))}]")
 
 
+def _need_out(t, dtype, shape, name, device):
+    """A caller-supplied output: a contiguous tensor of exactly this dtype,
+    shape and device (the library writes shape's bytes through its pointer)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != dtype or t.device != device or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _need_rows(t, n, name):
+    if int(t.shape[0]) != int(n):
+        raise ValueError(f"{name} has {int(t.shape[0])} rows, the graph has {int(n)}")
+
+
+def _need_res(res, count, device, name="res"):
+    """A caller-supplied result buffer: contiguous uint8 on the device holding
+    at least `count` fgbd_result records."""
+    torch = _torch()
+    if not isinstance(res, torch.Tensor) or res.dtype != torch.uint8 or res.device != device \
+            or not res.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous uint8 tensor on {device}")
+    if res.numel() < RESULT_BYTES * count:
+        raise ValueError(f"{name} holds fewer than {count} results ({RESULT_BYTES} bytes each)")
+
+
+def _need_graph(graph, device):
+    """col, dist2 and p of an SLGraph: contiguous [n, k] int32 / int32 / float32
+    tensors on the device."""
+    torch = _torch()
+    n, k = graph.n, graph.k
+    for name, t, dt in (("graph.col", graph.col, torch.int32), ("graph.dist2", graph.dist2, torch.int32),
+                        ("graph.p", graph.p, torch.float32)):
+        _need_out(t, dt, (n, k), name, device)
+
+
+def _need_disjoint(a, b, name_a, name_b):
+    if a is None or b is None or a.numel() == 0 or b.numel() == 0:
+        return
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    a1, b1 = a0 + a.numel() * a.element_size(), b0 + b.numel() * b.element_size()
+    if a0 < b1 and b0 < a1:
+        raise ValueError(f"{name_a} and {name_b} must not overlap")
+
+
 def new_result(device, count: int = 1) -> "object":
     """`count` zeroed device fgbd_result records (48 bytes each, as uint8)."""
     torch = _torch()
     return torch.zeros(RESULT_BYTES * count, dtype=torch.uint8, device=device)
 
 
-def read_results(res) -> list:
-    """Copy device fgbd_result records to the host (synchronises) and decode them."""
+def check_results(records: list) -> None:
+    """Raise FgbdStallError when a decoded result carries FGBD_ST_SWEEP_STALL;
+    warn on FGBD_ST_COORD_RANGE (coordinates outside the grid: the graph is
+    undefined) and FGBD_ST_BAD_OFFSETS (offsets were clamped)."""
+    import warnings
+
+    stalled = [i for i, r in enumerate(records) if r["status"] & FGBD_ST_SWEEP_STALL]
+    if stalled:
+        raise FgbdStallError(stalled)
+    rng = [i for i, r in enumerate(records) if r["status"] & FGBD_ST_COORD_RANGE]
+    if rng:
+        warnings.warn(f"coordinates outside 0..2^bits-1 in cloud(s) {rng}: their graphs are undefined",
+                      RuntimeWarning, stacklevel=3)
+    bad = [i for i, r in enumerate(records) if r["status"] & FGBD_ST_BAD_OFFSETS]
+    if bad:
+        warnings.warn("batched offsets were not a valid partition and were clamped into one", RuntimeWarning,
+                      stacklevel=3)
+
+
+def read_results(res, check: bool = True) -> list:
+    """Copy device fgbd_result records to the host (synchronises) and decode
+    them; with check, raise or warn on device-detected conditions
+    (check_results)."""
     raw = res.detach().cpu().numpy().tobytes()
     recs = np.frombuffer(raw, dtype=RESULT_DTYPE)
-    return [{name: rec[name].item() for name in RESULT_DTYPE.names} for rec in recs]
+    out = [{name: rec[name].item() for name in RESULT_DTYPE.names} for rec in recs]
+    if check:
+        check_results(out)
+    return out
 
 
-def read_result(res) -> dict:
+def read_result(res, check: bool = True) -> dict:
     """The first fgbd_result of a device buffer, decoded (synchronises)."""
-    return read_results(res[:RESULT_BYTES])[0]
+    return read_results(res[:RESULT_BYTES], check)[0]
 
 
 class SLGraph:
@@ -361,9 +449,9 @@ def estimate_noise(graph: SLGraph, rgb, params=None, ctx: Optional[Context] = No
     prm = as_params(params)
     ctx = ctx or default_context(rgb.device)
     _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    _need_graph(graph, ctx.device)
     n = graph.n
-    if rgb.shape[0] != n:
-        raise ValueError("rgb and graph sizes differ")
+    _need_rows(rgb, n, "rgb")
     ctx.reserve(prm, n)
     res = new_result(ctx.device)
     spread = torch.empty(n, dtype=torch.float64, device=ctx.device) if want_spread else None
@@ -382,7 +470,13 @@ def filter(graph: SLGraph, rgb, params=None, noise=None, spread=None, q_fixed: i
     prm = as_params(params)
     ctx = ctx or default_context(rgb.device)
     _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    _need_graph(graph, ctx.device)
     n = graph.n
+    _need_rows(rgb, n, "rgb")
+    if noise is not None:
+        _need_res(noise, 1, ctx.device, "noise")
+    if spread is not None:
+        _need_out(spread, torch.float64, (n,), "spread", ctx.device)
     ctx.reserve(prm, n)
     out = torch.empty_like(rgb)
     res = new_result(ctx.device)
@@ -402,12 +496,24 @@ def denoise(xyz, rgb, params=None, ctx: Optional[Context] = None, out=None, res=
     n = int(xyz.shape[0])
     if rgb.shape[0] != n:
         raise ValueError("xyz and rgb sizes differ")
+    _check_outputs(ctx, rgb, out, res, n, 1)
     ctx.reserve(prm, n)
     out = torch.empty_like(rgb) if out is None else out
     res = new_result(ctx.device) if res is None else res
     _check(lib().fgbd_denoise(ctx.handle, _ptr(xyz), _ptr(rgb), n, ctypes.byref(prm), _ptr(out), _ptr(res),
                               _stream(ctx, stream)))
     return out, res
+
+
+def _check_outputs(ctx, rgb, out, res, n, count):
+    """Caller-supplied colour output [n, 3] float32 (not overlapping the
+    input) and result buffer of `count` records."""
+    torch = _torch()
+    if out is not None:
+        _need_out(out, torch.float32, (n, 3), "out", ctx.device)
+        _need_disjoint(rgb, out, "rgb", "out")
+    if res is not None:
+        _need_res(res, count, ctx.device)
 
 
 def _batched_args(ctx, xyz, rgb, offsets):
@@ -433,11 +539,10 @@ def denoise_batched(xyz, rgb, offsets, params=None, ctx: Optional[Context] = Non
     prm = as_params(params)
     ctx = ctx or default_context(xyz.device)
     xyz, rgb, offsets, batch, n = _batched_args(ctx, xyz, rgb, offsets)
+    _check_outputs(ctx, rgb, out, res, n, max(batch, 1))
     ctx.reserve(prm, n, max(batch, 1))
     out = torch.empty_like(rgb) if out is None else out
     res = new_result(ctx.device, max(batch, 1)) if res is None else res
-    if res.numel() < RESULT_BYTES * max(batch, 1):
-        raise ValueError("res holds fewer than batch results")
     _check(lib().fgbd_denoise_batched(ctx.handle, _ptr(xyz), _ptr(rgb), n, _ptr(offsets), batch,
                                       ctypes.byref(prm), _ptr(out), _ptr(res), _stream(ctx, stream)))
     return out, res
@@ -453,11 +558,10 @@ def denoise_batched_fixed_q(xyz, rgb, offsets, q: int, params=None, ctx: Optiona
     prm = as_params(params)
     ctx = ctx or default_context(xyz.device)
     xyz, rgb, offsets, batch, n = _batched_args(ctx, xyz, rgb, offsets)
+    _check_outputs(ctx, rgb, out, res, n, max(batch, 1))
     ctx.reserve(prm, n, max(batch, 1))
     out = torch.empty_like(rgb) if out is None else out
     res = new_result(ctx.device, max(batch, 1)) if res is None else res
-    if res.numel() < RESULT_BYTES * max(batch, 1):
-        raise ValueError("res holds fewer than batch results")
     _check(lib().fgbd_denoise_batched_fixed_q(ctx.handle, _ptr(xyz), _ptr(rgb), n, _ptr(offsets), batch,
                                               ctypes.byref(prm), int(q), _ptr(out), _ptr(res),
                                               _stream(ctx, stream)))
@@ -473,6 +577,11 @@ def quantize(xyz, bits: int = 10, ctx: Optional[Context] = None, out=None, frame
     ctx = ctx or default_context(xyz.device)
     _need(xyz, torch.float32, (3,), "xyz", ctx.device)
     n = int(xyz.shape[0])
+    if out is not None:
+        _need_out(out, torch.int32, (n, 3), "out", ctx.device)
+        _need_disjoint(xyz, out, "xyz", "out")
+    if frame is not None:
+        _need_out(frame, torch.float64, (4,), "frame", ctx.device)
     out = torch.empty((n, 3), dtype=torch.int32, device=ctx.device) if out is None else out
     frame = torch.empty(4, dtype=torch.float64, device=ctx.device) if frame is None else frame
     _check(lib().fgbd_quantize(ctx.handle, _ptr(xyz), n, int(bits), _ptr(out), _ptr(frame), _stream(ctx, stream)))
@@ -487,6 +596,11 @@ def smooth_geometry(xyz, q: int, params=None, ctx: Optional[Context] = None, out
     ctx = ctx or default_context(xyz.device)
     _need(xyz, torch.int32, (3,), "xyz", ctx.device)
     n = int(xyz.shape[0])
+    if out is not None:
+        _need_out(out, torch.float32, (n, 3), "out", ctx.device)
+        _need_disjoint(xyz, out, "xyz", "out")
+    if res is not None:
+        _need_res(res, 1, ctx.device)
     ctx.reserve(prm, n)
     out = torch.empty((n, 3), dtype=torch.float32, device=ctx.device) if out is None else out
     res = new_result(ctx.device) if res is None else res
@@ -501,6 +615,9 @@ def round_u8(rgb, ctx: Optional[Context] = None, out=None, stream=None):
     ctx = ctx or default_context(rgb.device)
     _need(rgb, torch.float32, (3,), "rgb", ctx.device)
     n = int(rgb.shape[0])
+    if out is not None:
+        _need_out(out, torch.uint8, (n, 3), "out", ctx.device)
+        _need_disjoint(rgb, out, "rgb", "out")
     out = torch.empty((n, 3), dtype=torch.uint8, device=ctx.device) if out is None else out
     _check(lib().fgbd_round_u8(ctx.handle, _ptr(rgb), n, _ptr(out), _stream(ctx, stream)))
     return out
@@ -516,7 +633,9 @@ def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None,
         raise ValueError("coef must be a 1-D float32 device tensor")
     if sigma_g.dtype != torch.float64 or sigma_g.device != ctx.device or sigma_g.numel() != 1:
         raise ValueError("sigma_g must be a float64 device scalar")
+    _need_graph(graph, ctx.device)
     n, nc = graph.n, int(coef.numel())
+    _need_rows(x, n, "x")
     coef = coef.contiguous()
     sigma_g = sigma_g.contiguous()
     out = torch.empty_like(x)
@@ -534,7 +653,14 @@ def poly_filter_backward(graph: SLGraph, saved, coef, sigma_g, grad_out, ctx: Op
     ctx = ctx or default_context(grad_out.device)
     grad_out = grad_out.contiguous()
     _need(grad_out, torch.float32, (3,), "grad_out", ctx.device)
+    _need_graph(graph, ctx.device)
+    _need_rows(grad_out, graph.n, "grad_out")
+    if coef.dtype != torch.float32 or coef.device != ctx.device or coef.dim() != 1:
+        raise ValueError("coef must be a 1-D float32 device tensor")
+    if sigma_g.dtype != torch.float64 or sigma_g.device != ctx.device or sigma_g.numel() != 1:
+        raise ValueError("sigma_g must be a float64 device scalar")
     nc = int(coef.numel())
+    _need_out(saved, torch.float32, (nc, graph.n, 3), "saved", ctx.device)
     gx = torch.empty_like(grad_out)
     gc = torch.empty(nc, dtype=torch.float32, device=ctx.device)
     gsig = torch.empty((), dtype=torch.float64, device=ctx.device)

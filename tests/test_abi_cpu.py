@@ -42,7 +42,7 @@ def test_status_constants_match_header():
 
 
 def test_version_and_defaults():
-    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 4
+    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 5
     p = fgbd.default_params()
     assert (p.bits, p.num_dirs, p.window, p.k, p.patch, p.q_max) == (10, 8, 4, 8, 0, 32)
     assert p.fslr_kappa == 2.0 and p.sigma_g == 0.0
@@ -275,3 +275,118 @@ def test_profile_calls(ctx):
     assert lib.fgbd_profile_read(ctx, ms, nl, 9) == 0
     assert list(nl) == [0] * 9
     assert lib.fgbd_profile_read(ctx, ms, nl, 10) == fgbd.FGBD_E_INVALID
+
+
+# ------------------------------------------------ binding argument checks
+# The Python binding checks every caller-supplied tensor before it passes a
+# pointer to the library (a wrong row count or a short output buffer would make
+# the kernels read or write past it).  These run on a context whose "device" is
+# the CPU: every case below must raise before any library call.
+
+@pytest.fixture()
+def host_ctx():
+    import torch
+
+    c = fgbd.Context.__new__(fgbd.Context)
+    h = ctypes.c_void_p()
+    assert fgbd.lib().fgbd_create(ctypes.byref(h), 0) == 0
+    c.handle, c.device, c._ws, c._ws_bytes = h, torch.device("cpu"), None, 0
+    yield c
+    c.close()
+
+
+def _graph(n, k=8, p_shape=None):
+    import torch
+
+    col = torch.zeros((n, k), dtype=torch.int32)
+    d2 = torch.zeros((n, k), dtype=torch.int32)
+    p = torch.zeros(p_shape or (n, k), dtype=torch.float32)
+    return fgbd.SLGraph(col, d2, p, None)
+
+
+def test_binding_rejects_row_mismatch(host_ctx):
+    import torch
+
+    g = _graph(10)
+    with pytest.raises(ValueError, match="rows"):
+        fgbd.filter(g, torch.zeros((9, 3)), q_fixed=1, ctx=host_ctx)
+    with pytest.raises(ValueError, match="rows"):
+        fgbd.estimate_noise(g, torch.zeros((11, 3)), ctx=host_ctx)
+    coef = torch.ones(8)
+    sg = torch.ones((), dtype=torch.float64)
+    with pytest.raises(ValueError, match="rows"):
+        fgbd.poly_filter(g, torch.zeros((9, 3)), coef, sg, ctx=host_ctx)
+    saved = torch.zeros((8, 10, 3))
+    with pytest.raises(ValueError, match="rows"):
+        fgbd.poly_filter_backward(g, saved, coef, sg, torch.zeros((12, 3)), ctx=host_ctx)
+
+
+def test_binding_rejects_bad_graph_and_saved(host_ctx):
+    import torch
+
+    with pytest.raises(ValueError, match="graph.p"):
+        fgbd.estimate_noise(_graph(10, p_shape=(10, 7)), torch.zeros((10, 3)), ctx=host_ctx)
+    g = _graph(10)
+    coef, sg = torch.ones(8), torch.ones((), dtype=torch.float64)
+    for bad in (torch.zeros((7, 10, 3)), torch.zeros((8, 9, 3)), torch.zeros((8, 10, 3), dtype=torch.float64)):
+        with pytest.raises(ValueError, match="saved"):
+            fgbd.poly_filter_backward(g, bad, coef, sg, torch.zeros((10, 3)), ctx=host_ctx)
+    with pytest.raises(ValueError, match="coef"):
+        fgbd.poly_filter_backward(g, torch.zeros((8, 10, 3)), coef.double(), sg, torch.zeros((10, 3)),
+                                  ctx=host_ctx)
+    with pytest.raises(ValueError, match="spread"):
+        fgbd.filter(g, torch.zeros((10, 3)), noise=fgbd.new_result("cpu"), spread=torch.zeros(9, dtype=torch.float64),
+                    ctx=host_ctx)
+    with pytest.raises(ValueError, match="noise"):
+        fgbd.filter(g, torch.zeros((10, 3)), noise=torch.zeros(47, dtype=torch.uint8), ctx=host_ctx)
+
+
+def test_binding_rejects_bad_outputs(host_ctx):
+    import torch
+
+    n = 10
+    xyz = torch.zeros((n, 3), dtype=torch.int32)
+    rgb = torch.zeros((n, 3))
+    for out in (torch.zeros((n, 3), dtype=torch.float64), torch.zeros((n - 1, 3)), torch.zeros((n, 4)),
+                torch.zeros((3, n)).t()):
+        with pytest.raises(ValueError, match="out"):
+            fgbd.denoise(xyz, rgb, ctx=host_ctx, out=out)
+    with pytest.raises(ValueError, match="overlap"):
+        fgbd.denoise(xyz, rgb, ctx=host_ctx, out=rgb)
+    with pytest.raises(ValueError, match="res"):
+        fgbd.denoise(xyz, rgb, ctx=host_ctx, res=torch.zeros(fgbd.RESULT_BYTES - 1, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="res"):
+        fgbd.denoise(xyz, rgb, ctx=host_ctx, res=torch.zeros(fgbd.RESULT_BYTES, dtype=torch.int32))
+    offs = torch.tensor([0, 4, n], dtype=torch.int64)
+    with pytest.raises(ValueError, match="res"):
+        fgbd.denoise_batched(xyz, rgb, offs, ctx=host_ctx, res=fgbd.new_result("cpu", 1))
+    with pytest.raises(ValueError, match="out"):
+        fgbd.denoise_batched_fixed_q(xyz, rgb, offs, 2, ctx=host_ctx, out=torch.zeros((n + 1, 3)))
+    with pytest.raises(ValueError, match="out"):
+        fgbd.quantize(torch.zeros((n, 3)), ctx=host_ctx, out=torch.zeros((n, 3)))
+    with pytest.raises(ValueError, match="frame"):
+        fgbd.quantize(torch.zeros((n, 3)), ctx=host_ctx, frame=torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="out"):
+        fgbd.smooth_geometry(xyz, 2, ctx=host_ctx, out=torch.zeros((n, 2)))
+    with pytest.raises(ValueError, match="out"):
+        fgbd.round_u8(rgb, ctx=host_ctx, out=torch.zeros((n, 3), dtype=torch.int8))
+
+
+def test_sweep_wait_bound(ctx):
+    lib = fgbd.lib()
+    assert lib.fgbd_set_sweep_wait(None, 0) == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_set_sweep_wait(ctx, 10_000_001) == fgbd.FGBD_E_INVALID
+    for us in (-5, 0, 1, 500_000, 10_000_000):
+        assert lib.fgbd_set_sweep_wait(ctx, us) == fgbd.FGBD_OK
+
+
+def test_result_checks_raise_on_stall_and_warn():
+    rec = {name: 0 for name in fgbd.RESULT_DTYPE.names}
+    fgbd.check_results([dict(rec)])
+    with pytest.raises(fgbd.FgbdStallError) as e:
+        fgbd.check_results([dict(rec), dict(rec, status=fgbd.FGBD_ST_SWEEP_STALL | fgbd.FGBD_ST_NO_PATCH)])
+    assert e.value.clouds == [1]
+    with pytest.warns(RuntimeWarning, match="outside"):
+        fgbd.check_results([dict(rec, status=fgbd.FGBD_ST_COORD_RANGE)])
+    with pytest.warns(RuntimeWarning, match="clamped"):
+        fgbd.check_results([dict(rec, status=fgbd.FGBD_ST_BAD_OFFSETS)])

@@ -116,7 +116,8 @@ def test_bad_offsets_are_clamped_and_flagged():
     xyz, rgb = shape_cloud(51, 3000)
     n = len(xyz)
     bad = np.array([0, 500, 300, n + 100], np.int64)
-    out, results, _ = run_batched([(xyz, rgb)], prm, offsets=bad)
+    with pytest.warns(RuntimeWarning, match="clamped"):
+        out, results, _ = run_batched([(xyz, rgb)], prm, offsets=bad)
     for r in results:
         assert r["status"] & fgbd.FGBD_ST_BAD_OFFSETS
     used = np.array([0, 500, 500, n])

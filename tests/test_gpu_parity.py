@@ -90,7 +90,8 @@ def test_fixed_sigma_g():
 
 def test_coordinate_out_of_range_flagged():
     g = np.array([[0, 0, 0], [1, 0, 0], [1024, 0, 0], [2, 1, 0]], np.int32)
-    _, _, _, _, res = gpu_graph(g, fgbd.default_params(bits=10))
+    with pytest.warns(RuntimeWarning, match="outside"):
+        _, _, _, _, res = gpu_graph(g, fgbd.default_params(bits=10))
     assert res["status"] & fgbd.FGBD_ST_COORD_RANGE
 
 

@@ -191,3 +191,35 @@ def test_adaptive_launch_count_keeps_bits():
             seen.add(r["sweeps"])
     assert max(seen) - min(seen) >= 2, seen  # the counts really vary
     ctx.close()
+
+
+def test_wait_bound_zero_gives_up_with_defined_output():
+    """The in-launch sweep loop's wait bound set to 0 from the host: the loop
+    gives up at its first wait that is not already over, every block still
+    exits normally, the result carries FGBD_ST_SWEEP_STALL, the binding raises
+    on reading it, and every output row holds either the input colour or the
+    colour the unstalled call produces (no row is left unwritten).  The default
+    bound then gives the normal result again on the same context."""
+    prm = fgbd.default_params(bits=8)
+    xyz, rgb = cloud(81, 20000, 35.0)
+    ctx = fgbd.Context("cuda")
+    ref, rr = denoise_with(ctx, xyz, rgb, prm, 1024)  # every sweep a launch of its own: no waits
+    assert rr["sweeps"] >= 3, rr
+    ctx.set_sweep_wait(0)
+    ctx.set_schedule(1024, 1024, 1024, 1)
+    out = torch.full((len(xyz), 3), float("nan"), device="cuda")
+    out, res = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm, ctx=ctx, out=out)
+    torch.cuda.synchronize()
+    with pytest.raises(fgbd.FgbdStallError):
+        fgbd.read_result(res)
+    r = fgbd.read_result(res, check=False)
+    assert r["status"] & fgbd.FGBD_ST_SWEEP_STALL
+    o = out.cpu().numpy()
+    as_input = np.all(o == rgb, axis=1)
+    as_filtered = np.all(o == ref, axis=1)
+    assert np.all(as_input | as_filtered)
+    assert as_input.sum() > 0
+    ctx.set_sweep_wait(-1)
+    out2, r2 = denoise_with(ctx, xyz, rgb, prm, 1)
+    assert np.array_equal(out2, ref) and r2 == rr
+    ctx.close()
