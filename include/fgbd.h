@@ -187,6 +187,29 @@ fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fg
 fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb, const fgbd_params *params,
                                 fgbd_result *res, double *patch_spread, float *eig3, void *stream);
 
+/* fgbd_estimate_noise for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, checks, launches and results (bit for bit) as
+ * fgbd_estimate_noise, except:
+ *   - its scratch (segment table, patch-moment and edge-length accumulators)
+ *     is one fixed array of FGBD_NOALLOC_SCRATCH_BYTES inside the library,
+ *     one copy per GPU, held from the library's load until the process ends;
+ *     the context's workspace is neither used nor allocated, and the call
+ *     allocates nothing (no device memory, no events: per-kernel timing is
+ *     off for it).  Each call clears the accumulators it uses before use.
+ *   - patch_spread is required when n > 0 (there is no workspace to hold the
+ *     spreads otherwise).
+ *   - Every call on one GPU shares that GPU's array, which keeps the last
+ *     call's contents: calls that overlap in time on one GPU (other streams,
+ *     contexts or threads) race on it and give wrong results; serialise them.
+ *   - FGBD_E_WORKSPACE if the parameters need more scratch than the array
+ *     holds (the need depends on the patch size only and is at most about
+ *     350 KB, for k = patch = 32); FGBD_E_UNSUPPORTED for devices >= 64. */
+#define FGBD_NOALLOC_SCRATCH_BYTES (512 * 1024)
+fgbd_status fgbd_estimate_noise_noalloc(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb,
+                                        const fgbd_params *params, fgbd_result *res, double *patch_spread,
+                                        float *eig3, void *stream);
+
 /* Filter selection (FSLR, Sec. 2.4, eq. 6) and the low-pass filter (eq. 5).
  * With `noise` non-NULL: x_0 = rgb_in, x_q = T x_{q-1}; E(q) is the mean over
  * the FSLR subset and the channels of y^2 - x_q^2; sweeps stop at the first q

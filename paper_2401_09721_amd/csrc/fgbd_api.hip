@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "fgbd_internal.h"
@@ -388,6 +389,88 @@ fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const i
   return FGBD_OK;
 }
 
+// ------------------------------------------------ no-allocation variant
+// Scratch of fgbd_estimate_noise_noalloc: one fixed array in the library,
+// one copy per GPU at that GPU's own address, held until the process ends.
+// In host code the name `scratch` is only a stand-in for the symbol, not a
+// device address: it is never passed to a kernel or a copy.  The device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current, and kept in g_scratch_dev.
+constexpr size_t kNoAllocBytes = FGBD_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) static unsigned char scratch[kNoAllocBytes];
+constexpr int kNoAllocDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[kNoAllocDevices] = {};
+
+// The device address of this GPU's scratch array (the caller has made the
+// device current).
+fgbd_status scratch_address(int device, char **out) {
+  if (device < 0 || device >= kNoAllocDevices)
+    return fail(FGBD_E_UNSUPPORTED, "device %d: the no-allocation calls cover devices 0..%d", device,
+                kNoAllocDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(FGBD_E_HIP, "scratch array has no aligned device address");
+    g_scratch_dev[device] = (char *)ptr;
+  }
+  *out = g_scratch_dev[device];
+  return FGBD_OK;
+}
+
+// The buffers the noise estimate uses (segment table, edge-length and moment
+// accumulators, the sweep sums the setup launch clears) packed from offset 0;
+// every other buffer of the plan is absent.
+Plan noise_scratch_plan(int64_t n, const fgbd_params &p, const Tune &tune) {
+  Plan pl = make_plan(n, 1, p, tune);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  pl.off_segs = take(sizeof(Segs));
+  pl.off_edge_acc = take((size_t)pl.B * kEdgeSlots * kEdgeVals * 8);
+  pl.off_noise_acc = take((size_t)pl.B * pl.E1 * kNoiseSlots * 8);
+  pl.off_ctrl = take((size_t)2 * pl.B * sizeof(SweepCtrl));
+  pl.off_sweep_sums = take((size_t)3 * pl.B * kSweepSlots * kSweepParts * 8);
+  pl.total = off;
+  return pl;
+}
+
+// Argument checks of fgbd_estimate_noise (shared by its no-allocation variant).
+fgbd_status check_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb, const fgbd_params *params,
+                                 const fgbd_result *res) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  fgbd_status st = check_params(params);
+  if (st != FGBD_OK) return st;
+  if (!g) return fail(FGBD_E_INVALID, "graph is NULL");
+  if ((st = check_n(g->n)) != FGBD_OK) return st;
+  if (g->k != params->k) return fail(FGBD_E_INVALID, "graph k (%d) != params k (%d)", g->k, params->k);
+  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
+  if (g->n > 0 && (!rgb || !g->col)) return fail(FGBD_E_INVALID, "NULL colour or graph array");
+  return FGBD_OK;
+}
+
+// The launches of fgbd_estimate_noise on a prepared run: the setup launch
+// (segment table, cleared moment accumulators), the patch statistics and the
+// noise solve.  spread: where the FSLR spreads go (never NULL).
+fgbd_status run_estimate_noise(const Run &r, const fgbd_graph *g, const float *rgb, fgbd_result *res, double *spread,
+                               float *eig3) {
+  const int64_t n = g->n;
+  if (n == 0) {
+    HIP_TRY(launch_setup(r, nullptr, 0, res, 2), "setup launch");
+    return ok();
+  }
+  // one cloud of host-known size: the kernels do not read the segment table;
+  // the setup launch clears the moment accumulators
+  HIP_TRY(launch_setup(r, nullptr, n, nullptr, 0), "setup launch");
+  const fgbd_status st = run_noise(r, g->col, rgb, spread, eig3, res);
+  return st != FGBD_OK ? st : ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -493,32 +576,17 @@ fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fg
 
 fgbd_status fgbd_estimate_noise(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb, const fgbd_params *params,
                                 fgbd_result *res, double *patch_spread, float *eig3, void *stream) {
-  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
-  fgbd_status st = check_params(params);
+  fgbd_status st = check_estimate_noise(ctx, g, rgb, params, res);
   if (st != FGBD_OK) return st;
-  if (!g) return fail(FGBD_E_INVALID, "graph is NULL");
-  if ((st = check_n(g->n)) != FGBD_OK) return st;
-  if (g->k != params->k) return fail(FGBD_E_INVALID, "graph k (%d) != params k (%d)", g->k, params->k);
-  if (!res) return fail(FGBD_E_INVALID, "res is NULL");
-  const int64_t n = g->n;
-  if (n > 0 && (!rgb || !g->col)) return fail(FGBD_E_INVALID, "NULL colour or graph array");
-  hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  const Plan pl = make_plan(n, 1, *params, ctx->tune);
+  const Plan pl = make_plan(g->n, 1, *params, ctx->tune);
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
   EventProf ep(ctx, s);
-  const Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
-  if (n == 0) {
-    HIP_TRY(launch_setup(r, nullptr, 0, res, 2), "setup launch");
-    return ok();
-  }
-  // one cloud of host-known size: the kernels do not read the segment table;
-  // the setup launch clears the moment accumulators
-  HIP_TRY(launch_setup(r, nullptr, n, nullptr, 0), "setup launch");
-  if ((st = run_noise(r, g->col, rgb, patch_spread ? patch_spread : r.b.spread, eig3, res)) != FGBD_OK) return st;
-  return ok();
+  const Run r = make_run(ctx, pl, ws, *params, g->n, s, &ep);
+  return run_estimate_noise(r, g, rgb, res, patch_spread ? patch_spread : r.b.spread, eig3);
 }
 
 fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, const fgbd_params *params,
@@ -986,6 +1054,32 @@ fgbd_status fgbd_profile_read(fgbd_ctx ctx, double *ms, int64_t *launches, int32
     ctx->launches[i] = 0;
   }
   return ok();
+}
+
+fgbd_status fgbd_estimate_noise_noalloc(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb,
+                                        const fgbd_params *params, fgbd_result *res, double *patch_spread,
+                                        float *eig3, void *stream) {
+  fgbd_status st = check_estimate_noise(ctx, g, rgb, params, res);
+  if (st != FGBD_OK) return st;
+  if (g->n > 0 && !patch_spread) return fail(FGBD_E_INVALID, "patch_spread is required by the no-allocation call");
+  const Plan pl = noise_scratch_plan(g->n, *params, ctx->tune);
+  if (pl.total > kNoAllocBytes)
+    return fail(FGBD_E_WORKSPACE, "these parameters need %zu bytes of scratch, the array holds %zu", pl.total,
+                kNoAllocBytes);
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  char *ws = nullptr;
+  if ((st = scratch_address(ctx->device, &ws)) != FGBD_OK) return st;
+  Run r = make_run(ctx, pl, ws, *params, g->n, (hipStream_t)stream, nullptr);
+  // only the packed buffers exist
+  r.b.items_a = r.b.items_b = nullptr;
+  r.b.hist = r.b.rank = nullptr;
+  r.b.digits = nullptr;
+  r.b.col = r.b.dist2 = nullptr;
+  r.b.p = nullptr;
+  r.b.spread = nullptr;
+  r.b.xbuf = nullptr;
+  return run_estimate_noise(r, g, rgb, res, patch_spread, eig3);
 }
 
 }  // extern "C"

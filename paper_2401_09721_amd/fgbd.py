@@ -108,6 +108,9 @@ _SIGNATURES = {
     "fgbd_estimate_noise": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p,
                                            ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "fgbd_estimate_noise_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p,
+                                                   ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.POINTER(Params),
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p]),
@@ -460,6 +463,32 @@ def estimate_noise(graph: SLGraph, rgb, params=None, ctx: Optional[Context] = No
     _check(lib().fgbd_estimate_noise(ctx.handle, ctypes.byref(gs), _ptr(rgb), ctypes.byref(prm), _ptr(res),
                                      _ptr(spread), _ptr(eig3), _stream(ctx, stream)))
     return res, spread, eig3
+
+
+def estimate_noise_noalloc(graph: SLGraph, rgb, spread, params=None, ctx: Optional[Context] = None, res=None,
+                           eig3=None, stream=None):
+    """NE-GBP through the call that allocates nothing on the device: its
+    scratch is the library's fixed per-GPU array, so the caller passes every
+    output (spread: float64 [n]; res: a result buffer; eig3: optional
+    float32 [n, 3]).  Calls that overlap on one GPU race on that array.
+    Returns res."""
+    torch = _torch()
+    prm = as_params(params)
+    ctx = ctx or default_context(rgb.device)
+    _need(rgb, torch.float32, (3,), "rgb", ctx.device)
+    _need_graph(graph, ctx.device)
+    n = graph.n
+    _need_rows(rgb, n, "rgb")
+    _need_out(spread, torch.float64, (n,), "spread", ctx.device)
+    if eig3 is not None:
+        _need_out(eig3, torch.float32, (n, 3), "eig3", ctx.device)
+    if res is None:
+        raise ValueError("res is required (the call allocates nothing)")
+    _need_res(res, 1, ctx.device)
+    gs = graph.c_struct()
+    _check(lib().fgbd_estimate_noise_noalloc(ctx.handle, ctypes.byref(gs), _ptr(rgb), ctypes.byref(prm), _ptr(res),
+                                             _ptr(spread), _ptr(eig3), _stream(ctx, stream)))
+    return res
 
 
 def filter(graph: SLGraph, rgb, params=None, noise=None, spread=None, q_fixed: int = 0,

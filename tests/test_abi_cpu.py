@@ -390,3 +390,26 @@ def test_result_checks_raise_on_stall_and_warn():
         fgbd.check_results([dict(rec, status=fgbd.FGBD_ST_COORD_RANGE)])
     with pytest.warns(RuntimeWarning, match="clamped"):
         fgbd.check_results([dict(rec, status=fgbd.FGBD_ST_BAD_OFFSETS)])
+
+
+def test_noalloc_noise_call_errors(ctx):
+    """The no-allocation noise call checks its arguments like
+    fgbd_estimate_noise and also requires the spread output; a NULL one is an
+    error before any device work."""
+    lib = fgbd.lib()
+    p = fgbd.default_params()
+    E = fgbd.FGBD_E_INVALID
+    g = fgbd.Graph(0x1000, 0x2000, 0x3000, 10, 8, 0)
+    bad_k = fgbd.Graph(0x1000, 0x2000, 0x3000, 10, 6, 0)
+    call = lib.fgbd_estimate_noise_noalloc
+    assert call(None, ctypes.byref(g), FAKE, ctypes.byref(p), FAKE, FAKE, None, None) == E
+    assert call(ctx, None, FAKE, ctypes.byref(p), FAKE, FAKE, None, None) == E
+    assert call(ctx, ctypes.byref(bad_k), FAKE, ctypes.byref(p), FAKE, FAKE, None, None) == E
+    assert call(ctx, ctypes.byref(g), None, ctypes.byref(p), FAKE, FAKE, None, None) == E
+    assert call(ctx, ctypes.byref(g), FAKE, ctypes.byref(p), None, FAKE, None, None) == E
+    assert call(ctx, ctypes.byref(g), FAKE, ctypes.byref(p), FAKE, None, None, None) == E
+    assert "patch_spread" in lib.fgbd_last_error().decode()
+    bad = fgbd.default_params(k=40)
+    assert call(ctx, ctypes.byref(g), FAKE, ctypes.byref(bad), FAKE, FAKE, None, None) == E
+    hdr = open(HEADER).read()
+    assert int(eval(re.search(r"#define FGBD_NOALLOC_SCRATCH_BYTES \(([^)]*)\)", hdr).group(1))) == 512 * 1024
