@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 5
+#define FGBD_ABI_VERSION 6
 
 /* Largest number of clouds in one fgbd_denoise_batched call. */
 #define FGBD_MAX_BATCH 64
@@ -322,19 +322,41 @@ fgbd_status fgbd_autotune(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in,
 fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, const float *coef, int32_t ncoef,
                              const double *sigma_g, float *out, float *saved, void *stream);
 
+/* Transpose of a graph's directed edges, the structure the adjoint of eq. 5
+ * pulls along (T^T).  For every point j, the ids e = i * k + slot of the
+ * edges with col[i][slot] == j, in increasing order:
+ *   edge[off[j]] .. edge[off[j + 1] - 1],  off[0] = 0, off[n] = edges.
+ * The graph is fixed while a filter's coefficients and bandwidth are fitted,
+ * so the transpose is built once (fgbd_graph_transpose) and passed to every
+ * backward call.  Caller-owned device arrays. */
+typedef struct {
+  int32_t *off;  /* device int32 [n + 1] */
+  int32_t *edge; /* device int32 [n * k] (the first off[n] entries are used) */
+  int64_t n;
+  int32_t k;
+  int32_t pad_;
+} fgbd_transpose;
+
+/* Build t from the graph's col (t->n == g->n, t->k == g->k, n * k < 2^31).
+ * Deterministic (rows are sorted after their atomic placement).  Uses the
+ * context workspace (4 bytes per point).  Errors: FGBD_E_INVALID for NULL
+ * pointers or mismatched shapes. */
+fgbd_status fgbd_graph_transpose(fgbd_ctx ctx, const fgbd_graph *g, const fgbd_transpose *t, void *stream);
+
 /* Hand-written adjoint of fgbd_poly_filter for L = <grad_out, out>:
  *   grad_x = z_0 with z_{ncoef-1} = c_{ncoef-1} grad_out and
- *            z_k = c_k grad_out + T^T z_{k+1} (T^T from an explicit transpose
- *            of the directed graph, rows in source order);
+ *            z_k = c_k grad_out + T^T z_{k+1} (T^T along the transpose t);
  *   grad_coef[k] = <grad_out, x_k>;
  *   grad_sigma_g = sum_{m>=1} <z_m, (dT/dsigma_g) x_{m-1}>.
+ *   t: the graph's transpose from fgbd_graph_transpose, or NULL to build one
+ *   in the workspace for this call;
  *   saved: the iterates written by fgbd_poly_filter with the same g, coef,
  *   ncoef and sigma_g;  grad_out, grad_x: float32 [n][3] (must not overlap);
  *   grad_coef: optional device float32 [ncoef];  grad_sigma_g: optional device
  *   double.  Scalar gradients are reduced in a fixed order (deterministic). */
-fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const float *saved, const float *coef,
-                                      int32_t ncoef, const double *sigma_g, const float *grad_out, float *grad_x,
-                                      float *grad_coef, double *grad_sigma_g, void *stream);
+fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const fgbd_transpose *t, const float *saved,
+                                      const float *coef, int32_t ncoef, const double *sigma_g, const float *grad_out,
+                                      float *grad_x, float *grad_coef, double *grad_sigma_g, void *stream);
 
 /* Float coordinates onto the 2^bits integer grid that the scan-line graph
  * takes (Sec. 2.2 assumes voxelised integer coordinates).  One scale for the

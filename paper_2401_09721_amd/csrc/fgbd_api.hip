@@ -971,23 +971,45 @@ fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, 
   return ok();
 }
 
-fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const float *saved, const float *coef,
-                                      int32_t ncoef, const double *sigma_g, const float *grad_out, float *grad_x,
-                                      float *grad_coef, double *grad_sigma_g, void *stream) {
+fgbd_status fgbd_graph_transpose(fgbd_ctx ctx, const fgbd_graph *g, const fgbd_transpose *t, void *stream) {
+  if (!ctx) return fail(FGBD_E_INVALID, "ctx is NULL");
+  if (!g || !t) return fail(FGBD_E_INVALID, "graph or transpose is NULL");
+  fgbd_status st = check_n(g->n);
+  if (st != FGBD_OK) return st;
+  if (g->k < 1 || g->k > kMaxK) return fail(FGBD_E_INVALID, "graph k must be in 1..%d", kMaxK);
+  if (t->n != g->n || t->k != g->k) return fail(FGBD_E_INVALID, "transpose shape (%lld, %d) != graph (%lld, %d)",
+                                                 (long long)t->n, t->k, (long long)g->n, g->k);
+  if (!t->off) return fail(FGBD_E_INVALID, "transpose off is NULL");
+  if (g->n > 0 && (!g->col || !t->edge)) return fail(FGBD_E_INVALID, "NULL graph or transpose array");
+  if (g->n * (int64_t)g->k > (int64_t)0x7fffffff) return fail(FGBD_E_INVALID, "n * k must be below 2^31");
+  DeviceGuard dg(ctx->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  char *ws = nullptr;
+  if ((st = get_workspace(ctx, transpose_workspace(g->n), &ws)) != FGBD_OK) return st;
+  HIP_TRY(launch_transpose(g->n, g->k, g->col, t->off, t->edge, ws, (hipStream_t)stream), "transpose launch");
+  return ok();
+}
+
+fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const fgbd_transpose *t, const float *saved,
+                                      const float *coef, int32_t ncoef, const double *sigma_g, const float *grad_out,
+                                      float *grad_x, float *grad_coef, double *grad_sigma_g, void *stream) {
   fgbd_status st = check_poly(ctx, g, ncoef, sigma_g);
   if (st != FGBD_OK) return st;
   const int64_t n = g->n;
   if (n > 0 && (!saved || !coef || !grad_out || !grad_x)) return fail(FGBD_E_INVALID, "NULL input or output array");
   if (n > 0 && overlap(grad_out, (size_t)n * 12, grad_x, (size_t)n * 12))
     return fail(FGBD_E_INVALID, "grad_out and grad_x overlap");
+  if (t && (t->n != n || t->k != g->k || !t->off || (n > 0 && !t->edge)))
+    return fail(FGBD_E_INVALID, "transpose does not match the graph");
+  if (n * (int64_t)g->k > (int64_t)0x7fffffff) return fail(FGBD_E_INVALID, "n * k must be below 2^31");
   if (n == 0) return ok();
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   char *ws = nullptr;
   if ((st = get_workspace(ctx, poly_workspace(n, g->k, ncoef, kMaxGrid), &ws)) != FGBD_OK) return st;
-  HIP_TRY(launch_poly_backward(n, g->k, g->col, g->dist2, saved, coef, ncoef, sigma_g, grad_out, grad_x, grad_coef,
-                               grad_sigma_g, ws, s),
+  HIP_TRY(launch_poly_backward(n, g->k, g->col, g->dist2, t ? t->off : nullptr, t ? t->edge : nullptr, saved, coef,
+                               ncoef, sigma_g, grad_out, grad_x, grad_coef, grad_sigma_g, ws, s),
           "poly filter backward launch");
   return ok();
 }

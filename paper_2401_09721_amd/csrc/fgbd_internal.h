@@ -519,8 +519,14 @@ hipError_t launch_coords_f32(const int32_t *g, int64_t m, float *out, hipStream_
 hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *x,
                                const float *coef, int ncoef, const double *sigma_g, float *out, float *saved,
                                char *ws, hipStream_t s);
-hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *saved,
-                                const float *coef, int ncoef, const double *sigma_g, const float *grad_out,
-                                float *grad_x, float *grad_coef, double *grad_sigma, char *ws, hipStream_t s);
+hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const int32_t *t_off,
+                                const int32_t *t_edge, const float *saved, const float *coef, int ncoef,
+                                const double *sigma_g, const float *grad_out, float *grad_x, float *grad_coef,
+                                double *grad_sigma, char *ws, hipStream_t s);
+// Transpose of a graph's directed edges (off: [n + 1], edge: [n * k]); ws:
+// at least transpose_workspace(n) bytes.
+size_t transpose_workspace(int64_t n);
+hipError_t launch_transpose(int64_t n, int k, const int32_t *col, int32_t *off, int32_t *edge, char *ws,
+                            hipStream_t s);
 
 }  // namespace fgbd

@@ -4,43 +4,68 @@
 // graph's squared distances and a bandwidth sigma_g held in device memory
 // (eq. 4), so sigma_g can be a trained parameter.  c = e_q gives eq. 5.
 //
-// Forward: x_0 = x, x_k = T x_{k-1}; all iterates x_0..x_{n-1} are saved.
+// Forward: x_0 = x, x_k = T x_{k-1}; all iterates x_0..x_{n-1} are saved, and
+// the last sweep also forms out from them.
 // Backward, for L = <g, out>:
 //   dL/dc_k     = <g, x_k>
 //   z_{n-1} = c_{n-1} g,  z_k = c_k g + T^T z_{k+1},  dL/dx = z_0
 //   dL/dsigma_g = sum_{m=1}^{n-1} <z_m, (dT/dsigma_g) x_{m-1}>, where
 //     dT/dsigma_g = (1/2) dP/dsigma_g and dp_ik/dsigma_g = p_ik (a_ik - sum_k' p_ik' a_ik'),
 //     a_ik = 2 (d2_ik - d2_i0) / sigma_g^3 (the row shift cancels).
-// T^T uses an explicit transpose of the directed graph: for every point j
-// the edges (i, k) with col_ik = j, counted with integer atomics, placed, and
-// then sorted by source within each row so every sum has a fixed order.
-// Scalar gradients are FP64 per-block partials summed in block order by a
-// one-block kernel.  No floating-point atomics anywhere.
+// T^T pulls along an explicit transpose of the directed graph: for every point
+// j the edge ids e = i * K + slot with col[e] = j, in increasing order (built
+// once per graph by fgbd_graph_transpose, or per call).  One launch per
+// backward step computes z_{m-1}, the step's sigma_g term and the
+// coefficient products <g, x_{m-1}> together.  Scalar gradients are FP64
+// per-block partials summed in block order by a one-block kernel.  No
+// floating-point atomics anywhere, so every result is deterministic.
 #include "fgbd_internal.h"
 
 namespace fgbd {
 
 namespace {
 
-// Row-normalised weights from squared distances and a device bandwidth.
-__global__ __launch_bounds__(kBlock) void k_poly_weights(int32_t n, int32_t K, const int32_t *__restrict__ col,
+// Row-normalised weights of eq. 4 from squared distances and a device
+// bandwidth, with the graph builder's row_weights (the same bits as the
+// weights fgbd_build_slg stores for that bandwidth).
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_poly_weights(int32_t n, int32_t k_rt, const int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ dist2,
                                                          const double *__restrict__ sigma_g,
                                                          float *__restrict__ p) {
+  __shared__ double s_exp[kExpTable];
+  const int K = KT > 0 ? KT : k_rt;
   const double sg = *sigma_g;
-  const double inv = sg > 0.0 ? 1.0 / (sg * sg) : 0.0;
+  fill_exp_table(sg, s_exp);
+  __syncthreads();
+  constexpr int KB = KT > 0 ? KT : kMaxK;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    const int32_t *cr = col + i * K;
-    const int32_t *dr = dist2 + i * K;
-    const int d0 = dr[0];
-    double s = 0.0;
-    for (int k = 0; k < K; ++k)
-      if (cr[k] >= 0) s += sg > 0.0 ? exp(-(double)(dr[k] - d0) * inv) : (dr[k] == d0 ? 1.0 : 0.0);
-    const double rs = s > 0.0 ? 1.0 / s : 0.0;
-    for (int k = 0; k < K; ++k) {
-      double w = 0.0;
-      if (cr[k] >= 0) w = sg > 0.0 ? exp(-(double)(dr[k] - d0) * inv) : (dr[k] == d0 ? 1.0 : 0.0);
-      p[i * K + k] = (float)(w * rs);
+    int cv[KB], dv[KB];
+    if (KT == 8) {
+      const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
+      const int4 *dr = reinterpret_cast<const int4 *>(dist2 + i * 8);
+      const int4 c0 = cr[0], c1 = cr[1], e0 = dr[0], e1 = dr[1];
+      cv[0] = c0.x; cv[1] = c0.y; cv[2] = c0.z; cv[3] = c0.w;
+      cv[4] = c1.x; cv[5] = c1.y; cv[6] = c1.z; cv[7] = c1.w;
+      dv[0] = e0.x; dv[1] = e0.y; dv[2] = e0.z; dv[3] = e0.w;
+      dv[4] = e1.x; dv[5] = e1.y; dv[6] = e1.z; dv[7] = e1.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        cv[k] = k < K ? col[i * K + k] : -1;
+        dv[k] = k < K ? dist2[i * K + k] : 0;
+      }
+    }
+    float pw[KB];
+    row_weights<KB>(cv, dv, sg, s_exp, pw);
+    if (KT == 8) {
+      float4 *pr = reinterpret_cast<float4 *>(p + i * 8);
+      pr[0] = make_float4(pw[0], pw[1], pw[2], pw[3]);
+      pr[1] = make_float4(pw[4], pw[5], pw[6], pw[7]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        if (k < K) p[i * K + k] = pw[k];
     }
   }
 }
@@ -58,30 +83,54 @@ __global__ __launch_bounds__(kBlock) void k_indegree(int32_t n, int32_t K, const
   }
 }
 
-// Exclusive scan of n int32 counts into offsets[0..n] (one block of 1024
-// threads, chunks of 8 per thread with a running carry).
-__global__ __launch_bounds__(1024) void k_scan_counts(int32_t n, const int32_t *__restrict__ cnt,
-                                                      int32_t *__restrict__ off) {
+// Exclusive scan of n counts into off[0..n] in three launches: each block
+// sums one chunk of kScanChunk counts, one block scans the chunk sums, each
+// block rescans its chunk from its chunk's offset.
+constexpr int kScanPer = 8;
+constexpr int kScanChunkLen = kBlock * kScanPer;
+__global__ __launch_bounds__(kBlock) void k_chunk_sums(int32_t n, const int32_t *__restrict__ cnt,
+                                                       int32_t *__restrict__ sums) {
+  __shared__ uint32_t s_tmp[4];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunkLen + (int64_t)threadIdx.x * kScanPer;
+  uint32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) s += i0 + j < n ? (uint32_t)cnt[i0 + j] : 0u;
+  uint32_t tot;
+  (void)block_exclusive_scan_256(s, s_tmp, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = (int32_t)tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t m, int32_t *__restrict__ sums, int32_t *__restrict__ total) {
   __shared__ uint32_t s_tmp[16];
   uint32_t carry = 0;
-  for (int64_t base = 0; base < n; base += 1024 * 8) {
-    const int64_t i0 = base + (int64_t)threadIdx.x * 8;
-    uint32_t v[8], sum = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      v[j] = (i0 + j < n) ? (uint32_t)cnt[i0 + j] : 0u;
-      sum += v[j];
-    }
+  for (int64_t base = 0; base < m; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < m ? (uint32_t)sums[i] : 0u;
     uint32_t tot;
-    uint32_t run = carry + block_exclusive_scan(sum, s_tmp, &tot);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (i0 + j < n) off[i0 + j] = (int32_t)run;
-      run += v[j];
-    }
+    const uint32_t ex = block_exclusive_scan(v, s_tmp, &tot);
+    if (i < m) sums[i] = (int32_t)(carry + ex);
     carry += tot;
   }
-  if (threadIdx.x == 0) off[n] = (int32_t)carry;
+  if (threadIdx.x == 0) *total = (int32_t)carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_apply(int32_t n, const int32_t *__restrict__ cnt,
+                                                        const int32_t *__restrict__ sums, int32_t *__restrict__ off) {
+  __shared__ uint32_t s_tmp[4];
+  const int64_t i0 = (int64_t)blockIdx.x * kScanChunkLen + (int64_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer], s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    v[j] = i0 + j < n ? (uint32_t)cnt[i0 + j] : 0u;
+    s += v[j];
+  }
+  uint32_t tot;
+  uint32_t run = (uint32_t)sums[blockIdx.x] + block_exclusive_scan_256(s, s_tmp, &tot);
+#pragma unroll
+  for (int j = 0; j < kScanPer; ++j) {
+    if (i0 + j < n) off[i0 + j] = (int32_t)run;
+    run += v[j];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(int32_t n, int32_t K, const int32_t *__restrict__ col,
@@ -94,177 +143,273 @@ __global__ __launch_bounds__(kBlock) void k_fill(int32_t n, int32_t K, const int
 }
 
 // Sort each transposed row by edge id (= source * K + slot), giving a fixed
-// order independent of the atomics above.  Rows are short (about K).
+// order independent of the atomics above.  Rows of up to 16 entries are
+// sorted in registers; longer ones in place.
+constexpr int kRowReg = 16;
 __global__ __launch_bounds__(kBlock) void k_sort_rows(int32_t n, const int32_t *__restrict__ off,
                                                       int32_t *__restrict__ tsrc) {
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
     const int a = off[j], b = off[j + 1];
-    for (int u = a + 1; u < b; ++u) {
-      const int v = tsrc[u];
-      int w = u - 1;
-      while (w >= a && tsrc[w] > v) {
-        tsrc[w + 1] = tsrc[w];
-        --w;
+    const int len = b - a;
+    if (len <= kRowReg) {
+      int v[kRowReg];
+#pragma unroll
+      for (int u = 0; u < kRowReg; ++u) v[u] = u < len ? tsrc[a + u] : 0x7fffffff;
+      // odd-even transposition: kRowReg rounds sort kRowReg entries
+#pragma unroll
+      for (int r = 0; r < kRowReg; ++r) {
+#pragma unroll
+        for (int u = r & 1; u + 1 < kRowReg; u += 2) {
+          const int x = v[u], y = v[u + 1];
+          v[u] = min(x, y);
+          v[u + 1] = max(x, y);
+        }
       }
-      tsrc[w + 1] = v;
+#pragma unroll
+      for (int u = 0; u < kRowReg; ++u)
+        if (u < len) tsrc[a + u] = v[u];
+    } else {
+      for (int u = a + 1; u < b; ++u) {
+        const int v = tsrc[u];
+        int w = u - 1;
+        while (w >= a && tsrc[w] > v) {
+          tsrc[w + 1] = tsrc[w];
+          --w;
+        }
+        tsrc[w + 1] = v;
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------- forward
-// x_k = T x_{k-1} (k >= 1) into saved[k]; out = c_0 x_0 + ... accumulated.
-// k == 0 copies x into saved[0] and sets out = c_0 x.
-__global__ __launch_bounds__(kBlock) void k_poly_step(int32_t n, int32_t K, int k, const int32_t *__restrict__ col,
-                                                      const float *__restrict__ p, const float *__restrict__ x,
+__device__ __forceinline__ void ld3(const float *__restrict__ x, int64_t i, float &a, float &b, float &c) {
+  a = x[3 * i + 0];
+  b = x[3 * i + 1];
+  c = x[3 * i + 2];
+}
+__device__ __forceinline__ void st3(float *__restrict__ x, int64_t i, float a, float b, float c) {
+  x[3 * i + 0] = a;
+  x[3 * i + 1] = b;
+  x[3 * i + 2] = c;
+}
+
+// One sweep x_k = T x_{k-1} (k >= 1) into saved[k].  The last sweep
+// (k == ncoef - 1) also forms out = sum_k c_k x_k from the saved iterates.
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_poly_step(int32_t n, int32_t k_rt, int k, int ncoef,
+                                                      const int32_t *__restrict__ col, const float *__restrict__ p,
                                                       const float *__restrict__ coef, float *__restrict__ saved,
                                                       float *__restrict__ out) {
-  const float ck = coef[k];
+  const int K = KT > 0 ? KT : k_rt;
   const size_t S = (size_t)n * 3;
+  const float *xp = saved + (size_t)(k - 1) * S;
+  float *xs = saved + (size_t)k * S;
+  const bool last = k == ncoef - 1;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    float v[3];
-    if (k == 0) {
-      v[0] = x[3 * i + 0];
-      v[1] = x[3 * i + 1];
-      v[2] = x[3 * i + 2];
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    int c0;
+    if (KT == 8) {
+      const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
+      const float4 *pr = reinterpret_cast<const float4 *>(p + i * 8);
+      const int4 ca = cr[0], cb = cr[1];
+      const float4 pa = pr[0], pb = pr[1];
+      const int cv[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+      const float pv[8] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
+      c0 = cv[0];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int64_t j = cv[kk] >= 0 ? (int64_t)cv[kk] : i;  // empty slot: weight 0, read self
+        float y0, y1, y2;
+        ld3(xp, j, y0, y1, y2);
+        a0 = fmaf(pv[kk], y0, a0);
+        a1 = fmaf(pv[kk], y1, a1);
+        a2 = fmaf(pv[kk], y2, a2);
+      }
     } else {
-      const float *xp = saved + (size_t)(k - 1) * S;
       const int32_t *cr = col + i * K;
       const float *pr = p + i * K;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      c0 = cr[0];
       for (int kk = 0; kk < K; ++kk) {
-        const int64_t j = cr[kk] >= 0 ? (int64_t)cr[kk] : i;  // empty slot: weight 0, read self
+        const int64_t j = cr[kk] >= 0 ? (int64_t)cr[kk] : i;
         const float w = cr[kk] >= 0 ? pr[kk] : 0.0f;
-        a0 = fmaf(w, xp[3 * j + 0], a0);
-        a1 = fmaf(w, xp[3 * j + 1], a1);
-        a2 = fmaf(w, xp[3 * j + 2], a2);
-      }
-      const float s0 = xp[3 * i + 0], s1 = xp[3 * i + 1], s2 = xp[3 * i + 2];
-      if (cr[0] >= 0) {
-        v[0] = 0.5f * s0 + 0.5f * a0;
-        v[1] = 0.5f * s1 + 0.5f * a1;
-        v[2] = 0.5f * s2 + 0.5f * a2;
-      } else {
-        v[0] = s0;
-        v[1] = s1;
-        v[2] = s2;
+        float y0, y1, y2;
+        ld3(xp, j, y0, y1, y2);
+        a0 = fmaf(w, y0, a0);
+        a1 = fmaf(w, y1, a1);
+        a2 = fmaf(w, y2, a2);
       }
     }
-    float *xs = saved + (size_t)k * S;
-    xs[3 * i + 0] = v[0];
-    xs[3 * i + 1] = v[1];
-    xs[3 * i + 2] = v[2];
-    if (k == 0) {
-      out[3 * i + 0] = ck * v[0];
-      out[3 * i + 1] = ck * v[1];
-      out[3 * i + 2] = ck * v[2];
-    } else {
-      out[3 * i + 0] = fmaf(ck, v[0], out[3 * i + 0]);
-      out[3 * i + 1] = fmaf(ck, v[1], out[3 * i + 1]);
-      out[3 * i + 2] = fmaf(ck, v[2], out[3 * i + 2]);
+    float s0, s1, s2;
+    ld3(xp, i, s0, s1, s2);
+    float v0 = s0, v1 = s1, v2 = s2;
+    if (c0 >= 0) {
+      v0 = 0.5f * s0 + 0.5f * a0;
+      v1 = 0.5f * s1 + 0.5f * a1;
+      v2 = 0.5f * s2 + 0.5f * a2;
+    }
+    st3(xs, i, v0, v1, v2);
+    if (last) {
+      const float ck = coef[k];
+      float o0 = ck * v0, o1 = ck * v1, o2 = ck * v2;
+      for (int kk = k - 1; kk >= 0; --kk) {
+        float y0, y1, y2;
+        ld3(saved + (size_t)kk * S, i, y0, y1, y2);
+        const float c = coef[kk];
+        o0 = fmaf(c, y0, o0);
+        o1 = fmaf(c, y1, o1);
+        o2 = fmaf(c, y2, o2);
+      }
+      st3(out, i, o0, o1, o2);
     }
   }
 }
 
+// x_0 = x into saved[0] (and out = c_0 x when there is one coefficient).
+__global__ __launch_bounds__(kBlock) void k_poly_first(int32_t n, int ncoef, const float *__restrict__ x,
+                                                       const float *__restrict__ coef, float *__restrict__ saved,
+                                                       float *__restrict__ out) {
+  const float c0 = coef[0];
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < 3 * (int64_t)n; i += (int64_t)gridDim.x * kBlock) {
+    const float v = x[i];
+    saved[i] = v;
+    if (ncoef == 1) out[i] = c0 * v;
+  }
+}
+
 // ---------------------------------------------------------------- backward
-// One step m (n-1 >= m >= 1): from z_m compute z_{m-1} = c_{m-1} g + T^T z_m
-// and the sigma_g term of step m, <z_m, (dT/dsigma) x_{m-1}>, as per-block
-// FP64 partials.  z_m for m = n-1 is c_{n-1} g (read from g directly).
-__global__ __launch_bounds__(kBlock) void k_poly_back(int32_t n, int32_t K, int m, int last,
+// One step m (n-1 >= m >= 1), per point j:
+//   z_{m-1}[j] = c_{m-1} g[j] + T_jj z_m[j] + sum over in-edges e = i*K + slot
+//                of p_e / 2 z_m[i]                                    (T^T z_m)
+//   sigma_g term: (1/2) sum_k dp_jk <z_m[j], x_{m-1}[col_jk]>
+//   coefficient products <g[j], x_{m-1}[j]> (and <g[j], x_m[j]> at m = n-1)
+// with z_{n-1} = c_{n-1} g read from g directly.  Per-block FP64 partials:
+// sig_part[block], cpart[k][block].
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_poly_back(int32_t n, int32_t k_rt, int m, int last, int nb,
                                                       const int32_t *__restrict__ col, const int32_t *__restrict__ dist2,
                                                       const float *__restrict__ p, const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ tsrc, const double *__restrict__ sigma_g,
                                                       const float *__restrict__ coef, const float *__restrict__ g,
                                                       const float *__restrict__ saved, const float *__restrict__ zin,
-                                                      float *__restrict__ zout, double *__restrict__ part) {
-  __shared__ double s_red[8];
+                                                      float *__restrict__ zout, double *__restrict__ sig_part,
+                                                      double *__restrict__ cpart) {
+  __shared__ double s_red[8 * 3];
+  const int K = KT > 0 ? KT : k_rt;
   const double sg = *sigma_g;
   const double a_scale = sg > 0.0 ? 2.0 / (sg * sg * sg) : 0.0;
   const float cm = coef[m], cm1 = coef[m - 1];
-  const float *xprev = saved + (size_t)(m - 1) * n * 3;
-  double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-    // z_m of this point (z_{n-1} = c_{n-1} g)
+  const size_t S = (size_t)n * 3;
+  const float *xprev = saved + (size_t)(m - 1) * S;
+  const float *xcur = saved + (size_t)m * S;
+  // acc[0]: sigma_g term; acc[1]: <g, x_{m-1}>; acc[2]: <g, x_m> (last step only)
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+    float g0, g1, g2;
+    ld3(g, j, g0, g1, g2);
     float z0, z1, z2;
     if (last) {
-      z0 = cm * g[3 * i + 0];
-      z1 = cm * g[3 * i + 1];
-      z2 = cm * g[3 * i + 2];
+      z0 = cm * g0;
+      z1 = cm * g1;
+      z2 = cm * g2;
     } else {
-      z0 = zin[3 * i + 0];
-      z1 = zin[3 * i + 1];
-      z2 = zin[3 * i + 2];
+      ld3(zin, j, z0, z1, z2);
     }
-    // sigma_g term: (1/2) sum_k dp_ik <z_m[i], x_{m-1}[col_ik]>
-    const int32_t *cr = col + i * K;
-    if (cr[0] >= 0) {
-      const int32_t *dr = dist2 + i * K;
-      const float *pr = p + i * K;
-      const int d0 = dr[0];
+    float x0, x1, x2;
+    ld3(xprev, j, x0, x1, x2);
+    acc[1] += (double)g0 * x0 + (double)g1 * x1 + (double)g2 * x2;
+    if (last) {
+      float y0, y1, y2;
+      ld3(xcur, j, y0, y1, y2);
+      acc[2] += (double)g0 * y0 + (double)g1 * y1 + (double)g2 * y2;
+    }
+    // sigma_g term of row j
+    constexpr int KB = KT > 0 ? KT : kMaxK;
+    int cv[KB], dv[KB];
+    float pv[KB];
+    if (KT == 8) {
+      const int4 *cr = reinterpret_cast<const int4 *>(col + j * 8);
+      const int4 *dr = reinterpret_cast<const int4 *>(dist2 + j * 8);
+      const float4 *pr = reinterpret_cast<const float4 *>(p + j * 8);
+      const int4 ca = cr[0], cb = cr[1], da = dr[0], db = dr[1];
+      const float4 pa = pr[0], pb = pr[1];
+      cv[0] = ca.x; cv[1] = ca.y; cv[2] = ca.z; cv[3] = ca.w;
+      cv[4] = cb.x; cv[5] = cb.y; cv[6] = cb.z; cv[7] = cb.w;
+      dv[0] = da.x; dv[1] = da.y; dv[2] = da.z; dv[3] = da.w;
+      dv[4] = db.x; dv[5] = db.y; dv[6] = db.z; dv[7] = db.w;
+      pv[0] = pa.x; pv[1] = pa.y; pv[2] = pa.z; pv[3] = pa.w;
+      pv[4] = pb.x; pv[5] = pb.y; pv[6] = pb.z; pv[7] = pb.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        cv[k] = k < K ? col[j * K + k] : -1;
+        dv[k] = k < K ? dist2[j * K + k] : 0;
+        pv[k] = k < K ? p[j * K + k] : 0.f;
+      }
+    }
+    if (cv[0] >= 0) {
+      const int d0 = dv[0];
       double pa = 0.0;
-      for (int k = 0; k < K; ++k)
-        if (cr[k] >= 0) pa += (double)pr[k] * a_scale * (double)(dr[k] - d0);
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        if (cv[k] >= 0) pa += (double)pv[k] * a_scale * (double)(dv[k] - d0);
       double t = 0.0;
-      for (int k = 0; k < K; ++k) {
-        const int j = cr[k];
-        if (j >= 0) {
-          const double dp = (double)pr[k] * (a_scale * (double)(dr[k] - d0) - pa);
-          const double dot = (double)z0 * xprev[3 * (size_t)j + 0] + (double)z1 * xprev[3 * (size_t)j + 1] +
-                             (double)z2 * xprev[3 * (size_t)j + 2];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        if (cv[k] >= 0) {
+          float y0, y1, y2;
+          ld3(xprev, cv[k], y0, y1, y2);
+          const double dp = (double)pv[k] * (a_scale * (double)(dv[k] - d0) - pa);
+          const double dot = (double)z0 * y0 + (double)z1 * y1 + (double)z2 * y2;
           t += dp * dot;
         }
       }
       acc[0] += 0.5 * t;
     }
-    // z_{m-1}[i] = c_{m-1} g[i] + T_ii z_m[i] + sum over in-edges (e = src*K + k) of p_e / 2 z_m[src]
-    const float tii = cr[0] >= 0 ? 0.5f : 1.0f;
-    float r0 = tii * z0, r1 = tii * z1, r2 = tii * z2;
-    const int a = off[i], b = off[i + 1];
+    // T^T z_m at j
+    const float tjj = cv[0] >= 0 ? 0.5f : 1.0f;
+    float r0 = tjj * z0, r1 = tjj * z1, r2 = tjj * z2;
+    const int a = off[j], b = off[j + 1];
     for (int u = a; u < b; ++u) {
       const int e = tsrc[u];
       const int64_t src = e / K;
       const float w = 0.5f * p[e];
       float s0, s1, s2;
       if (last) {
-        s0 = cm * g[3 * src + 0];
-        s1 = cm * g[3 * src + 1];
-        s2 = cm * g[3 * src + 2];
+        ld3(g, src, s0, s1, s2);
+        s0 *= cm;
+        s1 *= cm;
+        s2 *= cm;
       } else {
-        s0 = zin[3 * src + 0];
-        s1 = zin[3 * src + 1];
-        s2 = zin[3 * src + 2];
+        ld3(zin, src, s0, s1, s2);
       }
       r0 = fmaf(w, s0, r0);
       r1 = fmaf(w, s1, r1);
       r2 = fmaf(w, s2, r2);
     }
-    zout[3 * i + 0] = fmaf(cm1, g[3 * i + 0], r0);
-    zout[3 * i + 1] = fmaf(cm1, g[3 * i + 1], r1);
-    zout[3 * i + 2] = fmaf(cm1, g[3 * i + 2], r2);
+    st3(zout, j, fmaf(cm1, g0, r0), fmaf(cm1, g1, r1), fmaf(cm1, g2, r2));
+  }
+  block_sum_f64<3>(acc, s_red);
+  if (threadIdx.x == 0) {
+    sig_part[blockIdx.x] = acc[0];
+    cpart[(size_t)(m - 1) * nb + blockIdx.x] = acc[1];
+    if (last) cpart[(size_t)m * nb + blockIdx.x] = acc[2];
+  }
+}
+
+// One coefficient: z_0 = c_0 g and <g, x_0>.
+__global__ __launch_bounds__(kBlock) void k_scale(int32_t n, const float *__restrict__ coef,
+                                                  const float *__restrict__ g, const float *__restrict__ x0,
+                                                  float *__restrict__ z, double *__restrict__ cpart) {
+  __shared__ double s_red[8];
+  const float c0 = coef[0];
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < 3 * (int64_t)n; i += (int64_t)gridDim.x * kBlock) {
+    z[i] = c0 * g[i];
+    acc[0] += (double)g[i] * x0[i];
   }
   block_sum_f64<1>(acc, s_red);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
-}
-
-// z_0 = c_0 g when there is a single coefficient.
-__global__ __launch_bounds__(kBlock) void k_scale(int32_t n, const float *__restrict__ coef,
-                                                  const float *__restrict__ g, float *__restrict__ z) {
-  const float c0 = coef[0];
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < 3 * (int64_t)n; i += (int64_t)gridDim.x * kBlock)
-    z[i] = c0 * g[i];
-}
-
-// <g, x_k> per block for every k.
-__global__ __launch_bounds__(kBlock) void k_coef_grad(int32_t n, int ncoef, const float *__restrict__ g,
-                                                      const float *__restrict__ saved, double *__restrict__ part) {
-  __shared__ double s_buf[8];
-  for (int k = 0; k < ncoef; ++k) {
-    const float *xk = saved + (size_t)k * n * 3;
-    double acc[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < 3 * (int64_t)n; i += (int64_t)gridDim.x * kBlock)
-      acc[0] += (double)g[i] * (double)xk[i];
-    block_sum_f64<1>(acc, s_buf);
-    if (threadIdx.x == 0) part[(size_t)k * gridDim.x + blockIdx.x] = acc[0];
-  }
+  if (threadIdx.x == 0) cpart[blockIdx.x] = acc[0];
 }
 
 // One block: sum partials in block order.  grad_coef[k] from coef partials,
@@ -292,25 +437,36 @@ __global__ __launch_bounds__(kBlock) void k_poly_reduce(int ncoef, int nb, const
 
 }  // namespace
 
+size_t transpose_workspace(int64_t n) {
+  const size_t N = (size_t)(n > 0 ? n : 1);
+  const size_t chunks = (N + kScanChunkLen - 1) / kScanChunkLen;
+  size_t b = 0;
+  auto take = [&](size_t bytes) { b += (bytes + 255) & ~(size_t)255; };
+  take(N * 4);             // in-degree / fill counters
+  take((chunks + 1) * 4);  // chunk sums
+  return b;
+}
+
 size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks) {
   const size_t N = (size_t)(n > 0 ? n : 1);
   size_t b = 0;
   auto take = [&](size_t bytes) { b += (bytes + 255) & ~(size_t)255; };
   take(N * k * 4);                     // p
-  take(N * 4);                         // indegree / fill counters
-  take((N + 1) * 4);                   // offsets
-  take(N * k * 4);                     // transposed edge ids
+  take((N + 1) * 4);                   // offsets (when no transpose is given)
+  take(N * k * 4);                     // transposed edge ids (same)
   take(2 * N * 3 * 4);                 // z ping-pong
   take((size_t)ncoef * nblocks * 8);   // coef partials
   take((size_t)ncoef * nblocks * 8);   // sigma partials
+  take(transpose_workspace(n));        // transpose scratch
   return b;
 }
 
 struct PolyBufs {
   float *p;
-  int32_t *cnt, *off, *tsrc;
+  int32_t *off, *tsrc;
   float *z[2];
   double *coef_part, *sig_part;
+  char *tws;
 };
 
 static PolyBufs poly_carve(char *ws, int64_t n, int k, int ncoef, int nblocks) {
@@ -323,13 +479,13 @@ static PolyBufs poly_carve(char *ws, int64_t n, int k, int ncoef, int nblocks) {
     return ptr;
   };
   pb.p = (float *)take(N * k * 4);
-  pb.cnt = (int32_t *)take(N * 4);
   pb.off = (int32_t *)take((N + 1) * 4);
   pb.tsrc = (int32_t *)take(N * k * 4);
   pb.z[0] = (float *)take(N * 3 * 4);
   pb.z[1] = (float *)take(N * 3 * 4);
   pb.coef_part = (double *)take((size_t)ncoef * nblocks * 8);
   pb.sig_part = (double *)take((size_t)ncoef * nblocks * 8);
+  pb.tws = take(transpose_workspace(n));
   return pb;
 }
 
@@ -338,45 +494,81 @@ static int grid_for(int64_t items) {
   return (int)(g < 1 ? 1 : (g < kMaxGrid ? g : kMaxGrid));
 }
 
+hipError_t launch_transpose(int64_t n, int k, const int32_t *col, int32_t *off, int32_t *tsrc, char *ws,
+                            hipStream_t s) {
+  const size_t N = (size_t)(n > 0 ? n : 1);
+  int32_t *cnt = (int32_t *)ws;
+  int32_t *sums = (int32_t *)(ws + ((N * 4 + 255) & ~(size_t)255));
+  const int chunks = (int)((N + kScanChunkLen - 1) / kScanChunkLen);
+  const int G = grid_for(n);
+  const int GE = grid_for(n * k);
+  k_zero_i32<<<G, kBlock, 0, s>>>(cnt, n);
+  k_indegree<<<GE, kBlock, 0, s>>>((int32_t)n, k, col, cnt);
+  k_chunk_sums<<<chunks, kBlock, 0, s>>>((int32_t)n, cnt, sums);
+  k_scan_sums<<<1, 1024, 0, s>>>(chunks, sums, off + n);
+  k_chunk_apply<<<chunks, kBlock, 0, s>>>((int32_t)n, cnt, sums, off);
+  k_zero_i32<<<G, kBlock, 0, s>>>(cnt, n);
+  k_fill<<<GE, kBlock, 0, s>>>((int32_t)n, k, col, off, cnt, tsrc);
+  k_sort_rows<<<G, kBlock, 0, s>>>((int32_t)n, off, tsrc);
+  return hipGetLastError();
+}
+
 hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *x,
                                const float *coef, int ncoef, const double *sigma_g, float *out, float *saved,
                                char *ws, hipStream_t s) {
   PolyBufs pb = poly_carve(ws, n, k, ncoef, kMaxGrid);
   const int G = grid_for(n);
-  k_poly_weights<<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
-  for (int kk = 0; kk < ncoef; ++kk)
-    k_poly_step<<<G, kBlock, 0, s>>>((int32_t)n, k, kk, col, pb.p, x, coef, saved, out);
+  k_poly_first<<<grid_for(3 * n), kBlock, 0, s>>>((int32_t)n, ncoef, x, coef, saved, out);
+  if (ncoef == 1) return hipGetLastError();
+  if (k == 8)
+    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+  else
+    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+  for (int kk = 1; kk < ncoef; ++kk) {
+    if (k == 8)
+      k_poly_step<8><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, coef, saved, out);
+    else
+      k_poly_step<0><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, coef, saved, out);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *saved,
-                                const float *coef, int ncoef, const double *sigma_g, const float *grad_out,
-                                float *grad_x, float *grad_coef, double *grad_sigma, char *ws, hipStream_t s) {
+hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const int32_t *t_off,
+                                const int32_t *t_edge, const float *saved, const float *coef, int ncoef,
+                                const double *sigma_g, const float *grad_out, float *grad_x, float *grad_coef,
+                                double *grad_sigma, char *ws, hipStream_t s) {
   PolyBufs pb = poly_carve(ws, n, k, ncoef, kMaxGrid);
   const int G = grid_for(n);
-  const int GE = grid_for(n * k);
-  k_poly_weights<<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
-  // transpose of the directed graph, rows sorted by source
-  k_zero_i32<<<G, kBlock, 0, s>>>(pb.cnt, n);
-  k_indegree<<<GE, kBlock, 0, s>>>((int32_t)n, k, col, pb.cnt);
-  k_scan_counts<<<1, 1024, 0, s>>>((int32_t)n, pb.cnt, pb.off);
-  k_zero_i32<<<G, kBlock, 0, s>>>(pb.cnt, n);
-  k_fill<<<GE, kBlock, 0, s>>>((int32_t)n, k, col, pb.off, pb.cnt, pb.tsrc);
-  k_sort_rows<<<G, kBlock, 0, s>>>((int32_t)n, pb.off, pb.tsrc);
-  // reverse Horner
   if (ncoef == 1) {
-    k_scale<<<grid_for(3 * n), kBlock, 0, s>>>((int32_t)n, coef, grad_out, grad_x);
-  } else {
-    const float *zin = nullptr;
-    for (int m = ncoef - 1; m >= 1; --m) {
-      float *zout = (m == 1) ? grad_x : pb.z[m & 1];
-      k_poly_back<<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, col, dist2, pb.p, pb.off, pb.tsrc, sigma_g,
-                                       coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G);
-      zin = zout;
-    }
+    const int G3 = grid_for(3 * n);
+    k_scale<<<G3, kBlock, 0, s>>>((int32_t)n, coef, grad_out, saved, grad_x, pb.coef_part);
+    k_poly_reduce<<<1, kBlock, 0, s>>>(1, G3, pb.coef_part, pb.sig_part, grad_coef, grad_sigma);
+    return hipGetLastError();
   }
-  k_coef_grad<<<G, kBlock, 0, s>>>((int32_t)n, ncoef, grad_out, saved, pb.coef_part);
-  // the reduce reads G partials per coefficient; coef partials are laid out [k][G]
+  if (!t_off) {  // no transpose given: build one in the workspace
+    hipError_t e = launch_transpose(n, k, col, pb.off, pb.tsrc, pb.tws, s);
+    if (e != hipSuccess) return e;
+    t_off = pb.off;
+    t_edge = pb.tsrc;
+  }
+  if (k == 8)
+    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+  else
+    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+  // reverse Horner; coefficient products ride along
+  const float *zin = nullptr;
+  for (int m = ncoef - 1; m >= 1; --m) {
+    float *zout = (m == 1) ? grad_x : pb.z[m & 1];
+    if (k == 8)
+      k_poly_back<8><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, col, dist2, pb.p, t_off, t_edge,
+                                          sigma_g, coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
+                                          pb.coef_part);
+    else
+      k_poly_back<0><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, col, dist2, pb.p, t_off, t_edge,
+                                          sigma_g, coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
+                                          pb.coef_part);
+    zin = zout;
+  }
   k_poly_reduce<<<1, kBlock, 0, s>>>(ncoef, G, pb.coef_part, pb.sig_part, grad_coef, grad_sigma);
   return hipGetLastError();
 }

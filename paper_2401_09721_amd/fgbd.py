@@ -7,8 +7,10 @@ library has not been built.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -26,7 +28,7 @@ FGBD_ST_NO_PATCH = 2
 FGBD_ST_BAD_OFFSETS = 4
 FGBD_ST_SWEEP_STALL = 8
 NUM_KERNELS = 9
-ABI_VERSION = 5
+ABI_VERSION = 6
 MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
            "finalize")
@@ -71,6 +73,18 @@ class Graph(ctypes.Structure):
         ("col", ctypes.c_void_p),
         ("dist2", ctypes.c_void_p),
         ("p", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("k", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+
+class Transpose(ctypes.Structure):
+    """fgbd_transpose: for every point the ids of the edges that point at it."""
+
+    _fields_ = [
+        ("off", ctypes.c_void_p),
+        ("edge", ctypes.c_void_p),
         ("n", ctypes.c_int64),
         ("k", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
@@ -137,7 +151,10 @@ _SIGNATURES = {
     "fgbd_poly_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
-    "fgbd_poly_filter_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p,
+    "fgbd_graph_transpose": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.POINTER(Transpose),
+                                            ctypes.c_void_p]),
+    "fgbd_poly_filter_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.POINTER(Transpose),
+                                                 ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fgbd_set_sweep_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
@@ -203,10 +220,33 @@ def _torch():
     return torch
 
 
+# Contexts still open, closed by an exit hook.  The hook is registered when the
+# first context is made, after torch has been imported and has registered its
+# own exit work; exit hooks run last-registered first, so every context is
+# destroyed (its events synchronised, its own workspace freed) while torch and
+# the HIP runtime are still up, never from a finaliser during interpreter
+# teardown.
+_live_contexts: "weakref.WeakSet" = weakref.WeakSet()
+_exit_hook = False
+_exiting = False
+
+
+def _close_all_contexts() -> None:
+    global _exiting
+    _exiting = True
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+    _contexts.clear()
+
+
 class Context:
     """A library context bound to one GPU, with a torch-allocated workspace."""
 
     def __init__(self, device=None):
+        global _exit_hook
         torch = _torch()
         dev = torch.device(device if device is not None else "cuda")
         idx = dev.index if dev.index is not None else torch.cuda.current_device()
@@ -216,6 +256,10 @@ class Context:
         self.handle = h
         self._ws = None
         self._ws_bytes = 0
+        _live_contexts.add(self)
+        if not _exit_hook:
+            atexit.register(_close_all_contexts)
+            _exit_hook = True
 
     def reserve(self, params, n: int, batch: int = 1) -> None:
         """Make sure the workspace covers n points in `batch` clouds (call it
@@ -274,11 +318,19 @@ class Context:
         return {KERNELS[i]: (ms[i], nl[i]) for i in range(NUM_KERNELS)}
 
     def close(self) -> None:
+        """Destroy the library context (waits for its pending events) and drop
+        the workspace.  Idempotent."""
         if self.handle:
             lib().fgbd_destroy(self.handle)
             self.handle = None
+        self._ws = None
+        self._ws_bytes = 0
+        _live_contexts.discard(self)
 
     def __del__(self):
+        # after the exit hook has run, the runtime may be going away: leave it
+        if _exiting:
+            return
         try:
             self.close()
         except Exception:
@@ -423,6 +475,14 @@ class SLGraph:
 
     def c_struct(self) -> Graph:
         return Graph(_ptr(self.col).value, _ptr(self.dist2).value, _ptr(self.p).value, self.n, self.k, 0)
+
+    def transpose(self, ctx: Optional["Context"] = None, stream=None):
+        """The graph's edge transpose (fgbd_graph_transpose), built on first use
+        and kept with the graph: (off int32 [n + 1], edge int32 [n * k]).
+        Build it again (rebuild=True) after changing col in place."""
+        if getattr(self, "_transpose", None) is None:
+            self._transpose = graph_transpose(self, ctx=ctx, stream=stream)
+        return self._transpose
 
 
 # ------------------------------------------------------------- the ABI calls
@@ -675,9 +735,28 @@ def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None,
     return out, saved
 
 
+def graph_transpose(graph: SLGraph, ctx: Optional[Context] = None, stream=None):
+    """Edge transpose of a graph: (off int32 [n + 1], edge int32 [n * k]) with
+    edge[off[j]:off[j + 1]] the ids i * k + slot of the edges pointing at j,
+    ascending."""
+    torch = _torch()
+    ctx = ctx or default_context(graph.col.device)
+    _need_out(graph.col, torch.int32, (graph.n, graph.k), "graph.col", ctx.device)
+    n, k = graph.n, graph.k
+    off = torch.empty(n + 1, dtype=torch.int32, device=ctx.device)
+    edge = torch.empty(max(n * k, 1), dtype=torch.int32, device=ctx.device)
+    gs = graph.c_struct()
+    ts = Transpose(_ptr(off).value, _ptr(edge).value, n, k, 0)
+    _check(lib().fgbd_graph_transpose(ctx.handle, ctypes.byref(gs), ctypes.byref(ts), _stream(ctx, stream)))
+    return off, edge
+
+
 def poly_filter_backward(graph: SLGraph, saved, coef, sigma_g, grad_out, ctx: Optional[Context] = None,
-                         stream=None):
-    """Adjoint of poly_filter.  Returns (grad_x, grad_coef, grad_sigma_g)."""
+                         stream=None, transpose=True):
+    """Adjoint of poly_filter.  transpose: True uses the graph's cached edge
+    transpose (built on first use), False builds one inside the call, or an
+    (off, edge) pair from graph_transpose.  Returns (grad_x, grad_coef,
+    grad_sigma_g)."""
     torch = _torch()
     ctx = ctx or default_context(grad_out.device)
     grad_out = grad_out.contiguous()
@@ -690,13 +769,24 @@ def poly_filter_backward(graph: SLGraph, saved, coef, sigma_g, grad_out, ctx: Op
         raise ValueError("sigma_g must be a float64 device scalar")
     nc = int(coef.numel())
     _need_out(saved, torch.float32, (nc, graph.n, 3), "saved", ctx.device)
+    ts = None
+    if transpose is True:
+        transpose = graph.transpose(ctx=ctx, stream=stream)
+    if transpose is not None and transpose is not False:
+        off, edge = transpose
+        _need_out(off, torch.int32, (graph.n + 1,), "transpose off", ctx.device)
+        if edge.dtype != torch.int32 or edge.device != ctx.device or not edge.is_contiguous() \
+                or edge.numel() < graph.n * graph.k:
+            raise ValueError(f"transpose edge must be a contiguous int32 tensor on {ctx.device} "
+                             f"with at least n * k entries")
+        ts = Transpose(_ptr(off).value, _ptr(edge).value, graph.n, graph.k, 0)
     gx = torch.empty_like(grad_out)
     gc = torch.empty(nc, dtype=torch.float32, device=ctx.device)
     gsig = torch.empty((), dtype=torch.float64, device=ctx.device)
     gs = graph.c_struct()
-    _check(lib().fgbd_poly_filter_backward(ctx.handle, ctypes.byref(gs), _ptr(saved), _ptr(coef.contiguous()), nc,
-                                           _ptr(sigma_g.contiguous()), _ptr(grad_out), _ptr(gx), _ptr(gc),
-                                           _ptr(gsig), _stream(ctx, stream)))
+    _check(lib().fgbd_poly_filter_backward(ctx.handle, ctypes.byref(gs), ctypes.byref(ts) if ts is not None else None,
+                                           _ptr(saved), _ptr(coef.contiguous()), nc, _ptr(sigma_g.contiguous()),
+                                           _ptr(grad_out), _ptr(gx), _ptr(gc), _ptr(gsig), _stream(ctx, stream)))
     return gx, gc, gsig
 
 

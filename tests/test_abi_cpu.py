@@ -42,7 +42,7 @@ def test_status_constants_match_header():
 
 
 def test_version_and_defaults():
-    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 5
+    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 6
     p = fgbd.default_params()
     assert (p.bits, p.num_dirs, p.window, p.k, p.patch, p.q_max) == (10, 8, 4, 8, 0, 32)
     assert p.fslr_kappa == 2.0 and p.sigma_g == 0.0
@@ -413,3 +413,23 @@ def test_noalloc_noise_call_errors(ctx):
     assert call(ctx, ctypes.byref(g), FAKE, ctypes.byref(bad), FAKE, FAKE, None, None) == E
     hdr = open(HEADER).read()
     assert int(eval(re.search(r"#define FGBD_NOALLOC_SCRATCH_BYTES \(([^)]*)\)", hdr).group(1))) == 512 * 1024
+
+
+def test_transpose_call_errors(ctx):
+    lib = fgbd.lib()
+    E = fgbd.FGBD_E_INVALID
+    g = fgbd.Graph(0x1000, 0x2000, 0x3000, 10, 8, 0)
+    t = fgbd.Transpose(0x4000, 0x5000, 10, 8, 0)
+    bad_n = fgbd.Transpose(0x4000, 0x5000, 11, 8, 0)
+    bad_k = fgbd.Transpose(0x4000, 0x5000, 10, 6, 0)
+    no_off = fgbd.Transpose(0, 0x5000, 10, 8, 0)
+    assert lib.fgbd_graph_transpose(None, ctypes.byref(g), ctypes.byref(t), None) == E
+    assert lib.fgbd_graph_transpose(ctx, None, ctypes.byref(t), None) == E
+    assert lib.fgbd_graph_transpose(ctx, ctypes.byref(g), None, None) == E
+    for bad in (bad_n, bad_k, no_off):
+        assert lib.fgbd_graph_transpose(ctx, ctypes.byref(g), ctypes.byref(bad), None) == E
+    # the backward rejects a transpose of another shape before any device work
+    sg = FAKE
+    assert lib.fgbd_poly_filter_backward(ctx, ctypes.byref(g), ctypes.byref(bad_n), FAKE, FAKE, 8, sg, FAKE,
+                                         ctypes.c_void_p(0x900000), None, None, None) == E
+    assert "transpose" in lib.fgbd_last_error().decode()

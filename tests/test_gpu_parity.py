@@ -291,6 +291,42 @@ def test_poly_filter_forward_and_adjoint(ncoef):
     assert math.isclose(float(gs), rs, rel_tol=1e-3, abs_tol=1e-3 * max(1.0, abs(rs)))
 
 
+def test_graph_transpose_matches_numpy():
+    """fgbd_graph_transpose: for every point the ids of the edges pointing at
+    it, ascending, against a numpy construction."""
+    for prm in (fgbd.default_params(bits=8), fgbd.default_params(bits=8, k=5, num_dirs=3, window=1)):
+        c = synth.tiny_cloud(0)
+        g = fgbd.build_slg(dev(c.xyz, torch.int32), prm)
+        off, edge = fgbd.graph_transpose(g)
+        torch.cuda.synchronize()
+        col = g.col.cpu().numpy().ravel()
+        e = np.nonzero(col >= 0)[0]
+        tgt = col[e]
+        order = np.lexsort((e, tgt))
+        exp_off = np.concatenate([[0], np.cumsum(np.bincount(tgt, minlength=g.n))])
+        off = off.cpu().numpy()
+        assert np.array_equal(off, exp_off)
+        assert np.array_equal(edge.cpu().numpy()[:off[-1]], e[order])
+
+
+def test_poly_backward_given_or_built_transpose_same_bits():
+    """The backward with the graph's cached transpose, with one built inside
+    the call, and twice in a row: bit-identical (fixed-order sums)."""
+    c, g, coef, sg, go = _poly_case(5)
+    x = dev(c.noisy, torch.float32)
+    ct = dev(coef, torch.float32)
+    st = torch.tensor(sg, dtype=torch.float64, device="cuda")
+    _, saved = fgbd.poly_filter(g, x, ct, st)
+    gt = dev(go, torch.float32)
+    a = fgbd.poly_filter_backward(g, saved, ct, st, gt)
+    b = fgbd.poly_filter_backward(g, saved, ct, st, gt, transpose=False)
+    c2 = fgbd.poly_filter_backward(g, saved, ct, st, gt)
+    torch.cuda.synchronize()
+    for u, v in ((a, b), (a, c2)):
+        for s, t in zip(u, v):
+            assert torch.equal(s, t)
+
+
 def test_poly_filter_e_q_is_eq5():
     c, g, _, _, _ = _poly_case(0)
     prm = fgbd.default_params(bits=8)
