@@ -134,8 +134,8 @@ struct MergeArgs {
 };
 
 // Exact (64-bit key) selection for one point, runtime window over positions
-// lo..hi: used for all points when the capacity reaches 2^24 and for the rare
-// point whose 32-bit selection kept a clamped distance.
+// lo..hi: used for every point of a cloud of more than 2^24 points and for
+// the rare point whose 32-bit selection kept a clamped distance.
 template <int KM>
 __device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int window,
                              const uint64_t *__restrict__ sorted, const uint32_t *__restrict__ rank,
@@ -156,13 +156,14 @@ __device__ void select_exact(const MergeArgs &a, int i, int lo, int hi, int wind
   }
 }
 
-// One thread per point.  WT > 0 (compile-time window, capacity < 2^24): the
+// One thread per point.  WT > 0 (compile-time window, clouds of at most 2^24
+// points; a block of a larger cloud takes the 64-bit selection): the
 // point's ranks in all directions go to LDS in one batch of loads; each
 // direction's 2*WT+1 window items (the centre gives the point's own code) are
 // then loaded as one batch and consumed (prefetching the next direction's
 // window would raise the register count from 83 to 109 and the occupancy from
 // six to four waves per SIMD, which measured slower); candidates are 31-bit
-// keys (min(d2, 127) << 24 | j), exact whenever no kept entry has a clamped
+// keys (min(d2, 127) << 24 | j - cloud start), exact whenever no kept entry has a clamped
 // distance, else the point is redone with 64-bit keys.  With w = 4 each
 // direction's 8 candidates are first sorted by a network: the first
 // direction's (distinct points, empty list) are the list, and later ones are
@@ -186,13 +187,18 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
   for (int v = t; v <= (int)kKeyD2Max; v += kBlock) s_sqrt[v] = sqrt((double)v);
   const SegBlock sb = seg_block(a.sa, kGridMerge);
   const int lo = (int)sb.begin, hi = (int)sb.end - 1;
+  // the 31-bit keys hold a cloud-local index in 24 bits: a cloud of 2^24 or
+  // more points takes the 64-bit selection (uniform over the block)
+  const bool fast = sb.end - sb.begin <= (int64_t)(1 << 24);
   __syncthreads();
   const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
     const int i = (int)(base + t);
     if (i >= sh.end) continue;
     uint64_t lst[KM];
-    if constexpr (WT > 0) {
+    if (WT > 0 && !fast) {
+      select_exact<KM>(a, i, lo, hi, a.window, sorted, rank, lst);
+    } else if constexpr (WT > 0) {
 #pragma unroll
       for (int d = 0; d < kMaxDirs; ++d)
         if (d < L) s_rank[d][t] = (int)rank[(size_t)d * a.stride + i];
@@ -218,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
           for (int s = 0; s < 2 * WT; ++s) {
             const uint64_t it = cur[s < WT ? s : s + 1];
             const uint32_t d2 = pt_dist2(pi, (uint32_t)(it >> 32), bits);
-            kc[s] = (min(d2, kKeyD2Max) << 24) | (uint32_t)it;
+            kc[s] = (min(d2, kKeyD2Max) << 24) | ((uint32_t)it - (uint32_t)lo);
           }
         } else {
           load_window<WT>(srt, r, lo, hi, cur);
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
           for (int s = 0; s < 2 * WT; ++s) {
             const uint64_t it = cur[s < WT ? s : s + 1];
             const uint32_t d2 = pt_dist2(pi, (uint32_t)(it >> 32), bits);
-            kc[s] = it == ~0ull ? ~0u : ((min(d2, kKeyD2Max) << 24) | (uint32_t)it);
+            kc[s] = it == ~0ull ? ~0u : ((min(d2, kKeyD2Max) << 24) | ((uint32_t)it - (uint32_t)lo));
           }
         }
         if constexpr (WT == 4) {
@@ -257,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
       } else {
 #pragma unroll
         for (int k = 0; k < KM; ++k)
-          lst[k] = key[k] == ~0u ? ~0ull : ((uint64_t)(key[k] >> 24) << 32) | (key[k] & 0xffffffu);
+          lst[k] = key[k] == ~0u ? ~0ull : ((uint64_t)(key[k] >> 24) << 32) | ((key[k] & 0xffffffu) + (uint32_t)lo);
       }
     } else {
       select_exact<KM>(a, i, lo, hi, a.window, sorted, rank, lst);
@@ -366,16 +372,17 @@ hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int3
   const uint32_t *rank = r.b.rank;
   unsigned long long *part = r.b.edge_acc;
   hipStream_t st = r.stream;
-  const bool small = r.pl.n_cap < (1 << 24);  // 32-bit keys hold the index in 24 bits
-  if (small && k <= 8 && window == 4)
+  // the compile-time-window kernels take 64-bit keys for a cloud of more
+  // than 2^24 points (their 31-bit keys hold a cloud-local index)
+  if (k <= 8 && window == 4)
     k_merge<8, 4><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
-  else if (small && k <= 8 && window == 1)
+  else if (k <= 8 && window == 1)
     k_merge<8, 1><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
-  else if (small && k <= 8 && window == 2)
+  else if (k <= 8 && window == 2)
     k_merge<8, 2><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else if (k <= 8)
     k_merge<8, 0><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
-  else if (small && k <= 16 && window == 4)
+  else if (k <= 16 && window == 4)
     k_merge<16, 4><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else if (k <= 16)
     k_merge<16, 0><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
