@@ -97,29 +97,45 @@ def _gen(job):
     return synth.moved_body_frame(**kw)  # (cloud, fitted scale)
 
 
+def selected_patterns(args) -> set:
+    return set() if args.no_patterns else {p.strip() for p in args.patterns.split(",") if p.strip()}
+
+
 def make_inputs(args, synth) -> dict:
-    """The headline frame plus the pattern workloads: 8 uneven clouds
-    (200k-1.2M points, sigma uniform in [5, 35]), a sequence of moving ~1M-point
-    frames (sigma 20) and 4 clouds of 500k points (sigma 25) with clean colours."""
+    """The headline frame plus the workloads of the selected patterns: 8 uneven
+    clouds (200k-1.2M points, sigma uniform in [5, 35]), a sequence of moving
+    ~1M-point frames (sigma 20) and 4 clouds of 500k points (sigma 25) with
+    clean colours."""
     import multiprocessing as mp
 
+    pats = selected_patterns(args)
+    want_batch = "batched" in pats
+    want_diff = "fwd_bwd" in pats
+    want_stream = bool(pats & {"streaming", "streaming_periodic"})
     jobs = [("body", dict(seed=synth.config_seed(1), target=args.points, sigma=args.sigma))]
     stream_seed = synth.config_seed(3)
-    if not args.no_patterns:
+    if want_batch:
         jobs += [("body", dict(bits=10, **kw)) for kw in synth.batched_specs(synth.config_seed(2), 8)]
+    if want_diff:
         jobs += [("body", dict(seed=synth.config_seed(4, c), target=500_000, sigma=25.0)) for c in range(4)]
+    if want_stream:
         jobs += [("frame", dict(seed=stream_seed, frame=0, target=args.points, sigma=20.0))]
     workers = max(1, min(16, os.cpu_count() or 1, len(jobs) + args.stream_frames))
     with mp.get_context("fork").Pool(workers) as pool:
         clouds = pool.map(_gen, jobs, chunksize=1)
         out = {"frame": clouds[0]}
-        if not args.no_patterns:
-            first, scale = clouds[13]  # later frames reuse the scale fitted on frame 0
+        k = 1
+        if want_batch:
+            out["batch"] = clouds[k:k + 8]
+            k += 8
+        if want_diff:
+            out["diff"] = clouds[k:k + 4]
+            k += 4
+        if want_stream:
+            first, scale = clouds[k]  # later frames reuse the scale fitted on frame 0
             rest = pool.map(_gen, [("frame", dict(seed=stream_seed, frame=f, target=args.points, sigma=20.0,
                                                   scale=scale)) for f in range(1, args.stream_frames)],
                             chunksize=1)
-            out["batch"] = clouds[1:9]
-            out["diff"] = clouds[9:13]
             out["stream"] = [first] + [c for c, _ in rest]
     return out
 
@@ -316,6 +332,37 @@ def bench_streaming_periodic(frames, prm, dev, fgbd, torch, np, period=10) -> di
             "latency_includes": "device copy of the frame + graph replay; full frames also the host read of q"}
 
 
+def bench_shuffled(cloud, prm, dev, args, fgbd, torch, np) -> dict:
+    """The headline frame with its points in a fixed random order (a capture
+    that is not in raster order): the same K timed fgbd_denoise steps, next to
+    the frame in its raster order."""
+    perm = np.random.default_rng(20240117).permutation(cloud.n)
+    stream = torch.cuda.current_stream(dev)
+    ctx = fgbd.Context(dev)
+    ctx.reserve(prm, cloud.n)
+    out = {}
+    for name, idx in (("raster", None), ("shuffled", perm)):
+        xyz = torch.as_tensor(cloud.xyz if idx is None else cloud.xyz[idx], device=dev)
+        rgb = torch.as_tensor(cloud.noisy if idx is None else cloud.noisy[idx], device=dev)
+        o = torch.empty_like(rgb)
+        res = fgbd.new_result(dev)
+        for _ in range(args.warmup):
+            fgbd.denoise(xyz, rgb, prm, ctx=ctx, out=o, res=res)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fgbd.denoise(xyz, rgb, prm, ctx=ctx, out=o, res=res)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        r = fgbd.read_result(res)
+        out[name] = {"ms_per_frame": e0.elapsed_time(e1) / args.steps, "q": r["q"], "sigma_est": r["sigma_est"]}
+    ctx.close()
+    out["slowdown"] = out["shuffled"]["ms_per_frame"] / out["raster"]["ms_per_frame"]
+    out["workload"] = f"the headline frame ({cloud.n} points) in its raster order and in a fixed random order"
+    return out
+
+
 def bench_io(cloud, prm, dev, fgbd, torch, np, reps: int = 20) -> dict:
     """The steps on either side of the path on the headline frame: its voxel
     coordinates as float32 (voxel centres) quantised onto the 2^b grid, the
@@ -354,6 +401,7 @@ def bench_io(cloud, prm, dev, fgbd, torch, np, reps: int = 20) -> dict:
             row["algorithmic_bytes"] = nbytes
             row["GB_per_s"] = nbytes / us / 1e3
         out[name] = row
+    ctx.close()
     return out
 
 
@@ -423,6 +471,88 @@ def bench_fwd_bwd(clouds, dev, args, fgbd, torch) -> dict:
             "coef": [round(v, 4) for v in coef.detach().cpu().tolist()], "sigma_g": float(sigma_g)}
 
 
+# ---------------------------------------------------------------- CPU baseline
+_CPU_JOB = None  # (xyz, rgb, params) inherited by the forked workers
+
+
+def oracle_params(args) -> dict:
+    """The library's default parameters (fgbd_default_params) for the oracle;
+    main() checks them against the library's own."""
+    return dict(bits=10, num_dirs=args.num_dirs, window=4, k=8, patch=0, q_max=32, fslr_kappa=2.0, sigma_g=0.0,
+                patch_order=0)
+
+
+def _oracle_stages(_=None):
+    """The oracle's per-frame path on the shared frame, its three stages timed
+    as the paper's Table 1 splits them: graph construction (scan-line graph,
+    bandwidth, eq. 4 weights), noise estimation (NE-GBP and the FSLR spreads),
+    low-pass filter (FSLR subset, eq. 6 selection and the eq. 5 sweeps).  The
+    calls are the oracle's own, in the order its denoise() makes them."""
+    import numpy as np
+
+    import oracle
+
+    xyz, rgb, prm = _CPU_JOB
+    g = np.asarray(xyz, np.int64)
+    y = np.asarray(rgb, np.float64)
+    t0 = time.perf_counter()
+    col, dist2 = oracle.slg_graph(g, prm["bits"], prm["num_dirs"], prm["window"], prm["k"])
+    sg = prm["sigma_g"] if prm["sigma_g"] > 0 else oracle.bandwidth(col, dist2)
+    p = oracle.edge_weights(col, dist2, sg)
+    t1 = time.perf_counter()
+    ne = oracle.estimate_noise(col, y, prm["patch"], prm["patch_order"])
+    spread = oracle.patch_spread(col, y, prm["patch"])
+    t2 = time.perf_counter()
+    S = oracle.fslr_subset(spread, ne["sigma_est"], prm["fslr_kappa"])
+    sel = oracle.select_filter(col, p, y, ne["sigma_est"], S, prm["q_max"])
+    t3 = time.perf_counter()
+    return {"GC": t1 - t0, "NE": t2 - t1, "LF": t3 - t2, "q": int(sel["q"])}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cloud, prm: dict) -> dict:
+    """The FP64 oracle on the host: one thread on the headline frame (stage
+    split as in Table 1), then all the host cores this process may use (at
+    most 16), one forked worker per core, each running the same frame, for the
+    aggregate points/s."""
+    import multiprocessing as mp
+
+    global _CPU_JOB
+    _CPU_JOB = (cloud.xyz, cloud.noisy, prm)
+    n = cloud.n
+    c0 = os.times()
+    w0 = time.perf_counter()
+    one = _oracle_stages()
+    wall1 = time.perf_counter() - w0
+    c1 = os.times()
+    busy = (c1.user - c0.user) + (c1.system - c0.system)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    procs = max(1, min(16, cores))
+    w0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        runs = pool.map(_oracle_stages, range(procs), chunksize=1)
+    wall_all = time.perf_counter() - w0
+    _CPU_JOB = None
+    stages = {k: one[k] for k in ("GC", "NE", "LF")}
+    return {"value": procs * n / wall_all, "unit": "points/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} forked processes, each the FP64 numpy oracle on the full headline frame "
+                      f"({n} points); {wall_all:.1f} s wall",
+            "single_thread": {"value": n / wall1, "unit": "points/s", "s_per_frame": wall1,
+                              "cpu_s": busy, "stages_s": stages, "q": one["q"]},
+            "all_cores_s_per_frame_mean": sum(sum(r[k] for k in ("GC", "NE", "LF")) for r in runs) / len(runs),
+            "host": {"nproc": os.cpu_count(), "usable_cores": cores, "cpu_model": _cpu_model()}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,6 +567,8 @@ def main() -> int:
                     help="let the library's autotuner pick the launch schedule of the headline frame first")
     ap.add_argument("--no-patterns", action="store_true",
                     help="skip the batched, streaming and forward+backward measurements")
+    ap.add_argument("--patterns", default="batched,streaming,streaming_periodic,fwd_bwd,io,shuffled",
+                    help="comma-separated patterns to run beside the headline (with --no-patterns: none)")
     ap.add_argument("--stream-frames", type=int, default=30)
     ap.add_argument("--adam-steps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -456,6 +588,9 @@ def main() -> int:
     inputs = make_inputs(args, synth)
     gen_s = time.time() - t0
     cloud = inputs["frame"]
+    # the CPU oracle on the host, also before the GPU is touched (its worker
+    # processes are forked): a reported baseline, not a target
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cloud, oracle_params(args))
 
     import numpy as np
     import torch
@@ -468,6 +603,8 @@ def main() -> int:
     xyz = torch.as_tensor(cloud.xyz, device=dev)
     rgb = torch.as_tensor(cloud.noisy, device=dev)
     prm = fgbd.default_params(num_dirs=args.num_dirs)
+    if dict(prm.as_dict()) != oracle_params(args):
+        raise RuntimeError("the CPU baseline's parameters differ from the library defaults")
     P = prm.patch if prm.patch > 0 else prm.k
     ctx = fgbd.Context(dev)
     ctx.reserve(prm, n)
@@ -594,17 +731,19 @@ def main() -> int:
                                   "bytes_per_launch": b, "us_per_launch": 1e3 * per_launch,
                                   "timing": f"(filter at q={qf} - filter at q=0) / {qf}, one event pair each"}
 
-    if not args.no_patterns:
-        line["batched"] = bench_batched(inputs["batch"], prm, dev, args, fgbd, torch)
-        print(f"# batched: {json.dumps(line['batched'])}", file=sys.stderr, flush=True)
-        line["streaming"] = bench_streaming(inputs["stream"], prm, dev, fgbd, torch, np)
-        print(f"# streaming: {json.dumps(line['streaming'])}", file=sys.stderr, flush=True)
-        line["streaming_periodic"] = bench_streaming_periodic(inputs["stream"], prm, dev, fgbd, torch, np)
-        print(f"# streaming_periodic: {json.dumps(line['streaming_periodic'])}", file=sys.stderr, flush=True)
-        line["fwd_bwd"] = bench_fwd_bwd(inputs["diff"], dev, args, fgbd, torch)
-        print(f"# fwd_bwd: {json.dumps(line['fwd_bwd'])}", file=sys.stderr, flush=True)
-        line["io"] = bench_io(cloud, prm, dev, fgbd, torch, np)
-        print(f"# io: {json.dumps(line['io'])}", file=sys.stderr, flush=True)
+    pats = selected_patterns(args)
+    runs = [
+        ("batched", lambda: bench_batched(inputs["batch"], prm, dev, args, fgbd, torch)),
+        ("streaming", lambda: bench_streaming(inputs["stream"], prm, dev, fgbd, torch, np)),
+        ("streaming_periodic", lambda: bench_streaming_periodic(inputs["stream"], prm, dev, fgbd, torch, np)),
+        ("fwd_bwd", lambda: bench_fwd_bwd(inputs["diff"], dev, args, fgbd, torch)),
+        ("io", lambda: bench_io(cloud, prm, dev, fgbd, torch, np)),
+        ("shuffled", lambda: bench_shuffled(cloud, prm, dev, args, fgbd, torch, np)),
+    ]
+    for name, fn in runs:
+        if name in pats:
+            line[name] = fn()
+            print(f"# {name}: {json.dumps(line[name])}", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)  # 256 MiB
@@ -614,20 +753,9 @@ def main() -> int:
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = {"read": src.numel() * 4, "written": dst.numel() * 4, "launches": 3}
 
-    # ---- CPU oracle on the host (reported baseline, not a target)
-    if not args.no_cpu_baseline:
-        import oracle
-
-        c0 = os.times()
-        w0 = time.perf_counter()
-        oracle.denoise(cloud.xyz, cloud.noisy, dict(prm.as_dict()))
-        wall = time.perf_counter() - w0
-        c1 = os.times()
-        cpu = (c1.user - c0.user) + (c1.system - c0.system)
-        line["cpu_baseline"] = {"value": n / wall, "unit": "points/s", "cores": max(1, round(cpu / wall)),
-                                "kind": "oracle",
-                                "sample": f"one full frame of the same workload ({n} points), FP64 numpy oracle, "
-                                          f"{wall:.1f} s wall"}
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    ctx.close()
     print(json.dumps(line), flush=True)
     return 0
 
