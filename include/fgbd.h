@@ -64,7 +64,7 @@ typedef enum {
   FGBD_E_NOMEM = -2,       /* device allocation of the workspace failed                   */
   FGBD_E_HIP = -3,         /* a HIP runtime call failed (message names it)                 */
   FGBD_E_WORKSPACE = -4,   /* the workspace set with fgbd_set_workspace is too small      */
-  FGBD_E_UNSUPPORTED = -5  /* valid but not supported by this build (e.g. bits > 10)      */
+  FGBD_E_UNSUPPORTED = -5  /* valid but not supported by this build (e.g. codes above 63 bits) */
 } fgbd_status;
 
 /* Device-detected conditions, OR-ed into fgbd_result.status. */
@@ -72,6 +72,16 @@ typedef enum {
 #define FGBD_ST_NO_PATCH 2    /* no point had P neighbours: sigma_est set to 0 (Sec. 2.3)    */
 #define FGBD_ST_BAD_OFFSETS 4 /* batched offsets did not start at 0, decreased, or exceeded
                                  n_total: they were clamped into range before use           */
+#define FGBD_ST_DIST_CLAMPED 32 /* a kept neighbour's squared distance exceeded 2^31 - 1 (grids above
+                                 2^15, neighbours more than 46340 voxels apart): its dist2 entry
+                                 holds 2^31 - 1 and the weights see that value               */
+#define FGBD_ST_RELABELED 16  /* information, not an error: the input's point order was far from
+                                 any spatial order (most points adjacent along scan line 0 lie
+                                 far apart in the input), so the graph was built with the input
+                                 numbering as always, then the noise estimate and the sweeps
+                                 ran with the points renumbered along scan order 0 and the
+                                 output was put back in the input order (same results up to
+                                 the rounding order of the patch-moment block sums)           */
 #define FGBD_ST_SWEEP_STALL 8 /* the sweeps run inside one launch waited longer than their
                                  bound (half a second by default, fgbd_set_sweep_wait) for
                                  each other (the GPU was shared with work that kept blocks
@@ -83,7 +93,11 @@ typedef enum {
 /* Parameters of one run.  fgbd_default_params gives the values used for 1M-point
  * frames (b = 10, L = 8, w = 4, K = 8). */
 typedef struct {
-  int32_t bits;       /* b: coordinates lie in 0 .. 2^b - 1 (Sec. 2.2); 1..10 (codes fit 32 bits) */
+  int32_t bits;       /* b: coordinates lie in 0 .. 2^b - 1 (Sec. 2.2); 1..21, as long as every scan
+                         code of the first num_dirs directions fits 63 bits (3b bits for the axis
+                         directions, 3b + 1 for (1,1,0)-type diagonals, 3b + 2 for the rest): b <= 20
+                         with all 16 directions, b = 21 with the three axis directions.  Codes above
+                         32 bits (b > 10) take more radix passes and a slower neighbour selection. */
   int32_t num_dirs;   /* L: scan directions 1..16; the first three are eqs. 1-3, the rest diagonal
                          lines (Sec. 2.2 mentions them as an alternative)                          */
   int32_t window;     /* w >= 1: candidates are the w predecessors and w successors in each scan
@@ -368,7 +382,7 @@ fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const f
  * coordinates take no part in the bounds and map to 0; an infinite one makes
  * s = 0 (every code 0).
  *   xyz:     device float32 [n][3], read only.
- *   bits:    1..21 (the per-frame calls take 1..10).
+ *   bits:    1..21 (the per-frame calls take the same range, see fgbd_params).
  *   xyz_out: device int32 [n][3], written; must not overlap xyz.
  *   frame:   device double[4], written: lo_x, lo_y, lo_z, s, so a voxel g maps
  *            back to lo + (g + 1/2) / s.  lo is NaN on an axis with no finite

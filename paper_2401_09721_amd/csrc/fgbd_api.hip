@@ -99,7 +99,11 @@ void make_dir_table(int bits, int num_dirs, DirTable *t) {
     di.uh = (int8_t)u[h];
     di.um = (int8_t)u[m];
     di.wm_extra = (int8_t)bit_length(abs(u[m]));
+    // code = ((e_h << B_m) + e_m) << b | g_a with e_j of b + bit_length(|u_j|) bits
+    const int width = (bits + bit_length(abs(u[h]))) + (bits + di.wm_extra) + bits;
+    t->code_bits = width > t->code_bits ? width : t->code_bits;
   }
+  t->passes = t->code_bits <= 32 ? 4 : 4 + (t->code_bits - 32 + 7) / 8;
 }
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -145,6 +149,9 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_p = take(N * pl.K * 4);
   pl.off_spread = take(N * 8);
   pl.off_xbuf = take(3 * N * 16);
+  pl.off_rgbw = take(N * 12);
+  pl.off_colw = take(N * pl.K * 4);
+  pl.off_dist2w = take(N * pl.K * 4);
   pl.off_edge_acc = take((size_t)B * kEdgeSlots * kEdgeVals * 8);
   pl.off_noise_acc = take((size_t)B * pl.E1 * kNoiseSlots * 8);
   pl.off_ctrl = take((size_t)2 * B * sizeof(SweepCtrl));
@@ -166,6 +173,9 @@ Bufs carve(char *ws, const Plan &pl) {
   b.p = (float *)(ws + pl.off_p);
   b.spread = (double *)(ws + pl.off_spread);
   b.xbuf = (float4 *)(ws + pl.off_xbuf);
+  b.rgb_w = (float *)(ws + pl.off_rgbw);
+  b.col_w = (int32_t *)(ws + pl.off_colw);
+  b.dist2_w = (int32_t *)(ws + pl.off_dist2w);
   b.edge_acc = (unsigned long long *)(ws + pl.off_edge_acc);
   b.noise_acc = (unsigned long long *)(ws + pl.off_noise_acc);
   b.ctrl = (SweepCtrl *)(ws + pl.off_ctrl);
@@ -180,7 +190,7 @@ namespace {
 fgbd_status check_params(const fgbd_params *p) {
   if (!p) return fail(FGBD_E_INVALID, "params is NULL");
   if (p->bits < 1) return fail(FGBD_E_INVALID, "bits must be >= 1 (got %d)", p->bits);
-  if (p->bits > 10) return fail(FGBD_E_UNSUPPORTED, "bits > 10 needs codes wider than 32 bits (got %d)", p->bits);
+  if (p->bits > 21) return fail(FGBD_E_UNSUPPORTED, "bits above 21 are not supported (got %d)", p->bits);
   if (p->num_dirs < 1 || p->num_dirs > kMaxDirs)
     return fail(FGBD_E_INVALID, "num_dirs must be in 1..%d (got %d)", kMaxDirs, p->num_dirs);
   if (p->window < 1 || p->window > 64) return fail(FGBD_E_INVALID, "window must be in 1..64 (got %d)", p->window);
@@ -192,6 +202,11 @@ fgbd_status check_params(const fgbd_params *p) {
   if (!isfinite(p->sigma_g)) return fail(FGBD_E_INVALID, "sigma_g must be finite");
   if (p->patch_order != 0 && p->patch_order != 1)
     return fail(FGBD_E_INVALID, "patch_order must be 0 or 1 (got %d)", p->patch_order);
+  DirTable dt;
+  make_dir_table(p->bits, p->num_dirs, &dt);
+  if (dt.code_bits > kMaxCodeBits)
+    return fail(FGBD_E_UNSUPPORTED, "bits %d with %d directions needs %d-bit scan codes (at most %d)", p->bits,
+                p->num_dirs, dt.code_bits, kMaxCodeBits);
   return FGBD_OK;
 }
 
@@ -326,12 +341,18 @@ Run make_run(fgbd_ctx ctx, const Plan &pl, char *ws, const fgbd_params &prm, int
 
 // Graph construction into (col, dist2, p); sigma_g into res.  p == NULL
 // stops after the merge: the sweeps then derive sigma_g and the weights.
-fgbd_status run_slg(const Run &r, const int32_t *xyz, int32_t *col, int32_t *dist2, float *p, fgbd_result *res) {
+fgbd_status run_slg(const Run &r, const int32_t *xyz, int32_t *col, int32_t *dist2, float *p, fgbd_result *res,
+                    const float *rgb = nullptr) {
   const uint64_t *sorted = nullptr;
   HIP_TRY(launch_sort(r, xyz, res, &sorted), "radix sort launch");
   FGBD_PRE(r.pf, kMerge);
-  HIP_TRY(launch_merge(r, sorted, col, dist2), "neighbour merge launch");
+  HIP_TRY(launch_merge(r, xyz, sorted, col, dist2, res), "neighbour merge launch");
   FGBD_POST(r.pf);
+  if (rgb && r.relabel_ok) {  // the per-frame path: renumber clouds whose input order is not spatial
+    FGBD_PRE(r.pf, kMerge);
+    HIP_TRY(launch_relabel(r, sorted, col, dist2, rgb), "relabel launch");
+    FGBD_POST(r.pf);
+  }
   if (p == nullptr) return FGBD_OK;
   FGBD_PRE(r.pf, kWeights);
   HIP_TRY(launch_weights(r, col, dist2, res, p), "weights launch");
@@ -687,7 +708,7 @@ static void request_hint(fgbd_ctx ctx, hipStream_t s, int B) {
 static fgbd_status run_denoise(const Run &r, const int32_t *xyz, const float *rgb_in, float *rgb_out,
                                fgbd_result *res) {
   fgbd_status st;
-  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
+  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res, rgb_in)) != FGBD_OK) return st;
   if (r.prm.k == 8 && r.pl.P == 8 && r.prm.patch_order == 0) {
     // the noise launch gathers each point's row and its neighbours' colours
     // anyway: it also computes the weights and the first sweep's colours, and
@@ -725,6 +746,7 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   r.fold_setup = true;
   r.setup = setup_args(r, nullptr, n, res, 1);
   r.sweep_launches = adaptive_sweep_launches(ctx, s, &r.hint);
+  r.relabel_ok = r.prm.patch_order == 0;  // index-ordered patches need the input numbering
   if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
   if (r.hint) request_hint(ctx, s, 1);
   return ok();
@@ -762,6 +784,7 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
   HIP_TRY(launch_setup(r, offsets, 0, res, n_total == 0 ? 2 : 1), "setup launch");
   if (n_total == 0) return ok();
   r.sweep_launches = adaptive_sweep_launches(ctx, s, &r.hint);
+  r.relabel_ok = r.prm.patch_order == 0;  // index-ordered patches need the input numbering
   if ((st = run_denoise(r, xyz, rgb_in, rgb_out, res)) != FGBD_OK) return st;
   if (r.hint) request_hint(ctx, s, batch);
   return ok();
@@ -785,7 +808,8 @@ fgbd_status fgbd_denoise_batched_fixed_q(fgbd_ctx ctx, const int32_t *xyz, const
   if (n_total == 0) return ok();
   // SLG, then q_fixed sweeps whose first derives sigma_g and the weights;
   // no noise estimate and no selection (every sweep is a launch of its own)
-  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res)) != FGBD_OK) return st;
+  r.relabel_ok = true;
+  if ((st = run_slg(r, xyz, r.b.col, r.b.dist2, nullptr, res, rgb_in)) != FGBD_OK) return st;
   return run_filter(r, r.b.col, r.b.p, r.b.dist2, rgb_in, nullptr, nullptr, 0, q_fixed, rgb_out, res);
 }
 

@@ -66,6 +66,13 @@ struct SweepArgs {
   double sigma_g_fixed;
   fgbd_result *res;
   float *p_out;
+  // per cloud: set when the cloud was renumbered along scan order 0 (NULL:
+  // never); its graph and input colours are then read from col_w, dist2_w
+  // and rgb_w, and the output of point i is the iterate at rank0[i]
+  const int32_t *relabel;
+  const float *rgb_w;
+  const int32_t *col_w, *dist2_w;
+  const uint32_t *rank0;
 };
 
 constexpr int kSlotVals = kSweepSlots * kSweepParts;  // integers per cloud and sweep
@@ -373,7 +380,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int q, const int3
                                                   const fgbd_result *__restrict__ noise) {
   __shared__ SweepLds<D2> lds;
   const SegBlock sb = seg_block(a.sa, kGridSweep);
-  sweep_step<KT, FIRST, D2, PRE>(a, sb, sweep_io(a, q), col, p, rgb_in, xbuf, spread, noise, lds);
+  const float *y = rgb_in;
+  if (a.relabel && a.relabel[sb.s]) {  // a renumbered cloud: its graph and colours in scan-order-0 numbering
+    y = a.rgb_w;
+    col = a.col_w;
+    a.dist2 = a.dist2_w;
+  }
+  sweep_step<KT, FIRST, D2, PRE>(a, sb, sweep_io(a, q), col, p, y, xbuf, spread, noise, lds);
 }
 
 // Waits until every block of the grid has arrived `epoch` times at this
@@ -421,7 +434,8 @@ __device__ __forceinline__ bool all_clouds_done(const SweepCtrl *states, int B) 
 __device__ __forceinline__ void finalize_block(const SegBlock &sb, const SweepCtrl &c, int64_t buf_stride,
                                                const float *__restrict__ rgb_in, const float4 *__restrict__ xbuf,
                                                const fgbd_result *__restrict__ noise, float *__restrict__ rgb_out,
-                                               fgbd_result *__restrict__ res, int32_t *hint) {
+                                               fgbd_result *__restrict__ res, int32_t *hint,
+                                               const uint32_t *__restrict__ rank0) {
   const int best = c.best_buf;
   const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
@@ -432,7 +446,7 @@ __device__ __forceinline__ void finalize_block(const SegBlock &sb, const SweepCt
       rgb_out[3 * i + 1] = rgb_in[3 * i + 1];
       rgb_out[3 * i + 2] = rgb_in[3 * i + 2];
     } else {
-      const float4 x = xbuf[(size_t)best * buf_stride + i];
+      const float4 x = xbuf[(size_t)best * buf_stride + (rank0 ? (int64_t)rank0[i] : i)];
       rgb_out[3 * i + 0] = x.x;
       rgb_out[3 * i + 1] = x.y;
       rgb_out[3 * i + 2] = x.z;
@@ -444,6 +458,7 @@ __device__ __forceinline__ void finalize_block(const SegBlock &sb, const SweepCt
     r->loss = c.best_loss;
     r->n_fslr = c.n_sel;
     r->sweeps = c.q;
+    if (rank0) r->status |= FGBD_ST_RELABELED;
     if (noise != nullptr && noise != res) r->sigma_est = noise[sb.s].sigma_est;
     if (hint != nullptr) hint[sb.s] = c.q;
   }
@@ -455,11 +470,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
                                                      const SweepCtrl *__restrict__ ctrl_prev,
                                                      const fgbd_result *__restrict__ noise,
                                                      float *__restrict__ rgb_out, fgbd_result *__restrict__ res,
-                                                     int32_t *hint) {
+                                                     int32_t *hint, const int32_t *__restrict__ relabel,
+                                                     const uint32_t *__restrict__ rank0) {
   const SegBlock sb = seg_block(sa, kGridSweep);
   SweepCtrl c;
   load_state(c, ctrl_prev + sb.s, sums_prev + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
-  finalize_block(sb, c, buf_stride, rgb_in, xbuf, noise, rgb_out, res, hint);
+  finalize_block(sb, c, buf_stride, rgb_in, xbuf, noise, rgb_out, res, hint,
+                 relabel && relabel[sb.s] ? rank0 : nullptr);
 }
 
 template <int KT>
@@ -472,6 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
   __shared__ SweepLds<false> lds;
   __shared__ int s_flag;
   const SegBlock sb = seg_block(a.sa, kGridSweep);
+  if (a.relabel && a.relabel[sb.s]) col = a.col_w;  // a renumbered cloud's graph
   const int B = a.sa.B;
   // state at the start of the last separate sweep, written by that launch
   const SweepCtrl *last = a.ctrl + ((q0 - 1) & 1) * B;
@@ -508,7 +526,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
     const unsigned long long *sums_last = a.sums3 + (size_t)(q_last % 3) * B * kSlotVals;
     load_state(c, a.ctrl + (q_last & 1) * B + sb.s, sums_last + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
   }
-  finalize_block(sb, c, a.buf_stride, rgb_in, xbuf, noise, rgb_out, a.res, hint);
+  finalize_block(sb, c, a.buf_stride, rgb_in, xbuf, noise, rgb_out, a.res, hint,
+                 a.relabel && a.relabel[sb.s] ? a.rank0 : nullptr);
 }
 
 SweepArgs sweep_args(const Run &r, const int32_t *dist2, float *p_out, fgbd_result *res, int select, int q_limit) {
@@ -526,6 +545,11 @@ SweepArgs sweep_args(const Run &r, const int32_t *dist2, float *p_out, fgbd_resu
   a.sigma_g_fixed = r.prm.sigma_g;
   a.res = res;
   a.p_out = p_out;
+  a.relabel = r.relabel_ok ? r.b.segs->relabel : nullptr;
+  a.rgb_w = r.b.rgb_w;
+  a.col_w = r.b.col_w;
+  a.dist2_w = r.b.dist2_w;
+  a.rank0 = r.b.rank;
   return a;
 }
 
@@ -628,7 +652,8 @@ hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, co
   const unsigned long long *sp = r.b.sums + (q_launches % 3) * S;
   const SweepCtrl *cp = r.b.ctrl + (q_launches & 1) * r.pl.B;
   k_finalize<<<r.pl.grid[kGridSweep], kBlock, 0, r.stream>>>(r.sa, r.pl.n_cap, rgb_in, r.b.xbuf, sp, cp, noise,
-                                                              rgb_out, res, r.hint);
+                                                              rgb_out, res, r.hint,
+                                                              r.relabel_ok ? r.b.segs->relabel : nullptr, r.b.rank);
   return hipGetLastError();
 }
 

@@ -174,12 +174,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
                                                   const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
                                                   int32_t *__restrict__ dist2,
                                                   unsigned long long *__restrict__ edge_acc) {
-  __shared__ double s_red[8];
+  __shared__ double s_red[4 * 3];  // block_sum_f64<3>: three doubles per wave
   __shared__ int s_rank[WT > 0 ? kMaxDirs : 1][kBlock];
   // edge lengths sqrt(d2) of the small squared distances, each computed once
   // per block (the same correctly rounded values as computing them inline)
   __shared__ double s_sqrt[kKeyD2Max + 1];
-  double acc[2] = {0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};  // edge lengths, edges, far edges
   const int L = a.dt.num_dirs;
   const int K = a.K;
   const int bits = a.dt.bits;
@@ -190,6 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
   // the 31-bit keys hold a cloud-local index in 24 bits: a cloud of 2^24 or
   // more points takes the 64-bit selection (uniform over the block)
   const bool fast = sb.end - sb.begin <= (int64_t)(1 << 24);
+  const uint32_t gap = (uint32_t)far_gap(sb.end - sb.begin);  // an edge spanning more indices is far
   __syncthreads();
   const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
@@ -274,10 +275,12 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
       const bool ok = lst[k] != ~0ull;
       const uint32_t d2 = (uint32_t)(lst[k] >> 32);
       cv[k] = ok ? (int32_t)(uint32_t)lst[k] : -1;
+
       dv[k] = ok ? (int32_t)d2 : 0;
       if (ok && k < K) {
         acc[0] += d2 <= kKeyD2Max ? s_sqrt[d2] : sqrt((double)d2);
         acc[1] += 1.0;
+        acc[2] += (uint32_t)abs(cv[k] - i) > gap ? 1.0 : 0.0;
       }
     }
     if (KM == 8 && K == 8) {
@@ -297,13 +300,170 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
       }
     }
   }
-  block_sum_f64<2>(acc, s_red);
+  block_sum_f64<3>(acc, s_red);
   if (threadIdx.x == 0) {
     unsigned long long *e = edge_acc + ((size_t)sb.s * kEdgeSlots + sb.lb % kEdgeSlots) * kEdgeVals;
     const double whole = floor(acc[0]);  // acc[0] >= 0; the fraction below is exact
     atomicAdd(&e[0], (unsigned long long)whole);
     atomicAdd(&e[1], (unsigned long long)llrint((acc[0] - whole) * kEdgeFrac));
     atomicAdd(&e[2], (unsigned long long)acc[1]);
+    atomicAdd(&e[3], (unsigned long long)acc[2]);
+  }
+}
+
+// Selection for grids above 2^10 (codes wider than 32 bits): the sorted items
+// hold only indices, so each candidate's coordinates come from the input;
+// squared distances are 64-bit and the K nearest are kept by (squared
+// distance, index) in a sorted list of pairs.  One thread per point, runtime
+// window.  dist2 saturates at 2^31 - 1 (FGBD_ST_DIST_CLAMPED), which only a
+// neighbour more than 46340 voxels away can reach.
+template <int KM>
+__global__ __launch_bounds__(kBlock) void k_merge_wide(MergeArgs a, const int32_t *__restrict__ xyz,
+                                                       const uint64_t *__restrict__ sorted,
+                                                       const uint32_t *__restrict__ rank, int32_t *__restrict__ col,
+                                                       int32_t *__restrict__ dist2,
+                                                       unsigned long long *__restrict__ edge_acc,
+                                                       fgbd_result *__restrict__ res) {
+  __shared__ double s_red[4 * 3];
+  double acc[3] = {0.0, 0.0, 0.0};  // edge lengths, edges, far edges
+  const int L = a.dt.num_dirs;
+  const int K = a.K;
+  const SegBlock sb = seg_block(a.sa, kGridMerge);
+  const int lo = (int)sb.begin, hi = (int)sb.end - 1;
+  const uint32_t gap = (uint32_t)far_gap(sb.end - sb.begin);
+  int clamped = 0;
+  const Share sh = seg_share(sb, kBlock);
+  for (int64_t base = sh.first; base < sh.end; base += sh.step) {
+    const int i = (int)(base + threadIdx.x);
+    if (i >= sh.end) continue;
+    const int64_t px = xyz[3 * (size_t)i + 0], py = xyz[3 * (size_t)i + 1], pz = xyz[3 * (size_t)i + 2];
+    uint64_t kd[KM];
+    uint32_t kj[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      kd[k] = ~0ull;
+      kj[k] = ~0u;
+    }
+    for (int d = 0; d < L; ++d) {
+      const uint64_t *srt = sorted + (size_t)d * a.stride;
+      const int r = (int)rank[(size_t)d * a.stride + i];
+      const int l = max(r - a.window, lo), h = min(r + a.window, hi);
+      for (int rr = l; rr <= h; ++rr) {
+        if (rr == r) continue;
+        const uint32_t j = (uint32_t)srt[rr];
+        const int64_t dx = xyz[3 * (size_t)j + 0] - px, dy = xyz[3 * (size_t)j + 1] - py,
+                      dz = xyz[3 * (size_t)j + 2] - pz;
+        uint64_t cd = (uint64_t)(dx * dx + dy * dy + dz * dz);
+        uint32_t cj = j;
+        // insert (cd, cj) into the list ordered by (distance, index), once
+        bool dup = false;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) dup |= kd[k] == cd && kj[k] == cj;
+        if (dup) continue;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+          const bool less = cd < kd[k] || (cd == kd[k] && cj < kj[k]);
+          const uint64_t td = kd[k];
+          const uint32_t tj = kj[k];
+          kd[k] = less ? cd : td;
+          kj[k] = less ? cj : tj;
+          cd = less ? td : cd;
+          cj = less ? tj : cj;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      if (k >= K) continue;
+      const bool ok = kj[k] != ~0u;
+      int32_t dv = 0;
+      if (ok) {
+        dv = kd[k] > 0x7fffffffull ? 0x7fffffff : (int32_t)kd[k];
+        clamped |= kd[k] > 0x7fffffffull;
+        acc[0] += sqrt((double)kd[k]);
+        acc[1] += 1.0;
+        acc[2] += (uint32_t)abs((int)kj[k] - i) > gap ? 1.0 : 0.0;
+      }
+      col[(size_t)i * K + k] = ok ? (int32_t)kj[k] : -1;
+      dist2[(size_t)i * K + k] = dv;
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64(clamped != 0) != 0 && lane_id() == 0)
+    atomicOr(&res[sb.s].status, FGBD_ST_DIST_CLAMPED);
+  block_sum_f64<3>(acc, s_red);
+  if (threadIdx.x == 0) {
+    unsigned long long *e = edge_acc + ((size_t)sb.s * kEdgeSlots + sb.lb % kEdgeSlots) * kEdgeVals;
+    const double whole = floor(acc[0]);
+    atomicAdd(&e[0], (unsigned long long)whole);
+    atomicAdd(&e[1], (unsigned long long)llrint((acc[0] - whole) * kEdgeFrac));
+    atomicAdd(&e[2], (unsigned long long)acc[1]);
+    atomicAdd(&e[3], (unsigned long long)acc[2]);
+  }
+}
+
+// Renumbering of a cloud along scan order 0, for clouds whose kept edges
+// mostly span more than far_gap input indices (an input order far from
+// spatial, where every gather of the noise estimate and the sweeps would touch
+// its own cache line): row r of col_w / dist2_w is the row of the point at
+// position r of scan order 0, each neighbour replaced by its own position, and
+// rgb_w[r] is that point's colour.  The rows keep their neighbours and their
+// order (the selection broke ties by input index).  Runs on the merge grid; a
+// cloud left as it is returns at once.
+template <int KT>
+__global__ __launch_bounds__(kBlock) void k_relabel(SegArgs sa, int32_t k_rt, Segs *__restrict__ order,
+                                                    const unsigned long long *__restrict__ edge_acc,
+                                                    const uint64_t *__restrict__ sorted0,
+                                                    const uint32_t *__restrict__ rank0,
+                                                    const int32_t *__restrict__ col, const int32_t *__restrict__ dist2,
+                                                    const float *__restrict__ rgb, int32_t *__restrict__ col_w,
+                                                    int32_t *__restrict__ dist2_w, float *__restrict__ rgb_w) {
+  const int K = KT > 0 ? KT : k_rt;
+  const SegBlock sb = seg_block(sa, kGridMerge);
+  __shared__ unsigned long long s_u[kEdgeVals];
+  if (threadIdx.x < kWave) {  // the cloud's edge and far-edge counts over its slots
+    static_assert(kEdgeSlots == kWave, "one slot per lane");
+    const unsigned long long *e = edge_acc + ((size_t)sb.s * kEdgeSlots + threadIdx.x) * kEdgeVals;
+    unsigned long long all = e[2], far = e[3];
+    for (int o = 32; o > 0; o >>= 1) {
+      all += __shfl_xor(all, o, kWave);
+      far += __shfl_xor(far, o, kWave);
+    }
+    if (threadIdx.x == 0) {
+      s_u[0] = all;
+      s_u[1] = far;
+    }
+  }
+  __syncthreads();
+  if (s_u[0] == 0 || 4ull * s_u[1] <= s_u[0]) return;  // uniform over the block
+  if (sb.lb == 0 && threadIdx.x == 0) order->relabel[sb.s] = 1;
+  const Share sh = seg_share(sb, kBlock);
+  for (int64_t base = sh.first; base < sh.end; base += sh.step) {
+    const int64_t r = base + threadIdx.x;
+    if (r >= sh.end) continue;
+    const int64_t i = (uint32_t)sorted0[r];  // the point at position r
+    rgb_w[3 * r + 0] = rgb[3 * i + 0];
+    rgb_w[3 * r + 1] = rgb[3 * i + 1];
+    rgb_w[3 * r + 2] = rgb[3 * i + 2];
+    if (KT == 8) {
+      const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
+      const int4 *dr = reinterpret_cast<const int4 *>(dist2 + i * 8);
+      const int4 c0 = cr[0], c1 = cr[1];
+      int cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cv[k] = cv[k] >= 0 ? (int)rank0[cv[k]] : -1;
+      int4 *cw = reinterpret_cast<int4 *>(col_w + r * 8);
+      int4 *dw = reinterpret_cast<int4 *>(dist2_w + r * 8);
+      cw[0] = make_int4(cv[0], cv[1], cv[2], cv[3]);
+      cw[1] = make_int4(cv[4], cv[5], cv[6], cv[7]);
+      dw[0] = dr[0];
+      dw[1] = dr[1];
+    } else {
+      for (int k = 0; k < K; ++k) {
+        const int c = col[i * K + k];
+        col_w[r * K + k] = c >= 0 ? (int)rank0[c] : -1;
+        dist2_w[r * K + k] = dist2[i * K + k];
+      }
+    }
   }
 }
 
@@ -360,7 +520,8 @@ __global__ __launch_bounds__(kBlock) void k_weights(SegArgs sa, int32_t k_rt, co
 
 }  // namespace
 
-hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int32_t *dist2) {
+hipError_t launch_merge(const Run &r, const int32_t *xyz, const uint64_t *sorted, int32_t *col, int32_t *dist2,
+                        fgbd_result *res) {
   MergeArgs a;
   a.dt = r.dt;
   a.sa = r.sa;
@@ -372,6 +533,15 @@ hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int3
   const uint32_t *rank = r.b.rank;
   unsigned long long *part = r.b.edge_acc;
   hipStream_t st = r.stream;
+  if (r.dt.passes > kSortPasses) {  // codes above 32 bits: items hold indices only
+    if (k <= 8)
+      k_merge_wide<8><<<nb, kBlock, 0, st>>>(a, xyz, sorted, rank, col, dist2, part, res);
+    else if (k <= 16)
+      k_merge_wide<16><<<nb, kBlock, 0, st>>>(a, xyz, sorted, rank, col, dist2, part, res);
+    else
+      k_merge_wide<32><<<nb, kBlock, 0, st>>>(a, xyz, sorted, rank, col, dist2, part, res);
+    return hipGetLastError();
+  }
   // the compile-time-window kernels take 64-bit keys for a cloud of more
   // than 2^24 points (their 31-bit keys hold a cloud-local index)
   if (k <= 8 && window == 4)
@@ -388,6 +558,19 @@ hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int3
     k_merge<16, 0><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
   else
     k_merge<32, 0><<<nb, kBlock, 0, st>>>(a, sorted, rank, col, dist2, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_relabel(const Run &r, const uint64_t *sorted, const int32_t *col, const int32_t *dist2,
+                          const float *rgb) {
+  if (!r.relabel_ok) return hipSuccess;
+  const int nb = r.pl.grid[kGridMerge];
+  if (r.prm.k == 8)
+    k_relabel<8><<<nb, kBlock, 0, r.stream>>>(r.sa, 8, r.b.segs, r.b.edge_acc, sorted, r.b.rank, col, dist2, rgb,
+                                              r.b.col_w, r.b.dist2_w, r.b.rgb_w);
+  else
+    k_relabel<0><<<nb, kBlock, 0, r.stream>>>(r.sa, r.prm.k, r.b.segs, r.b.edge_acc, sorted, r.b.rank, col, dist2,
+                                              rgb, r.b.col_w, r.b.dist2_w, r.b.rgb_w);
   return hipGetLastError();
 }
 

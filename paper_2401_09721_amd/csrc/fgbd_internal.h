@@ -27,7 +27,11 @@ struct DirTable {
   DirInfo d[kMaxDirs];
   int32_t bits;
   int32_t num_dirs;
+  int32_t code_bits;  // widest code of the table's first num_dirs directions
+  int32_t passes;     // radix passes of 8 bits: 4 for codes of up to 32 bits, 4 + more for the bits above
 };
+// Codes wider than 32 bits (bits > 10): items carry 32 code bits at a time.
+constexpr int kMaxCodeBits = 63;
 void make_dir_table(int bits, int num_dirs, DirTable *t);
 
 __device__ __forceinline__ uint32_t scan_code(int gx, int gy, int gz, const DirInfo &di, int bits) {
@@ -155,7 +159,17 @@ struct Segs {
   int32_t start[kMaxSeg + 1];
   int32_t tile_first[kMaxSeg + 1];
   int32_t blk_first[kNumGrids][kMaxSeg + 1];
+  // Per cloud: set by the relabel launch when more than a quarter of the
+  // kept edges are far (the merge's counts in the edge-length sums); 0 at
+  // setup.
+  int32_t relabel[kMaxSeg];
 };
+// An edge is far when its points are more than a sixteenth of the cloud, and
+// more than 4096 points, apart in the input numbering (a raster order keeps
+// the neighbours of a 1M-point frame within a few thousand indices).
+__host__ __device__ inline int64_t far_gap(int64_t cloud_n) {
+  return cloud_n / 16 > 4096 ? cloud_n / 16 : 4096;
+}
 
 // How kernels find their cloud: n_fixed >= 0 means one cloud of n_fixed
 // points known on the host (the table is not read); otherwise B clouds from
@@ -243,7 +257,9 @@ constexpr int kExpTable = 256;
 // block's sum is rounded by at most 2^-41).  Blocks spread their atomics over
 // kEdgeSlots slots (block index mod kEdgeSlots): thousands of blocks adding
 // into one word serialise.
-constexpr int kEdgeVals = 3;  // integer part, fraction * 2^40, count
+// integer part, fraction * 2^40, count, and the count of far edges (two
+// points more than far_gap(cloud size) apart in the input numbering)
+constexpr int kEdgeVals = 4;
 constexpr int kEdgeSlots = 64;
 constexpr double kEdgeFrac = 1099511627776.0;  // 2^40
 
@@ -339,7 +355,7 @@ struct Plan {
   int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)
   int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
   size_t off_segs, off_items_a, off_items_b, off_hist, off_rank, off_digits;
-  size_t off_col, off_dist2, off_p, off_spread, off_xbuf;
+  size_t off_col, off_dist2, off_p, off_spread, off_xbuf, off_rgbw, off_colw, off_dist2w;
   size_t off_edge_acc, off_noise_acc, off_ctrl, off_sweep_sums;
   size_t total;
 };
@@ -391,6 +407,9 @@ struct Bufs {
   float *p;                     // [n_cap][K] weights the fused path's first sweep stores
   double *spread;               // [n_cap]
   float4 *xbuf;                 // [3][n_cap]
+  // a relabelled cloud's graph and colours in scan-order-0 numbering
+  float *rgb_w;                 // [n_cap][3]
+  int32_t *col_w, *dist2_w;     // [n_cap][K]
   unsigned long long *edge_acc;  // [B][kEdgeSlots][kEdgeVals] edge-length sums for sigma_g
   unsigned long long *noise_acc;  // [B][kNoiseSlots][E1] fixed-point patch moments
   SweepCtrl *ctrl;              // [2][B]
@@ -446,6 +465,10 @@ struct Run {
   hipStream_t stream;
   Prof *pf;
   int32_t sweep_launches;  // sweeps enqueued as launches of their own
+  // the per-frame path may relabel points into scan order 0 when the input's
+  // point order is incoherent (not for graphs handed to the caller, nor for
+  // index-ordered patches)
+  bool relabel_ok = false;
   int32_t *hint = nullptr;  // host-mapped: the finalising launch stores each cloud's sweep count here
   // bound of each wait between sweeps in the in-launch sweep loop, in
   // microseconds (negative: half a second)
@@ -464,7 +487,19 @@ SetupArgs setup_args(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_
 
 hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const uint64_t **sorted_out);
 
-hipError_t launch_merge(const Run &r, const uint64_t *sorted, int32_t *col, int32_t *dist2);
+// With r.relabel_ok the merge also counts each cloud's far edges.
+// xyz: the input coordinates (read by the selection for codes above 32 bits);
+// res: FGBD_ST_DIST_CLAMPED is set there when a kept squared distance does not
+// fit int32.
+hipError_t launch_merge(const Run &r, const int32_t *xyz, const uint64_t *sorted, int32_t *col, int32_t *dist2,
+                        fgbd_result *res);
+
+// Relabelling (only when r.relabel_ok): for every cloud whose kept edges are
+// mostly far apart in the input numbering, the graph (col, dist2) and the
+// colours rgb renumbered along scan order 0 into r.b.col_w, dist2_w, rgb_w,
+// and the cloud's relabel flag set; other clouds are left as they are.
+hipError_t launch_relabel(const Run &r, const uint64_t *sorted, const int32_t *col, const int32_t *dist2,
+                          const float *rgb);
 
 // sigma_g of each cloud (the fixed value or the mean merge edge length, into
 // res[s].sigma_g) and the row-normalised weights p.

@@ -84,6 +84,11 @@ struct NoiseArgs {
   fgbd_result *res;  // receives sigma_g
   float *p_out;      // the weights, for the later sweeps
   float4 *x1;        // the first sweep's output buffer
+  // per cloud: set when the cloud was renumbered along scan order 0 (NULL:
+  // never); its graph and colours are then read from col_w, dist2_w, rgb_w
+  const int32_t *relabel;
+  const float *rgb_w;
+  const int32_t *col_w, *dist2_w;
 };
 
 // Adds entry e of a block's patch moments into its cloud's accumulators
@@ -524,7 +529,7 @@ __device__ __forceinline__ bool fused_point8(const NoiseArgs &a, int64_t i, cons
 
 template <int PT, bool EIG3>
 __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__restrict__ col,
-                                                  const float *__restrict__ rgb, double *__restrict__ spread,
+                                                  const float *__restrict__ rgb_in, double *__restrict__ spread,
                                                   float *__restrict__ eig3, unsigned long long *__restrict__ acc_all) {
   extern __shared__ float s_v[];  // [3 * TP][D] patch rows of the current tile
   __shared__ uint16_t s_pair[kMaxD * (kMaxD + 1) / 2];
@@ -553,6 +558,13 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
   __syncthreads();
 
   const SegBlock sb = seg_block(a.sa, kGridNoise);
+  // a renumbered cloud reads its graph and colours in scan-order-0 numbering
+  const bool relabelled = a.relabel && a.relabel[sb.s];
+  const float *__restrict__ rgb = relabelled ? a.rgb_w : rgb_in;
+  if (relabelled) {
+    col = a.col_w;
+    a.dist2 = a.dist2_w;
+  }
   const Share sh = seg_share(sb, TP);
   for (int64_t tbase = sh.first; tbase < sh.end; tbase += sh.step) {
     if (t < TP) {
@@ -666,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_noise(NoiseArgs a, const int32_t *__
 // of floats are exact in FP64; the accumulation order is fixed.
 template <int PT, bool EIG3, bool FUSE>
 __global__ __launch_bounds__(kBlock, 4) void k_noise_mfma(NoiseArgs a, const int32_t *__restrict__ col,
-                                                       const float *__restrict__ rgb, double *__restrict__ spread,
+                                                       const float *__restrict__ rgb_in, double *__restrict__ spread,
                                                        float *__restrict__ eig3,
                                                        unsigned long long *__restrict__ acc_all) {
   constexpr int D = PT + 1;
@@ -689,6 +701,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_noise_mfma(NoiseArgs a, const int
   double c1[4] = {0.0, 0.0, 0.0, 0.0}, c2[2] = {0.0, 0.0};
 
   const SegBlock sb = seg_block(a.sa, kGridNoise);
+  // a renumbered cloud reads its graph and colours in scan-order-0 numbering
+  const bool relabelled = a.relabel && a.relabel[sb.s];
+  const float *__restrict__ rgb = relabelled ? a.rgb_w : rgb_in;
+  if (relabelled) {
+    col = a.col_w;
+    a.dist2 = a.dist2_w;
+  }
   __shared__ double s_exp[FUSE ? kExpTable : 1];
   __shared__ unsigned long long s_u[kEdgeVals];
   double sg = 0.0;
@@ -978,6 +997,10 @@ NoiseArgs make_args(const SegArgs &sa, int k, int P, bool want_eig3) {
   a.res = nullptr;
   a.p_out = nullptr;
   a.x1 = nullptr;
+  a.relabel = nullptr;
+  a.rgb_w = nullptr;
+  a.col_w = nullptr;
+  a.dist2_w = nullptr;
   return a;
 }
 
@@ -987,6 +1010,12 @@ hipError_t launch_noise(const Run &r, const int32_t *col, const float *rgb, doub
                         fgbd_result *fuse_res) {
   NoiseArgs a = make_args(r.sa, r.prm.k, r.pl.P, eig3 != nullptr);
   a.order = r.prm.patch_order;
+  if (r.relabel_ok) {
+    a.relabel = r.b.segs->relabel;
+    a.rgb_w = r.b.rgb_w;
+    a.col_w = r.b.col_w;
+    a.dist2_w = r.b.dist2_w;
+  }
   const bool fuse = fuse_res != nullptr;
   if (fuse) {
     if (a.P != 8 || a.K != 8 || eig3 != nullptr || a.order != 0) return hipErrorInvalidValue;

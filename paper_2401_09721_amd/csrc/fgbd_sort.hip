@@ -16,6 +16,14 @@
 // sorted item with the point's packed coordinates (x | y << b | z << 2b) in
 // place of its code.
 //
+// Grids above 2^10 (b = 11..21) give codes of up to 63 bits.  Items then carry
+// the code 32 bits at a time: passes 0-3 sort by the low 32 bits, pass 3
+// re-keys every item with the high bits of its code (made again from the
+// point's coordinates), and passes 4.. sort by those (LSD over digit groups:
+// the order is by the whole code).  The last pass then stores only the index
+// (packed coordinates no longer fit beside it) and the neighbour search reads
+// coordinates from the input.
+//
 // Several clouds are sorted in the same launches, each inside its own range
 // of positions: tiles never straddle two clouds, the scan runs over all tiles
 // of each digit and also stores the total after the last tile, and with P the
@@ -33,8 +41,9 @@ struct SortArgs {
   SegArgs sa;
   int64_t stride;     // items per direction (capacity)
   int32_t row;        // hist row length (tile capacity + 1: the row total)
-  int32_t shift;      // digit shift of this pass
+  int32_t shift;      // digit shift of this pass inside the item's 32 code bits
   int32_t pass;
+  int32_t passes;     // passes of the sort (4, or more for codes above 32 bits)
   int32_t fold;       // pass 0 only: the first blocks also do the call's setup
   SetupArgs su;
 };
@@ -136,6 +145,16 @@ __device__ __forceinline__ uint32_t gen_code(const CodeGen &c, int gx, int gy, i
   return (((eh << c.wm) + em) << c.bits) | (uint32_t)ga;
 }
 
+// The code's bits above 32 (codes of grids above 2^10).
+__device__ __forceinline__ uint32_t gen_code_hi(const CodeGen &c, int gx, int gy, int gz) {
+  const int ga = c.ia == 0 ? gx : (c.ia == 1 ? gy : gz);
+  const int gh = c.ih == 0 ? gx : (c.ih == 1 ? gy : gz);
+  const int gm = c.im == 0 ? gx : (c.im == 1 ? gy : gz);
+  const uint64_t eh = (uint32_t)(gh - c.uh * ga) + c.oh;
+  const uint64_t em = (uint32_t)(gm - c.um * ga) + c.om;
+  return (uint32_t)((((eh << c.wm) + em) << c.bits | (uint32_t)ga) >> 32);
+}
+
 // The inverse of gen_code, packed as x | y << b | z << 2b (b = grid bits).
 __device__ __forceinline__ uint32_t decode_packed(const CodeGen &c, uint32_t code) {
   const uint32_t top = (1u << c.bits) - 1u;
@@ -179,6 +198,7 @@ __device__ __forceinline__ void setup_work(const SetupArgs &a, int block) {
   for (int i = block * blockDim.x + t; i < a.noise_count; i += stride) a.noise_acc[i] = 0ull;
   for (int i = block * blockDim.x + t; i < a.edge_count; i += stride) a.edge_acc[i] = 0ull;
   if (block != 0) return;  // uniform over the block
+  if (t < kMaxSeg) sg->relabel[t] = 0;
   const int B = a.B;
   if (t <= B) s_raw[t] = a.offsets ? a.offsets[t] : (t == 0 ? 0 : a.n_host);
   __syncthreads();
@@ -444,7 +464,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   __shared__ uint64_t s_stage[kSortTile];
 
   int d, tile;
-  if (a.pass == kSortPasses - 1)
+  if (a.pass == a.passes - 1)
     xcd_tile_last(d, tile);
   else
     xcd_tile(d, tile);
@@ -528,7 +548,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   }
   __syncthreads();
 
-  const bool last_pass = (a.pass == kSortPasses - 1);
+  const bool last_pass = (a.pass == a.passes - 1);
+  const bool wide = a.passes > kSortPasses;
+  const bool rekey = wide && a.pass == kSortPasses - 1;  // the low 32 code bits are done
   uint64_t *out = dst + (size_t)d * a.stride;
   uint8_t *dig = digits + (size_t)d * a.stride;
   for (int s = t; s < valid; s += kSortThreads) {
@@ -537,9 +559,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
     const uint32_t gpos = s_off[digit] + (uint32_t)s - s_base[digit];
     if (last_pass) {
       // the sorted item keeps its index and carries the point's packed
-      // coordinates instead of its code (the neighbour search's form)
-      out[gpos] = ((uint64_t)decode_packed(cg, (uint32_t)(it >> 32)) << 32) | (uint32_t)it;
-      rank[(size_t)d * a.stride + (uint32_t)it] = gpos;
+      // coordinates instead of its code (the neighbour search's form); wide
+      // codes keep the index only
+      const uint32_t idx = (uint32_t)it;
+      out[gpos] = wide ? (uint64_t)idx : ((uint64_t)decode_packed(cg, (uint32_t)(it >> 32)) << 32) | idx;
+      rank[(size_t)d * a.stride + idx] = gpos;
+    } else if (rekey) {
+      // the item's key becomes the code's bits above 32
+      const uint32_t idx = (uint32_t)it;
+      const uint32_t hi = gen_code_hi(cg, xyz[3 * (size_t)idx + 0], xyz[3 * (size_t)idx + 1], xyz[3 * (size_t)idx + 2]);
+      out[gpos] = ((uint64_t)hi << 32) | idx;
+      dig[gpos] = (uint8_t)hi;  // the next pass's digit
     } else {
       out[gpos] = it;
       dig[gpos] = (uint8_t)(it >> (40 + a.shift));  // the next pass's digit
@@ -589,9 +619,10 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
   const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
   const uint64_t *src = nullptr;
   uint64_t *bufs[2] = {r.b.items_a, r.b.items_b};
-  for (int pass = 0; pass < kSortPasses; ++pass) {
+  a.passes = r.dt.passes;
+  for (int pass = 0; pass < a.passes; ++pass) {
     a.pass = pass;
-    a.shift = 8 * pass;
+    a.shift = 8 * (pass % kSortPasses);
     uint64_t *dst = bufs[pass & 1];
     FGBD_PRE(r.pf, kUpsweep);
     a.fold = (pass == 0 && r.fold_setup) ? 1 : 0;

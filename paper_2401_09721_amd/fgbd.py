@@ -27,6 +27,8 @@ FGBD_ST_COORD_RANGE = 1
 FGBD_ST_NO_PATCH = 2
 FGBD_ST_BAD_OFFSETS = 4
 FGBD_ST_SWEEP_STALL = 8
+FGBD_ST_RELABELED = 16
+FGBD_ST_DIST_CLAMPED = 32
 NUM_KERNELS = 9
 ABI_VERSION = 6
 MAX_BATCH = 64

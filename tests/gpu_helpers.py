@@ -32,7 +32,10 @@ def compare_denoise(out, r, xyz, rgb, prm, ores=None, status_mask=~0):
     assert abs(r["sigma_est"] - ores["sigma_est"]) <= COLOUR_TOL
     assert math.isclose(r["sigma_g"], ores["sigma_g"], rel_tol=1e-12, abs_tol=1e-300)
     assert r["n_eff"] == ores["n_eff"]
-    assert (r["status"] & status_mask) == ores["status"]
+    # FGBD_ST_RELABELED reports how the path ran (an incoherent input order
+    # was renumbered along scan order 0), not a property of the result
+    from paper_2401_09721_amd import fgbd
+    assert (r["status"] & status_mask & ~fgbd.FGBD_ST_RELABELED) == ores["status"]
     q = r["q"]
     if q != ores["q"]:
         en = ores["energies"]

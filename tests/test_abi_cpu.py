@@ -96,10 +96,21 @@ def test_invalid_params_rejected(ctx, bad):
     assert lib.fgbd_workspace_size(ctypes.byref(p), 10, 1, ctypes.byref(out)) == fgbd.FGBD_E_INVALID
 
 
-def test_bits_above_10_unsupported(ctx):
-    p = fgbd.default_params(bits=11)
-    st = fgbd.lib().fgbd_denoise(ctx, FAKE, FAKE, 100, ctypes.byref(p), ctypes.c_void_p(0x900000), FAKE, None)
-    assert st == fgbd.FGBD_E_UNSUPPORTED
+def test_grid_bits_and_code_width_limits(ctx):
+    """Grids up to 2^21 are taken as long as every scan code of the chosen
+    directions fits 63 bits: axis directions 3b bits, (1,1,0)-type diagonals
+    3b + 1, (1,1,1) and the (1,2,0)-type 3b + 2."""
+    lib = fgbd.lib()
+    out = ctypes.c_size_t()
+    for bits, dirs, ok in [(11, 8, True), (16, 16, True), (20, 16, True), (21, 3, True), (21, 4, False),
+                           (21, 10, False), (21, 16, False), (22, 3, False)]:
+        p = fgbd.default_params(bits=bits, num_dirs=dirs)
+        st = lib.fgbd_workspace_size(ctypes.byref(p), 1000, 1, ctypes.byref(out))
+        assert st == (fgbd.FGBD_OK if ok else fgbd.FGBD_E_UNSUPPORTED), (bits, dirs)
+        if not ok:
+            st = lib.fgbd_denoise(ctx, FAKE, FAKE, 100, ctypes.byref(p), ctypes.c_void_p(0x900000), FAKE, None)
+            assert st == fgbd.FGBD_E_UNSUPPORTED
+            assert "bits" in lib.fgbd_last_error().decode()
 
 
 def test_null_and_size_errors(ctx):
