@@ -56,7 +56,7 @@ KIND_SOURCES = {
     "radix_upsweep": ("fgbd_sort.hip",), "radix_scan": ("fgbd_sort.hip",), "radix_downsweep": ("fgbd_sort.hip",),
     "merge": ("fgbd_graph.hip",), "weights": ("fgbd_graph.hip",),
     "noise": ("fgbd_noise.hip",), "noise_solve": ("fgbd_noise.hip",),
-    "sweep": ("fgbd_filter.hip",), "finalize": ("fgbd_filter.hip",),
+    "sweep": ("fgbd_filter.hip",), "finalize": ("fgbd_filter.hip",), "relabel": ("fgbd_graph.hip",),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fgbd_1M_frame.md")
 
@@ -175,13 +175,63 @@ def bench_batched(clouds, prm, dev, args, fgbd, torch) -> dict:
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     rs = fgbd.read_results(res)
+    out_line = {"workload": f"{len(clouds)} body clouds of {min(sizes)}-{max(sizes)} points (sizes uniform in "
+                            f"200k-1.2M), noise sigma uniform in [5, 35], 2^10 grid, one batched call",
+                "n_points": total, "clouds": len(clouds), "sizes": sizes, "steps": steps,
+                "ms_per_batch": ms, "points_per_s": total / (ms / 1e3), "clouds_per_s": len(clouds) / (ms / 1e3),
+                "schedule": schedule, "default_schedule": default, "autotune_s": tune_s,
+                "q": [r["q"] for r in rs], "sigma_est": [round(r["sigma_est"], 3) for r in rs]}
+    if not args.no_profile:
+        P = prm.patch if prm.patch > 0 else prm.k
+        # Per-kernel HIP events over the same calls.  A sweep launch moves the
+        # sweep's bytes for each cloud whose selection is still running, so
+        # the sweep's bytes per batch are the sum over clouds of sweeps x bytes.
+        ctx.profile(True)
+        ctx.profile_read()
+        for _ in range(steps):
+            fgbd.denoise_batched(xyz, rgb, offsets, prm, ctx=ctx, out=out, res=res)
+        torch.cuda.synchronize()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        rs = fgbd.read_results(res)
+        sweep_bytes = sum(algorithmic_bytes("sweep", n_s, prm.num_dirs, prm.k, P) * r["sweeps"]
+                          for n_s, r in zip(sizes, rs))
+        kernels = {}
+        for kind, (kms, launches) in prof.items():
+            if launches == 0:
+                continue
+            per_step = kms / steps
+            b = (sweep_bytes if kind == "sweep"
+                 else algorithmic_bytes(kind, total, prm.num_dirs, prm.k, P) * launches / steps)
+            kernels[kind] = {"ms_per_step": per_step, "launches_per_step": launches / steps,
+                             "us_per_launch": 1e3 * kms / launches,
+                             "algo_GBs": (b / (per_step / 1e3) / 1e9) if b else None}
+        out_line["kernels"] = kernels
+        out_line["sweeps"] = [r["sweeps"] for r in rs]
+        # Active sweeps on the whole batch (its sweep arrays exceed the
+        # 256 MB last-level cache): every cloud filtered at a fixed q, one
+        # event pair around q = 32 and one around q = 0, difference / 32.
+        qf = 32
+        fgbd.denoise_batched_fixed_q(xyz, rgb, offsets, qf, prm, ctx=ctx, out=out, res=res)
+        torch.cuda.synchronize()
+        times = {}
+        for q in (qf, 0):
+            a0, a1 = _events(torch)
+            a0.record()
+            for _ in range(steps):
+                fgbd.denoise_batched_fixed_q(xyz, rgb, offsets, q, prm, ctx=ctx, out=out, res=res)
+            a1.record()
+            torch.cuda.synchronize()
+            times[q] = a0.elapsed_time(a1) / steps
+        per_sweep = (times[qf] - times[0]) / qf
+        b = algorithmic_bytes("sweep", total, prm.num_dirs, prm.k, P)
+        out_line["roofline_sweep"] = {"kernel": "sweep (fixed q, every launch active)", "bound": "hbm",
+                                      "achieved": b / (per_sweep / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": b / (per_sweep / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                      "bytes_per_launch": b, "us_per_launch": 1e3 * per_sweep,
+                                      "timing": f"(batch at q={qf} - batch at q=0) / {qf}, one event pair each"}
     ctx.close()
-    return {"workload": f"{len(clouds)} body clouds of {min(sizes)}-{max(sizes)} points (sizes uniform in "
-                        f"200k-1.2M), noise sigma uniform in [5, 35], 2^10 grid, one batched call",
-            "n_points": total, "clouds": len(clouds), "sizes": sizes, "steps": steps,
-            "ms_per_batch": ms, "points_per_s": total / (ms / 1e3), "clouds_per_s": len(clouds) / (ms / 1e3),
-            "schedule": schedule, "default_schedule": default, "autotune_s": tune_s,
-            "q": [r["q"] for r in rs], "sigma_est": [round(r["sigma_est"], 3) for r in rs]}
+    return out_line
 
 
 def bench_streaming(frames, prm, dev, fgbd, torch, np) -> dict:

@@ -433,10 +433,11 @@ const char *fgbd_last_error(void);
  * counters.  Kinds:
  *   0 radix upsweep (digit counts; pass 0 also makes the codes), 1 radix scan,
  *   2 radix downsweep (stable scatter), 3 neighbour merge, 4 edge weights,
- *   5 patch statistics, 6 noise eigen-solve, 7 filter sweep, 8 finalise.
+ *   5 patch statistics, 6 noise eigen-solve, 7 filter sweep, 8 finalise,
+ *   9 renumbering of clouds stored in no spatial order.
  * The event records add a little time of their own between launches.
  * ms, launches: host arrays of `count` entries (count <= FGBD_NUM_KERNELS). */
-#define FGBD_NUM_KERNELS 9
+#define FGBD_NUM_KERNELS 10
 fgbd_status fgbd_profile_enable(fgbd_ctx ctx, int32_t enable);
 fgbd_status fgbd_profile_read(fgbd_ctx ctx, double *ms, int64_t *launches, int32_t count);
 

@@ -349,7 +349,7 @@ fgbd_status run_slg(const Run &r, const int32_t *xyz, int32_t *col, int32_t *dis
   HIP_TRY(launch_merge(r, xyz, sorted, col, dist2, res), "neighbour merge launch");
   FGBD_POST(r.pf);
   if (rgb && r.relabel_ok) {  // the per-frame path: renumber clouds whose input order is not spatial
-    FGBD_PRE(r.pf, kMerge);
+    FGBD_PRE(r.pf, kRelabel);
     HIP_TRY(launch_relabel(r, sorted, col, dist2, rgb), "relabel launch");
     FGBD_POST(r.pf);
   }

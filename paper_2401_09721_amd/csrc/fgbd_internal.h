@@ -418,7 +418,8 @@ struct Bufs {
 Bufs carve(char *ws, const Plan &pl);
 
 // ------------------------------------------------------------- profiling
-enum Kind { kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kNoiseSolve, kSweep, kFinalize, kNumKinds };
+enum Kind { kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kNoiseSolve, kSweep, kFinalize, kRelabel, kNumKinds };
+static_assert(kNumKinds == FGBD_NUM_KERNELS, "one profiling slot per kernel kind");
 // Optional per-launch timing hook (events around each launch).
 struct Prof {
   virtual void pre(int kind) = 0;

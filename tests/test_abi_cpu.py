@@ -280,12 +280,15 @@ def test_workspace_setting(ctx):
 
 def test_profile_calls(ctx):
     lib = fgbd.lib()
-    ms = (ctypes.c_double * 9)()
-    nl = (ctypes.c_int64 * 9)()
+    k = fgbd.NUM_KERNELS
+    ms = (ctypes.c_double * (k + 1))()
+    nl = (ctypes.c_int64 * (k + 1))()
     assert lib.fgbd_profile_enable(ctx, 1) == 0
-    assert lib.fgbd_profile_read(ctx, ms, nl, 9) == 0
-    assert list(nl) == [0] * 9
-    assert lib.fgbd_profile_read(ctx, ms, nl, 10) == fgbd.FGBD_E_INVALID
+    assert lib.fgbd_profile_read(ctx, ms, nl, k) == 0
+    assert list(nl)[:k] == [0] * k
+    assert lib.fgbd_profile_read(ctx, ms, nl, k - 1) == 0  # fewer kinds than there are is allowed
+    assert lib.fgbd_profile_read(ctx, ms, nl, k + 1) == fgbd.FGBD_E_INVALID
+    assert len(fgbd.KERNELS) == k
 
 
 # ------------------------------------------------ binding argument checks
