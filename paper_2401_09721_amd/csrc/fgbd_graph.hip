@@ -200,14 +200,21 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
     if (WT > 0 && !fast) {
       select_exact<KM>(a, i, lo, hi, a.window, sorted, rank, lst);
     } else if constexpr (WT > 0) {
+      // the first 8 directions' ranks load unconditionally (a direction
+      // index past L - 1 re-reads the last one) so all loads are in flight
+      // together; a conditional load per direction would be waited for
+      // before the next is issued
+      int rv[8];
 #pragma unroll
-      for (int d = 0; d < kMaxDirs; ++d)
-        if (d < L) s_rank[d][t] = (int)rank[(size_t)d * a.stride + i];
+      for (int d = 0; d < 8; ++d) rv[d] = (int)rank[(size_t)min(d, L - 1) * a.stride + i];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) s_rank[d][t] = rv[d];
+      for (int d = 8; d < L; ++d) s_rank[d][t] = (int)rank[(size_t)d * a.stride + i];
       uint32_t key[KM];
 #pragma unroll
       for (int k = 0; k < KM; ++k) key[k] = ~0u;
       // the point's own packed coordinates (the same item in every order)
-      const Pt pi = unpack_pt((uint32_t)(sorted[s_rank[0][t]] >> 32), bits);
+      const Pt pi = unpack_pt((uint32_t)(sorted[rv[0]] >> 32), bits);
       for (int d = 0; d < L; ++d) {
         const uint64_t *srt = sorted + (size_t)d * a.stride;
         const int r = s_rank[d][t];

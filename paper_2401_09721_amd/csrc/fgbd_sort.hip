@@ -459,7 +459,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
                                                                  fgbd_result *__restrict__ res) {
   __shared__ uint32_t s_wh[4][256];
   __shared__ uint32_t s_off[256];
-  __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_tmp[2][4];
   __shared__ uint64_t s_stage[kSortTile];
 
@@ -501,50 +500,63 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
 
   // Stable rank of each item among the equal digits of its wave: items are
   // visited in tile order (j major, lane minor within the wave).  The lanes
-  // holding the same digit are those that agree with it on all 8 ballots:
-  // with m = bit b of the digit spread over the word (0 or all ones), a lane
-  // keeps ~(vote ^ m), a pattern the compiler folds into 3-input bit
-  // operations.
-  uint32_t rk[kSortItems];
+  // holding the same digit (its peers) are those that agree with it on all 8
+  // ballots: with m = bit b of the digit spread over the word (0 or all
+  // ones), a lane keeps ~(vote ^ m).  Each round every lane reads the wave's
+  // count of its digit over the earlier rounds, and the first lane of each
+  // group of peers then adds the group's size to it.  A wave's LDS
+  // operations are performed in the order they are issued, so the rounds
+  // need no wait between them: the reads are waited for once, after the last
+  // round, and each item's rank is that count plus its peers in lower lanes.
+  uint32_t rk[kSortItems], before[kSortItems];
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const uint32_t digit = digit_of(item[j], a.shift);
-    uint32_t plo = ~0u, phi = ~0u;
+    int32_t m[8];
+    uint64_t vote[8];
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const int32_t m = bit_mask(digit, b);
-      const uint64_t vote = __builtin_amdgcn_ballot_w64(m != 0);
-      plo &= ~((uint32_t)vote ^ (uint32_t)m);
-      phi &= ~((uint32_t)(vote >> 32) ^ (uint32_t)m);
+      m[b] = bit_mask(digit, b);
+      vote[b] = __builtin_amdgcn_ballot_w64(m[b] != 0);
+    }
+    uint32_t plo = ~0u, phi = ~0u;  // lanes that agree with this one in every bit
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      plo &= ~((uint32_t)vote[b] ^ (uint32_t)m[b]);
+      phi &= ~((uint32_t)(vote[b] >> 32) ^ (uint32_t)m[b]);
     }
     const uint64_t peers = ((uint64_t)phi << 32) | plo;
-    const uint32_t before = count_below(peers);
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    const uint32_t cur = s_wh[wave][digit];
-    rk[j] = cur + before;
-    if (before == 0) s_wh[wave][digit] = cur + cnt;
+    before[j] = count_below(peers);
+    rk[j] = __hip_atomic_load(&s_wh[wave][digit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (before[j] == 0)
+      __hip_atomic_fetch_add(&s_wh[wave][digit], (uint32_t)__popcll(peers), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) rk[j] += before[j];
   __syncthreads();
 
-  // per digit: exclusive over waves, then exclusive over digits in the tile
-  // and (for the global offset) over the cloud's digit totals
+  // per digit: exclusive over digits in the tile and (for the global
+  // offset) over the cloud's digit totals; then each wave's start of the
+  // digit in the staged tile (the tile's start of the digit plus the counts
+  // of the waves before), and the global position of staged slot 0 of the
+  // digit's run (its global offset minus its start in the tile, mod 2^32)
   {
     const uint32_t c0 = s_wh[0][t], c1 = s_wh[1][t], c2 = s_wh[2][t], c3 = s_wh[3][t];
-    s_wh[0][t] = 0;
-    s_wh[1][t] = c0;
-    s_wh[2][t] = c0 + c1;
-    s_wh[3][t] = c0 + c1 + c2;
     uint32_t in_tile = c0 + c1 + c2 + c3;
     block_exclusive_scan2_256(in_tile, below_t, s_tmp);
-    s_base[t] = in_tile;
-    s_off[t] = (uint32_t)ti.seg_start + below_t + off_t;
+    s_wh[0][t] = in_tile;
+    s_wh[1][t] = in_tile + c0;
+    s_wh[2][t] = in_tile + c0 + c1;
+    s_wh[3][t] = in_tile + c0 + c1 + c2;
+    s_off[t] = (uint32_t)ti.seg_start + below_t + off_t - in_tile;
   }
   __syncthreads();
 
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const uint32_t digit = digit_of(item[j], a.shift);
-    s_stage[s_base[digit] + s_wh[wave][digit] + rk[j]] = item[j];
+    s_stage[s_wh[wave][digit] + rk[j]] = item[j];
   }
   __syncthreads();
 
@@ -553,26 +565,48 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   const bool rekey = wide && a.pass == kSortPasses - 1;  // the low 32 code bits are done
   uint64_t *out = dst + (size_t)d * a.stride;
   uint8_t *dig = digits + (size_t)d * a.stride;
-  for (int s = t; s < valid; s += kSortThreads) {
-    const uint64_t it = s_stage[s];
-    const uint32_t digit = digit_of(it, a.shift);
-    const uint32_t gpos = s_off[digit] + (uint32_t)s - s_base[digit];
-    if (last_pass) {
-      // the sorted item keeps its index and carries the point's packed
-      // coordinates instead of its code (the neighbour search's form); wide
-      // codes keep the index only
-      const uint32_t idx = (uint32_t)it;
-      out[gpos] = wide ? (uint64_t)idx : ((uint64_t)decode_packed(cg, (uint32_t)(it >> 32)) << 32) | idx;
-      rank[(size_t)d * a.stride + idx] = gpos;
-    } else if (rekey) {
-      // the item's key becomes the code's bits above 32
-      const uint32_t idx = (uint32_t)it;
-      const uint32_t hi = gen_code_hi(cg, xyz[3 * (size_t)idx + 0], xyz[3 * (size_t)idx + 1], xyz[3 * (size_t)idx + 2]);
-      out[gpos] = ((uint64_t)hi << 32) | idx;
-      dig[gpos] = (uint8_t)hi;  // the next pass's digit
-    } else {
-      out[gpos] = it;
-      dig[gpos] = (uint8_t)(it >> (40 + a.shift));  // the next pass's digit
+  // Write-out in staged order: thread t takes slots t + 256 j, so each
+  // store instruction of a wave covers 64 consecutive slots (runs of equal
+  // digits go to consecutive global positions).  All slots' LDS reads are
+  // issued before the first store (slots past the tile's items are read but
+  // not stored).
+  uint64_t st[kSortItems];
+  uint32_t gp[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) st[j] = s_stage[t + j * kSortThreads];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) gp[j] = s_off[digit_of(st[j], a.shift)] + (uint32_t)(t + j * kSortThreads);
+  if (last_pass) {
+    // the sorted item keeps its index and carries the point's packed
+    // coordinates instead of its code (the neighbour search's form); wide
+    // codes keep the index only
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      if (t + j * kSortThreads < valid) {
+        const uint32_t idx = (uint32_t)st[j];
+        out[gp[j]] = wide ? (uint64_t)idx : ((uint64_t)decode_packed(cg, (uint32_t)(st[j] >> 32)) << 32) | idx;
+        rank[(size_t)d * a.stride + idx] = gp[j];
+      }
+    }
+  } else if (rekey) {
+    // the item's key becomes the code's bits above 32
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      if (t + j * kSortThreads < valid) {
+        const uint32_t idx = (uint32_t)st[j];
+        const uint32_t hi =
+            gen_code_hi(cg, xyz[3 * (size_t)idx + 0], xyz[3 * (size_t)idx + 1], xyz[3 * (size_t)idx + 2]);
+        out[gp[j]] = ((uint64_t)hi << 32) | idx;
+        dig[gp[j]] = (uint8_t)hi;  // the next pass's digit
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      if (t + j * kSortThreads < valid) {
+        out[gp[j]] = st[j];
+        dig[gp[j]] = (uint8_t)(st[j] >> (40 + a.shift));  // the next pass's digit
+      }
     }
   }
 }
