@@ -95,6 +95,33 @@ __device__ __forceinline__ void topk_insert_minmax(uint32_t (&lst)[KM], uint32_t
   }
 }
 
+// Median of three unsigned words in one instruction (the compiler forms it
+// only from patterns with constants).  Vector registers only.
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// The same insertion with one median per slot: a candidate equal to a slot
+// is first turned into the all-ones sentinel (eight equality tests whose
+// results combine on the scalar unit), then slot k takes the median of the
+// old slots k - 1 and k and the candidate, which shifts the list up from the
+// candidate's place and drops the largest.
+template <int KM>
+__device__ __forceinline__ void topk_insert_med3(uint32_t (&lst)[KM], uint32_t c) {
+  bool dup = false;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) dup |= lst[k] == c;
+  c = dup ? ~0u : c;
+  uint32_t nw[KM];
+  nw[0] = min(lst[0], c);
+#pragma unroll
+  for (int k = 1; k < KM; ++k) nw[k] = med3_u32(lst[k - 1], c, lst[k]);
+#pragma unroll
+  for (int k = 0; k < KM; ++k) lst[k] = nw[k];
+}
+
 // Sorts 8 keys ascending (a 19-comparator network of depth 6).
 __device__ __forceinline__ void sort8(uint32_t (&v)[8]) {
   constexpr int net[19][2] = {{0, 2}, {1, 3}, {4, 6}, {5, 7}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {0, 1}, {2, 3},
@@ -256,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(MergeArgs a, const uint64_t *_
 #pragma unroll
           for (int s = 0; s < 8; ++s) {
             if (__builtin_amdgcn_ballot_w64(kc[s] < key[KM - 1]) == 0) break;
-            topk_insert_minmax<KM>(key, kc[s]);
+            topk_insert_med3<KM>(key, kc[s]);
           }
         } else {
 #pragma unroll
