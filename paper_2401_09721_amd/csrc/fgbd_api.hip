@@ -155,7 +155,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_edge_acc = take((size_t)B * kEdgeSlots * kEdgeVals * 8);
   pl.off_noise_acc = take((size_t)B * pl.E1 * kNoiseSlots * 8);
   pl.off_ctrl = take((size_t)2 * B * sizeof(SweepCtrl));
-  pl.off_sweep_sums = take((size_t)3 * B * kSweepSlots * kSweepParts * 8);
+  pl.off_sweep_sums = take((size_t)4 * B * kSweepSlots * kSweepParts * 8);  // 3 rotating + the fused first launch's
   pl.total = off;
   return pl;
 }
@@ -383,10 +383,13 @@ fgbd_status run_filter(const Run &r, const int32_t *col, const float *p, const i
   const int sweeps = q_limit > 0 ? q_limit : 1;
   // with fixed q every sweep computes: all of them are separate launches
   const int separate = (!select || sweeps < r.sweep_launches) ? sweeps : r.sweep_launches;
-  for (int q = 1; q <= separate; ++q) {
+  // The fused path with selection and at least two separate sweeps starts
+  // with one launch for sweeps 1 and 2 (x_1 came from the noise launch).
+  const bool merged = pre && select && separate >= 2 && r.prm.k == 8;
+  for (int q = merged ? 2 : 1; q <= separate; ++q) {
     FGBD_PRE(r.pf, kSweep);
     HIP_TRY(launch_sweep(r, col, p, q == 1 ? dist2 : nullptr, rgb_in, spread, noise, res, select, q_limit, q,
-                         pre && q == 1),
+                         pre && q == 1, merged && q == 2),
             "sweep launch");
     FGBD_POST(r.pf);
   }
@@ -456,7 +459,7 @@ Plan noise_scratch_plan(int64_t n, const fgbd_params &p, const Tune &tune) {
   pl.off_edge_acc = take((size_t)pl.B * kEdgeSlots * kEdgeVals * 8);
   pl.off_noise_acc = take((size_t)pl.B * pl.E1 * kNoiseSlots * 8);
   pl.off_ctrl = take((size_t)2 * pl.B * sizeof(SweepCtrl));
-  pl.off_sweep_sums = take((size_t)3 * pl.B * kSweepSlots * kSweepParts * 8);
+  pl.off_sweep_sums = take((size_t)4 * pl.B * kSweepSlots * kSweepParts * 8);
   pl.total = off;
   return pl;
 }

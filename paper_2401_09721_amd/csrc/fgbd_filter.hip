@@ -27,6 +27,12 @@
 // FSLR membership (spread_i <= kappa * sigma_est) in the fourth lane; its
 // partials also carry sum |y|^2 and |S|.  The finalising launch applies the
 // last sweep's partials the same way and writes the chosen iterate out.
+// In the fused per-frame path x_1 comes from the noise launch, and when the
+// selection has at least two separate sweeps one launch covers sweeps 1 and
+// 2: it marks membership, adds x_1's and the input's sums into a fourth sums
+// buffer outside the rotation (cleared by the call's setup) and computes x_2;
+// its stored state is flagged so that the next state load applies x_1's sums
+// before x_2's, exactly as two launches would have.
 //
 // Launch count: a launch that finds the selection done still costs about two
 // microseconds, and q_max of them are enqueued.  So only the first few sweeps
@@ -55,7 +61,8 @@ struct SweepArgs {
   int32_t select, q_limit;
   double kappa;
   int64_t buf_stride;  // float4 elements per buffer
-  unsigned long long *sums3;  // [3][B][slots][parts], rotating by sweep
+  unsigned long long *sums3;  // [4][B][slots][parts]: 0-2 rotate by sweep, 3 holds x_1's sums
+                              // when the fused first launch also computes x_2
   SweepCtrl *ctrl;            // [2][B], ping-pong by sweep
   // weights derived by the first sweep (the fused per-frame path): the
   // squared distances, the merge launch's edge-length sums, a fixed sigma_g
@@ -82,12 +89,13 @@ constexpr int kSlotVals = kSweepSlots * kSweepParts;  // integers per cloud and 
 struct SweepIO {
   const unsigned long long *sums_prev;
   unsigned long long *sums_out, *sums_clear;
+  unsigned long long *sums_first;  // x_1's sums of the fused first launch (never rotated)
   const SweepCtrl *ctrl_prev;
   SweepCtrl *ctrl_out;
 };
 __device__ __forceinline__ SweepIO sweep_io(const SweepArgs &a, int q) {
   const size_t S = (size_t)a.sa.B * kSlotVals;
-  return {a.sums3 + ((q - 1) % 3) * S, a.sums3 + (q % 3) * S, a.sums3 + ((q + 1) % 3) * S,
+  return {a.sums3 + ((q - 1) % 3) * S, a.sums3 + (q % 3) * S, a.sums3 + ((q + 1) % 3) * S, a.sums3 + 3 * S,
           a.ctrl + ((q - 1) & 1) * a.sa.B, a.ctrl + (q & 1) * a.sa.B};
 }
 
@@ -133,19 +141,18 @@ __device__ __forceinline__ void advance(SweepCtrl &c, const double (&t)[kSweepPa
 }
 
 // Selection state at the start of a launch: the stored state advanced by the
-// previous sweep's integer sums (identical in every block).  Called by every
-// thread of the block; wave 0 loads the slots (one per lane) and reduces them
-// with shuffles.
-__device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
-                           const unsigned long long *__restrict__ sums_prev, int n) {
-  __shared__ unsigned long long s_tot[kSweepParts];
-  c = *prev;
-  if (c.done) return;  // uniform: every thread read the same state
+// previous sweep's integer sums (identical in every block).  A state stored
+// by the fused first launch (first_pending) is first advanced by x_1's sums
+// from sums_first, then, unless that ended the selection, by x_2's.  Called
+// by every thread of the block; wave 0 loads the slots (one per lane) and
+// reduces them with shuffles.
+__device__ __forceinline__ void reduce_sums(const unsigned long long *__restrict__ sums, double (&t)[kSweepParts],
+                                            unsigned long long *s_tot) {
   if (threadIdx.x < kWave) {
     unsigned long long u[kSweepParts];
     const int sl = (int)threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < kSweepParts; ++j) u[j] = sl < kSweepSlots ? sums_prev[sl * kSweepParts + j] : 0ull;
+    for (int j = 0; j < kSweepParts; ++j) u[j] = sl < kSweepSlots ? sums[sl * kSweepParts + j] : 0ull;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
@@ -157,9 +164,24 @@ __device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__rest
     }
   }
   __syncthreads();
-  double t[kSweepParts];
 #pragma unroll
   for (int j = 0; j < kSweepParts; ++j) t[j] = j < 4 ? (double)s_tot[j] / kFix : (double)s_tot[j];
+  __syncthreads();  // s_tot may be written again by the next reduction
+}
+__device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
+                                           const unsigned long long *__restrict__ sums_prev,
+                                           const unsigned long long *__restrict__ sums_first, int n) {
+  __shared__ unsigned long long s_tot[kSweepParts];
+  c = *prev;
+  if (c.done) return;  // uniform: every thread read the same state
+  double t[kSweepParts];
+  if (c.first_pending) {  // x_1 sits in buffer 0, where the noise launch wrote it
+    reduce_sums(sums_first, t, s_tot);
+    advance(c, t, n, 0);
+    c.first_pending = 0;
+    if (c.done) return;
+  }
+  reduce_sums(sums_prev, t, s_tot);
   advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
 }
 
@@ -199,7 +221,13 @@ struct SweepLds {
 // edge-length sums and the squared distances (eq. 4, the graph builder's own
 // arithmetic) instead of a stored p; sigma_g goes to the results and the
 // weights into p_out for the later sweeps.
-template <int KT, bool FIRST, bool D2, bool PRE = false>
+// MERGED (the fused path's first launch when it runs more than one sweep):
+// x_1 is already in buffer 0 (the noise launch wrote it); the launch marks
+// FSLR membership, adds x_1's and the input's sums into sums_first and
+// computes x_2 (into buffer 1, its sums into the launch's own buffer), so the
+// launch of x_1's flags and sums alone is saved; the next launch applies both
+// sets of sums (load_state).
+template <int KT, bool FIRST, bool D2, bool PRE = false, bool MERGED = false>
 __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &sb, const SweepIO &io,
                                            const int32_t *__restrict__ col, const float *__restrict__ p,
                                            const float *__restrict__ rgb_in, float4 *__restrict__ xbuf,
@@ -214,6 +242,8 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
   SweepCtrl c;
   static_assert(FIRST || !D2, "only the first sweep derives the weights");
   static_assert(!PRE || (FIRST && !D2), "precomputed colours: first sweep, weights already stored");
+  static_assert(!MERGED || (FIRST && !D2 && !PRE), "the merged first launch reads x_1 and stored weights");
+  constexpr bool FROM_X = !FIRST || MERGED;  // colours (own and gathered) from a float4 iterate
   if (FIRST) {
     c.sigma_g = 0.0;
     if (D2) {
@@ -235,8 +265,10 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
     c.select = a.select;
     c.q_limit = a.q_limit;
     c.fslr = (a.select && a.kappa > 0.0) ? 1 : 0;
+    c.first_pending = MERGED ? 1 : 0;
+    c.pad_ = 0;
   } else {
-    load_state(c, io.ctrl_prev + sb.s, sums_prev, (int)(sb.end - sb.begin));
+    load_state(c, io.ctrl_prev + sb.s, sums_prev, io.sums_first + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
   }
   if (sb.lb == 0) {
     if (threadIdx.x == 0) ctrl_out[sb.s] = c;
@@ -249,17 +281,34 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
   }
 
   const double thr = c.fslr ? a.kappa * c.sigma_est : 0.0;
-  const int out_buf = free_buffer(c.in_buf, c.best_buf);
-  const float4 *xin = xbuf + (size_t)(c.in_buf < 3 ? c.in_buf : 0) * a.buf_stride;
+  // MERGED: x_1 in buffer 0, x_2 to buffer 1 (the buffer the next launch's
+  // second advance names: free_buffer(0, best) is 1 for best 0 or none)
+  const int out_buf = MERGED ? 1 : free_buffer(c.in_buf, c.best_buf);
+  const float4 *xin = xbuf + (size_t)(MERGED ? 0 : (c.in_buf < 3 ? c.in_buf : 0)) * a.buf_stride;
   float4 *xout = xbuf + (size_t)out_buf * a.buf_stride;
 
   unsigned long long v[kSweepParts] = {0, 0, 0, 0, 0};
+  unsigned long long vf[kSweepParts] = {0, 0, 0, 0, 0};  // MERGED: x_1's sums
   const Share sh = seg_share(sb, kBlock);
   for (int64_t base = sh.first; base < sh.end; base += sh.step) {
     const int64_t i = base + threadIdx.x;
     if (i >= sh.end) continue;
     float xr, xg, xb, member;
-    if (FIRST) {
+    if (MERGED) {
+      const float4 xi = xin[i];
+      xr = xi.x;
+      xg = xi.y;
+      xb = xi.z;
+      member = c.fslr ? (spread[i] <= thr ? 1.0f : 0.0f) : 1.0f;
+      const float y0 = rgb_in[3 * i + 0], y1 = rgb_in[3 * i + 1], y2 = rgb_in[3 * i + 2];
+      const unsigned long long x1s = to_fix((double)xr * xr + (double)xg * xg + (double)xb * xb);
+      vf[0] += member != 0.0f ? x1s : 0ull;
+      vf[1] += x1s;
+      const unsigned long long ys = to_fix((double)y0 * y0 + (double)y1 * y1 + (double)y2 * y2);
+      vf[2] += member != 0.0f ? ys : 0ull;
+      vf[3] += ys;
+      vf[4] += member != 0.0f ? 1ull : 0ull;
+    } else if (FIRST) {
       xr = rgb_in[3 * i + 0];
       xg = rgb_in[3 * i + 1];
       xb = rgb_in[3 * i + 2];
@@ -334,7 +383,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const int64_t cj = cc[k] >= 0 ? (int64_t)cc[k] : i;
-      if (FIRST) {
+      if (!FROM_X) {
         gx[k] = rgb_in[3 * cj + 0];
         gy[k] = rgb_in[3 * cj + 1];
         gz[k] = rgb_in[3 * cj + 2];
@@ -363,7 +412,7 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
     const unsigned long long x2 = to_fix((double)orr * orr + (double)og * og + (double)ob * ob);
     v[0] += member != 0.0f ? x2 : 0ull;
     v[1] += x2;
-    if (FIRST) {
+    if (FIRST && !MERGED) {
       const unsigned long long y2 = to_fix((double)xr * xr + (double)xg * xg + (double)xb * xb);
       v[2] += member != 0.0f ? y2 : 0ull;
       v[3] += y2;
@@ -371,9 +420,13 @@ __device__ __forceinline__ void sweep_step(const SweepArgs &a, const SegBlock &s
     }
   }
   add_sums(v, sums_out, sb.lb % kSweepSlots, lds.red);
+  if (MERGED) {
+    __syncthreads();  // lds.red is reused
+    add_sums(vf, io.sums_first + (size_t)sb.s * kSlotVals, sb.lb % kSweepSlots, lds.red);
+  }
 }
 
-template <int KT, bool FIRST, bool D2, bool PRE = false>
+template <int KT, bool FIRST, bool D2, bool PRE = false, bool MERGED = false>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int q, const int32_t *__restrict__ col,
                                                   const float *__restrict__ p, const float *__restrict__ rgb_in,
                                                   float4 *__restrict__ xbuf, const double *__restrict__ spread,
@@ -386,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int q, const int3
     col = a.col_w;
     a.dist2 = a.dist2_w;
   }
-  sweep_step<KT, FIRST, D2, PRE>(a, sb, sweep_io(a, q), col, p, y, xbuf, spread, noise, lds);
+  sweep_step<KT, FIRST, D2, PRE, MERGED>(a, sb, sweep_io(a, q), col, p, y, xbuf, spread, noise, lds);
 }
 
 // Waits until every block of the grid has arrived `epoch` times at this
@@ -467,6 +520,7 @@ __device__ __forceinline__ void finalize_block(const SegBlock &sb, const SweepCt
 __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_stride, const float *__restrict__ rgb_in,
                                                      const float4 *__restrict__ xbuf,
                                                      const unsigned long long *__restrict__ sums_prev,
+                                                     const unsigned long long *__restrict__ sums_first,
                                                      const SweepCtrl *__restrict__ ctrl_prev,
                                                      const fgbd_result *__restrict__ noise,
                                                      float *__restrict__ rgb_out, fgbd_result *__restrict__ res,
@@ -474,7 +528,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SegArgs sa, int64_t buf_str
                                                      const uint32_t *__restrict__ rank0) {
   const SegBlock sb = seg_block(sa, kGridSweep);
   SweepCtrl c;
-  load_state(c, ctrl_prev + sb.s, sums_prev + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
+  load_state(c, ctrl_prev + sb.s, sums_prev + (size_t)sb.s * kSlotVals, sums_first + (size_t)sb.s * kSlotVals,
+             (int)(sb.end - sb.begin));
   finalize_block(sb, c, buf_stride, rgb_in, xbuf, noise, rgb_out, res, hint,
                  relabel && relabel[sb.s] ? rank0 : nullptr);
 }
@@ -524,7 +579,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
     c = last[sb.s];
   } else {
     const unsigned long long *sums_last = a.sums3 + (size_t)(q_last % 3) * B * kSlotVals;
-    load_state(c, a.ctrl + (q_last & 1) * B + sb.s, sums_last + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
+    load_state(c, a.ctrl + (q_last & 1) * B + sb.s, sums_last + (size_t)sb.s * kSlotVals,
+               a.sums3 + (size_t)3 * B * kSlotVals + (size_t)sb.s * kSlotVals, (int)(sb.end - sb.begin));
   }
   finalize_block(sb, c, a.buf_stride, rgb_in, xbuf, noise, rgb_out, a.res, hint,
                  a.relabel && a.relabel[sb.s] ? a.rank0 : nullptr);
@@ -553,10 +609,10 @@ SweepArgs sweep_args(const Run &r, const int32_t *dist2, float *p_out, fgbd_resu
   return a;
 }
 
-template <int KT, bool FIRST, bool D2, bool PRE = false>
+template <int KT, bool FIRST, bool D2, bool PRE = false, bool MERGED = false>
 void sweep_kernel(int nb, hipStream_t st, const SweepArgs &a, int q, const int32_t *col, const float *p,
                   const float *rgb_in, float4 *xbuf, const double *spread, const fgbd_result *noise) {
-  k_sweep<KT, FIRST, D2, PRE><<<nb, kBlock, 0, st>>>(a, q, col, p, rgb_in, xbuf, spread, noise);
+  k_sweep<KT, FIRST, D2, PRE, MERGED><<<nb, kBlock, 0, st>>>(a, q, col, p, rgb_in, xbuf, spread, noise);
 }
 
 // Per device: blocks of k_sweep_tail<KT> resident at once, and ticks of the
@@ -606,9 +662,16 @@ hipError_t tail_kernel(int nb, hipStream_t st, const SweepArgs &a, int q0, int q
 
 hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
                         const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
-                        int select, int q_limit, int q, bool pre) {
+                        int select, int q_limit, int q, bool pre, bool merged) {
   const bool first = q == 1, d2 = dist2 != nullptr;
   if (d2 && !first) return hipErrorInvalidValue;  // only the first sweep derives the weights
+  if (merged) {  // sweeps 1 and 2 of the fused path in one launch (buffers of sweep 2)
+    if (q != 2 || d2 || pre || r.prm.k != 8) return hipErrorInvalidValue;
+    const SweepArgs a = sweep_args(r, nullptr, nullptr, res, select, q_limit);
+    sweep_kernel<8, true, false, false, true>(r.pl.grid[kGridSweep], r.stream, a, q, col, p, rgb_in, r.b.xbuf,
+                                              spread, noise);
+    return hipGetLastError();
+  }
   if (pre && (!first || d2 || r.prm.k != 8)) return hipErrorInvalidValue;
   if (pre) {
     const SweepArgs a = sweep_args(r, nullptr, nullptr, res, select, q_limit);
@@ -651,7 +714,8 @@ hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, co
   const size_t S = (size_t)r.pl.B * kSlotVals;
   const unsigned long long *sp = r.b.sums + (q_launches % 3) * S;
   const SweepCtrl *cp = r.b.ctrl + (q_launches & 1) * r.pl.B;
-  k_finalize<<<r.pl.grid[kGridSweep], kBlock, 0, r.stream>>>(r.sa, r.pl.n_cap, rgb_in, r.b.xbuf, sp, cp, noise,
+  k_finalize<<<r.pl.grid[kGridSweep], kBlock, 0, r.stream>>>(r.sa, r.pl.n_cap, rgb_in, r.b.xbuf, sp, r.b.sums + 3 * S, cp,
+                                                              noise,
                                                               rgb_out, res, r.hint,
                                                               r.relabel_ok ? r.b.segs->relabel : nullptr, r.b.rank);
   return hipGetLastError();

@@ -336,7 +336,9 @@ struct SweepCtrl {
   int32_t select;    // 1: eq. 6 selection, 0: fixed q
   int32_t q_limit;   // q_max (select) or q_fixed
   int32_t fslr;      // FSLR subset in use (select and kappa > 0)
-  int32_t pad_[2];
+  int32_t first_pending;  // stored by the fused first launch: the sums of x_1 (in the fourth
+                          // sums buffer) are still to be applied before those of x_2
+  int32_t pad_;
 };
 // No implicit padding: a copy of the struct then splits into its fields and
 // stays in registers (padding bytes inside a 16-byte chunk made the compiler
@@ -448,7 +450,7 @@ struct SetupArgs {
   int32_t B;
   int32_t grid[kNumGrids];
   int32_t zero_result;  // 0 leave res, 1 zero res[0..B-1], 2 zero and flag FGBD_ST_NO_PATCH
-  int32_t sums_count;   // first sweep's sums to clear (uint64)
+  int32_t sums_count;   // sweep sums of one buffer (uint64); buffers 1-3 are cleared
   int32_t noise_count;  // noise moment accumulators to clear (uint64)
   int32_t edge_count;   // edge-length sums to clear (uint64)
   int32_t blocks;       // blocks that share the clears
@@ -524,7 +526,7 @@ hipError_t launch_noise_solve(const Run &r, fgbd_result *res);
 // buffer; this launch adds the FSLR flags and the sums.
 hipError_t launch_sweep(const Run &r, const int32_t *col, const float *p, const int32_t *dist2,
                         const float *rgb_in, const double *spread, const fgbd_result *noise, fgbd_result *res,
-                        int select, int q_limit, int q, bool pre = false);
+                        int select, int q_limit, int q, bool pre = false, bool merged = false);
 
 // Whether the sweep grid of r fits on the current device at once, as the
 // in-launch sweep loop below needs.

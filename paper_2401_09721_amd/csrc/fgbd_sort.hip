@@ -194,7 +194,7 @@ __device__ __forceinline__ void setup_work(const SetupArgs &a, int block) {
   __shared__ int32_t s_bad;
   const int t = threadIdx.x;
   const int stride = a.blocks * (int)blockDim.x;
-  for (int i = block * blockDim.x + t; i < a.sums_count; i += stride) sums1[i] = 0ull;
+  for (int i = block * blockDim.x + t; i < 3 * a.sums_count; i += stride) sums1[i] = 0ull;
   for (int i = block * blockDim.x + t; i < a.noise_count; i += stride) a.noise_acc[i] = 0ull;
   for (int i = block * blockDim.x + t; i < a.edge_count; i += stride) a.edge_acc[i] = 0ull;
   if (block != 0) return;  // uniform over the block
@@ -624,10 +624,12 @@ SetupArgs setup_args(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_
   a.sums_count = r.pl.B * kSweepSlots * kSweepParts;
   a.noise_count = r.pl.B * r.pl.E1 * kNoiseSlots;
   a.edge_count = r.pl.B * kEdgeSlots * kEdgeVals;
-  const int most = a.sums_count > a.noise_count ? a.sums_count : a.noise_count;
+  const int most = 3 * a.sums_count > a.noise_count ? 3 * a.sums_count : a.noise_count;
   int blocks = (most + 256 * 8 - 1) / (256 * 8);
   a.blocks = blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks);
-  a.sums1 = r.b.sums + (size_t)a.sums_count;  // the first sweep adds into sums buffer 1 (see launch_sweep)
+  // the first sweep adds into sums buffer 1, the fused first launch into
+  // buffers 2 (x_2) and 3 (x_1): buffers 1-3 start cleared (see launch_sweep)
+  a.sums1 = r.b.sums + (size_t)a.sums_count;
   a.noise_acc = r.b.noise_acc;
   a.edge_acc = r.b.edge_acc;
   a.sg = r.b.segs;
