@@ -649,10 +649,11 @@ fgbd_status fgbd_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *rgb_in, 
 }
 
 // Separate sweep launches for an eager call: the schedule's count, lowered to
-// one more than the most sweeps any of the last eight read-back calls needed
-// (the extra launch is the one that finds the selection stopped, so the
-// in-launch loop after it returns at once).  Captured calls keep the
-// schedule's count.  *hint receives where this call's finalising launch
+// the most sweeps any of the last eight read-back calls needed when those
+// counts agree (the finalising launch then applies the last sweep's sums
+// itself and finds the selection stopped), else to one more (a launch that
+// finds it stopped, so the in-launch loop after it returns at once).
+// Captured calls keep the schedule's count.  *hint receives where this call's finalising launch
 // should store its sweep counts (NULL: no read-back requested).
 static int adaptive_sweep_launches(fgbd_ctx ctx, hipStream_t s, int32_t **hint) {
   *hint = nullptr;
@@ -687,9 +688,14 @@ static int adaptive_sweep_launches(fgbd_ctx ctx, hipStream_t s, int32_t **hint) 
   }
   if (!ctx->hint_pending) *hint = ctx->hint_dev;
   if (ctx->hint_count == 0) return cap;
-  int m = 0;
-  for (int i = 0; i < 8 && i < ctx->hint_count; ++i) m = ctx->hint_recent[i] > m ? ctx->hint_recent[i] : m;
-  return m + 1 < cap ? m + 1 : cap;
+  int m = 0, lo = 1 << 30;
+  const int k = ctx->hint_count < 8 ? ctx->hint_count : 8;
+  for (int i = 0; i < k; ++i) {
+    m = ctx->hint_recent[i] > m ? ctx->hint_recent[i] : m;
+    lo = ctx->hint_recent[i] < lo ? ctx->hint_recent[i] : lo;
+  }
+  const int want = (k >= 2 && lo == m) ? m : m + 1;  // steady counts: no spare launch
+  return want < 1 ? 1 : (want < cap ? want : cap);
 }
 
 // After the launches of an eager call that asked for a read-back: mark it.

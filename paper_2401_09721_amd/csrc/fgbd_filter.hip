@@ -185,6 +185,38 @@ __device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__rest
   advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
 }
 
+// The same advance by one wave alone (no block barrier): every lane loads
+// one slot, the sums are reduced with shuffles so every lane holds them, and
+// every lane advances its own copy of the state.
+__device__ __forceinline__ void wave_reduce_sums(const unsigned long long *__restrict__ sums, double (&t)[kSweepParts]) {
+  unsigned long long u[kSweepParts];
+  const int sl = (int)lane_id();
+#pragma unroll
+  for (int j = 0; j < kSweepParts; ++j) u[j] = sl < kSweepSlots ? sums[sl * kSweepParts + j] : 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int j = 0; j < kSweepParts; ++j) u[j] += __shfl_xor(u[j], o, kWave);
+  }
+#pragma unroll
+  for (int j = 0; j < kSweepParts; ++j) t[j] = j < 4 ? (double)u[j] / kFix : (double)u[j];
+}
+__device__ __forceinline__ void wave_advance(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
+                                             const unsigned long long *__restrict__ sums_prev,
+                                             const unsigned long long *__restrict__ sums_first, int n) {
+  c = *prev;
+  if (c.done) return;
+  double t[kSweepParts];
+  if (c.first_pending) {
+    wave_reduce_sums(sums_first, t);
+    advance(c, t, n, 0);
+    c.first_pending = 0;
+    if (c.done) return;
+  }
+  wave_reduce_sums(sums_prev, t);
+  advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
+}
+
 // Block-sum of per-thread integer sums, then one atomic per value per block
 // into slot `slot` of the cloud's sums.
 __device__ __forceinline__ void add_sums(unsigned long long (&v)[kSweepParts], unsigned long long *__restrict__ out,
@@ -548,6 +580,33 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
   const int B = a.sa.B;
   // state at the start of the last separate sweep, written by that launch
   const SweepCtrl *last = a.ctrl + ((q0 - 1) & 1) * B;
+  {
+    // Those states advanced by that sweep's sums, one wave per cloud: when
+    // every cloud is then done (the usual case once the schedule launches as
+    // many separate sweeps as the selection needs), finalise at once, with no
+    // loop and no wait for the other blocks.
+    __shared__ int s_open;
+    if (threadIdx.x == 0) s_open = 0;
+    __syncthreads();
+    const size_t S = (size_t)B * kSlotVals;
+    const unsigned long long *sums_sep = a.sums3 + (size_t)((q0 - 1) % 3) * S;
+    const unsigned long long *sums_first = a.sums3 + 3 * S;
+    for (int s2 = (int)threadIdx.x / kWave; s2 < B; s2 += kBlock / kWave) {
+      const int n2 = a.sa.n_fixed >= 0 ? a.sa.n_fixed : a.sa.segs->start[s2 + 1] - a.sa.segs->start[s2];
+      SweepCtrl cs;
+      wave_advance(cs, last + s2, sums_sep + (size_t)s2 * kSlotVals, sums_first + (size_t)s2 * kSlotVals, n2);
+      if (!cs.done && lane_id() == 0) s_open = 1;
+    }
+    __syncthreads();
+    if (s_open == 0) {  // uniform over the grid: every block read the same states and sums
+      SweepCtrl c;
+      load_state(c, last + sb.s, sums_sep + (size_t)sb.s * kSlotVals, sums_first + (size_t)sb.s * kSlotVals,
+                 (int)(sb.end - sb.begin));
+      finalize_block(sb, c, a.buf_stride, rgb_in, xbuf, noise, rgb_out, a.res, hint,
+                     a.relabel && a.relabel[sb.s] ? a.rank0 : nullptr);
+      return;
+    }
+  }
   int q = q0;
   bool done = all_clouds_done(last, B);
   uint32_t epoch = 0;

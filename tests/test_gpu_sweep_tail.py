@@ -223,3 +223,43 @@ def test_wait_bound_zero_gives_up_with_defined_output():
     out2, r2 = denoise_with(ctx, xyz, rgb, prm, 1)
     assert np.array_equal(out2, ref) and r2 == rr
     ctx.close()
+
+
+def test_steady_sweep_counts_finalise_in_the_tail():
+    """Calls whose recent sweep counts agree launch exactly as many separate
+    sweeps as the selection needed lately, and the finalising launch applies
+    the last sweep's sums itself before it finalises.  The same frame (and
+    the same batch) called again and again on one context gives, every time,
+    the bits of a fresh context."""
+    prm = fgbd.default_params(bits=8)
+    xyz, rgb = cloud(141, 15000, 20.0)
+    fresh = fgbd.Context("cuda")
+    ref, rres = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm, ctx=fresh)
+    torch.cuda.synchronize()
+    ref = ref.cpu().numpy()
+    rres = fgbd.read_result(rres)
+    fresh.close()
+    ctx = fgbd.Context("cuda")
+    for rep in range(6):
+        out, res = fgbd.denoise(dev(xyz, torch.int32), dev(rgb, torch.float32), prm, ctx=ctx)
+        torch.cuda.synchronize()  # lets the next call read this call's sweep count
+        assert np.array_equal(out.cpu().numpy(), ref), rep
+        assert fgbd.read_result(res) == rres, rep
+    # a batch of three clouds with different noise levels, called repeatedly
+    parts = [cloud(142, 9000, 5.0), cloud(143, 12000, 20.0), cloud(144, 7000, 35.0)]
+    bx = dev(np.concatenate([p[0] for p in parts]), torch.int32)
+    bc = dev(np.concatenate([p[1] for p in parts]), torch.float32)
+    offs = torch.tensor(np.concatenate([[0], np.cumsum([len(p[0]) for p in parts])]), dtype=torch.int64,
+                        device="cuda")
+    fresh = fgbd.Context("cuda")
+    bref, bres = fgbd.denoise_batched(bx, bc, offs, prm, ctx=fresh)
+    torch.cuda.synchronize()
+    bref = bref.cpu().numpy()
+    bres = fgbd.read_results(bres)
+    fresh.close()
+    for rep in range(6):
+        out, res = fgbd.denoise_batched(bx, bc, offs, prm, ctx=ctx)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), bref), rep
+        assert fgbd.read_results(res) == bres, rep
+    ctx.close()
