@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 6
+#define FGBD_ABI_VERSION 7
 
 /* Largest number of clouds in one fgbd_denoise_batched call. */
 #define FGBD_MAX_BATCH 64
@@ -332,7 +332,9 @@ fgbd_status fgbd_autotune(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in,
  *   g: col and dist2 of a graph from fgbd_build_slg;  x, out: float32 [n][3]
  *   (must not overlap);  coef: device float32 [ncoef], 1 <= ncoef <= 32;
  *   sigma_g: device double (one value, > 0);  saved: output float32
- *   [ncoef][n][3], the iterates x_0..x_{ncoef-1} the backward call needs. */
+ *   [2 ncoef - 1][n][3] the backward call needs: the iterates x_0..x_{ncoef-1},
+ *   then u_1..u_{ncoef-1} with u_m = 2 (dT/dsigma_g) x_{m-1} (formed from the
+ *   neighbour values the sweep gathers). */
 fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, const float *coef, int32_t ncoef,
                              const double *sigma_g, float *out, float *saved, void *stream);
 

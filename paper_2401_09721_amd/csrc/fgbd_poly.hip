@@ -5,16 +5,21 @@
 // (eq. 4), so sigma_g can be a trained parameter.  c = e_q gives eq. 5.
 //
 // Forward: x_0 = x, x_k = T x_{k-1}; all iterates x_0..x_{n-1} are saved, and
-// the last sweep also forms out from them.
+// the last sweep also forms out from them.  Each sweep also saves
+// u_k = sum_k' dp_ik' x_{k-1}[col_ik'] (2 (dT/dsigma_g) x_{k-1}, the per-slot
+// coefficients dp from the weights launch), from the neighbour values it
+// gathers anyway, so the backward's sigma_g term needs no gather.
 // Backward, for L = <g, out>:
 //   dL/dc_k     = <g, x_k>
 //   z_{n-1} = c_{n-1} g,  z_k = c_k g + T^T z_{k+1},  dL/dx = z_0
-//   dL/dsigma_g = sum_{m=1}^{n-1} <z_m, (dT/dsigma_g) x_{m-1}>, where
+//   dL/dsigma_g = sum_{m=1}^{n-1} <z_m, (dT/dsigma_g) x_{m-1}> = sum_m <z_m, u_m> / 2, where
 //     dT/dsigma_g = (1/2) dP/dsigma_g and dp_ik/dsigma_g = p_ik (a_ik - sum_k' p_ik' a_ik'),
 //     a_ik = 2 (d2_ik - d2_i0) / sigma_g^3 (the row shift cancels).
 // T^T pulls along an explicit transpose of the directed graph: for every point
 // j the edge ids e = i * K + slot with col[e] = j, in increasing order (built
-// once per graph by fgbd_graph_transpose, or per call).  One launch per
+// once per graph by fgbd_graph_transpose, or per call); the backward call
+// first lays the weights out in that order (p_T[u] = p[edge[u]] / 2), so a
+// step reads them contiguously and gathers only the adjoint.  One launch per
 // backward step computes z_{m-1}, the step's sigma_g term and the
 // coefficient products <g, x_{m-1}> together.  Scalar gradients are FP64
 // per-block partials summed in block order by a one-block kernel.  No
@@ -28,11 +33,15 @@ namespace {
 // Row-normalised weights of eq. 4 from squared distances and a device
 // bandwidth, with the graph builder's row_weights (the same bits as the
 // weights fgbd_build_slg stores for that bandwidth).
+// With dp given (the forward call), also the per-slot derivative coefficients
+//   dp_ik = p_ik (a_ik - sum_k' p_ik' a_ik'),  a_ik = 2 (d2_ik - d2_i0) / sigma_g^3
+// (FP64, rounded to float; 0 for an empty slot and for a row without edges),
+// so that dT/dsigma_g x = (1/2) sum_k dp_ik x[col_ik].
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_poly_weights(int32_t n, int32_t k_rt, const int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ dist2,
                                                          const double *__restrict__ sigma_g,
-                                                         float *__restrict__ p) {
+                                                         float *__restrict__ p, float *__restrict__ dp) {
   __shared__ double s_exp[kExpTable];
   const int K = KT > 0 ? KT : k_rt;
   const double sg = *sigma_g;
@@ -66,6 +75,27 @@ __global__ __launch_bounds__(kBlock) void k_poly_weights(int32_t n, int32_t k_rt
 #pragma unroll
       for (int k = 0; k < KB; ++k)
         if (k < K) p[i * K + k] = pw[k];
+    }
+    if (dp) {
+      const double a_scale = sg > 0.0 ? 2.0 / (sg * sg * sg) : 0.0;
+      float dw[KB];
+      double pa = 0.0;
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        if (k < K && cv[0] >= 0 && cv[k] >= 0) pa += (double)pw[k] * a_scale * (double)(dv[k] - dv[0]);
+#pragma unroll
+      for (int k = 0; k < KB; ++k)
+        dw[k] = (k < K && cv[0] >= 0 && cv[k] >= 0) ? (float)((double)pw[k] * (a_scale * (double)(dv[k] - dv[0]) - pa))
+                                                    : 0.0f;
+      if (KT == 8) {
+        float4 *dr = reinterpret_cast<float4 *>(dp + i * 8);
+        dr[0] = make_float4(dw[0], dw[1], dw[2], dw[3]);
+        dr[1] = make_float4(dw[4], dw[5], dw[6], dw[7]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+          if (k < K) dp[i * K + k] = dw[k];
+      }
     }
   }
 }
@@ -199,23 +229,27 @@ __device__ __forceinline__ void st3(float *__restrict__ x, int64_t i, float a, f
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_poly_step(int32_t n, int32_t k_rt, int k, int ncoef,
                                                       const int32_t *__restrict__ col, const float *__restrict__ p,
-                                                      const float *__restrict__ coef, float *__restrict__ saved,
-                                                      float *__restrict__ out) {
+                                                      const float *__restrict__ dp, const float *__restrict__ coef,
+                                                      float *__restrict__ saved, float *__restrict__ out) {
   const int K = KT > 0 ? KT : k_rt;
   const size_t S = (size_t)n * 3;
   const float *xp = saved + (size_t)(k - 1) * S;
   float *xs = saved + (size_t)k * S;
+  float *us = saved + (size_t)(ncoef + k - 1) * S;  // u_k after the ncoef iterates
   const bool last = k == ncoef - 1;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    float u0 = 0.f, u1 = 0.f, u2 = 0.f;
     int c0;
     if (KT == 8) {
       const int4 *cr = reinterpret_cast<const int4 *>(col + i * 8);
       const float4 *pr = reinterpret_cast<const float4 *>(p + i * 8);
+      const float4 *dr = reinterpret_cast<const float4 *>(dp + i * 8);
       const int4 ca = cr[0], cb = cr[1];
-      const float4 pa = pr[0], pb = pr[1];
+      const float4 pa = pr[0], pb = pr[1], da = dr[0], db = dr[1];
       const int cv[8] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
       const float pv[8] = {pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w};
+      const float dv[8] = {da.x, da.y, da.z, da.w, db.x, db.y, db.z, db.w};
       c0 = cv[0];
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
@@ -225,21 +259,30 @@ __global__ __launch_bounds__(kBlock) void k_poly_step(int32_t n, int32_t k_rt, i
         a0 = fmaf(pv[kk], y0, a0);
         a1 = fmaf(pv[kk], y1, a1);
         a2 = fmaf(pv[kk], y2, a2);
+        u0 = fmaf(dv[kk], y0, u0);
+        u1 = fmaf(dv[kk], y1, u1);
+        u2 = fmaf(dv[kk], y2, u2);
       }
     } else {
       const int32_t *cr = col + i * K;
       const float *pr = p + i * K;
+      const float *dr = dp + i * K;
       c0 = cr[0];
       for (int kk = 0; kk < K; ++kk) {
         const int64_t j = cr[kk] >= 0 ? (int64_t)cr[kk] : i;
         const float w = cr[kk] >= 0 ? pr[kk] : 0.0f;
+        const float dw = cr[kk] >= 0 ? dr[kk] : 0.0f;
         float y0, y1, y2;
         ld3(xp, j, y0, y1, y2);
         a0 = fmaf(w, y0, a0);
         a1 = fmaf(w, y1, a1);
         a2 = fmaf(w, y2, a2);
+        u0 = fmaf(dw, y0, u0);
+        u1 = fmaf(dw, y1, u1);
+        u2 = fmaf(dw, y2, u2);
       }
     }
+    st3(us, i, u0, u1, u2);
     float s0, s1, s2;
     ld3(xp, i, s0, s1, s2);
     float v0 = s0, v1 = s1, v2 = s2;
@@ -278,30 +321,37 @@ __global__ __launch_bounds__(kBlock) void k_poly_first(int32_t n, int ncoef, con
 }
 
 // ---------------------------------------------------------------- backward
-// One step m (n-1 >= m >= 1), per point j:
-//   z_{m-1}[j] = c_{m-1} g[j] + T_jj z_m[j] + sum over in-edges e = i*K + slot
-//                of p_e / 2 z_m[i]                                    (T^T z_m)
-//   sigma_g term: (1/2) sum_k dp_jk <z_m[j], x_{m-1}[col_jk]>
-//   coefficient products <g[j], x_{m-1}[j]> (and <g[j], x_m[j]> at m = n-1)
-// with z_{n-1} = c_{n-1} g read from g directly.  Per-block FP64 partials:
-// sig_part[block], cpart[k][block].
+// p_T[u] = p[edge[u]] / 2 for u < off[n]: the weights (with T's factor 1/2)
+// in the transpose's order, so each backward step reads them contiguously.
+__global__ __launch_bounds__(kBlock) void k_poly_ptrans(int32_t n, const int32_t *__restrict__ off,
+                                                        const int32_t *__restrict__ tsrc, const float *__restrict__ p,
+                                                        float *__restrict__ pt) {
+  const int64_t E = off[n];
+  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < E; u += (int64_t)gridDim.x * kBlock)
+    pt[u] = 0.5f * p[tsrc[u]];
+}
+
+// One backward step m (z_m in, z_{m-1} out) per point j:
+//   z_{m-1}[j] = c_{m-1} g[j] + T_jj z_m[j] + sum over edges e = (i -> j) of p_T z_m[i]
+// (T_jj = 1/2 for a point with edges, 1 without), with the sigma_g term
+// <z_m[j], u_m[j]> / 2 from the saved u_m and the coefficient product
+// <g[j], x_{m-1}[j]> (and <g[j], x_m[j]> at the last step, where
+// z_m = c_m g).  Only the adjoint is gathered.
 template <int KT>
-__global__ __launch_bounds__(kBlock) void k_poly_back(int32_t n, int32_t k_rt, int m, int last, int nb,
-                                                      const int32_t *__restrict__ col, const int32_t *__restrict__ dist2,
-                                                      const float *__restrict__ p, const int32_t *__restrict__ off,
-                                                      const int32_t *__restrict__ tsrc, const double *__restrict__ sigma_g,
+__global__ __launch_bounds__(kBlock) void k_poly_back(int32_t n, int32_t k_rt, int m, int last, int nb, int ncoef,
+                                                      const int32_t *__restrict__ col, const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ tsrc, const float *__restrict__ pt,
                                                       const float *__restrict__ coef, const float *__restrict__ g,
                                                       const float *__restrict__ saved, const float *__restrict__ zin,
                                                       float *__restrict__ zout, double *__restrict__ sig_part,
                                                       double *__restrict__ cpart) {
   __shared__ double s_red[8 * 3];
   const int K = KT > 0 ? KT : k_rt;
-  const double sg = *sigma_g;
-  const double a_scale = sg > 0.0 ? 2.0 / (sg * sg * sg) : 0.0;
   const float cm = coef[m], cm1 = coef[m - 1];
   const size_t S = (size_t)n * 3;
   const float *xprev = saved + (size_t)(m - 1) * S;
   const float *xcur = saved + (size_t)m * S;
+  const float *um = saved + (size_t)(ncoef + m - 1) * S;
   // acc[0]: sigma_g term; acc[1]: <g, x_{m-1}>; acc[2]: <g, x_m> (last step only)
   double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
@@ -323,69 +373,44 @@ __global__ __launch_bounds__(kBlock) void k_poly_back(int32_t n, int32_t k_rt, i
       ld3(xcur, j, y0, y1, y2);
       acc[2] += (double)g0 * y0 + (double)g1 * y1 + (double)g2 * y2;
     }
-    // sigma_g term of row j
-    constexpr int KB = KT > 0 ? KT : kMaxK;
-    int cv[KB], dv[KB];
-    float pv[KB];
-    if (KT == 8) {
-      const int4 *cr = reinterpret_cast<const int4 *>(col + j * 8);
-      const int4 *dr = reinterpret_cast<const int4 *>(dist2 + j * 8);
-      const float4 *pr = reinterpret_cast<const float4 *>(p + j * 8);
-      const int4 ca = cr[0], cb = cr[1], da = dr[0], db = dr[1];
-      const float4 pa = pr[0], pb = pr[1];
-      cv[0] = ca.x; cv[1] = ca.y; cv[2] = ca.z; cv[3] = ca.w;
-      cv[4] = cb.x; cv[5] = cb.y; cv[6] = cb.z; cv[7] = cb.w;
-      dv[0] = da.x; dv[1] = da.y; dv[2] = da.z; dv[3] = da.w;
-      dv[4] = db.x; dv[5] = db.y; dv[6] = db.z; dv[7] = db.w;
-      pv[0] = pa.x; pv[1] = pa.y; pv[2] = pa.z; pv[3] = pa.w;
-      pv[4] = pb.x; pv[5] = pb.y; pv[6] = pb.z; pv[7] = pb.w;
-    } else {
-#pragma unroll
-      for (int k = 0; k < KB; ++k) {
-        cv[k] = k < K ? col[j * K + k] : -1;
-        dv[k] = k < K ? dist2[j * K + k] : 0;
-        pv[k] = k < K ? p[j * K + k] : 0.f;
-      }
-    }
-    if (cv[0] >= 0) {
-      const int d0 = dv[0];
-      double pa = 0.0;
-#pragma unroll
-      for (int k = 0; k < KB; ++k)
-        if (cv[k] >= 0) pa += (double)pv[k] * a_scale * (double)(dv[k] - d0);
-      double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < KB; ++k) {
-        if (cv[k] >= 0) {
-          float y0, y1, y2;
-          ld3(xprev, cv[k], y0, y1, y2);
-          const double dp = (double)pv[k] * (a_scale * (double)(dv[k] - d0) - pa);
-          const double dot = (double)z0 * y0 + (double)z1 * y1 + (double)z2 * y2;
-          t += dp * dot;
-        }
-      }
-      acc[0] += 0.5 * t;
-    }
+    float u0, u1, u2;
+    ld3(um, j, u0, u1, u2);
+    acc[0] += 0.5 * ((double)z0 * u0 + (double)z1 * u1 + (double)z2 * u2);
     // T^T z_m at j
-    const float tjj = cv[0] >= 0 ? 0.5f : 1.0f;
+    const float tjj = col[j * K] >= 0 ? 0.5f : 1.0f;
     float r0 = tjj * z0, r1 = tjj * z1, r2 = tjj * z2;
+    // in-edges four at a time (their ids, weights and gathers all in flight
+    // together), then the rest one by one; the order of the additions is the
+    // edges' order either way
+    const float *zsrc = last ? g : zin;
+    const float zs = last ? cm : 1.0f;
     const int a = off[j], b = off[j + 1];
-    for (int u = a; u < b; ++u) {
-      const int e = tsrc[u];
-      const int64_t src = e / K;
-      const float w = 0.5f * p[e];
-      float s0, s1, s2;
-      if (last) {
-        ld3(g, src, s0, s1, s2);
-        s0 *= cm;
-        s1 *= cm;
-        s2 *= cm;
-      } else {
-        ld3(zin, src, s0, s1, s2);
+    int u = a;
+    for (; u + 4 <= b; u += 4) {
+      int64_t sr[4];
+      float w[4], s[4][3];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        sr[e] = tsrc[u + e] / K;
+        w[e] = pt[u + e];
       }
-      r0 = fmaf(w, s0, r0);
-      r1 = fmaf(w, s1, r1);
-      r2 = fmaf(w, s2, r2);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ld3(zsrc, sr[e], s[e][0], s[e][1], s[e][2]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        r0 = fmaf(w[e], zs * s[e][0], r0);
+        r1 = fmaf(w[e], zs * s[e][1], r1);
+        r2 = fmaf(w[e], zs * s[e][2], r2);
+      }
+    }
+    for (; u < b; ++u) {
+      const int64_t src = tsrc[u] / K;
+      const float w = pt[u];
+      float s0, s1, s2;
+      ld3(zsrc, src, s0, s1, s2);
+      r0 = fmaf(w, zs * s0, r0);
+      r1 = fmaf(w, zs * s1, r1);
+      r2 = fmaf(w, zs * s2, r2);
     }
     st3(zout, j, fmaf(cm1, g0, r0), fmaf(cm1, g1, r1), fmaf(cm1, g2, r2));
   }
@@ -418,19 +443,37 @@ __global__ __launch_bounds__(kBlock) void k_poly_reduce(int ncoef, int nb, const
                                                         const double *__restrict__ sig_part,
                                                         float *__restrict__ grad_coef,
                                                         double *__restrict__ grad_sigma) {
-  __shared__ double s_red[8];
-  for (int k = 0; k < ncoef; ++k) {
-    double v[1] = {0.0};
-    for (int b = threadIdx.x; b < nb; b += kBlock) v[0] += coef_part[(size_t)k * nb + b];
-    block_sum_f64<1>(v, s_red);
-    if (threadIdx.x == 0 && grad_coef) grad_coef[k] = (float)v[0];
-  }
-  double total = 0.0;
-  for (int m = 1; m < ncoef; ++m) {
-    double v[1] = {0.0};
-    for (int b = threadIdx.x; b < nb; b += kBlock) v[0] += sig_part[(size_t)m * nb + b];
-    block_sum_f64<1>(v, s_red);
-    total += v[0];  // valid in thread 0
+  // the 2 ncoef - 1 sums (coefficient k, then sigma_g term m = 1..ncoef-1)
+  // eight at a time: each thread adds its blocks' partials of eight sums,
+  // then one reduction tree per eight (the same per-value order as one tree
+  // per sum)
+  constexpr int G8 = 8;
+  __shared__ double s_red[4 * G8];
+  const int V = 2 * ncoef - 1;
+  double total = 0.0;  // thread 0: the sigma_g terms, added in m order
+  for (int v0 = 0; v0 < V; v0 += G8) {
+    double v[G8];
+#pragma unroll
+    for (int j = 0; j < G8; ++j) v[j] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+#pragma unroll
+      for (int j = 0; j < G8; ++j) {
+        const int idx = v0 + j;
+        if (idx < V) v[j] += idx < ncoef ? coef_part[(size_t)idx * nb + b] : sig_part[(size_t)(idx - ncoef + 1) * nb + b];
+      }
+    }
+    block_sum_f64<G8>(v, s_red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < G8; ++j) {
+        const int idx = v0 + j;
+        if (idx < ncoef) {
+          if (grad_coef) grad_coef[idx] = (float)v[j];
+        } else if (idx < V) {
+          total += v[j];
+        }
+      }
+    }
   }
   if (threadIdx.x == 0 && grad_sigma) *grad_sigma = total;
 }
@@ -452,6 +495,7 @@ size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks) {
   size_t b = 0;
   auto take = [&](size_t bytes) { b += (bytes + 255) & ~(size_t)255; };
   take(N * k * 4);                     // p
+  take(N * k * 4);                     // dp (forward) or p in the transpose's order (backward)
   take((N + 1) * 4);                   // offsets (when no transpose is given)
   take(N * k * 4);                     // transposed edge ids (same)
   take(2 * N * 3 * 4);                 // z ping-pong
@@ -462,7 +506,7 @@ size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks) {
 }
 
 struct PolyBufs {
-  float *p;
+  float *p, *aux;
   int32_t *off, *tsrc;
   float *z[2];
   double *coef_part, *sig_part;
@@ -479,6 +523,7 @@ static PolyBufs poly_carve(char *ws, int64_t n, int k, int ncoef, int nblocks) {
     return ptr;
   };
   pb.p = (float *)take(N * k * 4);
+  pb.aux = (float *)take(N * k * 4);
   pb.off = (int32_t *)take((N + 1) * 4);
   pb.tsrc = (int32_t *)take(N * k * 4);
   pb.z[0] = (float *)take(N * 3 * 4);
@@ -521,14 +566,14 @@ hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32
   k_poly_first<<<grid_for(3 * n), kBlock, 0, s>>>((int32_t)n, ncoef, x, coef, saved, out);
   if (ncoef == 1) return hipGetLastError();
   if (k == 8)
-    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux);
   else
-    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux);
   for (int kk = 1; kk < ncoef; ++kk) {
     if (k == 8)
-      k_poly_step<8><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, coef, saved, out);
+      k_poly_step<8><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, pb.aux, coef, saved, out);
     else
-      k_poly_step<0><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, coef, saved, out);
+      k_poly_step<0><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, pb.aux, coef, saved, out);
   }
   return hipGetLastError();
 }
@@ -552,20 +597,21 @@ hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int3
     t_edge = pb.tsrc;
   }
   if (k == 8)
-    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr);
   else
-    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p);
+    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr);
+  k_poly_ptrans<<<grid_for(n * k), kBlock, 0, s>>>((int32_t)n, t_off, t_edge, pb.p, pb.aux);
   // reverse Horner; coefficient products ride along
   const float *zin = nullptr;
   for (int m = ncoef - 1; m >= 1; --m) {
     float *zout = (m == 1) ? grad_x : pb.z[m & 1];
     if (k == 8)
-      k_poly_back<8><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, col, dist2, pb.p, t_off, t_edge,
-                                          sigma_g, coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
+      k_poly_back<8><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, col, t_off, t_edge, pb.aux,
+                                          coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
                                           pb.coef_part);
     else
-      k_poly_back<0><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, col, dist2, pb.p, t_off, t_edge,
-                                          sigma_g, coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
+      k_poly_back<0><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, col, t_off, t_edge, pb.aux,
+                                          coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
                                           pb.coef_part);
     zin = zout;
   }

@@ -30,7 +30,7 @@ FGBD_ST_SWEEP_STALL = 8
 FGBD_ST_RELABELED = 16
 FGBD_ST_DIST_CLAMPED = 32
 NUM_KERNELS = 10
-ABI_VERSION = 6
+ABI_VERSION = 7
 MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
            "finalize", "relabel")
@@ -716,7 +716,9 @@ def round_u8(rgb, ctx: Optional[Context] = None, out=None, stream=None):
 
 def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None, stream=None):
     """out = sum_k coef[k] T^k x with eq. 4 weights at the device bandwidth
-    sigma_g (float64 scalar tensor).  Returns (out, saved iterates)."""
+    sigma_g (float64 scalar tensor).  Returns (out, saved): saved holds the
+    2 ncoef - 1 arrays [n][3] the backward call needs (the iterates, then the
+    bandwidth derivatives u_m)."""
     torch = _torch()
     ctx = ctx or default_context(x.device)
     _need(x, torch.float32, (3,), "x", ctx.device)
@@ -730,7 +732,7 @@ def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None,
     coef = coef.contiguous()
     sigma_g = sigma_g.contiguous()
     out = torch.empty_like(x)
-    saved = torch.empty((nc, n, 3), dtype=torch.float32, device=ctx.device)
+    saved = torch.empty((2 * nc - 1, n, 3), dtype=torch.float32, device=ctx.device)
     gs = graph.c_struct()
     _check(lib().fgbd_poly_filter(ctx.handle, ctypes.byref(gs), _ptr(x), _ptr(coef), nc, _ptr(sigma_g), _ptr(out),
                                   _ptr(saved), _stream(ctx, stream)))
@@ -770,7 +772,7 @@ def poly_filter_backward(graph: SLGraph, saved, coef, sigma_g, grad_out, ctx: Op
     if sigma_g.dtype != torch.float64 or sigma_g.device != ctx.device or sigma_g.numel() != 1:
         raise ValueError("sigma_g must be a float64 device scalar")
     nc = int(coef.numel())
-    _need_out(saved, torch.float32, (nc, graph.n, 3), "saved", ctx.device)
+    _need_out(saved, torch.float32, (2 * nc - 1, graph.n, 3), "saved", ctx.device)
     ts = None
     if transpose is True:
         transpose = graph.transpose(ctx=ctx, stream=stream)
