@@ -45,6 +45,8 @@ def algorithmic_bytes(kind: str, n: int, L: int, K: int, P: int) -> float:
         return (8 * K + 16 + 16) * n
     if kind == "sweep_first_fused":  # float4 x1 in and out (FSLR flag added), y (12 B) and spread in
         return (16 + 16 + 12 + 8) * n
+    if kind == "sweep_first_merged":  # x1, y and spread in, col + p in, float4 x2 out
+        return (16 + 12 + 8 + 8 * K + 16) * n
     if kind == "finalize":  # float4 in, float32 x3 out (plus the last sweep partials)
         return (16 + 12) * n
     return 0.0

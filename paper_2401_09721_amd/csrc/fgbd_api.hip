@@ -560,7 +560,7 @@ fgbd_status fgbd_workspace_size(const fgbd_params *p, int64_t n_max, int32_t bat
   // sized for the largest schedule, so any later fgbd_set_schedule fits
   const Tune widest = {{kGridCapMax, kNoiseGridCapMax, kGridCapMax}, kDefaultSweepLaunches};
   const size_t a = make_plan(n_max, batch, *p, widest).total;
-  const size_t b = poly_workspace(n_max, p->k, kMaxPoly, kMaxGrid);
+  const size_t b = poly_workspace(n_max, p->k, kMaxPoly, kPolyGrid);
   *bytes = a > b ? a : b;
   return ok();
 }
@@ -998,7 +998,7 @@ fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, 
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   char *ws = nullptr;
-  if ((st = get_workspace(ctx, poly_workspace(n, g->k, ncoef, kMaxGrid), &ws)) != FGBD_OK) return st;
+  if ((st = get_workspace(ctx, poly_workspace(n, g->k, ncoef, kPolyGrid), &ws)) != FGBD_OK) return st;
   HIP_TRY(launch_poly_forward(n, g->k, g->col, g->dist2, x, coef, ncoef, sigma_g, out, saved, ws, s),
           "poly filter launch");
   return ok();
@@ -1040,7 +1040,7 @@ fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const f
   DeviceGuard dg(ctx->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   char *ws = nullptr;
-  if ((st = get_workspace(ctx, poly_workspace(n, g->k, ncoef, kMaxGrid), &ws)) != FGBD_OK) return st;
+  if ((st = get_workspace(ctx, poly_workspace(n, g->k, ncoef, kPolyGrid), &ws)) != FGBD_OK) return st;
   HIP_TRY(launch_poly_backward(n, g->k, g->col, g->dist2, t ? t->off : nullptr, t ? t->edge : nullptr, saved, coef,
                                ncoef, sigma_g, grad_out, grad_x, grad_coef, grad_sigma_g, ws, s),
           "poly filter backward launch");

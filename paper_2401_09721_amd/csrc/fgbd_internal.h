@@ -547,6 +547,9 @@ hipError_t launch_finalize(const Run &r, const float *rgb_in, int q_launches, co
 
 // Polynomial filter and its adjoint (ws: at least poly_workspace bytes).
 constexpr int kMaxPoly = 32;
+// grid cap of the polynomial filter's grid-stride kernels; also the length
+// of each of their per-block partial-sum rows
+constexpr int kPolyGrid = 1024;
 size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks);
 // Float coordinates onto the 2^bits grid (keys: 6 words of scratch) and
 // colours to uint8 (fgbd_io.hip).

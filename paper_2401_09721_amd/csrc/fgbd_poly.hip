@@ -36,12 +36,15 @@ namespace {
 // With dp given (the forward call), also the per-slot derivative coefficients
 //   dp_ik = p_ik (a_ik - sum_k' p_ik' a_ik'),  a_ik = 2 (d2_ik - d2_i0) / sigma_g^3
 // (FP64, rounded to float; 0 for an empty slot and for a row without edges),
-// so that dT/dsigma_g x = (1/2) sum_k dp_ik x[col_ik].
+// so that dT/dsigma_g x = (1/2) sum_k dp_ik x[col_ik].  With diag given (the
+// backward call), also T's diagonal per point, so the backward steps read
+// 4 bytes per point instead of the first slot of each neighbour row.
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_poly_weights(int32_t n, int32_t k_rt, const int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ dist2,
                                                          const double *__restrict__ sigma_g,
-                                                         float *__restrict__ p, float *__restrict__ dp) {
+                                                         float *__restrict__ p, float *__restrict__ dp,
+                                                         float *__restrict__ diag) {
   __shared__ double s_exp[kExpTable];
   const int K = KT > 0 ? KT : k_rt;
   const double sg = *sigma_g;
@@ -67,6 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_poly_weights(int32_t n, int32_t k_rt
     }
     float pw[KB];
     row_weights<KB>(cv, dv, sg, s_exp, pw);
+    if (diag) diag[i] = cv[0] >= 0 ? 0.5f : 1.0f;  // T's diagonal: 1/2 with edges, 1 without
     if (KT == 8) {
       float4 *pr = reinterpret_cast<float4 *>(p + i * 8);
       pr[0] = make_float4(pw[0], pw[1], pw[2], pw[3]);
@@ -327,19 +331,34 @@ __global__ __launch_bounds__(kBlock) void k_poly_ptrans(int32_t n, const int32_t
                                                         const int32_t *__restrict__ tsrc, const float *__restrict__ p,
                                                         float *__restrict__ pt) {
   const int64_t E = off[n];
-  for (int64_t u = (int64_t)blockIdx.x * kBlock + threadIdx.x; u < E; u += (int64_t)gridDim.x * kBlock)
-    pt[u] = 0.5f * p[tsrc[u]];
+  if (E <= 0) return;
+  // four edges per thread and round, their id loads and then their gathers
+  // in flight together (indices clamped, so no load needs a branch)
+  constexpr int U = 4;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t u0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; u0 < E; u0 += U * stride) {
+    int32_t e[U];
+    float w[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) e[j] = tsrc[min(u0 + j * stride, E - 1)];
+#pragma unroll
+    for (int j = 0; j < U; ++j) w[j] = p[e[j]];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+      if (u0 + j * stride < E) pt[u0 + j * stride] = 0.5f * w[j];
+  }
 }
 
 // One backward step m (z_m in, z_{m-1} out) per point j:
 //   z_{m-1}[j] = c_{m-1} g[j] + T_jj z_m[j] + sum over edges e = (i -> j) of p_T z_m[i]
-// (T_jj = 1/2 for a point with edges, 1 without), with the sigma_g term
+// (T_jj = 1/2 for a point with edges, 1 without, read from diag, which the
+// backward's weights launch writes), with the sigma_g term
 // <z_m[j], u_m[j]> / 2 from the saved u_m and the coefficient product
 // <g[j], x_{m-1}[j]> (and <g[j], x_m[j]> at the last step, where
 // z_m = c_m g).  Only the adjoint is gathered.
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_poly_back(int32_t n, int32_t k_rt, int m, int last, int nb, int ncoef,
-                                                      const int32_t *__restrict__ col, const int32_t *__restrict__ off,
+                                                      const float *__restrict__ diag, const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ tsrc, const float *__restrict__ pt,
                                                       const float *__restrict__ coef, const float *__restrict__ g,
                                                       const float *__restrict__ saved, const float *__restrict__ zin,
@@ -352,38 +371,36 @@ __global__ __launch_bounds__(kBlock) void k_poly_back(int32_t n, int32_t k_rt, i
   const float *xprev = saved + (size_t)(m - 1) * S;
   const float *xcur = saved + (size_t)m * S;
   const float *um = saved + (size_t)(ncoef + m - 1) * S;
+  // z_{m+1} is c_m g on the last step (m = ncoef - 1), else the previous step's
+  // output; <g, x_m> is needed on the last step only (yrow reads x_{m-1} again
+  // otherwise, from cache)
+  const float *zsrc = last ? g : zin;
+  const float zs = last ? cm : 1.0f;
+  const float *yrow = last ? xcur : xprev;
   // acc[0]: sigma_g term; acc[1]: <g, x_{m-1}>; acc[2]: <g, x_m> (last step only)
   double acc[3] = {0.0, 0.0, 0.0};
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-    float g0, g1, g2;
+    // every load of the row is unconditional (the step's kind only picks the
+    // pointers), so they are all in flight together
+    float g0, g1, g2, z0, z1, z2, x0, x1, x2, y0, y1, y2, u0, u1, u2;
     ld3(g, j, g0, g1, g2);
-    float z0, z1, z2;
-    if (last) {
-      z0 = cm * g0;
-      z1 = cm * g1;
-      z2 = cm * g2;
-    } else {
-      ld3(zin, j, z0, z1, z2);
-    }
-    float x0, x1, x2;
+    ld3(zsrc, j, z0, z1, z2);
     ld3(xprev, j, x0, x1, x2);
-    acc[1] += (double)g0 * x0 + (double)g1 * x1 + (double)g2 * x2;
-    if (last) {
-      float y0, y1, y2;
-      ld3(xcur, j, y0, y1, y2);
-      acc[2] += (double)g0 * y0 + (double)g1 * y1 + (double)g2 * y2;
-    }
-    float u0, u1, u2;
+    ld3(yrow, j, y0, y1, y2);
     ld3(um, j, u0, u1, u2);
+    z0 *= zs;
+    z1 *= zs;
+    z2 *= zs;
+    acc[1] += (double)g0 * x0 + (double)g1 * x1 + (double)g2 * x2;
+    const double gy = (double)g0 * y0 + (double)g1 * y1 + (double)g2 * y2;
+    acc[2] += last ? gy : 0.0;
     acc[0] += 0.5 * ((double)z0 * u0 + (double)z1 * u1 + (double)z2 * u2);
     // T^T z_m at j
-    const float tjj = col[j * K] >= 0 ? 0.5f : 1.0f;
+    const float tjj = diag[j];
     float r0 = tjj * z0, r1 = tjj * z1, r2 = tjj * z2;
     // in-edges four at a time (their ids, weights and gathers all in flight
     // together), then the rest one by one; the order of the additions is the
     // edges' order either way
-    const float *zsrc = last ? g : zin;
-    const float zs = last ? cm : 1.0f;
     const int a = off[j], b = off[j + 1];
     int u = a;
     for (; u + 4 <= b; u += 4) {
@@ -437,45 +454,44 @@ __global__ __launch_bounds__(kBlock) void k_scale(int32_t n, const float *__rest
   if (threadIdx.x == 0) cpart[blockIdx.x] = acc[0];
 }
 
-// One block: sum partials in block order.  grad_coef[k] from coef partials,
-// grad_sigma from the n-1 backward-step partials.
-__global__ __launch_bounds__(kBlock) void k_poly_reduce(int ncoef, int nb, const double *__restrict__ coef_part,
-                                                        const double *__restrict__ sig_part,
-                                                        float *__restrict__ grad_coef,
-                                                        double *__restrict__ grad_sigma) {
-  // the 2 ncoef - 1 sums (coefficient k, then sigma_g term m = 1..ncoef-1)
-  // eight at a time: each thread adds its blocks' partials of eight sums,
-  // then one reduction tree per eight (the same per-value order as one tree
-  // per sum)
-  constexpr int G8 = 8;
-  __shared__ double s_red[4 * G8];
+// One block of kReduceWaves waves: wave v sums value v's nb partials (v =
+// coefficient k < ncoef, then the sigma_g term of backward step m = v -
+// ncoef + 1): lane l adds partials l, l + 64, ... with all its loads in
+// flight together, then a shuffle tree adds the lanes; thread 0 writes the
+// coefficient gradients and adds the sigma_g terms in m order.  The order of
+// every sum is fixed.
+constexpr int kReduceWaves = 16;
+__global__ __launch_bounds__(kReduceWaves * kWave) void k_poly_reduce(int ncoef, int nb,
+                                                                     const double *__restrict__ coef_part,
+                                                                     const double *__restrict__ sig_part,
+                                                                     float *__restrict__ grad_coef,
+                                                                     double *__restrict__ grad_sigma) {
+  __shared__ double s_val[2 * kMaxPoly];
   const int V = 2 * ncoef - 1;
-  double total = 0.0;  // thread 0: the sigma_g terms, added in m order
-  for (int v0 = 0; v0 < V; v0 += G8) {
-    double v[G8];
+  const int wave = threadIdx.x / kWave, lane = (int)lane_id();
+  constexpr int U = 16;  // loads in flight per lane
+  for (int v = wave; v < V; v += kReduceWaves) {
+    const double *row = v < ncoef ? coef_part + (size_t)v * nb : sig_part + (size_t)(v - ncoef + 1) * nb;
+    double acc = 0.0;
+    for (int b0 = lane; b0 < nb; b0 += U * kWave) {
+      double x[U];
 #pragma unroll
-    for (int j = 0; j < G8; ++j) v[j] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) {
+      for (int j = 0; j < U; ++j) x[j] = row[min(b0 + j * kWave, nb - 1)];  // clamped: no branch per load
 #pragma unroll
-      for (int j = 0; j < G8; ++j) {
-        const int idx = v0 + j;
-        if (idx < V) v[j] += idx < ncoef ? coef_part[(size_t)idx * nb + b] : sig_part[(size_t)(idx - ncoef + 1) * nb + b];
-      }
+      for (int j = 0; j < U; ++j) acc += b0 + j * kWave < nb ? x[j] : 0.0;
     }
-    block_sum_f64<G8>(v, s_red);
-    if (threadIdx.x == 0) {
 #pragma unroll
-      for (int j = 0; j < G8; ++j) {
-        const int idx = v0 + j;
-        if (idx < ncoef) {
-          if (grad_coef) grad_coef[idx] = (float)v[j];
-        } else if (idx < V) {
-          total += v[j];
-        }
-      }
-    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, kWave);
+    if (lane == 0) s_val[v] = acc;
   }
-  if (threadIdx.x == 0 && grad_sigma) *grad_sigma = total;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 0; v < ncoef; ++v)
+      if (grad_coef) grad_coef[v] = (float)s_val[v];
+    double total = 0.0;
+    for (int v = ncoef; v < V; ++v) total += s_val[v];
+    if (grad_sigma) *grad_sigma = total;
+  }
 }
 
 }  // namespace
@@ -496,6 +512,7 @@ size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks) {
   auto take = [&](size_t bytes) { b += (bytes + 255) & ~(size_t)255; };
   take(N * k * 4);                     // p
   take(N * k * 4);                     // dp (forward) or p in the transpose's order (backward)
+  take(N * 4);                         // T's diagonal (backward)
   take((N + 1) * 4);                   // offsets (when no transpose is given)
   take(N * k * 4);                     // transposed edge ids (same)
   take(2 * N * 3 * 4);                 // z ping-pong
@@ -506,7 +523,7 @@ size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks) {
 }
 
 struct PolyBufs {
-  float *p, *aux;
+  float *p, *aux, *diag;
   int32_t *off, *tsrc;
   float *z[2];
   double *coef_part, *sig_part;
@@ -524,6 +541,7 @@ static PolyBufs poly_carve(char *ws, int64_t n, int k, int ncoef, int nblocks) {
   };
   pb.p = (float *)take(N * k * 4);
   pb.aux = (float *)take(N * k * 4);
+  pb.diag = (float *)take(N * 4);
   pb.off = (int32_t *)take((N + 1) * 4);
   pb.tsrc = (int32_t *)take(N * k * 4);
   pb.z[0] = (float *)take(N * 3 * 4);
@@ -536,7 +554,7 @@ static PolyBufs poly_carve(char *ws, int64_t n, int k, int ncoef, int nblocks) {
 
 static int grid_for(int64_t items) {
   const int64_t g = (items + kBlock - 1) / kBlock;
-  return (int)(g < 1 ? 1 : (g < kMaxGrid ? g : kMaxGrid));
+  return (int)(g < 1 ? 1 : (g < kPolyGrid ? g : kPolyGrid));
 }
 
 hipError_t launch_transpose(int64_t n, int k, const int32_t *col, int32_t *off, int32_t *tsrc, char *ws,
@@ -561,14 +579,14 @@ hipError_t launch_transpose(int64_t n, int k, const int32_t *col, int32_t *off, 
 hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *x,
                                const float *coef, int ncoef, const double *sigma_g, float *out, float *saved,
                                char *ws, hipStream_t s) {
-  PolyBufs pb = poly_carve(ws, n, k, ncoef, kMaxGrid);
+  PolyBufs pb = poly_carve(ws, n, k, ncoef, kPolyGrid);
   const int G = grid_for(n);
   k_poly_first<<<grid_for(3 * n), kBlock, 0, s>>>((int32_t)n, ncoef, x, coef, saved, out);
   if (ncoef == 1) return hipGetLastError();
   if (k == 8)
-    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux);
+    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux, nullptr);
   else
-    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux);
+    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux, nullptr);
   for (int kk = 1; kk < ncoef; ++kk) {
     if (k == 8)
       k_poly_step<8><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, pb.aux, coef, saved, out);
@@ -582,12 +600,12 @@ hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int3
                                 const int32_t *t_edge, const float *saved, const float *coef, int ncoef,
                                 const double *sigma_g, const float *grad_out, float *grad_x, float *grad_coef,
                                 double *grad_sigma, char *ws, hipStream_t s) {
-  PolyBufs pb = poly_carve(ws, n, k, ncoef, kMaxGrid);
+  PolyBufs pb = poly_carve(ws, n, k, ncoef, kPolyGrid);
   const int G = grid_for(n);
   if (ncoef == 1) {
     const int G3 = grid_for(3 * n);
     k_scale<<<G3, kBlock, 0, s>>>((int32_t)n, coef, grad_out, saved, grad_x, pb.coef_part);
-    k_poly_reduce<<<1, kBlock, 0, s>>>(1, G3, pb.coef_part, pb.sig_part, grad_coef, grad_sigma);
+    k_poly_reduce<<<1, kReduceWaves * kWave, 0, s>>>(1, G3, pb.coef_part, pb.sig_part, grad_coef, grad_sigma);
     return hipGetLastError();
   }
   if (!t_off) {  // no transpose given: build one in the workspace
@@ -597,25 +615,25 @@ hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int3
     t_edge = pb.tsrc;
   }
   if (k == 8)
-    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr);
+    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr, pb.diag);
   else
-    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr);
+    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr, pb.diag);
   k_poly_ptrans<<<grid_for(n * k), kBlock, 0, s>>>((int32_t)n, t_off, t_edge, pb.p, pb.aux);
   // reverse Horner; coefficient products ride along
   const float *zin = nullptr;
   for (int m = ncoef - 1; m >= 1; --m) {
     float *zout = (m == 1) ? grad_x : pb.z[m & 1];
     if (k == 8)
-      k_poly_back<8><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, col, t_off, t_edge, pb.aux,
+      k_poly_back<8><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, pb.diag, t_off, t_edge, pb.aux,
                                           coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
                                           pb.coef_part);
     else
-      k_poly_back<0><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, col, t_off, t_edge, pb.aux,
+      k_poly_back<0><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, pb.diag, t_off, t_edge, pb.aux,
                                           coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
                                           pb.coef_part);
     zin = zout;
   }
-  k_poly_reduce<<<1, kBlock, 0, s>>>(ncoef, G, pb.coef_part, pb.sig_part, grad_coef, grad_sigma);
+  k_poly_reduce<<<1, kReduceWaves * kWave, 0, s>>>(ncoef, G, pb.coef_part, pb.sig_part, grad_coef, grad_sigma);
   return hipGetLastError();
 }
 
