@@ -27,14 +27,17 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(kind: str, n: int, L: int, K: int, P: int) -> float:
     """Compulsory HBM bytes per launch of each kernel kind: every array a launch
     must read or write, read or written once, neighbour gathers counted as cache
-    hits.  Radix kernels are averaged over the 4 passes: pass 0 reads the int32
-    coordinates once (12 B/point for all L directions); each downsweep moves the
-    8-byte items (read and write) and writes the next pass's 1-byte digit, the
-    last one the 4-byte rank instead; upsweeps 1-3 read the 1-byte digits."""
+    hits.  Codes of at most 32 bits (grids up to 2^10, every workload here) sort
+    with one top-digit pass and the local sorts: the upsweep and the downsweep
+    read the int32 coordinates once (12 B/point for all L directions), the
+    downsweep writes the 8-byte items, and the local sort reads them and writes
+    the sorted items and the 4-byte rank."""
     if kind == "radix_upsweep":
-        return (12 * n + 3 * L * n) / 4
+        return 12 * n
     if kind == "radix_downsweep":
-        return (12 * n + 9 * L * n + 2 * 17 * L * n + 20 * L * n) / 4
+        return (12 + 8 * L) * n
+    if kind == "local_sort":
+        return (8 + 8 + 4) * L * n
     if kind == "merge":     # xyz, rank, sorted items once, col + dist2 out
         return (12 + 4 * L + 8 * L + 8 * K) * n
     if kind == "weights":   # col + dist2 in, p out
@@ -59,6 +62,7 @@ KIND_SOURCES = {
     "merge": ("fgbd_graph.hip",), "weights": ("fgbd_graph.hip",),
     "noise": ("fgbd_noise.hip",), "noise_solve": ("fgbd_noise.hip",),
     "sweep": ("fgbd_filter.hip",), "finalize": ("fgbd_filter.hip",), "relabel": ("fgbd_graph.hip",),
+    "local_sort": ("fgbd_sort.hip",),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fgbd_1M_frame.md")
 

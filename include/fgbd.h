@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 7
+#define FGBD_ABI_VERSION 8
 
 /* Largest number of clouds in one fgbd_denoise_batched call. */
 #define FGBD_MAX_BATCH 64
@@ -436,10 +436,13 @@ const char *fgbd_last_error(void);
  *   0 radix upsweep (digit counts; pass 0 also makes the codes), 1 radix scan,
  *   2 radix downsweep (stable scatter), 3 neighbour merge, 4 edge weights,
  *   5 patch statistics, 6 noise eigen-solve, 7 filter sweep, 8 finalise,
- *   9 renumbering of clouds stored in no spatial order.
+ *   9 renumbering of clouds stored in no spatial order, 10 local sort of the
+ *   buckets left by the top-digit pass (codes of at most 32 bits, which sort
+ *   with one top-digit pass of kinds 0-2 and this launch instead of four
+ *   LSD passes).
  * The event records add a little time of their own between launches.
  * ms, launches: host arrays of `count` entries (count <= FGBD_NUM_KERNELS). */
-#define FGBD_NUM_KERNELS 10
+#define FGBD_NUM_KERNELS 11
 fgbd_status fgbd_profile_enable(fgbd_ctx ctx, int32_t enable);
 fgbd_status fgbd_profile_read(fgbd_ctx ctx, double *ms, int64_t *launches, int32_t count);
 

@@ -141,7 +141,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_segs = take(sizeof(Segs));
   pl.off_items_a = take((size_t)pl.L * pl.stride * 8);
   pl.off_items_b = take((size_t)pl.L * pl.stride * 8);
-  pl.off_hist = take((size_t)pl.L * (pl.ntiles_cap + 1) * 256 * 4);
+  pl.off_hist = take((size_t)pl.L * (pl.ntiles_cap + 1) * kMsdBins * 4);  // 256 digits per tile row in LSD passes
   pl.off_rank = take((size_t)pl.L * pl.stride * 4);
   pl.off_digits = take((size_t)pl.L * pl.stride);
   pl.off_col = take(N * pl.K * 4);

@@ -366,6 +366,9 @@ constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
 constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit codes
+// codes of at most 32 bits: one pass on the top kMsdBits bits, then local sorts
+constexpr int kMsdBits = 10;
+constexpr int kMsdBins = 1 << kMsdBits;
 
 constexpr int kBlock = 256;
 constexpr int kMaxGrid = 1024;  // default grid cap of the grid-stride kernels
@@ -420,7 +423,10 @@ struct Bufs {
 Bufs carve(char *ws, const Plan &pl);
 
 // ------------------------------------------------------------- profiling
-enum Kind { kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kNoiseSolve, kSweep, kFinalize, kRelabel, kNumKinds };
+enum Kind {
+  kUpsweep = 0, kScan, kDownsweep, kMerge, kWeights, kNoise, kNoiseSolve, kSweep, kFinalize, kRelabel, kLocalSort,
+  kNumKinds
+};
 static_assert(kNumKinds == FGBD_NUM_KERNELS, "one profiling slot per kernel kind");
 // Optional per-launch timing hook (events around each launch).
 struct Prof {

@@ -342,27 +342,30 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_upsweep(SortArgs a, const
 
 // Exclusive prefix over tiles of every (direction, digit) count, and the
 // total after the last tile (row ntiles).  The counts are stored tile-major,
-// one 256-digit row per tile, so every access is a contiguous row segment.
-// One block per (direction, 64 digits): lane = digit, the 16 waves split the
-// tiles into 16 consecutive ranges; each wave sums its range with all loads
-// of a chunk in flight, the waves' sums are scanned in LDS, and each wave
-// writes its range's prefixes starting from the sums of the waves before it.
+// one row of BINS digits per tile, so every access is a contiguous row
+// segment.  One block per (direction, 64 digits): lane = digit, the 16 waves
+// split the tiles into 16 consecutive ranges; each wave sums its range with
+// all loads of a chunk in flight, the waves' sums are scanned in LDS, and
+// each wave writes its range's prefixes starting from the sums of the waves
+// before it.
 constexpr int kScanWaves = 16;
 constexpr int kScanChunk = 16;  // tiles per wave per round trip
+template <int BINS>
 __global__ __launch_bounds__(kScanWaves * 64) void k_sort_scan(SortArgs a, uint32_t *__restrict__ hist) {
   __shared__ uint32_t s_sum[kScanWaves][kWave];
-  const int d = blockIdx.x / 4;
-  const int digit = (blockIdx.x % 4) * kWave + (int)lane_id();
+  constexpr int kGroups = BINS / kWave;
+  const int d = blockIdx.x / kGroups;
+  const int digit = (blockIdx.x % kGroups) * kWave + (int)lane_id();
   const int w = threadIdx.x / kWave;
   const int ntiles = num_tiles(a);
   const int per = (ntiles + kScanWaves - 1) / kScanWaves;
   const int t0 = w * per, t1 = min(t0 + per, ntiles);
-  uint32_t *h = hist + (size_t)d * a.row * 256 + digit;  // h[tile * 256]
+  uint32_t *h = hist + (size_t)d * a.row * BINS + digit;  // h[tile * BINS]
   if (per <= kScanChunk) {  // (up to 256 tiles) one round trip: the counts stay in registers
     uint32_t v[kScanChunk];
     uint32_t sum = 0;
 #pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) v[j] = t0 + j < t1 ? h[(size_t)(t0 + j) * 256] : 0u;
+    for (int j = 0; j < kScanChunk; ++j) v[j] = t0 + j < t1 ? h[(size_t)(t0 + j) * BINS] : 0u;
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) sum += v[j];
     s_sum[w][lane_id()] = sum;
@@ -375,17 +378,17 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_sort_scan(SortArgs a, uint3
     }
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) {
-      if (t0 + j < t1) h[(size_t)(t0 + j) * 256] = run;
+      if (t0 + j < t1) h[(size_t)(t0 + j) * BINS] = run;
       run += v[j];
     }
-    if (w == kScanWaves - 1) h[(size_t)ntiles * 256] = total;
+    if (w == kScanWaves - 1) h[(size_t)ntiles * BINS] = total;
     return;
   }
   uint32_t sum = 0;
   for (int c0 = t0; c0 < t1; c0 += kScanChunk) {
     uint32_t v[kScanChunk];
 #pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < t1 ? h[(size_t)(c0 + j) * 256] : 0u;
+    for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < t1 ? h[(size_t)(c0 + j) * BINS] : 0u;
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) sum += v[j];
   }
@@ -400,14 +403,14 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_sort_scan(SortArgs a, uint3
   for (int c0 = t0; c0 < t1; c0 += kScanChunk) {
     uint32_t v[kScanChunk];
 #pragma unroll
-    for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < t1 ? h[(size_t)(c0 + j) * 256] : 0u;
+    for (int j = 0; j < kScanChunk; ++j) v[j] = c0 + j < t1 ? h[(size_t)(c0 + j) * BINS] : 0u;
 #pragma unroll
     for (int j = 0; j < kScanChunk; ++j) {
-      if (c0 + j < t1) h[(size_t)(c0 + j) * 256] = run;
+      if (c0 + j < t1) h[(size_t)(c0 + j) * BINS] = run;
       run += v[j];
     }
   }
-  if (w == kScanWaves - 1) h[(size_t)ntiles * 256] = total;
+  if (w == kScanWaves - 1) h[(size_t)ntiles * BINS] = total;
 }
 
 // This pass's digit of an item (code << 32 | index).
@@ -611,6 +614,583 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
   }
 }
 
+
+// ------------------------------------------------------------ hybrid sort
+// Codes of at most 32 bits (grids up to 2^10) take a shorter route.  One
+// pass on the kMsdBits most significant bits of each direction's code
+// (upsweep, scan and downsweep as above, with 2^kMsdBits digits, the codes
+// made from the coordinates) splits every cloud's points, stably, into
+// buckets of equal top digit.  k_local_sort then gives each window of
+// kLocalWin sorted positions of a direction one block, which sorts the
+// buckets that start in its window: their union [lo, hi) is bounded by the
+// first digit change (or cloud start) at or after each end of the window,
+// and its items are sorted, stably, by their codes less the smallest top
+// digit's base, with 8-bit LSD passes in LDS (three for the usual ranges).
+// Buckets are ordered by their top digits already, so sorting a range by the
+// whole code sorts each bucket and keeps the buckets in place; ties keep the
+// MSD pass's order, which is the input's.  The final pass writes the sorted
+// items in their final form and rank, as the last LSD pass does.  A range of
+// more than kLocalCap items, of two clouds, or of keys wider than 26 bits is
+// sorted by its block alone through the two item buffers (slower; inputs
+// whose points crowd into few top digits, such as a plane normal to a scan
+// axis, take it).
+
+__device__ __forceinline__ int code_width(const DirTable &dt, int d) {
+  const DirInfo di = dt.d[d];
+  const uint32_t uh = (uint32_t)(di.uh < 0 ? -di.uh : di.uh);
+  return 3 * dt.bits + (32 - __clz(uh)) + di.wm_extra;  // bit_length(0) = 0
+}
+__device__ __forceinline__ int msd_shift(const DirTable &dt, int d) {
+  const int w = code_width(dt, d);
+  return w > kMsdBits ? w - kMsdBits : 0;
+}
+// The top digit of a code (a field extract, so it stays below 2^kMsdBits
+// even for the codes of coordinates outside the grid).
+__device__ __forceinline__ uint32_t msd_digit(uint32_t code, int sh) {
+  return __builtin_amdgcn_ubfe(code, (uint32_t)sh, (uint32_t)kMsdBits);
+}
+
+// Per-tile counts of the top digits, codes made from the coordinates (and
+// the call's setup folded in, as in pass 0 of the LSD sort).
+__global__ __launch_bounds__(kSortThreads) void k_msd_upsweep(SortArgs a, const int32_t *__restrict__ xyz,
+                                                              uint32_t *__restrict__ hist) {
+  constexpr int kSub = 4, kSubStride = kMsdBins + 1;
+  __shared__ uint32_t s_hs[kSub * kSubStride];
+  if (a.fold) {
+    const int lin = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (lin < a.su.blocks) setup_work(a.su, lin);
+  }
+  int d, tile;
+  xcd_tile(d, tile);
+  TileInfo ti;
+  if (!tile_info(a, tile, ti)) return;  // uniform over the block
+  const int t = threadIdx.x;
+  for (int i = t; i < kSub * kSubStride; i += kSortThreads) s_hs[i] = 0;
+  __syncthreads();
+  uint32_t *s_h = s_hs + (lane_id() & (kSub - 1)) * kSubStride;
+  const int wave = t / kWave;
+  const int lane = (int)lane_id();
+  const int base = ti.begin + wave * kWave * kSortItems + lane;
+  int g[kSortItems][3];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int pos = min(base + j * kWave, ti.end - 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g[j][c] = xyz[3 * pos + c];
+  }
+  const CodeGen cg = code_gen(a.dt, d);
+  const int sh = msd_shift(a.dt, d);
+  uint32_t run_digit = 0, run_count = 0;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    if (base + j * kWave < ti.end) {
+      const uint32_t digit = msd_digit(gen_code(cg, g[j][0], g[j][1], g[j][2]), sh);
+      if (run_count != 0 && digit != run_digit) {
+        atomicAdd(&s_h[run_digit], run_count);
+        run_count = 0;
+      }
+      run_digit = digit;
+      ++run_count;
+    }
+  }
+  if (run_count != 0) atomicAdd(&s_h[run_digit], run_count);
+  __syncthreads();
+  uint32_t *row = hist + ((size_t)d * a.row + tile) * kMsdBins;
+#pragma unroll
+  for (int q = 0; q < kMsdBins / kSortThreads; ++q) {
+    const int c = t + q * kSortThreads;
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) v += s_hs[k * kSubStride + c];
+    row[c] = v;
+  }
+}
+
+// The stable partition by top digit: the LSD downsweep's ranking with
+// kMsdBits ballots, per-wave digit counts in LDS, staging in digit order and
+// runs written to their offsets.  Items keep their code (code << 32 | index).
+__global__ __launch_bounds__(kSortThreads) void k_msd_downsweep(SortArgs a, const int32_t *__restrict__ xyz,
+                                                                uint64_t *__restrict__ dst,
+                                                                const uint32_t *__restrict__ hist,
+                                                                fgbd_result *__restrict__ res) {
+  constexpr int kPer = kMsdBins / kSortThreads;  // digits per thread: kPer t .. kPer t + kPer - 1
+  static_assert(kPer == 4, "one 16-byte count load per tile row and thread");
+  __shared__ uint32_t s_wh[4][kMsdBins];
+  __shared__ uint32_t s_off[kMsdBins];
+  __shared__ uint32_t s_tmp[2][4];
+  __shared__ uint64_t s_stage[kSortTile];
+
+  int d, tile;
+  xcd_tile(d, tile);
+  TileInfo ti;
+  if (!tile_info(a, tile, ti)) return;  // uniform over the block
+  const int t = threadIdx.x;
+  const int wave = t / kWave;
+  const int lane = (int)lane_id();
+  const int valid = ti.end - ti.begin;
+  for (int i = t; i < 4 * kMsdBins; i += kSortThreads) (&s_wh[0][0])[i] = 0;
+  // scanned counts of the thread's digits: the cloud's count and this tile's
+  // offset inside the cloud
+  const uint32_t *hd = hist + (size_t)d * a.row * kMsdBins + kPer * t;
+  const uint4 pf = ti.first > 0 ? *reinterpret_cast<const uint4 *>(hd + (size_t)ti.first * kMsdBins)
+                                : make_uint4(0u, 0u, 0u, 0u);
+  const uint4 pt = *reinterpret_cast<const uint4 *>(hd + (size_t)tile * kMsdBins);
+  const uint4 pn = *reinterpret_cast<const uint4 *>(hd + (size_t)ti.next_first * kMsdBins);
+  const uint32_t off_q[kPer] = {pt.x - pf.x, pt.y - pf.y, pt.z - pf.z, pt.w - pf.w};
+  const uint32_t below_q[kPer] = {pn.x - pf.x, pn.y - pf.y, pn.z - pf.z, pn.w - pf.w};
+
+  uint64_t item[kSortItems];
+  const CodeGen cg = code_gen(a.dt, d);
+  const int sh = msd_shift(a.dt, d);
+  const int base = ti.begin + wave * kWave * kSortItems + lane;
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int pos = base + j * kWave;
+    item[j] = (pos < ti.end) ? load_item(a, cg, xyz, nullptr, d, pos, &bad) : ~0ull;
+  }
+  if (bad && d == 0) atomicOr(&res[ti.s].status, FGBD_ST_COORD_RANGE);
+  __syncthreads();
+
+  // stable rank among the wave's equal digits (as in k_sort_downsweep);
+  // items past the tile's end have the largest digit and come last
+  uint32_t rk[kSortItems], before[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint32_t digit = msd_digit((uint32_t)(item[j] >> 32), sh);
+    int32_t m[kMsdBits];
+    uint64_t vote[kMsdBits];
+#pragma unroll
+    for (int b = 0; b < kMsdBits; ++b) {
+      m[b] = bit_mask(digit, b);
+      vote[b] = __builtin_amdgcn_ballot_w64(m[b] != 0);
+    }
+    uint32_t plo = ~0u, phi = ~0u;
+#pragma unroll
+    for (int b = 0; b < kMsdBits; ++b) {
+      plo &= ~((uint32_t)vote[b] ^ (uint32_t)m[b]);
+      phi &= ~((uint32_t)(vote[b] >> 32) ^ (uint32_t)m[b]);
+    }
+    const uint64_t peers = ((uint64_t)phi << 32) | plo;
+    before[j] = count_below(peers);
+    rk[j] = __hip_atomic_load(&s_wh[wave][digit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (before[j] == 0)
+      __hip_atomic_fetch_add(&s_wh[wave][digit], (uint32_t)__popcll(peers), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) rk[j] += before[j];
+  __syncthreads();
+
+  // per digit: exclusive over the tile's digits and over the cloud's digit
+  // totals (over the thread's kPer digits, then over the threads), each
+  // wave's start of the digit in the staged tile, and the global position of
+  // staged slot 0 of the digit's run
+  {
+    uint32_t c[4][kPer], ex_in[kPer], ex_below[kPer];
+    uint32_t run_in = 0, run_below = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) c[w][q] = s_wh[w][kPer * t + q];
+      ex_in[q] = run_in;
+      run_in += c[0][q] + c[1][q] + c[2][q] + c[3][q];
+      ex_below[q] = run_below;
+      run_below += below_q[q];
+    }
+    block_exclusive_scan2_256(run_in, run_below, s_tmp);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t e = run_in + ex_in[q];
+      s_wh[0][kPer * t + q] = e;
+      s_wh[1][kPer * t + q] = e + c[0][q];
+      s_wh[2][kPer * t + q] = e + c[0][q] + c[1][q];
+      s_wh[3][kPer * t + q] = e + c[0][q] + c[1][q] + c[2][q];
+      s_off[kPer * t + q] = (uint32_t)ti.seg_start + run_below + ex_below[q] + off_q[q] - e;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint32_t digit = msd_digit((uint32_t)(item[j] >> 32), sh);
+    s_stage[s_wh[wave][digit] + rk[j]] = item[j];
+  }
+  __syncthreads();
+  uint64_t *out = dst + (size_t)d * a.stride;
+  uint64_t st[kSortItems];
+  uint32_t gp[kSortItems];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) st[j] = s_stage[t + j * kSortThreads];
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j)
+    gp[j] = s_off[msd_digit((uint32_t)(st[j] >> 32), sh)] + (uint32_t)(t + j * kSortThreads);
+  // (the offsets stay inside the direction's row for counts that agree
+  // with the upsweep's; the bound only keeps a broken count from writing
+  // outside it)
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j)
+    if (t + j * kSortThreads < valid && gp[j] < (uint32_t)a.stride) out[gp[j]] = st[j];
+}
+
+constexpr int kLocalThreads = 512;
+constexpr int kLocalWaves = kLocalThreads / kWave;
+constexpr int kLocalItems = 16;                         // per thread, in-LDS ranges
+constexpr int kLocalCap = kLocalThreads * kLocalItems;  // 8192 items
+constexpr int kLocalWin = 4096;                         // sorted positions per window
+constexpr int kPosBits = 14;                            // an item's position in its range
+constexpr int kLocalKeyBits = 32 - kPosBits + 8;        // key bits the LDS entries can carry
+constexpr int kSlowItems = 8;                           // per thread and chunk, slow path
+static_assert(kLocalCap <= (1 << kPosBits), "positions in a range fit the entry's low bits");
+static_assert(2 * kLocalThreads == kMsdBins, "two top digits per thread when the range is found");
+
+struct LocalArgs {
+  DirTable dt;
+  SegArgs sa;
+  int64_t stride;
+  int32_t row;  // hist row length, as in SortArgs
+};
+
+// Stable rank of an 8-bit digit among the wave's equal digits (the
+// downsweep's ballot matching): returns the wave's count of the digit so far
+// (an LDS read not yet waited for), sets `before` to the peers in lower
+// lanes, and the first lane of each group of peers adds the group's size.
+__device__ __forceinline__ uint32_t wave_rank8(uint32_t digit, uint32_t *cnt, uint32_t &before) {
+  int32_t m[8];
+  uint64_t vote[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    m[b] = bit_mask(digit, b);
+    vote[b] = __builtin_amdgcn_ballot_w64(m[b] != 0);
+  }
+  uint32_t plo = ~0u, phi = ~0u;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    plo &= ~((uint32_t)vote[b] ^ (uint32_t)m[b]);
+    phi &= ~((uint32_t)(vote[b] >> 32) ^ (uint32_t)m[b]);
+  }
+  const uint64_t peers = ((uint64_t)phi << 32) | plo;
+  before = count_below(peers);
+  const uint32_t r = __hip_atomic_load(&cnt[digit], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (before == 0)
+    __hip_atomic_fetch_add(&cnt[digit], (uint32_t)__popcll(peers), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return r;
+}
+
+// Exclusive prefix of v over the threads of the block (up to 16 waves);
+// every thread calls it.  s_w: 16 words.
+__device__ __forceinline__ uint32_t exclusive_scan_block(uint32_t v, uint32_t *s_w) {
+  const uint32_t lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= (uint32_t)o) x += y;
+  }
+  if (lane == kWave - 1) s_w[w] = x;
+  __syncthreads();
+  uint32_t b = 0;
+  for (int ww = 0; ww < w; ++ww) b += s_w[ww];
+  __syncthreads();  // s_w is free again when this returns
+  return b + x - v;
+}
+
+// The cloud holding position x: the last cloud whose start is at most x.
+__device__ __forceinline__ int cloud_at(const int32_t *starts, int B, int x) {
+  int l = 0, h = B;  // starts[l] <= x; h == B or starts[h] > x
+  while (h - l > 1) {
+    const int m = (l + h) >> 1;
+    if (starts[m] <= x)
+      l = m;
+    else
+      h = m;
+  }
+  return l;
+}
+
+// One block per (direction, window of kLocalWin sorted positions).
+__global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_local_sort(LocalArgs a, uint64_t *__restrict__ src,
+                                                              uint64_t *__restrict__ dst,
+                                                              const uint32_t *__restrict__ hist,
+                                                              uint32_t *__restrict__ rank) {
+  __shared__ uint32_t s_ent[kLocalCap];
+  __shared__ uint32_t s_cnt[2][kLocalWaves][256];  // pass i counts in s_cnt[i & 1]
+  __shared__ uint32_t s_base[256];
+  __shared__ uint32_t s_w[16];
+  __shared__ int32_t s_starts[kMaxSeg + 1];
+  __shared__ int32_t s_lo, s_hi, s_multi;
+  __shared__ unsigned long long s_max;
+
+  // each XCD takes one contiguous range of the direction-major sequence
+  int d, win;
+  xcd_tile_last(d, win);
+  const bool segmented = a.sa.n_fixed < 0;
+  const int B = segmented ? a.sa.segs->B : 1;
+  const int n_tot = segmented ? a.sa.segs->n : a.sa.n_fixed;
+  const int w0 = win * kLocalWin;
+  if (w0 >= n_tot) return;  // uniform over the block
+  const int w1 = min(w0 + kLocalWin, n_tot);
+  const int t = threadIdx.x;
+  const int wave = t / kWave;
+  const int lane = (int)lane_id();
+  const size_t dbase = (size_t)d * a.stride;
+  const uint64_t *items = src + dbase;
+  const uint32_t *codes = reinterpret_cast<const uint32_t *>(items) + 1;  // codes[2 p]: item p's code
+  const int sh = msd_shift(a.dt, d);
+
+  if (t == 0) {
+    s_lo = 0x7fffffff;
+    s_hi = n_tot;
+    s_multi = 0;
+    s_max = 0ull;
+  }
+  for (int i = t; i <= B; i += kLocalThreads) s_starts[i] = segmented ? a.sa.segs->start[i] : (i == 0 ? 0 : n_tot);
+  for (int i = t; i < 2 * kLocalWaves * 256; i += kLocalThreads) (&s_cnt[0][0][0])[i] = 0u;
+  __syncthreads();
+
+  // The range: buckets start at the cloud starts and, inside a cloud, where
+  // the top digit changes; those positions come from the MSD pass's counts
+  // (never from the items, which a neighbouring block may be reordering).
+  // lo = the first bucket start in [w0, w1), hi = the first at or after w1.
+  for (int i = t; i <= B; i += kLocalThreads) {
+    const int st = s_starts[i];
+    if (st >= w0 && st < w1) atomicMin(&s_lo, st);
+    if (st >= w1) atomicMin(&s_hi, st);
+  }
+  const int ca = cloud_at(s_starts, B, w0);
+  const int cb = w1 < n_tot ? cloud_at(s_starts, B, w1) : ca;
+  for (int k = 0; k < (cb != ca ? 2 : 1); ++k) {  // uniform
+    const int cs = k == 0 ? ca : cb;
+    const int tf = segmented ? a.sa.segs->tile_first[cs] : 0;
+    const int tn = segmented ? a.sa.segs->tile_first[cs + 1]
+                             : (a.sa.n_fixed + kSortTile - 1) / kSortTile;
+    const uint32_t *hd = hist + (size_t)d * a.row * kMsdBins;
+    // the sizes of buckets 2t and 2t + 1 (top digits) of cloud cs, then
+    // their starts
+    const uint32_t c0 = hd[(size_t)tn * kMsdBins + 2 * t] - (tf > 0 ? hd[(size_t)tf * kMsdBins + 2 * t] : 0u);
+    const uint32_t c1 =
+        hd[(size_t)tn * kMsdBins + 2 * t + 1] - (tf > 0 ? hd[(size_t)tf * kMsdBins + 2 * t + 1] : 0u);
+    const uint32_t ex = exclusive_scan_block(c0 + c1, s_w);
+    const int st0 = s_starts[cs] + (int)ex, st1 = st0 + (int)c0;
+    if (c0 > 0) {
+      if (st0 >= w0 && st0 < w1) atomicMin(&s_lo, st0);
+      if (st0 >= w1) atomicMin(&s_hi, st0);
+    }
+    if (c1 > 0) {
+      if (st1 >= w0 && st1 < w1) atomicMin(&s_lo, st1);
+      if (st1 >= w1) atomicMin(&s_hi, st1);
+    }
+  }
+  __syncthreads();
+  const int lo = s_lo, hi = s_hi;
+  if (lo >= w1) return;  // no bucket starts in the window (uniform)
+  for (int i = t; i <= B; i += kLocalThreads)
+    if (s_starts[i] > lo && s_starts[i] < hi) s_multi = 1;
+  __syncthreads();
+  const bool multi = s_multi != 0;
+  const int R = hi - lo;
+  const uint32_t cf = (uint32_t)(items[lo] >> 32), cl = (uint32_t)(items[hi - 1] >> 32);
+  const uint32_t df = msd_digit(cf, sh), dl = msd_digit(cl, sh);
+  const uint32_t base = df << sh;
+  const int bits = sh + (dl > df ? 32 - __clz(dl - df) : 0);
+  const CodeGen cg = code_gen(a.dt, d);
+  uint64_t *out = dst + dbase;
+
+  if (!multi && R <= kLocalCap && bits <= kLocalKeyBits) {
+    // ---- in LDS.  Slots: wave w holds range positions (w J + j) 64 + lane,
+    // j < J, so the visiting order (wave, round, lane) is the range order.
+    // Entries between passes: (key bits not yet used) << kPosBits | position.
+    // Slots past the range (positions >= R) get the largest digit in every
+    // pass, so they stay after every real item.
+    const int passes = (bits + 7) / 8;
+    const int J = (R + kLocalThreads - 1) / kLocalThreads;  // <= kLocalItems
+    constexpr uint32_t kPosMask = (1u << kPosBits) - 1u;
+    // Each slot holds this pass's digit dg and the entry e it writes:
+    // (key bits above this pass's digit) << kPosBits | position.
+    uint32_t e[kLocalItems], dg[kLocalItems];
+    {
+      const uint32_t pbase = (uint32_t)(wave * J * kWave + lane);
+#pragma unroll
+      for (int j = 0; j < kLocalItems; ++j) {
+        const int s = (wave * J + j) * kWave + lane;
+        const uint32_t c = codes[2 * (size_t)(lo + min(s, R - 1))];  // clamped: every load unconditional
+        const bool ok = j < J && s < R;
+        const uint32_t rel = c - base;
+        dg[j] = ok ? (rel & 255u) : 255u;
+        e[j] = ((rel >> 8) << kPosBits) | (pbase + (uint32_t)(j * kWave));
+      }
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+      const bool last = pass == passes - 1;
+      uint32_t(*cnt)[256] = s_cnt[pass & 1];
+      // the next pass's counts (last used two passes ago) start cleared
+      for (int i = t; i < kLocalWaves * 256; i += kLocalThreads) (&s_cnt[(pass + 1) & 1][0][0])[i] = 0u;
+      uint32_t rk[kLocalItems], bf[kLocalItems];
+#pragma unroll
+      for (int j = 0; j < kLocalItems; ++j)
+        if (j < J) rk[j] = wave_rank8(dg[j], cnt[wave], bf[j]);  // (j < J is uniform)
+#pragma unroll
+      for (int j = 0; j < kLocalItems; ++j)
+        if (j < J) rk[j] += bf[j];
+      __syncthreads();
+      // per digit t: the exclusive prefix over digits, then each wave's start
+      // (column t is read twice rather than held in registers)
+      uint32_t tot = 0;
+      if (t < 256) {
+#pragma unroll
+        for (int w = 0; w < kLocalWaves; ++w) tot += cnt[w][t];
+      }
+      const uint32_t ex = exclusive_scan_block(tot, s_w);
+      if (t < 256) {
+        uint32_t run = ex;
+#pragma unroll
+        for (int w = 0; w < kLocalWaves; ++w) {
+          const uint32_t c = cnt[w][t];
+          cnt[w][t] = run;
+          run += c;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kLocalItems; ++j)
+        if (j < J) s_ent[cnt[wave][dg[j]] + rk[j]] = e[j];
+      __syncthreads();
+      if (!last) {
+        // the next pass: its digit, and the entry it writes
+#pragma unroll
+        for (int j = 0; j < kLocalItems; ++j) {
+          if (j < J) {
+            const uint32_t v = s_ent[(wave * J + j) * kWave + lane];
+            const uint32_t pos = v & kPosMask;
+            dg[j] = pos >= (uint32_t)R ? 255u : ((v >> kPosBits) & 255u);
+            e[j] = ((v >> (kPosBits + 8)) << kPosBits) | pos;
+          }
+        }
+        // (the next scatter into s_ent follows at least two barriers later)
+      }
+    }
+    // write-out in sorted order: slot s names its item's position in the
+    // range; the item comes from the MSD output (this block's own range)
+    for (int i0 = 0; i0 * kLocalThreads < R; i0 += 4) {  // uniform
+      uint32_t pp[4];
+      uint64_t it[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = min(t + (i0 + u) * kLocalThreads, R - 1);
+        pp[u] = passes > 0 ? (s_ent[s] & ((1u << kPosBits) - 1u)) : (uint32_t)s;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) it[u] = items[lo + min(pp[u], (uint32_t)(R - 1))];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = t + (i0 + u) * kLocalThreads;
+        const uint32_t idx = (uint32_t)it[u];
+        if (s < R && idx < (uint32_t)a.stride) {  // (idx is a point of the range; the bound is a guard)
+          out[lo + s] = ((uint64_t)decode_packed(cg, (uint32_t)(it[u] >> 32)) << 32) | idx;
+          rank[dbase + idx] = (uint32_t)(lo + s);
+        }
+      }
+    }
+    return;
+  }
+
+  // ---- slow path: the block sorts its range alone, LSD over 8-bit digits of
+  // the 64-bit key ((cloud - first cloud) << 32 | code) - base, in chunks of
+  // kSlowItems * kLocalThreads items per round, through the two item buffers
+  // (its own range of each).  An odd number of passes (a first pass of digit
+  // 0, a plain stable copy, when needed) ends in dst, in the final form.
+  const int c_first = cloud_at(s_starts, B, lo);
+  const uint64_t base64 = (uint64_t)base;
+  // the widest key of the range, for the pass count
+  {
+    unsigned long long mx = 0ull;
+    for (int s = t; s < R; s += kLocalThreads) {
+      const uint64_t it = items[lo + s];
+      const int cr = multi ? cloud_at(s_starts, B, (int)(uint32_t)it) - c_first : 0;
+      const uint64_t k64 = ((((uint64_t)cr) << 32) | (it >> 32)) - base64;
+      mx = k64 > mx ? k64 : mx;
+    }
+    atomicMax(&s_max, mx);
+  }
+  __syncthreads();
+  const unsigned long long kmax = s_max;
+  int P = kmax ? (64 - __clzll(kmax) + 7) / 8 : 0;
+  const int extra = (P % 2 == 0) ? 1 : 0;
+  P += extra;
+  for (int q = 0; q < P; ++q) {
+    const uint64_t *rd = ((q & 1) == 0 ? src : dst) + dbase;
+    uint64_t *wr = ((q & 1) == 0 ? dst : src) + dbase;
+    const bool last = q == P - 1;
+    const int shift = 8 * (q - extra);  // q < extra: the copy pass (digit 0)
+    if (t < 256) s_base[t] = 0u;
+    __syncthreads();
+    for (int s = t; s < R; s += kLocalThreads) {
+      const uint64_t it = rd[lo + s];
+      const int cr = multi ? cloud_at(s_starts, B, (int)(uint32_t)it) - c_first : 0;
+      const uint64_t k64 = ((((uint64_t)cr) << 32) | (it >> 32)) - base64;
+      const uint32_t digit = q < extra ? 0u : (uint32_t)((k64 >> shift) & 255u);
+      atomicAdd(&s_base[digit], 1u);
+    }
+    __syncthreads();
+    const uint32_t hv = t < 256 ? s_base[t] : 0u;
+    const uint32_t hex = exclusive_scan_block(hv, s_w);
+    if (t < 256) s_base[t] = hex;
+    __syncthreads();
+    for (int c0 = 0; c0 < R; c0 += kSlowItems * kLocalThreads) {
+      for (int i = t; i < kLocalWaves * 256; i += kLocalThreads) (&s_cnt[0][0][0])[i] = 0u;
+      __syncthreads();
+      uint64_t it[kSlowItems];
+      uint32_t dg[kSlowItems], rk[kSlowItems], bf[kSlowItems];
+#pragma unroll
+      for (int j = 0; j < kSlowItems; ++j) {
+        const int s = c0 + (wave * kSlowItems + j) * kWave + lane;
+        it[j] = rd[lo + min(s, R - 1)];
+      }
+#pragma unroll
+      for (int j = 0; j < kSlowItems; ++j) {
+        const int s = c0 + (wave * kSlowItems + j) * kWave + lane;
+        const int cr = multi ? cloud_at(s_starts, B, (int)(uint32_t)it[j]) - c_first : 0;
+        const uint64_t k64 = ((((uint64_t)cr) << 32) | (it[j] >> 32)) - base64;
+        dg[j] = s >= R ? 255u : (q < extra ? 0u : (uint32_t)((k64 >> shift) & 255u));
+      }
+#pragma unroll
+      for (int j = 0; j < kSlowItems; ++j) rk[j] = wave_rank8(dg[j], s_cnt[0][wave], bf[j]);
+#pragma unroll
+      for (int j = 0; j < kSlowItems; ++j) rk[j] += bf[j];
+      __syncthreads();
+      uint32_t tot = 0;
+      if (t < 256) {
+        uint32_t run = s_base[t];
+#pragma unroll
+        for (int w = 0; w < kLocalWaves; ++w) {
+          const uint32_t c = s_cnt[0][w][t];
+          s_cnt[0][w][t] = run;
+          run += c;
+          tot += c;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kSlowItems; ++j) {
+        const int s = c0 + (wave * kSlowItems + j) * kWave + lane;
+        const uint32_t dest = s_cnt[0][wave][dg[j]] + rk[j];
+        if (s < R && dest < (uint32_t)R) {  // (dest < R for counts that agree; the bound is a guard)
+          if (last) {
+            const uint32_t idx = (uint32_t)it[j];
+            wr[lo + dest] = ((uint64_t)decode_packed(cg, (uint32_t)(it[j] >> 32)) << 32) | idx;
+            if (idx < (uint32_t)a.stride) rank[dbase + idx] = (uint32_t)(lo + dest);
+          } else {
+            wr[lo + dest] = it[j];
+          }
+        }
+      }
+      __syncthreads();
+      if (t < 256) s_base[t] += tot;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 SetupArgs setup_args(const Run &r, const int64_t *offsets, int64_t n_host, fgbd_result *res, int zero_result) {
@@ -653,6 +1233,36 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
   a.su = r.setup;
   const int ntiles = r.sa.n_fixed >= 0 ? (r.sa.n_fixed + kSortTile - 1) / kSortTile : r.pl.ntiles_cap;
   const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
+  if (r.dt.passes == kSortPasses) {
+    // codes of at most 32 bits: the MSD pass, then the windows' local sorts
+    a.pass = 0;
+    a.passes = 1;
+    a.shift = 0;
+    a.fold = r.fold_setup ? 1 : 0;
+    if (a.fold && a.su.blocks > (int)(grid.x * grid.y)) a.su.blocks = (int)(grid.x * grid.y);
+    FGBD_PRE(r.pf, kUpsweep);
+    k_msd_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, r.b.hist);
+    FGBD_POST(r.pf);
+    FGBD_PRE(r.pf, kScan);
+    k_sort_scan<kMsdBins><<<r.dt.num_dirs * (kMsdBins / kWave), kScanWaves * kWave, 0, r.stream>>>(a, r.b.hist);
+    FGBD_POST(r.pf);
+    FGBD_PRE(r.pf, kDownsweep);
+    k_msd_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, r.b.items_a, r.b.hist, res);
+    FGBD_POST(r.pf);
+    LocalArgs la;
+    la.dt = r.dt;
+    la.sa = r.sa;
+    la.stride = r.pl.stride;
+    la.row = a.row;
+    const int64_t npos = r.sa.n_fixed >= 0 ? r.sa.n_fixed : r.pl.n_cap;
+    const int nwin = (int)((npos + kLocalWin - 1) / kLocalWin);
+    FGBD_PRE(r.pf, kLocalSort);
+    k_local_sort<<<dim3(nwin > 0 ? nwin : 1, r.dt.num_dirs), kLocalThreads, 0, r.stream>>>(
+        la, r.b.items_a, r.b.items_b, r.b.hist, r.b.rank);
+    FGBD_POST(r.pf);
+    *sorted_out = r.b.items_b;
+    return hipGetLastError();
+  }
   const uint64_t *src = nullptr;
   uint64_t *bufs[2] = {r.b.items_a, r.b.items_b};
   a.passes = r.dt.passes;
@@ -666,7 +1276,7 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
     k_sort_upsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, r.b.digits, r.b.hist);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kScan);
-    k_sort_scan<<<r.dt.num_dirs * 4, kScanWaves * kWave, 0, r.stream>>>(a, r.b.hist);
+    k_sort_scan<256><<<r.dt.num_dirs * 4, kScanWaves * kWave, 0, r.stream>>>(a, r.b.hist);
     FGBD_POST(r.pf);
     FGBD_PRE(r.pf, kDownsweep);
     k_sort_downsweep<<<grid, kSortThreads, 0, r.stream>>>(a, xyz, src, dst, r.b.hist, r.b.digits, r.b.rank, res);

@@ -29,11 +29,11 @@ FGBD_ST_BAD_OFFSETS = 4
 FGBD_ST_SWEEP_STALL = 8
 FGBD_ST_RELABELED = 16
 FGBD_ST_DIST_CLAMPED = 32
-NUM_KERNELS = 10
-ABI_VERSION = 7
+NUM_KERNELS = 11
+ABI_VERSION = 8
 MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
-           "finalize", "relabel")
+           "finalize", "relabel", "local_sort")
 
 
 class FgbdError(RuntimeError):

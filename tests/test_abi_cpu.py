@@ -42,7 +42,7 @@ def test_status_constants_match_header():
 
 
 def test_version_and_defaults():
-    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 7
+    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 8
     p = fgbd.default_params()
     assert (p.bits, p.num_dirs, p.window, p.k, p.patch, p.q_max) == (10, 8, 4, 8, 0, 32)
     assert p.fslr_kappa == 2.0 and p.sigma_g == 0.0

@@ -83,6 +83,19 @@ def test_slg_all_directions_b10_extremes():
     check_graph(g, fgbd.default_params(bits=10, num_dirs=16, window=2, k=8))
 
 
+def test_slg_plane_normal_to_a_scan_axis():
+    # 25,600 points on the plane z = 500 share one top code digit in the scan
+    # orders whose high axis is z: a bucket far beyond one block's LDS, which
+    # the local sort then takes alone through the item buffers; the other
+    # orders and the scattered points take the in-LDS passes
+    rng = np.random.default_rng(11)
+    xs, ys = np.meshgrid(np.arange(300, 460), np.arange(200, 360), indexing="ij")
+    plane = np.stack([xs.ravel(), ys.ravel(), np.full(xs.size, 500)], axis=1)
+    extra = rng.integers(0, 1024, size=(3000, 3))
+    g = np.concatenate([plane, extra])[rng.permutation(plane.shape[0] + 3000)].astype(np.int32)
+    check_graph(g, fgbd.default_params(bits=10, num_dirs=8, window=4, k=8))
+
+
 def test_fixed_sigma_g():
     c = synth.tiny_cloud(0)
     check_graph(c.xyz, fgbd.default_params(bits=8, sigma_g=2.5))
