@@ -144,6 +144,7 @@ Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune) {
   pl.off_hist = take((size_t)pl.L * (pl.ntiles_cap + 1) * kMsdBins * 4);  // 256 digits per tile row in LSD passes
   pl.off_rank = take((size_t)pl.L * pl.stride * 4);
   pl.off_digits = take((size_t)pl.L * pl.stride);
+  pl.off_win = take((size_t)pl.L * ((N + kLocalWin - 1) / kLocalWin) * 4);
   pl.off_col = take(N * pl.K * 4);
   pl.off_dist2 = take(N * pl.K * 4);
   pl.off_p = take(N * pl.K * 4);
@@ -168,6 +169,7 @@ Bufs carve(char *ws, const Plan &pl) {
   b.hist = (uint32_t *)(ws + pl.off_hist);
   b.rank = (uint32_t *)(ws + pl.off_rank);
   b.digits = (uint8_t *)(ws + pl.off_digits);
+  b.win = (int32_t *)(ws + pl.off_win);
   b.col = (int32_t *)(ws + pl.off_col);
   b.dist2 = (int32_t *)(ws + pl.off_dist2);
   b.p = (float *)(ws + pl.off_p);
@@ -1130,6 +1132,7 @@ fgbd_status fgbd_estimate_noise_noalloc(fgbd_ctx ctx, const fgbd_graph *g, const
   r.b.items_a = r.b.items_b = nullptr;
   r.b.hist = r.b.rank = nullptr;
   r.b.digits = nullptr;
+  r.b.win = nullptr;
   r.b.col = r.b.dist2 = nullptr;
   r.b.p = nullptr;
   r.b.spread = nullptr;

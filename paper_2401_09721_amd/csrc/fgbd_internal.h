@@ -356,7 +356,7 @@ struct Plan {
   int32_t ntiles_cap;        // radix tiles: ceil(n_cap / tile) + B - 1
   int32_t grid[kNumGrids];   // blocks of the per-cloud grids (each >= B)
   int32_t E1;                // 1 + D(D+1)/2 + 3D: patch count and moment entries
-  size_t off_segs, off_items_a, off_items_b, off_hist, off_rank, off_digits;
+  size_t off_segs, off_items_a, off_items_b, off_hist, off_rank, off_digits, off_win;
   size_t off_col, off_dist2, off_p, off_spread, off_xbuf, off_rgbw, off_colw, off_dist2w;
   size_t off_edge_acc, off_noise_acc, off_ctrl, off_sweep_sums;
   size_t total;
@@ -369,6 +369,7 @@ constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit 
 // codes of at most 32 bits: one pass on the top kMsdBits bits, then local sorts
 constexpr int kMsdBits = 10;
 constexpr int kMsdBins = 1 << kMsdBits;
+constexpr int kLocalWin = kSortTile;  // sorted positions per local-sort window
 
 constexpr int kBlock = 256;
 constexpr int kMaxGrid = 1024;  // default grid cap of the grid-stride kernels
@@ -408,6 +409,7 @@ struct Bufs {
   uint32_t *hist;               // [L][ntiles_cap + 1][256]
   uint32_t *rank;               // [L][stride]
   uint8_t *digits;              // [L][stride]: the next radix pass's digit of each sorted item
+  int32_t *win;                 // [L][windows]: the first bucket start in each local-sort window
   int32_t *col, *dist2;         // [n_cap][K]
   float *p;                     // [n_cap][K] weights the fused path's first sweep stores
   double *spread;               // [n_cap]

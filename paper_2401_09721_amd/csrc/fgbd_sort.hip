@@ -46,6 +46,8 @@ struct SortArgs {
   int32_t passes;     // passes of the sort (4, or more for codes above 32 bits)
   int32_t fold;       // pass 0 only: the first blocks also do the call's setup
   SetupArgs su;
+  int32_t *win;       // top-digit pass: the first bucket start of each local-sort window
+  int32_t nwin;       // windows per direction
 };
 
 // The tile's cloud and point range; false for a tile beyond the last one.
@@ -662,6 +664,10 @@ __global__ __launch_bounds__(kSortThreads) void k_msd_upsweep(SortArgs a, const 
   }
   int d, tile;
   xcd_tile(d, tile);
+  // every (direction, window) entry of the window table starts empty; the
+  // downsweep then writes each window's first bucket start (blocks and
+  // windows pair up one to one: the grid has at least one tile per window)
+  if (threadIdx.x == 0 && tile < a.nwin) a.win[(size_t)d * a.nwin + tile] = 0x7fffffff;
   TileInfo ti;
   if (!tile_info(a, tile, ti)) return;  // uniform over the block
   const int t = threadIdx.x;
@@ -808,6 +814,17 @@ __global__ __launch_bounds__(kSortThreads) void k_msd_downsweep(SortArgs a, cons
       s_wh[3][kPer * t + q] = e + c[0][q] + c[1][q] + c[2][q];
       s_off[kPer * t + q] = (uint32_t)ti.seg_start + run_below + ex_below[q] + off_q[q] - e;
     }
+    // the cloud's first tile records where its buckets start: each window's
+    // entry keeps the first start inside it
+    if (tile == ti.first) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        if (below_q[q] > 0) {
+          const int st = ti.seg_start + (int)(run_below + ex_below[q]);
+          atomicMin(&a.win[(size_t)d * a.nwin + st / kLocalWin], st);
+        }
+      }
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -836,18 +853,16 @@ constexpr int kLocalThreads = 512;
 constexpr int kLocalWaves = kLocalThreads / kWave;
 constexpr int kLocalItems = 16;                         // per thread, in-LDS ranges
 constexpr int kLocalCap = kLocalThreads * kLocalItems;  // 8192 items
-constexpr int kLocalWin = 4096;                         // sorted positions per window
-constexpr int kPosBits = 14;                            // an item's position in its range
-constexpr int kLocalKeyBits = 32 - kPosBits + 8;        // key bits the LDS entries can carry
+constexpr int kLocalKeyBits = 26;                       // wider relative keys take the slow path
 constexpr int kSlowItems = 8;                           // per thread and chunk, slow path
-static_assert(kLocalCap <= (1 << kPosBits), "positions in a range fit the entry's low bits");
 static_assert(2 * kLocalThreads == kMsdBins, "two top digits per thread when the range is found");
 
 struct LocalArgs {
   DirTable dt;
   SegArgs sa;
   int64_t stride;
-  int32_t row;  // hist row length, as in SortArgs
+  const int32_t *win;  // [L][nwin]: each window's first bucket start (0x7fffffff: none)
+  int32_t nwin;
 };
 
 // Stable rank of an 8-bit digit among the wave's equal digits (the
@@ -909,16 +924,14 @@ __device__ __forceinline__ int cloud_at(const int32_t *starts, int B, int x) {
 }
 
 // One block per (direction, window of kLocalWin sorted positions).
-__global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_local_sort(LocalArgs a, uint64_t *__restrict__ src,
-                                                              uint64_t *__restrict__ dst,
-                                                              const uint32_t *__restrict__ hist,
-                                                              uint32_t *__restrict__ rank) {
-  __shared__ uint32_t s_ent[kLocalCap];
-  __shared__ uint32_t s_cnt[2][kLocalWaves][256];  // pass i counts in s_cnt[i & 1]
+__global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_local_sort(
+    LocalArgs a, uint64_t *__restrict__ src, uint64_t *__restrict__ dst, uint32_t *__restrict__ rank) {
+  __shared__ uint64_t s_it[kLocalCap];
+  __shared__ uint32_t s_cnt[kLocalWaves][256];
   __shared__ uint32_t s_base[256];
   __shared__ uint32_t s_w[16];
   __shared__ int32_t s_starts[kMaxSeg + 1];
-  __shared__ int32_t s_lo, s_hi, s_multi;
+  __shared__ int32_t s_multi;
   __shared__ unsigned long long s_max;
 
   // each XCD takes one contiguous range of the direction-major sequence
@@ -935,55 +948,31 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
   const int lane = (int)lane_id();
   const size_t dbase = (size_t)d * a.stride;
   const uint64_t *items = src + dbase;
-  const uint32_t *codes = reinterpret_cast<const uint32_t *>(items) + 1;  // codes[2 p]: item p's code
   const int sh = msd_shift(a.dt, d);
 
+  // The range: buckets start at the cloud starts and, inside a cloud, where
+  // the top digit changes.  The top-digit pass recorded each window's first
+  // bucket start (from its counts, never from the items, which a
+  // neighbouring block may be reordering): lo = this window's, hi = the
+  // next one recorded after it (or the end).
+  const int32_t *wrow = a.win + (size_t)d * a.nwin;
+  const int lo = wrow[win];
+  if (lo >= w1) return;  // no bucket starts in the window (uniform)
+  int hi = n_tot;
+  for (int k = win + 1; k < a.nwin; ++k) {  // uniform; nearly always one step
+    const int v = wrow[k];
+    if (v < n_tot) {
+      hi = v;
+      break;
+    }
+  }
   if (t == 0) {
-    s_lo = 0x7fffffff;
-    s_hi = n_tot;
     s_multi = 0;
     s_max = 0ull;
   }
   for (int i = t; i <= B; i += kLocalThreads) s_starts[i] = segmented ? a.sa.segs->start[i] : (i == 0 ? 0 : n_tot);
-  for (int i = t; i < 2 * kLocalWaves * 256; i += kLocalThreads) (&s_cnt[0][0][0])[i] = 0u;
+  for (int i = t; i < kLocalWaves * 256; i += kLocalThreads) (&s_cnt[0][0])[i] = 0u;  // the first pass's counts
   __syncthreads();
-
-  // The range: buckets start at the cloud starts and, inside a cloud, where
-  // the top digit changes; those positions come from the MSD pass's counts
-  // (never from the items, which a neighbouring block may be reordering).
-  // lo = the first bucket start in [w0, w1), hi = the first at or after w1.
-  for (int i = t; i <= B; i += kLocalThreads) {
-    const int st = s_starts[i];
-    if (st >= w0 && st < w1) atomicMin(&s_lo, st);
-    if (st >= w1) atomicMin(&s_hi, st);
-  }
-  const int ca = cloud_at(s_starts, B, w0);
-  const int cb = w1 < n_tot ? cloud_at(s_starts, B, w1) : ca;
-  for (int k = 0; k < (cb != ca ? 2 : 1); ++k) {  // uniform
-    const int cs = k == 0 ? ca : cb;
-    const int tf = segmented ? a.sa.segs->tile_first[cs] : 0;
-    const int tn = segmented ? a.sa.segs->tile_first[cs + 1]
-                             : (a.sa.n_fixed + kSortTile - 1) / kSortTile;
-    const uint32_t *hd = hist + (size_t)d * a.row * kMsdBins;
-    // the sizes of buckets 2t and 2t + 1 (top digits) of cloud cs, then
-    // their starts
-    const uint32_t c0 = hd[(size_t)tn * kMsdBins + 2 * t] - (tf > 0 ? hd[(size_t)tf * kMsdBins + 2 * t] : 0u);
-    const uint32_t c1 =
-        hd[(size_t)tn * kMsdBins + 2 * t + 1] - (tf > 0 ? hd[(size_t)tf * kMsdBins + 2 * t + 1] : 0u);
-    const uint32_t ex = exclusive_scan_block(c0 + c1, s_w);
-    const int st0 = s_starts[cs] + (int)ex, st1 = st0 + (int)c0;
-    if (c0 > 0) {
-      if (st0 >= w0 && st0 < w1) atomicMin(&s_lo, st0);
-      if (st0 >= w1) atomicMin(&s_hi, st0);
-    }
-    if (c1 > 0) {
-      if (st1 >= w0 && st1 < w1) atomicMin(&s_lo, st1);
-      if (st1 >= w1) atomicMin(&s_hi, st1);
-    }
-  }
-  __syncthreads();
-  const int lo = s_lo, hi = s_hi;
-  if (lo >= w1) return;  // no bucket starts in the window (uniform)
   for (int i = t; i <= B; i += kLocalThreads)
     if (s_starts[i] > lo && s_starts[i] < hi) s_multi = 1;
   __syncthreads();
@@ -999,36 +988,29 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
   if (!multi && R <= kLocalCap && bits <= kLocalKeyBits) {
     // ---- in LDS.  Slots: wave w holds range positions (w J + j) 64 + lane,
     // j < J, so the visiting order (wave, round, lane) is the range order.
-    // Entries between passes: (key bits not yet used) << kPosBits | position.
-    // Slots past the range (positions >= R) get the largest digit in every
-    // pass, so they stay after every real item.
-    const int passes = (bits + 7) / 8;
+    // The items themselves move from pass to pass through s_it; a pass's
+    // digit is a byte of the code less the range's base, and slots past the
+    // range (index all ones) take the largest digit, so they stay after
+    // every real item.
+    const int passes = bits > 0 ? (bits + 7) / 8 : 1;  // (one pass of digit 0 copies)
     const int J = (R + kLocalThreads - 1) / kLocalThreads;  // <= kLocalItems
-    constexpr uint32_t kPosMask = (1u << kPosBits) - 1u;
-    // Each slot holds this pass's digit dg and the entry e it writes:
-    // (key bits above this pass's digit) << kPosBits | position.
-    uint32_t e[kLocalItems], dg[kLocalItems];
-    {
-      const uint32_t pbase = (uint32_t)(wave * J * kWave + lane);
+    uint64_t it[kLocalItems];
 #pragma unroll
-      for (int j = 0; j < kLocalItems; ++j) {
-        const int s = (wave * J + j) * kWave + lane;
-        const uint32_t c = codes[2 * (size_t)(lo + min(s, R - 1))];  // clamped: every load unconditional
-        const bool ok = j < J && s < R;
-        const uint32_t rel = c - base;
-        dg[j] = ok ? (rel & 255u) : 255u;
-        e[j] = ((rel >> 8) << kPosBits) | (pbase + (uint32_t)(j * kWave));
-      }
+    for (int j = 0; j < kLocalItems; ++j) {
+      const int s = (wave * J + j) * kWave + lane;
+      const uint64_t v = items[lo + min(s, R - 1)];  // clamped: every load unconditional
+      it[j] = (j < J && s < R) ? v : ~0ull;
     }
     for (int pass = 0; pass < passes; ++pass) {
       const bool last = pass == passes - 1;
-      uint32_t(*cnt)[256] = s_cnt[pass & 1];
-      // the next pass's counts (last used two passes ago) start cleared
-      for (int i = t; i < kLocalWaves * 256; i += kLocalThreads) (&s_cnt[(pass + 1) & 1][0][0])[i] = 0u;
+      const uint32_t sft = 8u * (uint32_t)pass;
+      auto digit = [&](uint64_t v) {
+        return (uint32_t)v == ~0u ? 255u : __builtin_amdgcn_ubfe((uint32_t)(v >> 32) - base, sft, 8u);
+      };
       uint32_t rk[kLocalItems], bf[kLocalItems];
 #pragma unroll
       for (int j = 0; j < kLocalItems; ++j)
-        if (j < J) rk[j] = wave_rank8(dg[j], cnt[wave], bf[j]);  // (j < J is uniform)
+        if (j < J) rk[j] = wave_rank8(digit(it[j]), s_cnt[wave], bf[j]);  // (j < J is uniform)
 #pragma unroll
       for (int j = 0; j < kLocalItems; ++j)
         if (j < J) rk[j] += bf[j];
@@ -1038,55 +1020,42 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
       uint32_t tot = 0;
       if (t < 256) {
 #pragma unroll
-        for (int w = 0; w < kLocalWaves; ++w) tot += cnt[w][t];
+        for (int w = 0; w < kLocalWaves; ++w) tot += s_cnt[w][t];
       }
       const uint32_t ex = exclusive_scan_block(tot, s_w);
       if (t < 256) {
         uint32_t run = ex;
 #pragma unroll
         for (int w = 0; w < kLocalWaves; ++w) {
-          const uint32_t c = cnt[w][t];
-          cnt[w][t] = run;
+          const uint32_t c = s_cnt[w][t];
+          s_cnt[w][t] = run;
           run += c;
         }
       }
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < kLocalItems; ++j)
-        if (j < J) s_ent[cnt[wave][dg[j]] + rk[j]] = e[j];
+        if (j < J) s_it[s_cnt[wave][digit(it[j])] + rk[j]] = it[j];
       __syncthreads();
       if (!last) {
-        // the next pass: its digit, and the entry it writes
 #pragma unroll
-        for (int j = 0; j < kLocalItems; ++j) {
-          if (j < J) {
-            const uint32_t v = s_ent[(wave * J + j) * kWave + lane];
-            const uint32_t pos = v & kPosMask;
-            dg[j] = pos >= (uint32_t)R ? 255u : ((v >> kPosBits) & 255u);
-            e[j] = ((v >> (kPosBits + 8)) << kPosBits) | pos;
-          }
-        }
-        // (the next scatter into s_ent follows at least two barriers later)
+        for (int j = 0; j < kLocalItems; ++j)
+          if (j < J) it[j] = s_it[(wave * J + j) * kWave + lane];
+        for (int i = t; i < kLocalWaves * 256; i += kLocalThreads) (&s_cnt[0][0])[i] = 0u;
+        __syncthreads();
       }
     }
-    // write-out in sorted order: slot s names its item's position in the
-    // range; the item comes from the MSD output (this block's own range)
+    // write-out in sorted order, straight from LDS
     for (int i0 = 0; i0 * kLocalThreads < R; i0 += 4) {  // uniform
-      uint32_t pp[4];
-      uint64_t it[4];
+      uint64_t v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int s = min(t + (i0 + u) * kLocalThreads, R - 1);
-        pp[u] = passes > 0 ? (s_ent[s] & ((1u << kPosBits) - 1u)) : (uint32_t)s;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) it[u] = items[lo + min(pp[u], (uint32_t)(R - 1))];
+      for (int u = 0; u < 4; ++u) v[u] = s_it[min(t + (i0 + u) * kLocalThreads, R - 1)];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int s = t + (i0 + u) * kLocalThreads;
-        const uint32_t idx = (uint32_t)it[u];
+        const uint32_t idx = (uint32_t)v[u];
         if (s < R && idx < (uint32_t)a.stride) {  // (idx is a point of the range; the bound is a guard)
-          out[lo + s] = ((uint64_t)decode_packed(cg, (uint32_t)(it[u] >> 32)) << 32) | idx;
+          out[lo + s] = ((uint64_t)decode_packed(cg, (uint32_t)(v[u] >> 32)) << 32) | idx;
           rank[dbase + idx] = (uint32_t)(lo + s);
         }
       }
@@ -1137,7 +1106,7 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
     if (t < 256) s_base[t] = hex;
     __syncthreads();
     for (int c0 = 0; c0 < R; c0 += kSlowItems * kLocalThreads) {
-      for (int i = t; i < kLocalWaves * 256; i += kLocalThreads) (&s_cnt[0][0][0])[i] = 0u;
+      for (int i = t; i < kLocalWaves * 256; i += kLocalThreads) (&s_cnt[0][0])[i] = 0u;
       __syncthreads();
       uint64_t it[kSlowItems];
       uint32_t dg[kSlowItems], rk[kSlowItems], bf[kSlowItems];
@@ -1154,7 +1123,7 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
         dg[j] = s >= R ? 255u : (q < extra ? 0u : (uint32_t)((k64 >> shift) & 255u));
       }
 #pragma unroll
-      for (int j = 0; j < kSlowItems; ++j) rk[j] = wave_rank8(dg[j], s_cnt[0][wave], bf[j]);
+      for (int j = 0; j < kSlowItems; ++j) rk[j] = wave_rank8(dg[j], s_cnt[wave], bf[j]);
 #pragma unroll
       for (int j = 0; j < kSlowItems; ++j) rk[j] += bf[j];
       __syncthreads();
@@ -1163,8 +1132,8 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
         uint32_t run = s_base[t];
 #pragma unroll
         for (int w = 0; w < kLocalWaves; ++w) {
-          const uint32_t c = s_cnt[0][w][t];
-          s_cnt[0][w][t] = run;
+          const uint32_t c = s_cnt[w][t];
+          s_cnt[w][t] = run;
           run += c;
           tot += c;
         }
@@ -1173,7 +1142,7 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
       for (int j = 0; j < kSlowItems; ++j) {
         const int s = c0 + (wave * kSlowItems + j) * kWave + lane;
-        const uint32_t dest = s_cnt[0][wave][dg[j]] + rk[j];
+        const uint32_t dest = s_cnt[wave][dg[j]] + rk[j];
         if (s < R && dest < (uint32_t)R) {  // (dest < R for counts that agree; the bound is a guard)
           if (last) {
             const uint32_t idx = (uint32_t)it[j];
@@ -1225,6 +1194,8 @@ hipError_t launch_setup(const Run &r, const int64_t *offsets, int64_t n_host, fg
 
 hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const uint64_t **sorted_out) {
   SortArgs a;
+  a.win = nullptr;
+  a.nwin = 0;
   a.dt = r.dt;
   a.sa = r.sa;
   a.stride = r.pl.stride;
@@ -1235,6 +1206,10 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
   const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
   if (r.dt.passes == kSortPasses) {
     // codes of at most 32 bits: the MSD pass, then the windows' local sorts
+    const int64_t npos = r.sa.n_fixed >= 0 ? r.sa.n_fixed : r.pl.n_cap;
+    a.nwin = (int)((npos + kLocalWin - 1) / kLocalWin);
+    if (a.nwin < 1) a.nwin = 1;
+    a.win = r.b.win;
     a.pass = 0;
     a.passes = 1;
     a.shift = 0;
@@ -1253,12 +1228,11 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
     la.dt = r.dt;
     la.sa = r.sa;
     la.stride = r.pl.stride;
-    la.row = a.row;
-    const int64_t npos = r.sa.n_fixed >= 0 ? r.sa.n_fixed : r.pl.n_cap;
-    const int nwin = (int)((npos + kLocalWin - 1) / kLocalWin);
+    la.win = r.b.win;
+    la.nwin = a.nwin;
     FGBD_PRE(r.pf, kLocalSort);
-    k_local_sort<<<dim3(nwin > 0 ? nwin : 1, r.dt.num_dirs), kLocalThreads, 0, r.stream>>>(
-        la, r.b.items_a, r.b.items_b, r.b.hist, r.b.rank);
+    k_local_sort<<<dim3(a.nwin, r.dt.num_dirs), kLocalThreads, 0, r.stream>>>(la, r.b.items_a, r.b.items_b,
+                                                                              r.b.rank);
     FGBD_POST(r.pf);
     *sorted_out = r.b.items_b;
     return hipGetLastError();
