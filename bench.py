@@ -77,11 +77,10 @@ def source_digest(kind: str) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kind: str, config: dict):
-    """HBM bytes per launch of `kind` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
-    plain device copy), or None when the summary is missing, was taken on
-    another workload, or the kernel's sources changed since."""
+def _counter_record(kind: str, config: dict):
+    """The committed counter record of `kind`, or None when the summary is
+    missing, was taken on another workload, or the kernel's sources changed
+    since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             text = fh.read()
@@ -91,7 +90,32 @@ def measured_traffic(kind: str, config: dict):
     k = rec.get("kernels", {}).get(kind)
     if not k or rec.get("config") != config or k.get("source_sha256") != source_digest(kind):
         return None
-    return k["hbm_bytes_per_launch"]
+    return k
+
+
+def measured_traffic(kind: str, config: dict):
+    """HBM bytes per launch of `kind` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    plain device copy), or None (see _counter_record)."""
+    k = _counter_record(kind, config)
+    return k["hbm_bytes_per_launch"] if k else None
+
+
+# VALU issue peak: 256 compute units, each issuing one 64-lane vector
+# instruction per cycle (four SIMDs, four cycles each), at 2.4 GHz.
+VALU_ISSUE_PEAK = 256 * 2.4e9
+
+
+def measured_valu(kind: str, config: dict, us_per_launch: float):
+    """Vector instructions per launch of `kind` (SQ_INSTS_VALU, wave level) from
+    the committed counter summary, and the fraction of the VALU issue peak
+    they take at the measured duration; None when there is no record."""
+    k = _counter_record(kind, config)
+    if not k or not k.get("valu_insts"):
+        return None
+    insts = k["valu_insts"]
+    return {"insts_per_launch": insts, "issue_peak_per_s": VALU_ISSUE_PEAK,
+            "frac": insts / (us_per_launch * 1e-6) / VALU_ISSUE_PEAK}
 
 
 def _gen(job):
@@ -758,7 +782,8 @@ def main() -> int:
                             "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom, tcfg),
                             "bytes_per_step": step_bytes(dom), "ms_per_step": kernels[dom]["ms_per_step"],
                             "launches_per_step": kernels[dom]["launches_per_step"],
-                            "timing": "HIP events around each launch on the library's stream"}
+                            "timing": "HIP events around each launch on the library's stream",
+                            "valu": measured_valu(dom, tcfg, kernels[dom]["us_per_launch"])}
         print(f"# kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
         # Active sweeps alone, the kernel the bandwidth target is set on: the

@@ -1,8 +1,10 @@
-// Scan-line codes and the LSD radix sort of Sec. 2.2 (the paper orders the
+// Scan-line codes and the radix sort of Sec. 2.2 (the paper orders the
 // points of each code with a radix sort).  One launch covers all L directions
 // (grid.y = direction).  Items are 64-bit: code << 32 | point index, so each
 // pass moves 8 bytes per item and ties (duplicate points) keep index order
-// because every pass is stable.
+// because every pass is stable.  Codes of at most 32 bits take the top-digit
+// route at the end of this file (one pass on the top 10 bits, then each
+// window's buckets sorted in LDS); the LSD passes below sort wider codes.
 //
 // Per 8-bit digit pass (4 passes for 32-bit codes):
 //   upsweep   per tile digit histogram            -> hist[dir][tile][digit]
@@ -988,10 +990,10 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
   if (!multi && R <= kLocalCap && bits <= kLocalKeyBits) {
     // ---- in LDS.  Slots: wave w holds range positions (w J + j) 64 + lane,
     // j < J, so the visiting order (wave, round, lane) is the range order.
-    // The items themselves move from pass to pass through s_it; a pass's
-    // digit is a byte of the code less the range's base, and slots past the
-    // range (index all ones) take the largest digit, so they stay after
-    // every real item.
+    // The items move from pass to pass through s_it carrying the code less
+    // the range's base (rel << 32 | index), so a pass's digit is one byte of
+    // rel; slots past the range hold all ones, take the largest digit in
+    // every pass and stay after every real item.
     const int passes = bits > 0 ? (bits + 7) / 8 : 1;  // (one pass of digit 0 copies)
     const int J = (R + kLocalThreads - 1) / kLocalThreads;  // <= kLocalItems
     uint64_t it[kLocalItems];
@@ -999,14 +1001,12 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
     for (int j = 0; j < kLocalItems; ++j) {
       const int s = (wave * J + j) * kWave + lane;
       const uint64_t v = items[lo + min(s, R - 1)];  // clamped: every load unconditional
-      it[j] = (j < J && s < R) ? v : ~0ull;
+      it[j] = (j < J && s < R) ? v - ((uint64_t)base << 32) : ~0ull;
     }
     for (int pass = 0; pass < passes; ++pass) {
       const bool last = pass == passes - 1;
       const uint32_t sft = 8u * (uint32_t)pass;
-      auto digit = [&](uint64_t v) {
-        return (uint32_t)v == ~0u ? 255u : __builtin_amdgcn_ubfe((uint32_t)(v >> 32) - base, sft, 8u);
-      };
+      auto digit = [&](uint64_t v) { return __builtin_amdgcn_ubfe((uint32_t)(v >> 32), sft, 8u); };
       uint32_t rk[kLocalItems], bf[kLocalItems];
 #pragma unroll
       for (int j = 0; j < kLocalItems; ++j)
@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
         const int s = t + (i0 + u) * kLocalThreads;
         const uint32_t idx = (uint32_t)v[u];
         if (s < R && idx < (uint32_t)a.stride) {  // (idx is a point of the range; the bound is a guard)
-          out[lo + s] = ((uint64_t)decode_packed(cg, (uint32_t)(v[u] >> 32)) << 32) | idx;
+          out[lo + s] = ((uint64_t)decode_packed(cg, (uint32_t)(v[u] >> 32) + base) << 32) | idx;
           rank[dbase + idx] = (uint32_t)(lo + s);
         }
       }
