@@ -76,6 +76,16 @@ struct fgbd_ctx_s {
   int hint_B = 0;
   int hint_recent[8] = {0};      // ring of the last counts read (max over clouds)
   int hint_count = 0;
+  // Sort route: a host-mapped flag the local sort sets when a block sorted a
+  // very large range alone (points crowded into few top code digits, such as
+  // a plane normal to a scan axis), read back without waiting like the sweep
+  // counts; while sort_lsd_left > 0, eager calls sort by LSD passes.
+  int32_t *sort_flag_host = nullptr;
+  int32_t *sort_flag_dev = nullptr;
+  hipEvent_t sort_ev = nullptr;
+  bool sort_failed = false;
+  bool sort_pending = false;
+  int sort_lsd_left = 0;
   int64_t wait_us = -1;  // fgbd_set_sweep_wait
 };
 
@@ -341,6 +351,54 @@ Run make_run(fgbd_ctx ctx, const Plan &pl, char *ws, const fgbd_params &prm, int
   return r;
 }
 
+// The sort route of an eager call (captured calls keep the top-digit sort and
+// watch nothing).  A completed read-back that found a very large range sorted
+// by one block switches the context to LSD passes for kSortLsdCalls calls;
+// otherwise, with no read-back outstanding, the call arms the flag.
+static void sort_policy(fgbd_ctx ctx, hipStream_t s, Run &r) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (ctx->sort_failed) return;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (cs != hipStreamCaptureStatusNone) return;
+  if (!ctx->sort_flag_host) {
+    void *dev = nullptr;
+    if (hipHostMalloc((void **)&ctx->sort_flag_host, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer(&dev, ctx->sort_flag_host, 0) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->sort_ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->sort_failed = true;
+      return;
+    }
+    ctx->sort_flag_dev = (int32_t *)dev;
+  }
+  if (ctx->sort_pending) {
+    const hipError_t q = hipEventQuery(ctx->sort_ev);
+    if (q == hipSuccess) {
+      if (*(volatile int32_t *)ctx->sort_flag_host) ctx->sort_lsd_left = kSortLsdCalls;
+      ctx->sort_pending = false;
+    } else if (q != hipErrorNotReady) {
+      (void)hipGetLastError();
+      ctx->sort_failed = true;
+      return;
+    }
+  }
+  if (ctx->sort_lsd_left > 0) {
+    r.sort_lsd = true;
+    --ctx->sort_lsd_left;
+    return;
+  }
+  if (!ctx->sort_pending) {
+    *(volatile int32_t *)ctx->sort_flag_host = 0;
+    r.sort_big = ctx->sort_flag_dev;
+    r.sort_ev = ctx->sort_ev;
+    r.sort_pending = &ctx->sort_pending;
+  }
+}
+
 // Graph construction into (col, dist2, p); sigma_g into res.  p == NULL
 // stops after the merge: the sweeps then derive sigma_g and the weights.
 fgbd_status run_slg(const Run &r, const int32_t *xyz, int32_t *col, int32_t *dist2, float *p, fgbd_result *res,
@@ -532,13 +590,19 @@ fgbd_status fgbd_create(fgbd_ctx *out, int32_t hip_device) {
 
 fgbd_status fgbd_destroy(fgbd_ctx ctx) {
   if (!ctx) return ok();
-  if (ctx->own || !ctx->pool.empty() || !ctx->pending.empty() || ctx->hint_host || ctx->hint_ev) {
+  if (ctx->own || !ctx->pool.empty() || !ctx->pending.empty() || ctx->hint_host || ctx->hint_ev ||
+      ctx->sort_flag_host || ctx->sort_ev) {
     DeviceGuard g(ctx->device);
     if (ctx->hint_ev) {
       (void)hipEventSynchronize(ctx->hint_ev);
       (void)hipEventDestroy(ctx->hint_ev);
     }
     if (ctx->hint_host) (void)hipHostFree(ctx->hint_host);
+    if (ctx->sort_ev) {
+      (void)hipEventSynchronize(ctx->sort_ev);
+      (void)hipEventDestroy(ctx->sort_ev);
+    }
+    if (ctx->sort_flag_host) (void)hipHostFree(ctx->sort_flag_host);
     if (ctx->own) {
       (void)hipDeviceSynchronize();
       (void)hipFree(ctx->own);
@@ -593,7 +657,8 @@ fgbd_status fgbd_build_slg(fgbd_ctx ctx, const int32_t *xyz, int64_t n, const fg
   char *ws = nullptr;
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
-  const Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  sort_policy(ctx, s, r);
   HIP_TRY(launch_setup(r, nullptr, n, res, 1), "setup launch");
   if (n == 0) return ok();
   if ((st = run_slg(r, xyz, g->col, g->dist2, g->p, res)) != FGBD_OK) return st;
@@ -749,6 +814,7 @@ fgbd_status fgbd_denoise(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in, 
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
   Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  sort_policy(ctx, s, r);
   if (n == 0) {
     HIP_TRY(launch_setup(r, nullptr, n, res, 2), "setup launch");
     return ok();
@@ -792,6 +858,7 @@ fgbd_status fgbd_denoise_batched(fgbd_ctx ctx, const int32_t *xyz, const float *
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
   Run r = make_run(ctx, pl, ws, *params, -1, s, &ep);
+  sort_policy(ctx, s, r);
   HIP_TRY(launch_setup(r, offsets, 0, res, n_total == 0 ? 2 : 1), "setup launch");
   if (n_total == 0) return ok();
   r.sweep_launches = adaptive_sweep_launches(ctx, s, &r.hint);
@@ -815,6 +882,7 @@ fgbd_status fgbd_denoise_batched_fixed_q(fgbd_ctx ctx, const int32_t *xyz, const
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
   Run r = make_run(ctx, pl, ws, *params, -1, s, &ep);
+  sort_policy(ctx, s, r);
   HIP_TRY(launch_setup(r, offsets, 0, res, n_total == 0 ? 2 : 1), "setup launch");
   if (n_total == 0) return ok();
   // SLG, then q_fixed sweeps whose first derives sigma_g and the weights;
@@ -843,6 +911,7 @@ fgbd_status fgbd_smooth_geometry(fgbd_ctx ctx, const int32_t *xyz, int64_t n, co
   if ((st = get_workspace(ctx, pl.total, &ws)) != FGBD_OK) return st;
   EventProf ep(ctx, s);
   Run r = make_run(ctx, pl, ws, *params, n, s, &ep);
+  sort_policy(ctx, s, r);
   HIP_TRY(launch_setup(r, nullptr, n, res, n == 0 ? 2 : 1), "setup launch");
   if (n == 0) return ok();
   // the coordinates become the signal in the output buffer; with a fixed q

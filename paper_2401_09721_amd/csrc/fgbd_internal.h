@@ -370,6 +370,10 @@ constexpr int kSortPasses = 4;                        // 8-bit digits of 32-bit 
 constexpr int kMsdBits = 10;
 constexpr int kMsdBins = 1 << kMsdBits;
 constexpr int kLocalWin = kSortTile;  // sorted positions per local-sort window
+// a range this large sorted by one block makes later eager calls on the
+// context sort by LSD passes for kSortLsdCalls calls
+constexpr int kBigRange = 32768;
+constexpr int kSortLsdCalls = 32;
 
 constexpr int kBlock = 256;
 constexpr int kMaxGrid = 1024;  // default grid cap of the grid-stride kernels
@@ -481,6 +485,15 @@ struct Run {
   // index-ordered patches)
   bool relabel_ok = false;
   int32_t *hint = nullptr;  // host-mapped: the finalising launch stores each cloud's sweep count here
+  // Sort route for codes of at most 32 bits: the top-digit pass and local
+  // sorts unless sort_lsd.  sort_big (host-mapped, NULL: not watched): the
+  // local sort sets it when a block had to sort a range of more than
+  // kBigRange items alone; sort_ev is recorded after the sort, and
+  // *sort_pending marks the read-back outstanding.
+  bool sort_lsd = false;
+  int32_t *sort_big = nullptr;
+  hipEvent_t sort_ev = nullptr;
+  bool *sort_pending = nullptr;
   // bound of each wait between sweeps in the in-launch sweep loop, in
   // microseconds (negative: half a second)
   int64_t wait_us = -1;

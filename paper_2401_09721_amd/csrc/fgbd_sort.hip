@@ -865,6 +865,7 @@ struct LocalArgs {
   int64_t stride;
   const int32_t *win;  // [L][nwin]: each window's first bucket start (0x7fffffff: none)
   int32_t nwin;
+  int32_t *big;        // host-mapped flag set for a range of more than kBigRange items (NULL: none)
 };
 
 // Stable rank of an 8-bit digit among the wave's equal digits (the
@@ -1068,6 +1069,7 @@ __global__ __launch_bounds__(kLocalThreads) __attribute__((amdgpu_waves_per_eu(4
   // kSlowItems * kLocalThreads items per round, through the two item buffers
   // (its own range of each).  An odd number of passes (a first pass of digit
   // 0, a plain stable copy, when needed) ends in dst, in the final form.
+  if (a.big && R > kBigRange && t == 0) *a.big = 1;  // (only ever set to 1)
   const int c_first = cloud_at(s_starts, B, lo);
   const uint64_t base64 = (uint64_t)base;
   // the widest key of the range, for the pass count
@@ -1204,7 +1206,7 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
   a.su = r.setup;
   const int ntiles = r.sa.n_fixed >= 0 ? (r.sa.n_fixed + kSortTile - 1) / kSortTile : r.pl.ntiles_cap;
   const dim3 grid(ntiles > 0 ? ntiles : 1, r.dt.num_dirs);
-  if (r.dt.passes == kSortPasses) {
+  if (r.dt.passes == kSortPasses && !r.sort_lsd) {
     // codes of at most 32 bits: the MSD pass, then the windows' local sorts
     const int64_t npos = r.sa.n_fixed >= 0 ? r.sa.n_fixed : r.pl.n_cap;
     a.nwin = (int)((npos + kLocalWin - 1) / kLocalWin);
@@ -1230,10 +1232,17 @@ hipError_t launch_sort(const Run &r, const int32_t *xyz, fgbd_result *res, const
     la.stride = r.pl.stride;
     la.win = r.b.win;
     la.nwin = a.nwin;
+    la.big = r.sort_big;
     FGBD_PRE(r.pf, kLocalSort);
     k_local_sort<<<dim3(a.nwin, r.dt.num_dirs), kLocalThreads, 0, r.stream>>>(la, r.b.items_a, r.b.items_b,
                                                                               r.b.rank);
     FGBD_POST(r.pf);
+    if (r.sort_big && r.sort_ev) {
+      if (hipEventRecord(r.sort_ev, r.stream) == hipSuccess)
+        *r.sort_pending = true;
+      else
+        (void)hipGetLastError();
+    }
     *sorted_out = r.b.items_b;
     return hipGetLastError();
   }

@@ -96,6 +96,35 @@ def test_slg_plane_normal_to_a_scan_axis():
     check_graph(g, fgbd.default_params(bits=10, num_dirs=8, window=4, k=8))
 
 
+def test_sort_route_after_a_large_plane():
+    # 90,000 points on the plane z = 500: in the orders whose high axis is z
+    # they form ranges far larger than a block sorts quickly alone.  The first
+    # call flags that; once its read-back has completed, calls on the same
+    # context sort by LSD passes (no local-sort launch) and give the same graph.
+    xs, ys = np.meshgrid(np.arange(200, 500), np.arange(100, 400), indexing="ij")
+    plane = np.stack([xs.ravel(), ys.ravel(), np.full(xs.size, 500)], axis=1)
+    rng = np.random.default_rng(12)
+    g = np.concatenate([plane, rng.integers(0, 1024, size=(5000, 3))]).astype(np.int32)
+    prm = fgbd.default_params(bits=10, num_dirs=8, window=4, k=8)
+    ctx = fgbd.Context("cuda")
+    x = dev(g, torch.int32)
+    ctx.profile(True)
+    first = fgbd.build_slg(x, prm, ctx=ctx)
+    torch.cuda.synchronize()
+    p1 = ctx.profile_read()
+    second = fgbd.build_slg(x, prm, ctx=ctx)
+    torch.cuda.synchronize()
+    p2 = ctx.profile_read()
+    ctx.profile(False)
+    assert p1["local_sort"][1] == 1 and p1["radix_downsweep"][1] == 1
+    assert p2["local_sort"][1] == 0 and p2["radix_downsweep"][1] == 4
+    ocol, od2 = O.slg_graph(g, prm.bits, prm.num_dirs, prm.window, prm.k)
+    for gr in (first, second):
+        assert np.array_equal(gr.col.cpu().numpy(), ocol)
+        assert np.array_equal(gr.dist2.cpu().numpy(), od2)
+    ctx.close()
+
+
 def test_fixed_sigma_g():
     c = synth.tiny_cloud(0)
     check_graph(c.xyz, fgbd.default_params(bits=8, sigma_g=2.5))
