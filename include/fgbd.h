@@ -42,6 +42,13 @@
  *     identical outputs on the same device (no floating-point atomics).
  *   - Calls on one context must not overlap in time (they share the
  *     workspace); use one context per concurrent stream.
+ *   - A context adapts its launch schedule to what its recent eager calls
+ *     found, read back without waiting: the number of sweep launches, and
+ *     the radix sort's route (a call whose points crowd into few top code
+ *     digits, such as a large plane normal to a scan axis, makes the next
+ *     calls sort by LSD passes for a while).  Either route gives the same
+ *     result; only the time differs.  Calls under stream capture keep the
+ *     default schedule.
  */
 #ifndef FGBD_H_
 #define FGBD_H_

@@ -624,20 +624,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_downsweep(SortArgs a, con
 // pass on the kMsdBits most significant bits of each direction's code
 // (upsweep, scan and downsweep as above, with 2^kMsdBits digits, the codes
 // made from the coordinates) splits every cloud's points, stably, into
-// buckets of equal top digit.  k_local_sort then gives each window of
-// kLocalWin sorted positions of a direction one block, which sorts the
-// buckets that start in its window: their union [lo, hi) is bounded by the
-// first digit change (or cloud start) at or after each end of the window,
-// and its items are sorted, stably, by their codes less the smallest top
+// buckets of equal top digit; the downsweep also records, from its counts,
+// the first bucket start inside every window of kLocalWin sorted positions.
+// k_local_sort then gives each window of a direction one block, which sorts
+// the buckets that start in its window (the range from its recorded start
+// to the next window's), stably, by their codes less the smallest top
 // digit's base, with 8-bit LSD passes in LDS (three for the usual ranges).
 // Buckets are ordered by their top digits already, so sorting a range by the
 // whole code sorts each bucket and keeps the buckets in place; ties keep the
 // MSD pass's order, which is the input's.  The final pass writes the sorted
 // items in their final form and rank, as the last LSD pass does.  A range of
 // more than kLocalCap items, of two clouds, or of keys wider than 26 bits is
-// sorted by its block alone through the two item buffers (slower; inputs
-// whose points crowd into few top digits, such as a plane normal to a scan
-// axis, take it).
+// sorted by its block alone through the two item buffers: correct for any
+// input, slow for a very large range (points crowded into few top digits,
+// such as a plane normal to a scan axis), which the block then reports
+// through a host-mapped flag so that the caller's context can choose the LSD
+// passes for its next calls.
 
 __device__ __forceinline__ int code_width(const DirTable &dt, int d) {
   const DirInfo di = dt.d[d];
