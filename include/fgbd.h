@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define FGBD_ABI_VERSION 8
+#define FGBD_ABI_VERSION 9
 
 /* Largest number of clouds in one fgbd_denoise_batched call. */
 #define FGBD_MAX_BATCH 64
@@ -338,12 +338,19 @@ fgbd_status fgbd_autotune(fgbd_ctx ctx, const int32_t *xyz, const float *rgb_in,
  * g->p is not used).  coef = e_q reproduces fgbd_filter with q_fixed = q.
  *   g: col and dist2 of a graph from fgbd_build_slg;  x, out: float32 [n][3]
  *   (must not overlap);  coef: device float32 [ncoef], 1 <= ncoef <= 32;
- *   sigma_g: device double (one value, > 0);  saved: output float32
- *   [2 ncoef - 1][n][3] the backward call needs: the iterates x_0..x_{ncoef-1},
- *   then u_1..u_{ncoef-1} with u_m = 2 (dT/dsigma_g) x_{m-1} (formed from the
- *   neighbour values the sweep gathers). */
+ *   sigma_g: device double (one value, > 0);  saved: output float32 buffer of
+ *   fgbd_poly_saved_floats(n, k, ncoef) floats that the backward call needs:
+ *   [2 ncoef - 1][n][3], the iterates x_0..x_{ncoef-1}, then u_1..u_{ncoef-1}
+ *   with u_m = 2 (dT/dsigma_g) x_{m-1} (formed from the neighbour values the
+ *   sweep gathers); for ncoef >= 2 then, from the next multiple of 64 floats,
+ *   the weights p [n][k] and T's diagonal [n] the forward used. */
 fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, const float *coef, int32_t ncoef,
                              const double *sigma_g, float *out, float *saved, void *stream);
+
+/* Floats of fgbd_poly_filter's saved buffer for n points, k neighbours per
+ * row and ncoef coefficients; -1 for n < 0, k < 1 or ncoef outside 1..32.
+ * Host only. */
+int64_t fgbd_poly_saved_floats(int64_t n, int32_t k, int32_t ncoef);
 
 /* Transpose of a graph's directed edges, the structure the adjoint of eq. 5
  * pulls along (T^T).  For every point j, the ids e = i * k + slot of the
@@ -373,8 +380,8 @@ fgbd_status fgbd_graph_transpose(fgbd_ctx ctx, const fgbd_graph *g, const fgbd_t
  *   grad_sigma_g = sum_{m>=1} <z_m, (dT/dsigma_g) x_{m-1}>.
  *   t: the graph's transpose from fgbd_graph_transpose, or NULL to build one
  *   in the workspace for this call;
- *   saved: the iterates written by fgbd_poly_filter with the same g, coef,
- *   ncoef and sigma_g;  grad_out, grad_x: float32 [n][3] (must not overlap);
+ *   saved: the buffer written by fgbd_poly_filter with the same g, coef,
+ *   ncoef and sigma_g (its weights are used, not recomputed);  grad_out, grad_x: float32 [n][3] (must not overlap);
  *   grad_coef: optional device float32 [ncoef];  grad_sigma_g: optional device
  *   double.  Scalar gradients are reduced in a fixed order (deterministic). */
 fgbd_status fgbd_poly_filter_backward(fgbd_ctx ctx, const fgbd_graph *g, const fgbd_transpose *t, const float *saved,

@@ -1057,6 +1057,11 @@ static fgbd_status check_poly(fgbd_ctx ctx, const fgbd_graph *g, int32_t ncoef, 
   return FGBD_OK;
 }
 
+int64_t fgbd_poly_saved_floats(int64_t n, int32_t k, int32_t ncoef) {
+  if (n < 0 || k < 1 || ncoef < 1 || ncoef > kMaxPoly) return -1;
+  return (int64_t)poly_saved_floats(n, k, ncoef);
+}
+
 fgbd_status fgbd_poly_filter(fgbd_ctx ctx, const fgbd_graph *g, const float *x, const float *coef, int32_t ncoef,
                              const double *sigma_g, float *out, float *saved, void *stream) {
   fgbd_status st = check_poly(ctx, g, ncoef, sigma_g);

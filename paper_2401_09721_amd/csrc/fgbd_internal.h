@@ -572,6 +572,8 @@ constexpr int kMaxPoly = 32;
 // of each of their per-block partial-sum rows
 constexpr int kPolyGrid = 1024;
 size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks);
+// floats of the saved buffer of a polynomial filter call
+size_t poly_saved_floats(int64_t n, int k, int ncoef);
 // Float coordinates onto the 2^bits grid (keys: 6 words of scratch) and
 // colours to uint8 (fgbd_io.hip).
 hipError_t launch_quantize(const float *xyz, int64_t n, int32_t bits, int32_t *out, double *frame, uint32_t *keys,

@@ -36,9 +36,10 @@ namespace {
 // With dp given (the forward call), also the per-slot derivative coefficients
 //   dp_ik = p_ik (a_ik - sum_k' p_ik' a_ik'),  a_ik = 2 (d2_ik - d2_i0) / sigma_g^3
 // (FP64, rounded to float; 0 for an empty slot and for a row without edges),
-// so that dT/dsigma_g x = (1/2) sum_k dp_ik x[col_ik].  With diag given (the
-// backward call), also T's diagonal per point, so the backward steps read
-// 4 bytes per point instead of the first slot of each neighbour row.
+// so that dT/dsigma_g x = (1/2) sum_k dp_ik x[col_ik].  With diag given, also
+// T's diagonal per point (the forward call stores it with p in saved, so the
+// backward steps read 4 bytes per point instead of the first slot of each
+// neighbour row).
 template <int KT>
 __global__ __launch_bounds__(kBlock) void k_poly_weights(int32_t n, int32_t k_rt, const int32_t *__restrict__ col,
                                                          const int32_t *__restrict__ dist2,
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_poly_ptrans(int32_t n, const int32_t
 // One backward step m (z_m in, z_{m-1} out) per point j:
 //   z_{m-1}[j] = c_{m-1} g[j] + T_jj z_m[j] + sum over edges e = (i -> j) of p_T z_m[i]
 // (T_jj = 1/2 for a point with edges, 1 without, read from diag, which the
-// backward's weights launch writes), with the sigma_g term
+// forward's weights launch stored in saved), with the sigma_g term
 // <z_m[j], u_m[j]> / 2 from the saved u_m and the coefficient product
 // <g[j], x_{m-1}[j]> (and <g[j], x_m[j]> at the last step, where
 // z_m = c_m g).  Only the adjoint is gathered.
@@ -510,9 +511,7 @@ size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks) {
   const size_t N = (size_t)(n > 0 ? n : 1);
   size_t b = 0;
   auto take = [&](size_t bytes) { b += (bytes + 255) & ~(size_t)255; };
-  take(N * k * 4);                     // p
   take(N * k * 4);                     // dp (forward) or p in the transpose's order (backward)
-  take(N * 4);                         // T's diagonal (backward)
   take((N + 1) * 4);                   // offsets (when no transpose is given)
   take(N * k * 4);                     // transposed edge ids (same)
   take(2 * N * 3 * 4);                 // z ping-pong
@@ -523,7 +522,7 @@ size_t poly_workspace(int64_t n, int k, int ncoef, int nblocks) {
 }
 
 struct PolyBufs {
-  float *p, *aux, *diag;
+  float *aux;
   int32_t *off, *tsrc;
   float *z[2];
   double *coef_part, *sig_part;
@@ -539,9 +538,7 @@ static PolyBufs poly_carve(char *ws, int64_t n, int k, int ncoef, int nblocks) {
     o += (bytes + 255) & ~(size_t)255;
     return ptr;
   };
-  pb.p = (float *)take(N * k * 4);
   pb.aux = (float *)take(N * k * 4);
-  pb.diag = (float *)take(N * 4);
   pb.off = (int32_t *)take((N + 1) * 4);
   pb.tsrc = (int32_t *)take(N * k * 4);
   pb.z[0] = (float *)take(N * 3 * 4);
@@ -576,6 +573,19 @@ hipError_t launch_transpose(int64_t n, int k, const int32_t *col, int32_t *off, 
   return hipGetLastError();
 }
 
+// saved: the 2 ncoef - 1 arrays [n][3] (iterates, then u_m), and for ncoef >= 2
+// the forward's weights p [n][k] (from a 64-float boundary, so rows stay
+// 16-byte aligned) and T's diagonal [n], which the backward reads instead of
+// recomputing them.
+static size_t poly_saved_p_offset(int64_t n, int ncoef) {
+  const size_t iter = (size_t)(2 * ncoef - 1) * 3 * (size_t)n;
+  return (iter + 63) / 64 * 64;
+}
+size_t poly_saved_floats(int64_t n, int k, int ncoef) {
+  const size_t iter = (size_t)(2 * ncoef - 1) * 3 * (size_t)n;
+  return ncoef >= 2 ? poly_saved_p_offset(n, ncoef) + (size_t)n * k + (size_t)n : iter;
+}
+
 hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32_t *dist2, const float *x,
                                const float *coef, int ncoef, const double *sigma_g, float *out, float *saved,
                                char *ws, hipStream_t s) {
@@ -583,15 +593,17 @@ hipError_t launch_poly_forward(int64_t n, int k, const int32_t *col, const int32
   const int G = grid_for(n);
   k_poly_first<<<grid_for(3 * n), kBlock, 0, s>>>((int32_t)n, ncoef, x, coef, saved, out);
   if (ncoef == 1) return hipGetLastError();
+  float *p = saved + poly_saved_p_offset(n, ncoef);
+  float *diag = p + (size_t)n * k;
   if (k == 8)
-    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux, nullptr);
+    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, p, pb.aux, diag);
   else
-    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, pb.aux, nullptr);
+    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, p, pb.aux, diag);
   for (int kk = 1; kk < ncoef; ++kk) {
     if (k == 8)
-      k_poly_step<8><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, pb.aux, coef, saved, out);
+      k_poly_step<8><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, p, pb.aux, coef, saved, out);
     else
-      k_poly_step<0><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, pb.p, pb.aux, coef, saved, out);
+      k_poly_step<0><<<G, kBlock, 0, s>>>((int32_t)n, k, kk, ncoef, col, p, pb.aux, coef, saved, out);
   }
   return hipGetLastError();
 }
@@ -614,21 +626,20 @@ hipError_t launch_poly_backward(int64_t n, int k, const int32_t *col, const int3
     t_off = pb.off;
     t_edge = pb.tsrc;
   }
-  if (k == 8)
-    k_poly_weights<8><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr, pb.diag);
-  else
-    k_poly_weights<0><<<G, kBlock, 0, s>>>((int32_t)n, k, col, dist2, sigma_g, pb.p, nullptr, pb.diag);
-  k_poly_ptrans<<<grid_for(n * k), kBlock, 0, s>>>((int32_t)n, t_off, t_edge, pb.p, pb.aux);
+  // the forward's weights and T's diagonal, from saved
+  const float *p = saved + poly_saved_p_offset(n, ncoef);
+  const float *diag = p + (size_t)n * k;
+  k_poly_ptrans<<<grid_for(n * k), kBlock, 0, s>>>((int32_t)n, t_off, t_edge, p, pb.aux);
   // reverse Horner; coefficient products ride along
   const float *zin = nullptr;
   for (int m = ncoef - 1; m >= 1; --m) {
     float *zout = (m == 1) ? grad_x : pb.z[m & 1];
     if (k == 8)
-      k_poly_back<8><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, pb.diag, t_off, t_edge, pb.aux,
+      k_poly_back<8><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, diag, t_off, t_edge, pb.aux,
                                           coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
                                           pb.coef_part);
     else
-      k_poly_back<0><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, pb.diag, t_off, t_edge, pb.aux,
+      k_poly_back<0><<<G, kBlock, 0, s>>>((int32_t)n, k, m, m == ncoef - 1, G, ncoef, diag, t_off, t_edge, pb.aux,
                                           coef, grad_out, saved, zin, zout, pb.sig_part + (size_t)m * G,
                                           pb.coef_part);
     zin = zout;

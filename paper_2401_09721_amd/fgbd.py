@@ -30,7 +30,7 @@ FGBD_ST_SWEEP_STALL = 8
 FGBD_ST_RELABELED = 16
 FGBD_ST_DIST_CLAMPED = 32
 NUM_KERNELS = 11
-ABI_VERSION = 8
+ABI_VERSION = 9
 MAX_BATCH = 64
 KERNELS = ("radix_upsweep", "radix_scan", "radix_downsweep", "merge", "weights", "noise", "noise_solve", "sweep",
            "finalize", "relabel", "local_sort")
@@ -153,6 +153,7 @@ _SIGNATURES = {
     "fgbd_poly_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "fgbd_poly_saved_floats": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
     "fgbd_graph_transpose": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.POINTER(Transpose),
                                             ctypes.c_void_p]),
     "fgbd_poly_filter_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Graph), ctypes.POINTER(Transpose),
@@ -714,11 +715,20 @@ def round_u8(rgb, ctx: Optional[Context] = None, out=None, stream=None):
     return out
 
 
+def saved_floats(n: int, k: int, ncoef: int) -> int:
+    """Length of poly_filter's saved buffer (fgbd_poly_saved_floats)."""
+    v = int(lib().fgbd_poly_saved_floats(int(n), int(k), int(ncoef)))
+    if v < 0:
+        raise ValueError(f"no saved buffer for n={n}, k={k}, ncoef={ncoef}")
+    return v
+
+
 def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None, stream=None):
     """out = sum_k coef[k] T^k x with eq. 4 weights at the device bandwidth
-    sigma_g (float64 scalar tensor).  Returns (out, saved): saved holds the
-    2 ncoef - 1 arrays [n][3] the backward call needs (the iterates, then the
-    bandwidth derivatives u_m)."""
+    sigma_g (float64 scalar tensor).  Returns (out, saved): saved is a flat
+    float32 buffer of what the backward call needs (the iterates and the
+    bandwidth derivatives u_m, [2 ncoef - 1][n][3], then the forward's weights
+    and T's diagonal)."""
     torch = _torch()
     ctx = ctx or default_context(x.device)
     _need(x, torch.float32, (3,), "x", ctx.device)
@@ -732,7 +742,7 @@ def poly_filter(graph: SLGraph, x, coef, sigma_g, ctx: Optional[Context] = None,
     coef = coef.contiguous()
     sigma_g = sigma_g.contiguous()
     out = torch.empty_like(x)
-    saved = torch.empty((2 * nc - 1, n, 3), dtype=torch.float32, device=ctx.device)
+    saved = torch.empty(saved_floats(n, graph.k, nc), dtype=torch.float32, device=ctx.device)
     gs = graph.c_struct()
     _check(lib().fgbd_poly_filter(ctx.handle, ctypes.byref(gs), _ptr(x), _ptr(coef), nc, _ptr(sigma_g), _ptr(out),
                                   _ptr(saved), _stream(ctx, stream)))
@@ -772,7 +782,7 @@ def poly_filter_backward(graph: SLGraph, saved, coef, sigma_g, grad_out, ctx: Op
     if sigma_g.dtype != torch.float64 or sigma_g.device != ctx.device or sigma_g.numel() != 1:
         raise ValueError("sigma_g must be a float64 device scalar")
     nc = int(coef.numel())
-    _need_out(saved, torch.float32, (2 * nc - 1, graph.n, 3), "saved", ctx.device)
+    _need_out(saved, torch.float32, (saved_floats(graph.n, graph.k, nc),), "saved", ctx.device)
     ts = None
     if transpose is True:
         transpose = graph.transpose(ctx=ctx, stream=stream)

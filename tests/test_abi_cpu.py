@@ -42,7 +42,7 @@ def test_status_constants_match_header():
 
 
 def test_version_and_defaults():
-    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 8
+    assert fgbd.lib().fgbd_abi_version() == fgbd.ABI_VERSION == 9
     p = fgbd.default_params()
     assert (p.bits, p.num_dirs, p.window, p.k, p.patch, p.q_max) == (10, 8, 4, 8, 0, 32)
     assert p.fslr_kappa == 2.0 and p.sigma_g == 0.0
@@ -330,7 +330,7 @@ def test_binding_rejects_row_mismatch(host_ctx):
     sg = torch.ones((), dtype=torch.float64)
     with pytest.raises(ValueError, match="rows"):
         fgbd.poly_filter(g, torch.zeros((9, 3)), coef, sg, ctx=host_ctx)
-    saved = torch.zeros((15, 10, 3))
+    saved = torch.zeros(fgbd.saved_floats(10, 8, 8))
     with pytest.raises(ValueError, match="rows"):
         fgbd.poly_filter_backward(g, saved, coef, sg, torch.zeros((12, 3)), ctx=host_ctx)
 
@@ -342,14 +342,19 @@ def test_binding_rejects_bad_graph_and_saved(host_ctx):
         fgbd.estimate_noise(_graph(10, p_shape=(10, 7)), torch.zeros((10, 3)), ctx=host_ctx)
     g = _graph(10)
     coef, sg = torch.ones(8), torch.ones((), dtype=torch.float64)
-    # saved holds 2 ncoef - 1 arrays: the iterates, then the bandwidth derivatives
-    for bad in (torch.zeros((8, 10, 3)), torch.zeros((14, 10, 3)), torch.zeros((15, 9, 3)),
-                torch.zeros((15, 10, 3), dtype=torch.float64)):
+    # saved: the 2 ncoef - 1 arrays [n][3] (iterates, then the bandwidth
+    # derivatives), then from a 64-float boundary the weights [n][k] and T's
+    # diagonal [n]
+    m = fgbd.saved_floats(10, 8, 8)
+    assert m == (15 * 30 + 63) // 64 * 64 + 10 * 8 + 10
+    assert fgbd.saved_floats(10, 8, 1) == 30
+    for bad in (torch.zeros(m - 1), torch.zeros(m + 1), torch.zeros((15, 10, 3)), torch.zeros(m, dtype=torch.float64)):
         with pytest.raises(ValueError, match="saved"):
             fgbd.poly_filter_backward(g, bad, coef, sg, torch.zeros((10, 3)), ctx=host_ctx)
     with pytest.raises(ValueError, match="coef"):
-        fgbd.poly_filter_backward(g, torch.zeros((15, 10, 3)), coef.double(), sg, torch.zeros((10, 3)),
-                                  ctx=host_ctx)
+        fgbd.poly_filter_backward(g, torch.zeros(m), coef.double(), sg, torch.zeros((10, 3)), ctx=host_ctx)
+    with pytest.raises(ValueError, match="saved buffer"):
+        fgbd.saved_floats(10, 8, 33)
     with pytest.raises(ValueError, match="spread"):
         fgbd.filter(g, torch.zeros((10, 3)), noise=fgbd.new_result("cpu"), spread=torch.zeros(9, dtype=torch.float64),
                     ctx=host_ctx)
