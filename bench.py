@@ -151,7 +151,11 @@ def make_inputs(args, synth) -> dict:
     if want_stream:
         jobs += [("frame", dict(seed=stream_seed, frame=0, target=args.points, sigma=20.0))]
     workers = max(1, min(16, os.cpu_count() or 1, len(jobs) + args.stream_frames))
-    with mp.get_context("fork").Pool(workers) as pool:
+    # The pool is closed and joined rather than terminated: a worker that ends
+    # on SIGTERM runs whatever signal handler a preloaded profiler installed,
+    # and one that deadlocks there leaves this process waiting forever.
+    pool = mp.get_context("fork").Pool(workers)
+    try:
         clouds = pool.map(_gen, jobs, chunksize=1)
         out = {"frame": clouds[0]}
         k = 1
@@ -167,6 +171,9 @@ def make_inputs(args, synth) -> dict:
                                                   scale=scale)) for f in range(1, args.stream_frames)],
                             chunksize=1)
             out["stream"] = [first] + [c for c, _ in rest]
+    finally:
+        pool.close()
+        pool.join()
     return out
 
 
@@ -619,8 +626,12 @@ def cpu_baseline(cloud, prm: dict) -> dict:
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     procs = max(1, min(16, cores))
     w0 = time.perf_counter()
-    with mp.get_context("fork").Pool(procs) as pool:
+    pool = mp.get_context("fork").Pool(procs)  # closed, not terminated, as in make_inputs
+    try:
         runs = pool.map(_oracle_stages, range(procs), chunksize=1)
+    finally:
+        pool.close()
+        pool.join()
     wall_all = time.perf_counter() - w0
     _CPU_JOB = None
     stages = {k: one[k] for k in ("GC", "NE", "LF")}
