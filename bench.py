@@ -55,6 +55,21 @@ def algorithmic_bytes(kind: str, n: int, L: int, K: int, P: int) -> float:
     return 0.0
 
 
+def sweep_kind_bytes(n: int, sweeps: int, L: int, K: int, P: int, tail_finalises: bool) -> float:
+    """Bytes the sweep launches of one fused-path call move for a cloud of n
+    points whose selection computed `sweeps` iterates.  x_1 comes from the
+    noise launch (its bytes are the noise kind's); the first sweep launch adds
+    x_1's flags and sums and, with K = 8, computes x_2 in the same launch;
+    every later iterate is one plain sweep (a launch of its own or a pass of
+    the tail's loop); launches that find the selection stopped move nothing;
+    the tail launch finalises when no separate finalize launch ran."""
+    merged = K == 8 and sweeps >= 2
+    first = algorithmic_bytes("sweep_first_merged" if merged else "sweep_first_fused", n, L, K, P)
+    later = max(sweeps - (2 if merged else 1), 0)
+    fin = algorithmic_bytes("finalize", n, L, K, P) if tail_finalises else 0.0
+    return first + later * algorithmic_bytes("sweep", n, L, K, P) + fin
+
+
 # Source files each kernel kind is compiled from: a traffic figure measured
 # with hardware counters is only reported while these are unchanged.
 KIND_SOURCES = {
@@ -222,7 +237,7 @@ def bench_batched(clouds, prm, dev, args, fgbd, torch) -> dict:
         P = prm.patch if prm.patch > 0 else prm.k
         # Per-kernel HIP events over the same calls.  A sweep launch moves the
         # sweep's bytes for each cloud whose selection is still running, so
-        # the sweep's bytes per batch are the sum over clouds of sweeps x bytes.
+        # the sweep kind's bytes per batch are the sum over the clouds.
         ctx.profile(True)
         ctx.profile_read()
         for _ in range(steps):
@@ -231,7 +246,8 @@ def bench_batched(clouds, prm, dev, args, fgbd, torch) -> dict:
         prof = ctx.profile_read()
         ctx.profile(False)
         rs = fgbd.read_results(res)
-        sweep_bytes = sum(algorithmic_bytes("sweep", n_s, prm.num_dirs, prm.k, P) * r["sweeps"]
+        tail_fin = prof.get("finalize", (0.0, 0))[1] == 0
+        sweep_bytes = sum(sweep_kind_bytes(n_s, r["sweeps"], prm.num_dirs, prm.k, P, tail_fin)
                           for n_s, r in zip(sizes, rs))
         kernels = {}
         for kind, (kms, launches) in prof.items():
@@ -776,13 +792,11 @@ def main() -> int:
         line["kernels"] = kernels
         line["profiled_ms_per_step"] = sum(v["ms_per_step"] for v in kernels.values())
         # Bytes each kind moves per step: its algorithmic bytes per launch for
-        # every launch that computes; of the sweep launches only r["sweeps"]
-        # compute (the later ones return after reading the stopped selection).
+        # every launch that computes (the sweep kind: sweep_kind_bytes).
         def step_bytes(kind):
-            b = algorithmic_bytes(kind, n, prm.num_dirs, prm.k, P)
             if kind == "sweep":
-                return b * r["sweeps"]
-            return b * kernels[kind]["launches_per_step"]
+                return sweep_kind_bytes(n, r["sweeps"], prm.num_dirs, prm.k, P, "finalize" not in kernels)
+            return algorithmic_bytes(kind, n, prm.num_dirs, prm.k, P) * kernels[kind]["launches_per_step"]
 
         dom = max((k for k in kernels if algorithmic_bytes(k, n, prm.num_dirs, prm.k, P) > 0),
                   key=lambda k: kernels[k]["ms_per_step"])

@@ -143,78 +143,83 @@ __device__ __forceinline__ void advance(SweepCtrl &c, const double (&t)[kSweepPa
 // Selection state at the start of a launch: the stored state advanced by the
 // previous sweep's integer sums (identical in every block).  A state stored
 // by the fused first launch (first_pending) is first advanced by x_1's sums
-// from sums_first, then, unless that ended the selection, by x_2's.  Called
-// by every thread of the block; wave 0 loads the slots (one per lane) and
-// reduces them with shuffles.
-__device__ __forceinline__ void reduce_sums(const unsigned long long *__restrict__ sums, double (&t)[kSweepParts],
-                                            unsigned long long *s_tot) {
-  if (threadIdx.x < kWave) {
-    unsigned long long u[kSweepParts];
-    const int sl = (int)threadIdx.x;
+// from sums_first, then, unless that ended the selection, by x_2's.  The
+// state and both sets of slots are loaded at once (the slots of x_1 are read
+// whether or not the state needs them), so the launch waits for one round
+// trip before its sweep.  Every lane of a wave loads one slot of each set and
+// the sums are reduced with shuffles, so every lane holds the totals.
+__device__ __forceinline__ void wave_reduce_both(const unsigned long long *__restrict__ sums_first,
+                                                 const unsigned long long *__restrict__ sums_prev,
+                                                 unsigned long long (&f)[kSweepParts],
+                                                 unsigned long long (&u)[kSweepParts]) {
+  const int sl = (int)lane_id();
 #pragma unroll
-    for (int j = 0; j < kSweepParts; ++j) u[j] = sl < kSweepSlots ? sums[sl * kSweepParts + j] : 0ull;
+  for (int j = 0; j < kSweepParts; ++j) {
+    f[j] = sl < kSweepSlots ? sums_first[sl * kSweepParts + j] : 0ull;
+    u[j] = sl < kSweepSlots ? sums_prev[sl * kSweepParts + j] : 0ull;
+  }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+  for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-      for (int j = 0; j < kSweepParts; ++j) u[j] += __shfl_xor(u[j], o, kWave);
-    }
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int j = 0; j < kSweepParts; ++j) s_tot[j] = u[j];
+    for (int j = 0; j < kSweepParts; ++j) {
+      f[j] += __shfl_xor(f[j], o, kWave);
+      u[j] += __shfl_xor(u[j], o, kWave);
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < kSweepParts; ++j) t[j] = j < 4 ? (double)s_tot[j] / kFix : (double)s_tot[j];
-  __syncthreads();  // s_tot may be written again by the next reduction
 }
-__device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
-                                           const unsigned long long *__restrict__ sums_prev,
-                                           const unsigned long long *__restrict__ sums_first, int n) {
-  __shared__ unsigned long long s_tot[kSweepParts];
-  c = *prev;
-  if (c.done) return;  // uniform: every thread read the same state
+__device__ __forceinline__ void sums_to_double(const unsigned long long *u, double (&t)[kSweepParts]) {
+#pragma unroll
+  for (int j = 0; j < kSweepParts; ++j) t[j] = j < 4 ? (double)u[j] / kFix : (double)u[j];
+}
+// Advance a loaded state by the reduced sums (see above).
+__device__ __forceinline__ void advance_loaded(SweepCtrl &c, const unsigned long long *f,
+                                               const unsigned long long *u, int n) {
+  if (c.done) return;
   double t[kSweepParts];
   if (c.first_pending) {  // x_1 sits in buffer 0, where the noise launch wrote it
-    reduce_sums(sums_first, t, s_tot);
+    sums_to_double(f, t);
     advance(c, t, n, 0);
     c.first_pending = 0;
     if (c.done) return;
   }
-  reduce_sums(sums_prev, t, s_tot);
+  sums_to_double(u, t);
   advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
 }
-
-// The same advance by one wave alone (no block barrier): every lane loads
-// one slot, the sums are reduced with shuffles so every lane holds them, and
-// every lane advances its own copy of the state.
-__device__ __forceinline__ void wave_reduce_sums(const unsigned long long *__restrict__ sums, double (&t)[kSweepParts]) {
-  unsigned long long u[kSweepParts];
-  const int sl = (int)lane_id();
+// Called by every thread of the block; wave 0 loads and reduces the slots.
+__device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
+                                           const unsigned long long *__restrict__ sums_prev,
+                                           const unsigned long long *__restrict__ sums_first, int n) {
+  __shared__ unsigned long long s_tot[2 * kSweepParts];
+  c = *prev;
+  if (threadIdx.x < kWave) {
+    unsigned long long f[kSweepParts], u[kSweepParts];
+    wave_reduce_both(sums_first, sums_prev, f, u);
+    if (threadIdx.x == 0) {
 #pragma unroll
-  for (int j = 0; j < kSweepParts; ++j) u[j] = sl < kSweepSlots ? sums[sl * kSweepParts + j] : 0ull;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-    for (int j = 0; j < kSweepParts; ++j) u[j] += __shfl_xor(u[j], o, kWave);
+      for (int j = 0; j < kSweepParts; ++j) {
+        s_tot[j] = f[j];
+        s_tot[kSweepParts + j] = u[j];
+      }
+    }
   }
+  __syncthreads();
+  unsigned long long f[kSweepParts], u[kSweepParts];
 #pragma unroll
-  for (int j = 0; j < kSweepParts; ++j) t[j] = j < 4 ? (double)u[j] / kFix : (double)u[j];
+  for (int j = 0; j < kSweepParts; ++j) {
+    f[j] = s_tot[j];
+    u[j] = s_tot[kSweepParts + j];
+  }
+  __syncthreads();  // s_tot is written again by the next call (the in-launch sweep loop)
+  advance_loaded(c, f, u, n);
 }
+// The same advance by one wave alone (no block barrier).
 __device__ __forceinline__ void wave_advance(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
                                              const unsigned long long *__restrict__ sums_prev,
                                              const unsigned long long *__restrict__ sums_first, int n) {
   c = *prev;
-  if (c.done) return;
-  double t[kSweepParts];
-  if (c.first_pending) {
-    wave_reduce_sums(sums_first, t);
-    advance(c, t, n, 0);
-    c.first_pending = 0;
-    if (c.done) return;
-  }
-  wave_reduce_sums(sums_prev, t);
-  advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
+  unsigned long long f[kSweepParts], u[kSweepParts];
+  wave_reduce_both(sums_first, sums_prev, f, u);
+  advance_loaded(c, f, u, n);
 }
 
 // Block-sum of per-thread integer sums, then one atomic per value per block
@@ -523,18 +528,33 @@ __device__ __forceinline__ void finalize_block(const SegBlock &sb, const SweepCt
                                                const uint32_t *__restrict__ rank0) {
   const int best = c.best_buf;
   const Share sh = seg_share(sb, kBlock);
-  for (int64_t base = sh.first; base < sh.end; base += sh.step) {
-    const int64_t i = base + threadIdx.x;
-    if (i >= sh.end) continue;
-    if (best == 3) {
+  if (best == 3) {
+    for (int64_t base = sh.first; base < sh.end; base += sh.step) {
+      const int64_t i = base + threadIdx.x;
+      if (i >= sh.end) continue;
       rgb_out[3 * i + 0] = rgb_in[3 * i + 0];
       rgb_out[3 * i + 1] = rgb_in[3 * i + 1];
       rgb_out[3 * i + 2] = rgb_in[3 * i + 2];
-    } else {
-      const float4 x = xbuf[(size_t)best * buf_stride + (rank0 ? (int64_t)rank0[i] : i)];
-      rgb_out[3 * i + 0] = x.x;
-      rgb_out[3 * i + 1] = x.y;
-      rgb_out[3 * i + 2] = x.z;
+    }
+  } else {
+    // four chunks per pass, all their loads in flight before any store
+    constexpr int U = 4;
+    const float4 *xs = xbuf + (size_t)best * buf_stride;
+    for (int64_t base = sh.first; base < sh.end; base += U * sh.step) {
+      float4 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = base + u * sh.step + threadIdx.x;
+        if (i < sh.end) x[u] = xs[rank0 ? (int64_t)rank0[i] : i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = base + u * sh.step + threadIdx.x;
+        if (i >= sh.end) continue;
+        rgb_out[3 * i + 0] = x[u].x;
+        rgb_out[3 * i + 1] = x[u].y;
+        rgb_out[3 * i + 2] = x[u].z;
+      }
     }
   }
   if (sb.lb == 0 && threadIdx.x == 0) {
@@ -586,6 +606,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
     // many separate sweeps as the selection needs), finalise at once, with no
     // loop and no wait for the other blocks.
     __shared__ int s_open;
+    __shared__ SweepCtrl s_mine;  // this block's cloud, as the wave that advanced it left it
     if (threadIdx.x == 0) s_open = 0;
     __syncthreads();
     const size_t S = (size_t)B * kSlotVals;
@@ -596,12 +617,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tail(SweepArgs a, int q0, int 
       SweepCtrl cs;
       wave_advance(cs, last + s2, sums_sep + (size_t)s2 * kSlotVals, sums_first + (size_t)s2 * kSlotVals, n2);
       if (!cs.done && lane_id() == 0) s_open = 1;
+      if (s2 == sb.s && lane_id() == 0) s_mine = cs;
     }
     __syncthreads();
     if (s_open == 0) {  // uniform over the grid: every block read the same states and sums
-      SweepCtrl c;
-      load_state(c, last + sb.s, sums_sep + (size_t)sb.s * kSlotVals, sums_first + (size_t)sb.s * kSlotVals,
-                 (int)(sb.end - sb.begin));
+      const SweepCtrl c = s_mine;
       finalize_block(sb, c, a.buf_stride, rgb_in, xbuf, noise, rgb_out, a.res, hint,
                      a.relabel && a.relabel[sb.s] ? a.rank0 : nullptr);
       return;
