@@ -55,19 +55,30 @@ def algorithmic_bytes(kind: str, n: int, L: int, K: int, P: int) -> float:
     return 0.0
 
 
-def sweep_kind_bytes(n: int, sweeps: int, L: int, K: int, P: int, tail_finalises: bool) -> float:
-    """Bytes the sweep launches of one fused-path call move for a cloud of n
-    points whose selection computed `sweeps` iterates.  x_1 comes from the
-    noise launch (its bytes are the noise kind's); the first sweep launch adds
-    x_1's flags and sums and, with K = 8, computes x_2 in the same launch;
-    every later iterate is one plain sweep (a launch of its own or a pass of
-    the tail's loop); launches that find the selection stopped move nothing;
-    the tail launch finalises when no separate finalize launch ran."""
+def sweep_kind_sum(sweeps: int, K: int, tail_finalises: bool, per_launch):
+    """Bytes the sweep launches of one fused-path call (K = P = 8: the noise
+    launch computes x_1) move for a cloud whose selection computed `sweeps`
+    iterates, from per_launch(record kind) -> bytes or None.  x_1's bytes are
+    the noise kind's; the first sweep launch adds x_1's flags and sums and,
+    with K = 8, computes x_2 in the same launch ("sweep_first_merged"); every
+    later iterate is one plain sweep (a launch of its own or a pass of the
+    tail's loop); launches that find the selection stopped move nothing; the
+    tail launch finalises ("sweep_tail") when no separate finalize launch ran.
+    None when a needed figure is missing."""
     merged = K == 8 and sweeps >= 2
-    first = algorithmic_bytes("sweep_first_merged" if merged else "sweep_first_fused", n, L, K, P)
+    first = per_launch("sweep_first_merged" if merged else "sweep_first_fused")
     later = max(sweeps - (2 if merged else 1), 0)
-    fin = algorithmic_bytes("finalize", n, L, K, P) if tail_finalises else 0.0
-    return first + later * algorithmic_bytes("sweep", n, L, K, P) + fin
+    plain = per_launch("sweep") if later else 0.0
+    tail = per_launch("sweep_tail") if tail_finalises else 0.0
+    if first is None or plain is None or tail is None:
+        return None
+    return first + later * plain + tail
+
+
+def sweep_kind_bytes(n: int, sweeps: int, L: int, K: int, P: int, tail_finalises: bool) -> float:
+    """Algorithmic bytes of sweep_kind_sum (the tail's are the finalize kind's)."""
+    return sweep_kind_sum(sweeps, K, tail_finalises,
+                          lambda k: algorithmic_bytes("finalize" if k == "sweep_tail" else k, n, L, K, P))
 
 
 # Source files each kernel kind is compiled from: a traffic figure measured
@@ -798,13 +809,24 @@ def main() -> int:
                 return sweep_kind_bytes(n, r["sweeps"], prm.num_dirs, prm.k, P, "finalize" not in kernels)
             return algorithmic_bytes(kind, n, prm.num_dirs, prm.k, P) * kernels[kind]["launches_per_step"]
 
+        tcfg = {"n_points": n, "num_dirs": prm.num_dirs, "window": prm.window, "k": prm.k, "patch": P,
+                "sigma": args.sigma}
+
+        # Counter-measured HBM bytes of the same launches per step (None while
+        # a kernel's sources differ from the ones the record was taken on).
+        def step_traffic(kind):
+            if kind == "sweep":
+                return sweep_kind_sum(r["sweeps"], prm.k, "finalize" not in kernels,
+                                      lambda k: measured_traffic(k, tcfg))
+            t = measured_traffic(kind, tcfg)
+            return t * kernels[kind]["launches_per_step"] if t is not None else None
+
         dom = max((k for k in kernels if algorithmic_bytes(k, n, prm.num_dirs, prm.k, P) > 0),
                   key=lambda k: kernels[k]["ms_per_step"])
         gbs = step_bytes(dom) / (kernels[dom]["ms_per_step"] / 1e3) / 1e9
-        tcfg = {"n_points": n, "num_dirs": prm.num_dirs, "window": prm.window, "k": prm.k, "patch": P,
-                "sigma": args.sigma}
         line["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom, tcfg),
+                            "frac": gbs / HBM_PEAK_GBS, "traffic": step_traffic(dom),
+                            "traffic_basis": "HBM bytes per step of the same launches as bytes_per_step",
                             "bytes_per_step": step_bytes(dom), "ms_per_step": kernels[dom]["ms_per_step"],
                             "launches_per_step": kernels[dom]["launches_per_step"],
                             "timing": "HIP events around each launch on the library's stream",
