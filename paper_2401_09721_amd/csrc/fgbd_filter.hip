@@ -144,37 +144,30 @@ __device__ __forceinline__ void advance(SweepCtrl &c, const double (&t)[kSweepPa
 // previous sweep's integer sums (identical in every block).  A state stored
 // by the fused first launch (first_pending) is first advanced by x_1's sums
 // from sums_first, then, unless that ended the selection, by x_2's.  The
-// state and both sets of slots are loaded at once (the slots of x_1 are read
-// whether or not the state needs them), so the launch waits for one round
-// trip before its sweep.  Every lane of a wave loads one slot of each set and
-// the sums are reduced with shuffles, so every lane holds the totals.
-__device__ __forceinline__ void wave_reduce_both(const unsigned long long *__restrict__ sums_first,
-                                                 const unsigned long long *__restrict__ sums_prev,
-                                                 unsigned long long (&f)[kSweepParts],
-                                                 unsigned long long (&u)[kSweepParts]) {
+// state and both sets of slots are loaded at once (one round trip before the
+// sweep); only the sets the state needs are then reduced, and a state that
+// is already done returns before any reduction.  A wave reduces a set with
+// every lane holding one slot, by shuffles, so every lane holds the totals.
+__device__ __forceinline__ void load_slots(const unsigned long long *__restrict__ sums,
+                                           unsigned long long (&u)[kSweepParts]) {
   const int sl = (int)lane_id();
 #pragma unroll
-  for (int j = 0; j < kSweepParts; ++j) {
-    f[j] = sl < kSweepSlots ? sums_first[sl * kSweepParts + j] : 0ull;
-    u[j] = sl < kSweepSlots ? sums_prev[sl * kSweepParts + j] : 0ull;
-  }
+  for (int j = 0; j < kSweepParts; ++j) u[j] = sl < kSweepSlots ? sums[sl * kSweepParts + j] : 0ull;
+}
+__device__ __forceinline__ void wave_sum(unsigned long long (&u)[kSweepParts]) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-    for (int j = 0; j < kSweepParts; ++j) {
-      f[j] += __shfl_xor(f[j], o, kWave);
-      u[j] += __shfl_xor(u[j], o, kWave);
-    }
+    for (int j = 0; j < kSweepParts; ++j) u[j] += __shfl_xor(u[j], o, kWave);
   }
 }
 __device__ __forceinline__ void sums_to_double(const unsigned long long *u, double (&t)[kSweepParts]) {
 #pragma unroll
   for (int j = 0; j < kSweepParts; ++j) t[j] = j < 4 ? (double)u[j] / kFix : (double)u[j];
 }
-// Advance a loaded state by the reduced sums (see above).
+// Advance a state that is not done by the reduced sums (see above).
 __device__ __forceinline__ void advance_loaded(SweepCtrl &c, const unsigned long long *f,
                                                const unsigned long long *u, int n) {
-  if (c.done) return;
   double t[kSweepParts];
   if (c.first_pending) {  // x_1 sits in buffer 0, where the noise launch wrote it
     sums_to_double(f, t);
@@ -185,7 +178,8 @@ __device__ __forceinline__ void advance_loaded(SweepCtrl &c, const unsigned long
   sums_to_double(u, t);
   advance(c, t, n, free_buffer(c.in_buf, c.best_buf));
 }
-// Called by every thread of the block; wave 0 loads and reduces the slots.
+// Called by every thread of the block (the state, and so c.done, is the
+// same for all of them); wave 0 loads and reduces the slots.
 __device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__restrict__ prev,
                                            const unsigned long long *__restrict__ sums_prev,
                                            const unsigned long long *__restrict__ sums_first, int n) {
@@ -193,15 +187,21 @@ __device__ __forceinline__ void load_state(SweepCtrl &c, const SweepCtrl *__rest
   c = *prev;
   if (threadIdx.x < kWave) {
     unsigned long long f[kSweepParts], u[kSweepParts];
-    wave_reduce_both(sums_first, sums_prev, f, u);
-    if (threadIdx.x == 0) {
+    load_slots(sums_first, f);
+    load_slots(sums_prev, u);
+    if (!c.done) {
+      if (c.first_pending) wave_sum(f);
+      wave_sum(u);
+      if (threadIdx.x == 0) {
 #pragma unroll
-      for (int j = 0; j < kSweepParts; ++j) {
-        s_tot[j] = f[j];
-        s_tot[kSweepParts + j] = u[j];
+        for (int j = 0; j < kSweepParts; ++j) {
+          s_tot[j] = f[j];
+          s_tot[kSweepParts + j] = u[j];
+        }
       }
     }
   }
+  if (c.done) return;
   __syncthreads();
   unsigned long long f[kSweepParts], u[kSweepParts];
 #pragma unroll
@@ -218,7 +218,11 @@ __device__ __forceinline__ void wave_advance(SweepCtrl &c, const SweepCtrl *__re
                                              const unsigned long long *__restrict__ sums_first, int n) {
   c = *prev;
   unsigned long long f[kSweepParts], u[kSweepParts];
-  wave_reduce_both(sums_first, sums_prev, f, u);
+  load_slots(sums_first, f);
+  load_slots(sums_prev, u);
+  if (c.done) return;
+  if (c.first_pending) wave_sum(f);
+  wave_sum(u);
   advance_loaded(c, f, u, n);
 }
 
