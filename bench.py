@@ -824,13 +824,29 @@ def main() -> int:
         dom = max((k for k in kernels if algorithmic_bytes(k, n, prm.num_dirs, prm.k, P) > 0),
                   key=lambda k: kernels[k]["ms_per_step"])
         gbs = step_bytes(dom) / (kernels[dom]["ms_per_step"] / 1e3) / 1e9
-        line["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": gbs / HBM_PEAK_GBS, "traffic": step_traffic(dom),
-                            "traffic_basis": "HBM bytes per step of the same launches as bytes_per_step",
-                            "bytes_per_step": step_bytes(dom), "ms_per_step": kernels[dom]["ms_per_step"],
-                            "launches_per_step": kernels[dom]["launches_per_step"],
-                            "timing": "HIP events around each launch on the library's stream",
-                            "valu": measured_valu(dom, tcfg, kernels[dom]["us_per_launch"])}
+        hbm = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": gbs / HBM_PEAK_GBS, "traffic": step_traffic(dom),
+               "traffic_basis": "HBM bytes per step of the same launches as bytes_per_step",
+               "bytes_per_step": step_bytes(dom), "ms_per_step": kernels[dom]["ms_per_step"],
+               "launches_per_step": kernels[dom]["launches_per_step"],
+               "timing": "HIP events around each launch on the library's stream"}
+        valu = measured_valu(dom, tcfg, kernels[dom]["us_per_launch"])
+        if valu is not None and valu["frac"] > hbm["frac"]:
+            # Bound by vector instruction issue, not by its bytes: the
+            # instruction rate against the issue peak, the HBM view beside it.
+            # The count is the counter-measured one (a ballot ranking has no
+            # algorithmic flop count), so the fraction says how busy the issue
+            # port is, not how little work the kernel does.
+            rate = valu["insts_per_launch"] / (kernels[dom]["us_per_launch"] * 1e-6)
+            line["roofline"] = {"kernel": dom, "bound": "alu", "achieved": rate / 1e9,
+                                "peak": VALU_ISSUE_PEAK / 1e9, "unit": "G wave instructions/s",
+                                "frac": rate / VALU_ISSUE_PEAK, "traffic": hbm["traffic"],
+                                "peak_basis": "256 CUs x one 64-lane vector instruction per cycle x 2.4 GHz",
+                                "work": "SQ_INSTS_VALU per launch from the committed counter record",
+                                "insts_per_launch": valu["insts_per_launch"],
+                                "us_per_launch": kernels[dom]["us_per_launch"], "hbm": hbm}
+        else:
+            line["roofline"] = dict(hbm, valu=valu)
         print(f"# kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
         # Active sweeps alone, the kernel the bandwidth target is set on: the
