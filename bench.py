@@ -88,7 +88,8 @@ KIND_SOURCES = {
     "merge": ("fgbd_graph.hip",), "weights": ("fgbd_graph.hip",),
     "noise": ("fgbd_noise.hip",), "noise_solve": ("fgbd_noise.hip",),
     "sweep": ("fgbd_filter.hip",), "finalize": ("fgbd_filter.hip",), "relabel": ("fgbd_graph.hip",),
-    "local_sort": ("fgbd_sort.hip",),
+    "local_sort": ("fgbd_sort.hip",), "sweep_first_merged": ("fgbd_filter.hip",),
+    "sweep_first": ("fgbd_filter.hip",), "sweep_tail": ("fgbd_filter.hip",),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fgbd_1M_frame.md")
 
@@ -142,6 +143,32 @@ def measured_valu(kind: str, config: dict, us_per_launch: float):
     insts = k["valu_insts"]
     return {"insts_per_launch": insts, "issue_peak_per_s": VALU_ISSUE_PEAK,
             "frac": insts / (us_per_launch * 1e-6) / VALU_ISSUE_PEAK}
+
+
+def roofline_object(kind: str, k: dict, bytes_per_step: float, traffic, valu) -> dict:
+    """The roofline of the dominant kind from its per-step time `k`
+    (ms_per_step, launches_per_step, us_per_launch), its algorithmic bytes per
+    step, its counter-measured HBM bytes per step (or None) and measured_valu
+    (or None).  HBM view by default; when the VALU issue fraction is the
+    larger, the instruction rate against the issue peak ("bound": "alu") with
+    the HBM view under "hbm".  The instruction count is the counter-measured
+    one (a ballot ranking has no algorithmic flop count), so that fraction
+    says how busy the issue port is, not how little work the kernel does."""
+    gbs = bytes_per_step / (k["ms_per_step"] / 1e3) / 1e9
+    hbm = {"kernel": kind, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+           "traffic_basis": "HBM bytes per step of the same launches as bytes_per_step",
+           "bytes_per_step": bytes_per_step, "ms_per_step": k["ms_per_step"],
+           "launches_per_step": k["launches_per_step"],
+           "timing": "HIP events around each launch on the library's stream"}
+    if valu is None or valu["frac"] <= hbm["frac"]:
+        return dict(hbm, valu=valu)
+    rate = valu["insts_per_launch"] / (k["us_per_launch"] * 1e-6)
+    return {"kernel": kind, "bound": "alu", "achieved": rate / 1e9, "peak": VALU_ISSUE_PEAK / 1e9,
+            "unit": "G wave instructions/s", "frac": rate / VALU_ISSUE_PEAK, "traffic": traffic,
+            "peak_basis": "256 CUs x one 64-lane vector instruction per cycle x 2.4 GHz",
+            "work": "SQ_INSTS_VALU per launch from the committed counter record",
+            "insts_per_launch": valu["insts_per_launch"], "us_per_launch": k["us_per_launch"], "hbm": hbm}
 
 
 def _gen(job):
@@ -823,30 +850,8 @@ def main() -> int:
 
         dom = max((k for k in kernels if algorithmic_bytes(k, n, prm.num_dirs, prm.k, P) > 0),
                   key=lambda k: kernels[k]["ms_per_step"])
-        gbs = step_bytes(dom) / (kernels[dom]["ms_per_step"] / 1e3) / 1e9
-        hbm = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": gbs / HBM_PEAK_GBS, "traffic": step_traffic(dom),
-               "traffic_basis": "HBM bytes per step of the same launches as bytes_per_step",
-               "bytes_per_step": step_bytes(dom), "ms_per_step": kernels[dom]["ms_per_step"],
-               "launches_per_step": kernels[dom]["launches_per_step"],
-               "timing": "HIP events around each launch on the library's stream"}
-        valu = measured_valu(dom, tcfg, kernels[dom]["us_per_launch"])
-        if valu is not None and valu["frac"] > hbm["frac"]:
-            # Bound by vector instruction issue, not by its bytes: the
-            # instruction rate against the issue peak, the HBM view beside it.
-            # The count is the counter-measured one (a ballot ranking has no
-            # algorithmic flop count), so the fraction says how busy the issue
-            # port is, not how little work the kernel does.
-            rate = valu["insts_per_launch"] / (kernels[dom]["us_per_launch"] * 1e-6)
-            line["roofline"] = {"kernel": dom, "bound": "alu", "achieved": rate / 1e9,
-                                "peak": VALU_ISSUE_PEAK / 1e9, "unit": "G wave instructions/s",
-                                "frac": rate / VALU_ISSUE_PEAK, "traffic": hbm["traffic"],
-                                "peak_basis": "256 CUs x one 64-lane vector instruction per cycle x 2.4 GHz",
-                                "work": "SQ_INSTS_VALU per launch from the committed counter record",
-                                "insts_per_launch": valu["insts_per_launch"],
-                                "us_per_launch": kernels[dom]["us_per_launch"], "hbm": hbm}
-        else:
-            line["roofline"] = dict(hbm, valu=valu)
+        line["roofline"] = roofline_object(dom, kernels[dom], step_bytes(dom), step_traffic(dom),
+                                           measured_valu(dom, tcfg, kernels[dom]["us_per_launch"]))
         print(f"# kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
         # Active sweeps alone, the kernel the bandwidth target is set on: the
