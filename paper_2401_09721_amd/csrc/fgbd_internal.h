@@ -401,7 +401,7 @@ struct Tune {
 };
 constexpr int kDefaultSweepLaunches = 8;
 constexpr int kMaxSweepLaunches = 1024;
-constexpr int kDefaultMergeGrid = 2048;  // the merge gains from more blocks than the other kernels
+constexpr int kDefaultMergeGrid = 4096;  // the merge gains from more blocks than the other kernels
 constexpr Tune kDefaultTune = {{kDefaultMergeGrid, kMaxGrid, kMaxGrid}, kDefaultSweepLaunches};
 
 Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune = kDefaultTune);
