@@ -300,7 +300,7 @@ fgbd_status fgbd_denoise_batched_fixed_q(fgbd_ctx ctx, const int32_t *xyz, const
  * for all blocks costs far more than a launch boundary, so the count should
  * cover the sweeps a workload usually needs).  When the sweep grid cannot be
  * resident on the device at once, every sweep is a launch of its own.
- * Defaults 4096, 1024, 1024 and 8.  A schedule changes no result beyond the
+ * Defaults 4096, 1024, 512 and 8.  A schedule changes no result beyond the
  * rounding order of FP64 sums (block partials); it is a property of the
  * context and applies to every later call on it.  Valid ranges:
  * merge_blocks and sweep_blocks 64..4096, noise_blocks 64..1024,

@@ -402,7 +402,8 @@ struct Tune {
 constexpr int kDefaultSweepLaunches = 8;
 constexpr int kMaxSweepLaunches = 1024;
 constexpr int kDefaultMergeGrid = 4096;  // the merge gains from more blocks than the other kernels
-constexpr Tune kDefaultTune = {{kDefaultMergeGrid, kMaxGrid, kMaxGrid}, kDefaultSweepLaunches};
+constexpr int kDefaultSweepGrid = 512;  // fewer, longer-running sweep blocks: less block start and sum traffic
+constexpr Tune kDefaultTune = {{kDefaultMergeGrid, kMaxGrid, kDefaultSweepGrid}, kDefaultSweepLaunches};
 
 Plan make_plan(int64_t n_cap, int B, const fgbd_params &p, const Tune &tune = kDefaultTune);
 

@@ -237,7 +237,7 @@ def test_schedule_get_set(ctx):
     lib = fgbd.lib()
     sc = fgbd.Schedule()
     assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
-    assert sc.as_dict() == {"merge_blocks": 4096, "noise_blocks": 1024, "sweep_blocks": 1024, "sweep_launches": 8}
+    assert sc.as_dict() == {"merge_blocks": 4096, "noise_blocks": 1024, "sweep_blocks": 512, "sweep_launches": 8}
     new = fgbd.Schedule(2048, 512, 256, 5)
     assert lib.fgbd_set_schedule(ctx, ctypes.byref(new)) == 0
     assert lib.fgbd_get_schedule(ctx, ctypes.byref(sc)) == 0
